@@ -1,0 +1,277 @@
+"""Workload generators (see the package docstring).
+
+Graph model: a directed attributed graph (Def. 1) given as a vertex table and an
+edge table.  Vertex ``i`` has uint32 attribute columns ``vcols[name][i]``; edge
+row ``e`` goes from ``src[e]`` to ``dst[e]`` and has columns ``ecols[name][e]``.
+A query is a path v_0 -> v_1 -> ... -> v_{k-1}; each predicate targets one query
+vertex (``target < n_qv``) or one query edge (``target = n_qv + j`` for the
+edge v_j -> v_{j+1}), and is an equality ``x == a`` or a half-open range
+``lo <= x < hi`` on one column.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+U32 = np.uint32
+
+
+def _rng(*key) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(k) for k in key])))
+
+
+@dataclass
+class Pred:
+    target: int
+    kind: str            # "eq" | "range"
+    column: str
+    a: int = 0
+    lo: int = 0
+    hi: int = 0
+
+    def holds(self, x: np.ndarray) -> np.ndarray:
+        x = x.astype(np.uint64)
+        if self.kind == "eq":
+            return x == self.a
+        return (x >= self.lo) & (x < self.hi)
+
+
+@dataclass
+class Query:
+    query_id: int
+    n_qv: int
+    preds: list = field(default_factory=list)
+
+
+@dataclass
+class Graph:
+    n_vertices: int
+    src: np.ndarray
+    dst: np.ndarray
+    vcols: dict
+    ecols: dict
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.src.size)
+
+
+def rows_of_target(graph: Graph, query: Query, target: int) -> int:
+    return graph.n_vertices if target < query.n_qv else graph.n_edges
+
+
+def column_of(graph: Graph, query: Query, pred: Pred) -> np.ndarray:
+    return graph.vcols[pred.column] if pred.target < query.n_qv else graph.ecols[pred.column]
+
+
+# --------------------------------------------------------------------------- distributions
+
+def zipf_column(rng: np.random.Generator, size: int, s: float = 1.1) -> np.ndarray:
+    """Zipf(s) ranks k >= 1 over [1, 2^32], returned as k - 1 (ranks above 2^32
+    are drawn again)."""
+    out = rng.zipf(s, size).astype(np.uint64)
+    bad = out > (1 << 32)
+    while bad.any():
+        out[bad] = rng.zipf(s, int(bad.sum())).astype(np.uint64)
+        bad = out > (1 << 32)
+    return (out - 1).astype(U32)
+
+
+def vertex_table(seed: int, n: int) -> dict:
+    """Two labels uniform in [0, 64) and two Zipf(1.1) integers over [0, 2^32)."""
+    rng = _rng(seed, 11)
+    return {
+        "l0": rng.integers(0, 64, n, dtype=U32),
+        "l1": rng.integers(0, 64, n, dtype=U32),
+        "z0": zipf_column(rng, n),
+        "z1": zipf_column(rng, n),
+    }
+
+
+def er_graph(seed: int, n_vertices: int, n_edges: int) -> tuple:
+    """Erdos-Renyi G(n, m): m distinct directed pairs (u, v), u != v."""
+    rng = _rng(seed, 21)
+    assert n_edges <= n_vertices * (n_vertices - 1)
+    chosen = set()
+    src, dst = [], []
+    while len(src) < n_edges:
+        need = n_edges - len(src)
+        u = rng.integers(0, n_vertices, 2 * need)
+        v = rng.integers(0, n_vertices, 2 * need)
+        for a, b in zip(u.tolist(), v.tolist()):
+            if a != b and (a, b) not in chosen:
+                chosen.add((a, b))
+                src.append(a)
+                dst.append(b)
+                if len(src) == n_edges:
+                    break
+    return np.array(src, U32), np.array(dst, U32)
+
+
+def chung_lu_graph(seed: int, n_vertices: int, n_edges: int, gamma: float = 2.1) -> tuple:
+    """Chung-Lu power-law graph: endpoints drawn with probability proportional to
+    w_i = (i + 1)^(-1 / (gamma - 1)); self-loops are drawn again, multi-edges kept."""
+    rng = _rng(seed, 31)
+    w = np.arange(1, n_vertices + 1, dtype=np.float64) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+
+    def draw(k):
+        return np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), n_vertices - 1)
+
+    src = draw(n_edges)
+    dst = draw(n_edges)
+    loop = src == dst
+    while loop.any():
+        dst[loop] = draw(int(loop.sum()))
+        loop = src == dst
+    return src.astype(U32), dst.astype(U32)
+
+
+# --------------------------------------------------------------------------- shares and masks
+
+def share_column(rng: np.random.Generator, x: np.ndarray) -> tuple:
+    """Two-party additive shares mod 2^32: x0 uniform, x1 = x - x0."""
+    x0 = rng.integers(0, 1 << 32, x.size, dtype=np.uint64).astype(U32)
+    x1 = (x.astype(np.uint64) - x0.astype(np.uint64)).astype(U32)
+    return x0, x1
+
+
+def share_columns(seed: int, cols: dict) -> dict:
+    return {name: share_column(_rng(seed, 41, i), cols[name]) for i, name in enumerate(sorted(cols))}
+
+
+def pred_masks(seed: int, query: Query, graph: Graph) -> list:
+    """One fresh uint32 mask per (query, predicate, row)."""
+    return [_rng(seed, 51, query.query_id, k).integers(0, 1 << 32, rows_of_target(graph, query, p.target),
+                                                       dtype=np.uint64).astype(U32)
+            for k, p in enumerate(query.preds)]
+
+
+# --------------------------------------------------------------------------- workloads
+
+def tiny_graph(seed: int, n_vertices: int = 12, n_edges: int = 30, label_range: int = 4,
+               attr_range: int = 16, multi_edges: bool = True) -> Graph:
+    """A very small graph (for brute force over every injective vertex map).
+    Multi-edges are allowed so that distinct edge rows between one vertex pair
+    show up as distinct results."""
+    rng = _rng(seed, 61)
+    src = rng.integers(0, n_vertices, n_edges)
+    dst = rng.integers(0, n_vertices, n_edges)
+    loop = src == dst
+    while loop.any():
+        dst[loop] = rng.integers(0, n_vertices, int(loop.sum()))
+        loop = src == dst
+    if not multi_edges:
+        pairs = {}
+        for e, (u, v) in enumerate(zip(src.tolist(), dst.tolist())):
+            pairs.setdefault((u, v), e)
+        keep = np.array(sorted(pairs.values()))
+        src, dst = src[keep], dst[keep]
+    vcols = {"label": rng.integers(0, label_range, n_vertices, dtype=U32),
+             "attr": rng.integers(0, attr_range, n_vertices, dtype=U32)}
+    ecols = {"label": rng.integers(0, label_range, src.size, dtype=U32),
+             "weight": rng.integers(0, attr_range, src.size, dtype=U32)}
+    return Graph(n_vertices, src.astype(U32), dst.astype(U32), vcols, ecols)
+
+
+def config1(seed: int = 1) -> tuple:
+    """Tiny plain query: ER graph of 1,024 vertices and 8,192 edges; vertex label
+    in [0,16), vertex attribute in [0,2^20), edge label in [0,4).  Query v1 -> v2
+    with v1.label == A, lo <= v2.attr < hi (hi = lo + 2^18) and edge label == C."""
+    src, dst = er_graph(seed, 1024, 8192)
+    rng = _rng(seed, 71)
+    vcols = {"label": rng.integers(0, 16, 1024, dtype=U32),
+             "attr": rng.integers(0, 1 << 20, 1024, dtype=U32)}
+    ecols = {"label": rng.integers(0, 4, 8192, dtype=U32)}
+    g = Graph(1024, src, dst, vcols, ecols)
+    lo = int(rng.integers(0, (1 << 20) - (1 << 18)))
+    q = Query(query_id=1, n_qv=2, preds=[
+        Pred(0, "eq", "label", a=int(rng.integers(0, 16))),
+        Pred(1, "range", "attr", lo=lo, hi=lo + (1 << 18)),
+        Pred(2, "eq", "label", a=int(rng.integers(0, 4))),
+    ])
+    return g, q
+
+
+def _quartile_range(col: np.ndarray) -> tuple:
+    lo, hi = np.quantile(col.astype(np.float64), [0.25, 0.75])
+    lo, hi = int(lo), int(hi)
+    if hi <= lo:
+        hi = lo + 1
+    return lo, hi
+
+
+def config2(seed: int = 2, n: int = 1 << 22) -> tuple:
+    """Vertex filtering at scale: n rows x (l0, l1, z0, z1); one query with
+    l0 == A, l1 == B, z0 in [q25, q75), z1 in [q25, q75)."""
+    cols = vertex_table(seed, n)
+    rng = _rng(seed, 81)
+    z0 = _quartile_range(cols["z0"])
+    z1 = _quartile_range(cols["z1"])
+    g = Graph(n, np.zeros(0, U32), np.zeros(0, U32), cols, {})
+    q = Query(query_id=2, n_qv=1, preds=[
+        Pred(0, "eq", "l0", a=int(rng.integers(0, 64))),
+        Pred(0, "eq", "l1", a=int(rng.integers(0, 64))),
+        Pred(0, "range", "z0", lo=z0[0], hi=z0[1]),
+        Pred(0, "range", "z1", lo=z1[0], hi=z1[1]),
+    ])
+    return g, q
+
+
+def config3(seed: int = 3, n_vertices: int = 1 << 22, n_edges: int = 1 << 25) -> tuple:
+    """Full plain query: Chung-Lu (gamma 2.1) graph; vertex columns as config2,
+    edge label in [0,4), edge weight in [0,2^16).  Path a -> b -> c with
+    a.l0 == A, b.z0 in [q25,q75), c.l1 == B and c.z1 in [q25,q75),
+    e_ab.label == C, e_bc.weight in [w_lo, w_lo + 2^14)."""
+    src, dst = chung_lu_graph(seed, n_vertices, n_edges)
+    cols = vertex_table(seed, n_vertices)
+    rng = _rng(seed, 91)
+    ecols = {"label": rng.integers(0, 4, n_edges, dtype=U32),
+             "weight": rng.integers(0, 1 << 16, n_edges, dtype=U32)}
+    g = Graph(n_vertices, src, dst, cols, ecols)
+    z0 = _quartile_range(cols["z0"])
+    z1 = _quartile_range(cols["z1"])
+    w_lo = int(rng.integers(0, (1 << 16) - (1 << 14)))
+    q = Query(query_id=3, n_qv=3, preds=[
+        Pred(0, "eq", "l0", a=int(rng.integers(0, 64))),
+        Pred(1, "range", "z0", lo=z0[0], hi=z0[1]),
+        Pred(2, "eq", "l1", a=int(rng.integers(0, 64))),
+        Pred(2, "range", "z1", lo=z1[0], hi=z1[1]),
+        Pred(3, "eq", "label", a=int(rng.integers(0, 4))),
+        Pred(4, "range", "weight", lo=w_lo, hi=w_lo + (1 << 14)),
+    ])
+    return g, q
+
+
+def batch_queries(seed: int, graph: Graph, count: int = 64, min_log_rows: int = 12,
+                  max_log_rows: int = 22) -> list:
+    """Uneven query mix: 1-5 predicates (equality : range = 1 : 1) over 1-4 query
+    vertices (path shaped); candidate table size R log-uniform in
+    [2^min_log_rows, 2^max_log_rows] (candidates are rows [0, R)).  Returns a
+    list of (query, R)."""
+    rng = _rng(seed, 101)
+    out = []
+    vcols = sorted(graph.vcols)
+    ecols = sorted(graph.ecols)
+    for i in range(count):
+        n_qv = int(rng.integers(1, 5))
+        n_pred = int(rng.integers(1, 6))
+        rows = int(round(2.0 ** rng.uniform(min_log_rows, max_log_rows)))
+        rows = max(1, min(rows, graph.n_vertices))
+        preds = []
+        for k in range(n_pred):
+            on_edge = n_qv > 1 and ecols and rng.random() < 0.3
+            target = n_qv + int(rng.integers(0, n_qv - 1)) if on_edge else int(rng.integers(0, n_qv))
+            cols = ecols if on_edge else vcols
+            col = cols[int(rng.integers(0, len(cols)))]
+            values = (graph.ecols if on_edge else graph.vcols)[col]
+            if rng.random() < 0.5:
+                preds.append(Pred(target, "eq", col, a=int(values[int(rng.integers(0, values.size))])))
+            else:
+                sample = values[rng.integers(0, values.size, 4096)]
+                lo, hi = _quartile_range(sample)
+                preds.append(Pred(target, "range", col, lo=lo, hi=hi))
+        out.append((Query(query_id=1000 + i, n_qv=n_qv, preds=preds), rows))
+    return out
