@@ -1,0 +1,200 @@
+/*
+ * oblivgm_fss.h -- C ABI of the MI355X (gfx950) FSS-evaluation library.
+ *
+ * Masked-input function secret sharing over secret-shared attribute tables,
+ * after OblivGM (arXiv 2209.03526): DPF evaluation for equality predicates and
+ * DCF evaluation for range predicates (Sec. V-C), shared AND of predicate bits
+ * (Sec. III-B, Sec. V-D), and a path query joined along public edge endpoints
+ * (Alg. 2).  Two parties; both may be simulated on one GPU.
+ *
+ * Conventions for every call:
+ *   - Buffers named d_* are DEVICE pointers owned by the caller.  The library
+ *     never allocates or frees caller memory; it holds no device memory of its
+ *     own except constant tables.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls validate
+ *     their arguments synchronously, enqueue kernels on `stream` and return
+ *     without waiting.  A negative return means nothing was enqueued;
+ *     fss_last_error() (thread-local) then says why.  Device faults surface at
+ *     the caller's next synchronisation.
+ *   - Packed bits: row i is bit (i % 32) of 32-bit word i / 32; bits of rows
+ *     beyond the table (pad bits of the last word) are 0 in every output share.
+ *   - nbits (the FSS input domain) is 8..32.  Masked values are uint32; only
+ *     their low nbits bits are evaluated.  Production inputs use nbits = 32.
+ *   - Results are a pure function of the inputs: no atomics whose order matters.
+ *
+ * Key batch layout (per party), rows padded to Np = round_up(n, 64):
+ *   a batch is a sequence of planes; plane p holds one field for every row,
+ *   row e at byte offset plane_offset + e * field_size.
+ *   DPF (nu = nbits - 7):   root[16] | scw_0[16] .. scw_{nu-1}[16] | tl[4] | tr[4] | cwout[16]
+ *   DCF (nbits levels):     root[16] | scw_0[16] .. scw_{nbits-1}[16] | tl[4] | tr[4] | vcw[4] | fin[4]
+ *   RANGE key:              DCF at U = hi + r, then DCF at L = lo + r
+ *   bit i of tl/tr/vcw belongs to level i (level 0 consumes the most
+ *   significant input bit); fin bit 0 is the final correction bit; bit 31 of
+ *   the upper DCF's fin is the party's wrap share c_b.  Per element and
+ *   party: DPF 16*nbits - 72 bytes (440 at 32 bits), RANGE 2 * (16*nbits + 32)
+ *   bytes (1,088 at 32 bits).
+ */
+#ifndef OBLIVGM_FSS_H
+#define OBLIVGM_FSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSS_OK = 0,
+    FSS_EINVAL = -1,        /* bad argument (null pointer, size, bound, party ...) */
+    FSS_ENOMEM = -2,        /* caller-provided workspace too small */
+    FSS_EDEVICE = -3,       /* HIP runtime error while enqueuing */
+    FSS_EUNSUPPORTED = -4   /* valid request this build does not serve */
+} fss_status;
+
+typedef enum {
+    FSS_EQ = 0,             /* x == a                          (one DPF)          */
+    FSS_RANGE = 1           /* lo <= x < hi, half-open         (two DCFs + wrap)  */
+} fss_kind;
+
+/* One predicate's keys for n rows.  key[b] is party b's batch (device memory,
+ * fss_keybatch_bytes(kind, nbits, n) bytes, 256-byte aligned). */
+typedef struct fss_keybatch {
+    int32_t  kind;          /* fss_kind */
+    uint32_t nbits;         /* 8..32 */
+    uint64_t n;             /* rows */
+    void*    key[2];
+} fss_keybatch;
+
+/* Bytes of one element's key for one party (DPF 440 / RANGE 1,088 at 32 bits);
+ * 0 for an invalid kind or nbits. */
+uint64_t fss_key_bytes(int32_t kind, uint32_t nbits);
+
+/* Bytes of a whole batch for one party: fss_key_bytes * round_up(n, 64). */
+uint64_t fss_keybatch_bytes(int32_t kind, uint32_t nbits, uint64_t n);
+
+/* Thread-local description of the last failed call ("" if none). */
+const char* fss_last_error(void);
+
+/* Library version string. */
+const char* fss_version(void);
+
+/*
+ * A1 -- open the masked value (Sec. V-B additive shares, Sec. V-C masked input):
+ *   d_xhat[i] = d_x0[i] + d_x1[i] + d_r[i]  (mod 2^32),  i < n.
+ * In a deployment party b publishes x_b + r_b; with both parties simulated
+ * the sum is formed at once.  d_xhat may alias none of the inputs' other rows
+ * (in-place on d_x0 is allowed).
+ */
+int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const uint32_t* d_r,
+                  uint32_t* d_xhat, void* stream);
+
+/*
+ * A2 -- dealer key generation (Def. 3 Gen; Sec. V-C token generation in its
+ * masked-input form).  For every row e < out->n, with mask d_r[e]:
+ *   FSS_EQ:    DPF at alpha = (a_or_lo + r) mod 2^nbits          (hi ignored)
+ *   FSS_RANGE: DCF at U = hi + r and at L = a_or_lo + r, wrap share c_b with
+ *              c_1 = c_0 xor [L > U]                               (lo <= hi)
+ * Randomness (root seeds, c_0) comes from the dealer's counter-mode AES
+ * generator keyed by `seed`, addressed by (query_id, pred_id, row).
+ * Writes out->key[0] and out->key[1] (both parties).
+ * Errors: EINVAL if out, its key pointers or d_r is NULL, nbits is outside
+ * 8..32, a_or_lo / hi do not fit nbits, lo > hi, or a key pointer is not
+ * 256-byte aligned.
+ */
+int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or_lo, uint32_t hi,
+               const uint32_t* d_r, const fss_keybatch* out, void* stream);
+
+/*
+ * A3 + A5 -- DPF evaluation (Def. 3 Eval) by `party` (0 or 1) on the opened
+ * values d_xhat[0..n): writes ceil(n/32) packed share words to d_out_bits.
+ * XOR of both parties' words is [x == a] per row.  k->kind must be FSS_EQ.
+ */
+int fss_eval_eq(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits,
+                void* stream);
+
+/*
+ * A4 + A5 -- range evaluation: two DCF walks and the wrap share (interval
+ * containment from comparisons, Sec. V-C).  XOR of both parties' words is
+ * [lo <= x < hi].  k->kind must be FSS_RANGE.
+ */
+int fss_eval_lt(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits,
+                void* stream);
+
+/*
+ * A6 -- shared AND of packed bits by Beaver triples (two-party analogue of the
+ * AND of Sec. III-B; aggregation of predicates by AND, Sec. V-D).
+ *
+ * ss_triples: dealer's triples for AND number `and_id` of query `query_id`:
+ *   d_trip0 / d_trip1 receive 3*nwords words a_b | b_b | c_b (party 0 / 1),
+ *   with (a0^a1) & (b0^b1) = c0^c1, from the counter-mode generator (domain 4).
+ * ss_and, phase SS_AND_OPEN:  out = d_b | e_b (2*nwords words),
+ *   d_b = x ^ a_b, e_b = y ^ b_b.
+ * ss_and, phase SS_AND_CLOSE: de_open = d | e (2*nwords words, the XOR of the
+ *   two parties' OPEN messages); out = z_b (nwords words)
+ *   = c_b ^ (d & b_b) ^ (e & a_b) ^ [party == 0](d & e), pad bits beyond nrows
+ *   cleared.  x, y are ignored in CLOSE; de_open is ignored in OPEN.
+ */
+enum { SS_AND_OPEN = 0, SS_AND_CLOSE = 1 };
+int ss_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nwords, uint32_t* d_trip0,
+               uint32_t* d_trip1, void* stream);
+int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, const uint32_t* d_y,
+           const uint32_t* d_triple, const uint32_t* d_de_open, uint32_t* d_out, void* stream);
+
+/*
+ * A7 -- a whole path query v_0 -> v_1 -> ... -> v_{n_qv-1} (Alg. 2, secMatch,
+ * with public edge endpoints) for BOTH simulated parties.
+ *
+ * Predicate k targets query vertex `target` (< n_qv; rows = vertex table) or
+ * query edge target - n_qv (edge v_j -> v_{j+1}; rows = edge table).  Its keys
+ * must have been made with pred_id = k, and d_xhat holds the target table's
+ * opened values.  Semantics:
+ *   1. each party evaluates every predicate (DPF / range) on its rows;
+ *   2. per query vertex, then per query edge, its predicate bits are ANDed as
+ *      a left fold in plan order (none: the public constant 1);
+ *   3. per hop j: h_j = (m_j[src] AND m_{j+1}[dst]) AND q_j over edge rows,
+ *      where m[src] gathers each party's own share bit at the public index;
+ *   4. ANDs are numbered 0,1,... in execution order (step 2 vertex folds, then
+ *      edge folds, then two per hop) and AND i uses the Beaver triple stream
+ *      (seed, query_id, i); an AND with a public-1 operand is skipped and
+ *      takes no number.
+ * Output d_out[b] (party b): n_qv == 1 -> m_0, ceil(n_vertices/32) words;
+ * else h_0 .. h_{n_qv-2}, each ceil(n_edges/32) words, hop after hop.
+ * Workspace: match_workspace_bytes(plan) bytes of device memory, 256-aligned.
+ * party_mask must be 3 (both parties simulated); a single party's half of a
+ * deployment uses fss_eval_* and ss_and directly.
+ */
+#define FSS_MAX_QV 8
+#define FSS_MAX_PREDS 32
+
+typedef struct fss_pred {
+    int32_t target;                 /* query vertex, or n_qv + query edge */
+    int32_t reserved;
+    const fss_keybatch* keys;       /* host pointer; device key buffers */
+    const uint32_t* d_xhat;         /* opened values of the target table */
+} fss_pred;
+
+typedef struct match_plan {
+    uint64_t seed;                  /* dealer seed of the Beaver triples */
+    uint32_t query_id;
+    uint32_t n_qv;                  /* 1 .. FSS_MAX_QV */
+    uint32_t n_pred;                /* 0 .. FSS_MAX_PREDS */
+    uint32_t reserved;
+    uint64_t n_vertices;
+    uint64_t n_edges;
+    const uint32_t* d_src;          /* public endpoints (n_edges each); unused when n_qv == 1 */
+    const uint32_t* d_dst;
+    const fss_pred* preds;          /* host array of n_pred predicates */
+    uint32_t* d_out[2];
+    void* d_workspace;
+    uint64_t workspace_bytes;
+} match_plan;
+
+uint64_t match_workspace_bytes(const match_plan* plan);
+int match_query(const match_plan* plan, int32_t party_mask, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OBLIVGM_FSS_H */

@@ -1,0 +1,205 @@
+// aes_gfx950.hpp -- AES-128 encryption for gfx950 wavefronts, T-table in LDS.
+//
+// The PRG of the FSS trees is fixed-key AES-128 in Matyas-Meyer-Oseas form
+// (lambda = 128, Sec. VII-A); the dealer's randomness is AES-128 in counter
+// mode under a per-call key.  Both run through aes128_encrypt() below.
+//
+// Table layout.  One 256-entry table T0[x] = (2S(x), S(x), S(x), 3S(x)) (bytes
+// 0..3, i.e. the MixColumns image of S(x) in row 0) is replicated 64 times in
+// LDS, one copy per wavefront lane: entry x of lane l's copy sits at byte
+// address (x << 8) | (l << 2).  A lane therefore always reads bank (l mod
+// banks): every ds_read_b32 of a round is conflict-free whatever the data.
+// The address of "byte k of state word w" is one v_perm_b32: byte 1 of the
+// result is byte k of w, byte 0 is the lane offset, bytes 2..3 are zero.
+// Rows 1..3 use T0 rotated by 8/16/24 bits (v_alignbit).  The last round takes
+// S(x) = byte 1 of T0[x] and assembles the column with two v_perm_b32.
+// 64 KiB of LDS per workgroup.
+//
+// Tables and the fixed key schedule are generated at compile time from GF(2^8)
+// arithmetic (log/antilog tables over the generator 3) and FIPS-197's affine
+// map; nothing is pasted.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ogm {
+
+// ----------------------------------------------------------------- compile-time tables
+
+constexpr uint8_t xtime(uint8_t a) { return (uint8_t)((a << 1) ^ ((a & 0x80) ? 0x1b : 0x00)); }
+
+struct GfLogExp {
+    uint8_t exp[256];
+    uint8_t log[256];
+};
+
+constexpr GfLogExp make_log_exp() {
+    GfLogExp t{};
+    uint8_t v = 1;
+    for (int i = 0; i < 255; i++) {
+        t.exp[i] = v;
+        t.log[v] = (uint8_t)i;
+        v = (uint8_t)(v ^ xtime(v));  // multiply by the generator 3
+    }
+    t.exp[255] = t.exp[0];
+    return t;
+}
+
+constexpr GfLogExp kLogExp = make_log_exp();
+
+constexpr uint8_t gf_inverse(uint8_t x) {
+    return x == 0 ? 0 : kLogExp.exp[(255 - kLogExp.log[x]) % 255];
+}
+
+constexpr uint8_t rot8(uint8_t x, int k) { return (uint8_t)((x << k) | (x >> (8 - k))); }
+
+constexpr uint8_t sub_byte(uint8_t x) {
+    uint8_t b = gf_inverse(x);
+    return (uint8_t)(b ^ rot8(b, 1) ^ rot8(b, 2) ^ rot8(b, 3) ^ rot8(b, 4) ^ 0x63);
+}
+
+struct AesTables {
+    uint8_t sbox[256];
+    uint32_t t0[256];
+};
+
+constexpr AesTables make_tables() {
+    AesTables t{};
+    for (int x = 0; x < 256; x++) {
+        uint8_t s = sub_byte((uint8_t)x);
+        uint8_t s2 = xtime(s);
+        uint8_t s3 = (uint8_t)(s2 ^ s);
+        t.sbox[x] = s;
+        t.t0[x] = (uint32_t)s2 | ((uint32_t)s << 8) | ((uint32_t)s << 16) | ((uint32_t)s3 << 24);
+    }
+    return t;
+}
+
+constexpr AesTables kTables = make_tables();
+
+// Round keys as 44 little-endian words: word 4r + c is column c of round r.
+struct RoundKeys {
+    uint32_t w[44];
+};
+
+constexpr RoundKeys expand_key(const uint8_t (&key)[16]) {
+    RoundKeys rk{};
+    uint8_t b[176] = {};
+    for (int i = 0; i < 16; i++) b[i] = key[i];
+    uint8_t rcon = 1;
+    for (int i = 4; i < 44; i++) {
+        uint8_t t[4] = {b[4 * i - 4], b[4 * i - 3], b[4 * i - 2], b[4 * i - 1]};
+        if (i % 4 == 0) {
+            uint8_t first = t[0];
+            t[0] = (uint8_t)(kTables.sbox[t[1]] ^ rcon);
+            t[1] = kTables.sbox[t[2]];
+            t[2] = kTables.sbox[t[3]];
+            t[3] = kTables.sbox[first];
+            rcon = xtime(rcon);
+        }
+        for (int k = 0; k < 4; k++) b[4 * i + k] = (uint8_t)(b[4 * i - 16 + k] ^ t[k]);
+    }
+    for (int i = 0; i < 44; i++)
+        rk.w[i] = (uint32_t)b[4 * i] | ((uint32_t)b[4 * i + 1] << 8) | ((uint32_t)b[4 * i + 2] << 16) |
+                  ((uint32_t)b[4 * i + 3] << 24);
+    return rk;
+}
+
+constexpr uint8_t kPrgKeyBytes[16] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+constexpr RoundKeys kPrgKeys = expand_key(kPrgKeyBytes);
+
+// The fixed PRG key schedule, folded into instruction constants after unrolling.
+struct FixedPrgKey {
+    __device__ __forceinline__ constexpr uint32_t operator[](int i) const { return kPrgKeys.w[i]; }
+};
+
+// A per-call key schedule held in kernel arguments (scalar registers).
+struct ArgKey {
+    const RoundKeys& rk;
+    __device__ __forceinline__ uint32_t operator[](int i) const { return rk.w[i]; }
+};
+
+// ----------------------------------------------------------------- LDS table
+
+constexpr int kLdsTableWords = 256 * 64;  // 64 KiB
+
+// Fills the replicated table; every thread of the workgroup takes part.  The
+// caller synchronises the workgroup before the first lookup.
+__device__ __forceinline__ void lds_table_fill(uint32_t* tab, const uint32_t* g_t0) {
+    for (int i = threadIdx.x; i < kLdsTableWords; i += blockDim.x) tab[i] = g_t0[i >> 6];
+}
+
+__device__ __forceinline__ uint32_t lane_offset() { return (threadIdx.x & 63u) << 2; }
+
+__device__ __forceinline__ uint32_t lds_word(const uint32_t* tab, uint32_t byte_addr) {
+    return *(const uint32_t*)((const char*)tab + byte_addr);
+}
+
+// Lookup of T0[byte k of w] in this lane's copy.
+template <int K>
+__device__ __forceinline__ uint32_t tlook(const uint32_t* tab, uint32_t w, uint32_t loff) {
+    constexpr uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + K) << 8);
+    return lds_word(tab, __builtin_amdgcn_perm(w, loff, sel));
+}
+
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
+
+// One full round: out_c = T0[b0(s_c)] ^ T1[b1(s_c+1)] ^ T2[b2(s_c+2)] ^ T3[b3(s_c+3)] ^ rk_c.
+__device__ __forceinline__ uint32_t round_col(const uint32_t* tab, uint32_t loff, uint32_t a, uint32_t b,
+                                              uint32_t c, uint32_t d, uint32_t k) {
+    uint32_t t0 = tlook<0>(tab, a, loff);
+    uint32_t t1 = tlook<1>(tab, b, loff);
+    uint32_t t2 = tlook<2>(tab, c, loff);
+    uint32_t t3 = tlook<3>(tab, d, loff);
+    return t0 ^ rotl32(t1, 8) ^ rotl32(t2, 16) ^ rotl32(t3, 24) ^ k;
+}
+
+// Last round: out_c = S(b0(s_c)) | S(b1(s_c+1)) << 8 | S(b2(s_c+2)) << 16 | S(b3(s_c+3)) << 24, ^ rk.
+__device__ __forceinline__ uint32_t final_col(const uint32_t* tab, uint32_t loff, uint32_t a, uint32_t b,
+                                              uint32_t c, uint32_t d, uint32_t k) {
+    uint32_t t0 = tlook<0>(tab, a, loff);
+    uint32_t t1 = tlook<1>(tab, b, loff);
+    uint32_t t2 = tlook<2>(tab, c, loff);
+    uint32_t t3 = tlook<3>(tab, d, loff);
+    uint32_t lo = __builtin_amdgcn_perm(t1, t0, 0x0C0C0501u);  // (S(b), S(a)) in bytes 1, 0
+    uint32_t hi = __builtin_amdgcn_perm(t3, t2, 0x05010C0Cu);  // (S(d), S(c)) in bytes 3, 2
+    return lo ^ hi ^ k;
+}
+
+template <class RK>
+__device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, uint32_t loff) {
+    uint32_t s0 = in.x ^ rk[0], s1 = in.y ^ rk[1], s2 = in.z ^ rk[2], s3 = in.w ^ rk[3];
+#pragma unroll
+    for (int r = 1; r < 10; r++) {
+        uint32_t n0 = round_col(tab, loff, s0, s1, s2, s3, rk[4 * r + 0]);
+        uint32_t n1 = round_col(tab, loff, s1, s2, s3, s0, rk[4 * r + 1]);
+        uint32_t n2 = round_col(tab, loff, s2, s3, s0, s1, rk[4 * r + 2]);
+        uint32_t n3 = round_col(tab, loff, s3, s0, s1, s2, rk[4 * r + 3]);
+        s0 = n0; s1 = n1; s2 = n2; s3 = n3;
+    }
+    uint4 out;
+    out.x = final_col(tab, loff, s0, s1, s2, s3, rk[40]);
+    out.y = final_col(tab, loff, s1, s2, s3, s0, rk[41]);
+    out.z = final_col(tab, loff, s2, s3, s0, s1, rk[42]);
+    out.w = final_col(tab, loff, s3, s0, s1, s2, rk[43]);
+    return out;
+}
+
+__device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
+    return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
+}
+
+__device__ __forceinline__ uint4 and4(uint4 a, uint32_t m) {
+    return make_uint4(a.x & m, a.y & m, a.z & m, a.w & m);
+}
+
+// G_sigma(s) = AES_K(u) ^ u, u = s ^ sigma (sigma enters byte 0; seeds have
+// bits 0 and 1 clear, so sigma in {0,1,2} never collides).
+__device__ __forceinline__ uint4 prg(uint4 s, uint32_t sigma, const uint32_t* tab, uint32_t loff) {
+    uint4 u = s;
+    u.x ^= sigma;
+    return xor4(aes128_encrypt(u, FixedPrgKey{}, tab, loff), u);
+}
+
+}  // namespace ogm

@@ -1,0 +1,846 @@
+// fss_lib.hip -- kernels and C ABI of the masked-input FSS library (gfx950).
+//
+// What is computed, and where the paper defines it, is stated per entry point
+// in include/oblivgm_fss.h.  This file holds:
+//   k_mask_open     A1  xhat = x0 + x1 + r                       (HBM stream)
+//   k_keygen        A2  dealer: DPF / 2xDCF Gen per row           (VALU, AES)
+//   k_eval          A3/A4/A5  DPF / 2xDCF Eval per row, ballot    (VALU, AES)
+//   k_triples       A6  dealer: Beaver triples                    (VALU, AES)
+//   k_and_open/close, k_and_both, k_gather, k_public_one  A6/A7  (HBM stream)
+// and the host code of the C ABI (validation, launch, match_query plan).
+//
+// Every AES-using kernel runs 1024-thread workgroups that first fill the
+// 64 KiB replicated T-table in LDS (aes_gfx950.hpp).  One thread owns one
+// table row (one element, one predicate, one party); the 64 lanes of a wave
+// own 64 consecutive rows, so the per-level correction words of a wave are one
+// contiguous 1 KiB read, and the wave's 64 output bits are one ballot.
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/oblivgm_fss.h"
+#include "aes_gfx950.hpp"
+
+using namespace ogm;
+
+namespace {
+
+constexpr int kBlock = 1024;            // threads per AES workgroup
+constexpr int kEvalInline = 16;         // eval descriptors carried in kernel arguments
+
+__constant__ AesTables g_tables = kTables;
+
+// ----------------------------------------------------------------- key layout
+
+inline __host__ __device__ uint64_t pad_rows(uint64_t n) { return (n + 63) & ~63ull; }
+
+// Byte offsets of the planes of one DPF / DCF sub-key, relative to its start.
+struct DpfPlanes {
+    uint64_t np;
+    uint32_t nu;
+    __host__ __device__ uint64_t root() const { return 0; }
+    __host__ __device__ uint64_t scw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
+    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)nu); }
+    __host__ __device__ uint64_t tr() const { return tl() + 4 * np; }
+    __host__ __device__ uint64_t cwout() const { return tl() + 8 * np; }
+    __host__ __device__ uint64_t bytes() const { return cwout() + 16 * np; }
+};
+
+struct DcfPlanes {
+    uint64_t np;
+    uint32_t n;
+    __host__ __device__ uint64_t root() const { return 0; }
+    __host__ __device__ uint64_t scw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
+    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)n); }
+    __host__ __device__ uint64_t tr() const { return tl() + 4 * np; }
+    __host__ __device__ uint64_t vcw() const { return tl() + 8 * np; }
+    __host__ __device__ uint64_t fin() const { return tl() + 12 * np; }
+    __host__ __device__ uint64_t bytes() const { return tl() + 16 * np; }
+};
+
+template <class T>
+__device__ __forceinline__ const T& at(const uint8_t* base, uint64_t off, uint64_t row) {
+    return ((const T*)(base + off))[row];
+}
+
+template <class T>
+__device__ __forceinline__ T& at_w(uint8_t* base, uint64_t off, uint64_t row) {
+    return ((T*)(base + off))[row];
+}
+
+__device__ __forceinline__ uint4 clear_tv(uint4 w) {
+    w.x &= ~3u;
+    return w;
+}
+
+// ----------------------------------------------------------------- Eval (A3 / A4)
+
+// Party `party`'s DPF output bit at x (nu = nbits - 7 levels, 128-bit leaf).
+__device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
+                                             uint32_t party, uint32_t x, const uint32_t* tab, uint32_t loff) {
+    const DpfPlanes P{np, nbits - 7};
+    uint4 s = at<uint4>(key, P.root(), row);
+    const uint32_t tlw = at<uint32_t>(key, P.tl(), row);
+    const uint32_t trw = at<uint32_t>(key, P.tr(), row);
+    uint32_t t = party;
+    for (uint32_t i = 0; i < P.nu; i++) {
+        const uint4 cw = at<uint4>(key, P.scw(i), row);
+        const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
+        uint4 w = prg(s, xi, tab, loff);
+        const uint32_t m = 0u - t;
+        s = xor4(clear_tv(w), and4(cw, m));
+        t = (w.x & 1u) ^ (t & ((xi ? trw : tlw) >> i));
+        t &= 1u;
+    }
+    const uint4 cwo = at<uint4>(key, P.cwout(), row);
+    uint4 g = xor4(prg(s, 2u, tab, loff), and4(cwo, 0u - t));
+    const uint32_t idx = x & 127u;
+    const uint32_t word = idx < 64 ? (idx < 32 ? g.x : g.y) : (idx < 96 ? g.z : g.w);
+    return (word >> (idx & 31u)) & 1u;
+}
+
+// Party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in step.
+__device__ __forceinline__ uint32_t range_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
+                                               uint32_t party, uint32_t x, const uint32_t* tab,
+                                               uint32_t loff) {
+    const DcfPlanes P{np, nbits};
+    const uint8_t* ku = key;
+    const uint8_t* kl = key + P.bytes();
+    uint4 su = at<uint4>(ku, P.root(), row);
+    uint4 sl = at<uint4>(kl, P.root(), row);
+    const uint32_t tlu = at<uint32_t>(ku, P.tl(), row), tru = at<uint32_t>(ku, P.tr(), row);
+    const uint32_t vcu = at<uint32_t>(ku, P.vcw(), row), finu = at<uint32_t>(ku, P.fin(), row);
+    const uint32_t tll = at<uint32_t>(kl, P.tl(), row), trl = at<uint32_t>(kl, P.tr(), row);
+    const uint32_t vcl = at<uint32_t>(kl, P.vcw(), row), finl = at<uint32_t>(kl, P.fin(), row);
+    uint32_t tu = party, tv = party, vu = 0, vl = 0;
+    for (uint32_t i = 0; i < nbits; i++) {
+        const uint4 cwu = at<uint4>(ku, P.scw(i), row);
+        const uint4 cwl = at<uint4>(kl, P.scw(i), row);
+        const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
+        const uint4 wu = prg(su, xi, tab, loff);
+        const uint4 wl = prg(sl, xi, tab, loff);
+        vu ^= (wu.x >> 1) ^ (tu & (vcu >> i));
+        vl ^= (wl.x >> 1) ^ (tv & (vcl >> i));
+        su = xor4(clear_tv(wu), and4(cwu, 0u - tu));
+        sl = xor4(clear_tv(wl), and4(cwl, 0u - tv));
+        tu = ((wu.x ^ (tu & ((xi ? tru : tlu) >> i))) & 1u);
+        tv = ((wl.x ^ (tv & ((xi ? trl : tll) >> i))) & 1u);
+    }
+    const uint32_t yu = vu ^ (su.x >> 2) ^ (tu & finu);
+    const uint32_t yl = vl ^ (sl.x >> 2) ^ (tv & finl);
+    return (yu ^ yl ^ (finu >> 31)) & 1u;
+}
+
+struct EvalDesc {
+    const uint8_t* key;
+    const uint32_t* xhat;
+    uint32_t* out;
+    uint64_t n;
+    uint32_t kind;
+    uint32_t nbits;
+    uint32_t party;
+    uint32_t block_start;   // first workgroup of this descriptor
+};
+
+struct EvalBatch {
+    uint32_t count;
+    uint32_t total_blocks;
+    EvalDesc d[kEvalInline];
+};
+
+__global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+
+    uint32_t di = 0;
+    while (di + 1 < batch.count && blockIdx.x >= batch.d[di + 1].block_start) di++;
+    const EvalDesc& D = batch.d[di];
+    const uint64_t row = (uint64_t)(blockIdx.x - D.block_start) * kBlock + threadIdx.x;
+    const uint64_t np = pad_rows(D.n);
+    const uint32_t loff = lane_offset();
+
+    uint32_t bit = 0;
+    if (row < D.n) {
+        const uint32_t x = D.xhat[row];
+        if (D.kind == FSS_EQ)
+            bit = dpf_eval(D.key, np, row, D.nbits, D.party, x, tab, loff);
+        else
+            bit = range_eval(D.key, np, row, D.nbits, D.party, x, tab, loff);
+    }
+    const uint64_t ballot = __ballot(bit);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = row >> 5;          // row is a multiple of 64 here
+        const uint64_t nwords = (D.n + 31) >> 5;
+        if (w < nwords) D.out[w] = (uint32_t)ballot;
+        if (w + 1 < nwords) D.out[w + 1] = (uint32_t)(ballot >> 32);
+    }
+}
+
+// ----------------------------------------------------------------- dealer (A2, A6)
+
+struct DealerArgs {
+    RoundKeys rk;           // AES key schedule of LE64(seed) || "OBLIVGM1"
+    uint8_t* key0;
+    uint8_t* key1;
+    const uint32_t* r;
+    uint64_t n;
+    uint32_t kind;
+    uint32_t nbits;
+    uint32_t query;
+    uint32_t pred;
+    uint32_t a_or_lo;
+    uint32_t hi;
+};
+
+// Counter-mode block (domain, j, query, pred, elem) under the dealer key.
+__device__ __forceinline__ uint4 rng_block(const RoundKeys& rk, uint32_t domain, uint32_t j, uint32_t query,
+                                           uint32_t pred, uint32_t elem, const uint32_t* tab, uint32_t loff) {
+    const uint4 in = make_uint4(domain | (j << 16), query, pred, elem);
+    return aes128_encrypt(in, ArgKey{rk}, tab, loff);
+}
+
+__device__ __forceinline__ uint32_t sel(uint32_t c, uint32_t a, uint32_t b) { return c ? a : b; }
+__device__ __forceinline__ uint4 sel4(uint32_t c, uint4 a, uint4 b) { return c ? a : b; }
+
+// DPF Gen for alpha over nbits; writes both parties' keys of `row`.
+__device__ __forceinline__ void dpf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
+                                        uint32_t alpha, uint4 s0, uint4 s1, const uint32_t* tab, uint32_t loff) {
+    const DpfPlanes P{np, nbits - 7};
+    at_w<uint4>(k0, P.root(), row) = s0;
+    at_w<uint4>(k1, P.root(), row) = s1;
+    uint32_t t0 = 0, t1 = 1, tlw = 0, trw = 0;
+    for (uint32_t i = 0; i < P.nu; i++) {
+        const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
+        const uint4 wl0 = prg(s0, 0u, tab, loff), wr0 = prg(s0, 1u, tab, loff);
+        const uint4 wl1 = prg(s1, 0u, tab, loff), wr1 = prg(s1, 1u, tab, loff);
+        const uint4 keep0 = clear_tv(sel4(a, wr0, wl0)), keep1 = clear_tv(sel4(a, wr1, wl1));
+        const uint4 scw = xor4(clear_tv(sel4(a, wl0, wr0)), clear_tv(sel4(a, wl1, wr1)));
+        const uint32_t tlcw = (wl0.x ^ wl1.x ^ a ^ 1u) & 1u;
+        const uint32_t trcw = (wr0.x ^ wr1.x ^ a) & 1u;
+        const uint32_t tkcw = sel(a, trcw, tlcw);
+        const uint32_t tk0 = sel(a, wr0.x, wl0.x) & 1u, tk1 = sel(a, wr1.x, wl1.x) & 1u;
+        s0 = xor4(keep0, and4(scw, 0u - t0));
+        s1 = xor4(keep1, and4(scw, 0u - t1));
+        t0 = tk0 ^ (t0 & tkcw);
+        t1 = tk1 ^ (t1 & tkcw);
+        at_w<uint4>(k0, P.scw(i), row) = scw;
+        at_w<uint4>(k1, P.scw(i), row) = scw;
+        tlw |= tlcw << i;
+        trw |= trcw << i;
+    }
+    uint4 cw = xor4(prg(s0, 2u, tab, loff), prg(s1, 2u, tab, loff));
+    const uint32_t low = alpha & 127u;
+    const uint32_t bit = 1u << (low & 31u);
+    cw.x ^= (low >> 5) == 0 ? bit : 0u;
+    cw.y ^= (low >> 5) == 1 ? bit : 0u;
+    cw.z ^= (low >> 5) == 2 ? bit : 0u;
+    cw.w ^= (low >> 5) == 3 ? bit : 0u;
+    at_w<uint32_t>(k0, P.tl(), row) = tlw;
+    at_w<uint32_t>(k1, P.tl(), row) = tlw;
+    at_w<uint32_t>(k0, P.tr(), row) = trw;
+    at_w<uint32_t>(k1, P.tr(), row) = trw;
+    at_w<uint4>(k0, P.cwout(), row) = cw;
+    at_w<uint4>(k1, P.cwout(), row) = cw;
+}
+
+// DCF Gen for [x < alpha] over nbits (Z_2 values); `wrap0/1` go to fin bit 31.
+__device__ __forceinline__ void dcf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
+                                        uint32_t alpha, uint4 s0, uint4 s1, uint32_t wrap0, uint32_t wrap1,
+                                        const uint32_t* tab, uint32_t loff) {
+    const DcfPlanes P{np, nbits};
+    at_w<uint4>(k0, P.root(), row) = s0;
+    at_w<uint4>(k1, P.root(), row) = s1;
+    uint32_t t0 = 0, t1 = 1, va = 0, tlw = 0, trw = 0, vw = 0;
+    for (uint32_t i = 0; i < nbits; i++) {
+        const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
+        const uint4 wl0 = prg(s0, 0u, tab, loff), wr0 = prg(s0, 1u, tab, loff);
+        const uint4 wl1 = prg(s1, 0u, tab, loff), wr1 = prg(s1, 1u, tab, loff);
+        const uint4 keep0 = clear_tv(sel4(a, wr0, wl0)), keep1 = clear_tv(sel4(a, wr1, wl1));
+        const uint4 scw = xor4(clear_tv(sel4(a, wl0, wr0)), clear_tv(sel4(a, wl1, wr1)));
+        const uint32_t vlose = (sel(a, wl0.x, wr0.x) ^ sel(a, wl1.x, wr1.x)) >> 1;
+        const uint32_t vkeep = (sel(a, wr0.x, wl0.x) ^ sel(a, wr1.x, wl1.x)) >> 1;
+        const uint32_t vcw = (vlose ^ va ^ a) & 1u;
+        va = (va ^ vkeep ^ vcw) & 1u;
+        const uint32_t tlcw = (wl0.x ^ wl1.x ^ a ^ 1u) & 1u;
+        const uint32_t trcw = (wr0.x ^ wr1.x ^ a) & 1u;
+        const uint32_t tkcw = sel(a, trcw, tlcw);
+        const uint32_t tk0 = sel(a, wr0.x, wl0.x) & 1u, tk1 = sel(a, wr1.x, wl1.x) & 1u;
+        s0 = xor4(keep0, and4(scw, 0u - t0));
+        s1 = xor4(keep1, and4(scw, 0u - t1));
+        t0 = tk0 ^ (t0 & tkcw);
+        t1 = tk1 ^ (t1 & tkcw);
+        at_w<uint4>(k0, P.scw(i), row) = scw;
+        at_w<uint4>(k1, P.scw(i), row) = scw;
+        tlw |= tlcw << i;
+        trw |= trcw << i;
+        vw |= vcw << i;
+    }
+    const uint32_t fin = ((s0.x >> 2) ^ (s1.x >> 2) ^ va) & 1u;
+    at_w<uint32_t>(k0, P.tl(), row) = tlw;
+    at_w<uint32_t>(k1, P.tl(), row) = tlw;
+    at_w<uint32_t>(k0, P.tr(), row) = trw;
+    at_w<uint32_t>(k1, P.tr(), row) = trw;
+    at_w<uint32_t>(k0, P.vcw(), row) = vw;
+    at_w<uint32_t>(k1, P.vcw(), row) = vw;
+    at_w<uint32_t>(k0, P.fin(), row) = fin | (wrap0 << 31);
+    at_w<uint32_t>(k1, P.fin(), row) = fin | (wrap1 << 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_keygen(DealerArgs A) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t row = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row >= A.n) return;
+    const uint32_t loff = lane_offset();
+    const uint64_t np = pad_rows(A.n);
+    const uint32_t mask = A.nbits >= 32 ? 0xFFFFFFFFu : ((1u << A.nbits) - 1u);
+    const uint32_t r = A.r[row];
+    const uint32_t e = (uint32_t)row;
+    const uint4 s0 = clear_tv(rng_block(A.rk, 3, 0, A.query, A.pred, e, tab, loff));
+    const uint4 s1 = clear_tv(rng_block(A.rk, 3, 1, A.query, A.pred, e, tab, loff));
+    if (A.kind == FSS_EQ) {
+        dpf_gen(A.key0, A.key1, np, row, A.nbits, (A.a_or_lo + r) & mask, s0, s1, tab, loff);
+    } else {
+        const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
+        const uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
+        const uint32_t c1 = c0 ^ (L > U ? 1u : 0u);
+        dcf_gen(A.key0, A.key1, np, row, A.nbits, U, s0, s1, c0, c1, tab, loff);
+        const uint4 l0 = clear_tv(rng_block(A.rk, 3, 3, A.query, A.pred, e, tab, loff));
+        const uint4 l1 = clear_tv(rng_block(A.rk, 3, 4, A.query, A.pred, e, tab, loff));
+        const uint64_t half = DcfPlanes{np, A.nbits}.bytes();
+        dcf_gen(A.key0 + half, A.key1 + half, np, row, A.nbits, L, l0, l1, 0u, 0u, tab, loff);
+    }
+}
+
+struct TripleArgs {
+    RoundKeys rk;
+    uint32_t* t0;           // a0 | b0 | c0
+    uint32_t* t1;           // a1 | b1 | c1
+    uint64_t nwords;
+    uint32_t query;
+    uint32_t and_id;
+};
+
+// Thread m makes triple words 4m .. 4m+3 from stream blocks 5m .. 5m+4.
+__global__ __launch_bounds__(kBlock) void k_triples(TripleArgs A) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (4 * m >= A.nwords) return;
+    const uint32_t loff = lane_offset();
+    uint32_t R[20];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const uint4 b = rng_block(A.rk, 4, 0, A.query, A.and_id, (uint32_t)(5 * m + q), tab, loff);
+        R[4 * q + 0] = b.x; R[4 * q + 1] = b.y; R[4 * q + 2] = b.z; R[4 * q + 3] = b.w;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint64_t w = 4 * m + q;
+        if (w < A.nwords) {
+            const uint32_t a0 = R[5 * q], a1 = R[5 * q + 1], b0 = R[5 * q + 2], b1 = R[5 * q + 3];
+            const uint32_t c0 = R[5 * q + 4];
+            A.t0[w] = a0; A.t0[A.nwords + w] = b0; A.t0[2 * A.nwords + w] = c0;
+            A.t1[w] = a1; A.t1[A.nwords + w] = b1; A.t1[2 * A.nwords + w] = ((a0 ^ a1) & (b0 ^ b1)) ^ c0;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- streaming kernels (A1, A6, A7)
+
+__global__ void k_mask_open(uint64_t n, const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1,
+                            const uint32_t* __restrict__ r, uint32_t* __restrict__ xhat) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        xhat[i] = x0[i] + x1[i] + r[i];
+}
+
+__device__ __forceinline__ uint32_t pad_mask(uint64_t w, uint64_t nrows) {
+    const uint64_t first = w * 32;
+    if (first + 32 <= nrows) return 0xFFFFFFFFu;
+    if (first >= nrows) return 0u;
+    return (1u << (uint32_t)(nrows - first)) - 1u;
+}
+
+__global__ void k_and_open(uint64_t nwords, const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+                           const uint32_t* __restrict__ trip, uint32_t* __restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        out[w] = x[w] ^ trip[w];
+        out[nwords + w] = y[w] ^ trip[nwords + w];
+    }
+}
+
+__global__ void k_and_close(uint64_t nwords, uint64_t nrows, uint32_t party, const uint32_t* __restrict__ trip,
+                            const uint32_t* __restrict__ de, uint32_t* __restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        const uint32_t d = de[w], e = de[nwords + w];
+        uint32_t z = trip[2 * nwords + w] ^ (d & trip[nwords + w]) ^ (e & trip[w]);
+        if (party == 0) z ^= d & e;
+        out[w] = z & pad_mask(w, nrows);
+    }
+}
+
+// Both simulated parties at once: open, exchange (an XOR), close.
+__global__ void k_and_both(uint64_t nwords, uint64_t nrows, const uint32_t* __restrict__ x0,
+                           const uint32_t* __restrict__ x1, const uint32_t* __restrict__ y0,
+                           const uint32_t* __restrict__ y1, const uint32_t* __restrict__ t0,
+                           const uint32_t* __restrict__ t1, uint32_t* __restrict__ z0, uint32_t* __restrict__ z1) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        const uint32_t a0 = t0[w], b0 = t0[nwords + w], c0 = t0[2 * nwords + w];
+        const uint32_t a1 = t1[w], b1 = t1[nwords + w], c1 = t1[2 * nwords + w];
+        const uint32_t d = (x0[w] ^ a0) ^ (x1[w] ^ a1);
+        const uint32_t e = (y0[w] ^ b0) ^ (y1[w] ^ b1);
+        const uint32_t pm = pad_mask(w, nrows);
+        z0[w] = (c0 ^ (d & b0) ^ (e & a0) ^ (d & e)) & pm;
+        z1[w] = (c1 ^ (d & b1) ^ (e & a1)) & pm;
+    }
+}
+
+// out_b[e] = bit idx[e] of m_b (each party gathers its own share at a public
+// index); an index >= nsrc gathers 0 for both parties.
+__global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ m0,
+                         const uint32_t* __restrict__ m1, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t b0 = 0, b1 = 0;
+    if (e < n && idx[e] < nsrc) {
+        const uint32_t v = idx[e];
+        b0 = (m0[v >> 5] >> (v & 31u)) & 1u;
+        b1 = (m1[v >> 5] >> (v & 31u)) & 1u;
+    }
+    const uint64_t g0 = __ballot(b0), g1 = __ballot(b1);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = e >> 5, nwords = (n + 31) >> 5;
+        if (w < nwords) { o0[w] = (uint32_t)g0; o1[w] = (uint32_t)g1; }
+        if (w + 1 < nwords) { o0[w + 1] = (uint32_t)(g0 >> 32); o1[w + 1] = (uint32_t)(g1 >> 32); }
+    }
+}
+
+// Shares of the public constant 1 over nrows rows.
+__global__ void k_public_one(uint64_t nwords, uint64_t nrows, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        o0[w] = pad_mask(w, nrows);
+        o1[w] = 0u;
+    }
+}
+
+// ----------------------------------------------------------------- host side
+
+thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FSS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return FSS_OK;
+}
+
+bool valid_nbits(uint32_t nbits) { return nbits >= 8 && nbits <= 32; }
+
+uint64_t key_bytes(int32_t kind, uint32_t nbits) {
+    if (!valid_nbits(nbits)) return 0;
+    if (kind == FSS_EQ) return 16ull * nbits - 72;
+    if (kind == FSS_RANGE) return 2ull * (16ull * nbits + 32);
+    return 0;
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+RoundKeys dealer_key(uint64_t seed) {
+    uint8_t k[16];
+    for (int i = 0; i < 8; i++) k[i] = (uint8_t)(seed >> (8 * i));
+    memcpy(k + 8, "OBLIVGM1", 8);
+    return expand_key(k);
+}
+
+int check_batch(const fss_keybatch* k, int32_t want_kind, const char* who) {
+    if (!k) return fail(FSS_EINVAL, "%s: key batch is NULL", who);
+    if (k->kind != want_kind) return fail(FSS_EINVAL, "%s: key batch kind %d, expected %d", who, k->kind, want_kind);
+    if (!valid_nbits(k->nbits)) return fail(FSS_EINVAL, "%s: nbits %u outside 8..32", who, k->nbits);
+    if (k->n > 0xFFFFFFFFull) return fail(FSS_EUNSUPPORTED, "%s: more than 2^32 rows", who);
+    return FSS_OK;
+}
+
+// Enqueue one k_eval launch for up to kEvalInline descriptors (heaviest first).
+int launch_eval(EvalDesc* descs, uint32_t count, hipStream_t stream) {
+    // range walks cost ~2.5x an equality walk: put them first so the tail is light
+    EvalBatch b{};
+    uint32_t k = 0;
+    for (int pass = 0; pass < 2; pass++)
+        for (uint32_t i = 0; i < count; i++)
+            if ((pass == 0) == (descs[i].kind == FSS_RANGE) && descs[i].n > 0) b.d[k++] = descs[i];
+    b.count = k;
+    uint32_t blocks = 0;
+    for (uint32_t i = 0; i < k; i++) {
+        b.d[i].block_start = blocks;
+        blocks += (uint32_t)((b.d[i].n + kBlock - 1) / kBlock);
+    }
+    b.total_blocks = blocks;
+    if (blocks == 0) return FSS_OK;
+    hipLaunchKernelGGL(k_eval, dim3(blocks), dim3(kBlock), 0, stream, b);
+    return check_launch("k_eval");
+}
+
+int eval_one(int32_t party, const fss_keybatch* k, int32_t kind, const uint32_t* d_xhat, uint32_t* d_out,
+             void* stream, const char* who) {
+    int rc = check_batch(k, kind, who);
+    if (rc) return rc;
+    if (party != 0 && party != 1) return fail(FSS_EINVAL, "%s: party %d is not 0 or 1", who, party);
+    if (k->n == 0) return FSS_OK;
+    if (!d_xhat || !d_out || !k->key[party]) return fail(FSS_EINVAL, "%s: NULL buffer", who);
+    if (!aligned256(k->key[party])) return fail(FSS_EINVAL, "%s: key buffer not 256-byte aligned", who);
+    EvalDesc d{};
+    d.key = (const uint8_t*)k->key[party];
+    d.xhat = d_xhat;
+    d.out = d_out;
+    d.n = k->n;
+    d.kind = (uint32_t)kind;
+    d.nbits = k->nbits;
+    d.party = (uint32_t)party;
+    return launch_eval(&d, 1, (hipStream_t)stream);
+}
+
+int launch_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nwords, uint32_t* t0, uint32_t* t1,
+                   hipStream_t stream) {
+    if (nwords == 0) return FSS_OK;
+    TripleArgs A{};
+    A.rk = dealer_key(seed);
+    A.t0 = t0;
+    A.t1 = t1;
+    A.nwords = nwords;
+    A.query = query_id;
+    A.and_id = and_id;
+    const uint64_t threads = (nwords + 3) / 4;
+    hipLaunchKernelGGL(k_triples, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, A);
+    return check_launch("k_triples");
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+uint64_t fss_key_bytes(int32_t kind, uint32_t nbits) { return key_bytes(kind, nbits); }
+
+uint64_t fss_keybatch_bytes(int32_t kind, uint32_t nbits, uint64_t n) { return key_bytes(kind, nbits) * pad_rows(n); }
+
+const char* fss_last_error(void) { return t_err.c_str(); }
+
+const char* fss_version(void) { return "oblivgm-fss 0.1 gfx950 lds-ttable"; }
+
+int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const uint32_t* d_r, uint32_t* d_xhat,
+                  void* stream) {
+    t_err.clear();
+    if (n == 0) return FSS_OK;
+    if (!d_x0 || !d_x1 || !d_r || !d_xhat) return fail(FSS_EINVAL, "fss_mask_open: NULL buffer");
+    hipLaunchKernelGGL(k_mask_open, dim3(grid_for(n, 256, 8192)), dim3(256), 0, (hipStream_t)stream, n, d_x0, d_x1,
+                       d_r, d_xhat);
+    return check_launch("k_mask_open");
+}
+
+int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or_lo, uint32_t hi,
+               const uint32_t* d_r, const fss_keybatch* out, void* stream) {
+    t_err.clear();
+    if (!out) return fail(FSS_EINVAL, "fss_keygen: out is NULL");
+    if (out->kind != FSS_EQ && out->kind != FSS_RANGE) return fail(FSS_EINVAL, "fss_keygen: bad kind %d", out->kind);
+    if (!valid_nbits(out->nbits)) return fail(FSS_EINVAL, "fss_keygen: nbits %u outside 8..32", out->nbits);
+    if (out->n > 0xFFFFFFFFull) return fail(FSS_EUNSUPPORTED, "fss_keygen: more than 2^32 rows");
+    const uint64_t lim = 1ull << out->nbits;
+    if (out->kind == FSS_EQ && a_or_lo >= lim) return fail(FSS_EINVAL, "fss_keygen: a does not fit nbits");
+    if (out->kind == FSS_RANGE) {
+        if (a_or_lo > hi) return fail(FSS_EINVAL, "fss_keygen: lo %u > hi %u", a_or_lo, hi);
+        if (hi >= lim) return fail(FSS_EINVAL, "fss_keygen: hi does not fit nbits (full domain not expressible)");
+    }
+    if (out->n == 0) return FSS_OK;
+    if (!d_r || !out->key[0] || !out->key[1]) return fail(FSS_EINVAL, "fss_keygen: NULL buffer");
+    if (!aligned256(out->key[0]) || !aligned256(out->key[1]))
+        return fail(FSS_EINVAL, "fss_keygen: key buffers must be 256-byte aligned");
+    DealerArgs A{};
+    A.rk = dealer_key(seed);
+    A.key0 = (uint8_t*)out->key[0];
+    A.key1 = (uint8_t*)out->key[1];
+    A.r = d_r;
+    A.n = out->n;
+    A.kind = (uint32_t)out->kind;
+    A.nbits = out->nbits;
+    A.query = query_id;
+    A.pred = pred_id;
+    A.a_or_lo = a_or_lo;
+    A.hi = hi;
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)((out->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, A);
+    return check_launch("k_keygen");
+}
+
+int fss_eval_eq(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits, void* stream) {
+    t_err.clear();
+    return eval_one(party, k, FSS_EQ, d_xhat, d_out_bits, stream, "fss_eval_eq");
+}
+
+int fss_eval_lt(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits, void* stream) {
+    t_err.clear();
+    return eval_one(party, k, FSS_RANGE, d_xhat, d_out_bits, stream, "fss_eval_lt");
+}
+
+int ss_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nwords, uint32_t* d_trip0,
+               uint32_t* d_trip1, void* stream) {
+    t_err.clear();
+    if (nwords == 0) return FSS_OK;
+    if (!d_trip0 || !d_trip1) return fail(FSS_EINVAL, "ss_triples: NULL buffer");
+    if (nwords > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "ss_triples: too many words");
+    return launch_triples(seed, query_id, and_id, nwords, d_trip0, d_trip1, (hipStream_t)stream);
+}
+
+int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, const uint32_t* d_y,
+           const uint32_t* d_triple, const uint32_t* d_de_open, uint32_t* d_out, void* stream) {
+    t_err.clear();
+    if (party != 0 && party != 1) return fail(FSS_EINVAL, "ss_and: party %d is not 0 or 1", party);
+    const uint64_t nwords = (nrows + 31) / 32;
+    if (nwords == 0) return FSS_OK;
+    if (!d_triple || !d_out) return fail(FSS_EINVAL, "ss_and: NULL buffer");
+    const unsigned grid = grid_for(nwords, 256, 8192);
+    if (phase == SS_AND_OPEN) {
+        if (!d_x || !d_y) return fail(FSS_EINVAL, "ss_and: NULL input");
+        hipLaunchKernelGGL(k_and_open, dim3(grid), dim3(256), 0, (hipStream_t)stream, nwords, d_x, d_y, d_triple,
+                           d_out);
+        return check_launch("k_and_open");
+    }
+    if (phase == SS_AND_CLOSE) {
+        if (!d_de_open) return fail(FSS_EINVAL, "ss_and: NULL opened values");
+        hipLaunchKernelGGL(k_and_close, dim3(grid), dim3(256), 0, (hipStream_t)stream, nwords, nrows,
+                           (uint32_t)party, d_triple, d_de_open, d_out);
+        return check_launch("k_and_close");
+    }
+    return fail(FSS_EINVAL, "ss_and: phase %d is neither OPEN nor CLOSE", phase);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- match_query
+
+namespace {
+
+struct Shares {
+    uint32_t* p[2] = {nullptr, nullptr};   // both null: the public constant 1
+    bool is_public() const { return p[0] == nullptr; }
+};
+
+struct Arena {
+    uint8_t* base;
+    uint64_t size;
+    uint64_t used;
+    uint32_t* take(uint64_t words) {
+        uint64_t bytes = (words * 4 + 255) & ~255ull;
+        if (used + bytes > size) return nullptr;
+        uint32_t* p = (uint32_t*)(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+uint64_t words_of(uint64_t rows) { return (rows + 31) / 32; }
+
+// Workspace bytes the plan needs: predicate bits, vertex / edge results,
+// hop temporaries and one triple buffer, per party.
+uint64_t plan_workspace(const match_plan* P) {
+    auto rnd = [](uint64_t words) { return (words * 4 + 255) & ~255ull; };
+    const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
+    uint64_t total = 0;
+    // predicate bits, and at most one AND result per predicate in the folds
+    for (uint32_t k = 0; k < P->n_pred; k++)
+        total += 4 * rnd((uint32_t)P->preds[k].target < P->n_qv ? wv : we);
+    // per hop: two gathers and two AND results, both parties
+    if (P->n_qv > 1) total += 8 * (uint64_t)(P->n_qv - 1) * rnd(we);
+    const uint64_t wmax = wv > we ? wv : we;
+    total += 2 * rnd(3 * wmax);
+    return total;
+}
+
+struct PlanRun {
+    const match_plan* P;
+    hipStream_t s;
+    Arena ws;
+    uint32_t next_and = 0;
+    uint32_t* trip[2] = {nullptr, nullptr};
+
+    int AND(const Shares& x, const Shares& y, uint64_t nrows, Shares* z) {
+        if (x.is_public()) { *z = y; return FSS_OK; }
+        if (y.is_public()) { *z = x; return FSS_OK; }
+        const uint64_t nw = words_of(nrows);
+        Shares out;
+        for (int b = 0; b < 2; b++)
+            if (!(out.p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+        int rc = launch_triples(P->seed, P->query_id, next_and++, nw, trip[0], trip[1], s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_and_both, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, x.p[0], x.p[1],
+                           y.p[0], y.p[1], trip[0], trip[1], out.p[0], out.p[1]);
+        *z = out;
+        return check_launch("k_and_both");
+    }
+
+    int gather(const Shares& m, const uint32_t* idx, Shares* out) {
+        if (m.is_public()) { *out = m; return FSS_OK; }
+        const uint64_t ne = P->n_edges, nw = words_of(ne);
+        for (int b = 0; b < 2; b++)
+            if (!(out->p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, P->n_vertices, idx,
+                           m.p[0], m.p[1], out->p[0], out->p[1]);
+        return check_launch("k_gather");
+    }
+
+    int emit(const Shares& m, uint64_t nrows, uint64_t word_offset) {
+        const uint64_t nw = words_of(nrows);
+        uint32_t* o0 = P->d_out[0] + word_offset;
+        uint32_t* o1 = P->d_out[1] + word_offset;
+        if (m.is_public()) {
+            hipLaunchKernelGGL(k_public_one, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, o0, o1);
+            return check_launch("k_public_one");
+        }
+        for (int b = 0; b < 2; b++) {
+            hipError_t e = hipMemcpyAsync(b ? o1 : o0, m.p[b], nw * 4, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail(FSS_EDEVICE, "match_query: copy: %s", hipGetErrorString(e));
+        }
+        return FSS_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+uint64_t match_workspace_bytes(const match_plan* plan) {
+    if (!plan || plan->n_qv == 0 || plan->n_qv > FSS_MAX_QV || plan->n_pred > FSS_MAX_PREDS) return 0;
+    if (plan->n_pred && !plan->preds) return 0;
+    return plan_workspace(plan);
+}
+
+int match_query(const match_plan* P, int32_t party_mask, void* stream) {
+    t_err.clear();
+    if (!P) return fail(FSS_EINVAL, "match_query: plan is NULL");
+    if (party_mask != 3) return fail(FSS_EUNSUPPORTED, "match_query: party_mask must be 3 (both parties simulated)");
+    if (P->n_qv == 0 || P->n_qv > FSS_MAX_QV) return fail(FSS_EINVAL, "match_query: n_qv %u outside 1..%d", P->n_qv, FSS_MAX_QV);
+    if (P->n_pred > FSS_MAX_PREDS) return fail(FSS_EINVAL, "match_query: more than %d predicates", FSS_MAX_PREDS);
+    if (P->n_pred && !P->preds) return fail(FSS_EINVAL, "match_query: preds is NULL");
+    if (P->n_vertices > 0xFFFFFFFFull || P->n_edges > 0xFFFFFFFFull)
+        return fail(FSS_EUNSUPPORTED, "match_query: more than 2^32 rows");
+    if (!P->d_out[0] || !P->d_out[1]) return fail(FSS_EINVAL, "match_query: NULL output");
+    if (P->n_qv > 1 && (!P->d_src || !P->d_dst)) return fail(FSS_EINVAL, "match_query: NULL edge endpoints");
+    const uint32_t ntarget = 2 * P->n_qv - 1;
+    for (uint32_t k = 0; k < P->n_pred; k++) {
+        const fss_pred& p = P->preds[k];
+        if (p.target < 0 || (uint32_t)p.target >= ntarget)
+            return fail(FSS_EINVAL, "match_query: predicate %u targets %d (of %u)", k, p.target, ntarget);
+        const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
+        if (!p.keys || (p.keys->kind != FSS_EQ && p.keys->kind != FSS_RANGE))
+            return fail(FSS_EINVAL, "match_query: predicate %u has no valid key batch", k);
+        int rc = check_batch(p.keys, p.keys->kind, "match_query");
+        if (rc) return rc;
+        if (p.keys->n != rows) return fail(FSS_EINVAL, "match_query: predicate %u keys cover %llu rows, table has %llu",
+                                           k, (unsigned long long)p.keys->n, (unsigned long long)rows);
+        if (rows && (!p.d_xhat || !p.keys->key[0] || !p.keys->key[1]))
+            return fail(FSS_EINVAL, "match_query: predicate %u has a NULL buffer", k);
+        if (rows && (!aligned256(p.keys->key[0]) || !aligned256(p.keys->key[1])))
+            return fail(FSS_EINVAL, "match_query: predicate %u key buffers not 256-byte aligned", k);
+    }
+    const uint64_t need = plan_workspace(P);
+    if (!P->d_workspace || P->workspace_bytes < need)
+        return fail(FSS_ENOMEM, "match_query: workspace needs %llu bytes", (unsigned long long)need);
+
+    PlanRun R{P, (hipStream_t)stream, Arena{(uint8_t*)P->d_workspace, P->workspace_bytes, 0}};
+    const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
+    const uint64_t wmax = wv > we ? wv : we;
+    for (int b = 0; b < 2; b++)
+        if (!(R.trip[b] = R.ws.take(3 * wmax))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+
+    // 1. every predicate, both parties, in launches of up to kEvalInline descriptors
+    Shares pbits[FSS_MAX_PREDS];
+    EvalDesc descs[kEvalInline];
+    uint32_t nd = 0;
+    for (uint32_t k = 0; k < P->n_pred; k++) {
+        const fss_pred& p = P->preds[k];
+        const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
+        for (int b = 0; b < 2; b++) {
+            if (!(pbits[k].p[b] = R.ws.take(words_of(rows)))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+            if (rows == 0) continue;
+            EvalDesc& d = descs[nd++];
+            d = EvalDesc{};
+            d.key = (const uint8_t*)p.keys->key[b];
+            d.xhat = p.d_xhat;
+            d.out = pbits[k].p[b];
+            d.n = rows;
+            d.kind = (uint32_t)p.keys->kind;
+            d.nbits = p.keys->nbits;
+            d.party = (uint32_t)b;
+            if (nd == kEvalInline) {
+                int rc = launch_eval(descs, nd, R.s);
+                if (rc) return rc;
+                nd = 0;
+            }
+        }
+    }
+    if (nd) {
+        int rc = launch_eval(descs, nd, R.s);
+        if (rc) return rc;
+    }
+
+    // 2. AND-fold per query vertex, then per query edge
+    Shares m[FSS_MAX_QV], q[FSS_MAX_QV];
+    for (uint32_t i = 0; i < P->n_qv; i++) {
+        for (uint32_t k = 0; k < P->n_pred; k++)
+            if ((uint32_t)P->preds[k].target == i) {
+                int rc = R.AND(m[i], pbits[k], P->n_vertices, &m[i]);
+                if (rc) return rc;
+            }
+    }
+    for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
+        for (uint32_t k = 0; k < P->n_pred; k++)
+            if ((uint32_t)P->preds[k].target == P->n_qv + j) {
+                int rc = R.AND(q[j], pbits[k], P->n_edges, &q[j]);
+                if (rc) return rc;
+            }
+    }
+    if (P->n_qv == 1) return R.emit(m[0], P->n_vertices, 0);
+
+    // 3. hops: gather both endpoints' shares, then two ANDs
+    for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
+        Shares g, h, r1, r2;
+        int rc = R.gather(m[j], P->d_src, &g);
+        if (!rc) rc = R.gather(m[j + 1], P->d_dst, &h);
+        if (!rc) rc = R.AND(g, h, P->n_edges, &r1);
+        if (!rc) rc = R.AND(r1, q[j], P->n_edges, &r2);
+        if (!rc) rc = R.emit(r2, P->n_edges, (uint64_t)j * we);
+        if (rc) return rc;
+    }
+    return FSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+"""Python binding of ``liboblivgm_fss.so``: the C ABI of include/oblivgm_fss.h,
+same names, argument marshalling only.  Device buffers are torch tensors on a
+HIP device; ``stream`` defaults to torch's current stream.  Every computation
+runs in the library's HIP kernels; there is no host fallback: importing this
+module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import build as _build
+
+EQ, RANGE = 0, 1
+SS_AND_OPEN, SS_AND_CLOSE = 0, 1
+MAX_QV, MAX_PREDS = 8, 32
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+
+
+class FssError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class fss_keybatch(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nbits", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("key", ctypes.c_void_p * 2)]
+
+
+class fss_pred(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("keys", ctypes.POINTER(fss_keybatch)), ("d_xhat", ctypes.c_void_p)]
+
+
+class match_plan(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("query_id", ctypes.c_uint32), ("n_qv", ctypes.c_uint32),
+                ("n_pred", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n_vertices", ctypes.c_uint64), ("n_edges", ctypes.c_uint64),
+                ("d_src", ctypes.c_void_p), ("d_dst", ctypes.c_void_p),
+                ("preds", ctypes.POINTER(fss_pred)), ("d_out", ctypes.c_void_p * 2),
+                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(_build.LIB):
+        raise ImportError(f"HIP library not built: {_build.LIB} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_build.LIB)
+    P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    sigs = {
+        "fss_key_bytes": ([i32, u32], u64),
+        "fss_keybatch_bytes": ([i32, u32, u64], u64),
+        "fss_last_error": ([], ctypes.c_char_p),
+        "fss_version": ([], ctypes.c_char_p),
+        "fss_mask_open": ([u64, P, P, P, P, P], ctypes.c_int),
+        "fss_keygen": ([u64, u32, u32, u32, u32, P, ctypes.POINTER(fss_keybatch), P], ctypes.c_int),
+        "fss_eval_eq": ([i32, ctypes.POINTER(fss_keybatch), P, P, P], ctypes.c_int),
+        "fss_eval_lt": ([i32, ctypes.POINTER(fss_keybatch), P, P, P], ctypes.c_int),
+        "ss_triples": ([u64, u32, u32, u64, P, P, P], ctypes.c_int),
+        "ss_and": ([i32, i32, u64, P, P, P, P, P, P], ctypes.c_int),
+        "match_workspace_bytes": ([ctypes.POINTER(match_plan)], u64),
+        "match_query": ([ctypes.POINTER(match_plan), i32, P], ctypes.c_int),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+LIB = _load()
+EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
+           "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
+           "match_query")
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FssError(rc, LIB.fss_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return stream
+
+
+def words(rows: int) -> int:
+    return (rows + 31) // 32
+
+
+def version() -> str:
+    return LIB.fss_version().decode()
+
+
+def fss_key_bytes(kind: int, nbits: int) -> int:
+    return int(LIB.fss_key_bytes(kind, nbits))
+
+
+def fss_keybatch_bytes(kind: int, nbits: int, n: int) -> int:
+    return int(LIB.fss_keybatch_bytes(kind, nbits, n))
+
+
+class KeyBatch:
+    """One predicate's keys for n rows, both parties, in device memory."""
+
+    def __init__(self, kind: int, nbits: int, n: int, device=None):
+        self.kind, self.nbits, self.n = kind, nbits, n
+        nbytes = fss_keybatch_bytes(kind, nbits, n)
+        if nbytes == 0 and n > 0:
+            raise FssError(EINVAL, f"bad key kind {kind} / nbits {nbits}")
+        dev = device or torch.device("cuda")
+        # torch's caching allocator returns 256-byte aligned blocks of >= 512 bytes
+        self.key = [torch.empty(max(nbytes, 512), dtype=torch.uint8, device=dev) for _ in range(2)]
+        self.c = fss_keybatch(kind, nbits, n, (ctypes.c_void_p * 2)(self.key[0].data_ptr(), self.key[1].data_ptr()))
+
+    @property
+    def bytes_per_party(self) -> int:
+        return fss_keybatch_bytes(self.kind, self.nbits, self.n)
+
+
+def fss_mask_open(x0, x1, r, xhat, stream=None):
+    _check(LIB.fss_mask_open(x0.numel(), _ptr(x0), _ptr(x1), _ptr(r), _ptr(xhat), _stream(stream)))
+
+
+def fss_keygen(seed: int, query_id: int, pred_id: int, a_or_lo: int, hi: int, r, out: KeyBatch, stream=None):
+    _check(LIB.fss_keygen(seed, query_id, pred_id, a_or_lo, hi, _ptr(r), ctypes.byref(out.c), _stream(stream)))
+
+
+def fss_eval_eq(party: int, keys: KeyBatch, xhat, out_bits, stream=None):
+    _check(LIB.fss_eval_eq(party, ctypes.byref(keys.c), _ptr(xhat), _ptr(out_bits), _stream(stream)))
+
+
+def fss_eval_lt(party: int, keys: KeyBatch, xhat, out_bits, stream=None):
+    _check(LIB.fss_eval_lt(party, ctypes.byref(keys.c), _ptr(xhat), _ptr(out_bits), _stream(stream)))
+
+
+def ss_triples(seed: int, query_id: int, and_id: int, nwords: int, trip0, trip1, stream=None):
+    _check(LIB.ss_triples(seed, query_id, and_id, nwords, _ptr(trip0), _ptr(trip1), _stream(stream)))
+
+
+def ss_and(phase: int, party: int, nrows: int, x, y, triple, de_open, out, stream=None):
+    _check(LIB.ss_and(phase, party, nrows, _ptr(x), _ptr(y), _ptr(triple), _ptr(de_open), _ptr(out),
+                      _stream(stream)))
+
+
+class Plan:
+    """A match_plan with its ctypes storage kept alive."""
+
+    def __init__(self, seed, query_id, n_qv, n_vertices, n_edges, preds, src=None, dst=None):
+        """preds: list of (target, KeyBatch, xhat tensor)."""
+        self._preds = (fss_pred * max(1, len(preds)))()
+        self._keep = []
+        for i, (target, kb, xhat) in enumerate(preds):
+            self._preds[i] = fss_pred(target, 0, ctypes.pointer(kb.c), _ptr(xhat))
+            self._keep.append((kb, xhat))
+        self.c = match_plan()
+        self.c.seed = seed
+        self.c.query_id = query_id
+        self.c.n_qv = n_qv
+        self.c.n_pred = len(preds)
+        self.c.n_vertices = n_vertices
+        self.c.n_edges = n_edges
+        self.c.d_src = _ptr(src)
+        self.c.d_dst = _ptr(dst)
+        self.c.preds = ctypes.cast(self._preds, ctypes.POINTER(fss_pred))
+        self._keep.append((src, dst))
+        self.out = None
+        self.workspace = None
+
+    def out_words(self) -> int:
+        if self.c.n_qv == 1:
+            return words(self.c.n_vertices)
+        return (self.c.n_qv - 1) * words(self.c.n_edges)
+
+    def allocate(self, device=None):
+        dev = device or torch.device("cuda")
+        self.out = [torch.empty(max(1, self.out_words()), dtype=torch.int32, device=dev) for _ in range(2)]
+        nbytes = int(LIB.match_workspace_bytes(ctypes.byref(self.c)))
+        self.workspace = torch.empty(max(nbytes, 512), dtype=torch.uint8, device=dev)
+        self.c.d_out[0] = self.out[0].data_ptr()
+        self.c.d_out[1] = self.out[1].data_ptr()
+        self.c.d_workspace = self.workspace.data_ptr()
+        self.c.workspace_bytes = self.workspace.numel()
+        return self
+
+
+def match_workspace_bytes(plan: Plan) -> int:
+    return int(LIB.match_workspace_bytes(ctypes.byref(plan.c)))
+
+
+def match_query(plan: Plan, party_mask: int = 3, stream=None):
+    _check(LIB.match_query(ctypes.byref(plan.c), party_mask, _stream(stream)))

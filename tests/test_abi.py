@@ -1,0 +1,100 @@
+"""CPU-side checks of the C ABI: the built library loads, exports every
+function include/oblivgm_fss.h declares, reports the documented key sizes and
+rejects bad arguments on the host before any kernel is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "oblivgm_fss.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def fss():
+    from paper_2209_03526_amd import fss as lib
+    return lib
+
+
+def test_every_declared_symbol_is_exported(fss):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(fss.LIB, name), name
+        assert name in fss.EXPORTS, name
+
+
+def test_key_sizes(fss):
+    assert fss.fss_key_bytes(fss.EQ, 32) == 440
+    assert fss.fss_key_bytes(fss.RANGE, 32) == 1088
+    assert fss.fss_key_bytes(fss.EQ, 8) == 16 * 8 - 72
+    assert fss.fss_key_bytes(fss.RANGE, 12) == 2 * (16 * 12 + 32)
+    assert fss.fss_key_bytes(fss.EQ, 7) == 0 and fss.fss_key_bytes(fss.RANGE, 33) == 0
+    assert fss.fss_key_bytes(5, 32) == 0
+    assert fss.fss_keybatch_bytes(fss.RANGE, 32, 65) == 1088 * 128
+    assert fss.fss_keybatch_bytes(fss.EQ, 32, 0) == 0
+
+
+def _kb(fss, kind, nbits, n, p0=256, p1=512):
+    return fss.fss_keybatch(kind, nbits, n, (ctypes.c_void_p * 2)(p0, p1))
+
+
+def test_keygen_argument_errors(fss):
+    L = fss.LIB
+    r = ctypes.c_void_p(4096)
+    assert L.fss_keygen(1, 1, 1, 9, 3, r, ctypes.byref(_kb(fss, fss.RANGE, 32, 10)), None) == fss.EINVAL
+    assert b"lo" in L.fss_last_error()
+    assert L.fss_keygen(1, 1, 1, 0, 256, r, ctypes.byref(_kb(fss, fss.RANGE, 8, 10)), None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 300, 0, r, ctypes.byref(_kb(fss, fss.EQ, 8, 10)), None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 0, 0, r, ctypes.byref(_kb(fss, fss.EQ, 40, 10)), None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 0, 0, r, ctypes.byref(_kb(fss, 3, 32, 10)), None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 0, 0, None, ctypes.byref(_kb(fss, fss.EQ, 32, 10)), None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 0, 0, r, ctypes.byref(_kb(fss, fss.EQ, 32, 10, 256, 300)), None) == fss.EINVAL
+    assert b"aligned" in L.fss_last_error()
+    assert L.fss_keygen(1, 1, 1, 0, 0, r, None, None) == fss.EINVAL
+    assert L.fss_keygen(1, 1, 1, 0, 0, r, ctypes.byref(_kb(fss, fss.EQ, 32, 2**33)), None) == fss.EUNSUPPORTED
+
+
+def test_eval_and_argument_errors(fss):
+    L = fss.LIB
+    kb = _kb(fss, fss.EQ, 32, 10)
+    buf = ctypes.c_void_p(4096)
+    assert L.fss_eval_eq(2, ctypes.byref(kb), buf, buf, None) == fss.EINVAL
+    assert L.fss_eval_lt(0, ctypes.byref(kb), buf, buf, None) == fss.EINVAL      # kind mismatch
+    assert L.fss_eval_eq(0, None, buf, buf, None) == fss.EINVAL
+    assert L.fss_eval_eq(0, ctypes.byref(kb), None, buf, None) == fss.EINVAL
+    assert L.ss_and(7, 0, 64, buf, buf, buf, buf, buf, None) == fss.EINVAL
+    assert L.ss_and(0, 3, 64, buf, buf, buf, buf, buf, None) == fss.EINVAL
+    assert L.ss_and(1, 0, 64, None, None, buf, None, buf, None) == fss.EINVAL
+    assert L.ss_triples(1, 1, 1, 10, None, buf, None) == fss.EINVAL
+    assert L.fss_mask_open(5, None, buf, buf, buf, None) == fss.EINVAL
+    # zero-sized work is a no-op that touches nothing
+    assert L.fss_mask_open(0, None, None, None, None, None) == fss.OK
+    assert L.ss_triples(1, 1, 1, 0, None, None, None) == fss.OK
+
+
+def test_match_plan_validation(fss):
+    L = fss.LIB
+    plan = fss.match_plan()
+    plan.n_qv = 0
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL
+    plan.n_qv = 9
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL
+    plan.n_qv = 1
+    assert L.match_query(ctypes.byref(plan), 1, None) == fss.EUNSUPPORTED
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL     # no outputs
+    plan.d_out[0] = 256
+    plan.d_out[1] = 512
+    plan.n_vertices = 100
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.ENOMEM     # no workspace
+    assert L.match_workspace_bytes(ctypes.byref(plan)) > 0
+    plan.n_qv = 2
+    plan.n_edges = 10
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL     # no endpoints
