@@ -226,3 +226,113 @@ def brute_force_pairs(graph, query):
         if pair_ok[u, w] and eok[e]:
             results.add((e,))
     return results
+
+
+# --------------------------------------------------------------------------- sampled rows
+
+def _and_schedule(query, n_vertices, n_edges):
+    """The and_id of every AND the plan performs, found by walking the plan
+    with public-ness only (no data): returns (vertex_fold, edge_fold, hop)
+    where vertex_fold[i] / edge_fold[j] list (pred index, and_id or None) in
+    fold order and hop[j] = (and_id of m_j[src] AND m_{j+1}[dst] or None,
+    and_id of that AND q_j or None)."""
+    n_qv = query.n_qv
+    next_id = [0]
+
+    def take():
+        next_id[0] += 1
+        return next_id[0] - 1
+
+    vertex_fold, edge_fold, public_v, public_e = [], [], [], []
+    for i in range(n_qv):
+        steps, pub = [], True
+        for k, p in enumerate(query.preds):
+            if p.target == i:
+                steps.append((k, None if pub else take()))
+                pub = False
+        vertex_fold.append(steps)
+        public_v.append(pub)
+    for j in range(n_qv - 1):
+        steps, pub = [], True
+        for k, p in enumerate(query.preds):
+            if p.target == n_qv + j:
+                steps.append((k, None if pub else take()))
+                pub = False
+        edge_fold.append(steps)
+        public_e.append(pub)
+    hop = []
+    for j in range(n_qv - 1):
+        gh_public = public_v[j] and public_v[j + 1]
+        a1 = take() if (not public_v[j] and not public_v[j + 1]) else None
+        a2 = take() if (not gh_public and not public_e[j]) else None
+        hop.append((a1, a2))
+    return vertex_fold, edge_fold, hop, public_v, public_e
+
+
+def sampled_outputs(nbits, seed, graph, query, shares, masks, out_rows):
+    """Both parties' share bits of the plan's outputs at the given rows only,
+    computed row by row (keys of the needed rows, triple words of the needed
+    positions).  ``out_rows``: vertex rows for a one-vertex query, else edge
+    rows (the same rows are read from every hop).  Returns an array of shape
+    (n_outputs, 2, len(out_rows)) of 0/1."""
+    n_qv = query.n_qv
+    vfold, efold, hop, public_v, public_e = _and_schedule(query, graph.n_vertices, graph.n_edges)
+    qid = query.query_id
+
+    def pred_bits(k, rows):
+        p = query.preds[k]
+        on_edge = p.target >= n_qv
+        x0, x1 = shares[("e:" if on_edge else "") + p.column]
+        r = masks[k][rows]
+        xhat = fss.mask_open(x0[rows], x1[rows], r)
+        if p.kind == "eq":
+            k0, k1 = fss.keygen_eq(nbits, seed, qid, k, p.a, r, rows=rows)
+            return np.stack([fss.eval_eq(nbits, 0, k0, xhat), fss.eval_eq(nbits, 1, k1, xhat)])
+        k0, k1 = fss.keygen_range(nbits, seed, qid, k, p.lo, p.hi, r, rows=rows)
+        return np.stack([fss.eval_range(nbits, 0, k0, xhat), fss.eval_range(nbits, 1, k1, xhat)])
+
+    def and_bits(x, y, and_id, rows):
+        words = (rows // 32).astype(np.uint32)
+        t = fss.triples(seed, qid, and_id, 0, words=words)
+        sh = (rows % 32).astype(np.uint32)
+        bit = lambda w: ((w >> sh) & 1).astype(np.uint8)
+        a = [bit(t["a"][b]) for b in range(2)]
+        bb = [bit(t["b"][b]) for b in range(2)]
+        c = [bit(t["c"][b]) for b in range(2)]
+        d = (x[0] ^ a[0]) ^ (x[1] ^ a[1])
+        e = (y[0] ^ bb[0]) ^ (y[1] ^ bb[1])
+        z0 = c[0] ^ (d & bb[0]) ^ (e & a[0]) ^ (d & e)
+        z1 = c[1] ^ (d & bb[1]) ^ (e & a[1])
+        return np.stack([z0, z1])
+
+    def fold(steps, rows, public):
+        if public:
+            return np.stack([np.ones(rows.size, np.uint8), np.zeros(rows.size, np.uint8)])
+        acc = None
+        for k, and_id in steps:
+            pb = pred_bits(k, rows)
+            acc = pb if and_id is None else and_bits(acc, pb, and_id, rows)
+        return acc
+
+    out_rows = np.asarray(out_rows, dtype=np.int64)
+    if n_qv == 1:
+        return fold(vfold[0], out_rows, public_v[0])[None]
+    outs = []
+    for j in range(n_qv - 1):
+        src = graph.src[out_rows].astype(np.int64)
+        dst = graph.dst[out_rows].astype(np.int64)
+        g = fold(vfold[j], src, public_v[j])
+        h = fold(vfold[j + 1], dst, public_v[j + 1])
+        q = fold(efold[j], out_rows, public_e[j])
+        a1, a2 = hop[j]
+        if a1 is not None:
+            r1 = and_bits(g, h, a1, out_rows)
+        else:
+            r1 = h if public_v[j] else g
+        r1_public = public_v[j] and public_v[j + 1]
+        if a2 is not None:
+            r2 = and_bits(r1, q, a2, out_rows)
+        else:
+            r2 = q if r1_public else r1
+        outs.append(r2)
+    return np.stack(outs)

@@ -145,6 +145,11 @@ __device__ __forceinline__ uint32_t tlook(const uint32_t* tab, uint32_t w, uint3
 
 __device__ __forceinline__ uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // One full round: out_c = T0[b0(s_c)] ^ T1[b1(s_c+1)] ^ T2[b2(s_c+2)] ^ T3[b3(s_c+3)] ^ rk_c.
 __device__ __forceinline__ uint32_t round_col(const uint32_t* tab, uint32_t loff, uint32_t a, uint32_t b,
                                               uint32_t c, uint32_t d, uint32_t k) {
@@ -152,7 +157,7 @@ __device__ __forceinline__ uint32_t round_col(const uint32_t* tab, uint32_t loff
     uint32_t t1 = tlook<1>(tab, b, loff);
     uint32_t t2 = tlook<2>(tab, c, loff);
     uint32_t t3 = tlook<3>(tab, d, loff);
-    return t0 ^ rotl32(t1, 8) ^ rotl32(t2, 16) ^ rotl32(t3, 24) ^ k;
+    return xor3(xor3(t0, rotl32(t1, 8), rotl32(t2, 16)), rotl32(t3, 24), k);
 }
 
 // Last round: out_c = S(b0(s_c)) | S(b1(s_c+1)) << 8 | S(b2(s_c+2)) << 16 | S(b3(s_c+3)) << 24, ^ rk.
@@ -164,7 +169,7 @@ __device__ __forceinline__ uint32_t final_col(const uint32_t* tab, uint32_t loff
     uint32_t t3 = tlook<3>(tab, d, loff);
     uint32_t lo = __builtin_amdgcn_perm(t1, t0, 0x0C0C0501u);  // (S(b), S(a)) in bytes 1, 0
     uint32_t hi = __builtin_amdgcn_perm(t3, t2, 0x05010C0Cu);  // (S(d), S(c)) in bytes 3, 2
-    return lo ^ hi ^ k;
+    return xor3(lo, hi, k);
 }
 
 template <class RK>

@@ -117,8 +117,23 @@ def chung_lu_graph(seed: int, n_vertices: int, n_edges: int, gamma: float = 2.1)
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
 
+    # index of the first cdf entry above u (searchsorted, side="right"), sped up
+    # by a guide table over [0,1) and a vectorised binary search in each bucket
+    buckets = 1 << 22
+    guide = np.searchsorted(cdf, np.arange(buckets + 1) / buckets, side="right")
+
     def draw(k):
-        return np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), n_vertices - 1)
+        u = rng.random(k)
+        j = np.minimum((u * buckets).astype(np.int64), buckets - 1)
+        lo, hi = guide[j].copy(), guide[j + 1].copy()
+        act = np.flatnonzero(lo < hi)
+        while act.size:
+            mid = (lo[act] + hi[act]) // 2
+            right = cdf[mid] <= u[act]
+            lo[act] = np.where(right, mid + 1, lo[act])
+            hi[act] = np.where(right, hi[act], mid)
+            act = act[lo[act] < hi[act]]
+        return np.minimum(lo, n_vertices - 1)
 
     src = draw(n_edges)
     dst = draw(n_edges)

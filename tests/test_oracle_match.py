@@ -67,3 +67,20 @@ def test_er_1024_workload():
     got = _run(g, q)
     assert got == match.brute_force_pairs(g, q)
     assert len(got) > 0
+
+
+@pytest.mark.parametrize("qi", range(len(QUERIES)))
+def test_sampled_rows_equal_full_plan(qi):
+    """The row-by-row oracle used for full-size sampling gives the same share
+    bits as the whole-table plan."""
+    q = QUERIES[qi]
+    g = synth.tiny_graph(qi, n_vertices=10 if q.n_qv == 4 else 12, n_edges=30)
+    sh = _shares(g, 5)
+    masks = synth.pred_masks(5, q, g)
+    full = match.run_plan(32, 9, g, q, sh, masks)
+    nrows = g.n_vertices if q.n_qv == 1 else g.n_edges
+    rows = np.arange(nrows)[::-1]
+    samp = match.sampled_outputs(32, 9, g, q, sh, masks, rows)
+    for j, o in enumerate(full):
+        for b in range(2):
+            np.testing.assert_array_equal(match.fss.unpack_bits(o[b], nrows)[rows], samp[j, b])
