@@ -54,8 +54,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log-rows", type=int, default=LOG_ROWS)
-    ap.add_argument("--cpu-sample-log-rows", type=int, default=17)
+    ap.add_argument("--cpu-sample-log-rows", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -118,6 +120,14 @@ def main():
         if record:
             e1.record(stream)
             ev["match"].append(("all", e0, e1))
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of 1 GiB done")
 
     for i in range(args.warmup):
         step(False)

@@ -4,16 +4,21 @@
 // (lambda = 128, Sec. VII-A); the dealer's randomness is AES-128 in counter
 // mode under a per-call key.  Both run through aes128_encrypt() below.
 //
-// Table layout.  One 256-entry table T0[x] = (2S(x), S(x), S(x), 3S(x)) (bytes
-// 0..3, i.e. the MixColumns image of S(x) in row 0) is replicated 64 times in
-// LDS, one copy per wavefront lane: entry x of lane l's copy sits at byte
-// address (x << 8) | (l << 2).  A lane therefore always reads bank (l mod
-// banks): every ds_read_b32 of a round is conflict-free whatever the data.
-// The address of "byte k of state word w" is one v_perm_b32: byte 1 of the
-// result is byte k of w, byte 0 is the lane offset, bytes 2..3 are zero.
-// Rows 1..3 use T0 rotated by 8/16/24 bits (v_alignbit).  The last round takes
-// S(x) = byte 1 of T0[x] and assembles the column with two v_perm_b32.
-// 64 KiB of LDS per workgroup.
+// Table layout.  T0[x] = (2S(x), S(x), S(x), 3S(x)) (bytes 0..3: the
+// MixColumns image of S(x) in row 0) and T1 = rotl8(T0) sit in LDS as 256 rows
+// of 256 bytes: row x holds 32 copies of T0[x], then 32 copies of T1[x].  Lane
+// l reads copy (l mod 32), i.e. byte address (x << 8) | (t << 7) | ((l & 31) << 2):
+// within each half-wave every lane reads its own bank whatever the data, so
+// the lookups are free of bank conflicts (measured: zero).  The address of
+// "byte k of state word w in table t" is one v_perm_b32 -- byte 1 of the result
+// is byte k of w, byte 0 the lane's offset for table t, bytes 2..3 zero.
+// With T2 = rotl16(T0) and T3 = rotl16(T1), a round column is
+//   T0[a] ^ T1[b] ^ rotl16(T0[c] ^ T1[d] ^ rotr16(k)),
+// i.e. 4 perms, 4 ds_read_b32, 2 three-input XORs and one rotate.  The last
+// round takes S(x) = byte 1 of T0[x] and assembles a column with two perms.
+// 64 KiB of LDS per workgroup.  At 160 lookups per block this round function
+// keeps the LDS pipe (32 dwords per clock per CU) nearly saturated; the VALU
+// has some slack.
 //
 // Tables and the fixed key schedule are generated at compile time from GF(2^8)
 // arithmetic (log/antilog tables over the generator 3) and FIPS-197's affine
@@ -112,82 +117,98 @@ constexpr RoundKeys kPrgKeys = expand_key(kPrgKeyBytes);
 // The fixed PRG key schedule, folded into instruction constants after unrolling.
 struct FixedPrgKey {
     __device__ __forceinline__ constexpr uint32_t operator[](int i) const { return kPrgKeys.w[i]; }
+    __device__ __forceinline__ constexpr uint32_t rotr16(int i) const {
+        return (kPrgKeys.w[i] >> 16) | (kPrgKeys.w[i] << 16);
+    }
 };
 
 // A per-call key schedule held in kernel arguments (scalar registers).
 struct ArgKey {
     const RoundKeys& rk;
     __device__ __forceinline__ uint32_t operator[](int i) const { return rk.w[i]; }
+    __device__ __forceinline__ uint32_t rotr16(int i) const { return (rk.w[i] >> 16) | (rk.w[i] << 16); }
 };
 
 // ----------------------------------------------------------------- LDS table
 
 constexpr int kLdsTableWords = 256 * 64;  // 64 KiB
 
-// Fills the replicated table; every thread of the workgroup takes part.  The
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
+
+// Fills the replicated tables; every thread of the workgroup takes part.  The
 // caller synchronises the workgroup before the first lookup.
 __device__ __forceinline__ void lds_table_fill(uint32_t* tab, const uint32_t* g_t0) {
-    for (int i = threadIdx.x; i < kLdsTableWords; i += blockDim.x) tab[i] = g_t0[i >> 6];
+    for (int i = threadIdx.x; i < kLdsTableWords; i += blockDim.x) {
+        const uint32_t v = g_t0[i >> 6];
+        tab[i] = (i & 32) ? rotl32(v, 8) : v;     // word i: row i >> 6, table (i >> 5) & 1
+    }
 }
 
-__device__ __forceinline__ uint32_t lane_offset() { return (threadIdx.x & 63u) << 2; }
+// This lane's byte offsets into row x of T0 and of T1.
+struct LaneOff {
+    uint32_t t0, t1;
+};
+
+__device__ __forceinline__ LaneOff lane_offset() {
+    const uint32_t c = (threadIdx.x & 31u) << 2;
+    return LaneOff{c, 128u | c};
+}
 
 __device__ __forceinline__ uint32_t lds_word(const uint32_t* tab, uint32_t byte_addr) {
     return *(const uint32_t*)((const char*)tab + byte_addr);
 }
 
-// Lookup of T0[byte k of w] in this lane's copy.
+// Lookup of T[byte k of w] in this lane's copy of the table whose lane offset is `off`.
 template <int K>
-__device__ __forceinline__ uint32_t tlook(const uint32_t* tab, uint32_t w, uint32_t loff) {
+__device__ __forceinline__ uint32_t tlook(const uint32_t* tab, uint32_t w, uint32_t off) {
     constexpr uint32_t sel = 0x0C0C0000u | ((uint32_t)(4 + K) << 8);
-    return lds_word(tab, __builtin_amdgcn_perm(w, loff, sel));
+    return lds_word(tab, __builtin_amdgcn_perm(w, off, sel));
 }
-
-__device__ __forceinline__ uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
 
 // a ^ b ^ c in one v_bitop3_b32 (truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// One full round: out_c = T0[b0(s_c)] ^ T1[b1(s_c+1)] ^ T2[b2(s_c+2)] ^ T3[b3(s_c+3)] ^ rk_c.
-__device__ __forceinline__ uint32_t round_col(const uint32_t* tab, uint32_t loff, uint32_t a, uint32_t b,
-                                              uint32_t c, uint32_t d, uint32_t k) {
-    uint32_t t0 = tlook<0>(tab, a, loff);
-    uint32_t t1 = tlook<1>(tab, b, loff);
-    uint32_t t2 = tlook<2>(tab, c, loff);
-    uint32_t t3 = tlook<3>(tab, d, loff);
-    return xor3(xor3(t0, rotl32(t1, 8), rotl32(t2, 16)), rotl32(t3, 24), k);
+// One full round: out_c = T0[b0(s_c)] ^ T1[b1(s_c+1)] ^ T2[b2(s_c+2)] ^ T3[b3(s_c+3)] ^ rk_c
+// with T2[y] = rotl16(T0[y]), T3[y] = rotl16(T1[y]); kr = rotr16(rk_c).
+__device__ __forceinline__ uint32_t round_col(const uint32_t* tab, LaneOff lo, uint32_t a, uint32_t b,
+                                              uint32_t c, uint32_t d, uint32_t kr) {
+    const uint32_t t0 = tlook<0>(tab, a, lo.t0);
+    const uint32_t t1 = tlook<1>(tab, b, lo.t1);
+    const uint32_t t2 = tlook<2>(tab, c, lo.t0);
+    const uint32_t t3 = tlook<3>(tab, d, lo.t1);
+    return xor3(t0, t1, rotl32(xor3(t2, t3, kr), 16));
 }
 
 // Last round: out_c = S(b0(s_c)) | S(b1(s_c+1)) << 8 | S(b2(s_c+2)) << 16 | S(b3(s_c+3)) << 24, ^ rk.
-__device__ __forceinline__ uint32_t final_col(const uint32_t* tab, uint32_t loff, uint32_t a, uint32_t b,
+__device__ __forceinline__ uint32_t final_col(const uint32_t* tab, LaneOff lo, uint32_t a, uint32_t b,
                                               uint32_t c, uint32_t d, uint32_t k) {
-    uint32_t t0 = tlook<0>(tab, a, loff);
-    uint32_t t1 = tlook<1>(tab, b, loff);
-    uint32_t t2 = tlook<2>(tab, c, loff);
-    uint32_t t3 = tlook<3>(tab, d, loff);
-    uint32_t lo = __builtin_amdgcn_perm(t1, t0, 0x0C0C0501u);  // (S(b), S(a)) in bytes 1, 0
-    uint32_t hi = __builtin_amdgcn_perm(t3, t2, 0x05010C0Cu);  // (S(d), S(c)) in bytes 3, 2
-    return xor3(lo, hi, k);
+    const uint32_t t0 = tlook<0>(tab, a, lo.t0);
+    const uint32_t t1 = tlook<1>(tab, b, lo.t0);
+    const uint32_t t2 = tlook<2>(tab, c, lo.t0);
+    const uint32_t t3 = tlook<3>(tab, d, lo.t0);
+    const uint32_t low = __builtin_amdgcn_perm(t1, t0, 0x0C0C0501u);   // (S(b), S(a)) in bytes 1, 0
+    const uint32_t high = __builtin_amdgcn_perm(t3, t2, 0x05010C0Cu);  // (S(d), S(c)) in bytes 3, 2
+    return xor3(low, high, k);
 }
 
 template <class RK>
-__device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, uint32_t loff) {
+__device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, LaneOff lo) {
     uint32_t s0 = in.x ^ rk[0], s1 = in.y ^ rk[1], s2 = in.z ^ rk[2], s3 = in.w ^ rk[3];
 #pragma unroll
     for (int r = 1; r < 10; r++) {
-        uint32_t n0 = round_col(tab, loff, s0, s1, s2, s3, rk[4 * r + 0]);
-        uint32_t n1 = round_col(tab, loff, s1, s2, s3, s0, rk[4 * r + 1]);
-        uint32_t n2 = round_col(tab, loff, s2, s3, s0, s1, rk[4 * r + 2]);
-        uint32_t n3 = round_col(tab, loff, s3, s0, s1, s2, rk[4 * r + 3]);
+        const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.rotr16(4 * r + 0));
+        const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(4 * r + 1));
+        const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(4 * r + 2));
+        const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(4 * r + 3));
         s0 = n0; s1 = n1; s2 = n2; s3 = n3;
     }
     uint4 out;
-    out.x = final_col(tab, loff, s0, s1, s2, s3, rk[40]);
-    out.y = final_col(tab, loff, s1, s2, s3, s0, rk[41]);
-    out.z = final_col(tab, loff, s2, s3, s0, s1, rk[42]);
-    out.w = final_col(tab, loff, s3, s0, s1, s2, rk[43]);
+    out.x = final_col(tab, lo, s0, s1, s2, s3, rk[40]);
+    out.y = final_col(tab, lo, s1, s2, s3, s0, rk[41]);
+    out.z = final_col(tab, lo, s2, s3, s0, s1, rk[42]);
+    out.w = final_col(tab, lo, s3, s0, s1, s2, rk[43]);
     return out;
 }
 
@@ -201,10 +222,10 @@ __device__ __forceinline__ uint4 and4(uint4 a, uint32_t m) {
 
 // G_sigma(s) = AES_K(u) ^ u, u = s ^ sigma (sigma enters byte 0; seeds have
 // bits 0 and 1 clear, so sigma in {0,1,2} never collides).
-__device__ __forceinline__ uint4 prg(uint4 s, uint32_t sigma, const uint32_t* tab, uint32_t loff) {
+__device__ __forceinline__ uint4 prg(uint4 s, uint32_t sigma, const uint32_t* tab, LaneOff lo) {
     uint4 u = s;
     u.x ^= sigma;
-    return xor4(aes128_encrypt(u, FixedPrgKey{}, tab, loff), u);
+    return xor4(aes128_encrypt(u, FixedPrgKey{}, tab, lo), u);
 }
 
 }  // namespace ogm

@@ -10,7 +10,7 @@
 // and the host code of the C ABI (validation, launch, match_query plan).
 //
 // Every AES-using kernel runs 1024-thread workgroups that first fill the
-// 64 KiB replicated T-table in LDS (aes_gfx950.hpp).  One thread owns one
+// 64 KiB replicated T-tables in LDS (aes_gfx950.hpp).  One thread owns one
 // table row (one element, one predicate, one party); the 64 lanes of a wave
 // own 64 consecutive rows, so the per-level correction words of a wave are one
 // contiguous 1 KiB read, and the wave's 64 output bits are one ballot.
@@ -82,7 +82,7 @@ __device__ __forceinline__ uint4 clear_tv(uint4 w) {
 
 // Party `party`'s DPF output bit at x (nu = nbits - 7 levels, 128-bit leaf).
 __device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
-                                             uint32_t party, uint32_t x, const uint32_t* tab, uint32_t loff) {
+                                             uint32_t party, uint32_t x, const uint32_t* tab, LaneOff loff) {
     const DpfPlanes P{np, nbits - 7};
     uint4 s = at<uint4>(key, P.root(), row);
     const uint32_t tlw = at<uint32_t>(key, P.tl(), row);
@@ -107,7 +107,7 @@ __device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, ui
 // Party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in step.
 __device__ __forceinline__ uint32_t range_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
                                                uint32_t party, uint32_t x, const uint32_t* tab,
-                                               uint32_t loff) {
+                                               LaneOff loff) {
     const DcfPlanes P{np, nbits};
     const uint8_t* ku = key;
     const uint8_t* kl = key + P.bytes();
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
     const EvalDesc& D = batch.d[di];
     const uint64_t row = (uint64_t)(blockIdx.x - D.block_start) * kBlock + threadIdx.x;
     const uint64_t np = pad_rows(D.n);
-    const uint32_t loff = lane_offset();
+    const LaneOff loff = lane_offset();
 
     uint32_t bit = 0;
     if (row < D.n) {
@@ -200,7 +200,7 @@ struct DealerArgs {
 
 // Counter-mode block (domain, j, query, pred, elem) under the dealer key.
 __device__ __forceinline__ uint4 rng_block(const RoundKeys& rk, uint32_t domain, uint32_t j, uint32_t query,
-                                           uint32_t pred, uint32_t elem, const uint32_t* tab, uint32_t loff) {
+                                           uint32_t pred, uint32_t elem, const uint32_t* tab, LaneOff loff) {
     const uint4 in = make_uint4(domain | (j << 16), query, pred, elem);
     return aes128_encrypt(in, ArgKey{rk}, tab, loff);
 }
@@ -210,7 +210,7 @@ __device__ __forceinline__ uint4 sel4(uint32_t c, uint4 a, uint4 b) { return c ?
 
 // DPF Gen for alpha over nbits; writes both parties' keys of `row`.
 __device__ __forceinline__ void dpf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
-                                        uint32_t alpha, uint4 s0, uint4 s1, const uint32_t* tab, uint32_t loff) {
+                                        uint32_t alpha, uint4 s0, uint4 s1, const uint32_t* tab, LaneOff loff) {
     const DpfPlanes P{np, nbits - 7};
     at_w<uint4>(k0, P.root(), row) = s0;
     at_w<uint4>(k1, P.root(), row) = s1;
@@ -252,7 +252,7 @@ __device__ __forceinline__ void dpf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, u
 // DCF Gen for [x < alpha] over nbits (Z_2 values); `wrap0/1` go to fin bit 31.
 __device__ __forceinline__ void dcf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
                                         uint32_t alpha, uint4 s0, uint4 s1, uint32_t wrap0, uint32_t wrap1,
-                                        const uint32_t* tab, uint32_t loff) {
+                                        const uint32_t* tab, LaneOff loff) {
     const DcfPlanes P{np, nbits};
     at_w<uint4>(k0, P.root(), row) = s0;
     at_w<uint4>(k1, P.root(), row) = s1;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_keygen(DealerArgs A) {
     __syncthreads();
     const uint64_t row = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (row >= A.n) return;
-    const uint32_t loff = lane_offset();
+    const LaneOff loff = lane_offset();
     const uint64_t np = pad_rows(A.n);
     const uint32_t mask = A.nbits >= 32 ? 0xFFFFFFFFu : ((1u << A.nbits) - 1u);
     const uint32_t r = A.r[row];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_triples(TripleArgs A) {
     __syncthreads();
     const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (4 * m >= A.nwords) return;
-    const uint32_t loff = lane_offset();
+    const LaneOff loff = lane_offset();
     uint32_t R[20];
 #pragma unroll
     for (int q = 0; q < 5; q++) {
