@@ -10,7 +10,8 @@
  * Conventions for every call:
  *   - Buffers named d_* are DEVICE pointers owned by the caller.  The library
  *     never allocates or frees caller memory; it holds no device memory of its
- *     own except constant tables.
+ *     own except constant tables (batch calls stage their descriptors through
+ *     one pinned host buffer it owns).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls validate
  *     their arguments synchronously, enqueue kernels on `stream` and return
  *     without waiting.  A negative return means nothing was enqueued;
@@ -172,6 +173,10 @@ typedef struct fss_pred {
     int32_t reserved;
     const fss_keybatch* keys;       /* host pointer; device key buffers */
     const uint32_t* d_xhat;         /* opened values of the target table */
+    const uint32_t* d_bits[2];      /* optional: both parties' packed share bits of this
+                                       predicate, already evaluated (e.g. chunk by chunk
+                                       with fss_eval_batch); then keys and d_xhat are
+                                       ignored.  NULL, NULL: match_query evaluates. */
 } fss_pred;
 
 typedef struct match_plan {
@@ -192,6 +197,62 @@ typedef struct match_plan {
 
 uint64_t match_workspace_bytes(const match_plan* plan);
 int match_query(const match_plan* plan, int32_t party_mask, void* stream);
+
+/*
+ * Batches: many requests in ONE persistent launch each.  The work of all
+ * requests is cut into tiles (512 rows for keygen, 1024 x rows_per_thread
+ * rows for evaluation); at most wg_per_cu workgroups per CU pull tiles from
+ * a device work queue, ranges and larger tables first.  Results are
+ * bit-identical to the per-request calls above, whatever the tuning.
+ *
+ * d_queue: caller-provided device memory of fss_queue_workspace_bytes(count)
+ * bytes (256-aligned) holding the queue counter and the descriptors.  The
+ * descriptors are staged through a pinned host buffer owned by the library
+ * (one per process, reused after its previous upload has completed).  Batch
+ * calls on one stream run in order; batches that share a d_queue must be on
+ * one stream.
+ *
+ * fss_keygen_batch (A2 for many predicates / queries): each request is one
+ * fss_keygen call (same meaning, same checks).
+ * fss_eval_batch (A3/A4 for many predicates, parties, queries): each request
+ * is one fss_eval_eq / fss_eval_lt call, chosen by keys->kind.
+ * match_query_batch (A7 for many plans): every predicate of every plan, both
+ * parties, in one persistent launch; then each plan's ANDs and joins in plan
+ * order.  Each plan has its own outputs and workspace as in match_query.
+ */
+typedef struct fss_keygen_req {
+    uint64_t seed;
+    uint32_t query_id;
+    uint32_t pred_id;
+    uint32_t a_or_lo;
+    uint32_t hi;
+    const uint32_t* d_r;            /* masks of the request's rows */
+    const fss_keybatch* out;
+    uint32_t row_offset;            /* table row of the request's first row: a chunk of
+                                       rows [row_offset, row_offset + out->n) gets exactly
+                                       the keys a whole-table request gives those rows */
+    uint32_t reserved;
+} fss_keygen_req;
+
+typedef struct fss_eval_req {
+    int32_t party;
+    int32_t reserved;
+    const fss_keybatch* keys;
+    const uint32_t* d_xhat;
+    uint32_t* d_out_bits;
+} fss_eval_req;
+
+uint64_t fss_queue_workspace_bytes(uint64_t count);
+int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes, void* stream);
+int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes, void* stream);
+int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
+                      uint64_t queue_bytes, void* stream);
+
+/* Tile / occupancy shape of the persistent launches (process-wide):
+ * rows_per_thread 1..8 (evaluation tile = 1024 * rows_per_thread rows),
+ * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */
+int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu);
+int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu);
 
 #ifdef __cplusplus
 }

@@ -193,11 +193,12 @@ __device__ __forceinline__ uint32_t final_col(const uint32_t* tab, LaneOff lo, u
     return xor3(low, high, k);
 }
 
+// Rounds 2..10 from the state after round 1.
 template <class RK>
-__device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, LaneOff lo) {
-    uint32_t s0 = in.x ^ rk[0], s1 = in.y ^ rk[1], s2 = in.z ^ rk[2], s3 = in.w ^ rk[3];
+__device__ __forceinline__ uint4 aes128_rounds_2_10(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3, const RK& rk,
+                                                    const uint32_t* tab, LaneOff lo) {
 #pragma unroll
-    for (int r = 1; r < 10; r++) {
+    for (int r = 2; r < 10; r++) {
         const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.rotr16(4 * r + 0));
         const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(4 * r + 1));
         const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(4 * r + 2));
@@ -210,6 +211,16 @@ __device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const ui
     out.z = final_col(tab, lo, s2, s3, s0, s1, rk[42]);
     out.w = final_col(tab, lo, s3, s0, s1, s2, rk[43]);
     return out;
+}
+
+template <class RK>
+__device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, LaneOff lo) {
+    const uint32_t s0 = in.x ^ rk[0], s1 = in.y ^ rk[1], s2 = in.z ^ rk[2], s3 = in.w ^ rk[3];
+    const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.rotr16(4));
+    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(5));
+    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(6));
+    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(7));
+    return aes128_rounds_2_10(n0, n1, n2, n3, rk, tab, lo);
 }
 
 __device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
@@ -226,6 +237,30 @@ __device__ __forceinline__ uint4 prg(uint4 s, uint32_t sigma, const uint32_t* ta
     uint4 u = s;
     u.x ^= sigma;
     return xor4(aes128_encrypt(u, FixedPrgKey{}, tab, lo), u);
+}
+
+// Both children of one seed, G_0(s) and G_1(s).  Their AES inputs differ only
+// in byte 0, which after ShiftRows feeds column 0 of round 1 alone: columns
+// 1..3 of round 1 are shared, and column 0 of the right child is the left
+// one's with its T0 term swapped (one extra lookup instead of sixteen).
+__device__ __forceinline__ void prg_pair(uint4 s, const uint32_t* tab, LaneOff lo, uint4& wl, uint4& wr) {
+    const FixedPrgKey rk{};
+    const uint32_t s0 = s.x ^ rk[0], s1 = s.y ^ rk[1], s2 = s.z ^ rk[2], s3 = s.w ^ rk[3];
+    const uint32_t a_l = tlook<0>(tab, s0, lo.t0);
+    const uint32_t a_r = tlook<0>(tab, s0 ^ 1u, lo.t0);
+    const uint32_t b = tlook<1>(tab, s1, lo.t1);
+    const uint32_t c = tlook<2>(tab, s2, lo.t0);
+    const uint32_t d = tlook<3>(tab, s3, lo.t1);
+    const uint32_t cd = rotl32(xor3(c, d, rk.rotr16(4)), 16);
+    const uint32_t n0l = xor3(a_l, b, cd);
+    const uint32_t n0r = xor3(a_r, b, cd);
+    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(5));
+    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(6));
+    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(7));
+    uint4 ur = s;
+    ur.x ^= 1u;
+    wl = xor4(aes128_rounds_2_10(n0l, n1, n2, n3, rk, tab, lo), s);
+    wr = xor4(aes128_rounds_2_10(n0r, n1, n2, n3, rk, tab, lo), ur);
 }
 
 }  // namespace ogm

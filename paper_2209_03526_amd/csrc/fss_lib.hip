@@ -21,7 +21,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/oblivgm_fss.h"
 #include "aes_gfx950.hpp"
@@ -153,18 +156,11 @@ struct EvalBatch {
     EvalDesc d[kEvalInline];
 };
 
-__global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tables.t0);
-    __syncthreads();
-
-    uint32_t di = 0;
-    while (di + 1 < batch.count && blockIdx.x >= batch.d[di + 1].block_start) di++;
-    const EvalDesc& D = batch.d[di];
-    const uint64_t row = (uint64_t)(blockIdx.x - D.block_start) * kBlock + threadIdx.x;
+// One workgroup-sized slice of rows [row0, row0 + kBlock) of descriptor D:
+// every thread evaluates one row, each wave stores its 64 bits as two words.
+__device__ __forceinline__ void eval_rows(const EvalDesc& D, uint64_t row0, const uint32_t* tab, LaneOff loff) {
+    const uint64_t row = row0 + threadIdx.x;
     const uint64_t np = pad_rows(D.n);
-    const LaneOff loff = lane_offset();
-
     uint32_t bit = 0;
     if (row < D.n) {
         const uint32_t x = D.xhat[row];
@@ -182,6 +178,17 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+
+    uint32_t di = 0;
+    while (di + 1 < batch.count && blockIdx.x >= batch.d[di + 1].block_start) di++;
+    const EvalDesc& D = batch.d[di];
+    eval_rows(D, (uint64_t)(blockIdx.x - D.block_start) * kBlock, tab, lane_offset());
+}
+
 // ----------------------------------------------------------------- dealer (A2, A6)
 
 struct DealerArgs {
@@ -196,6 +203,8 @@ struct DealerArgs {
     uint32_t pred;
     uint32_t a_or_lo;
     uint32_t hi;
+    uint32_t row_offset;    // table row of key row 0 (dealer randomness is addressed by table row)
+    uint32_t pad;
 };
 
 // Counter-mode block (domain, j, query, pred, elem) under the dealer key.
@@ -208,114 +217,203 @@ __device__ __forceinline__ uint4 rng_block(const RoundKeys& rk, uint32_t domain,
 __device__ __forceinline__ uint32_t sel(uint32_t c, uint32_t a, uint32_t b) { return c ? a : b; }
 __device__ __forceinline__ uint4 sel4(uint32_t c, uint4 a, uint4 b) { return c ? a : b; }
 
-// DPF Gen for alpha over nbits; writes both parties' keys of `row`.
-__device__ __forceinline__ void dpf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
-                                        uint32_t alpha, uint4 s0, uint4 s1, const uint32_t* tab, LaneOff loff) {
+// The dealer's work for one row is split over a lane pair: even lane = party 0,
+// odd lane = party 1.  Each lane expands only its own seed (2 AES per level);
+// what Gen needs of the other party -- its "lose" child and its t / v bits --
+// comes from the partner lane through a DPP quad permutation (lanes 0<->1,
+// 2<->3), so both lanes form the same correction words and each writes them
+// into its own party's key.
+
+// Value of `v` in the partner lane (lane ^ 1).
+__device__ __forceinline__ uint32_t partner(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+}
+
+__device__ __forceinline__ uint4 partner4(uint4 v) {
+    return make_uint4(partner(v.x), partner(v.y), partner(v.z), partner(v.w));
+}
+
+// DPF Gen for alpha over nbits, this lane's party b: writes key `k` of `row`.
+__device__ __forceinline__ void dpf_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
+                                        uint32_t b, uint4 s, const uint32_t* tab, LaneOff loff) {
     const DpfPlanes P{np, nbits - 7};
-    at_w<uint4>(k0, P.root(), row) = s0;
-    at_w<uint4>(k1, P.root(), row) = s1;
-    uint32_t t0 = 0, t1 = 1, tlw = 0, trw = 0;
+    at_w<uint4>(k, P.root(), row) = s;
+    uint32_t t = b, tlw = 0, trw = 0;
     for (uint32_t i = 0; i < P.nu; i++) {
         const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
-        const uint4 wl0 = prg(s0, 0u, tab, loff), wr0 = prg(s0, 1u, tab, loff);
-        const uint4 wl1 = prg(s1, 0u, tab, loff), wr1 = prg(s1, 1u, tab, loff);
-        const uint4 keep0 = clear_tv(sel4(a, wr0, wl0)), keep1 = clear_tv(sel4(a, wr1, wl1));
-        const uint4 scw = xor4(clear_tv(sel4(a, wl0, wr0)), clear_tv(sel4(a, wl1, wr1)));
-        const uint32_t tlcw = (wl0.x ^ wl1.x ^ a ^ 1u) & 1u;
-        const uint32_t trcw = (wr0.x ^ wr1.x ^ a) & 1u;
+        uint4 wl, wr;
+        prg_pair(s, tab, loff, wl, wr);
+        const uint4 keep = clear_tv(sel4(a, wr, wl));
+        const uint4 lose = clear_tv(sel4(a, wl, wr));
+        const uint32_t bits = (wl.x & 1u) | ((wr.x & 1u) << 1);       // t^L, t^R of this party
+        const uint32_t both = bits ^ partner(bits);                   // t^L_0 ^ t^L_1, t^R_0 ^ t^R_1
+        const uint4 scw = xor4(lose, partner4(lose));
+        const uint32_t tlcw = (both ^ a ^ 1u) & 1u;
+        const uint32_t trcw = ((both >> 1) ^ a) & 1u;
         const uint32_t tkcw = sel(a, trcw, tlcw);
-        const uint32_t tk0 = sel(a, wr0.x, wl0.x) & 1u, tk1 = sel(a, wr1.x, wl1.x) & 1u;
-        s0 = xor4(keep0, and4(scw, 0u - t0));
-        s1 = xor4(keep1, and4(scw, 0u - t1));
-        t0 = tk0 ^ (t0 & tkcw);
-        t1 = tk1 ^ (t1 & tkcw);
-        at_w<uint4>(k0, P.scw(i), row) = scw;
-        at_w<uint4>(k1, P.scw(i), row) = scw;
+        const uint32_t tk = (sel(a, wr.x, wl.x)) & 1u;
+        s = xor4(keep, and4(scw, 0u - t));
+        t = tk ^ (t & tkcw);
+        at_w<uint4>(k, P.scw(i), row) = scw;
         tlw |= tlcw << i;
         trw |= trcw << i;
     }
-    uint4 cw = xor4(prg(s0, 2u, tab, loff), prg(s1, 2u, tab, loff));
+    const uint4 g = prg(s, 2u, tab, loff);
+    uint4 cw = xor4(g, partner4(g));
     const uint32_t low = alpha & 127u;
     const uint32_t bit = 1u << (low & 31u);
     cw.x ^= (low >> 5) == 0 ? bit : 0u;
     cw.y ^= (low >> 5) == 1 ? bit : 0u;
     cw.z ^= (low >> 5) == 2 ? bit : 0u;
     cw.w ^= (low >> 5) == 3 ? bit : 0u;
-    at_w<uint32_t>(k0, P.tl(), row) = tlw;
-    at_w<uint32_t>(k1, P.tl(), row) = tlw;
-    at_w<uint32_t>(k0, P.tr(), row) = trw;
-    at_w<uint32_t>(k1, P.tr(), row) = trw;
-    at_w<uint4>(k0, P.cwout(), row) = cw;
-    at_w<uint4>(k1, P.cwout(), row) = cw;
+    at_w<uint32_t>(k, P.tl(), row) = tlw;
+    at_w<uint32_t>(k, P.tr(), row) = trw;
+    at_w<uint4>(k, P.cwout(), row) = cw;
 }
 
-// DCF Gen for [x < alpha] over nbits (Z_2 values); `wrap0/1` go to fin bit 31.
-__device__ __forceinline__ void dcf_gen(uint8_t* k0, uint8_t* k1, uint64_t np, uint64_t row, uint32_t nbits,
-                                        uint32_t alpha, uint4 s0, uint4 s1, uint32_t wrap0, uint32_t wrap1,
-                                        const uint32_t* tab, LaneOff loff) {
+// DCF Gen for [x < alpha] over nbits (Z_2 values), this lane's party b; `wrap`
+// is the party's wrap share, stored in fin bit 31.
+__device__ __forceinline__ void dcf_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
+                                        uint32_t b, uint4 s, uint32_t wrap, const uint32_t* tab, LaneOff loff) {
     const DcfPlanes P{np, nbits};
-    at_w<uint4>(k0, P.root(), row) = s0;
-    at_w<uint4>(k1, P.root(), row) = s1;
-    uint32_t t0 = 0, t1 = 1, va = 0, tlw = 0, trw = 0, vw = 0;
+    at_w<uint4>(k, P.root(), row) = s;
+    uint32_t t = b, va = 0, tlw = 0, trw = 0, vw = 0;
     for (uint32_t i = 0; i < nbits; i++) {
         const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
-        const uint4 wl0 = prg(s0, 0u, tab, loff), wr0 = prg(s0, 1u, tab, loff);
-        const uint4 wl1 = prg(s1, 0u, tab, loff), wr1 = prg(s1, 1u, tab, loff);
-        const uint4 keep0 = clear_tv(sel4(a, wr0, wl0)), keep1 = clear_tv(sel4(a, wr1, wl1));
-        const uint4 scw = xor4(clear_tv(sel4(a, wl0, wr0)), clear_tv(sel4(a, wl1, wr1)));
-        const uint32_t vlose = (sel(a, wl0.x, wr0.x) ^ sel(a, wl1.x, wr1.x)) >> 1;
-        const uint32_t vkeep = (sel(a, wr0.x, wl0.x) ^ sel(a, wr1.x, wl1.x)) >> 1;
-        const uint32_t vcw = (vlose ^ va ^ a) & 1u;
-        va = (va ^ vkeep ^ vcw) & 1u;
-        const uint32_t tlcw = (wl0.x ^ wl1.x ^ a ^ 1u) & 1u;
-        const uint32_t trcw = (wr0.x ^ wr1.x ^ a) & 1u;
+        uint4 wl, wr;
+        prg_pair(s, tab, loff, wl, wr);
+        const uint4 keep = clear_tv(sel4(a, wr, wl));
+        const uint4 lose = clear_tv(sel4(a, wl, wr));
+        // bit 0: t^L, 1: t^R, 2: v^L, 3: v^R of this party; XOR with the partner's
+        const uint32_t bits = (wl.x & 1u) | ((wr.x & 1u) << 1) | ((wl.x & 2u) << 1) | ((wr.x & 2u) << 2);
+        const uint32_t both = bits ^ partner(bits);
+        const uint4 scw = xor4(lose, partner4(lose));
+        const uint32_t vlose = sel(a, both >> 2, both >> 3) & 1u;
+        const uint32_t vkeep = sel(a, both >> 3, both >> 2) & 1u;
+        const uint32_t vcw = vlose ^ va ^ a;
+        va = va ^ vkeep ^ vcw;
+        const uint32_t tlcw = (both ^ a ^ 1u) & 1u;
+        const uint32_t trcw = ((both >> 1) ^ a) & 1u;
         const uint32_t tkcw = sel(a, trcw, tlcw);
-        const uint32_t tk0 = sel(a, wr0.x, wl0.x) & 1u, tk1 = sel(a, wr1.x, wl1.x) & 1u;
-        s0 = xor4(keep0, and4(scw, 0u - t0));
-        s1 = xor4(keep1, and4(scw, 0u - t1));
-        t0 = tk0 ^ (t0 & tkcw);
-        t1 = tk1 ^ (t1 & tkcw);
-        at_w<uint4>(k0, P.scw(i), row) = scw;
-        at_w<uint4>(k1, P.scw(i), row) = scw;
+        const uint32_t tk = (sel(a, wr.x, wl.x)) & 1u;
+        s = xor4(keep, and4(scw, 0u - t));
+        t = tk ^ (t & tkcw);
+        at_w<uint4>(k, P.scw(i), row) = scw;
         tlw |= tlcw << i;
         trw |= trcw << i;
         vw |= vcw << i;
     }
-    const uint32_t fin = ((s0.x >> 2) ^ (s1.x >> 2) ^ va) & 1u;
-    at_w<uint32_t>(k0, P.tl(), row) = tlw;
-    at_w<uint32_t>(k1, P.tl(), row) = tlw;
-    at_w<uint32_t>(k0, P.tr(), row) = trw;
-    at_w<uint32_t>(k1, P.tr(), row) = trw;
-    at_w<uint32_t>(k0, P.vcw(), row) = vw;
-    at_w<uint32_t>(k1, P.vcw(), row) = vw;
-    at_w<uint32_t>(k0, P.fin(), row) = fin | (wrap0 << 31);
-    at_w<uint32_t>(k1, P.fin(), row) = fin | (wrap1 << 31);
+    const uint32_t c = (s.x >> 2) & 1u;
+    const uint32_t fin = (c ^ partner(c) ^ va) & 1u;
+    at_w<uint32_t>(k, P.tl(), row) = tlw;
+    at_w<uint32_t>(k, P.tr(), row) = trw;
+    at_w<uint32_t>(k, P.vcw(), row) = vw;
+    at_w<uint32_t>(k, P.fin(), row) = fin | (wrap << 31);
 }
 
+// Both lanes of row `row`'s pair (b = party of this lane).
+__device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, uint32_t b, const uint32_t* tab,
+                                           LaneOff loff) {
+    const uint64_t np = pad_rows(A.n);
+    const uint32_t mask = A.nbits >= 32 ? 0xFFFFFFFFu : ((1u << A.nbits) - 1u);
+    const uint32_t r = A.r[row];
+    const uint32_t e = (uint32_t)row + A.row_offset;
+    uint8_t* key = b ? A.key1 : A.key0;
+    const uint4 s = clear_tv(rng_block(A.rk, 3, b, A.query, A.pred, e, tab, loff));
+    if (A.kind == FSS_EQ) {
+        dpf_gen(key, np, row, A.nbits, (A.a_or_lo + r) & mask, b, s, tab, loff);
+    } else {
+        const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
+        const uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
+        const uint32_t cb = c0 ^ (b & (L > U ? 1u : 0u));
+        dcf_gen(key, np, row, A.nbits, U, b, s, cb, tab, loff);
+        const uint4 sl = clear_tv(rng_block(A.rk, 3, 3 + b, A.query, A.pred, e, tab, loff));
+        dcf_gen(key + DcfPlanes{np, A.nbits}.bytes(), np, row, A.nbits, L, b, sl, 0u, tab, loff);
+    }
+}
+
+// Two lanes per row (see above); 512 rows per workgroup.
 __global__ __launch_bounds__(kBlock) void k_keygen(DealerArgs A) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tables.t0);
     __syncthreads();
-    const uint64_t row = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (row >= A.n) return;
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t row = gid >> 1;
+    if (row >= A.n) return;                 // both lanes of a pair leave together
+    keygen_row(A, row, (uint32_t)(gid & 1u), tab, lane_offset());
+}
+
+// ----------------------------------------------------------------- persistent work queue (batches)
+//
+// A batch is a list of descriptors in device memory; descriptor i owns tiles
+// [tile_start_i, tile_start_i + tiles_i) of one global tile range.  A grid of
+// at most two workgroups per CU pulls tile numbers from one atomic counter
+// (zeroed by the launch before) until the range is exhausted, so every
+// workgroup leaves once all tiles are taken.  Each tile is a pure function of
+// its descriptor and rows: results do not depend on which workgroup took it.
+
+struct QKeygen {
+    DealerArgs a;
+    uint32_t tile_start;    // tiles of 512 rows
+    uint32_t pad;
+};
+
+struct QEval {
+    EvalDesc d;             // d.block_start = first tile; tiles of kBlock * rows_per_thread rows
+};
+
+__global__ void k_zero_counter(uint32_t* c) {
+    if (threadIdx.x == 0) *c = 0u;
+}
+
+// Last descriptor whose first tile is <= tile (descriptors in tile order).
+template <class F>
+__device__ __forceinline__ uint32_t find_desc(uint32_t count, uint32_t tile, F start_of) {
+    uint32_t lo = 0, hi = count;    // invariant: start_of(lo) <= tile, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (start_of(mid) <= tile) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_tile) {
+    __syncthreads();                         // everyone is done with the previous tile number
+    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, 1u);
+    __syncthreads();
+    return *s_tile;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keygen_queue(const QKeygen* __restrict__ q, uint32_t count,
+                                                        uint32_t total_tiles, uint32_t* counter) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    __shared__ uint32_t s_tile;
+    lds_table_fill(tab, g_tables.t0);
     const LaneOff loff = lane_offset();
-    const uint64_t np = pad_rows(A.n);
-    const uint32_t mask = A.nbits >= 32 ? 0xFFFFFFFFu : ((1u << A.nbits) - 1u);
-    const uint32_t r = A.r[row];
-    const uint32_t e = (uint32_t)row;
-    const uint4 s0 = clear_tv(rng_block(A.rk, 3, 0, A.query, A.pred, e, tab, loff));
-    const uint4 s1 = clear_tv(rng_block(A.rk, 3, 1, A.query, A.pred, e, tab, loff));
-    if (A.kind == FSS_EQ) {
-        dpf_gen(A.key0, A.key1, np, row, A.nbits, (A.a_or_lo + r) & mask, s0, s1, tab, loff);
-    } else {
-        const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
-        const uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
-        const uint32_t c1 = c0 ^ (L > U ? 1u : 0u);
-        dcf_gen(A.key0, A.key1, np, row, A.nbits, U, s0, s1, c0, c1, tab, loff);
-        const uint4 l0 = clear_tv(rng_block(A.rk, 3, 3, A.query, A.pred, e, tab, loff));
-        const uint4 l1 = clear_tv(rng_block(A.rk, 3, 4, A.query, A.pred, e, tab, loff));
-        const uint64_t half = DcfPlanes{np, A.nbits}.bytes();
-        dcf_gen(A.key0 + half, A.key1 + half, np, row, A.nbits, L, l0, l1, 0u, 0u, tab, loff);
+    for (;;) {
+        const uint32_t tile = next_tile(counter, &s_tile);   // also orders the table fill
+        if (tile >= total_tiles) break;
+        const uint32_t di = find_desc(count, tile, [&](uint32_t i) { return q[i].tile_start; });
+        const DealerArgs& A = q[di].a;
+        const uint64_t row = (uint64_t)(tile - q[di].tile_start) * (kBlock / 2) + (threadIdx.x >> 1);
+        if (row < A.n) keygen_row(A, row, threadIdx.x & 1u, tab, loff);
+    }
+}
+
+__global__ __launch_bounds__(kBlock, 8) void k_eval_queue(const QEval* __restrict__ q, uint32_t count,
+                                                      uint32_t total_tiles, uint32_t rows_per_thread,
+                                                      uint32_t* counter) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    __shared__ uint32_t s_tile;
+    lds_table_fill(tab, g_tables.t0);
+    const LaneOff loff = lane_offset();
+    for (;;) {
+        const uint32_t tile = next_tile(counter, &s_tile);
+        if (tile >= total_tiles) break;
+        const uint32_t di = find_desc(count, tile, [&](uint32_t i) { return q[i].d.block_start; });
+        const EvalDesc& D = q[di].d;
+        const uint64_t row0 = (uint64_t)(tile - D.block_start) * kBlock * rows_per_thread;
+        for (uint32_t k = 0; k < rows_per_thread; k++) eval_rows(D, row0 + (uint64_t)k * kBlock, tab, loff);
     }
 }
 
@@ -596,7 +694,7 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
     A.pred = pred_id;
     A.a_or_lo = a_or_lo;
     A.hi = hi;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)((out->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)((2 * out->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        (hipStream_t)stream, A);
     return check_launch("k_keygen");
 }
@@ -669,20 +767,65 @@ struct Arena {
 
 uint64_t words_of(uint64_t rows) { return (rows + 31) / 32; }
 
-// Workspace bytes the plan needs: predicate bits, vertex / edge results,
-// hop temporaries and one triple buffer, per party.
+// Workspace bytes the plan needs (an upper bound): predicate bits and at most
+// one AND result per predicate, per hop two gathers and two AND results, and
+// one triple buffer -- per party.
 uint64_t plan_workspace(const match_plan* P) {
     auto rnd = [](uint64_t words) { return (words * 4 + 255) & ~255ull; };
     const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
     uint64_t total = 0;
-    // predicate bits, and at most one AND result per predicate in the folds
     for (uint32_t k = 0; k < P->n_pred; k++)
         total += 4 * rnd((uint32_t)P->preds[k].target < P->n_qv ? wv : we);
-    // per hop: two gathers and two AND results, both parties
     if (P->n_qv > 1) total += 8 * (uint64_t)(P->n_qv - 1) * rnd(we);
     const uint64_t wmax = wv > we ? wv : we;
     total += 2 * rnd(3 * wmax);
     return total;
+}
+
+__global__ void k_copy_words(uint64_t nwords, const uint32_t* __restrict__ a0, const uint32_t* __restrict__ a1,
+                             uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        o0[w] = a0[w];
+        o1[w] = a1[w];
+    }
+}
+
+int validate_plan(const match_plan* P, const char* who) {
+    if (!P) return fail(FSS_EINVAL, "%s: plan is NULL", who);
+    if (P->n_qv == 0 || P->n_qv > FSS_MAX_QV) return fail(FSS_EINVAL, "%s: n_qv %u outside 1..%d", who, P->n_qv, FSS_MAX_QV);
+    if (P->n_pred > FSS_MAX_PREDS) return fail(FSS_EINVAL, "%s: more than %d predicates", who, FSS_MAX_PREDS);
+    if (P->n_pred && !P->preds) return fail(FSS_EINVAL, "%s: preds is NULL", who);
+    if (P->n_vertices > 0xFFFFFFFFull || P->n_edges > 0xFFFFFFFFull)
+        return fail(FSS_EUNSUPPORTED, "%s: more than 2^32 rows", who);
+    if (!P->d_out[0] || !P->d_out[1]) return fail(FSS_EINVAL, "%s: NULL output", who);
+    if (P->n_qv > 1 && P->n_edges && (!P->d_src || !P->d_dst)) return fail(FSS_EINVAL, "%s: NULL edge endpoints", who);
+    const uint32_t ntarget = 2 * P->n_qv - 1;
+    for (uint32_t k = 0; k < P->n_pred; k++) {
+        const fss_pred& p = P->preds[k];
+        if (p.target < 0 || (uint32_t)p.target >= ntarget)
+            return fail(FSS_EINVAL, "%s: predicate %u targets %d (of %u)", who, k, p.target, ntarget);
+        const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
+        if (p.d_bits[0] || p.d_bits[1]) {
+            if (!p.d_bits[0] || !p.d_bits[1]) return fail(FSS_EINVAL, "%s: predicate %u has one bit pointer", who, k);
+            continue;   // share bits already evaluated: keys and d_xhat are not used
+        }
+        if (!p.keys || (p.keys->kind != FSS_EQ && p.keys->kind != FSS_RANGE))
+            return fail(FSS_EINVAL, "%s: predicate %u has no valid key batch", who, k);
+        int rc = check_batch(p.keys, p.keys->kind, who);
+        if (rc) return rc;
+        if (p.keys->n != rows)
+            return fail(FSS_EINVAL, "%s: predicate %u keys cover %llu rows, table has %llu", who, k,
+                        (unsigned long long)p.keys->n, (unsigned long long)rows);
+        if (rows && (!p.d_xhat || !p.keys->key[0] || !p.keys->key[1]))
+            return fail(FSS_EINVAL, "%s: predicate %u has a NULL buffer", who, k);
+        if (rows && (!aligned256(p.keys->key[0]) || !aligned256(p.keys->key[1])))
+            return fail(FSS_EINVAL, "%s: predicate %u key buffers not 256-byte aligned", who, k);
+    }
+    const uint64_t need = plan_workspace(P);
+    if (!P->d_workspace || P->workspace_bytes < need)
+        return fail(FSS_ENOMEM, "%s: workspace needs %llu bytes", who, (unsigned long long)need);
+    return FSS_OK;
 }
 
 struct PlanRun {
@@ -691,6 +834,40 @@ struct PlanRun {
     Arena ws;
     uint32_t next_and = 0;
     uint32_t* trip[2] = {nullptr, nullptr};
+    Shares pbits[FSS_MAX_PREDS];
+
+    // Carve the triple buffers and the predicate-bit buffers; append one eval
+    // descriptor per (predicate, party) with rows to `out`.
+    int setup(std::vector<EvalDesc>& out) {
+        const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
+        const uint64_t wmax = wv > we ? wv : we;
+        for (int b = 0; b < 2; b++)
+            if (!(trip[b] = ws.take(3 * wmax))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+        for (uint32_t k = 0; k < P->n_pred; k++) {
+            const fss_pred& p = P->preds[k];
+            const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
+            if (p.d_bits[0]) {       // evaluated by the caller
+                pbits[k].p[0] = const_cast<uint32_t*>(p.d_bits[0]);
+                pbits[k].p[1] = const_cast<uint32_t*>(p.d_bits[1]);
+                continue;
+            }
+            for (int b = 0; b < 2; b++) {
+                if (!(pbits[k].p[b] = ws.take(words_of(rows))))
+                    return fail(FSS_ENOMEM, "match_query: workspace too small");
+                if (rows == 0) continue;
+                EvalDesc d{};
+                d.key = (const uint8_t*)p.keys->key[b];
+                d.xhat = p.d_xhat;
+                d.out = pbits[k].p[b];
+                d.n = rows;
+                d.kind = (uint32_t)p.keys->kind;
+                d.nbits = p.keys->nbits;
+                d.party = (uint32_t)b;
+                out.push_back(d);
+            }
+        }
+        return FSS_OK;
+    }
 
     int AND(const Shares& x, const Shares& y, uint64_t nrows, Shares* z) {
         if (x.is_public()) { *z = y; return FSS_OK; }
@@ -701,10 +878,13 @@ struct PlanRun {
             if (!(out.p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
         int rc = launch_triples(P->seed, P->query_id, next_and++, nw, trip[0], trip[1], s);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_and_both, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, x.p[0], x.p[1],
-                           y.p[0], y.p[1], trip[0], trip[1], out.p[0], out.p[1]);
+        if (nw) {
+            hipLaunchKernelGGL(k_and_both, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, x.p[0],
+                               x.p[1], y.p[0], y.p[1], trip[0], trip[1], out.p[0], out.p[1]);
+            rc = check_launch("k_and_both");
+        }
         *z = out;
-        return check_launch("k_and_both");
+        return rc;
     }
 
     int gather(const Shares& m, const uint32_t* idx, Shares* out) {
@@ -712,6 +892,7 @@ struct PlanRun {
         const uint64_t ne = P->n_edges, nw = words_of(ne);
         for (int b = 0; b < 2; b++)
             if (!(out->p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+        if (ne == 0) return FSS_OK;
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, P->n_vertices, idx,
                            m.p[0], m.p[1], out->p[0], out->p[1]);
         return check_launch("k_gather");
@@ -719,19 +900,138 @@ struct PlanRun {
 
     int emit(const Shares& m, uint64_t nrows, uint64_t word_offset) {
         const uint64_t nw = words_of(nrows);
+        if (nw == 0) return FSS_OK;
         uint32_t* o0 = P->d_out[0] + word_offset;
         uint32_t* o1 = P->d_out[1] + word_offset;
         if (m.is_public()) {
             hipLaunchKernelGGL(k_public_one, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, o0, o1);
             return check_launch("k_public_one");
         }
-        for (int b = 0; b < 2; b++) {
-            hipError_t e = hipMemcpyAsync(b ? o1 : o0, m.p[b], nw * 4, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return fail(FSS_EDEVICE, "match_query: copy: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL(k_copy_words, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, m.p[0], m.p[1], o0, o1);
+        return check_launch("k_copy_words");
+    }
+
+    // Steps 2 and 3 of the plan, after the predicate bits exist.
+    int finish() {
+        Shares m[FSS_MAX_QV], q[FSS_MAX_QV];
+        for (uint32_t i = 0; i < P->n_qv; i++)
+            for (uint32_t k = 0; k < P->n_pred; k++)
+                if ((uint32_t)P->preds[k].target == i) {
+                    int rc = AND(m[i], pbits[k], P->n_vertices, &m[i]);
+                    if (rc) return rc;
+                }
+        for (uint32_t j = 0; j + 1 < P->n_qv; j++)
+            for (uint32_t k = 0; k < P->n_pred; k++)
+                if ((uint32_t)P->preds[k].target == P->n_qv + j) {
+                    int rc = AND(q[j], pbits[k], P->n_edges, &q[j]);
+                    if (rc) return rc;
+                }
+        if (P->n_qv == 1) return emit(m[0], P->n_vertices, 0);
+        const uint64_t we = words_of(P->n_edges);
+        for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
+            Shares g, h, r1, r2;
+            int rc = gather(m[j], P->d_src, &g);
+            if (!rc) rc = gather(m[j + 1], P->d_dst, &h);
+            if (!rc) rc = AND(g, h, P->n_edges, &r1);
+            if (!rc) rc = AND(r1, q[j], P->n_edges, &r2);
+            if (!rc) rc = emit(r2, P->n_edges, (uint64_t)j * we);
+            if (rc) return rc;
         }
         return FSS_OK;
     }
 };
+
+// ----------------------------------------------------------------- batch queue plumbing
+
+struct Tuning {
+    uint32_t rows_per_thread = 1;   // eval tile = 1024 * rows_per_thread rows
+    uint32_t wg_per_cu = 2;         // persistent grid = wg_per_cu * CUs
+};
+Tuning g_tuning;
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Descriptors reach the device through a pinned staging buffer owned by the
+// library; a buffer is reused only after its previous upload completed.
+struct Staging {
+    std::mutex mu;
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+Staging g_staging;
+
+int upload(const void* src, size_t bytes, void* d_dst, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_staging.mu);
+    if (g_staging.pending) {
+        if (hipEventSynchronize(g_staging.done) != hipSuccess) return fail(FSS_EDEVICE, "batch: staging wait failed");
+        g_staging.pending = false;
+    }
+    if (!g_staging.done && hipEventCreateWithFlags(&g_staging.done, hipEventDisableTiming) != hipSuccess)
+        return fail(FSS_EDEVICE, "batch: event creation failed");
+    if (g_staging.cap < bytes) {
+        if (g_staging.host) (void)hipHostFree(g_staging.host);
+        g_staging.host = nullptr;
+        g_staging.cap = 0;
+        if (hipHostMalloc(&g_staging.host, bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(FSS_EDEVICE, "batch: pinned staging allocation failed");
+        g_staging.cap = bytes;
+    }
+    memcpy(g_staging.host, src, bytes);
+    if (hipMemcpyAsync(d_dst, g_staging.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(g_staging.done, s) != hipSuccess)
+        return fail(FSS_EDEVICE, "batch: descriptor upload failed");
+    g_staging.pending = true;
+    return FSS_OK;
+}
+
+constexpr uint64_t kQueueHeader = 256;   // the tile counter
+
+uint64_t queue_bytes(uint64_t count) {
+    const uint64_t per = sizeof(QKeygen) > sizeof(QEval) ? sizeof(QKeygen) : sizeof(QEval);
+    return kQueueHeader + ((count * per + 255) & ~255ull);
+}
+
+// Heaviest descriptors first (ranges, then larger tables), tile offsets, one launch.
+int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_bytes, hipStream_t s) {
+    std::vector<QEval> q;
+    q.reserve(descs.size());
+    for (int pass = 0; pass < 2; pass++)
+        for (auto& d : descs)
+            if ((pass == 0) == (d.kind == FSS_RANGE) && d.n > 0) q.push_back(QEval{d});
+    std::stable_sort(q.begin(), q.end(), [](const QEval& a, const QEval& b) {
+        return (a.d.kind == FSS_RANGE) != (b.d.kind == FSS_RANGE) ? a.d.kind == FSS_RANGE : a.d.n > b.d.n;
+    });
+    if (q.empty()) return FSS_OK;
+    const uint64_t tile_rows = (uint64_t)kBlock * g_tuning.rows_per_thread;
+    uint64_t tiles = 0;
+    for (auto& e : q) {
+        e.d.block_start = (uint32_t)tiles;
+        tiles += (e.d.n + tile_rows - 1) / tile_rows;
+    }
+    if (tiles > 0xFFFFFFF0ull) return fail(FSS_EUNSUPPORTED, "batch: too many tiles");
+    if (!d_ws || ws_bytes < queue_bytes(q.size()))
+        return fail(FSS_ENOMEM, "batch: queue workspace needs %llu bytes", (unsigned long long)queue_bytes(q.size()));
+    uint32_t* counter = (uint32_t*)d_ws;
+    QEval* dq = (QEval*)((uint8_t*)d_ws + kQueueHeader);
+    int rc = upload(q.data(), q.size() * sizeof(QEval), dq, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
+    hipLaunchKernelGGL(k_eval_queue, dim3((unsigned)grid), dim3(kBlock), 0, s, dq, (uint32_t)q.size(),
+                       (uint32_t)tiles, g_tuning.rows_per_thread, counter);
+    return check_launch("k_eval_queue");
+}
 
 }  // namespace
 
@@ -745,99 +1045,156 @@ uint64_t match_workspace_bytes(const match_plan* plan) {
 
 int match_query(const match_plan* P, int32_t party_mask, void* stream) {
     t_err.clear();
-    if (!P) return fail(FSS_EINVAL, "match_query: plan is NULL");
     if (party_mask != 3) return fail(FSS_EUNSUPPORTED, "match_query: party_mask must be 3 (both parties simulated)");
-    if (P->n_qv == 0 || P->n_qv > FSS_MAX_QV) return fail(FSS_EINVAL, "match_query: n_qv %u outside 1..%d", P->n_qv, FSS_MAX_QV);
-    if (P->n_pred > FSS_MAX_PREDS) return fail(FSS_EINVAL, "match_query: more than %d predicates", FSS_MAX_PREDS);
-    if (P->n_pred && !P->preds) return fail(FSS_EINVAL, "match_query: preds is NULL");
-    if (P->n_vertices > 0xFFFFFFFFull || P->n_edges > 0xFFFFFFFFull)
-        return fail(FSS_EUNSUPPORTED, "match_query: more than 2^32 rows");
-    if (!P->d_out[0] || !P->d_out[1]) return fail(FSS_EINVAL, "match_query: NULL output");
-    if (P->n_qv > 1 && (!P->d_src || !P->d_dst)) return fail(FSS_EINVAL, "match_query: NULL edge endpoints");
-    const uint32_t ntarget = 2 * P->n_qv - 1;
-    for (uint32_t k = 0; k < P->n_pred; k++) {
-        const fss_pred& p = P->preds[k];
-        if (p.target < 0 || (uint32_t)p.target >= ntarget)
-            return fail(FSS_EINVAL, "match_query: predicate %u targets %d (of %u)", k, p.target, ntarget);
-        const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
-        if (!p.keys || (p.keys->kind != FSS_EQ && p.keys->kind != FSS_RANGE))
-            return fail(FSS_EINVAL, "match_query: predicate %u has no valid key batch", k);
-        int rc = check_batch(p.keys, p.keys->kind, "match_query");
-        if (rc) return rc;
-        if (p.keys->n != rows) return fail(FSS_EINVAL, "match_query: predicate %u keys cover %llu rows, table has %llu",
-                                           k, (unsigned long long)p.keys->n, (unsigned long long)rows);
-        if (rows && (!p.d_xhat || !p.keys->key[0] || !p.keys->key[1]))
-            return fail(FSS_EINVAL, "match_query: predicate %u has a NULL buffer", k);
-        if (rows && (!aligned256(p.keys->key[0]) || !aligned256(p.keys->key[1])))
-            return fail(FSS_EINVAL, "match_query: predicate %u key buffers not 256-byte aligned", k);
-    }
-    const uint64_t need = plan_workspace(P);
-    if (!P->d_workspace || P->workspace_bytes < need)
-        return fail(FSS_ENOMEM, "match_query: workspace needs %llu bytes", (unsigned long long)need);
-
+    int rc = validate_plan(P, "match_query");
+    if (rc) return rc;
     PlanRun R{P, (hipStream_t)stream, Arena{(uint8_t*)P->d_workspace, P->workspace_bytes, 0}};
-    const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
-    const uint64_t wmax = wv > we ? wv : we;
-    for (int b = 0; b < 2; b++)
-        if (!(R.trip[b] = R.ws.take(3 * wmax))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-
-    // 1. every predicate, both parties, in launches of up to kEvalInline descriptors
-    Shares pbits[FSS_MAX_PREDS];
-    EvalDesc descs[kEvalInline];
-    uint32_t nd = 0;
-    for (uint32_t k = 0; k < P->n_pred; k++) {
-        const fss_pred& p = P->preds[k];
-        const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
-        for (int b = 0; b < 2; b++) {
-            if (!(pbits[k].p[b] = R.ws.take(words_of(rows)))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-            if (rows == 0) continue;
-            EvalDesc& d = descs[nd++];
-            d = EvalDesc{};
-            d.key = (const uint8_t*)p.keys->key[b];
-            d.xhat = p.d_xhat;
-            d.out = pbits[k].p[b];
-            d.n = rows;
-            d.kind = (uint32_t)p.keys->kind;
-            d.nbits = p.keys->nbits;
-            d.party = (uint32_t)b;
-            if (nd == kEvalInline) {
-                int rc = launch_eval(descs, nd, R.s);
-                if (rc) return rc;
-                nd = 0;
-            }
-        }
-    }
-    if (nd) {
-        int rc = launch_eval(descs, nd, R.s);
+    std::vector<EvalDesc> descs;
+    rc = R.setup(descs);
+    if (rc) return rc;
+    // every predicate, both parties, in launches of up to kEvalInline descriptors
+    for (size_t i = 0; i < descs.size(); i += kEvalInline) {
+        rc = launch_eval(descs.data() + i, (uint32_t)std::min<size_t>(kEvalInline, descs.size() - i), R.s);
         if (rc) return rc;
     }
+    return R.finish();
+}
 
-    // 2. AND-fold per query vertex, then per query edge
-    Shares m[FSS_MAX_QV], q[FSS_MAX_QV];
-    for (uint32_t i = 0; i < P->n_qv; i++) {
-        for (uint32_t k = 0; k < P->n_pred; k++)
-            if ((uint32_t)P->preds[k].target == i) {
-                int rc = R.AND(m[i], pbits[k], P->n_vertices, &m[i]);
-                if (rc) return rc;
-            }
-    }
-    for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
-        for (uint32_t k = 0; k < P->n_pred; k++)
-            if ((uint32_t)P->preds[k].target == P->n_qv + j) {
-                int rc = R.AND(q[j], pbits[k], P->n_edges, &q[j]);
-                if (rc) return rc;
-            }
-    }
-    if (P->n_qv == 1) return R.emit(m[0], P->n_vertices, 0);
+uint64_t fss_queue_workspace_bytes(uint64_t count) { return queue_bytes(count); }
 
-    // 3. hops: gather both endpoints' shares, then two ANDs
-    for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
-        Shares g, h, r1, r2;
-        int rc = R.gather(m[j], P->d_src, &g);
-        if (!rc) rc = R.gather(m[j + 1], P->d_dst, &h);
-        if (!rc) rc = R.AND(g, h, P->n_edges, &r1);
-        if (!rc) rc = R.AND(r1, q[j], P->n_edges, &r2);
-        if (!rc) rc = R.emit(r2, P->n_edges, (uint64_t)j * we);
+int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu) {
+    t_err.clear();
+    if (rows_per_thread < 1 || rows_per_thread > 8 || wg_per_cu < 1 || wg_per_cu > 2)
+        return fail(FSS_EINVAL, "fss_set_tuning: rows_per_thread 1..8, wg_per_cu 1..2");
+    g_tuning.rows_per_thread = rows_per_thread;
+    g_tuning.wg_per_cu = wg_per_cu;
+    return FSS_OK;
+}
+
+int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu) {
+    if (rows_per_thread) *rows_per_thread = g_tuning.rows_per_thread;
+    if (wg_per_cu) *wg_per_cu = g_tuning.wg_per_cu;
+    return FSS_OK;
+}
+
+int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,
+                     void* stream) {
+    t_err.clear();
+    if (count == 0) return FSS_OK;
+    if (!reqs) return fail(FSS_EINVAL, "fss_keygen_batch: reqs is NULL");
+    std::vector<QKeygen> q;
+    q.reserve(count);
+    for (uint32_t i = 0; i < count; i++) {
+        const fss_keygen_req& r = reqs[i];
+        const fss_keybatch* out = r.out;
+        if (!out) return fail(FSS_EINVAL, "fss_keygen_batch: request %u has no output", i);
+        if (out->kind != FSS_EQ && out->kind != FSS_RANGE)
+            return fail(FSS_EINVAL, "fss_keygen_batch: request %u bad kind", i);
+        if (!valid_nbits(out->nbits)) return fail(FSS_EINVAL, "fss_keygen_batch: request %u nbits", i);
+        if (out->n > 0xFFFFFFFFull) return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: more than 2^32 rows");
+        const uint64_t lim = 1ull << out->nbits;
+        if (out->kind == FSS_EQ && r.a_or_lo >= lim) return fail(FSS_EINVAL, "fss_keygen_batch: request %u a", i);
+        if (out->kind == FSS_RANGE && (r.a_or_lo > r.hi || r.hi >= lim))
+            return fail(FSS_EINVAL, "fss_keygen_batch: request %u bounds", i);
+        if (out->n == 0) continue;
+        if (!r.d_r || !out->key[0] || !out->key[1] || !aligned256(out->key[0]) || !aligned256(out->key[1]))
+            return fail(FSS_EINVAL, "fss_keygen_batch: request %u buffers", i);
+        QKeygen e{};
+        e.a.rk = dealer_key(r.seed);
+        e.a.key0 = (uint8_t*)out->key[0];
+        e.a.key1 = (uint8_t*)out->key[1];
+        e.a.r = r.d_r;
+        e.a.n = out->n;
+        e.a.kind = (uint32_t)out->kind;
+        e.a.nbits = out->nbits;
+        e.a.query = r.query_id;
+        e.a.pred = r.pred_id;
+        e.a.a_or_lo = r.a_or_lo;
+        e.a.hi = r.hi;
+        e.a.row_offset = r.row_offset;
+        if ((uint64_t)r.row_offset + out->n > (1ull << 32))
+            return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: request %u rows beyond 2^32", i);
+        q.push_back(e);
+    }
+    if (q.empty()) return FSS_OK;
+    std::stable_sort(q.begin(), q.end(), [](const QKeygen& a, const QKeygen& b) {
+        return (a.a.kind == FSS_RANGE) != (b.a.kind == FSS_RANGE) ? a.a.kind == FSS_RANGE : a.a.n > b.a.n;
+    });
+    uint64_t tiles = 0;
+    for (auto& e : q) {
+        e.tile_start = (uint32_t)tiles;
+        tiles += (e.a.n + kBlock / 2 - 1) / (kBlock / 2);
+    }
+    if (tiles > 0xFFFFFFF0ull) return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: too many tiles");
+    if (!d_queue || queue_bytes_avail < queue_bytes(q.size()))
+        return fail(FSS_ENOMEM, "fss_keygen_batch: queue workspace needs %llu bytes",
+                    (unsigned long long)queue_bytes(q.size()));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* counter = (uint32_t*)d_queue;
+    QKeygen* dq = (QKeygen*)((uint8_t*)d_queue + kQueueHeader);
+    int rc = upload(q.data(), q.size() * sizeof(QKeygen), dq, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
+    hipLaunchKernelGGL(k_keygen_queue, dim3((unsigned)grid), dim3(kBlock), 0, s, dq, (uint32_t)q.size(),
+                       (uint32_t)tiles, counter);
+    return check_launch("k_keygen_queue");
+}
+
+int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,
+                   void* stream) {
+    t_err.clear();
+    if (count == 0) return FSS_OK;
+    if (!reqs) return fail(FSS_EINVAL, "fss_eval_batch: reqs is NULL");
+    std::vector<EvalDesc> descs;
+    descs.reserve(count);
+    for (uint32_t i = 0; i < count; i++) {
+        const fss_eval_req& r = reqs[i];
+        if (!r.keys) return fail(FSS_EINVAL, "fss_eval_batch: request %u has no keys", i);
+        int rc = check_batch(r.keys, r.keys->kind, "fss_eval_batch");
+        if (rc) return rc;
+        if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "fss_eval_batch: request %u party", i);
+        if (r.keys->n == 0) continue;
+        if (!r.d_xhat || !r.d_out_bits || !r.keys->key[r.party] || !aligned256(r.keys->key[r.party]))
+            return fail(FSS_EINVAL, "fss_eval_batch: request %u buffers", i);
+        EvalDesc d{};
+        d.key = (const uint8_t*)r.keys->key[r.party];
+        d.xhat = r.d_xhat;
+        d.out = r.d_out_bits;
+        d.n = r.keys->n;
+        d.kind = (uint32_t)r.keys->kind;
+        d.nbits = r.keys->nbits;
+        d.party = (uint32_t)r.party;
+        descs.push_back(d);
+    }
+    return launch_eval_queue(descs, d_queue, queue_bytes_avail, (hipStream_t)stream);
+}
+
+int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
+                      uint64_t queue_bytes_avail, void* stream) {
+    t_err.clear();
+    if (count == 0) return FSS_OK;
+    if (!plans) return fail(FSS_EINVAL, "match_query_batch: plans is NULL");
+    if (party_mask != 3)
+        return fail(FSS_EUNSUPPORTED, "match_query_batch: party_mask must be 3 (both parties simulated)");
+    for (uint32_t i = 0; i < count; i++) {
+        int rc = validate_plan(&plans[i], "match_query_batch");
+        if (rc) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<PlanRun> runs;
+    runs.reserve(count);
+    std::vector<EvalDesc> descs;
+    for (uint32_t i = 0; i < count; i++) {
+        const match_plan* P = &plans[i];
+        runs.push_back(PlanRun{P, s, Arena{(uint8_t*)P->d_workspace, P->workspace_bytes, 0}});
+        int rc = runs.back().setup(descs);
+        if (rc) return rc;
+    }
+    int rc = launch_eval_queue(descs, d_queue, queue_bytes_avail, s);
+    if (rc) return rc;
+    for (auto& R : runs) {
+        rc = R.finish();
         if (rc) return rc;
     }
     return FSS_OK;

@@ -33,7 +33,8 @@ class fss_keybatch(ctypes.Structure):
 
 class fss_pred(ctypes.Structure):
     _fields_ = [("target", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("keys", ctypes.POINTER(fss_keybatch)), ("d_xhat", ctypes.c_void_p)]
+                ("keys", ctypes.POINTER(fss_keybatch)), ("d_xhat", ctypes.c_void_p),
+                ("d_bits", ctypes.c_void_p * 2)]
 
 
 class match_plan(ctypes.Structure):
@@ -43,6 +44,18 @@ class match_plan(ctypes.Structure):
                 ("d_src", ctypes.c_void_p), ("d_dst", ctypes.c_void_p),
                 ("preds", ctypes.POINTER(fss_pred)), ("d_out", ctypes.c_void_p * 2),
                 ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class fss_keygen_req(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("query_id", ctypes.c_uint32), ("pred_id", ctypes.c_uint32),
+                ("a_or_lo", ctypes.c_uint32), ("hi", ctypes.c_uint32), ("d_r", ctypes.c_void_p),
+                ("out", ctypes.POINTER(fss_keybatch)), ("row_offset", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class fss_eval_req(ctypes.Structure):
+    _fields_ = [("party", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keys", ctypes.POINTER(fss_keybatch)),
+                ("d_xhat", ctypes.c_void_p), ("d_out_bits", ctypes.c_void_p)]
 
 
 def _load():
@@ -63,6 +76,12 @@ def _load():
         "ss_and": ([i32, i32, u64, P, P, P, P, P, P], ctypes.c_int),
         "match_workspace_bytes": ([ctypes.POINTER(match_plan)], u64),
         "match_query": ([ctypes.POINTER(match_plan), i32, P], ctypes.c_int),
+        "fss_queue_workspace_bytes": ([u64], u64),
+        "fss_keygen_batch": ([ctypes.POINTER(fss_keygen_req), u32, P, u64, P], ctypes.c_int),
+        "fss_eval_batch": ([ctypes.POINTER(fss_eval_req), u32, P, u64, P], ctypes.c_int),
+        "match_query_batch": ([ctypes.POINTER(match_plan), u32, i32, P, u64, P], ctypes.c_int),
+        "fss_set_tuning": ([u32, u32], ctypes.c_int),
+        "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -74,7 +93,8 @@ def _load():
 LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
-           "match_query")
+           "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
+           "fss_set_tuning", "fss_get_tuning")
 
 
 def _check(rc: int):
@@ -127,6 +147,15 @@ class KeyBatch:
         self.key = [torch.empty(max(nbytes, 512), dtype=torch.uint8, device=dev) for _ in range(2)]
         self.c = fss_keybatch(kind, nbits, n, (ctypes.c_void_p * 2)(self.key[0].data_ptr(), self.key[1].data_ptr()))
 
+    @classmethod
+    def view(cls, kind: int, nbits: int, n: int, ptr0: int, ptr1: int):
+        """A batch over device memory owned elsewhere (256-byte aligned pointers)."""
+        kb = cls.__new__(cls)
+        kb.kind, kb.nbits, kb.n = kind, nbits, n
+        kb.key = [None, None]
+        kb.c = fss_keybatch(kind, nbits, n, (ctypes.c_void_p * 2)(ptr0, ptr1))
+        return kb
+
     @property
     def bytes_per_party(self) -> int:
         return fss_keybatch_bytes(self.kind, self.nbits, self.n)
@@ -161,12 +190,16 @@ class Plan:
     """A match_plan with its ctypes storage kept alive."""
 
     def __init__(self, seed, query_id, n_qv, n_vertices, n_edges, preds, src=None, dst=None):
-        """preds: list of (target, KeyBatch, xhat tensor)."""
+        """preds: list of (target, KeyBatch, xhat tensor) -- evaluated by match_query --
+        or (target, None, None, (bits0, bits1)) -- share bits already evaluated."""
         self._preds = (fss_pred * max(1, len(preds)))()
         self._keep = []
-        for i, (target, kb, xhat) in enumerate(preds):
-            self._preds[i] = fss_pred(target, 0, ctypes.pointer(kb.c), _ptr(xhat))
-            self._keep.append((kb, xhat))
+        for i, pr in enumerate(preds):
+            target, kb, xhat = pr[:3]
+            bits = pr[3] if len(pr) > 3 else (None, None)
+            self._preds[i] = fss_pred(target, 0, ctypes.pointer(kb.c) if kb is not None else None, _ptr(xhat),
+                                      (ctypes.c_void_p * 2)(_ptr(bits[0]), _ptr(bits[1])))
+            self._keep.append((kb, xhat, bits))
         self.c = match_plan()
         self.c.seed = seed
         self.c.query_id = query_id
@@ -204,3 +237,59 @@ def match_workspace_bytes(plan: Plan) -> int:
 
 def match_query(plan: Plan, party_mask: int = 3, stream=None):
     _check(LIB.match_query(ctypes.byref(plan.c), party_mask, _stream(stream)))
+
+
+# --------------------------------------------------------------------------- batches
+
+def fss_queue_workspace_bytes(count: int) -> int:
+    return int(LIB.fss_queue_workspace_bytes(count))
+
+
+class Queue:
+    """Device memory for the work queue of batch calls (counter + descriptors)."""
+
+    def __init__(self, capacity: int, device=None):
+        self.capacity = capacity
+        nbytes = fss_queue_workspace_bytes(max(1, capacity))
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device or torch.device("cuda"))
+
+    def ptr(self):
+        return self.buf.data_ptr(), self.buf.numel()
+
+
+def fss_keygen_batch(reqs, queue: Queue, stream=None):
+    """reqs: list of (seed, query_id, pred_id, a_or_lo, hi, r tensor, KeyBatch[, row_offset])."""
+    arr = (fss_keygen_req * max(1, len(reqs)))()
+    for i, rq in enumerate(reqs):
+        seed, qid, pid, a, hi, r, kb = rq[:7]
+        off = rq[7] if len(rq) > 7 else 0
+        arr[i] = fss_keygen_req(seed, qid, pid, a, hi, _ptr(r), ctypes.pointer(kb.c), off, 0)
+    d, nbytes = queue.ptr()
+    _check(LIB.fss_keygen_batch(arr, len(reqs), d, nbytes, _stream(stream)))
+
+
+def fss_eval_batch(reqs, queue: Queue, stream=None):
+    """reqs: list of (party, KeyBatch, xhat tensor, out tensor)."""
+    arr = (fss_eval_req * max(1, len(reqs)))()
+    for i, (party, kb, xhat, out) in enumerate(reqs):
+        arr[i] = fss_eval_req(party, 0, ctypes.pointer(kb.c), _ptr(xhat), _ptr(out))
+    d, nbytes = queue.ptr()
+    _check(LIB.fss_eval_batch(arr, len(reqs), d, nbytes, _stream(stream)))
+
+
+def match_query_batch(plans, queue: Queue, party_mask: int = 3, stream=None):
+    arr = (match_plan * max(1, len(plans)))()
+    for i, p in enumerate(plans):
+        arr[i] = p.c
+    d, nbytes = queue.ptr()
+    _check(LIB.match_query_batch(arr, len(plans), party_mask, d, nbytes, _stream(stream)))
+
+
+def set_tuning(rows_per_thread: int, wg_per_cu: int):
+    _check(LIB.fss_set_tuning(rows_per_thread, wg_per_cu))
+
+
+def get_tuning():
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    LIB.fss_get_tuning(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value

@@ -260,6 +260,28 @@ def config3(seed: int = 3, n_vertices: int = 1 << 22, n_edges: int = 1 << 25) ->
     return g, q
 
 
+def candidate_view(graph: Graph, rows: int) -> tuple:
+    """A query's candidate tables over ``rows`` rows: vertices [0, rows) and the
+    first ``rows`` edge rows whose endpoints are both below ``rows`` (a public
+    filter).  Returns (view graph, edge rows of the view in the full table)."""
+    r = min(rows, graph.n_vertices)
+    erows = np.flatnonzero((graph.src < r) & (graph.dst < r))[:rows]
+    view = Graph(r, graph.src[erows], graph.dst[erows], {k: v[:r] for k, v in graph.vcols.items()},
+                 {k: v[erows] for k, v in graph.ecols.items()})
+    return view, erows
+
+
+def view_shares(shares: dict, graph: Graph, view: Graph, erows: np.ndarray) -> dict:
+    """The servers' shares restricted to a candidate view (same share values)."""
+    out = {}
+    for k, (x0, x1) in shares.items():
+        if k.startswith("e:"):
+            out[k] = (x0[erows], x1[erows])
+        else:
+            out[k] = (x0[:view.n_vertices], x1[:view.n_vertices])
+    return out
+
+
 def batch_queries(seed: int, graph: Graph, count: int = 64, min_log_rows: int = 12,
                   max_log_rows: int = 22) -> list:
     """Uneven query mix: 1-5 predicates (equality : range = 1 : 1) over 1-4 query
