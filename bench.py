@@ -48,6 +48,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2209_03526_amd/csrc/fss_lib.hip", "paper_2209_03526_amd/csrc/aes_gfx950.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading), or
+    None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}.traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +86,9 @@ def parse():
     ap.add_argument("--log-rows", type=int, default=LOG_ROWS)
     ap.add_argument("--cpu-sample-log-rows", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="vertex-filter", choices=["vertex-filter", "batch64"])
+    ap.add_argument("--budget-gb", type=float, default=96.0, help="batch64: key memory budget of the batched runner")
+    ap.add_argument("--chunk-log-rows", type=int, default=20, help="batch64: rows per keygen/eval chunk (log2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
     return ap.parse_args()
@@ -72,6 +105,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch64":
+        return run_batch64(args, torch, fss, dev)
     n = 1 << args.log_rows
     log(f"generating {n} rows")
     graph, query = synth.config2(2, n=n)
@@ -171,7 +206,7 @@ def main():
     achieved = ops / (dk["ms"] / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 3),
                 "unit": "T int32 VALU ops/s (AES blocks x %d ops)" % AES_OPS,
-                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": measured_traffic(dom),
                 "aes_blocks_per_s": dk["aes_blocks"] / (dk["ms"] / 1e3)}
     for k, v in kernels.items():
         v["aes_gblocks_per_s"] = round(v["aes_blocks"] / (v["ms"] / 1e3) / 1e9, 3) if v["ms"] else None
@@ -205,6 +240,105 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_batch64(args, torch, fss, dev):
+    """64 uneven queries over the power-law graph (2^22 vertices, 2^25 edges):
+    plain = one query after another (per-predicate keygen launches, then
+    match_query); batched = chunked waves of one persistent keygen launch and
+    one persistent eval launch, then the queries' ANDs and joins."""
+    from paper_2209_03526_amd import autotune
+    from paper_2209_03526_amd.runner import ChunkedRunner, QueryJob
+
+    log("generating the 2^22 / 2^25 power-law graph")
+    g, _ = synth.config3(3)
+    shares = synth.share_columns(SEED, g.vcols)
+    shares.update({"e:" + k: v for k, v in synth.share_columns(SEED + 1, g.ecols).items()})
+    mix = synth.batch_queries(4, g, count=64)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
+
+    jobs, walks = [], 0
+    for q, rows in mix:
+        view, erows = synth.candidate_view(g, rows)
+        vsh = synth.view_shares(shares, g, view, erows)
+        masks = synth.pred_masks(SEED, q, view)
+        preds = []
+        for k, p in enumerate(q.preds):
+            on_edge = p.target >= q.n_qv
+            x0, x1 = vsh[("e:" if on_edge else "") + p.column]
+            nrow = view.n_edges if on_edge else view.n_vertices
+            r = T(masks[k]) if nrow else torch.zeros(1, dtype=torch.int32, device=dev)
+            xhat = torch.empty(max(nrow, 1), dtype=torch.int32, device=dev)
+            if nrow:
+                fss.fss_mask_open(T(x0), T(x1), r, xhat)
+            walks += 2 * nrow * (1 if p.kind == "eq" else 2)
+            preds.append(dict(target=p.target, kind=fss.EQ if p.kind == "eq" else fss.RANGE, rows=nrow,
+                              a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
+        jobs.append(QueryJob(SEED, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds,
+                             T(view.src) if view.n_edges else None, T(view.dst) if view.n_edges else None))
+    torch.cuda.synchronize()
+    log(f"64 queries ready: {walks / 1e6:.1f} M tree walks (both parties)")
+
+    def outputs(plan, job):
+        w = (job.n_vertices + 31) // 32 if job.n_qv == 1 else (job.n_qv - 1) * ((job.n_edges + 31) // 32)
+        return [plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
+
+    # plain: one query at a time
+    def plain():
+        res = []
+        for job in jobs:
+            kbs = []
+            for k, p in enumerate(job.preds):
+                kb = fss.KeyBatch(p["kind"], job.nbits, p["rows"], dev)
+                if p["rows"]:
+                    fss.fss_keygen(job.seed, job.query_id, k, p["a_or_lo"], p["hi"], p["r"], kb)
+                kbs.append((p["target"], kb, p["xhat"]))
+            plan = fss.Plan(job.seed, job.query_id, job.n_qv, job.n_vertices, job.n_edges, kbs, job.src,
+                            job.dst).allocate(dev)
+            fss.match_query(plan)
+            res.append(plan)
+            del kbs
+        return res
+
+    runner = ChunkedRunner(int(args.budget_gb * 1e9), chunk_rows=1 << args.chunk_log_rows, device=dev)
+    # autotune the persistent evaluation shape on one representative wave
+    probe = [j for j in jobs if any(p["rows"] >= 1 << 20 for p in j.preds)][:1] or jobs[:1]
+    autotune.tune(lambda: runner.run(probe), sum(p["rows"] for j in probe for p in j.preds))
+    log(f"tuning chosen: {autotune.chosen()}")
+
+    times = {}
+    for name in ("plain", "batched"):
+        for rep in range(1 + args.warmup):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "plain":
+                plans = plain()
+            else:
+                runner.waves = 0
+                runner.run(jobs)
+                plans = [j.plan for j in jobs]
+            torch.cuda.synchronize()
+            times[name] = time.perf_counter() - t0
+            log(f"{name} pass {rep + 1}: {times[name] * 1e3:.1f} ms")
+        if name == "plain":
+            plain_out = [outputs(p, j) for p, j in zip(plans, jobs)]
+            del plans
+            torch.cuda.empty_cache()
+    exact = all(np.array_equal(a[b], outputs(j.plan, j)[b]) for a, j in zip(plain_out, jobs) for b in range(2))
+    out = {
+        "metric": "queries/s, 64 uneven queries (1-5 predicates, 1-4 query vertices, 2^12..2^22 candidate rows)",
+        "value": 64 / times["batched"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "plain_qps": 64 / times["plain"], "speedup_vs_plain": times["plain"] / times["batched"],
+        "batched_ms": times["batched"] * 1e3, "plain_ms": times["plain"] * 1e3,
+        "walks": walks, "batched_evals_per_s_incl_keygen": walks / times["batched"],
+        "waves": runner.waves, "budget_gb": args.budget_gb, "chunk_rows": 1 << args.chunk_log_rows,
+        "tuning": {str(k): v for k, v in autotune.chosen().items()},
+        "bit_exact_batched_vs_plain": bool(exact), "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batch64: Chung-Lu 2^22 vertices / 2^25 edges, 64 queries"},
     }
     print(json.dumps(out), flush=True)
 

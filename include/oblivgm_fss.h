@@ -248,6 +248,29 @@ int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
                       uint64_t queue_bytes, void* stream);
 
+/*
+ * The paper's own secure predicate evaluation over one-hot attributes in
+ * three-party binary replicated secret sharing (Sec. V-B, Sec. V-C token of
+ * three replicated key pairs, Eq. predEval, Alg. 3).
+ *
+ * fss_eval_all: full-domain evaluation of ONE key -- party `party`'s key in row
+ *   key_row of batch k -- at every public position x in [0, npoints)
+ *   (npoints <= 2^nbits); ceil(npoints/32) packed words.  With masks r = 0 and
+ *   rows 0..2 of one fss_keygen call as the replicas j = 1..3, party 0 / 1 of
+ *   row j-1 is k_1^j / k_2^j.
+ * rss_sec_eval: one server's two terms of Eq. predEval for every candidate c:
+ *   out bit c = XOR_l (E_a[l] & S_a[c][l])  XOR  XOR_l (E_b[l] & S_b[c][l]),
+ *   where E_a, E_b are the full-domain evaluations of the server's two keys
+ *   (ceil(npos/32) words each) and S_a, S_b its two shares of the one-hot
+ *   attribute vectors, word-major: word w of candidate c at [w * ncand + c],
+ *   position p in bit p % 32 of word p / 32 (positions >= npos must be 0).
+ *   The three servers' outputs XOR to the predicate bit (a 3-out-of-3 share).
+ */
+int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_t npoints, uint32_t* d_out_bits,
+                 void* stream);
+int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
+                 const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream);
+
 /* Tile / occupancy shape of the persistent launches (process-wide):
  * rows_per_thread 1..8 (evaluation tile = 1024 * rows_per_thread rows),
  * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */

@@ -452,6 +452,58 @@ __global__ __launch_bounds__(kBlock) void k_triples(TripleArgs A) {
     }
 }
 
+// ----------------------------------------------------------------- one-hot RSS secEval (Eq. predEval)
+
+// Full-domain evaluation: key row `row` of a batch (party `party`) at every
+// point x in [0, npoints); each wave packs its 64 bits.
+__global__ __launch_bounds__(kBlock) void k_eval_points(const uint8_t* key, uint64_t n, uint64_t row, uint32_t kind,
+                                                       uint32_t nbits, uint32_t party, uint64_t npoints,
+                                                       uint32_t* out) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const LaneOff loff = lane_offset();
+    const uint64_t np = pad_rows(n);
+    uint32_t bit = 0;
+    if (x < npoints) {
+        if (kind == FSS_EQ)
+            bit = dpf_eval(key, np, row, nbits, party, (uint32_t)x, tab, loff);
+        else
+            bit = range_eval(key, np, row, nbits, party, (uint32_t)x, tab, loff);
+    }
+    const uint64_t ballot = __ballot(bit);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = x >> 5, nwords = (npoints + 31) >> 5;
+        if (w < nwords) out[w] = (uint32_t)ballot;
+        if (w + 1 < nwords) out[w + 1] = (uint32_t)(ballot >> 32);
+    }
+}
+
+// One server's share of the predicate bit of every candidate: the XOR over
+// positions of Eval(k_a, l) & <e[l]>_a, XORed with the same for (k_b, share b).
+// Shares are word-major ([word][candidate]): a wave reads 256 contiguous bytes
+// per word; the evaluation words are uniform (scalar loads).
+__global__ void k_rss_eval(uint64_t ncand, uint32_t nwords_pos, const uint32_t* __restrict__ eval_a,
+                           const uint32_t* __restrict__ eval_b, const uint32_t* __restrict__ share_a,
+                           const uint32_t* __restrict__ share_b, uint32_t* __restrict__ out) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    if (c < ncand) {
+        for (uint32_t w = 0; w < nwords_pos; w++) {
+            const uint64_t at = (uint64_t)w * ncand + c;
+            acc = __builtin_amdgcn_bitop3_b32(acc, share_a[at], eval_a[w], 0x78);   // acc ^ (s & e): f(0xF0, 0xCC, 0xAA)
+            acc = __builtin_amdgcn_bitop3_b32(acc, share_b[at], eval_b[w], 0x78);
+        }
+    }
+    const uint64_t ballot = __ballot(__builtin_popcount(acc) & 1u);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = c >> 5, nw = (ncand + 31) >> 5;
+        if (w < nw) out[w] = (uint32_t)ballot;
+        if (w + 1 < nw) out[w + 1] = (uint32_t)(ballot >> 32);
+    }
+}
+
 // ----------------------------------------------------------------- streaming kernels (A1, A6, A7)
 
 __global__ void k_mask_open(uint64_t n, const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1,
@@ -1061,6 +1113,36 @@ int match_query(const match_plan* P, int32_t party_mask, void* stream) {
 }
 
 uint64_t fss_queue_workspace_bytes(uint64_t count) { return queue_bytes(count); }
+
+int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_t npoints, uint32_t* d_out_bits,
+                 void* stream) {
+    t_err.clear();
+    if (!k) return fail(FSS_EINVAL, "fss_eval_all: key batch is NULL");
+    int rc = check_batch(k, k->kind, "fss_eval_all");
+    if (rc) return rc;
+    if (party != 0 && party != 1) return fail(FSS_EINVAL, "fss_eval_all: party %d is not 0 or 1", party);
+    if (key_row >= k->n) return fail(FSS_EINVAL, "fss_eval_all: key row %llu of %llu", (unsigned long long)key_row,
+                                     (unsigned long long)k->n);
+    if (npoints > (1ull << k->nbits)) return fail(FSS_EINVAL, "fss_eval_all: more points than the domain");
+    if (npoints == 0) return FSS_OK;
+    if (!d_out_bits || !k->key[party] || !aligned256(k->key[party])) return fail(FSS_EINVAL, "fss_eval_all: buffers");
+    hipLaunchKernelGGL(k_eval_points, dim3((unsigned)((npoints + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, (const uint8_t*)k->key[party], k->n, key_row, (uint32_t)k->kind,
+                       k->nbits, (uint32_t)party, npoints, d_out_bits);
+    return check_launch("k_eval_points");
+}
+
+int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
+                 const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream) {
+    t_err.clear();
+    if (ncand == 0) return FSS_OK;
+    if (npos == 0) return fail(FSS_EINVAL, "rss_sec_eval: no positions");
+    if (!d_eval_a || !d_eval_b || !d_share_a || !d_share_b || !d_out_bits)
+        return fail(FSS_EINVAL, "rss_sec_eval: NULL buffer");
+    hipLaunchKernelGGL(k_rss_eval, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, (hipStream_t)stream, ncand,
+                       (npos + 31) / 32, d_eval_a, d_eval_b, d_share_a, d_share_b, d_out_bits);
+    return check_launch("k_rss_eval");
+}
 
 int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu) {
     t_err.clear();

@@ -81,6 +81,8 @@ def _load():
         "fss_eval_batch": ([ctypes.POINTER(fss_eval_req), u32, P, u64, P], ctypes.c_int),
         "match_query_batch": ([ctypes.POINTER(match_plan), u32, i32, P, u64, P], ctypes.c_int),
         "fss_set_tuning": ([u32, u32], ctypes.c_int),
+        "fss_eval_all": ([i32, ctypes.POINTER(fss_keybatch), u64, u64, P, P], ctypes.c_int),
+        "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
@@ -94,7 +96,7 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning")
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval")
 
 
 def _check(rc: int):
@@ -293,3 +295,14 @@ def get_tuning():
     a, b = ctypes.c_uint32(), ctypes.c_uint32()
     LIB.fss_get_tuning(ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+# --------------------------------------------------------------------------- one-hot RSS secEval
+
+def fss_eval_all(party: int, keys: KeyBatch, key_row: int, npoints: int, out_bits, stream=None):
+    _check(LIB.fss_eval_all(party, ctypes.byref(keys.c), key_row, npoints, _ptr(out_bits), _stream(stream)))
+
+
+def rss_sec_eval(ncand: int, npos: int, eval_a, eval_b, share_a, share_b, out_bits, stream=None):
+    _check(LIB.rss_sec_eval(ncand, npos, _ptr(eval_a), _ptr(eval_b), _ptr(share_a), _ptr(share_b), _ptr(out_bits),
+                            _stream(stream)))

@@ -164,6 +164,30 @@ def pred_masks(seed: int, query: Query, graph: Graph) -> list:
             for k, p in enumerate(query.preds)]
 
 
+def onehot_rss(seed: int, values: np.ndarray, npos: int) -> np.ndarray:
+    """Three binary shares of the one-hot encoding of each value (Sec. V-B):
+    shares 1 and 2 uniform, share 3 = onehot ^ share 1 ^ share 2.
+    Returns a (3, C, npos) array of 0/1."""
+    rng = _rng(seed, 121)
+    c = values.size
+    onehot = np.zeros((c, npos), np.uint8)
+    onehot[np.arange(c), values.astype(np.int64)] = 1
+    s1 = rng.integers(0, 2, (c, npos), dtype=np.uint8)
+    s2 = rng.integers(0, 2, (c, npos), dtype=np.uint8)
+    return np.stack([s1, s2, onehot ^ s1 ^ s2])
+
+
+def pack_word_major(bits: np.ndarray) -> np.ndarray:
+    """(C, npos) 0/1 -> uint32 words laid out [word][candidate]: word w of
+    candidate c holds positions 32w .. 32w+31 (position p at bit p % 32)."""
+    c, npos = bits.shape
+    nw = (npos + 31) // 32
+    padded = np.zeros((c, nw * 32), np.uint8)
+    padded[:, :npos] = bits
+    words = np.packbits(padded.reshape(c, nw, 32), axis=2, bitorder="little").view("<u4").reshape(c, nw)
+    return np.ascontiguousarray(words.T).astype(np.uint32)
+
+
 # --------------------------------------------------------------------------- workloads
 
 def tiny_graph(seed: int, n_vertices: int = 12, n_edges: int = 30, label_range: int = 4,

@@ -1,0 +1,65 @@
+"""Parity of the paper's own secEval on the GPU (one-hot RSS attributes,
+replicated FSS keys, Eq. predEval): full-domain evaluations and each server's
+share bits equal the oracle's bit for bit; the three shares XOR to the
+plaintext predicate."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import DEV, T, U
+from oracle import fss as ofss
+from oracle import rss as orss
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_03526_amd import fss as lib
+    torch.cuda.set_device(0)
+    return lib
+
+
+def _gpu_token(fss, kind, npos, seed, query, pred, a=0, lo=0, hi=0):
+    nb = orss.domain_bits(npos)
+    kb = fss.KeyBatch(fss.EQ if kind == "eq" else fss.RANGE, nb, 3)
+    fss.fss_keygen(seed, query, pred, a if kind == "eq" else lo, hi, torch.zeros(3, dtype=torch.int32, device=DEV), kb)
+    return kb, nb
+
+
+@pytest.mark.parametrize("kind,npos,ncand", [("eq", 64, 100003), ("eq", 256, 4099), ("range", 200, 70001),
+                                             ("range", 16, 1), ("eq", 33, 640)])
+def test_sec_eval_parity(fss, kind, npos, ncand):
+    rng = np.random.default_rng(npos + ncand)
+    values = rng.integers(0, npos, ncand).astype(np.uint32)
+    shares = synth.onehot_rss(npos + 7, values, npos)
+    a, lo, hi = int(values[0]), npos // 5, npos - npos // 4
+    seed, q, p = 77, 5, 3
+    okeys, nb = orss.token(kind, npos, seed, q, p, a=a, lo=lo, hi=hi)
+    kb, nb2 = _gpu_token(fss, kind, npos, seed, q, p, a=a, lo=lo, hi=hi)
+    assert nb == nb2
+    nw = (npos + 31) // 32
+    ev = {}
+    for party in (0, 1):
+        for rep in range(3):
+            o = torch.zeros(nw, dtype=torch.int32, device=DEV)
+            fss.fss_eval_all(party, kb, rep, npos, o)
+            got = ofss.unpack_bits(U(o), npos)
+            want = orss.eval_all(kind, nb, party, okeys[party], rep, npos)
+            np.testing.assert_array_equal(got, want)
+            ev[(party, rep)] = o
+    dev_sh = [T(synth.pack_word_major(shares[j])) for j in range(3)]
+    want = orss.server_shares(kind, npos, okeys, nb, shares)
+    xs = []
+    for i, ((pa, ra, ja), (pb, rb, jb)) in enumerate(orss.SERVER_TERMS):
+        out = torch.full(((ncand + 31) // 32,), -1, dtype=torch.int32, device=DEV)
+        fss.rss_sec_eval(ncand, npos, ev[(pa, ra)], ev[(pb, rb)], dev_sh[ja], dev_sh[jb], out)
+        xi = ofss.unpack_bits(U(out), ncand)
+        np.testing.assert_array_equal(xi, want[i])
+        xs.append(U(out))
+    truth = (values == a) if kind == "eq" else ((values >= lo) & (values < hi))
+    np.testing.assert_array_equal(ofss.unpack_bits(xs[0] ^ xs[1] ^ xs[2], ncand), truth.astype(np.uint8))
+    assert (xs[0][-1] >> (ncand % 32 or 32) if ncand % 32 else 0) == 0
