@@ -107,6 +107,16 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
                const uint32_t* d_r, const fss_keybatch* out, void* stream);
 
 /*
+ * A2 (dealer) -- the per-row masks r of the masked-input approach (Sec. V-C),
+ * drawn from the dealer's counter-mode generator: d_r[i] = little-endian word 0
+ * of AES_{LE64(seed)||"OBLIVGM1"}(LE16 2 || LE16 0 || LE32 query_id ||
+ * LE32 pred_id || LE32 (row_offset + i)), i < n.  (Callers may also supply
+ * masks of their own; fss_keygen only needs them to be fresh per row.)
+ */
+int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t row_offset, uint64_t n,
+                     uint32_t* d_r, void* stream);
+
+/*
  * A3 + A5 -- DPF evaluation (Def. 3 Eval) by `party` (0 or 1) on the opened
  * values d_xhat[0..n): writes ceil(n/32) packed share words to d_out_bits.
  * XOR of both parties' words is [x == a] per row.  k->kind must be FSS_EQ.

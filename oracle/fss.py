@@ -74,6 +74,7 @@ def lib():
             "oracle_eval_eq": ([u32, i32, P, P, sz, P], None),
             "oracle_eval_range": ([u32, i32, P, P, sz, P], None),
             "oracle_triples": ([u64, u32, u32, P, sz, P, P, P, P, P, P], None),
+            "oracle_masks": ([u64, u32, u32, u32, sz, P], None),
             "oracle_sizeof_dpf_key": ([], sz),
             "oracle_sizeof_dcf_key": ([], sz),
             "oracle_sizeof_range_key": ([], sz),
@@ -213,6 +214,13 @@ def eval_range(n: int, party: int, keys: np.ndarray, xhat: np.ndarray) -> np.nda
     out = np.zeros(xhat.size, np.uint8)
     lib().oracle_eval_range(n, party, _p(keys), _p(xhat), xhat.size, _p(out))
     return out
+
+
+def masks(seed: int, query: int, pred: int, count: int, row_offset: int = 0) -> np.ndarray:
+    """The dealer's masks drawn from its counter-mode generator (domain 2)."""
+    r = np.zeros(count, np.uint32)
+    lib().oracle_masks(seed, query, pred, row_offset, count, _p(r))
+    return r
 
 
 def mask_open(x0: np.ndarray, x1: np.ndarray, r: np.ndarray) -> np.ndarray:

@@ -570,6 +570,20 @@ void oracle_triples(uint64_t seed, uint32_t query, uint32_t and_id, const uint32
     }
 }
 
+/* Dealer masks (RNG domain 2): r[i] = little-endian word 0 of block
+ * (2, 0, query, pred, row_offset + i). */
+void oracle_masks(uint64_t seed, uint32_t query, uint32_t pred, uint32_t row_offset, size_t count, uint32_t *r)
+{
+    uint8_t rk[176];
+    oracle_rng_key(seed, rk);
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < (long long)count; i++) {
+        uint8_t blk[16];
+        oracle_rng_block_rk(rk, 2, 0, query, pred, row_offset + (uint32_t)i, blk);
+        r[i] = le32(blk);
+    }
+}
+
 size_t oracle_sizeof_dpf_key(void) { return sizeof(oracle_dpf_key); }
 size_t oracle_sizeof_dcf_key(void) { return sizeof(oracle_dcf_key); }
 size_t oracle_sizeof_range_key(void) { return sizeof(oracle_range_key); }

@@ -417,6 +417,25 @@ __global__ __launch_bounds__(kBlock, 8) void k_eval_queue(const QEval* __restric
     }
 }
 
+struct MaskArgs {
+    RoundKeys rk;
+    uint32_t* r;
+    uint64_t n;
+    uint32_t query;
+    uint32_t pred;
+    uint32_t row_offset;
+};
+
+// r[i] = word 0 of the counter-mode block (2, 0, query, pred, row_offset + i).
+__global__ __launch_bounds__(kBlock) void k_masks(MaskArgs A) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= A.n) return;
+    A.r[i] = rng_block(A.rk, 2, 0, A.query, A.pred, A.row_offset + (uint32_t)i, tab, lane_offset()).x;
+}
+
 struct TripleArgs {
     RoundKeys rk;
     uint32_t* t0;           // a0 | b0 | c0
@@ -749,6 +768,23 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
     hipLaunchKernelGGL(k_keygen, dim3((unsigned)((2 * out->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        (hipStream_t)stream, A);
     return check_launch("k_keygen");
+}
+
+int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t row_offset, uint64_t n,
+                     uint32_t* d_r, void* stream) {
+    t_err.clear();
+    if (n == 0) return FSS_OK;
+    if (!d_r) return fail(FSS_EINVAL, "fss_dealer_masks: NULL buffer");
+    if ((uint64_t)row_offset + n > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "fss_dealer_masks: rows beyond 2^32");
+    MaskArgs A{};
+    A.rk = dealer_key(seed);
+    A.r = d_r;
+    A.n = n;
+    A.query = query_id;
+    A.pred = pred_id;
+    A.row_offset = row_offset;
+    hipLaunchKernelGGL(k_masks, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, A);
+    return check_launch("k_masks");
 }
 
 int fss_eval_eq(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits, void* stream) {

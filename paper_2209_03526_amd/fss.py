@@ -82,6 +82,7 @@ def _load():
         "match_query_batch": ([ctypes.POINTER(match_plan), u32, i32, P, u64, P], ctypes.c_int),
         "fss_set_tuning": ([u32, u32], ctypes.c_int),
         "fss_eval_all": ([i32, ctypes.POINTER(fss_keybatch), u64, u64, P, P], ctypes.c_int),
+        "fss_dealer_masks": ([u64, u32, u32, u32, u64, P, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
@@ -96,7 +97,7 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval")
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks")
 
 
 def _check(rc: int):
@@ -169,6 +170,10 @@ def fss_mask_open(x0, x1, r, xhat, stream=None):
 
 def fss_keygen(seed: int, query_id: int, pred_id: int, a_or_lo: int, hi: int, r, out: KeyBatch, stream=None):
     _check(LIB.fss_keygen(seed, query_id, pred_id, a_or_lo, hi, _ptr(r), ctypes.byref(out.c), _stream(stream)))
+
+
+def fss_dealer_masks(seed: int, query_id: int, pred_id: int, n: int, r, row_offset: int = 0, stream=None):
+    _check(LIB.fss_dealer_masks(seed, query_id, pred_id, row_offset, n, _ptr(r), _stream(stream)))
 
 
 def fss_eval_eq(party: int, keys: KeyBatch, xhat, out_bits, stream=None):

@@ -259,3 +259,10 @@ def test_empty_inputs_are_noops(fss):
     fss.fss_keygen(1, 1, 1, 0, 5, torch.zeros(1, dtype=torch.int32, device=DEV), kb)
     fss.fss_eval_lt(0, kb, torch.zeros(1, dtype=torch.int32, device=DEV), torch.zeros(1, dtype=torch.int32, device=DEV))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,off", [(1, 0), (1000, 0), (70001, 12345)])
+def test_dealer_masks(fss, n, off):
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    fss.fss_dealer_masks(31337, 8, 2, n, out, row_offset=off)
+    np.testing.assert_array_equal(U(out), ofss.masks(31337, 8, 2, n, row_offset=off))

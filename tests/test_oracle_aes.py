@@ -83,3 +83,13 @@ def test_dealer_rng_is_aes_counter_mode():
         blk = (dom.to_bytes(2, "little") + j.to_bytes(2, "little") + q.to_bytes(4, "little") +
                p.to_bytes(4, "little") + e.to_bytes(4, "little"))
         assert fss.rng_block(seed, dom, j, q, p, e) == _openssl_ecb(key, blk)
+
+
+@pytest.mark.skipif(shutil.which("openssl") is None, reason="openssl CLI not present")
+def test_dealer_masks_are_domain_2_words():
+    r = fss.masks(0xABCDEF, 9, 4, 6, row_offset=100)
+    key = (0xABCDEF).to_bytes(8, "little") + b"OBLIVGM1"
+    for i in range(6):
+        blk = (2).to_bytes(2, "little") + (0).to_bytes(2, "little") + (9).to_bytes(4, "little") + \
+              (4).to_bytes(4, "little") + (100 + i).to_bytes(4, "little")
+        assert int(r[i]) == int.from_bytes(_openssl_ecb(key, blk)[:4], "little")
