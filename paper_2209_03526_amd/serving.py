@@ -1,0 +1,280 @@
+"""Serving loop over a graph resident in HBM.
+
+Requests (path queries over candidate tables of the resident graph) arrive
+over time.  The served path admits them in arrival order while the device
+memory they need (masks, opened values, share bits, plan workspace, candidate
+edge tables) fits the budget left next to the key arena, and runs continuous
+batching: every wave takes the not-yet-evaluated row chunks of all admitted
+requests, in arrival order, up to the key arena -- so requests that arrived
+while others were on the GPU join the next wave -- as one persistent dealer
+launch and one persistent evaluation launch.  A request whose predicate bits
+are complete is finished (ANDs, joins) right after that wave.  The plain path
+serves one request at a time with the per-request calls.
+
+Latency is arrival -> result shares in device memory, timed by HIP events on
+the serving stream against an event recorded when the clock starts.  Results
+are bit-identical on both paths (every kernel is a pure function of its rows),
+which the tests check request by request.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import fss
+from .runner import KeyArena
+
+
+@dataclass
+class ResidentGraph:
+    """Both servers' shares of every column plus the public endpoints, on the device."""
+    n_vertices: int
+    n_edges: int
+    src: torch.Tensor
+    dst: torch.Tensor
+    vshares: dict            # column -> (x0, x1) int32 tensors
+    eshares: dict
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds after the start
+    query: object            # synth.Query (query_id unique per request)
+    rows: int                # candidate table size
+    seed: int
+    # filled while served
+    view: dict = field(default_factory=dict)
+    preds: list = field(default_factory=list)
+    bits: list = field(default_factory=list)
+    plan: object = None
+    mem: int = 0
+    done_event: object = None
+    latency_ms: float = 0.0
+
+
+def _words(rows):
+    return max(1, (rows + 31) // 32)
+
+
+def prepare(req: Request, g: ResidentGraph, device, stream=None):
+    """Candidate view, fresh dealer masks and opened values on the device."""
+    q = req.query
+    r_v = min(req.rows, g.n_vertices)
+    need_edges = q.n_qv > 1
+    if need_edges:
+        ok = torch.nonzero((g.src < r_v) & (g.dst < r_v)).flatten()[:req.rows]
+        erows = ok
+        n_e = int(erows.numel())
+        src, dst = g.src[erows].contiguous(), g.dst[erows].contiguous()
+    else:
+        erows, n_e, src, dst = None, 0, None, None
+    req.view = dict(n_vertices=r_v, n_edges=n_e, src=src, dst=dst)
+    req.preds = []
+    for k, p in enumerate(q.preds):
+        on_edge = p.target >= q.n_qv
+        rows = n_e if on_edge else r_v
+        if on_edge:
+            x0, x1 = (t[erows] for t in g.eshares[p.column])
+        else:
+            x0, x1 = (t[:r_v] for t in g.vshares[p.column])
+        r = torch.empty(max(rows, 1), dtype=torch.int32, device=device)
+        xhat = torch.empty(max(rows, 1), dtype=torch.int32, device=device)
+        if rows:
+            fss.fss_dealer_masks(req.seed, q.query_id, k, rows, r, stream=stream)
+            fss.fss_mask_open(x0.contiguous(), x1.contiguous(), r, xhat, stream)
+        req.preds.append(dict(target=p.target, kind=fss.EQ if p.kind == "eq" else fss.RANGE, rows=rows,
+                              a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
+    return req
+
+
+def memory_bound(req: Request) -> int:
+    """Device bytes a request holds while admitted (keys excluded: they live
+    in the wave arena): candidate edge endpoints and columns, masks, opened
+    values, share bits and the plan workspace -- bounded with every table at
+    ``rows`` rows."""
+    rows = req.rows
+    npred = len(req.query.preds)
+    per_table = 8 * rows + 16 * _words(rows)
+    return 16 * rows + npred * (per_table + 16 * rows) + 32 * _words(rows) * (2 * npred + 8 * req.query.n_qv)
+
+
+def request_key_bytes(req: Request) -> int:
+    return sum(2 * fss.fss_keybatch_bytes(p["kind"], 32, p["rows"]) for p in req.preds)
+
+
+def _plan(req: Request, bits_given: bool, device):
+    q, v = req.query, req.view
+    if bits_given:
+        preds = [(p["target"], None, None, req.bits[k]) for k, p in enumerate(req.preds)]
+    else:
+        preds = [(p["target"], p["kb"], p["xhat"]) for p in req.preds]
+    return fss.Plan(req.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
+                    v["dst"]).allocate(device)
+
+
+class ServedPath:
+    def __init__(self, graph: ResidentGraph, budget_bytes: int, key_arena_bytes: int, chunk_rows: int = 1 << 20,
+                 device=None, stream=None):
+        assert key_arena_bytes < budget_bytes and chunk_rows % 64 == 0
+        self.g = graph
+        self.device = device or torch.device("cuda")
+        self.stream = stream or torch.cuda.current_stream()
+        self.budget = budget_bytes
+        self.arena = KeyArena(key_arena_bytes, self.device)
+        self.chunk_rows = chunk_rows
+        self.queue = fss.Queue(2048, self.device)
+        self.waves = 0
+        self.max_in_flight = 0
+
+    def run(self, requests, clock_start_event, t0):
+        """Serve `requests` (sorted by arrival) in real time from host time t0."""
+        pending = deque(requests)
+        admitted = []           # requests with chunks left: (req, deque of chunk items)
+        in_mem = []             # admitted, not released
+        used = 0
+        free_at = self.budget - self.arena.nbytes
+        while pending or admitted:
+            now = time.perf_counter() - t0
+            # admission, in arrival order, while memory allows
+            while pending and pending[0].arrival <= now:
+                req = pending[0]
+                req.mem = memory_bound(req)
+                if in_mem and used + req.mem > free_at:
+                    break          # admitted once memory frees up (arrival order is kept)
+                pending.popleft()
+                prepare(req, self.g, self.device, self.stream)
+                req.bits = [tuple(torch.empty(_words(p["rows"]), dtype=torch.int32, device=self.device)
+                                  for _ in range(2)) for p in req.preds]
+                items = deque()
+                for k, p in enumerate(req.preds):
+                    for c0 in range(0, p["rows"], self.chunk_rows):
+                        items.append((k, c0, min(self.chunk_rows, p["rows"] - c0)))
+                admitted.append((req, items))
+                in_mem.append(req)
+                used += req.mem
+            self.max_in_flight = max(self.max_in_flight, len(admitted))
+            if not admitted:
+                if pending:
+                    wait = pending[0].arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.002))
+                continue
+            # one wave over the admitted requests' chunks, oldest first
+            self.arena.reset()
+            kg, ev, finished = [], [], []
+            for req, items in admitted:
+                while items:
+                    k, c0, n = items[0]
+                    p = req.preds[k]
+                    half = fss.fss_keybatch_bytes(p["kind"], 32, n)
+                    if kg and self.arena.used + 2 * half > self.arena.nbytes:
+                        break
+                    items.popleft()
+                    kb = fss.KeyBatch.view(p["kind"], 32, n, self.arena.take(half), self.arena.take(half))
+                    kg.append((req.seed, req.query.query_id, k, p["a_or_lo"], p["hi"], p["r"][c0:c0 + n], kb, c0))
+                    for b in range(2):
+                        ev.append((b, kb, p["xhat"][c0:c0 + n], req.bits[k][b][c0 // 32:]))
+                if not items:
+                    finished.append(req)
+                if kg and self.arena.used >= self.arena.nbytes:
+                    break
+            if kg:
+                if len(ev) > self.queue.capacity:
+                    self.queue = fss.Queue(2 * len(ev), self.device)
+                fss.fss_keygen_batch(kg, self.queue, self.stream)
+                fss.fss_eval_batch(ev, self.queue, self.stream)
+                self.waves += 1
+            if finished:
+                plans = []
+                for req in finished:
+                    req.plan = _plan(req, True, self.device)
+                    plans.append(req.plan)
+                fss.match_query_batch(plans, self.queue, 3, self.stream)
+                for req in finished:
+                    req.done_event = torch.cuda.Event(enable_timing=True)
+                    req.done_event.record(self.stream)
+                    _drop_intermediates(req)   # stream-ordered allocator: safe once enqueued
+                admitted = [(r, it) for r, it in admitted if r not in finished]
+            # the admission budget is returned once a request's results are in device memory
+            keep = []
+            for req in in_mem:
+                if req.done_event is not None and req.done_event.query():
+                    used -= req.mem
+                else:
+                    keep.append(req)
+            in_mem = keep
+        torch.cuda.synchronize()
+        for req in requests:
+            req.latency_ms = clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival
+        return requests
+
+
+class PlainPath:
+    """One request at a time: masks, open, per-predicate keygen, match_query."""
+
+    def __init__(self, graph: ResidentGraph, device=None, stream=None):
+        self.g = graph
+        self.device = device or torch.device("cuda")
+        self.stream = stream or torch.cuda.current_stream()
+
+    def run(self, requests, clock_start_event, t0):
+        for req in requests:
+            wait = req.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            prepare(req, self.g, self.device, self.stream)
+            for k, p in enumerate(req.preds):
+                p["kb"] = fss.KeyBatch(p["kind"], 32, p["rows"], self.device)
+                if p["rows"]:
+                    fss.fss_keygen(req.seed, req.query.query_id, k, p["a_or_lo"], p["hi"], p["r"], p["kb"],
+                                   self.stream)
+            req.plan = _plan(req, False, self.device)
+            fss.match_query(req.plan, 3, self.stream)
+            req.done_event = torch.cuda.Event(enable_timing=True)
+            req.done_event.record(self.stream)
+            _drop_intermediates(req)
+        torch.cuda.synchronize()
+        for req in requests:
+            req.latency_ms = clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival
+        return requests
+
+
+def _drop_intermediates(req: Request):
+    """Release everything but the result shares (their last use is enqueued)."""
+    req.preds = [dict(target=p["target"], rows=p["rows"], kind=p["kind"]) for p in req.preds]
+    req.bits = []
+    req.view = dict(n_vertices=req.view["n_vertices"], n_edges=req.view["n_edges"], src=None, dst=None)
+    if req.plan is not None:
+        req.plan.workspace = None
+        req.plan._keep = []
+
+
+def outputs(req: Request):
+    v = req.view
+    w = _words(v["n_vertices"]) if req.query.n_qv == 1 else (req.query.n_qv - 1) * _words(v["n_edges"])
+    return [req.plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
+
+
+def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, count))
+
+
+def summarize(requests, wall_s: float) -> dict:
+    lat = np.array([r.latency_ms for r in requests])
+    return {"requests": len(requests), "qps": len(requests) / wall_s, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "wall_s": wall_s}
+
+
+def resident_graph(n_vertices, n_edges, src, dst, vshares, eshares, device) -> ResidentGraph:
+    """Upload both servers' column shares and the public endpoints (numpy uint32)."""
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)
+    return ResidentGraph(n_vertices, n_edges, T(src), T(dst),
+                         {k: (T(v[0]), T(v[1])) for k, v in vshares.items()},
+                         {k: (T(v[0]), T(v[1])) for k, v in eshares.items()})
