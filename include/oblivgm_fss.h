@@ -281,6 +281,25 @@ int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_
 int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
                  const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream);
 
+/*
+ * Three-party binary RSS arithmetic (Sec. III-B), all three parties simulated.
+ * Share vectors are packed words (ceil(nrows/32) each); party P_i holds shares
+ * i and i+1 (indices mod 3).  Zero sharing: <alpha>_i = F(k_i, j) ^ F(k_{i-1}, j)
+ * with F(k, j) word w = little-endian word (w mod 4) of
+ * AES_{LE64(k)||"OBLIVGM1"}(LE16 5 || LE16 0 || LE32 j || LE32 0 || LE32 (w div 4)),
+ * j = `counter` (fresh per call), k_i = prf_keys[i].  Pad bits are cleared.
+ * rss_reshare: three-out-of-three XOR shares x_i -> RSS shares z_i = x_i ^ <alpha>_i
+ *   (P_i keeps z_i and obtains z_{i+1} from P_{i+1}; the paper words this as a
+ *   send to P_{i+1}, which under its own holding convention is the same ring
+ *   taken the other way).
+ * rss_and: z = x AND y on RSS shares: P_i forms x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i,
+ *   then re-shares as above.
+ */
+int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf_keys[3], uint32_t counter,
+                uint32_t* const d_z[3], void* stream);
+int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],
+            uint32_t counter, uint32_t* const d_z[3], void* stream);
+
 /* Tile / occupancy shape of the persistent launches (process-wide):
  * rows_per_thread 1..8 (evaluation tile = 1024 * rows_per_thread rows),
  * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */

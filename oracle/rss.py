@@ -72,3 +72,43 @@ def server_shares(kind: str, npos: int, keys_pair, nbits: int, shares) -> np.nda
             # XOR over positions of Eval(k, l) AND <e[l]>_j
             out[i] ^= (np.bitwise_and(shares[j], ev[key][None, :]).sum(axis=1) & 1).astype(np.uint8)
     return out
+
+
+# --------------------------------------------------------------------------- three-party RSS arithmetic
+
+def prf_words(key_seed: int, counter: int, nwords: int) -> np.ndarray:
+    """F(k, j) on packed words: word w is little-endian word (w mod 4) of
+    AES_{LE64(k)||"OBLIVGM1"}(LE16 5 || LE16 0 || LE32 counter || LE32 0 || LE32 (w div 4))
+    (the generator's domain 5)."""
+    out = np.zeros(nwords, np.uint32)
+    for blk in range((nwords + 3) // 4):
+        b = fss.rng_block(key_seed, 5, 0, counter, 0, blk)
+        for q in range(4):
+            w = 4 * blk + q
+            if w < nwords:
+                out[w] = int.from_bytes(b[4 * q:4 * q + 4], "little")
+    return out
+
+
+def zero_shares(prf_keys, counter: int, nwords: int):
+    """<alpha>_i = F(k_i, j) ^ F(k_{i-1}, j): three shares of 0 (Sec. III-B)."""
+    f = [prf_words(k, counter, nwords) for k in prf_keys]
+    return [f[i] ^ f[(i - 1) % 3] for i in range(3)]
+
+
+def reshare(x3, prf_keys, counter: int, nrows: int):
+    """Three-out-of-three XOR shares x_1, x_2, x_3 (packed words) -> RSS shares:
+    z_i = x_i ^ <alpha>_i.  Party P_i keeps z_i and receives z_{i+1} from P_{i+1}
+    so that it holds (z_i, z_{i+1}).  Pad bits beyond nrows cleared."""
+    nwords = x3[0].size
+    a = zero_shares(prf_keys, counter, nwords)
+    vm = fss.valid_mask(nrows)
+    return [(x3[i] ^ a[i]) & vm for i in range(3)]
+
+
+def rss_and(x, y, prf_keys, counter: int, nrows: int):
+    """AND of two RSS-shared packed bit vectors (Sec. III-B): P_i forms
+    z_i = x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i from the shares it holds, then
+    the result is re-shared."""
+    z3 = [(x[i] & y[i]) ^ (x[i] & y[(i + 1) % 3]) ^ (x[(i + 1) % 3] & y[i]) for i in range(3)]
+    return reshare(z3, prf_keys, counter, nrows)

@@ -595,6 +595,54 @@ __global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__
     }
 }
 
+// ----------------------------------------------------------------- three-party RSS arithmetic
+
+struct RssArgs {
+    RoundKeys prf[3];       // F(k_i, .) = AES under LE64(k_i) || "OBLIVGM1"
+    const uint32_t* x[3];
+    const uint32_t* y[3];   // null for a plain re-share
+    uint32_t* z[3];
+    uint64_t nrows;
+    uint64_t nwords;
+    uint32_t counter;
+};
+
+// Thread m owns words 4m .. 4m+3.  For the AND, party P_i first forms
+// z_i = x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i from the two shares it holds; then
+// z_i ^= F(k_i, j) ^ F(k_{i-1}, j) (a fresh sharing of zero), pad bits cleared.
+__global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (4 * m >= A.nwords) return;
+    const LaneOff loff = lane_offset();
+    uint4 f[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+        f[i] = aes128_encrypt(make_uint4(5u, A.counter, 0u, (uint32_t)m), ArgKey{A.prf[i]}, tab, loff);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint64_t w = 4 * m + q;
+        if (w >= A.nwords) break;
+        const uint32_t pm = pad_mask(w, A.nrows);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int nx = (i + 1) % 3, pv = (i + 2) % 3;
+            uint32_t zi;
+            if (A.y[0]) {
+                const uint32_t xi = A.x[i][w], xn = A.x[nx][w], yi = A.y[i][w], yn = A.y[nx][w];
+                zi = (xi & yi) ^ (xi & yn) ^ (xn & yi);
+            } else {
+                zi = A.x[i][w];
+            }
+            const uint32_t fi = q == 0 ? f[i].x : q == 1 ? f[i].y : q == 2 ? f[i].z : f[i].w;
+            const uint32_t fp = q == 0 ? f[pv].x : q == 1 ? f[pv].y : q == 2 ? f[pv].z : f[pv].w;
+            A.z[i][w] = (zi ^ fi ^ fp) & pm;
+        }
+    }
+}
+
 // Shares of the public constant 1 over nrows rows.
 __global__ void k_public_one(uint64_t nwords, uint64_t nrows, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1166,6 +1214,40 @@ int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_
                        (hipStream_t)stream, (const uint8_t*)k->key[party], k->n, key_row, (uint32_t)k->kind,
                        k->nbits, (uint32_t)party, npoints, d_out_bits);
     return check_launch("k_eval_points");
+}
+
+static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* const* d_y, const uint64_t* prf_keys,
+            uint32_t counter, uint32_t* const* d_z, void* stream, const char* who) {
+    t_err.clear();
+    if (nrows == 0) return FSS_OK;
+    if (!d_x || !d_z || !prf_keys) return fail(FSS_EINVAL, "%s: NULL argument", who);
+    RssArgs A{};
+    for (int i = 0; i < 3; i++) {
+        if (!d_x[i] || !d_z[i] || (d_y && !d_y[i])) return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
+        A.prf[i] = dealer_key(prf_keys[i]);
+        A.x[i] = d_x[i];
+        A.y[i] = d_y ? d_y[i] : nullptr;
+        A.z[i] = d_z[i];
+    }
+    A.nrows = nrows;
+    A.nwords = (nrows + 31) / 32;
+    A.counter = counter;
+    const uint64_t threads = (A.nwords + 3) / 4;
+    hipLaunchKernelGGL(k_rss, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, A);
+    return check_launch("k_rss");
+}
+
+
+int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf_keys[3], uint32_t counter,
+                uint32_t* const d_z[3], void* stream) {
+    return rss_run(nrows, d_x, nullptr, prf_keys, counter, d_z, stream, "rss_reshare");
+}
+
+int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],
+            uint32_t counter, uint32_t* const d_z[3], void* stream) {
+    if (!d_y) { t_err = "rss_and: NULL y"; return FSS_EINVAL; }
+    return rss_run(nrows, d_x, d_y, prf_keys, counter, d_z, stream, "rss_and");
 }
 
 int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,

@@ -83,6 +83,8 @@ def _load():
         "fss_set_tuning": ([u32, u32], ctypes.c_int),
         "fss_eval_all": ([i32, ctypes.POINTER(fss_keybatch), u64, u64, P, P], ctypes.c_int),
         "fss_dealer_masks": ([u64, u32, u32, u32, u64, P, P], ctypes.c_int),
+        "rss_reshare": ([u64, P, P, u32, P, P], ctypes.c_int),
+        "rss_and": ([u64, P, P, P, u32, P, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
@@ -97,7 +99,7 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks")
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and")
 
 
 def _check(rc: int):
@@ -311,3 +313,17 @@ def fss_eval_all(party: int, keys: KeyBatch, key_row: int, npoints: int, out_bit
 def rss_sec_eval(ncand: int, npos: int, eval_a, eval_b, share_a, share_b, out_bits, stream=None):
     _check(LIB.rss_sec_eval(ncand, npos, _ptr(eval_a), _ptr(eval_b), _ptr(share_a), _ptr(share_b), _ptr(out_bits),
                             _stream(stream)))
+
+
+def _ptr3(ts):
+    return (ctypes.c_void_p * 3)(*[_ptr(t) for t in ts])
+
+
+def rss_reshare(nrows: int, x3, prf_keys, counter: int, z3, stream=None):
+    keys = (ctypes.c_uint64 * 3)(*prf_keys)
+    _check(LIB.rss_reshare(nrows, _ptr3(x3), keys, counter, _ptr3(z3), _stream(stream)))
+
+
+def rss_and(nrows: int, x3, y3, prf_keys, counter: int, z3, stream=None):
+    keys = (ctypes.c_uint64 * 3)(*prf_keys)
+    _check(LIB.rss_and(nrows, _ptr3(x3), _ptr3(y3), keys, counter, _ptr3(z3), _stream(stream)))

@@ -63,3 +63,24 @@ def test_sec_eval_parity(fss, kind, npos, ncand):
     truth = (values == a) if kind == "eq" else ((values >= lo) & (values < hi))
     np.testing.assert_array_equal(ofss.unpack_bits(xs[0] ^ xs[1] ^ xs[2], ncand), truth.astype(np.uint8))
     assert (xs[0][-1] >> (ncand % 32 or 32) if ncand % 32 else 0) == 0
+
+
+@pytest.mark.parametrize("nrows", [1, 33, 4096, 100001])
+def test_rss_reshare_and_and(fss, nrows):
+    nw = (nrows + 31) // 32
+    rng = np.random.default_rng(nrows)
+    vm = ofss.valid_mask(nrows)
+    x = [rng.integers(0, 2**32, nw, dtype=np.uint64).astype(np.uint32) & vm for _ in range(3)]
+    y = [rng.integers(0, 2**32, nw, dtype=np.uint64).astype(np.uint32) & vm for _ in range(3)]
+    keys = [101, 202, 303]
+    z = [torch.empty(nw, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_reshare(nrows, [T(a) for a in x], keys, 9, z)
+    want = orss.reshare(x, keys, 9, nrows)
+    for i in range(3):
+        np.testing.assert_array_equal(U(z[i]), want[i])
+    fss.rss_and(nrows, [T(a) for a in x], [T(b) for b in y], keys, 10, z)
+    want = orss.rss_and(x, y, keys, 10, nrows)
+    got = [U(t) for t in z]
+    for i in range(3):
+        np.testing.assert_array_equal(got[i], want[i])
+    np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], (x[0] ^ x[1] ^ x[2]) & (y[0] ^ y[1] ^ y[2]))

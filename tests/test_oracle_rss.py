@@ -49,3 +49,59 @@ def test_word_major_packing():
     w = synth.pack_word_major(bits)
     assert w.shape == (2, 3)
     assert w[0, 1] == 1 and w[1, 1] == 2 and w[1, 2] == 1 << 7 and w[0, 0] == 0
+
+
+def _rand_words(seed, n):
+    return np.random.default_rng(seed).integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+
+
+def test_zero_shares_xor_to_zero_and_look_random():
+    a = rss.zero_shares([11, 22, 33], 7, 64)
+    assert not (a[0] ^ a[1] ^ a[2]).any()
+    for i in range(3):
+        bits = np.unpackbits(a[i].view(np.uint8))
+        assert 0.4 < bits.mean() < 0.6
+
+
+def test_rss_and_truth_table():
+    """Every assignment of the three shares of x and y (packed 64 ways into
+    words) reconstructs to x AND y."""
+    n = 64 * 32
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        x = [_rand_words(10 * trial + i, n // 32) for i in range(3)]
+        y = [_rand_words(10 * trial + 5 + i, n // 32) for i in range(3)]
+        z = rss.rss_and(x, y, [1, 2, 3 + trial], trial, n)
+        np.testing.assert_array_equal(z[0] ^ z[1] ^ z[2], (x[0] ^ x[1] ^ x[2]) & (y[0] ^ y[1] ^ y[2]))
+    # a dropped cross term is caught
+    x = [_rand_words(100 + i, 8) for i in range(3)]
+    y = [_rand_words(200 + i, 8) for i in range(3)]
+    bad = [(x[i] & y[i]) ^ (x[i] & y[(i + 1) % 3]) for i in range(3)]
+    assert ((bad[0] ^ bad[1] ^ bad[2]) != ((x[0] ^ x[1] ^ x[2]) & (y[0] ^ y[1] ^ y[2]))).any()
+
+
+def test_reshare_keeps_the_value_and_clears_pad():
+    x3 = [_rand_words(7 + i, 5) for i in range(3)]
+    vm = rss.fss.valid_mask(150)
+    z = rss.reshare(x3, [4, 5, 6], 1, 150)
+    np.testing.assert_array_equal(z[0] ^ z[1] ^ z[2], (x3[0] ^ x3[1] ^ x3[2]) & vm)
+    assert (z[0][-1] >> (150 % 32)) == 0
+
+
+def test_sec_eval_then_rss_and_is_the_conjunction():
+    """Two predicates by secEval, re-shared into RSS, ANDed: the reconstruction
+    is the conjunction of the plaintext predicates (multi-predicate
+    aggregation of Sec. V-D in the paper's own three-party form)."""
+    npos = 64
+    values = np.random.default_rng(8).integers(0, npos, 1000).astype(np.uint32)
+    shares = synth.onehot_rss(21, values, npos)
+    k1, nb = rss.token("range", npos, 5, 1, 0, lo=10, hi=40)
+    k2, _ = rss.token("range", npos, 5, 1, 1, lo=30, hi=60)
+    x1 = rss.server_shares("range", npos, k1, nb, shares)
+    x2 = rss.server_shares("range", npos, k2, nb, shares)
+    from oracle import fss as ofss
+    p1 = rss.reshare([ofss.pack_bits(x1[i]) for i in range(3)], [7, 8, 9], 0, values.size)
+    p2 = rss.reshare([ofss.pack_bits(x2[i]) for i in range(3)], [7, 8, 9], 1, values.size)
+    z = rss.rss_and(p1, p2, [7, 8, 9], 2, values.size)
+    got = ofss.unpack_bits(z[0] ^ z[1] ^ z[2], values.size)
+    np.testing.assert_array_equal(got, ((values >= 30) & (values < 40)).astype(np.uint8))
