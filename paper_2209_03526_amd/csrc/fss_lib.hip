@@ -28,8 +28,41 @@
 
 #include "../../include/oblivgm_fss.h"
 #include "aes_gfx950.hpp"
+#include "common.hpp"
 
 using namespace ogm;
+
+namespace ogm {
+
+std::string& last_error() {
+    thread_local std::string err;
+    return err;
+}
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    last_error() = buf;
+    return code;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FSS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return FSS_OK;
+}
+
+RoundKeys seed_key(uint64_t seed) {
+    uint8_t k[16];
+    for (int i = 0; i < 8; i++) k[i] = (uint8_t)(seed >> (8 * i));
+    memcpy(k + 8, "OBLIVGM1", 8);
+    return expand_key(k);
+}
+
+}  // namespace ogm
 
 namespace {
 
@@ -654,24 +687,8 @@ __global__ void k_public_one(uint64_t nwords, uint64_t nrows, uint32_t* __restri
 
 // ----------------------------------------------------------------- host side
 
-thread_local std::string t_err;
-
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    t_err = buf;
-    return code;
-}
-
-int check_launch(const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(FSS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-    return FSS_OK;
-}
+using ogm::fail;
+using ogm::check_launch;
 
 bool valid_nbits(uint32_t nbits) { return nbits >= 8 && nbits <= 32; }
 
@@ -691,12 +708,7 @@ unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
     return (unsigned)g;
 }
 
-RoundKeys dealer_key(uint64_t seed) {
-    uint8_t k[16];
-    for (int i = 0; i < 8; i++) k[i] = (uint8_t)(seed >> (8 * i));
-    memcpy(k + 8, "OBLIVGM1", 8);
-    return expand_key(k);
-}
+RoundKeys dealer_key(uint64_t seed) { return ogm::seed_key(seed); }
 
 int check_batch(const fss_keybatch* k, int32_t want_kind, const char* who) {
     if (!k) return fail(FSS_EINVAL, "%s: key batch is NULL", who);
@@ -770,13 +782,13 @@ uint64_t fss_key_bytes(int32_t kind, uint32_t nbits) { return key_bytes(kind, nb
 
 uint64_t fss_keybatch_bytes(int32_t kind, uint32_t nbits, uint64_t n) { return key_bytes(kind, nbits) * pad_rows(n); }
 
-const char* fss_last_error(void) { return t_err.c_str(); }
+const char* fss_last_error(void) { return ogm::last_error().c_str(); }
 
 const char* fss_version(void) { return "oblivgm-fss 0.1 gfx950 lds-ttable"; }
 
 int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const uint32_t* d_r, uint32_t* d_xhat,
                   void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (n == 0) return FSS_OK;
     if (!d_x0 || !d_x1 || !d_r || !d_xhat) return fail(FSS_EINVAL, "fss_mask_open: NULL buffer");
     hipLaunchKernelGGL(k_mask_open, dim3(grid_for(n, 256, 8192)), dim3(256), 0, (hipStream_t)stream, n, d_x0, d_x1,
@@ -786,7 +798,7 @@ int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const 
 
 int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or_lo, uint32_t hi,
                const uint32_t* d_r, const fss_keybatch* out, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (!out) return fail(FSS_EINVAL, "fss_keygen: out is NULL");
     if (out->kind != FSS_EQ && out->kind != FSS_RANGE) return fail(FSS_EINVAL, "fss_keygen: bad kind %d", out->kind);
     if (!valid_nbits(out->nbits)) return fail(FSS_EINVAL, "fss_keygen: nbits %u outside 8..32", out->nbits);
@@ -820,7 +832,7 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
 
 int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t row_offset, uint64_t n,
                      uint32_t* d_r, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (n == 0) return FSS_OK;
     if (!d_r) return fail(FSS_EINVAL, "fss_dealer_masks: NULL buffer");
     if ((uint64_t)row_offset + n > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "fss_dealer_masks: rows beyond 2^32");
@@ -836,18 +848,18 @@ int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_
 }
 
 int fss_eval_eq(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     return eval_one(party, k, FSS_EQ, d_xhat, d_out_bits, stream, "fss_eval_eq");
 }
 
 int fss_eval_lt(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, uint32_t* d_out_bits, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     return eval_one(party, k, FSS_RANGE, d_xhat, d_out_bits, stream, "fss_eval_lt");
 }
 
 int ss_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nwords, uint32_t* d_trip0,
                uint32_t* d_trip1, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (nwords == 0) return FSS_OK;
     if (!d_trip0 || !d_trip1) return fail(FSS_EINVAL, "ss_triples: NULL buffer");
     if (nwords > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "ss_triples: too many words");
@@ -856,7 +868,7 @@ int ss_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nword
 
 int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, const uint32_t* d_y,
            const uint32_t* d_triple, const uint32_t* d_de_open, uint32_t* d_out, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (party != 0 && party != 1) return fail(FSS_EINVAL, "ss_and: party %d is not 0 or 1", party);
     const uint64_t nwords = (nrows + 31) / 32;
     if (nwords == 0) return FSS_OK;
@@ -1180,7 +1192,7 @@ uint64_t match_workspace_bytes(const match_plan* plan) {
 }
 
 int match_query(const match_plan* P, int32_t party_mask, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (party_mask != 3) return fail(FSS_EUNSUPPORTED, "match_query: party_mask must be 3 (both parties simulated)");
     int rc = validate_plan(P, "match_query");
     if (rc) return rc;
@@ -1200,7 +1212,7 @@ uint64_t fss_queue_workspace_bytes(uint64_t count) { return queue_bytes(count); 
 
 int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_t npoints, uint32_t* d_out_bits,
                  void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (!k) return fail(FSS_EINVAL, "fss_eval_all: key batch is NULL");
     int rc = check_batch(k, k->kind, "fss_eval_all");
     if (rc) return rc;
@@ -1218,7 +1230,7 @@ int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_
 
 static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* const* d_y, const uint64_t* prf_keys,
             uint32_t counter, uint32_t* const* d_z, void* stream, const char* who) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (nrows == 0) return FSS_OK;
     if (!d_x || !d_z || !prf_keys) return fail(FSS_EINVAL, "%s: NULL argument", who);
     RssArgs A{};
@@ -1246,13 +1258,13 @@ int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf
 
 int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],
             uint32_t counter, uint32_t* const d_z[3], void* stream) {
-    if (!d_y) { t_err = "rss_and: NULL y"; return FSS_EINVAL; }
+    if (!d_y) { ogm::last_error() = "rss_and: NULL y"; return FSS_EINVAL; }
     return rss_run(nrows, d_x, d_y, prf_keys, counter, d_z, stream, "rss_and");
 }
 
 int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
                  const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (ncand == 0) return FSS_OK;
     if (npos == 0) return fail(FSS_EINVAL, "rss_sec_eval: no positions");
     if (!d_eval_a || !d_eval_b || !d_share_a || !d_share_b || !d_out_bits)
@@ -1263,7 +1275,7 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
 }
 
 int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (rows_per_thread < 1 || rows_per_thread > 8 || wg_per_cu < 1 || wg_per_cu > 2)
         return fail(FSS_EINVAL, "fss_set_tuning: rows_per_thread 1..8, wg_per_cu 1..2");
     g_tuning.rows_per_thread = rows_per_thread;
@@ -1279,7 +1291,7 @@ int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu) {
 
 int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,
                      void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (count == 0) return FSS_OK;
     if (!reqs) return fail(FSS_EINVAL, "fss_keygen_batch: reqs is NULL");
     std::vector<QKeygen> q;
@@ -1343,7 +1355,7 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
 
 int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,
                    void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (count == 0) return FSS_OK;
     if (!reqs) return fail(FSS_EINVAL, "fss_eval_batch: reqs is NULL");
     std::vector<EvalDesc> descs;
@@ -1372,7 +1384,7 @@ int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint
 
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
                       uint64_t queue_bytes_avail, void* stream) {
-    t_err.clear();
+    ogm::last_error().clear();
     if (count == 0) return FSS_OK;
     if (!plans) return fail(FSS_EINVAL, "match_query_batch: plans is NULL");
     if (party_mask != 3)
