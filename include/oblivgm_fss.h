@@ -300,6 +300,43 @@ int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf
 int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],
             uint32_t counter, uint32_t* const d_z[3], void* stream);
 
+/*
+ * Secret-shared shuffle (Alg. 5, after Araki et al.) and secure fetching of the
+ * matched records (Alg. 4), three servers simulated.  A table is nrows records
+ * of nwords 32-bit words, row-major, in binary RSS: d_in[i] is share i+1 and
+ * CS_i holds shares i and i+1.  seeds = {s12, s23, s31}, the pairwise seeds.
+ * Each pair derives its permutations (stable sort of one 64-bit key per row)
+ * and mask tables from its seed with the counter-mode generator, domain 6:
+ *   mask word k = r*nwords + w of table t = word (k mod 4) of block
+ *   (6, t, nwords, 0, k div 4), T12 = 1, R2 = 2, T23 = 3, T31 = 4, R1 = 5;
+ *   sort key of row r for pi12 / pi23 / pi31 = words 0-1 of block (6, 16+p, 0, 0, r),
+ *   p = 0 / 1 / 2; a permutation applied to a table gathers out[i] = in[perm[i]].
+ * The messages follow the algorithm (its X_2 in CS2's step is the X1 it
+ * received): X1 = pi31[pi12(D1^D2^T12)^T31]; Y1 = pi12(D3^T12);
+ * C1 = pi23(X1^T23)^R2; C2 = pi23[pi31(Y1^T31)^T23]^R1; R3 = C1^C2.
+ * rss_shuffle: d_out = (R1, R2, R3), an RSS of pi23(pi31(pi12(D))).
+ * rss_fetch_unique (Case I, one matching candidate): d_x[i] = packed share i+1
+ *   of the predicate bits; d_rows[i] = share i+1 of the records (ncand x nwords);
+ *   d_out[i] (nwords) = XOR over candidates of the three-out-of-three products
+ *   x_i r_i ^ x_i r_{i+1} ^ x_{i+1} r_i: additive shares of the matching record
+ *   (rss_reshare turns them into RSS).
+ * rss_fetch_many (Case II): word 0 bit 0 of each record of d_table is the
+ *   shared predicate bit.  The table is shuffled, the bit column opened, and the
+ *   kept records (words 1..nwords-1 of each share) are written in shuffled order
+ *   to d_out[i] (capacity ncand x (nwords-1)), their shuffled positions to
+ *   d_rows_out, their number to *d_count (device memory; read after the stream
+ *   synchronises).  Workspaces: *_workspace_bytes, caller-provided device memory.
+ */
+uint64_t rss_shuffle_workspace_bytes(uint64_t nrows, uint32_t nwords);
+int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],
+                uint32_t* const d_out[3], void* d_work, uint64_t work_bytes, void* stream);
+int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],
+                     uint32_t* const d_out[3], void* stream);
+uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords);
+int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
+                   uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
+                   uint64_t work_bytes, void* stream);
+
 /* Tile / occupancy shape of the persistent launches (process-wide):
  * rows_per_thread 1..8 (evaluation tile = 1024 * rows_per_thread rows),
  * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */

@@ -7,8 +7,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "fss_lib.hip")
-HEADERS = [os.path.join(HERE, "csrc", "aes_gfx950.hpp"), os.path.join(ROOT, "include", "oblivgm_fss.h")]
+SRCS = [os.path.join(HERE, "csrc", "fss_lib.hip"), os.path.join(HERE, "csrc", "shuffle.hip")]
+SRC = SRCS[0]
+HEADERS = [os.path.join(HERE, "csrc", "aes_gfx950.hpp"), os.path.join(HERE, "csrc", "common.hpp"),
+           os.path.join(ROOT, "include", "oblivgm_fss.h")]
 LIB = os.path.join(HERE, "liboblivgm_fss.so")
 
 HIPCC_FLAGS = [
@@ -29,7 +31,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Always recompiles (the caller asked for a build)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -46,7 +48,7 @@ def needs_build() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in [SRC, *HEADERS])
+    return any(os.path.getmtime(p) > t for p in [*SRCS, *HEADERS])
 
 
 if __name__ == "__main__":

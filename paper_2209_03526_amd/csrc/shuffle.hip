@@ -1,0 +1,365 @@
+// shuffle.hip -- three-party secret-shared shuffle (Alg. 5) and secure fetching
+// of matched records (Alg. 4, Cases I and II), all three servers simulated.
+//
+// Tables are row-major: record r of a W-word table at words [r*W, r*W + W).
+// Each pair of servers derives from its seed, with the counter-mode generator
+// (domain 6), its permutations (stable sort of one 64-bit key per row) and
+// mask tables (one AES block per four words); applying a permutation is the
+// row gather out[i] = in[perm[i]].  The sequence of Alg. 5 is kept message
+// by message (X1, Y1, C1, C2, R3), so each intermediate is what one server
+// computes and sends.
+
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <stdint.h>
+
+#include "../../include/oblivgm_fss.h"
+#include "aes_gfx950.hpp"
+#include "common.hpp"
+
+using namespace ogm;
+
+namespace {
+
+constexpr int kBlock = 1024;
+__constant__ AesTables g_tab = kTables;
+
+enum { kT12 = 1, kR2 = 2, kT23 = 3, kT31 = 4, kR1 = 5 };
+enum { kP12 = 0, kP23 = 1, kP31 = 2 };
+
+// Mask table `table` of the pair seed: word k = r*W + w is word (k mod 4) of
+// block (6, table, W, 0, k div 4).  Thread m writes words 4m .. 4m+3.
+__global__ __launch_bounds__(kBlock) void k_mask_table(RoundKeys rk, uint32_t table, uint32_t nwords, uint64_t total,
+                                                      uint32_t* __restrict__ out) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tab.t0);
+    __syncthreads();
+    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (4 * m >= total) return;
+    const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, (uint32_t)m), ArgKey{rk}, tab,
+                                   lane_offset());
+    const uint32_t v[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (4 * m + q < total) out[4 * m + q] = v[q];
+}
+
+// Sort keys of permutation p: row r -> words 0-1 of block (6, 16 + p, 0, 0, r).
+__global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, uint64_t nrows,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tab.t0);
+    __syncthreads();
+    const uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab,
+                                   lane_offset());
+    keys[r] = (uint64_t)b.x | ((uint64_t)b.y << 32);
+    idx[r] = (uint32_t)r;
+}
+
+// out[i] = a[p] ^ b[p] ^ c[p] ^ post[i], p = perm[i] (absent tables skipped);
+// one thread per output word.
+__global__ void k_gather_xor(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ perm,
+                             const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                             const uint32_t* __restrict__ c, const uint32_t* __restrict__ post,
+                             uint32_t* __restrict__ out) {
+    const uint64_t total = nrows * nwords;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+        const uint64_t i = k / nwords, w = k % nwords;
+        const uint64_t src = (uint64_t)perm[i] * nwords + w;
+        uint32_t v = a[src];
+        if (b) v ^= b[src];
+        if (c) v ^= c[src];
+        if (post) v ^= post[k];
+        out[k] = v;
+    }
+}
+
+__global__ void k_xor2(uint64_t total, const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                       uint32_t* __restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) out[k] = a[k] ^ b[k];
+}
+
+// Case I: XOR over candidates of (r_i & m_i) ^ (r_j & m_i) ^ (r_i & m_j), the
+// three-out-of-three products of record shares with the predicate-bit
+// shares, j = i + 1.  XOR is order-free, so per-block partials are combined
+// with atomicXor into the zeroed output.
+__global__ void k_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* __restrict__ x0,
+                               const uint32_t* __restrict__ x1, const uint32_t* __restrict__ x2,
+                               const uint32_t* __restrict__ r0, const uint32_t* __restrict__ r1,
+                               const uint32_t* __restrict__ r2, uint32_t* __restrict__ out0,
+                               uint32_t* __restrict__ out1, uint32_t* __restrict__ out2) {
+    const uint32_t w = blockIdx.y;
+    const uint32_t* xs[3] = {x0, x1, x2};
+    const uint32_t* rs[3] = {r0, r1, r2};
+    uint32_t* outs[3] = {out0, out1, out2};
+    uint32_t acc[3] = {0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand; c += stride) {
+        uint32_t m[3], rv[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            m[i] = 0u - ((xs[i][c >> 5] >> (c & 31)) & 1u);
+            rv[i] = rs[i][c * nwords + w];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int j = (i + 1) % 3;
+            acc[i] ^= (rv[i] & m[i]) ^ (rv[j] & m[i]) ^ (rv[i] & m[j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        uint32_t v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v ^= __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0 && v) atomicXor(&outs[i][w], v);
+    }
+}
+
+__global__ void k_zero(uint64_t n, uint32_t* __restrict__ p) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0u;
+}
+
+// Case II: flag of shuffled record i = bit 0 of word 0 of R1 ^ R2 ^ R3 (the opened x).
+__global__ void k_open_flags(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ a,
+                             const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
+                             uint32_t* __restrict__ flags) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nrows) flags[i] = (a[i * nwords] ^ b[i * nwords] ^ c[i * nwords]) & 1u;
+}
+
+// Copy the kept records (words 1..W-1) of the three share tables to their slots.
+__global__ void k_compact(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ flags,
+                          const uint32_t* __restrict__ pos, const uint32_t* __restrict__ s0,
+                          const uint32_t* __restrict__ s1, const uint32_t* __restrict__ s2,
+                          uint32_t* __restrict__ o0, uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
+                          uint32_t* __restrict__ rows_out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows || !flags[i]) return;
+    const uint64_t d = pos[i];
+    const uint32_t rw = nwords - 1;
+    for (uint32_t w = 0; w < rw; w++) {
+        o0[d * rw + w] = s0[i * nwords + 1 + w];
+        o1[d * rw + w] = s1[i * nwords + 1 + w];
+        o2[d * rw + w] = s2[i * nwords + 1 + w];
+    }
+    rows_out[d] = (uint32_t)i;
+}
+
+// count of kept records = last exclusive prefix + last flag
+__global__ void k_count(uint64_t n, const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                        uint32_t* __restrict__ count) {
+    if (threadIdx.x == 0) *count = pos[n - 1] + flags[n - 1];
+}
+
+unsigned grid_of(uint64_t n, unsigned block) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    if (g > 16384) g = 16384;
+    return (unsigned)g;
+}
+
+struct Carve {
+    uint8_t* p;
+    uint64_t left;
+    bool ok = true;
+    template <class T>
+    T* take(uint64_t count) {
+        const uint64_t bytes = (count * sizeof(T) + 255) & ~255ull;
+        if (bytes > left) { ok = false; return nullptr; }
+        T* r = (T*)p;
+        p += bytes;
+        left -= bytes;
+        return r;
+    }
+};
+
+size_t sort_temp_bytes(uint64_t nrows) {
+    size_t b = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nrows);
+    return b;
+}
+
+uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
+    auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
+    const uint64_t tw = nrows * nwords * 4;
+    return 5 * r(tw) + 4 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + r(nrows * 4) + r(sort_temp_bytes(nrows)) +
+           4096;
+}
+
+// perm = stable argsort of the pair seed's row keys.
+int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, uint64_t* keys, uint64_t* keys_sorted,
+              uint32_t* idx, uint32_t* perm, void* temp, size_t temp_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)((nrows + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, rk, p, nrows,
+                       keys, idx);
+    int rc = check_launch("k_perm_keys");
+    if (rc) return rc;
+    if (hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, perm, (int)nrows, 0, 64, s) !=
+        hipSuccess)
+        return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
+    return FSS_OK;
+}
+
+int mask(const RoundKeys& rk, uint32_t table, uint64_t nrows, uint32_t nwords, uint32_t* out, hipStream_t s) {
+    const uint64_t total = nrows * nwords;
+    const uint64_t threads = (total + 3) / 4;
+    hipLaunchKernelGGL(k_mask_table, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, rk, table,
+                       nwords, total, out);
+    return check_launch("k_mask_table");
+}
+
+int gather(uint64_t nrows, uint32_t nwords, const uint32_t* perm, const uint32_t* a, const uint32_t* b,
+           const uint32_t* c, const uint32_t* post, uint32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_xor, dim3(grid_of(nrows * nwords, 256)), dim3(256), 0, s, nrows, nwords, perm, a, b, c,
+                       post, out);
+    return check_launch("k_gather_xor");
+}
+
+// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
+int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
+                uint32_t* const out[3], Carve& ws, hipStream_t s) {
+    const uint64_t tw = nrows * nwords;
+    const RoundKeys k12 = seed_key(seeds[0]), k23 = seed_key(seeds[1]), k31 = seed_key(seeds[2]);
+    uint32_t* t12 = ws.take<uint32_t>(tw);
+    uint32_t* t23 = ws.take<uint32_t>(tw);
+    uint32_t* t31 = ws.take<uint32_t>(tw);
+    uint32_t* u = ws.take<uint32_t>(tw);
+    uint32_t* x1 = ws.take<uint32_t>(tw);
+    uint32_t* y1 = ws.take<uint32_t>(tw);
+    uint32_t* c1 = ws.take<uint32_t>(tw);
+    uint32_t* p12 = ws.take<uint32_t>(nrows);
+    uint32_t* p23 = ws.take<uint32_t>(nrows);
+    uint32_t* p31 = ws.take<uint32_t>(nrows);
+    uint64_t* keys = ws.take<uint64_t>(nrows);
+    uint64_t* keys_sorted = ws.take<uint64_t>(nrows);
+    uint32_t* idx = ws.take<uint32_t>(nrows);
+    const size_t tb = sort_temp_bytes(nrows);
+    void* temp = ws.take<uint8_t>(tb);
+    if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
+    int rc = FSS_OK;
+    // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1
+    if (!rc) rc = make_perm(k12, kP12, nrows, keys, keys_sorted, idx, p12, temp, tb, s);
+    if (!rc) rc = make_perm(k23, kP23, nrows, keys, keys_sorted, idx, p23, temp, tb, s);
+    if (!rc) rc = make_perm(k31, kP31, nrows, keys, keys_sorted, idx, p31, temp, tb, s);
+    if (!rc) rc = mask(k12, kT12, nrows, nwords, t12, s);
+    if (!rc) rc = mask(k12, kR2, nrows, nwords, out[1], s);       // R2
+    if (!rc) rc = mask(k23, kT23, nrows, nwords, t23, s);
+    if (!rc) rc = mask(k31, kT31, nrows, nwords, t31, s);
+    if (!rc) rc = mask(k31, kR1, nrows, nwords, out[0], s);       // R1
+    // CS1: X1 = pi31[pi12(D1 ^ D2 ^ T12) ^ T31]
+    if (!rc) rc = gather(nrows, nwords, p12, d[0], d[1], t12, nullptr, u, s);
+    if (!rc) rc = gather(nrows, nwords, p31, u, t31, nullptr, nullptr, x1, s);
+    // CS2: Y1 = pi12(D3 ^ T12); C1 = pi23(X1 ^ T23) ^ R2
+    if (!rc) rc = gather(nrows, nwords, p12, d[2], t12, nullptr, nullptr, y1, s);
+    if (!rc) rc = gather(nrows, nwords, p23, x1, t23, nullptr, out[1], c1, s);
+    // CS3: C2 = pi23[pi31(Y1 ^ T31) ^ T23] ^ R1; R3 = C1 ^ C2
+    if (!rc) rc = gather(nrows, nwords, p31, y1, t31, nullptr, nullptr, u, s);
+    if (!rc) rc = gather(nrows, nwords, p23, u, t23, nullptr, out[0], x1, s);   // x1 now holds C2
+    if (!rc) {
+        hipLaunchKernelGGL(k_xor2, dim3(grid_of(tw, 256)), dim3(256), 0, s, tw, c1, x1, out[2]);
+        rc = check_launch("k_xor2");
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t rss_shuffle_workspace_bytes(uint64_t nrows, uint32_t nwords) {
+    if (nrows == 0 || nwords == 0) return 0;
+    return shuffle_ws(nrows, nwords);
+}
+
+int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],
+                uint32_t* const d_out[3], void* d_work, uint64_t work_bytes, void* stream) {
+    last_error().clear();
+    if (nrows == 0 || nwords == 0) return FSS_OK;
+    if (nrows > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_shuffle: more than 2^31 rows");
+    if (!d_in || !d_out || !seeds) return fail(FSS_EINVAL, "rss_shuffle: NULL argument");
+    for (int i = 0; i < 3; i++)
+        if (!d_in[i] || !d_out[i]) return fail(FSS_EINVAL, "rss_shuffle: NULL share %d", i);
+    if (!d_work || work_bytes < shuffle_ws(nrows, nwords))
+        return fail(FSS_ENOMEM, "rss_shuffle: workspace needs %llu bytes",
+                    (unsigned long long)shuffle_ws(nrows, nwords));
+    Carve ws{(uint8_t*)d_work, work_bytes};
+    return run_shuffle(nrows, nwords, d_in, seeds, d_out, ws, (hipStream_t)stream);
+}
+
+int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],
+                     uint32_t* const d_out[3], void* stream) {
+    last_error().clear();
+    if (nwords == 0) return FSS_OK;
+    if (nwords > 65535) return fail(FSS_EUNSUPPORTED, "rss_fetch_unique: more than 65535 words per record");
+    if (!d_x || !d_rows || !d_out) return fail(FSS_EINVAL, "rss_fetch_unique: NULL argument");
+    for (int i = 0; i < 3; i++)
+        if (!d_x[i] || !d_rows[i] || !d_out[i]) return fail(FSS_EINVAL, "rss_fetch_unique: NULL share %d", i);
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < 3; i++) {
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (uint64_t)nwords, d_out[i]);
+        int rc = check_launch("k_zero");
+        if (rc) return rc;
+    }
+    if (ncand == 0) return FSS_OK;
+    dim3 grid(grid_of(ncand, 256) > 1024 ? 1024 : grid_of(ncand, 256), nwords);
+    hipLaunchKernelGGL(k_fetch_unique, grid, dim3(256), 0, s, ncand, nwords, d_x[0], d_x[1], d_x[2], d_rows[0],
+                       d_rows[1], d_rows[2], d_out[0], d_out[1], d_out[2]);
+    return check_launch("k_fetch_unique");
+}
+
+uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords) {
+    if (ncand == 0 || nwords == 0) return 0;
+    size_t scan = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)ncand);
+    const uint64_t tw = ncand * nwords * 4;
+    return shuffle_ws(ncand, nwords) + 3 * ((tw + 255) & ~255ull) + 2 * ((ncand * 4 + 255) & ~255ull) +
+           ((scan + 255) & ~255ull) + 4096;
+}
+
+int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
+                   uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
+                   uint64_t work_bytes, void* stream) {
+    last_error().clear();
+    if (nwords < 2) return fail(FSS_EINVAL, "rss_fetch_many: records need the bit word and at least one word");
+    if (!d_table || !d_out || !seeds || !d_rows_out || !d_count) return fail(FSS_EINVAL, "rss_fetch_many: NULL argument");
+    for (int i = 0; i < 3; i++)
+        if (!d_table[i] || !d_out[i]) return fail(FSS_EINVAL, "rss_fetch_many: NULL share %d", i);
+    if (ncand > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_fetch_many: more than 2^31 rows");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (uint64_t)1, d_count);
+    int rc = check_launch("k_zero");
+    if (rc || ncand == 0) return rc;
+    if (!d_work || work_bytes < rss_fetch_many_workspace_bytes(ncand, nwords))
+        return fail(FSS_ENOMEM, "rss_fetch_many: workspace needs %llu bytes",
+                    (unsigned long long)rss_fetch_many_workspace_bytes(ncand, nwords));
+    Carve ws{(uint8_t*)d_work, work_bytes};
+    const uint64_t tw = ncand * nwords;
+    uint32_t* sh[3] = {ws.take<uint32_t>(tw), ws.take<uint32_t>(tw), ws.take<uint32_t>(tw)};
+    uint32_t* flags = ws.take<uint32_t>(ncand);
+    uint32_t* pos = ws.take<uint32_t>(ncand);
+    size_t scan = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)ncand);
+    void* scan_tmp = ws.take<uint8_t>(scan);
+    if (!ws.ok) return fail(FSS_ENOMEM, "rss_fetch_many: workspace too small");
+    rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_open_flags, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords, sh[0],
+                       sh[1], sh[2], flags);
+    rc = check_launch("k_open_flags");
+    if (rc) return rc;
+    if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan, flags, pos, (int)ncand, s) != hipSuccess)
+        return fail(FSS_EDEVICE, "rss_fetch_many: scan failed");
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords, flags, pos,
+                       sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out);
+    rc = check_launch("k_compact");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, ncand, flags, pos, d_count);
+    return check_launch("k_count");
+}
+
+}  // extern "C"

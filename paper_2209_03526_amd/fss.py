@@ -85,6 +85,11 @@ def _load():
         "fss_dealer_masks": ([u64, u32, u32, u32, u64, P, P], ctypes.c_int),
         "rss_reshare": ([u64, P, P, u32, P, P], ctypes.c_int),
         "rss_and": ([u64, P, P, P, u32, P, P], ctypes.c_int),
+        "rss_shuffle_workspace_bytes": ([u64, u32], u64),
+        "rss_shuffle": ([u64, u32, P, P, P, P, u64, P], ctypes.c_int),
+        "rss_fetch_unique": ([u64, u32, P, P, P, P], ctypes.c_int),
+        "rss_fetch_many_workspace_bytes": ([u64, u32], u64),
+        "rss_fetch_many": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
@@ -99,7 +104,9 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and")
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
+           "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_fetch_unique", "rss_fetch_many_workspace_bytes",
+           "rss_fetch_many")
 
 
 def _check(rc: int):
@@ -327,3 +334,23 @@ def rss_reshare(nrows: int, x3, prf_keys, counter: int, z3, stream=None):
 def rss_and(nrows: int, x3, y3, prf_keys, counter: int, z3, stream=None):
     keys = (ctypes.c_uint64 * 3)(*prf_keys)
     _check(LIB.rss_and(nrows, _ptr3(x3), _ptr3(y3), keys, counter, _ptr3(z3), _stream(stream)))
+
+
+def rss_shuffle(nrows: int, nwords: int, d3, seeds, out3, stream=None):
+    nbytes = int(LIB.rss_shuffle_workspace_bytes(nrows, nwords))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=d3[0].device)
+    _check(LIB.rss_shuffle(nrows, nwords, _ptr3(d3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3), _ptr(work),
+                           work.numel(), _stream(stream)))
+    return work
+
+
+def rss_fetch_unique(ncand: int, nwords: int, x3, rows3, out3, stream=None):
+    _check(LIB.rss_fetch_unique(ncand, nwords, _ptr3(x3), _ptr3(rows3), _ptr3(out3), _stream(stream)))
+
+
+def rss_fetch_many(ncand: int, nwords: int, table3, seeds, out3, rows_out, count, stream=None):
+    nbytes = int(LIB.rss_fetch_many_workspace_bytes(ncand, nwords))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=table3[0].device)
+    _check(LIB.rss_fetch_many(ncand, nwords, _ptr3(table3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3),
+                              _ptr(rows_out), _ptr(count), _ptr(work), work.numel(), _stream(stream)))
+    return work
