@@ -333,6 +333,13 @@ int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], 
 int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],
                      uint32_t* const d_out[3], void* stream);
 uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords);
+/* secAccess filter (Alg. 6): shuffle the fetched posting-list records, open
+ * y = XOR of all bits of each record (1 for a one-hot ID, 0 for a dummy
+ * all-zero ID), keep the whole records with y = 1 in shuffled order.  Same
+ * outputs and workspace as rss_fetch_many, records of nwords words kept whole. */
+int rss_compact_valid(uint64_t nrec, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
+                      uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
+                      uint64_t work_bytes, void* stream);
 int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
                    uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
                    uint64_t work_bytes, void* stream);

@@ -1,0 +1,107 @@
+"""Oracle for secure neighbouring-vertex access (Alg. 6) over a graph encoded
+as in Sec. V-B / Alg. 1: one-hot IDs in binary RSS, posting lists padded with
+0-vectors (dummy IDs) to a common length.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/fss.py``).
+
+Encoding (client side, Alg. 1): the X vertices of the neighbour type carry
+IDs 0..X-1; a candidate's posting list is its neighbours' one-hot IDs, padded
+with all-zero IDs.  The paper pads each group of k same-type vertices of
+similar degree to one length; a table of records needs one length, so every
+list is padded to the maximum L_max -- a special case that keeps each group
+equal.  Pads are placed at random positions within the list (seeded).
+
+Access for a matched vertex with one-hot ID id_m over the C candidates:
+  1. P_m[l] = XOR_c id_m[c] AND id_{c,l}  (a selection product; the
+     three-out-of-three products are re-shared into RSS)
+  2. shuffle the L_max fetched records, open y = XOR of the bits of each,
+     keep the records with y = 1 (valid IDs)
+  3. d_ne = XOR_x id_ne[x] AND d_x for each kept ID  (selection product,
+     re-shared)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import rss, shuffle
+
+
+def words(bits: int) -> int:
+    return (bits + 31) // 32
+
+
+def pack_rows(bits: np.ndarray) -> np.ndarray:
+    """(R, nbits) 0/1 -> (R, words) uint32, bit p of a row in word p // 32."""
+    r, nb = bits.shape
+    w = words(nb)
+    padded = np.zeros((r, w * 32), np.uint8)
+    padded[:, :nb] = bits
+    return np.packbits(padded.reshape(r, w, 32), axis=2, bitorder="little").view("<u4").reshape(r, w).astype(np.uint32)
+
+
+def encode_posting_lists(adj, x_count: int, seed: int):
+    """adj: list over candidates of neighbour-ID lists.  Returns the plaintext
+    table (C, L_max, words(X)) of one-hot IDs with 0-vector pads."""
+    rng = np.random.default_rng(seed)
+    lmax = max(1, max(len(a) for a in adj))
+    table = np.zeros((len(adj), lmax, x_count), np.uint8)
+    for c, nbrs in enumerate(adj):
+        slots = rng.permutation(lmax)[:len(nbrs)]
+        for s, v in zip(slots, nbrs):
+            table[c, s, v] = 1
+    packed = pack_rows(table.reshape(len(adj) * lmax, x_count)).reshape(len(adj), lmax, words(x_count))
+    return packed, lmax
+
+
+def rss_split(table: np.ndarray, seed: int):
+    rng = np.random.default_rng(seed)
+    s1 = rng.integers(0, 2**32, table.shape, dtype=np.uint64).astype(np.uint32)
+    s2 = rng.integers(0, 2**32, table.shape, dtype=np.uint64).astype(np.uint32)
+    return [s1, s2, table ^ s1 ^ s2]
+
+
+def selection(x_bits, rows, prf_keys, counter: int):
+    """XOR over c of x[c] AND rows[c] on RSS shares, re-shared into RSS.
+    x_bits: three (C,) 0/1 share vectors; rows: three (C, W) tables."""
+    add = shuffle.fetch_case1(x_bits, rows)
+    w = rows[0].shape[1]
+    return rss.reshare(add, prf_keys, counter, 32 * w)
+
+
+def compact_valid(table, seeds):
+    """Shuffle records, open the XOR of each record's bits, keep y = 1."""
+    r = shuffle.sec_shuffle(table, *seeds)
+    full = r[0] ^ r[1] ^ r[2]
+    parity = np.zeros(full.shape[0], np.uint32)
+    for w in range(full.shape[1]):
+        parity ^= full[:, w]
+    y = np.array([bin(int(v)).count("1") & 1 for v in parity], np.uint8)
+    keep = np.flatnonzero(y)
+    return keep, [r[i][keep] for i in range(3)]
+
+
+def unpack_onehot(record_bits: np.ndarray, nbits: int):
+    """(W,) uint32 -> position list of set bits among the first nbits."""
+    bits = np.unpackbits(record_bits.astype("<u4").view(np.uint8), bitorder="little")[:nbits]
+    return np.flatnonzero(bits)
+
+
+def sec_access(idm_shares, posting_shares, attr_shares, x_count: int, prf_keys, seeds, counter0: int = 0):
+    """Alg. 6 for one matched vertex.  idm_shares: three (C,) 0/1 vectors;
+    posting_shares: three (C, L_max, Wx) tables; attr_shares: three (X, Wd)
+    tables.  Returns (ID record shares, attribute record shares), both lists
+    of three arrays (one row per kept neighbour)."""
+    c, lmax, wx = posting_shares[0].shape
+    rows = [p.reshape(c, lmax * wx) for p in posting_shares]
+    pm = selection(idm_shares, rows, prf_keys, counter0)
+    table = [p.reshape(lmax, wx) for p in pm]
+    keep, ids = compact_valid(table, seeds)
+    attrs = [[], [], []]
+    for k in range(keep.size):
+        xb = [np.unpackbits(ids[i][k].astype("<u4").view(np.uint8), bitorder="little")[:x_count]
+              for i in range(3)]
+        d = selection(xb, attr_shares, prf_keys, counter0 + 1 + k)
+        for i in range(3):
+            attrs[i].append(d[i])
+    wd = attr_shares[0].shape[1]
+    return ids, [np.array(a, np.uint32).reshape(keep.size, wd) for a in attrs]

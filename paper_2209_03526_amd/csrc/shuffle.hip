@@ -132,8 +132,20 @@ __global__ void k_open_flags(uint64_t nrows, uint32_t nwords, const uint32_t* __
     if (i < nrows) flags[i] = (a[i * nwords] ^ b[i * nwords] ^ c[i * nwords]) & 1u;
 }
 
-// Copy the kept records (words 1..W-1) of the three share tables to their slots.
-__global__ void k_compact(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ flags,
+// secAccess filter: flag of shuffled record i = parity of all bits of R1 ^ R2 ^ R3
+// (1 for a one-hot ID, 0 for a dummy all-zero ID).
+__global__ void k_open_parity(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ a,
+                              const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
+                              uint32_t* __restrict__ flags) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < nwords; w++) acc ^= a[i * nwords + w] ^ b[i * nwords + w] ^ c[i * nwords + w];
+    flags[i] = __builtin_popcount(acc) & 1u;
+}
+
+// Copy the kept records (words first..W-1) of the three share tables to their slots.
+__global__ void k_compact(uint64_t nrows, uint32_t nwords, uint32_t first, const uint32_t* __restrict__ flags,
                           const uint32_t* __restrict__ pos, const uint32_t* __restrict__ s0,
                           const uint32_t* __restrict__ s1, const uint32_t* __restrict__ s2,
                           uint32_t* __restrict__ o0, uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
@@ -141,11 +153,11 @@ __global__ void k_compact(uint64_t nrows, uint32_t nwords, const uint32_t* __res
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows || !flags[i]) return;
     const uint64_t d = pos[i];
-    const uint32_t rw = nwords - 1;
+    const uint32_t rw = nwords - first;
     for (uint32_t w = 0; w < rw; w++) {
-        o0[d * rw + w] = s0[i * nwords + 1 + w];
-        o1[d * rw + w] = s1[i * nwords + 1 + w];
-        o2[d * rw + w] = s2[i * nwords + 1 + w];
+        o0[d * rw + w] = s0[i * nwords + first + w];
+        o1[d * rw + w] = s1[i * nwords + first + w];
+        o2[d * rw + w] = s2[i * nwords + first + w];
     }
     rows_out[d] = (uint32_t)i;
 }
@@ -321,21 +333,23 @@ uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords) {
            ((scan + 255) & ~255ull) + 4096;
 }
 
-int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
-                   uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
-                   uint64_t work_bytes, void* stream) {
+static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3],
+                                const uint64_t seeds[3], uint32_t* const d_out[3], uint32_t* d_rows_out,
+                                uint32_t* d_count, void* d_work, uint64_t work_bytes, void* stream, bool parity,
+                                const char* who) {
     last_error().clear();
-    if (nwords < 2) return fail(FSS_EINVAL, "rss_fetch_many: records need the bit word and at least one word");
-    if (!d_table || !d_out || !seeds || !d_rows_out || !d_count) return fail(FSS_EINVAL, "rss_fetch_many: NULL argument");
+    if (!parity && nwords < 2) return fail(FSS_EINVAL, "%s: records need the bit word and at least one word", who);
+    if (nwords == 0) return fail(FSS_EINVAL, "%s: empty records", who);
+    if (!d_table || !d_out || !seeds || !d_rows_out || !d_count) return fail(FSS_EINVAL, "%s: NULL argument", who);
     for (int i = 0; i < 3; i++)
-        if (!d_table[i] || !d_out[i]) return fail(FSS_EINVAL, "rss_fetch_many: NULL share %d", i);
-    if (ncand > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_fetch_many: more than 2^31 rows");
+        if (!d_table[i] || !d_out[i]) return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
+    if (ncand > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "%s: more than 2^31 rows", who);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (uint64_t)1, d_count);
     int rc = check_launch("k_zero");
     if (rc || ncand == 0) return rc;
     if (!d_work || work_bytes < rss_fetch_many_workspace_bytes(ncand, nwords))
-        return fail(FSS_ENOMEM, "rss_fetch_many: workspace needs %llu bytes",
+        return fail(FSS_ENOMEM, "%s: workspace needs %llu bytes", who,
                     (unsigned long long)rss_fetch_many_workspace_bytes(ncand, nwords));
     Carve ws{(uint8_t*)d_work, work_bytes};
     const uint64_t tw = ncand * nwords;
@@ -345,21 +359,39 @@ int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_tabl
     size_t scan = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)ncand);
     void* scan_tmp = ws.take<uint8_t>(scan);
-    if (!ws.ok) return fail(FSS_ENOMEM, "rss_fetch_many: workspace too small");
+    if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
     rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_open_flags, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords, sh[0],
-                       sh[1], sh[2], flags);
-    rc = check_launch("k_open_flags");
+    if (parity)
+        hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+                           sh[0], sh[1], sh[2], flags);
+    else
+        hipLaunchKernelGGL(k_open_flags, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+                           sh[0], sh[1], sh[2], flags);
+    rc = check_launch("k_open");
     if (rc) return rc;
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan, flags, pos, (int)ncand, s) != hipSuccess)
-        return fail(FSS_EDEVICE, "rss_fetch_many: scan failed");
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords, flags, pos,
-                       sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out);
+        return fail(FSS_EDEVICE, "%s: scan failed", who);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+                       parity ? 0u : 1u, flags, pos, sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out);
     rc = check_launch("k_compact");
     if (rc) return rc;
     hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, ncand, flags, pos, d_count);
     return check_launch("k_count");
+}
+
+int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
+                   uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
+                   uint64_t work_bytes, void* stream) {
+    return shuffle_open_compact(ncand, nwords, d_table, seeds, d_out, d_rows_out, d_count, d_work, work_bytes, stream,
+                                false, "rss_fetch_many");
+}
+
+int rss_compact_valid(uint64_t nrec, uint32_t nwords, const uint32_t* const d_table[3], const uint64_t seeds[3],
+                      uint32_t* const d_out[3], uint32_t* d_rows_out, uint32_t* d_count, void* d_work,
+                      uint64_t work_bytes, void* stream) {
+    return shuffle_open_compact(nrec, nwords, d_table, seeds, d_out, d_rows_out, d_count, d_work, work_bytes, stream,
+                                true, "rss_compact_valid");
 }
 
 }  // extern "C"

@@ -90,6 +90,7 @@ def _load():
         "rss_fetch_unique": ([u64, u32, P, P, P, P], ctypes.c_int),
         "rss_fetch_many_workspace_bytes": ([u64, u32], u64),
         "rss_fetch_many": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
+        "rss_compact_valid": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
     }
@@ -106,7 +107,7 @@ EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
            "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_fetch_unique", "rss_fetch_many_workspace_bytes",
-           "rss_fetch_many")
+           "rss_fetch_many", "rss_compact_valid")
 
 
 def _check(rc: int):
@@ -353,4 +354,12 @@ def rss_fetch_many(ncand: int, nwords: int, table3, seeds, out3, rows_out, count
     work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=table3[0].device)
     _check(LIB.rss_fetch_many(ncand, nwords, _ptr3(table3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3),
                               _ptr(rows_out), _ptr(count), _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def rss_compact_valid(nrec: int, nwords: int, table3, seeds, out3, rows_out, count, stream=None):
+    nbytes = int(LIB.rss_fetch_many_workspace_bytes(nrec, nwords))
+    work = torch.empty(max(nbytes, 256), dtype=torch.int8, device=table3[0].device)
+    _check(LIB.rss_compact_valid(nrec, nwords, _ptr3(table3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3),
+                                 _ptr(rows_out), _ptr(count), _ptr(work), work.numel(), _stream(stream)))
     return work

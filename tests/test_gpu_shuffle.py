@@ -86,3 +86,54 @@ def test_fetch_many(fss):
         np.testing.assert_array_equal(got[i], want[i])
     rec = got[0] ^ got[1] ^ got[2]
     assert sorted(map(tuple, rec.tolist())) == sorted(map(tuple, d[x == 1].tolist()))
+
+
+def test_sec_access_composed(fss):
+    """Alg. 6 composed from the library calls (selection product + re-share,
+    shuffled parity filter, attribute selection + re-share) equals the oracle
+    share for share, and reconstructs to the plaintext neighbours."""
+    from oracle import access
+    rng = np.random.default_rng(21)
+    c_count, x_count, wd = 40, 100, 2
+    adj = [sorted(rng.choice(x_count, rng.integers(0, 9), replace=False).tolist()) for _ in range(c_count)]
+    attr = rng.integers(0, 2**32, (x_count, wd), dtype=np.uint64).astype(np.uint32)
+    post, lmax = access.encode_posting_lists(adj, x_count, 5)
+    wx = post.shape[2]
+    post_sh = access.rss_split(post, 6)
+    attr_sh = access.rss_split(attr, 7)
+    prf, m = [3, 4, 5], 17
+    seeds = (10, 20, 30)
+    idm = np.zeros(c_count, np.uint8)
+    idm[m] = 1
+    s1 = rng.integers(0, 2, c_count, dtype=np.uint8)
+    s2 = rng.integers(0, 2, c_count, dtype=np.uint8)
+    idm_sh = [s1, s2, idm ^ s1 ^ s2]
+    want_ids, want_attrs = access.sec_access(idm_sh, post_sh, attr_sh, x_count, prf, seeds)
+    # 1. posting list of the matched vertex: selection product, then re-share
+    rec_words = lmax * wx
+    add = [torch.empty(rec_words, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_fetch_unique(c_count, rec_words, [T(ofss.pack_bits(v)) for v in idm_sh],
+                         [T(p.reshape(c_count, rec_words).ravel()) for p in post_sh], add)
+    pm = [torch.empty(rec_words, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_reshare(32 * rec_words, add, prf, 0, pm)
+    # 2. shuffled parity filter
+    ids = [torch.empty(rec_words, dtype=torch.int32, device=DEV) for _ in range(3)]
+    pos = torch.empty(lmax, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    fss.rss_compact_valid(lmax, wx, pm, seeds, ids, pos, cnt)
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    assert k == len(adj[m]) == want_ids[0].shape[0]
+    got_ids = [U(t)[:k * wx].reshape(k, wx) for t in ids]
+    for i in range(3):
+        np.testing.assert_array_equal(got_ids[i], want_ids[i])
+    # 3. attributes of each kept neighbour
+    for j in range(k):
+        a = [torch.empty(wd, dtype=torch.int32, device=DEV) for _ in range(3)]
+        fss.rss_fetch_unique(x_count, wd, [T(got_ids[i][j]) for i in range(3)], [T(s.ravel()) for s in attr_sh], a)
+        d = [torch.empty(wd, dtype=torch.int32, device=DEV) for _ in range(3)]
+        fss.rss_reshare(32 * wd, a, prf, 1 + j, d)
+        for i in range(3):
+            np.testing.assert_array_equal(U(d[i]), want_attrs[i][j])
+    rec = got_ids[0] ^ got_ids[1] ^ got_ids[2]
+    assert sorted(int(access.unpack_onehot(r, x_count)[0]) for r in rec) == adj[m]
