@@ -121,6 +121,10 @@ class ServedPath:
     def __init__(self, graph: ResidentGraph, budget_bytes: int, key_arena_bytes: int, chunk_rows: int = 1 << 20,
                  device=None, stream=None):
         assert key_arena_bytes < budget_bytes and chunk_rows % 64 == 0
+        chunk_keys = 2 * fss.fss_keybatch_bytes(fss.RANGE, 32, chunk_rows)
+        if chunk_keys > key_arena_bytes:
+            raise ValueError(f"a {chunk_rows}-row chunk needs {chunk_keys} key bytes; the key arena holds "
+                             f"{key_arena_bytes}")
         self.g = graph
         self.device = device or torch.device("cuda")
         self.stream = stream or torch.cuda.current_stream()
@@ -139,6 +143,14 @@ class ServedPath:
         used = 0
         free_at = self.budget - self.arena.nbytes
         while pending or admitted:
+            # the admission budget is returned once a request's results are in device memory
+            keep = []
+            for req in in_mem:
+                if req.done_event is not None and req.done_event.query():
+                    used -= req.mem
+                else:
+                    keep.append(req)
+            in_mem = keep
             now = time.perf_counter() - t0
             # admission, in arrival order, while memory allows
             while pending and pending[0].arrival <= now:
@@ -159,10 +171,13 @@ class ServedPath:
                 used += req.mem
             self.max_in_flight = max(self.max_in_flight, len(admitted))
             if not admitted:
-                if pending:
-                    wait = pending[0].arrival - (time.perf_counter() - t0)
-                    if wait > 0:
-                        time.sleep(min(wait, 0.002))
+                wait = pending[0].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.002))
+                elif in_mem:
+                    # the head request waits for memory: every admitted request is
+                    # finished and enqueued, so the oldest one's results free it
+                    in_mem[0].done_event.synchronize()
                 continue
             # one wave over the admitted requests' chunks, oldest first
             self.arena.reset()
@@ -200,14 +215,6 @@ class ServedPath:
                     req.done_event.record(self.stream)
                     _drop_intermediates(req)   # stream-ordered allocator: safe once enqueued
                 admitted = [(r, it) for r, it in admitted if r not in finished]
-            # the admission budget is returned once a request's results are in device memory
-            keep = []
-            for req in in_mem:
-                if req.done_event is not None and req.done_event.query():
-                    used -= req.mem
-                else:
-                    keep.append(req)
-            in_mem = keep
         torch.cuda.synchronize()
         for req in requests:
             req.latency_ms = clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival

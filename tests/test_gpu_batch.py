@@ -183,8 +183,9 @@ def _job_inputs(fss, view, q, vsh, masks, seed):
 
 
 def test_chunked_runner_matches_whole_table(fss):
-    """Waves of 4,096-row chunks under a 12 MB key budget give the same shares
-    as whole-table calls (dealer randomness is addressed by table row)."""
+    """Waves of 4,096-row chunks under a key budget smaller than the jobs' keys
+    give the same shares as whole-table calls (dealer randomness is addressed by
+    table row)."""
     from paper_2209_03526_amd.runner import ChunkedRunner
     g, q = synth.config1(1)
     seed = 4242
@@ -198,7 +199,13 @@ def test_chunked_runner_matches_whole_table(fss):
     tm = synth.pred_masks(7, tq, tiny)
     twant = omatch.run_plan(32, 7, tiny, tq, tsh, tm)
     jobs = [_job_inputs(fss, g, q, shares, masks, seed), _job_inputs(fss, tiny, tq, tsh, tm, 7)]
-    runner = ChunkedRunner(budget_bytes=12 << 20, chunk_rows=4096)
+    # the budget holds the largest chunk's keys (both parties) but well under
+    # half of all keys, so the run needs several waves
+    chunk_keys = [2 * fss.fss_keybatch_bytes(p["kind"], 32, min(4096, p["rows"] - c0))
+                  for job in jobs for p in job.preds for c0 in range(0, p["rows"], 4096)]
+    budget = max(max(chunk_keys) + 4096, sum(chunk_keys) // 3)
+    assert budget < sum(chunk_keys) // 2
+    runner = ChunkedRunner(budget_bytes=budget, chunk_rows=4096)
     runner.run(jobs)
     torch.cuda.synchronize()
     assert runner.waves >= 2
