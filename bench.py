@@ -7,7 +7,7 @@ over all rows for both simulated parties, and the 4 shared bits ANDed into one
 match bit per vertex.
 
 One step is the whole path over that batch: for each predicate the dealer's
-key generation (A2) and the masked open (A1), then match_query (A3-A7: one
+key generation and the masked open, then match_query (one
 k_eval launch over all predicates and both parties, three Beaver ANDs).  The
 reported value counts DPF and DCF tree walks of both parties (a range is two
 DCF walks) per second of step time, keygen included.
@@ -34,14 +34,41 @@ import synth  # noqa: E402
 LOG_ROWS = 22
 NBITS = 32
 SEED = 20220907
-# int32 VALU lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU instructions per AES-128 block in this build's round function (counted
-# from the gfx950 assembly of k_eval; see the design notes)
-AES_OPS = 360
-# AES blocks per row and party of one evaluation, and per row of dealer keygen
-AES_EVAL = {"eq": NBITS - 7 + 1, "range": 2 * NBITS}
-AES_KEYGEN = {"eq": 2 + 4 * (NBITS - 7) + 2, "range": 5 + 2 * 4 * NBITS}
+# Issue floor of the T-table AES on one CDNA4 CU: 4 SIMDs x 16 lanes of VALU
+# (64 lane-ops per clock) and one LDS pipe serving 32 random 32-bit reads per
+# clock (128 B), at 2.4 GHz on 256 CUs.
+CUS, CLOCK_HZ = 256, 2.4e9
+VALU_PER_CLK, LDS_PER_CLK = 64, 32
+PEAK_INT_TOPS = CUS * VALU_PER_CLK * CLOCK_HZ / 1e12
+# (VALU lane-ops, LDS table reads) of one AES-128 block in this design: 9 full
+# rounds of 4 columns x (4 byte-select perms, 4 reads, 2 xor3, 1 rotate), a last
+# round of 4 x (4 perms, 4 reads, 2 perms, 1 xor3), 4 XORs of the first round key
+# and 4 of the Matyas-Meyer-Oseas feed-forward.
+AES_SINGLE = (9 * 4 * 7 + 4 * 7 + 4 + 4, 10 * 16)
+# Both children G_0(s), G_1(s) of one seed: their inputs differ in byte 0 only,
+# so they share the first round-key XOR, three columns of round 1 (column 0
+# takes one extra read, costs 10 ops instead of 2 x 7) and three of the four
+# terms of every round-2 column (the right child's round 2 is 4 reads, 12 ops);
+# the right child's feed-forward input costs one op.
+AES_PAIR = (2 * AES_SINGLE[0] - 4 - (21 + 4) - 16 + 1, 2 * AES_SINGLE[1] - 15 - 12)
+# AES work per table row: (single blocks, sibling pairs); eval walks one child
+# per level per party, the dealer expands both children for both parties.
+AES_WORK = {
+    "eval_eq": (2 * (NBITS - 7 + 1), 0),
+    "eval_range": (2 * 2 * NBITS, 0),
+    "keygen_eq": (4, 2 * (NBITS - 7)),
+    "keygen_range": (5, 2 * 2 * NBITS),
+}
+
+
+def aes_floor(singles: float, pairs: float) -> dict:
+    """Issue-bound time of that much AES work on the whole chip."""
+    valu = singles * AES_SINGLE[0] + pairs * AES_PAIR[0]
+    lds = singles * AES_SINGLE[1] + pairs * AES_PAIR[1]
+    t_valu = valu / VALU_PER_CLK / CUS / CLOCK_HZ
+    t_lds = lds / LDS_PER_CLK / CUS / CLOCK_HZ
+    return {"blocks": singles + 2 * pairs, "valu_ops": valu, "lds_reads": lds, "t_valu": t_valu, "t_lds": t_lds,
+            "t_floor": max(t_valu, t_lds), "binding": "lds" if t_lds >= t_valu else "valu"}
 
 
 def log(msg):
@@ -101,7 +128,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the design notes describe how the path would shard)"}))
+                                   "(a multi-GPU run would shard the rows of each table)"}))
         sys.exit(2)
     import torch
     from paper_2209_03526_amd import fss
@@ -196,27 +223,39 @@ def main():
     kg_eq_ms = float(np.mean(kg["eq"])) if kg["eq"] else 0.0
     kg_rg_ms = float(np.mean(kg["range"])) if kg["range"] else 0.0
     match_mean = float(np.mean(match_ms))
-    eval_aes = 2 * n * (n_eq * AES_EVAL["eq"] + n_rg * AES_EVAL["range"])
-    kg_rg_aes = n * AES_KEYGEN["range"]
-    kg_eq_aes = n * AES_KEYGEN["eq"]
+    def work(key, rows):
+        singles, pairs = AES_WORK[key]
+        return aes_floor(singles * rows, pairs * rows)
+
+    ev_eq, ev_rg = work("eval_eq", n * n_eq), work("eval_range", n * n_rg)
+    eval_floor = aes_floor(0, 0)
+    for k in eval_floor:
+        if k != "binding":
+            eval_floor[k] = ev_eq[k] + ev_rg[k]
+    eval_floor["binding"] = "lds" if eval_floor["t_lds"] >= eval_floor["t_valu"] else "valu"
     kernels = {
-        "k_keygen_range": {"ms": kg_rg_ms, "aes_blocks": kg_rg_aes, "launches_per_step": n_rg},
-        "k_keygen_eq": {"ms": kg_eq_ms, "aes_blocks": kg_eq_aes, "launches_per_step": n_eq},
-        "match_query(k_eval+ands)": {"ms": match_mean, "aes_blocks": eval_aes, "launches_per_step": 1},
+        "k_keygen_range": {"ms": kg_rg_ms, "launches_per_step": n_rg, "floor": work("keygen_range", n)},
+        "k_keygen_eq": {"ms": kg_eq_ms, "launches_per_step": n_eq, "floor": work("keygen_eq", n)},
+        "match_query(k_eval+ands)": {"ms": match_mean, "launches_per_step": 1, "floor": eval_floor},
     }
     share = {k: v["ms"] * v["launches_per_step"] for k, v in kernels.items()}
     dom = max(share, key=share.get)
-    dk = kernels[dom]
-    ops = dk["aes_blocks"] * AES_OPS
-    achieved = ops / (dk["ms"] / 1e3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 3),
-                "unit": "T int32 VALU ops/s (AES blocks x %d ops)" % AES_OPS,
-                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": measured_traffic(dom),
-                "aes_blocks_per_s": dk["aes_blocks"] / (dk["ms"] / 1e3)}
     for k, v in kernels.items():
-        v["aes_gblocks_per_s"] = round(v["aes_blocks"] / (v["ms"] / 1e3) / 1e9, 3) if v["ms"] else None
-        v["frac_of_valu_peak"] = round(v["aes_blocks"] * AES_OPS / (v["ms"] / 1e3) / 1e12 / PEAK_INT_TOPS, 4) \
-            if v["ms"] else None
+        f = v.pop("floor")
+        t = v["ms"] / 1e3
+        v["aes_blocks"] = int(f["blocks"])
+        v["aes_gblocks_per_s"] = round(f["blocks"] / t / 1e9, 3) if t else None
+        v["floor_gblocks_per_s"] = round(f["blocks"] / f["t_floor"] / 1e9, 3)
+        v["binding_unit"] = f["binding"]
+        v["frac_of_floor"] = round(f["t_floor"] / t, 4) if t else None
+        v["valu_frac"] = round(f["t_valu"] / t, 4) if t else None
+        v["lds_frac"] = round(f["t_lds"] / t, 4) if t else None
+    dk = kernels[dom]
+    roofline = {"bound": "alu", "kernel": dom, "achieved": dk["aes_gblocks_per_s"],
+                "peak": dk["floor_gblocks_per_s"],
+                "unit": "G AES-128 blocks/s (peak: VALU and LDS-read issue floor, 256 CUs at 2.4 GHz)",
+                "frac": dk["frac_of_floor"], "traffic": measured_traffic(dom),
+                "binding_unit": dk["binding_unit"], "valu_frac": dk["valu_frac"], "lds_frac": dk["lds_frac"]}
     eval_evals_per_s = evals_per_step / (match_mean / 1e3)
 
     cpu = None

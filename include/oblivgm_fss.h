@@ -81,7 +81,7 @@ const char* fss_last_error(void);
 const char* fss_version(void);
 
 /*
- * A1 -- open the masked value (Sec. V-B additive shares, Sec. V-C masked input):
+ * Open the masked value (Sec. V-B additive shares, Sec. V-C masked input):
  *   d_xhat[i] = d_x0[i] + d_x1[i] + d_r[i]  (mod 2^32),  i < n.
  * In a deployment party b publishes x_b + r_b; with both parties simulated
  * the sum is formed at once.  d_xhat may alias none of the inputs' other rows
@@ -91,7 +91,7 @@ int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const 
                   uint32_t* d_xhat, void* stream);
 
 /*
- * A2 -- dealer key generation (Def. 3 Gen; Sec. V-C token generation in its
+ * Dealer key generation (Def. 3 Gen; Sec. V-C token generation in its
  * masked-input form).  For every row e < out->n, with mask d_r[e]:
  *   FSS_EQ:    DPF at alpha = (a_or_lo + r) mod 2^nbits          (hi ignored)
  *   FSS_RANGE: DCF at U = hi + r and at L = a_or_lo + r, wrap share c_b with
@@ -107,7 +107,7 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
                const uint32_t* d_r, const fss_keybatch* out, void* stream);
 
 /*
- * A2 (dealer) -- the per-row masks r of the masked-input approach (Sec. V-C),
+ * Dealer masks -- the per-row masks r of the masked-input approach (Sec. V-C),
  * drawn from the dealer's counter-mode generator: d_r[i] = little-endian word 0
  * of AES_{LE64(seed)||"OBLIVGM1"}(LE16 2 || LE16 0 || LE32 query_id ||
  * LE32 pred_id || LE32 (row_offset + i)), i < n.  (Callers may also supply
@@ -117,7 +117,7 @@ int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_
                      uint32_t* d_r, void* stream);
 
 /*
- * A3 + A5 -- DPF evaluation (Def. 3 Eval) by `party` (0 or 1) on the opened
+ * DPF evaluation (Def. 3 Eval) by `party` (0 or 1) on the opened
  * values d_xhat[0..n): writes ceil(n/32) packed share words to d_out_bits.
  * XOR of both parties' words is [x == a] per row.  k->kind must be FSS_EQ.
  */
@@ -125,7 +125,7 @@ int fss_eval_eq(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, ui
                 void* stream);
 
 /*
- * A4 + A5 -- range evaluation: two DCF walks and the wrap share (interval
+ * Range evaluation: two DCF walks and the wrap share (interval
  * containment from comparisons, Sec. V-C).  XOR of both parties' words is
  * [lo <= x < hi].  k->kind must be FSS_RANGE.
  */
@@ -133,7 +133,7 @@ int fss_eval_lt(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, ui
                 void* stream);
 
 /*
- * A6 -- shared AND of packed bits by Beaver triples (two-party analogue of the
+ * Shared AND of packed bits by Beaver triples (two-party analogue of the
  * AND of Sec. III-B; aggregation of predicates by AND, Sec. V-D).
  *
  * ss_triples: dealer's triples for AND number `and_id` of query `query_id`:
@@ -153,7 +153,7 @@ int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, co
            const uint32_t* d_triple, const uint32_t* d_de_open, uint32_t* d_out, void* stream);
 
 /*
- * A7 -- a whole path query v_0 -> v_1 -> ... -> v_{n_qv-1} (Alg. 2, secMatch,
+ * Edge matching -- a whole path query v_0 -> v_1 -> ... -> v_{n_qv-1} (Alg. 2, secMatch,
  * with public edge endpoints) for BOTH simulated parties.
  *
  * Predicate k targets query vertex `target` (< n_qv; rows = vertex table) or
@@ -222,11 +222,11 @@ int match_query(const match_plan* plan, int32_t party_mask, void* stream);
  * calls on one stream run in order; batches that share a d_queue must be on
  * one stream.
  *
- * fss_keygen_batch (A2 for many predicates / queries): each request is one
+ * fss_keygen_batch (dealer keygen for many predicates / queries): each request is one
  * fss_keygen call (same meaning, same checks).
- * fss_eval_batch (A3/A4 for many predicates, parties, queries): each request
+ * fss_eval_batch (DPF / range evaluation for many predicates, parties, queries): each request
  * is one fss_eval_eq / fss_eval_lt call, chosen by keys->kind.
- * match_query_batch (A7 for many plans): every predicate of every plan, both
+ * match_query_batch (edge matching for many plans): every predicate of every plan, both
  * parties, in one persistent launch; then each plan's ANDs and joins in plan
  * order.  Each plan has its own outputs and workspace as in match_query.
  */

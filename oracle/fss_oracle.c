@@ -19,7 +19,7 @@
  *     AES blocks): Sec. VII-A, protocol instantiation.
  *   - AES-128 itself: FIPS-197 (Sec. 5.1 cipher, Sec. 5.2 key expansion).
  * The paper fixes neither the PRG nor the tree construction's bit conventions;
- * the readings taken here are the FSS specification listed in the design notes
+ * the readings taken here form this FSS specification
  * (PRG = fixed-key AES in Matyas-Meyer-Oseas form with the branch tweak XORed
  * into byte 0; tree walk MSB first; t = bit 0, v = bit 1, next seed = block with
  * bits 0 and 1 cleared; DPF stops nu = n - 7 levels above the leaves and ends

@@ -2,11 +2,11 @@
 //
 // What is computed, and where the paper defines it, is stated per entry point
 // in include/oblivgm_fss.h.  This file holds:
-//   k_mask_open     A1  xhat = x0 + x1 + r                       (HBM stream)
-//   k_keygen        A2  dealer: DPF / 2xDCF Gen per row           (VALU, AES)
-//   k_eval          A3/A4/A5  DPF / 2xDCF Eval per row, ballot    (VALU, AES)
-//   k_triples       A6  dealer: Beaver triples                    (VALU, AES)
-//   k_and_open/close, k_and_both, k_gather, k_public_one  A6/A7  (HBM stream)
+//   k_mask_open            xhat = x0 + x1 + r                          (HBM stream)
+//   k_keygen_eq/_range     dealer: DPF / 2xDCF Gen per row             (LDS + VALU, AES)
+//   k_eval                 DPF / 2xDCF Eval per row, ballot            (LDS + VALU, AES)
+//   k_triples              dealer: Beaver triples                      (LDS + VALU, AES)
+//   k_and_open/close, k_and_both, k_gather, k_public_one  ANDs, joins  (HBM stream)
 // and the host code of the C ABI (validation, launch, match_query plan).
 //
 // Every AES-using kernel runs 1024-thread workgroups that first fill the
@@ -114,7 +114,7 @@ __device__ __forceinline__ uint4 clear_tv(uint4 w) {
     return w;
 }
 
-// ----------------------------------------------------------------- Eval (A3 / A4)
+// ----------------------------------------------------------------- Eval (DPF, DCF)
 
 // Party `party`'s DPF output bit at x (nu = nbits - 7 levels, 128-bit leaf).
 __device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalBatch batch) {
     eval_rows(D, (uint64_t)(blockIdx.x - D.block_start) * kBlock, tab, lane_offset());
 }
 
-// ----------------------------------------------------------------- dealer (A2, A6)
+// ----------------------------------------------------------------- dealer (keys, triples)
 
 struct DealerArgs {
     RoundKeys rk;           // AES key schedule of LE64(seed) || "OBLIVGM1"
@@ -344,7 +344,8 @@ __device__ __forceinline__ void dcf_gen(uint8_t* k, uint64_t np, uint64_t row, u
     at_w<uint32_t>(k, P.fin(), row) = fin | (wrap << 31);
 }
 
-// Both lanes of row `row`'s pair (b = party of this lane).
+// Both lanes of row `row`'s pair (b = party of this lane); KIND is the key kind.
+template <int KIND>
 __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, uint32_t b, const uint32_t* tab,
                                            LaneOff loff) {
     const uint64_t np = pad_rows(A.n);
@@ -353,7 +354,7 @@ __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, ui
     const uint32_t e = (uint32_t)row + A.row_offset;
     uint8_t* key = b ? A.key1 : A.key0;
     const uint4 s = clear_tv(rng_block(A.rk, 3, b, A.query, A.pred, e, tab, loff));
-    if (A.kind == FSS_EQ) {
+    if (KIND == FSS_EQ) {
         dpf_gen(key, np, row, A.nbits, (A.a_or_lo + r) & mask, b, s, tab, loff);
     } else {
         const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
@@ -365,16 +366,21 @@ __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, ui
     }
 }
 
-// Two lanes per row (see above); 512 rows per workgroup.
-__global__ __launch_bounds__(kBlock) void k_keygen(DealerArgs A) {
+// Two lanes per row (see above); 512 rows per workgroup.  One kernel per key
+// kind, so each is compiled for its own Gen alone.
+template <int KIND>
+__device__ __forceinline__ void keygen_grid(const DealerArgs& A) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tables.t0);
     __syncthreads();
     const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t row = gid >> 1;
     if (row >= A.n) return;                 // both lanes of a pair leave together
-    keygen_row(A, row, (uint32_t)(gid & 1u), tab, lane_offset());
+    keygen_row<KIND>(A, row, (uint32_t)(gid & 1u), tab, lane_offset());
 }
+
+__global__ __launch_bounds__(kBlock) void k_keygen_eq(DealerArgs A) { keygen_grid<FSS_EQ>(A); }
+__global__ __launch_bounds__(kBlock) void k_keygen_range(DealerArgs A) { keygen_grid<FSS_RANGE>(A); }
 
 // ----------------------------------------------------------------- persistent work queue (batches)
 //
@@ -429,7 +435,12 @@ __global__ __launch_bounds__(kBlock) void k_keygen_queue(const QKeygen* __restri
         const uint32_t di = find_desc(count, tile, [&](uint32_t i) { return q[i].tile_start; });
         const DealerArgs& A = q[di].a;
         const uint64_t row = (uint64_t)(tile - q[di].tile_start) * (kBlock / 2) + (threadIdx.x >> 1);
-        if (row < A.n) keygen_row(A, row, threadIdx.x & 1u, tab, loff);
+        if (row < A.n) {
+            if (A.kind == FSS_EQ)
+                keygen_row<FSS_EQ>(A, row, threadIdx.x & 1u, tab, loff);
+            else
+                keygen_row<FSS_RANGE>(A, row, threadIdx.x & 1u, tab, loff);
+        }
     }
 }
 
@@ -556,7 +567,7 @@ __global__ void k_rss_eval(uint64_t ncand, uint32_t nwords_pos, const uint32_t* 
     }
 }
 
-// ----------------------------------------------------------------- streaming kernels (A1, A6, A7)
+// ----------------------------------------------------------------- streaming kernels (open, ANDs, joins)
 
 __global__ void k_mask_open(uint64_t n, const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1,
                             const uint32_t* __restrict__ r, uint32_t* __restrict__ xhat) {
@@ -825,8 +836,11 @@ int fss_keygen(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_t a_or
     A.pred = pred_id;
     A.a_or_lo = a_or_lo;
     A.hi = hi;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)((2 * out->n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       (hipStream_t)stream, A);
+    const dim3 grid((unsigned)((2 * out->n + kBlock - 1) / kBlock));
+    if (out->kind == FSS_EQ)
+        hipLaunchKernelGGL(k_keygen_eq, grid, dim3(kBlock), 0, (hipStream_t)stream, A);
+    else
+        hipLaunchKernelGGL(k_keygen_range, grid, dim3(kBlock), 0, (hipStream_t)stream, A);
     return check_launch("k_keygen");
 }
 

@@ -121,10 +121,6 @@ class ServedPath:
     def __init__(self, graph: ResidentGraph, budget_bytes: int, key_arena_bytes: int, chunk_rows: int = 1 << 20,
                  device=None, stream=None):
         assert key_arena_bytes < budget_bytes and chunk_rows % 64 == 0
-        chunk_keys = 2 * fss.fss_keybatch_bytes(fss.RANGE, 32, chunk_rows)
-        if chunk_keys > key_arena_bytes:
-            raise ValueError(f"a {chunk_rows}-row chunk needs {chunk_keys} key bytes; the key arena holds "
-                             f"{key_arena_bytes}")
         self.g = graph
         self.device = device or torch.device("cuda")
         self.stream = stream or torch.cuda.current_stream()
@@ -187,7 +183,10 @@ class ServedPath:
                     k, c0, n = items[0]
                     p = req.preds[k]
                     half = fss.fss_keybatch_bytes(p["kind"], 32, n)
-                    if kg and self.arena.used + 2 * half > self.arena.nbytes:
+                    if self.arena.used + 2 * half > self.arena.nbytes:
+                        if not kg:
+                            raise ValueError(f"a {n}-row chunk needs {2 * half} key bytes; the key arena "
+                                             f"holds {self.arena.nbytes}")
                         break
                     items.popleft()
                     kb = fss.KeyBatch.view(p["kind"], 32, n, self.arena.take(half), self.arena.take(half))

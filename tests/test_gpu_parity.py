@@ -29,7 +29,7 @@ def _rand_u32(seed, n):
     return np.random.default_rng(seed).integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
 
 
-# --------------------------------------------------------------------------- A1
+# --------------------------------------------------------------------------- masked open
 
 @pytest.mark.parametrize("n", [1, 255, 1024, 1000003])
 def test_mask_open(fss, n):
@@ -39,7 +39,7 @@ def test_mask_open(fss, n):
     np.testing.assert_array_equal(U(out), ofss.mask_open(x0, x1, r))
 
 
-# --------------------------------------------------------------------------- A2 keygen
+# --------------------------------------------------------------------------- dealer keygen
 
 KG_CASES = [(kind, nbits, n) for kind in (0, 1) for nbits in (8, 12, 32) for n in (1, 65, 1000)] + \
            [(0, 32, 4099), (1, 32, 4099), (0, 20, 2048), (1, 17, 333)]
@@ -66,7 +66,7 @@ def test_keygen_bit_exact(fss, kind, nbits, n):
         assert got.tobytes() == want.tobytes(), f"party {b} keys differ"
 
 
-# --------------------------------------------------------------------------- A3/A4 eval on oracle keys
+# --------------------------------------------------------------------------- eval on oracle keys
 
 @pytest.mark.parametrize("kind,nbits,n", [(0, 32, 3001), (1, 32, 3001), (0, 8, 70), (1, 12, 129), (0, 12, 1),
                                           (1, 32, 64)])
@@ -156,7 +156,7 @@ def test_small_domain_ignores_high_bits(fss):
     np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, 256), (x == 77).astype(np.uint8))
 
 
-# --------------------------------------------------------------------------- A6
+# --------------------------------------------------------------------------- Beaver AND
 
 @pytest.mark.parametrize("nrows", [1, 31, 32, 1000, 65537])
 def test_triples_and_per_party(fss, nrows):
@@ -188,7 +188,7 @@ def test_triples_and_per_party(fss, nrows):
     np.testing.assert_array_equal(z[0] ^ z[1], (x[0] ^ x[1]) & (y[0] ^ y[1]))
 
 
-# --------------------------------------------------------------------------- A7
+# --------------------------------------------------------------------------- edge matching
 
 P = synth.Pred
 TINY_QUERIES = [

@@ -120,6 +120,7 @@ def test_continuous_batching_mixes_arrivals(fake):
 
 
 def test_chunk_larger_than_key_arena_is_rejected(fake):
+    path = serving.ServedPath(None, budget_bytes=1 << 30, key_arena_bytes=1 << 20, chunk_rows=512, device="cpu",
+                              stream=object())
     with pytest.raises(ValueError, match="key arena"):
-        serving.ServedPath(None, budget_bytes=1 << 30, key_arena_bytes=1 << 20, chunk_rows=512, device="cpu",
-                           stream=object())
+        _run(path, _reqs([0.0]))
