@@ -344,6 +344,7 @@ def run_batch64(args, torch, fss, dev):
             plan = fss.Plan(job.seed, job.query_id, job.n_qv, job.n_vertices, job.n_edges, kbs, job.src,
                             job.dst).allocate(dev)
             fss.match_query(plan)
+            plan.release_inputs()      # the keys are not needed once match_query is enqueued
             res.append(plan)
             del kbs
         return res

@@ -83,10 +83,16 @@ constexpr AesTables make_tables() {
 
 constexpr AesTables kTables = make_tables();
 
-// Round keys as 44 little-endian words: word 4r + c is column c of round r.
+// Round keys as 44 little-endian words, word 4r + c = column c of round r,
+// each kept in the form the cipher consumes it: the first (whitening) and last
+// round keys as they are, the keys of rounds 1..9 rotated right by 16 bits
+// (round_col folds them in before its rotate).  A per-call schedule then costs
+// no rotate in the kernel and 44 scalar registers.
 struct RoundKeys {
     uint32_t w[44];
 };
+
+constexpr bool kRotatedRoundKey(int i) { return i >= 4 && i < 40; }
 
 constexpr RoundKeys expand_key(const uint8_t (&key)[16]) {
     RoundKeys rk{};
@@ -105,28 +111,31 @@ constexpr RoundKeys expand_key(const uint8_t (&key)[16]) {
         }
         for (int k = 0; k < 4; k++) b[4 * i + k] = (uint8_t)(b[4 * i - 16 + k] ^ t[k]);
     }
-    for (int i = 0; i < 44; i++)
+    for (int i = 0; i < 44; i++) {
         rk.w[i] = (uint32_t)b[4 * i] | ((uint32_t)b[4 * i + 1] << 8) | ((uint32_t)b[4 * i + 2] << 16) |
                   ((uint32_t)b[4 * i + 3] << 24);
+        if (kRotatedRoundKey(i)) rk.w[i] = (rk.w[i] >> 16) | (rk.w[i] << 16);
+    }
     return rk;
 }
 
 constexpr uint8_t kPrgKeyBytes[16] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
 constexpr RoundKeys kPrgKeys = expand_key(kPrgKeyBytes);
 
+// Key sources: k[i] is word i for the whitening (i < 4) and last (i >= 40)
+// round keys, k.mid(i) a word of rounds 1..9, already rotated.
+//
 // The fixed PRG key schedule, folded into instruction constants after unrolling.
 struct FixedPrgKey {
     __device__ __forceinline__ constexpr uint32_t operator[](int i) const { return kPrgKeys.w[i]; }
-    __device__ __forceinline__ constexpr uint32_t rotr16(int i) const {
-        return (kPrgKeys.w[i] >> 16) | (kPrgKeys.w[i] << 16);
-    }
+    __device__ __forceinline__ constexpr uint32_t mid(int i) const { return kPrgKeys.w[i]; }
 };
 
 // A per-call key schedule held in kernel arguments (scalar registers).
 struct ArgKey {
     const RoundKeys& rk;
     __device__ __forceinline__ uint32_t operator[](int i) const { return rk.w[i]; }
-    __device__ __forceinline__ uint32_t rotr16(int i) const { return (rk.w[i] >> 16) | (rk.w[i] << 16); }
+    __device__ __forceinline__ uint32_t mid(int i) const { return rk.w[i]; }
 };
 
 // ----------------------------------------------------------------- LDS table
@@ -199,10 +208,10 @@ __device__ __forceinline__ uint4 aes128_rounds_2_10(uint32_t s0, uint32_t s1, ui
                                                     const uint32_t* tab, LaneOff lo) {
 #pragma unroll
     for (int r = 2; r < 10; r++) {
-        const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.rotr16(4 * r + 0));
-        const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(4 * r + 1));
-        const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(4 * r + 2));
-        const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(4 * r + 3));
+        const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.mid(4 * r + 0));
+        const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.mid(4 * r + 1));
+        const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.mid(4 * r + 2));
+        const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.mid(4 * r + 3));
         s0 = n0; s1 = n1; s2 = n2; s3 = n3;
     }
     uint4 out;
@@ -216,10 +225,10 @@ __device__ __forceinline__ uint4 aes128_rounds_2_10(uint32_t s0, uint32_t s1, ui
 template <class RK>
 __device__ __forceinline__ uint4 aes128_encrypt(uint4 in, const RK& rk, const uint32_t* tab, LaneOff lo) {
     const uint32_t s0 = in.x ^ rk[0], s1 = in.y ^ rk[1], s2 = in.z ^ rk[2], s3 = in.w ^ rk[3];
-    const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.rotr16(4));
-    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(5));
-    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(6));
-    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(7));
+    const uint32_t n0 = round_col(tab, lo, s0, s1, s2, s3, rk.mid(4));
+    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.mid(5));
+    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.mid(6));
+    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.mid(7));
     return aes128_rounds_2_10(n0, n1, n2, n3, rk, tab, lo);
 }
 
@@ -251,12 +260,12 @@ __device__ __forceinline__ void prg_pair(uint4 s, const uint32_t* tab, LaneOff l
     const uint32_t b = tlook<1>(tab, s1, lo.t1);
     const uint32_t c = tlook<2>(tab, s2, lo.t0);
     const uint32_t d = tlook<3>(tab, s3, lo.t1);
-    const uint32_t cd = rotl32(xor3(c, d, rk.rotr16(4)), 16);
+    const uint32_t cd = rotl32(xor3(c, d, rk.mid(4)), 16);
     const uint32_t n0l = xor3(a_l, b, cd);
     const uint32_t n0r = xor3(a_r, b, cd);
-    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.rotr16(5));
-    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.rotr16(6));
-    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.rotr16(7));
+    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.mid(5));
+    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.mid(6));
+    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.mid(7));
     uint4 ur = s;
     ur.x ^= 1u;
     wl = xor4(aes128_rounds_2_10(n0l, n1, n2, n3, rk, tab, lo), s);

@@ -247,6 +247,16 @@ __device__ __forceinline__ uint4 rng_block(const RoundKeys& rk, uint32_t domain,
     return aes128_encrypt(in, ArgKey{rk}, tab, loff);
 }
 
+// An empty asm statement that claims to rewrite v and memory: the value is
+// complete here, in registers, and neither its computation nor the table reads
+// of the next one move across this point (the dealer's root blocks are drawn
+// one after the other instead of side by side, which bounds register use).
+__device__ __forceinline__ void pin_in_vgprs(uint4& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w) : : "memory");
+}
+
+__device__ __forceinline__ void pin_in_vgprs(uint32_t& v) { asm volatile("" : "+v"(v) : : "memory"); }
+
 __device__ __forceinline__ uint32_t sel(uint32_t c, uint32_t a, uint32_t b) { return c ? a : b; }
 __device__ __forceinline__ uint4 sel4(uint32_t c, uint4 a, uint4 b) { return c ? a : b; }
 
@@ -353,15 +363,20 @@ __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, ui
     const uint32_t r = A.r[row];
     const uint32_t e = (uint32_t)row + A.row_offset;
     uint8_t* key = b ? A.key1 : A.key0;
-    const uint4 s = clear_tv(rng_block(A.rk, 3, b, A.query, A.pred, e, tab, loff));
+    uint4 s = clear_tv(rng_block(A.rk, 3, b, A.query, A.pred, e, tab, loff));
+    pin_in_vgprs(s);
     if (KIND == FSS_EQ) {
         dpf_gen(key, np, row, A.nbits, (A.a_or_lo + r) & mask, b, s, tab, loff);
     } else {
         const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
-        const uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
+        uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
+        pin_in_vgprs(c0);
         const uint32_t cb = c0 ^ (b & (L > U ? 1u : 0u));
+        // all three root blocks are drawn before the first tree walk, so that
+        // nothing of their AES work stays live across it
+        uint4 sl = clear_tv(rng_block(A.rk, 3, 3 + b, A.query, A.pred, e, tab, loff));
+        pin_in_vgprs(sl);
         dcf_gen(key, np, row, A.nbits, U, b, s, cb, tab, loff);
-        const uint4 sl = clear_tv(rng_block(A.rk, 3, 3 + b, A.query, A.pred, e, tab, loff));
         dcf_gen(key + DcfPlanes{np, A.nbits}.bytes(), np, row, A.nbits, L, b, sl, 0u, tab, loff);
     }
 }
@@ -423,8 +438,11 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_til
     return *s_tile;
 }
 
-__global__ __launch_bounds__(kBlock) void k_keygen_queue(const QKeygen* __restrict__ q, uint32_t count,
-                                                        uint32_t total_tiles, uint32_t* counter) {
+// One key kind per launch (the host splits a batch by kind), so each kernel
+// holds one Gen's registers.
+template <int KIND>
+__device__ __forceinline__ void keygen_queue(const QKeygen* __restrict__ q, uint32_t count, uint32_t total_tiles,
+                                             uint32_t* counter) {
     __shared__ uint32_t tab[kLdsTableWords];
     __shared__ uint32_t s_tile;
     lds_table_fill(tab, g_tables.t0);
@@ -435,13 +453,18 @@ __global__ __launch_bounds__(kBlock) void k_keygen_queue(const QKeygen* __restri
         const uint32_t di = find_desc(count, tile, [&](uint32_t i) { return q[i].tile_start; });
         const DealerArgs& A = q[di].a;
         const uint64_t row = (uint64_t)(tile - q[di].tile_start) * (kBlock / 2) + (threadIdx.x >> 1);
-        if (row < A.n) {
-            if (A.kind == FSS_EQ)
-                keygen_row<FSS_EQ>(A, row, threadIdx.x & 1u, tab, loff);
-            else
-                keygen_row<FSS_RANGE>(A, row, threadIdx.x & 1u, tab, loff);
-        }
+        if (row < A.n) keygen_row<KIND>(A, row, threadIdx.x & 1u, tab, loff);
     }
+}
+
+__global__ __launch_bounds__(kBlock, 8) void k_keygen_queue_eq(const QKeygen* __restrict__ q, uint32_t count,
+                                                           uint32_t total_tiles, uint32_t* counter) {
+    keygen_queue<FSS_EQ>(q, count, total_tiles, counter);
+}
+
+__global__ __launch_bounds__(kBlock, 8) void k_keygen_queue_range(const QKeygen* __restrict__ q, uint32_t count,
+                                                              uint32_t total_tiles, uint32_t* counter) {
+    keygen_queue<FSS_RANGE>(q, count, total_tiles, counter);
 }
 
 __global__ __launch_bounds__(kBlock, 8) void k_eval_queue(const QEval* __restrict__ q, uint32_t count,
@@ -1346,12 +1369,18 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
     std::stable_sort(q.begin(), q.end(), [](const QKeygen& a, const QKeygen& b) {
         return (a.a.kind == FSS_RANGE) != (b.a.kind == FSS_RANGE) ? a.a.kind == FSS_RANGE : a.a.n > b.a.n;
     });
-    uint64_t tiles = 0;
-    for (auto& e : q) {
-        e.tile_start = (uint32_t)tiles;
-        tiles += (e.a.n + kBlock / 2 - 1) / (kBlock / 2);
+    // range descriptors first, then equality ones; tile numbers restart per kind
+    const size_t n_range = (size_t)(std::find_if(q.begin(), q.end(),
+                                                 [](const QKeygen& e) { return e.a.kind != FSS_RANGE; }) -
+                                    q.begin());
+    uint64_t tiles[2] = {0, 0};
+    for (size_t i = 0; i < q.size(); i++) {
+        uint64_t& t = tiles[i < n_range ? 0 : 1];
+        q[i].tile_start = (uint32_t)t;
+        t += (q[i].a.n + kBlock / 2 - 1) / (kBlock / 2);
     }
-    if (tiles > 0xFFFFFFF0ull) return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: too many tiles");
+    if (tiles[0] > 0xFFFFFFF0ull || tiles[1] > 0xFFFFFFF0ull)
+        return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: too many tiles");
     if (!d_queue || queue_bytes_avail < queue_bytes(q.size()))
         return fail(FSS_ENOMEM, "fss_keygen_batch: queue workspace needs %llu bytes",
                     (unsigned long long)queue_bytes(q.size()));
@@ -1360,11 +1389,23 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
     QKeygen* dq = (QKeygen*)((uint8_t*)d_queue + kQueueHeader);
     int rc = upload(q.data(), q.size() * sizeof(QKeygen), dq, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
-    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
-    hipLaunchKernelGGL(k_keygen_queue, dim3((unsigned)grid), dim3(kBlock), 0, s, dq, (uint32_t)q.size(),
-                       (uint32_t)tiles, counter);
-    return check_launch("k_keygen_queue");
+    const uint64_t slots = (uint64_t)g_tuning.wg_per_cu * device_cus();
+    // the two launches share the counter; stream order puts each zeroing
+    // after the previous launch has drained
+    if (tiles[0]) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+        hipLaunchKernelGGL(k_keygen_queue_range, dim3((unsigned)std::min(tiles[0], slots)), dim3(kBlock), 0, s,
+                           dq, (uint32_t)n_range, (uint32_t)tiles[0], counter);
+        rc = check_launch("k_keygen_queue_range");
+        if (rc) return rc;
+    }
+    if (tiles[1]) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+        hipLaunchKernelGGL(k_keygen_queue_eq, dim3((unsigned)std::min(tiles[1], slots)), dim3(kBlock), 0, s,
+                           dq + n_range, (uint32_t)(q.size() - n_range), (uint32_t)tiles[1], counter);
+        rc = check_launch("k_keygen_queue_eq");
+    }
+    return rc;
 }
 
 int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,

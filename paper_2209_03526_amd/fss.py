@@ -247,6 +247,13 @@ class Plan:
         self.c.workspace_bytes = self.workspace.numel()
         return self
 
+    def release_inputs(self):
+        """Drop the references to keys, opened values, share bits and the
+        workspace once the plan's work is enqueued (the caching allocator
+        reuses the memory in stream order); only the result shares stay."""
+        self._keep = []
+        self.workspace = None
+
 
 def match_workspace_bytes(plan: Plan) -> int:
     return int(LIB.match_workspace_bytes(ctypes.byref(plan.c)))

@@ -150,3 +150,6 @@ class ChunkedRunner:
             job.plan = plan
             plans.append(plan)
         fss.match_query_batch(plans, self.queue, 3, self.stream)
+        for job, plan in zip(jobs, plans):
+            plan.release_inputs()
+            job.bits = []

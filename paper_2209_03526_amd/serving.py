@@ -256,8 +256,7 @@ def _drop_intermediates(req: Request):
     req.bits = []
     req.view = dict(n_vertices=req.view["n_vertices"], n_edges=req.view["n_edges"], src=None, dst=None)
     if req.plan is not None:
-        req.plan.workspace = None
-        req.plan._keep = []
+        req.plan.release_inputs()
 
 
 def outputs(req: Request):

@@ -71,7 +71,7 @@ def fake(monkeypatch):
     monkeypatch.setattr(serving, "fss", _fake_fss(log))
     monkeypatch.setattr(serving, "KeyArena", FakeArena)
     monkeypatch.setattr(serving, "prepare", _prepare)
-    monkeypatch.setattr(serving, "_plan", lambda req, given, dev: types.SimpleNamespace(workspace=1, _keep=[]))
+    monkeypatch.setattr(serving, "_plan", lambda req, given, dev: types.SimpleNamespace(release_inputs=lambda: None))
     monkeypatch.setattr(torch.cuda, "Event", FakeEvent)
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
     return log
