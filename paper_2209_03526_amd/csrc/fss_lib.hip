@@ -1147,36 +1147,50 @@ int device_cus() {
 
 // Descriptors reach the device through a pinned staging buffer owned by the
 // library; a buffer is reused only after its previous upload completed.
-struct Staging {
-    std::mutex mu;
+// Descriptor uploads go through a ring of pinned host slots.  A slot is
+// rewritten only after the copy that last read it has executed (its event),
+// so the host can run several batch calls ahead of the stream.  Device-side
+// queue buffers need no such care: an upload and the kernel that reads it are
+// ordered on the caller's stream.
+constexpr int kStagingSlots = 8;
+
+struct StagingSlot {
     void* host = nullptr;
     size_t cap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
+
+struct Staging {
+    std::mutex mu;
+    StagingSlot slot[kStagingSlots];
+    int next = 0;
+};
 Staging g_staging;
 
 int upload(const void* src, size_t bytes, void* d_dst, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_staging.mu);
-    if (g_staging.pending) {
-        if (hipEventSynchronize(g_staging.done) != hipSuccess) return fail(FSS_EDEVICE, "batch: staging wait failed");
-        g_staging.pending = false;
+    StagingSlot& sl = g_staging.slot[g_staging.next];
+    g_staging.next = (g_staging.next + 1) % kStagingSlots;
+    if (sl.pending) {
+        if (hipEventSynchronize(sl.done) != hipSuccess) return fail(FSS_EDEVICE, "batch: staging wait failed");
+        sl.pending = false;
     }
-    if (!g_staging.done && hipEventCreateWithFlags(&g_staging.done, hipEventDisableTiming) != hipSuccess)
+    if (!sl.done && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
         return fail(FSS_EDEVICE, "batch: event creation failed");
-    if (g_staging.cap < bytes) {
-        if (g_staging.host) (void)hipHostFree(g_staging.host);
-        g_staging.host = nullptr;
-        g_staging.cap = 0;
-        if (hipHostMalloc(&g_staging.host, bytes, hipHostMallocDefault) != hipSuccess)
+    if (sl.cap < bytes) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.cap = 0;
+        if (hipHostMalloc(&sl.host, bytes, hipHostMallocDefault) != hipSuccess)
             return fail(FSS_EDEVICE, "batch: pinned staging allocation failed");
-        g_staging.cap = bytes;
+        sl.cap = bytes;
     }
-    memcpy(g_staging.host, src, bytes);
-    if (hipMemcpyAsync(d_dst, g_staging.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipEventRecord(g_staging.done, s) != hipSuccess)
+    memcpy(sl.host, src, bytes);
+    if (hipMemcpyAsync(d_dst, sl.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(sl.done, s) != hipSuccess)
         return fail(FSS_EDEVICE, "batch: descriptor upload failed");
-    g_staging.pending = true;
+    sl.pending = true;
     return FSS_OK;
 }
 

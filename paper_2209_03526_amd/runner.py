@@ -91,8 +91,17 @@ class ChunkedRunner:
         if count > self.queue.capacity:
             self.queue = fss.Queue(max(count, 2 * self.queue.capacity), self.device)
 
-    def run(self, jobs):
-        """Evaluate and finish every job; returns the jobs (outputs in job.plan.out)."""
+    def _event(self):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.stream if isinstance(self.stream, torch.cuda.Stream) else torch.cuda.current_stream())
+        return e
+
+    def run(self, jobs, timings=None):
+        """Evaluate and finish every job; returns the jobs (outputs in job.plan.out).
+
+        timings: optional list that receives ("keygen" | "eval", start event,
+        end event) per wave (HIP events on the launch stream; the stream must
+        be None or a torch stream)."""
         for job in jobs:
             job.bits = []
             for p in job.preds:
@@ -124,8 +133,14 @@ class ChunkedRunner:
                 for b in range(2):
                     ev.append((b, kb, xh, job.bits[k][b][c0 // 32:]))
                 keep.append(kb)
+            if timings is not None:
+                e0 = self._event()
             fss.fss_keygen_batch(kg, self.queue, self.stream)
+            if timings is not None:
+                e1 = self._event()
             fss.fss_eval_batch(ev, self.queue, self.stream)
+            if timings is not None:
+                timings += [("keygen", e0, e1), ("eval", e1, self._event())]
             self.waves += 1
             done = []
             for qi, k, c0, n, kb in wave:

@@ -31,13 +31,18 @@ from .runner import KeyArena
 
 @dataclass
 class ResidentGraph:
-    """Both servers' shares of every column plus the public endpoints, on the device."""
+    """Both servers' shares of every column plus the public endpoints, on the
+    device.  Edge rows are stored sorted by (larger endpoint, row): the
+    candidate edges of a request over r vertices are then a prefix, whose
+    length comes from the host copy of the sorted larger endpoints, so a
+    request's edge tables are slices -- no gather and no device round trip."""
     n_vertices: int
     n_edges: int
-    src: torch.Tensor
+    src: torch.Tensor        # in edge order
     dst: torch.Tensor
     vshares: dict            # column -> (x0, x1) int32 tensors
-    eshares: dict
+    eshares: dict            # column -> (x0, x1), in edge order
+    edge_keys: np.ndarray = None    # host: sorted larger endpoints
 
 
 @dataclass
@@ -65,21 +70,20 @@ def prepare(req: Request, g: ResidentGraph, device, stream=None):
     """Candidate view, fresh dealer masks and opened values on the device."""
     q = req.query
     r_v = min(req.rows, g.n_vertices)
-    need_edges = q.n_qv > 1
-    if need_edges:
-        ok = torch.nonzero((g.src < r_v) & (g.dst < r_v)).flatten()[:req.rows]
-        erows = ok
-        n_e = int(erows.numel())
-        src, dst = g.src[erows].contiguous(), g.dst[erows].contiguous()
+    if q.n_qv > 1:
+        # the bound in the keys' own dtype: a Python int would make numpy
+        # convert the whole key array before searching
+        n_e = min(req.rows, int(np.searchsorted(g.edge_keys, g.edge_keys.dtype.type(r_v), side="left")))
+        src, dst = g.src[:n_e], g.dst[:n_e]
     else:
-        erows, n_e, src, dst = None, 0, None, None
+        n_e, src, dst = 0, None, None
     req.view = dict(n_vertices=r_v, n_edges=n_e, src=src, dst=dst)
     req.preds = []
     for k, p in enumerate(q.preds):
         on_edge = p.target >= q.n_qv
         rows = n_e if on_edge else r_v
         if on_edge:
-            x0, x1 = (t[erows] for t in g.eshares[p.column])
+            x0, x1 = (t[:n_e] for t in g.eshares[p.column])
         else:
             x0, x1 = (t[:r_v] for t in g.vshares[p.column])
         r = torch.empty(max(rows, 1), dtype=torch.int32, device=device)
@@ -94,9 +98,9 @@ def prepare(req: Request, g: ResidentGraph, device, stream=None):
 
 def memory_bound(req: Request) -> int:
     """Device bytes a request holds while admitted (keys excluded: they live
-    in the wave arena): candidate edge endpoints and columns, masks, opened
-    values, share bits and the plan workspace -- bounded with every table at
-    ``rows`` rows."""
+    in the wave arena): masks, opened values, share bits and the plan
+    workspace, bounded with every table at ``rows`` rows (plus a margin for
+    edge tables, which are slices of the resident graph)."""
     rows = req.rows
     npred = len(req.query.preds)
     per_table = 8 * rows + 16 * _words(rows)
@@ -221,12 +225,17 @@ class ServedPath:
 
 
 class PlainPath:
-    """One request at a time: masks, open, per-predicate keygen, match_query."""
+    """One request at a time: masks, open, per-predicate keygen, match_query.
 
-    def __init__(self, graph: ResidentGraph, device=None, stream=None):
+    sync=True waits for each request's results before taking the next (a
+    server that answers one query before it starts another); sync=False only
+    enqueues, so the host prepares request i+1 while the GPU runs request i."""
+
+    def __init__(self, graph: ResidentGraph, device=None, stream=None, sync: bool = False):
         self.g = graph
         self.device = device or torch.device("cuda")
         self.stream = stream or torch.cuda.current_stream()
+        self.sync = sync
 
     def run(self, requests, clock_start_event, t0):
         for req in requests:
@@ -244,6 +253,8 @@ class PlainPath:
             req.done_event = torch.cuda.Event(enable_timing=True)
             req.done_event.record(self.stream)
             _drop_intermediates(req)
+            if self.sync:
+                req.done_event.synchronize()
         torch.cuda.synchronize()
         for req in requests:
             req.latency_ms = clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival
@@ -277,9 +288,14 @@ def summarize(requests, wall_s: float) -> dict:
 
 
 def resident_graph(n_vertices, n_edges, src, dst, vshares, eshares, device) -> ResidentGraph:
-    """Upload both servers' column shares and the public endpoints (numpy uint32)."""
+    """Upload both servers' column shares and the public endpoints (numpy
+    uint32), edge rows sorted by (larger endpoint, row) -- the order of
+    ``synth.Graph.edge_order``."""
     def T(a):
         return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)
-    return ResidentGraph(n_vertices, n_edges, T(src), T(dst),
+    key = np.maximum(src, dst)
+    order = np.argsort(key, kind="stable")
+    return ResidentGraph(n_vertices, n_edges, T(src[order]), T(dst[order]),
                          {k: (T(v[0]), T(v[1])) for k, v in vshares.items()},
-                         {k: (T(v[0]), T(v[1])) for k, v in eshares.items()})
+                         {k: (T(v[0][order]), T(v[1][order])) for k, v in eshares.items()},
+                         np.ascontiguousarray(key[order]))

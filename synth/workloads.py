@@ -51,10 +51,21 @@ class Graph:
     dst: np.ndarray
     vcols: dict
     ecols: dict
+    _order: object = field(default=None, repr=False, compare=False)
 
     @property
     def n_edges(self) -> int:
         return int(self.src.size)
+
+    def edge_order(self) -> tuple:
+        """Edge rows sorted by (larger endpoint, row), and the sorted larger
+        endpoints: the edges whose endpoints are both below r are the first
+        searchsorted(keys, r) rows of this order (computed once per graph)."""
+        if self._order is None:
+            key = np.maximum(self.src, self.dst)
+            order = np.argsort(key, kind="stable")
+            self._order = (order, key[order])
+        return self._order
 
 
 def rows_of_target(graph: Graph, query: Query, target: int) -> int:
@@ -285,11 +296,14 @@ def config3(seed: int = 3, n_vertices: int = 1 << 22, n_edges: int = 1 << 25) ->
 
 
 def candidate_view(graph: Graph, rows: int) -> tuple:
-    """A query's candidate tables over ``rows`` rows: vertices [0, rows) and the
-    first ``rows`` edge rows whose endpoints are both below ``rows`` (a public
-    filter).  Returns (view graph, edge rows of the view in the full table)."""
+    """A query's candidate tables over ``rows`` rows: vertices [0, rows) and,
+    among the edges whose endpoints are both below ``rows`` (a public filter),
+    the first ``rows`` in the order of ``Graph.edge_order`` -- so every
+    candidate edge table is a prefix of one fixed order of the edge table.
+    Returns (view graph, edge rows of the view in the full table)."""
     r = min(rows, graph.n_vertices)
-    erows = np.flatnonzero((graph.src < r) & (graph.dst < r))[:rows]
+    order, keys = graph.edge_order()
+    erows = order[:min(rows, int(np.searchsorted(keys, keys.dtype.type(r), side="left")))]
     view = Graph(r, graph.src[erows], graph.dst[erows], {k: v[:r] for k, v in graph.vcols.items()},
                  {k: v[erows] for k, v in graph.ecols.items()})
     return view, erows

@@ -124,3 +124,41 @@ def test_chunk_larger_than_key_arena_is_rejected(fake):
                               stream=object())
     with pytest.raises(ValueError, match="key arena"):
         _run(path, _reqs([0.0]))
+
+
+def test_resident_edge_prefix_is_the_candidate_view(monkeypatch):
+    """A request's edge tables on the served path (prefix slices of the
+    resident graph) are the candidate view's edges, in the same order, with
+    the same shares; the prefix length is found without converting the key
+    array (a search bound of another dtype would copy all of it per request)."""
+    import numpy as np
+    import synth
+    calls = []
+    f = _fake_fss(calls)
+    f.fss_dealer_masks = lambda *a, **k: None
+    f.fss_mask_open = lambda x0, x1, r, xh, s=None: calls.append(("open", x0.clone(), x1.clone()))
+    monkeypatch.setattr(serving, "fss", f)
+    real_search = np.searchsorted
+
+    def search(a, v, side="left"):
+        # a Python int bound makes numpy convert the whole key array first
+        assert isinstance(v, np.generic) and v.dtype == a.dtype, "bound must be in the keys' dtype"
+        return real_search(a, v, side=side)
+
+    nv, ne = 1 << 12, 1 << 20
+    src, dst = synth.chung_lu_graph(5, nv, ne)
+    g = synth.Graph(nv, src, dst, {}, {"w": np.arange(ne, dtype=np.uint32)})
+    esh = {"w": (np.arange(ne, dtype=np.uint32), np.zeros(ne, np.uint32))}
+    rg = serving.resident_graph(nv, ne, src, dst, {}, esh, "cpu")
+    monkeypatch.setattr(np, "searchsorted", search)
+    for rows in (0, 1, 100, 3000, 1 << 12, 1 << 16):
+        q = types.SimpleNamespace(query_id=1, n_qv=2, preds=[synth.Pred(2, "eq", "w", a=3)])
+        req = serving.Request(0, 0.0, q, rows, 7)
+        calls.clear()
+        serving.prepare(req, rg, "cpu")
+        view, erows = synth.candidate_view(g, rows)
+        assert req.view["n_edges"] == view.n_edges
+        if view.n_edges:
+            assert np.array_equal(req.view["src"].numpy().view(np.uint32), view.src)
+            assert np.array_equal(req.view["dst"].numpy().view(np.uint32), view.dst)
+            assert np.array_equal(calls[0][1].numpy().view(np.uint32), erows.astype(np.uint32))
