@@ -11,7 +11,8 @@
  *   - Buffers named d_* are DEVICE pointers owned by the caller.  The library
  *     never allocates or frees caller memory; it holds no device memory of its
  *     own except constant tables (batch calls stage their descriptors through
- *     one pinned host buffer it owns).
+ *     a ring of eight pinned host buffers it owns; a buffer is reused once the
+ *     copy that last read it has executed, which may make a batch call wait).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls validate
  *     their arguments synchronously, enqueue kernels on `stream` and return
  *     without waiting.  A negative return means nothing was enqueued;
@@ -217,10 +218,10 @@ int match_query(const match_plan* plan, int32_t party_mask, void* stream);
  *
  * d_queue: caller-provided device memory of fss_queue_workspace_bytes(count)
  * bytes (256-aligned) holding the queue counter and the descriptors.  The
- * descriptors are staged through a pinned host buffer owned by the library
- * (one per process, reused after its previous upload has completed).  Batch
- * calls on one stream run in order; batches that share a d_queue must be on
- * one stream.
+ * descriptors are staged through the library's ring of pinned host buffers
+ * (see the conventions above).  Batch calls on one stream run in order;
+ * batches that share a d_queue must be on one stream.  A keygen batch runs as
+ * one launch per key kind present (ranges first), each over its own tiles.
  *
  * fss_keygen_batch (dealer keygen for many predicates / queries): each request is one
  * fss_keygen call (same meaning, same checks).
