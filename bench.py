@@ -113,7 +113,7 @@ def parse():
     ap.add_argument("--log-rows", type=int, default=LOG_ROWS)
     ap.add_argument("--cpu-sample-log-rows", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="vertex-filter", choices=["vertex-filter", "batch64", "serve"])
+    ap.add_argument("--workload", default="vertex-filter", choices=["vertex-filter", "batch64", "serve", "next"])
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="serve: arrival window per rate")
     ap.add_argument("--serve-max", type=int, default=600, help="serve: at most this many requests per rate")
@@ -139,6 +139,8 @@ def main():
         return run_batch64(args, torch, fss, dev)
     if args.workload == "serve":
         return run_serve(args, torch, fss, dev)
+    if args.workload == "next":
+        return run_next(args, torch, fss, dev)
     n = 1 << args.log_rows
     log(f"generating {n} rows")
     graph, query = synth.config2(2, n=n)
@@ -497,6 +499,121 @@ def run_serve(args, torch, fss, dev):
            "paths": {"served": "continuous batching, admission by memory (64 GB: 48 GB key arena + intermediates)",
                      "plain": "one request at a time, results awaited before the next request starts",
                      "plain_pipelined": "one request at a time on one stream, host runs ahead (no wait)"}}
+    print(json.dumps(out), flush=True)
+
+
+HBM_BYTES_PER_S = 8e12
+
+
+def run_next(args, torch, fss, dev):
+    """The rows built beyond the hot path, each timed alone with HIP events on
+    the launch stream (median of 5 after one warm-up) against its floor: the
+    larger of its algorithmic HBM bytes at 8 TB/s and its AES blocks at the
+    single-block issue floor (160 LDS reads per block, 32 per clock per CU)."""
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device=dev)
+    g.manual_seed(SEED)
+
+    def rnd(*shape):
+        return torch.randint(-2**31, 2**31 - 1, shape, dtype=torch.int32, device=dev, generator=g)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(5):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    def row(name, ms, hbm_bytes, aes_blocks, what):
+        t = ms / 1e3
+        t_hbm = hbm_bytes / HBM_BYTES_PER_S
+        t_aes = aes_floor(aes_blocks, 0)["t_floor"]
+        out = {"ms": round(ms, 4), "hbm_gb": round(hbm_bytes / 1e9, 4), "aes_mblocks": round(aes_blocks / 1e6, 3),
+               "hbm_gb_per_s": round(hbm_bytes / t / 1e9, 1), "aes_gblocks_per_s": round(aes_blocks / t / 1e9, 2),
+               "binding": "hbm" if t_hbm >= t_aes else "aes", "frac_of_floor": round(max(t_hbm, t_aes) / t, 4),
+               "work": what}
+        log(f"{name}: {out}")
+        return out
+
+    res = {}
+    # secEval over one-hot RSS attributes: 2^20 candidates, a 12-bit attribute (4,096 positions)
+    ncand, npos = 1 << 20, 4096
+    nwp = npos // 32
+    kb = fss.KeyBatch(fss.RANGE, 12, 3, dev)
+    zero = torch.zeros(3, dtype=torch.int32, device=dev)
+    fss.fss_keygen(SEED, 7, 0, 100, 3000, zero, kb)
+    evals = [torch.empty(nwp, dtype=torch.int32, device=dev) for _ in range(6)]
+    sh = [rnd(nwp * ncand) for _ in range(3)]
+    outs = [torch.empty((ncand + 31) // 32, dtype=torch.int32, device=dev) for _ in range(3)]
+    terms = [((0, 0), (0, 1)), ((1, 1), (0, 2)), ((1, 2), (1, 0))]     # (party, replica) of each server's two keys
+
+    def sec_eval():
+        for i, ((pa, ra), (pb, rb)) in enumerate(terms):
+            fss.fss_eval_all(pa, kb, ra, npos, evals[2 * i], stream)
+            fss.fss_eval_all(pb, kb, rb, npos, evals[2 * i + 1], stream)
+            fss.rss_sec_eval(ncand, npos, evals[2 * i], evals[2 * i + 1], sh[i], sh[(i + 1) % 3], outs[i], stream)
+
+    res["sec_eval"] = row("sec_eval", timed(sec_eval), 3 * (2 * 4 * nwp * ncand + ncand // 8),
+                          6 * npos * 2 * 12, f"3 servers x (2 full-domain range evals over {npos} positions + "
+                          f"AND-parity over {ncand} candidates x {npos}-bit one-hot shares)")
+    del sh, outs
+    # RSS AND and re-share of 2^30 shared bits (2^25 words per share)
+    nrows = 1 << 30
+    nw = nrows // 32
+    x3, y3, z3 = [rnd(nw) for _ in range(3)], [rnd(nw) for _ in range(3)], [rnd(nw) for _ in range(3)]
+    keys = [11, 22, 33]
+    res["rss_and"] = row("rss_and", timed(lambda: fss.rss_and(nrows, x3, y3, keys, 5, z3, stream)),
+                         9 * 4 * nw, 3 * nw / 4, f"{nrows} bits: 6 shares read, 3 written, 3 PRF streams")
+    res["rss_reshare"] = row("rss_reshare", timed(lambda: fss.rss_reshare(nrows, x3, keys, 6, z3, stream)),
+                             6 * 4 * nw, 3 * nw / 4, f"{nrows} bits: 3 shares read, 3 written, 3 PRF streams")
+    del x3, y3, z3
+    # secShuffle of 2^22 records of 64 B, and the fetches
+    nrec, nwords = 1 << 22, 16
+    tbytes = nrec * nwords * 4
+    d3 = [rnd(nrec * nwords) for _ in range(3)]
+    o3 = [torch.empty(nrec * nwords, dtype=torch.int32, device=dev) for _ in range(3)]
+    seeds = [101, 202, 303]
+    work = {}
+
+    def shuffle():
+        work["w"] = fss.rss_shuffle(nrec, nwords, d3, seeds, o3, stream)
+
+    res["rss_shuffle"] = row("rss_shuffle", timed(shuffle), 14 * tbytes, 5 * tbytes / 16 + 3 * nrec,
+                             f"{nrec} records x {nwords * 4} B: 3 shares in, messages X1 Y1 C1 C2 written and read, "
+                             "3 shares out; AES for 5 mask tables and 3 permutations' keys (sorts not counted)")
+    xb = [rnd((nrec + 31) // 32) for _ in range(3)]
+    f3 = [torch.empty(nwords, dtype=torch.int32, device=dev) for _ in range(3)]
+    res["rss_fetch_unique"] = row("rss_fetch_unique",
+                                  timed(lambda: fss.rss_fetch_unique(nrec, nwords, xb, d3, f3, stream)),
+                                  3 * tbytes + 3 * nrec // 8, 0,
+                                  f"selection product over {nrec} candidates x {nwords * 4} B, 3 shares")
+    rows_out = torch.empty(nrec, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def fetch_many():
+        work["w"] = fss.rss_fetch_many(nrec, nwords, d3, seeds, o3, rows_out, count, stream)
+
+    res["rss_fetch_many"] = row("rss_fetch_many", timed(fetch_many), 14 * tbytes + 3 * tbytes // 2,
+                                5 * tbytes / 16 + 3 * nrec,
+                                f"shuffle of {nrec} records (bit column + {(nwords - 1) * 4} B), open, compact "
+                                "(about half kept)")
+
+    def compact():
+        work["w"] = fss.rss_compact_valid(nrec, nwords, d3, seeds, o3, rows_out, count, stream)
+
+    res["rss_compact_valid"] = row("rss_compact_valid", timed(compact), 14 * tbytes + 3 * tbytes // 2,
+                                   5 * tbytes / 16 + 3 * nrec,
+                                   f"secAccess filter: shuffle {nrec} records of {nwords * 4} B, open parity, compact")
+    out = {"metric": "next rows: time per call and fraction of the HBM / AES floor", "value": None, "unit": "ms",
+           "n_gpus": 1, "rows": res, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "next: secEval 2^20 x 4096, RSS 2^30 bits, shuffle/fetch 2^22 x 64 B"}}
     print(json.dumps(out), flush=True)
 
 
