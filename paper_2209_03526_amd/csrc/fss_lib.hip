@@ -498,9 +498,10 @@ __global__ __launch_bounds__(kBlock) void k_masks(MaskArgs A) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tables.t0);
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= A.n) return;
-    A.r[i] = rng_block(A.rk, 2, 0, A.query, A.pred, A.row_offset + (uint32_t)i, tab, lane_offset()).x;
+    const LaneOff loff = lane_offset();
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < A.n; i += stride)
+        A.r[i] = rng_block(A.rk, 2, 0, A.query, A.pred, A.row_offset + (uint32_t)i, tab, loff).x;
 }
 
 struct TripleArgs {
@@ -512,28 +513,31 @@ struct TripleArgs {
     uint32_t and_id;
 };
 
-// Thread m makes triple words 4m .. 4m+3 from stream blocks 5m .. 5m+4.
+// Work item m makes triple words 4m .. 4m+3 from stream blocks 5m .. 5m+4.
 __global__ __launch_bounds__(kBlock) void k_triples(TripleArgs A) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tables.t0);
     __syncthreads();
-    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (4 * m >= A.nwords) return;
     const LaneOff loff = lane_offset();
-    uint32_t R[20];
+    const uint64_t groups = (A.nwords + 3) / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x; m < groups; m += stride) {
+        uint32_t R[20];
 #pragma unroll
-    for (int q = 0; q < 5; q++) {
-        const uint4 b = rng_block(A.rk, 4, 0, A.query, A.and_id, (uint32_t)(5 * m + q), tab, loff);
-        R[4 * q + 0] = b.x; R[4 * q + 1] = b.y; R[4 * q + 2] = b.z; R[4 * q + 3] = b.w;
-    }
+        for (int q = 0; q < 5; q++) {
+            uint4 b = rng_block(A.rk, 4, 0, A.query, A.and_id, (uint32_t)(5 * m + q), tab, loff);
+            pin_in_vgprs(b);        // one block at a time
+            R[4 * q + 0] = b.x; R[4 * q + 1] = b.y; R[4 * q + 2] = b.z; R[4 * q + 3] = b.w;
+        }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint64_t w = 4 * m + q;
-        if (w < A.nwords) {
-            const uint32_t a0 = R[5 * q], a1 = R[5 * q + 1], b0 = R[5 * q + 2], b1 = R[5 * q + 3];
-            const uint32_t c0 = R[5 * q + 4];
-            A.t0[w] = a0; A.t0[A.nwords + w] = b0; A.t0[2 * A.nwords + w] = c0;
-            A.t1[w] = a1; A.t1[A.nwords + w] = b1; A.t1[2 * A.nwords + w] = ((a0 ^ a1) & (b0 ^ b1)) ^ c0;
+        for (int q = 0; q < 4; q++) {
+            const uint64_t w = 4 * m + q;
+            if (w < A.nwords) {
+                const uint32_t a0 = R[5 * q], a1 = R[5 * q + 1], b0 = R[5 * q + 2], b1 = R[5 * q + 3];
+                const uint32_t c0 = R[5 * q + 4];
+                A.t0[w] = a0; A.t0[A.nwords + w] = b0; A.t0[2 * A.nwords + w] = c0;
+                A.t1[w] = a1; A.t1[A.nwords + w] = b1; A.t1[2 * A.nwords + w] = ((a0 ^ a1) & (b0 ^ b1)) ^ c0;
+            }
         }
     }
 }
@@ -672,6 +676,7 @@ struct RssArgs {
     uint64_t nrows;
     uint64_t nwords;
     uint32_t counter;
+    uint32_t vec;           // every share buffer 16-byte aligned: 16-byte loads / stores
 };
 
 // Thread m owns words 4m .. 4m+3.  For the AND, party P_i first forms
@@ -681,6 +686,9 @@ __global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tables.t0);
     __syncthreads();
+    // One group of 4 words per thread: with no loop around them, the three
+    // per-party key schedules are read from the kernel arguments where each
+    // block needs them instead of being held in scalar registers together.
     const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (4 * m >= A.nwords) return;
     const LaneOff loff = lane_offset();
@@ -688,6 +696,26 @@ __global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
 #pragma unroll
     for (int i = 0; i < 3; i++)
         f[i] = aes128_encrypt(make_uint4(5u, A.counter, 0u, (uint32_t)m), ArgKey{A.prf[i]}, tab, loff);
+    if (A.vec && 4 * m + 4 <= A.nwords) {
+        // four whole words: 16-byte loads and stores
+        const uint32_t pm[4] = {pad_mask(4 * m, A.nrows), pad_mask(4 * m + 1, A.nrows), pad_mask(4 * m + 2, A.nrows),
+                                pad_mask(4 * m + 3, A.nrows)};
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int nx = (i + 1) % 3, pv = (i + 2) % 3;
+            const uint4 xi = ((const uint4*)A.x[i])[m];
+            uint4 z = xi;
+            if (A.y[0]) {
+                const uint4 xn = ((const uint4*)A.x[nx])[m];
+                const uint4 yi = ((const uint4*)A.y[i])[m], yn = ((const uint4*)A.y[nx])[m];
+                z = make_uint4((xi.x & yi.x) ^ (xi.x & yn.x) ^ (xn.x & yi.x), (xi.y & yi.y) ^ (xi.y & yn.y) ^ (xn.y & yi.y),
+                               (xi.z & yi.z) ^ (xi.z & yn.z) ^ (xn.z & yi.z), (xi.w & yi.w) ^ (xi.w & yn.w) ^ (xn.w & yi.w));
+            }
+            z = xor4(xor4(z, f[i]), f[pv]);
+            ((uint4*)A.z[i])[m] = make_uint4(z.x & pm[0], z.y & pm[1], z.z & pm[2], z.w & pm[3]);
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const uint64_t w = 4 * m + q;
@@ -734,6 +762,27 @@ uint64_t key_bytes(int32_t kind, uint32_t nbits) {
 }
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Workgroups of a grid-stride AES kernel over `items` work items: two per CU
+// at most (what the LDS holds), so each fills its 64 KiB tables once and then
+// loops over many items.
+unsigned aes_grid(uint64_t items) {
+    const uint64_t need = (items + kBlock - 1) / kBlock;
+    const uint64_t cap = 2ull * (uint64_t)device_cus();
+    return (unsigned)(need < 1 ? 1 : (need < cap ? need : cap));
+}
 
 unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
     uint64_t g = (n + block - 1) / block;
@@ -801,8 +850,7 @@ int launch_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t n
     A.nwords = nwords;
     A.query = query_id;
     A.and_id = and_id;
-    const uint64_t threads = (nwords + 3) / 4;
-    hipLaunchKernelGGL(k_triples, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, A);
+    hipLaunchKernelGGL(k_triples, dim3(aes_grid((nwords + 3) / 4)), dim3(kBlock), 0, stream, A);
     return check_launch("k_triples");
 }
 
@@ -880,7 +928,7 @@ int fss_dealer_masks(uint64_t seed, uint32_t query_id, uint32_t pred_id, uint32_
     A.query = query_id;
     A.pred = pred_id;
     A.row_offset = row_offset;
-    hipLaunchKernelGGL(k_masks, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, A);
+    hipLaunchKernelGGL(k_masks, dim3(aes_grid(n)), dim3(kBlock), 0, (hipStream_t)stream, A);
     return check_launch("k_masks");
 }
 
@@ -1134,19 +1182,6 @@ struct Tuning {
 };
 Tuning g_tuning;
 
-int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
-    return cus;
-}
-
-// Descriptors reach the device through a pinned staging buffer owned by the
-// library; a buffer is reused only after its previous upload completed.
 // Descriptor uploads go through a ring of pinned host slots.  A slot is
 // rewritten only after the copy that last read it has executed (its event),
 // so the host can run several batch calls ahead of the stream.  Device-side
@@ -1295,9 +1330,11 @@ static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* c
     A.nrows = nrows;
     A.nwords = (nrows + 31) / 32;
     A.counter = counter;
-    const uint64_t threads = (A.nwords + 3) / 4;
-    hipLaunchKernelGGL(k_rss, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       (hipStream_t)stream, A);
+    A.vec = 1;
+    for (int i = 0; i < 3; i++)
+        if (!aligned16(A.x[i]) || !aligned16(A.y[i]) || !aligned16(A.z[i])) A.vec = 0;
+    const uint64_t groups = (A.nwords + 3) / 4;
+    hipLaunchKernelGGL(k_rss, dim3((unsigned)((groups + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, A);
     return check_launch("k_rss");
 }
 

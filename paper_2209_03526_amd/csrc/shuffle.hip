@@ -27,21 +27,44 @@ __constant__ AesTables g_tab = kTables;
 enum { kT12 = 1, kR2 = 2, kT23 = 3, kT31 = 4, kR1 = 5 };
 enum { kP12 = 0, kP23 = 1, kP31 = 2 };
 
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }   // NULL counts as aligned
+
+// Number of workgroups for a grid-stride AES kernel: enough to fill every CU
+// twice, never more than the work needs.  A workgroup fills its 64 KiB LDS
+// tables once and then loops, so the fill is spread over many blocks.
+unsigned aes_grid(uint64_t items) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    const uint64_t need = (items + kBlock - 1) / kBlock;
+    const uint64_t cap = 2ull * (uint64_t)cus;
+    return (unsigned)(need < 1 ? 1 : (need < cap ? need : cap));
+}
+
 // Mask table `table` of the pair seed: word k = r*W + w is word (k mod 4) of
-// block (6, table, W, 0, k div 4).  Thread m writes words 4m .. 4m+3.
+// block (6, table, W, 0, k div 4).  Block m gives words 4m .. 4m+3.
 __global__ __launch_bounds__(kBlock) void k_mask_table(RoundKeys rk, uint32_t table, uint32_t nwords, uint64_t total,
-                                                      uint32_t* __restrict__ out) {
+                                                      uint32_t vec, uint32_t* __restrict__ out) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tab.t0);
     __syncthreads();
-    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (4 * m >= total) return;
-    const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, (uint32_t)m), ArgKey{rk}, tab,
-                                   lane_offset());
-    const uint32_t v[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-        if (4 * m + q < total) out[4 * m + q] = v[q];
+    const LaneOff lo = lane_offset();
+    const uint64_t nblk = (total + 3) / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x; m < nblk; m += stride) {
+        const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, (uint32_t)m), ArgKey{rk}, tab, lo);
+        if (vec && 4 * m + 4 <= total) {
+            *(uint4*)(out + 4 * m) = b;
+        } else {
+            const uint32_t v[4] = {b.x, b.y, b.z, b.w};
+            for (int q = 0; q < 4; q++)
+                if (4 * m + q < total) out[4 * m + q] = v[q];
+        }
+    }
 }
 
 // Sort keys of permutation p: row r -> words 0-1 of block (6, 16 + p, 0, 0, r).
@@ -50,24 +73,41 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, 
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tab.t0);
     __syncthreads();
-    const uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= nrows) return;
-    const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab,
-                                   lane_offset());
-    keys[r] = (uint64_t)b.x | ((uint64_t)b.y << 32);
-    idx[r] = (uint32_t)r;
+    const LaneOff lo = lane_offset();
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += stride) {
+        const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab, lo);
+        keys[r] = (uint64_t)b.x | ((uint64_t)b.y << 32);
+        idx[r] = (uint32_t)r;
+    }
 }
 
-// out[i] = a[p] ^ b[p] ^ c[p] ^ post[i], p = perm[i] (absent tables skipped);
-// one thread per output word.
-__global__ void k_gather_xor(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ perm,
+// out[i] = a[p] ^ b[p] ^ c[p] ^ post[i], p = perm[i] (absent tables skipped).
+// With vec (record width a multiple of 4 words, every table 16-byte aligned)
+// one thread moves 4 words with 16-byte loads and stores, else one word; row
+// and word come from 32-bit division (rows < 2^31, checked by the callers).
+__global__ void k_gather_xor(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ perm,
                              const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                              const uint32_t* __restrict__ c, const uint32_t* __restrict__ post,
                              uint32_t* __restrict__ out) {
-    const uint64_t total = nrows * nwords;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (vec) {
+        const uint32_t q = nwords >> 2;                 // uint4 per record
+        const uint64_t total = nrows * q;
+        for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+            const uint32_t i = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)i * q);
+            const uint64_t src = (uint64_t)perm[i] * q + w;
+            uint4 v = ((const uint4*)a)[src];
+            if (b) v = xor4(v, ((const uint4*)b)[src]);
+            if (c) v = xor4(v, ((const uint4*)c)[src]);
+            if (post) v = xor4(v, ((const uint4*)post)[k]);
+            ((uint4*)out)[k] = v;
+        }
+        return;
+    }
+    const uint64_t total = nrows * nwords;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
-        const uint64_t i = k / nwords, w = k % nwords;
+        const uint32_t i = (uint32_t)(k / nwords), w = (uint32_t)(k - (uint64_t)i * nwords);
         const uint64_t src = (uint64_t)perm[i] * nwords + w;
         uint32_t v = a[src];
         if (b) v ^= b[src];
@@ -85,37 +125,59 @@ __global__ void k_xor2(uint64_t total, const uint32_t* __restrict__ a, const uin
 
 // Case I: XOR over candidates of (r_i & m_i) ^ (r_j & m_i) ^ (r_i & m_j), the
 // three-out-of-three products of record shares with the predicate-bit
-// shares, j = i + 1.  XOR is order-free, so per-block partials are combined
-// with atomicXor into the zeroed output.
-__global__ void k_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* __restrict__ x0,
-                               const uint32_t* __restrict__ x1, const uint32_t* __restrict__ x2,
-                               const uint32_t* __restrict__ r0, const uint32_t* __restrict__ r1,
-                               const uint32_t* __restrict__ r2, uint32_t* __restrict__ out0,
-                               uint32_t* __restrict__ out1, uint32_t* __restrict__ out2) {
-    const uint32_t w = blockIdx.y;
+// shares, j = i + 1.  The block walks its candidates record by record with
+// the words of a tile of each record on consecutive threads (coalesced), each
+// thread keeping one word's partial; the partials of equal words meet in LDS
+// and one atomicXor per word and share goes to the zeroed output (XOR is
+// order-free, so the result does not depend on the order).
+constexpr int kFetchBlock = 256;
+
+__global__ __launch_bounds__(kFetchBlock) void k_fetch_unique(
+    uint64_t ncand, uint32_t nwords, const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1,
+    const uint32_t* __restrict__ x2, const uint32_t* __restrict__ r0, const uint32_t* __restrict__ r1,
+    const uint32_t* __restrict__ r2, uint32_t* __restrict__ out0, uint32_t* __restrict__ out1,
+    uint32_t* __restrict__ out2) {
+    __shared__ uint32_t part[3][kFetchBlock];
     const uint32_t* xs[3] = {x0, x1, x2};
     const uint32_t* rs[3] = {r0, r1, r2};
     uint32_t* outs[3] = {out0, out1, out2};
-    uint32_t acc[3] = {0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand; c += stride) {
-        uint32_t m[3], rv[3];
+    // this block's candidates
+    const uint64_t per = (ncand + gridDim.x - 1) / gridDim.x;
+    const uint64_t c0 = (uint64_t)blockIdx.x * per;
+    const uint64_t c1 = c0 + per < ncand ? c0 + per : ncand;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t w0 = 0; w0 < nwords; w0 += kFetchBlock) {
+        const uint32_t tw = nwords - w0 < kFetchBlock ? nwords - w0 : kFetchBlock;   // words in this tile
+        const uint32_t lanes = kFetchBlock / tw;                                       // candidates per pass
+        const uint32_t w = t % tw, g = t / tw;
+        uint32_t acc[3] = {0, 0, 0};
+        if (g < lanes) {
+            for (uint64_t c = c0 + g; c < c1; c += lanes) {
+                uint32_t m[3], rv[3];
 #pragma unroll
-        for (int i = 0; i < 3; i++) {
-            m[i] = 0u - ((xs[i][c >> 5] >> (c & 31)) & 1u);
-            rv[i] = rs[i][c * nwords + w];
+                for (int i = 0; i < 3; i++) {
+                    m[i] = 0u - ((xs[i][c >> 5] >> (c & 31)) & 1u);
+                    rv[i] = rs[i][c * nwords + w0 + w];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    const int j = (i + 1) % 3;
+                    acc[i] ^= (rv[i] & m[i]) ^ (rv[j] & m[i]) ^ (rv[i] & m[j]);
+                }
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 3; i++) {
-            const int j = (i + 1) % 3;
-            acc[i] ^= (rv[i] & m[i]) ^ (rv[j] & m[i]) ^ (rv[i] & m[j]);
-        }
-    }
+        for (int i = 0; i < 3; i++) part[i][t] = acc[i];
+        __syncthreads();
+        if (t < tw) {
 #pragma unroll
-    for (int i = 0; i < 3; i++) {
-        uint32_t v = acc[i];
-        for (int off = 32; off > 0; off >>= 1) v ^= __shfl_xor(v, off);
-        if ((threadIdx.x & 63) == 0 && v) atomicXor(&outs[i][w], v);
+            for (int i = 0; i < 3; i++) {
+                uint32_t v = 0;
+                for (uint32_t k = 0; k < lanes; k++) v ^= part[i][k * tw + t];
+                if (v) atomicXor(&outs[i][w0 + t], v);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -133,33 +195,47 @@ __global__ void k_open_flags(uint64_t nrows, uint32_t nwords, const uint32_t* __
 }
 
 // secAccess filter: flag of shuffled record i = parity of all bits of R1 ^ R2 ^ R3
-// (1 for a one-hot ID, 0 for a dummy all-zero ID).
-__global__ void k_open_parity(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ a,
+// (1 for a one-hot ID, 0 for a dummy all-zero ID).  With vec (width a
+// multiple of 4 words, tables 16-byte aligned) the loads are 16 bytes.
+__global__ void k_open_parity(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ a,
                               const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
                               uint32_t* __restrict__ flags) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
     uint32_t acc = 0;
-    for (uint32_t w = 0; w < nwords; w++) acc ^= a[i * nwords + w] ^ b[i * nwords + w] ^ c[i * nwords + w];
+    if (vec) {
+        const uint64_t base = i * (nwords >> 2);
+        for (uint32_t w = 0; w < (nwords >> 2); w++) {
+            const uint4 v = xor4(xor4(((const uint4*)a)[base + w], ((const uint4*)b)[base + w]),
+                                 ((const uint4*)c)[base + w]);
+            acc ^= v.x ^ v.y ^ v.z ^ v.w;
+        }
+    } else {
+        for (uint32_t w = 0; w < nwords; w++) acc ^= a[i * nwords + w] ^ b[i * nwords + w] ^ c[i * nwords + w];
+    }
     flags[i] = __builtin_popcount(acc) & 1u;
 }
 
-// Copy the kept records (words first..W-1) of the three share tables to their slots.
+// Copy the kept records (words first..W-1) of the three share tables to their
+// slots: one thread per (record, word) so that reads and writes are coalesced.
 __global__ void k_compact(uint64_t nrows, uint32_t nwords, uint32_t first, const uint32_t* __restrict__ flags,
                           const uint32_t* __restrict__ pos, const uint32_t* __restrict__ s0,
                           const uint32_t* __restrict__ s1, const uint32_t* __restrict__ s2,
                           uint32_t* __restrict__ o0, uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
                           uint32_t* __restrict__ rows_out) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows || !flags[i]) return;
-    const uint64_t d = pos[i];
     const uint32_t rw = nwords - first;
-    for (uint32_t w = 0; w < rw; w++) {
-        o0[d * rw + w] = s0[i * nwords + first + w];
-        o1[d * rw + w] = s1[i * nwords + first + w];
-        o2[d * rw + w] = s2[i * nwords + first + w];
+    const uint64_t total = nrows * rw;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+        const uint32_t i = (uint32_t)(k / rw), w = (uint32_t)(k - (uint64_t)i * rw);
+        if (!flags[i]) continue;
+        const uint64_t d = pos[i];
+        const uint64_t src = (uint64_t)i * nwords + first + w;
+        o0[d * rw + w] = s0[src];
+        o1[d * rw + w] = s1[src];
+        o2[d * rw + w] = s2[src];
+        if (w == 0) rows_out[d] = i;
     }
-    rows_out[d] = (uint32_t)i;
 }
 
 // count of kept records = last exclusive prefix + last flag
@@ -207,8 +283,7 @@ uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
 // perm = stable argsort of the pair seed's row keys.
 int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, uint64_t* keys, uint64_t* keys_sorted,
               uint32_t* idx, uint32_t* perm, void* temp, size_t temp_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)((nrows + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, rk, p, nrows,
-                       keys, idx);
+    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, keys, idx);
     int rc = check_launch("k_perm_keys");
     if (rc) return rc;
     if (hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, perm, (int)nrows, 0, 64, s) !=
@@ -219,16 +294,18 @@ int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, uint64_t* keys, u
 
 int mask(const RoundKeys& rk, uint32_t table, uint64_t nrows, uint32_t nwords, uint32_t* out, hipStream_t s) {
     const uint64_t total = nrows * nwords;
-    const uint64_t threads = (total + 3) / 4;
-    hipLaunchKernelGGL(k_mask_table, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, rk, table,
-                       nwords, total, out);
+    const uint64_t blocks = (total + 3) / 4;
+    hipLaunchKernelGGL(k_mask_table, dim3(aes_grid(blocks)), dim3(kBlock), 0, s, rk, table, nwords, total,
+                       (uint32_t)aligned16(out), out);
     return check_launch("k_mask_table");
 }
 
 int gather(uint64_t nrows, uint32_t nwords, const uint32_t* perm, const uint32_t* a, const uint32_t* b,
            const uint32_t* c, const uint32_t* post, uint32_t* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_xor, dim3(grid_of(nrows * nwords, 256)), dim3(256), 0, s, nrows, nwords, perm, a, b, c,
-                       post, out);
+    const bool vec = (nwords & 3u) == 0 && aligned16(a) && aligned16(b) && aligned16(c) && aligned16(post) &&
+                     aligned16(out);
+    hipLaunchKernelGGL(k_gather_xor, dim3(grid_of(vec ? nrows * nwords / 4 : nrows * nwords, 256)), dim3(256), 0, s,
+                       nrows, nwords, (uint32_t)vec, perm, a, b, c, post, out);
     return check_launch("k_gather_xor");
 }
 
@@ -318,8 +395,9 @@ int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[
         if (rc) return rc;
     }
     if (ncand == 0) return FSS_OK;
-    dim3 grid(grid_of(ncand, 256) > 1024 ? 1024 : grid_of(ncand, 256), nwords);
-    hipLaunchKernelGGL(k_fetch_unique, grid, dim3(256), 0, s, ncand, nwords, d_x[0], d_x[1], d_x[2], d_rows[0],
+    // about 8 blocks per CU; each block takes a contiguous run of candidates
+    const unsigned grid = grid_of(ncand, kFetchBlock) > 2048 ? 2048 : grid_of(ncand, kFetchBlock);
+    hipLaunchKernelGGL(k_fetch_unique, dim3(grid), dim3(kFetchBlock), 0, s, ncand, nwords, d_x[0], d_x[1], d_x[2], d_rows[0],
                        d_rows[1], d_rows[2], d_out[0], d_out[1], d_out[2]);
     return check_launch("k_fetch_unique");
 }
@@ -364,6 +442,7 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     if (rc) return rc;
     if (parity)
         hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+                           (uint32_t)((nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2])),
                            sh[0], sh[1], sh[2], flags);
     else
         hipLaunchKernelGGL(k_open_flags, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
@@ -372,7 +451,7 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     if (rc) return rc;
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan, flags, pos, (int)ncand, s) != hipSuccess)
         return fail(FSS_EDEVICE, "%s: scan failed", who);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+    hipLaunchKernelGGL(k_compact, dim3(grid_of(ncand * (nwords - (parity ? 0u : 1u)), 256)), dim3(256), 0, s, ncand, nwords,
                        parity ? 0u : 1u, flags, pos, sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out);
     rc = check_launch("k_compact");
     if (rc) return rc;
