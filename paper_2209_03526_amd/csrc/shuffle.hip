@@ -5,9 +5,10 @@
 // Each pair of servers derives from its seed, with the counter-mode generator
 // (domain 6), its permutations (stable sort of one 64-bit key per row) and
 // mask tables (one AES block per four words); applying a permutation is the
-// row gather out[i] = in[perm[i]].  The sequence of Alg. 5 is kept message
-// by message (X1, Y1, C1, C2, R3), so each intermediate is what one server
-// computes and sends.
+// row gather out[i] = in[perm[i]].  The sequence of Alg. 5 is kept: X1, Y1
+// and C1 are stored as the messages one server computes and sends; a message
+// built with two permutations (X1, C2) is gathered through both in one pass,
+// and C2 is folded into CS2's R3 = C1 ^ C2 as it is formed.
 
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -117,10 +118,40 @@ __global__ void k_gather_xor(uint64_t nrows, uint32_t nwords, uint32_t vec, cons
     }
 }
 
-__global__ void k_xor2(uint64_t total, const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
-                       uint32_t* __restrict__ out) {
+// Two permutations in one pass: out[i] = A[q] ^ mid[p] ^ post[i] ^ post2[i]
+// with p = p_out[i], q = p_in[p] and A = a ^ b ^ c (absent tables skipped):
+// pi_out(pi_in(A) ^ mid) ^ post ^ post2 without writing pi_in(A) ^ mid.
+// vec as in k_gather_xor.
+__global__ void k_gather2_xor(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ p_out,
+                              const uint32_t* __restrict__ p_in, const uint32_t* __restrict__ a,
+                              const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
+                              const uint32_t* __restrict__ mid, const uint32_t* __restrict__ post,
+                              const uint32_t* __restrict__ post2, uint32_t* __restrict__ out) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) out[k] = a[k] ^ b[k];
+    const uint32_t q = vec ? nwords >> 2 : nwords;       // units (uint4 or word) per record
+    const uint64_t total = nrows * q;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+        const uint32_t i = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)i * q);
+        const uint32_t p = p_out[i];
+        const uint64_t sp = (uint64_t)p * q + w, sq = (uint64_t)p_in[p] * q + w;
+        if (vec) {
+            uint4 v = ((const uint4*)a)[sq];
+            if (b) v = xor4(v, ((const uint4*)b)[sq]);
+            if (c) v = xor4(v, ((const uint4*)c)[sq]);
+            if (mid) v = xor4(v, ((const uint4*)mid)[sp]);
+            if (post) v = xor4(v, ((const uint4*)post)[k]);
+            if (post2) v = xor4(v, ((const uint4*)post2)[k]);
+            ((uint4*)out)[k] = v;
+        } else {
+            uint32_t v = a[sq];
+            if (b) v ^= b[sq];
+            if (c) v ^= c[sq];
+            if (mid) v ^= mid[sp];
+            if (post) v ^= post[k];
+            if (post2) v ^= post2[k];
+            out[k] = v;
+        }
+    }
 }
 
 // Case I: XOR over candidates of (r_i & m_i) ^ (r_j & m_i) ^ (r_i & m_j), the
@@ -276,8 +307,9 @@ size_t sort_temp_bytes(uint64_t nrows) {
 uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
     auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
     const uint64_t tw = nrows * nwords * 4;
-    return 5 * r(tw) + 4 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + r(nrows * 4) + r(sort_temp_bytes(nrows)) +
-           4096;
+    // tables T12 T23 T31 X1 Y1 C1; three permutations; sort keys in and out;
+    // the identity index; the sort's temporary storage
+    return 6 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + r(nrows * 4) + r(sort_temp_bytes(nrows)) + 4096;
 }
 
 // perm = stable argsort of the pair seed's row keys.
@@ -309,6 +341,16 @@ int gather(uint64_t nrows, uint32_t nwords, const uint32_t* perm, const uint32_t
     return check_launch("k_gather_xor");
 }
 
+int gather2(uint64_t nrows, uint32_t nwords, const uint32_t* p_out, const uint32_t* p_in, const uint32_t* a,
+            const uint32_t* b, const uint32_t* c, const uint32_t* mid, const uint32_t* post, const uint32_t* post2,
+            uint32_t* out, hipStream_t s) {
+    const bool vec = (nwords & 3u) == 0 && aligned16(a) && aligned16(b) && aligned16(c) && aligned16(mid) &&
+                     aligned16(post) && aligned16(post2) && aligned16(out);
+    hipLaunchKernelGGL(k_gather2_xor, dim3(grid_of(vec ? nrows * nwords / 4 : nrows * nwords, 256)), dim3(256), 0, s,
+                       nrows, nwords, (uint32_t)vec, p_out, p_in, a, b, c, mid, post, post2, out);
+    return check_launch("k_gather2_xor");
+}
+
 // Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
@@ -317,7 +359,6 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     uint32_t* t12 = ws.take<uint32_t>(tw);
     uint32_t* t23 = ws.take<uint32_t>(tw);
     uint32_t* t31 = ws.take<uint32_t>(tw);
-    uint32_t* u = ws.take<uint32_t>(tw);
     uint32_t* x1 = ws.take<uint32_t>(tw);
     uint32_t* y1 = ws.take<uint32_t>(tw);
     uint32_t* c1 = ws.take<uint32_t>(tw);
@@ -340,19 +381,14 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     if (!rc) rc = mask(k23, kT23, nrows, nwords, t23, s);
     if (!rc) rc = mask(k31, kT31, nrows, nwords, t31, s);
     if (!rc) rc = mask(k31, kR1, nrows, nwords, out[0], s);       // R1
-    // CS1: X1 = pi31[pi12(D1 ^ D2 ^ T12) ^ T31]
-    if (!rc) rc = gather(nrows, nwords, p12, d[0], d[1], t12, nullptr, u, s);
-    if (!rc) rc = gather(nrows, nwords, p31, u, t31, nullptr, nullptr, x1, s);
+    // CS1: X1 = pi31[pi12(D1 ^ D2 ^ T12) ^ T31]  (both permutations in one pass)
+    if (!rc) rc = gather2(nrows, nwords, p31, p12, d[0], d[1], t12, t31, nullptr, nullptr, x1, s);
     // CS2: Y1 = pi12(D3 ^ T12); C1 = pi23(X1 ^ T23) ^ R2
     if (!rc) rc = gather(nrows, nwords, p12, d[2], t12, nullptr, nullptr, y1, s);
     if (!rc) rc = gather(nrows, nwords, p23, x1, t23, nullptr, out[1], c1, s);
-    // CS3: C2 = pi23[pi31(Y1 ^ T31) ^ T23] ^ R1; R3 = C1 ^ C2
-    if (!rc) rc = gather(nrows, nwords, p31, y1, t31, nullptr, nullptr, u, s);
-    if (!rc) rc = gather(nrows, nwords, p23, u, t23, nullptr, out[0], x1, s);   // x1 now holds C2
-    if (!rc) {
-        hipLaunchKernelGGL(k_xor2, dim3(grid_of(tw, 256)), dim3(256), 0, s, tw, c1, x1, out[2]);
-        rc = check_launch("k_xor2");
-    }
+    // CS3: C2 = pi23[pi31(Y1 ^ T31) ^ T23] ^ R1, and CS2's R3 = C1 ^ C2, in one
+    // pass (with the servers simulated together, C2 need not be stored)
+    if (!rc) rc = gather2(nrows, nwords, p23, p31, y1, t31, nullptr, t23, out[0], c1, out[2], s);
     return rc;
 }
 

@@ -63,3 +63,17 @@ def plan_outputs(plan, query, graph):
     we = (graph.n_edges + 31) // 32
     o0, o1 = U(plan.out[0]), U(plan.out[1])
     return [(o0[j * we:(j + 1) * we], o1[j * we:(j + 1) * we]) for j in range(query.n_qv - 1)]
+
+
+def T_off(a, dtype=np.uint32):
+    """Like T, but the data starts one word into its allocation (a view whose
+    address is 4 bytes past a 16-byte boundary)."""
+    a = np.ascontiguousarray(a, dtype=dtype)
+    buf = torch.empty(a.size + 1, dtype=torch.int32, device=DEV)
+    buf[1:].copy_(torch.from_numpy(a.view(np.int32)))
+    return buf[1:]
+
+
+def empty_off(n):
+    """An uninitialised int32 device view of n words, 4 bytes past a 16-byte boundary."""
+    return torch.empty(n + 1, dtype=torch.int32, device=DEV)[1:]

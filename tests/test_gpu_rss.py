@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import DEV, T, U
+from gpu_util import DEV, T, T_off, U, empty_off
 from oracle import fss as ofss
 from oracle import rss as orss
 
@@ -84,3 +84,21 @@ def test_rss_reshare_and_and(fss, nrows):
     for i in range(3):
         np.testing.assert_array_equal(got[i], want[i])
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], (x[0] ^ x[1] ^ x[2]) & (y[0] ^ y[1] ^ y[2]))
+
+
+@pytest.mark.parametrize("nrows", [4096 * 32 + 5, 1000])
+def test_rss_and_unaligned_buffers(fss, nrows):
+    """Share buffers that are not 16-byte aligned take the word-by-word path
+    and give the same shares."""
+    nw = (nrows + 31) // 32
+    rng = np.random.default_rng(nrows + 1)
+    vm = ofss.valid_mask(nrows)
+    x = [rng.integers(0, 2**32, nw, dtype=np.uint64).astype(np.uint32) & vm for _ in range(3)]
+    y = [rng.integers(0, 2**32, nw, dtype=np.uint64).astype(np.uint32) & vm for _ in range(3)]
+    keys = [7, 8, 9]
+    z = [empty_off(nw) for _ in range(3)]
+    assert all(t.data_ptr() % 16 == 4 for t in z)
+    fss.rss_and(nrows, [T_off(a) for a in x], [T(b) for b in y], keys, 3, z)
+    want = orss.rss_and(x, y, keys, 3, nrows)
+    for i in range(3):
+        np.testing.assert_array_equal(U(z[i]), want[i])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, T, U
+from gpu_util import DEV, T, T_off, U, empty_off
 from oracle import fss as ofss
 from oracle import shuffle as osh
 
@@ -42,6 +42,20 @@ def test_shuffle_parity(fss, n, w):
     for i in range(3):
         np.testing.assert_array_equal(got[i], want[i])
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], d[osh.composed_permutation(*seeds, n)])
+
+
+@pytest.mark.parametrize("n,w", [(1000, 8), (513, 4)])
+def test_shuffle_unaligned_buffers(fss, n, w):
+    """Inputs and outputs 4 bytes past a 16-byte boundary: the gathers and the
+    mask tables written into the outputs take the word-by-word path."""
+    d, sh = _rss_table(n * w + 5, n, w)
+    seeds = (11, 22, 33)
+    out = [empty_off(n * w) for _ in range(3)]
+    fss.rss_shuffle(n, w, [T_off(s.ravel()) for s in sh], seeds, out)
+    torch.cuda.synchronize()
+    want = osh.sec_shuffle(sh, *seeds)
+    for i in range(3):
+        np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i])
 
 
 def test_fetch_unique(fss):
