@@ -554,10 +554,11 @@ def run_next(args, torch, fss, dev):
     outs = [torch.empty((ncand + 31) // 32, dtype=torch.int32, device=dev) for _ in range(3)]
     terms = [((0, 0), (0, 1)), ((1, 1), (0, 2)), ((1, 2), (1, 0))]     # (party, replica) of each server's two keys
 
+    eval_reqs = [(p, kb, r, npos, evals[2 * i + j]) for i, t in enumerate(terms) for j, (p, r) in enumerate(t)]
+
     def sec_eval():
-        for i, ((pa, ra), (pb, rb)) in enumerate(terms):
-            fss.fss_eval_all(pa, kb, ra, npos, evals[2 * i], stream)
-            fss.fss_eval_all(pb, kb, rb, npos, evals[2 * i + 1], stream)
+        fss.fss_eval_all_batch(eval_reqs, stream)     # the six full-domain evaluations, side by side
+        for i in range(3):
             fss.rss_sec_eval(ncand, npos, evals[2 * i], evals[2 * i + 1], sh[i], sh[(i + 1) % 3], outs[i], stream)
 
     res["sec_eval"] = row("sec_eval", timed(sec_eval), 3 * (2 * 4 * nwp * ncand + ncand // 8),

@@ -279,6 +279,22 @@ int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mas
  */
 int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_t npoints, uint32_t* d_out_bits,
                  void* stream);
+
+/*
+ * fss_eval_all_batch: `count` fss_eval_all requests (same meaning, same checks;
+ *   all are validated before anything is enqueued) run side by side, eight per
+ *   launch -- e.g. the six keys of one secEval predicate.
+ */
+typedef struct fss_eval_all_req {
+    int32_t party;
+    int32_t reserved;
+    const fss_keybatch* keys;
+    uint64_t key_row;
+    uint64_t npoints;
+    uint32_t* d_out_bits;
+} fss_eval_all_req;
+
+int fss_eval_all_batch(const fss_eval_all_req* reqs, uint32_t count, void* stream);
 int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
                  const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream);
 

@@ -570,6 +570,51 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(const uint8_t* key, uint
     }
 }
 
+// Several full-domain evaluations in one launch (blockIdx.y = request): the
+// six keys of one secEval predicate (two per server) are small and
+// latency-bound, so they run side by side instead of one after another.
+constexpr int kEvalAllMax = 8;
+
+struct EvalAllReq {
+    const uint8_t* key;         // this party's key batch
+    uint32_t* out;
+    uint64_t n;                 // rows of the batch
+    uint64_t row;               // key row evaluated
+    uint64_t npoints;
+    uint32_t kind;
+    uint32_t nbits;
+    uint32_t party;
+    uint32_t pad;
+};
+
+struct EvalAllBatch {
+    EvalAllReq r[kEvalAllMax];
+};
+
+__global__ __launch_bounds__(kBlock) void k_eval_points_batch(EvalAllBatch B) {
+    const EvalAllReq& R = B.r[blockIdx.y];
+    if ((uint64_t)blockIdx.x * kBlock >= R.npoints) return;     // the whole block leaves
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const LaneOff loff = lane_offset();
+    const uint64_t np = pad_rows(R.n);
+    uint32_t bit = 0;
+    if (x < R.npoints) {
+        if (R.kind == FSS_EQ)
+            bit = dpf_eval(R.key, np, R.row, R.nbits, R.party, (uint32_t)x, tab, loff);
+        else
+            bit = range_eval(R.key, np, R.row, R.nbits, R.party, (uint32_t)x, tab, loff);
+    }
+    const uint64_t ballot = __ballot(bit);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = x >> 5, nwords = (R.npoints + 31) >> 5;
+        if (w < nwords) R.out[w] = (uint32_t)ballot;
+        if (w + 1 < nwords) R.out[w + 1] = (uint32_t)(ballot >> 32);
+    }
+}
+
 // One server's share of the predicate bit of every candidate: the XOR over
 // positions of Eval(k_a, l) & <e[l]>_a, XORed with the same for (k_b, share b).
 // Shares are word-major ([word][candidate]): a wave reads 256 contiguous bytes
@@ -580,7 +625,8 @@ __global__ void k_rss_eval(uint64_t ncand, uint32_t nwords_pos, const uint32_t* 
     const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
     if (c < ncand) {
-        for (uint32_t w = 0; w < nwords_pos; w++) {
+#pragma unroll 8
+        for (uint32_t w = 0; w < nwords_pos; w++) {      // unrolled: 16 loads in flight per thread
             const uint64_t at = (uint64_t)w * ncand + c;
             acc = __builtin_amdgcn_bitop3_b32(acc, share_a[at], eval_a[w], 0x78);   // acc ^ (s & e): f(0xF0, 0xCC, 0xAA)
             acc = __builtin_amdgcn_bitop3_b32(acc, share_b[at], eval_b[w], 0x78);
@@ -1312,6 +1358,48 @@ int fss_eval_all(int32_t party, const fss_keybatch* k, uint64_t key_row, uint64_
                        (hipStream_t)stream, (const uint8_t*)k->key[party], k->n, key_row, (uint32_t)k->kind,
                        k->nbits, (uint32_t)party, npoints, d_out_bits);
     return check_launch("k_eval_points");
+}
+
+int fss_eval_all_batch(const fss_eval_all_req* reqs, uint32_t count, void* stream) {
+    ogm::last_error().clear();
+    if (count == 0) return FSS_OK;
+    if (!reqs) return fail(FSS_EINVAL, "fss_eval_all_batch: reqs is NULL");
+    for (uint32_t i = 0; i < count; i++) {
+        const fss_eval_all_req& r = reqs[i];
+        const fss_keybatch* k = r.keys;
+        if (!k) return fail(FSS_EINVAL, "fss_eval_all_batch: request %u has no keys", i);
+        int rc = check_batch(k, k->kind, "fss_eval_all_batch");
+        if (rc) return rc;
+        if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "fss_eval_all_batch: request %u party", i);
+        if (r.key_row >= k->n) return fail(FSS_EINVAL, "fss_eval_all_batch: request %u key row", i);
+        if (r.npoints > (1ull << k->nbits)) return fail(FSS_EINVAL, "fss_eval_all_batch: request %u points", i);
+        if (r.npoints && (!r.d_out_bits || !k->key[r.party] || !aligned256(k->key[r.party])))
+            return fail(FSS_EINVAL, "fss_eval_all_batch: request %u buffers", i);
+    }
+    for (uint32_t i0 = 0; i0 < count; i0 += kEvalAllMax) {
+        EvalAllBatch B{};
+        uint64_t blocks = 0;
+        const uint32_t m = count - i0 < (uint32_t)kEvalAllMax ? count - i0 : (uint32_t)kEvalAllMax;
+        for (uint32_t j = 0; j < m; j++) {
+            const fss_eval_all_req& r = reqs[i0 + j];
+            EvalAllReq& e = B.r[j];
+            e.key = (const uint8_t*)r.keys->key[r.party];
+            e.out = r.d_out_bits;
+            e.n = r.keys->n;
+            e.row = r.key_row;
+            e.npoints = r.npoints;
+            e.kind = (uint32_t)r.keys->kind;
+            e.nbits = r.keys->nbits;
+            e.party = (uint32_t)r.party;
+            const uint64_t b = (r.npoints + kBlock - 1) / kBlock;
+            blocks = b > blocks ? b : blocks;
+        }
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL(k_eval_points_batch, dim3((unsigned)blocks, m), dim3(kBlock), 0, (hipStream_t)stream, B);
+        int rc = check_launch("k_eval_points_batch");
+        if (rc) return rc;
+    }
+    return FSS_OK;
 }
 
 static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* const* d_y, const uint64_t* prf_keys,

@@ -58,6 +58,11 @@ class fss_eval_req(ctypes.Structure):
                 ("d_xhat", ctypes.c_void_p), ("d_out_bits", ctypes.c_void_p)]
 
 
+class fss_eval_all_req(ctypes.Structure):
+    _fields_ = [("party", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keys", ctypes.POINTER(fss_keybatch)),
+                ("key_row", ctypes.c_uint64), ("npoints", ctypes.c_uint64), ("d_out_bits", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(_build.LIB):
         raise ImportError(f"HIP library not built: {_build.LIB} (run __graft_entry__.build())")
@@ -82,6 +87,7 @@ def _load():
         "match_query_batch": ([ctypes.POINTER(match_plan), u32, i32, P, u64, P], ctypes.c_int),
         "fss_set_tuning": ([u32, u32], ctypes.c_int),
         "fss_eval_all": ([i32, ctypes.POINTER(fss_keybatch), u64, u64, P, P], ctypes.c_int),
+        "fss_eval_all_batch": ([ctypes.POINTER(fss_eval_all_req), u32, P], ctypes.c_int),
         "fss_dealer_masks": ([u64, u32, u32, u32, u64, P, P], ctypes.c_int),
         "rss_reshare": ([u64, P, P, u32, P, P], ctypes.c_int),
         "rss_and": ([u64, P, P, P, u32, P, P], ctypes.c_int),
@@ -105,7 +111,7 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_fetch_unique", "rss_fetch_many_workspace_bytes",
            "rss_fetch_many", "rss_compact_valid")
 
@@ -323,6 +329,14 @@ def get_tuning():
 
 def fss_eval_all(party: int, keys: KeyBatch, key_row: int, npoints: int, out_bits, stream=None):
     _check(LIB.fss_eval_all(party, ctypes.byref(keys.c), key_row, npoints, _ptr(out_bits), _stream(stream)))
+
+
+def fss_eval_all_batch(reqs, stream=None):
+    """reqs: list of (party, KeyBatch, key_row, npoints, out_bits tensor)."""
+    arr = (fss_eval_all_req * max(1, len(reqs)))()
+    for i, (party, kb, row, npoints, out) in enumerate(reqs):
+        arr[i] = fss_eval_all_req(party, 0, ctypes.pointer(kb.c), row, npoints, _ptr(out))
+    _check(LIB.fss_eval_all_batch(arr, len(reqs), _stream(stream)))
 
 
 def rss_sec_eval(ncand: int, npos: int, eval_a, eval_b, share_a, share_b, out_bits, stream=None):

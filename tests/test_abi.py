@@ -98,3 +98,16 @@ def test_match_plan_validation(fss):
     plan.n_qv = 2
     plan.n_edges = 10
     assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL     # no endpoints
+
+
+def test_eval_all_batch_argument_errors(fss):
+    kb = _kb(fss, fss.RANGE, 12, 3)
+    req = fss.fss_eval_all_req(0, 0, ctypes.pointer(kb), 1, 4096, 4096)
+    assert fss.LIB.fss_eval_all_batch(None, 1, None) == fss.EINVAL
+    assert fss.LIB.fss_eval_all_batch(ctypes.byref(req), 0, None) == fss.OK
+    bad = fss.fss_eval_all_req(2, 0, ctypes.pointer(kb), 1, 4096, 4096)
+    assert fss.LIB.fss_eval_all_batch(ctypes.byref(bad), 1, None) == fss.EINVAL and b"party" in fss.LIB.fss_last_error()
+    bad = fss.fss_eval_all_req(0, 0, ctypes.pointer(kb), 3, 4096, 4096)
+    assert fss.LIB.fss_eval_all_batch(ctypes.byref(bad), 1, None) == fss.EINVAL and b"row" in fss.LIB.fss_last_error()
+    bad = fss.fss_eval_all_req(0, 0, ctypes.pointer(kb), 0, 4097, 4096)
+    assert fss.LIB.fss_eval_all_batch(ctypes.byref(bad), 1, None) == fss.EINVAL and b"points" in fss.LIB.fss_last_error()

@@ -102,3 +102,30 @@ def test_rss_and_unaligned_buffers(fss, nrows):
     want = orss.rss_and(x, y, keys, 3, nrows)
     for i in range(3):
         np.testing.assert_array_equal(U(z[i]), want[i])
+
+
+def test_eval_all_batch_matches_oracle(fss):
+    """Ten full-domain evaluations in one call (two launches of at most eight):
+    equality and range keys, both parties, several point counts -- each equals
+    the oracle's evaluation at every position."""
+    seed, q = 31, 9
+    tok = {"eq": _gpu_token(fss, "eq", 200, seed, q, 0, a=77), "range": _gpu_token(fss, "range", 3000, seed, q, 1,
+                                                                                  lo=100, hi=2500)}
+    otok = {"eq": orss.token("eq", 200, seed, q, 0, a=77), "range": orss.token("range", 3000, seed, q, 1, lo=100,
+                                                                                hi=2500)}
+    reqs, want = [], []
+    for i in range(10):
+        kind = "eq" if i % 3 == 0 else "range"
+        party, rep = i % 2, i % 3
+        npos = {"eq": [200, 64, 1][i % 3], "range": [3000, 1025, 33][i % 3]}[kind]
+        kb, nb = tok[kind]
+        okeys, onb = otok[kind]
+        out = torch.full(((npos + 31) // 32,), -1, dtype=torch.int32, device=DEV)
+        reqs.append((party, kb, rep, npos, out))
+        want.append(orss.eval_all(kind, onb, party, okeys[party], rep, npos))
+    fss.fss_eval_all_batch(reqs)
+    torch.cuda.synchronize()
+    for (party, kb, rep, npos, out), w in zip(reqs, want):
+        got = U(out)
+        np.testing.assert_array_equal(ofss.unpack_bits(got, npos), w)
+        assert npos % 32 == 0 or (got[-1] >> (npos % 32)) == 0
