@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="serve: arrival window per rate")
     ap.add_argument("--serve-max", type=int, default=600, help="serve: at most this many requests per rate")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="batch64: key memory budget of the batched runner")
+    ap.add_argument("--wave-gb", type=float, default=0.0,
+                    help="serve: cap on the keys of one wave (0: a wave may fill the 48 GB key arena)")
     ap.add_argument("--chunk-log-rows", type=int, default=20, help="batch64: rows per keygen/eval chunk (log2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
@@ -460,7 +462,8 @@ def run_serve(args, torch, fss, dev):
     budget = 64 * 10**9
 
     def served_path():
-        return serving.ServedPath(rg, budget, key_arena_bytes=48 * 10**9, chunk_rows=1 << 20, device=dev)
+        return serving.ServedPath(rg, budget, key_arena_bytes=48 * 10**9, chunk_rows=1 << 20, device=dev,
+                                  wave_bytes=int(args.wave_gb * 1e9) if args.wave_gb else None)
 
     paths = {"served": served_path,
              "plain": lambda: serving.PlainPath(rg, device=dev, sync=True),
@@ -494,7 +497,7 @@ def run_serve(args, torch, fss, dev):
     out = {"metric": "served vs plain queries/s and p50/p99 latency (ms), Poisson arrivals",
            "value": max(v["served"]["qps"] for v in results.values()), "unit": "queries/s", "n_gpus": 1,
            "higher_is_better": True, "rates": results, "bit_exact_served_vs_plain": bool(exact),
-           "budget_gb": 64, "dtype": "u32", "data": "synthetic",
+           "budget_gb": 64, "wave_gb": args.wave_gb or None, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "serve: Chung-Lu 2^22 vertices / 2^25 edges resident, 64-shape query mix"},
            "paths": {"served": "continuous batching, admission by memory (64 GB: 48 GB key arena + intermediates)",
                      "plain": "one request at a time, results awaited before the next request starts",

@@ -123,13 +123,17 @@ def _plan(req: Request, bits_given: bool, device):
 
 class ServedPath:
     def __init__(self, graph: ResidentGraph, budget_bytes: int, key_arena_bytes: int, chunk_rows: int = 1 << 20,
-                 device=None, stream=None):
+                 device=None, stream=None, wave_bytes: int = None):
+        """wave_bytes caps the keys (both parties) of one wave, i.e. its work:
+        shorter waves let a request that arrives behind a large one finish one
+        short wave later.  None: a wave may fill the whole key arena."""
         assert key_arena_bytes < budget_bytes and chunk_rows % 64 == 0
         self.g = graph
         self.device = device or torch.device("cuda")
         self.stream = stream or torch.cuda.current_stream()
         self.budget = budget_bytes
         self.arena = KeyArena(key_arena_bytes, self.device)
+        self.wave_cap = min(key_arena_bytes, wave_bytes) if wave_bytes else key_arena_bytes
         self.chunk_rows = chunk_rows
         self.queue = fss.Queue(2048, self.device)
         self.waves = 0
@@ -192,6 +196,8 @@ class ServedPath:
                             raise ValueError(f"a {n}-row chunk needs {2 * half} key bytes; the key arena "
                                              f"holds {self.arena.nbytes}")
                         break
+                    if kg and self.arena.used + 2 * half > self.wave_cap:
+                        break
                     items.popleft()
                     kb = fss.KeyBatch.view(p["kind"], 32, n, self.arena.take(half), self.arena.take(half))
                     kg.append((req.seed, req.query.query_id, k, p["a_or_lo"], p["hi"], p["r"][c0:c0 + n], kb, c0))
@@ -199,7 +205,7 @@ class ServedPath:
                         ev.append((b, kb, p["xhat"][c0:c0 + n], req.bits[k][b][c0 // 32:]))
                 if not items:
                     finished.append(req)
-                if kg and self.arena.used >= self.arena.nbytes:
+                if kg and self.arena.used >= self.wave_cap:
                     break
             if kg:
                 if len(ev) > self.queue.capacity:

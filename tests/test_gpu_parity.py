@@ -148,6 +148,27 @@ def test_12bit_domain(fss):
         np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, 4096), ((xs >= lo) & (xs < hi)).astype(np.uint8))
 
 
+def test_32bit_edges(fss):
+    """32-bit domain at its edges: bounds 0 and 2^32 - 1, empty ranges, x at and
+    around every bound, masks 0, 2^32 - 1 and random (so L > U wraps occur)."""
+    top = 2**32 - 1
+    cases = [(0, 0), (0, 1), (0, top), (top - 1, top), (5, 5), (1, 2**31), (2**31, top), (12345, 12346)]
+    for i, (lo, hi) in enumerate(cases):
+        pts = {0, 1, top - 1, top, 2**31 - 1, 2**31}
+        for b in (lo, hi):
+            pts |= {(b + d) % 2**32 for d in (-1, 0, 1)}
+        x = np.array(sorted(pts), dtype=np.uint32)
+        n = x.size
+        for j, r in enumerate([np.zeros(n, np.uint32), np.full(n, top, np.uint32), _rand_u32(4000 + i, n)]):
+            s0, s1 = _gpu_pred(fss, 1, 32, lo, hi, x, r, 11, 10 * i + j)
+            want = ((x >= lo) & (x < hi)).astype(np.uint8)
+            np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, n), want, err_msg=f"[{lo},{hi}) r#{j}")
+            a = lo
+            s0, s1 = _gpu_pred(fss, 0, 32, a, 0, x, r, 12, 10 * i + j)
+            np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, n), (x == a).astype(np.uint8),
+                                          err_msg=f"a={a} r#{j}")
+
+
 def test_small_domain_ignores_high_bits(fss):
     """With nbits < 32 only the low nbits of xhat are evaluated."""
     x = np.arange(256, dtype=np.uint32)

@@ -162,3 +162,22 @@ def test_resident_edge_prefix_is_the_candidate_view(monkeypatch):
             assert np.array_equal(req.view["src"].numpy().view(np.uint32), view.src)
             assert np.array_equal(req.view["dst"].numpy().view(np.uint32), view.dst)
             assert np.array_equal(calls[0][1].numpy().view(np.uint32), erows.astype(np.uint32))
+
+
+@pytest.mark.timeout(30)
+def test_wave_cap_splits_work(fake):
+    """A wave never holds more keys than wave_bytes (beyond its first chunk)."""
+    reqs = _reqs([0.0] * 4, rows=4096)
+    chunk_keys = 2 * 512 * 1088
+    path = serving.ServedPath(None, budget_bytes=1 << 30, key_arena_bytes=64 << 20, chunk_rows=512,
+                              device="cpu", stream=object(), wave_bytes=3 * chunk_keys)
+    sizes = []
+    f = serving.fss
+    keygen = f.fss_keygen_batch
+    f.fss_keygen_batch = lambda kg, q, st: (sizes.append([2 * f.fss_keybatch_bytes(k[6][0], 32, k[6][1]) for k in kg]),
+                                            keygen(kg, q, st))
+    _run(path, reqs)
+    assert sum(len(w) for w in sizes) == 4 * 2 * 8          # every chunk exactly once
+    assert all(sum(w) <= 3 * chunk_keys or len(w) == 1 for w in sizes)
+    assert len(sizes) >= 8
+    assert all(r.done_event is not None for r in reqs)
