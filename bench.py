@@ -55,9 +55,9 @@ AES_PAIR = (2 * AES_SINGLE[0] - 4 - (21 + 4) - 16 + 1, 2 * AES_SINGLE[1] - 15 - 
 # per level per party, the dealer expands both children for both parties.
 AES_WORK = {
     "eval_eq": (2 * (NBITS - 7 + 1), 0),
-    "eval_range": (2 * 2 * NBITS, 0),
+    "eval_range": (2 * 2 * (NBITS - 7 + 1), 0),
     "keygen_eq": (4, 2 * (NBITS - 7)),
-    "keygen_range": (5, 2 * 2 * NBITS),
+    "keygen_range": (5 + 4, 2 * 2 * (NBITS - 7)),
 }
 
 
@@ -565,7 +565,7 @@ def run_next(args, torch, fss, dev):
             fss.rss_sec_eval(ncand, npos, evals[2 * i], evals[2 * i + 1], sh[i], sh[(i + 1) % 3], outs[i], stream)
 
     res["sec_eval"] = row("sec_eval", timed(sec_eval), 3 * (2 * 4 * nwp * ncand + ncand // 8),
-                          6 * npos * 2 * 12, f"3 servers x (2 full-domain range evals over {npos} positions + "
+                          6 * npos * 2 * (12 - 7 + 1), f"3 servers x (2 full-domain range evals over {npos} positions + "
                           f"AND-parity over {ncand} candidates x {npos}-bit one-hot shares)")
     del sh, outs
     # RSS AND and re-share of 2^30 shared bits (2^25 words per share)

@@ -28,13 +28,14 @@
  *   a batch is a sequence of planes; plane p holds one field for every row,
  *   row e at byte offset plane_offset + e * field_size.
  *   DPF (nu = nbits - 7):   root[16] | scw_0[16] .. scw_{nu-1}[16] | tl[4] | tr[4] | cwout[16]
- *   DCF (nbits levels):     root[16] | scw_0[16] .. scw_{nbits-1}[16] | tl[4] | tr[4] | vcw[4] | fin[4]
+ *   DCF (nu = nbits - 7):   root[16] | scw_0[16] .. scw_{nu-1}[16] | tl[4] | tr[4] | vcw[4] | cwleaf[16]
  *   RANGE key:              DCF at U = hi + r, then DCF at L = lo + r
  *   bit i of tl/tr/vcw belongs to level i (level 0 consumes the most
- *   significant input bit); fin bit 0 is the final correction bit; bit 31 of
- *   the upper DCF's fin is the party's wrap share c_b.  Per element and
- *   party: DPF 16*nbits - 72 bytes (440 at 32 bits), RANGE 2 * (16*nbits + 32)
- *   bytes (1,088 at 32 bits).
+ *   significant input bit); both trees stop nu levels down and a 128-bit leaf
+ *   (cwout / cwleaf corrects G_C of the last seed) answers the low 7 input
+ *   bits; bit 31 of the upper DCF's vcw is the party's wrap share c_b.  Per
+ *   element and party: DPF 16*nbits - 72 bytes (440 at 32 bits), RANGE
+ *   2 * (16*nbits - 68) bytes (888 at 32 bits).
  */
 #ifndef OBLIVGM_FSS_H
 #define OBLIVGM_FSS_H
@@ -68,7 +69,7 @@ typedef struct fss_keybatch {
     void*    key[2];
 } fss_keybatch;
 
-/* Bytes of one element's key for one party (DPF 440 / RANGE 1,088 at 32 bits);
+/* Bytes of one element's key for one party (DPF 440 / RANGE 888 at 32 bits);
  * 0 for an invalid kind or nbits. */
 uint64_t fss_key_bytes(int32_t kind, uint32_t nbits);
 

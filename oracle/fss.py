@@ -35,7 +35,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 DPF_KEY = np.dtype([("root", "u1", 16), ("scw", "u1", (32, 16)), ("tl", "<u4"), ("tr", "<u4"),
                     ("cwout", "u1", 16)])
 DCF_KEY = np.dtype([("root", "u1", 16), ("scw", "u1", (32, 16)), ("tl", "<u4"), ("tr", "<u4"),
-                    ("vcw", "<u4"), ("fin", "<u4")])
+                    ("vcw", "<u4"), ("cwleaf", "u1", 16)])
 RANGE_KEY = np.dtype([("upper", DCF_KEY), ("lower", DCF_KEY)])
 
 

@@ -22,8 +22,9 @@
  * the readings taken here form this FSS specification
  * (PRG = fixed-key AES in Matyas-Meyer-Oseas form with the branch tweak XORed
  * into byte 0; tree walk MSB first; t = bit 0, v = bit 1, next seed = block with
- * bits 0 and 1 cleared; DPF stops nu = n - 7 levels above the leaves and ends
- * in a 128-bit leaf; DCF final output bit c(s) = bit 2 of the last seed).
+ * bits 0 and 1 cleared; DPF and DCF both stop nu = n - 7 levels above the
+ * leaves and end in a 128-bit leaf G_C(s) whose correction word answers the
+ * last 7 input bits).
  * Share-level values (which random seed, which key bytes) therefore are pinned
  * only through AES and through the reconstruction identities; see the tests.
  *
@@ -227,10 +228,10 @@ typedef struct {
 
 typedef struct {
     uint8_t  root[16];
-    uint8_t  scw[32][16];     /* level i = 0..n-1 */
-    uint32_t tl, tr, vcw;     /* bit i: t-left, t-right and value correction of level i */
-    uint32_t fin;             /* bit 0: final correction bit; bit 31: wrap share c_b
-                                 (only in the upper-bound half of a range key) */
+    uint8_t  scw[32][16];     /* level i = 0..nu-1, nu = n - 7 */
+    uint32_t tl, tr, vcw;     /* bit i: t-left, t-right and value correction of level i;
+                                 vcw bit 31: wrap share c_b (upper-bound half of a range key) */
+    uint8_t  cwleaf[16];      /* leaf correction word: 128 outputs for the last 7 input bits */
 } oracle_dcf_key;
 
 typedef struct {
@@ -328,11 +329,17 @@ int oracle_dpf_eval(int party, const oracle_dpf_key *k, uint32_t n, uint32_t x)
     return block_bit(g, (int)(x & 127u));
 }
 
-/* DCF Gen for g^<_{alpha,1} over n-bit inputs with output in Z_2 (no early
- * termination).  Vα accumulates the value corrections along alpha's path. */
+/* DCF Gen for g^<_{alpha,1} over n-bit inputs with output in Z_2.  The tree
+ * is walked for the nu = n - 7 high input bits; V_alpha accumulates the value
+ * corrections along alpha's path.  The last 7 input bits are answered, as in
+ * the DPF, by a 128-bit leaf G_C(s) corrected on alpha's path: once the
+ * evaluation path has left alpha's path its two seeds and t bits are equal,
+ * the leaves cancel and the value bits already hold [x < alpha]; on alpha's
+ * path the leaf must reconstruct to [x_lo < alpha_lo] xor V_alpha. */
 void oracle_dcf_gen(uint32_t n, uint32_t alpha, const uint8_t root0[16], const uint8_t root1[16],
                     oracle_dcf_key *k0, oracle_dcf_key *k1)
 {
+    uint32_t nu = n - 7;
     uint8_t s[2][16];
     int t[2] = {0, 1};
     int valpha = 0;
@@ -343,7 +350,7 @@ void oracle_dcf_gen(uint32_t n, uint32_t alpha, const uint8_t root0[16], const u
     memcpy(k0->root, root0, 16);
     memcpy(k1->root, root1, 16);
 
-    for (uint32_t i = 1; i <= n; i++) {
+    for (uint32_t i = 1; i <= nu; i++) {
         uint8_t sl[2][16], sr[2][16];
         int tlb[2], trb[2], vlb[2], vrb[2];
         for (int b = 0; b < 2; b++) {
@@ -381,23 +388,31 @@ void oracle_dcf_gen(uint32_t n, uint32_t alpha, const uint8_t root0[16], const u
         k0->tr |= (uint32_t)trcw << (i - 1);
         k0->vcw |= (uint32_t)vcw << (i - 1);
     }
-    /* Final correction: c(s_0) xor c(s_1) xor Vα, with c(s) = bit 2 of s. */
-    int fin = block_bit(s[0], 2) ^ block_bit(s[1], 2) ^ valpha;
-    k0->fin = (uint32_t)fin;
+    /* Leaf: bit j of CW = bit j of G_C(s_0) xor G_C(s_1), xor [j < alpha mod 128],
+     * xor V_alpha. */
+    uint8_t g0[16], g1[16], cw[16];
+    oracle_prg(2, s[0], g0);
+    oracle_prg(2, s[1], g1);
+    block_xor(cw, g0, g1);
+    uint32_t low = alpha & 127u;
+    for (uint32_t j = 0; j < 128; j++)
+        if ((int)(j < low) ^ valpha) cw[j >> 3] ^= (uint8_t)(1u << (j & 7));
+    memcpy(k0->cwleaf, cw, 16);
+    memcpy(k1->cwleaf, cw, 16);
     k1->tl = k0->tl;
     k1->tr = k0->tr;
     k1->vcw = k0->vcw;
-    k1->fin = k0->fin;
 }
 
 int oracle_dcf_eval(int party, const oracle_dcf_key *k, uint32_t n, uint32_t x)
 {
+    uint32_t nu = n - 7;
     uint8_t s[16];
     int t = party;
     int v = 0;
     x &= dom_mask(n);
     memcpy(s, k->root, 16);
-    for (uint32_t i = 1; i <= n; i++) {
+    for (uint32_t i = 1; i <= nu; i++) {
         int xi = msb_bit(x, n, i);
         uint8_t ns[16];
         int nt, nv;
@@ -409,7 +424,10 @@ int oracle_dcf_eval(int party, const oracle_dcf_key *k, uint32_t n, uint32_t x)
         memcpy(s, ns, 16);
         t = nt;
     }
-    return v ^ block_bit(s, 2) ^ (t & (int)(k->fin & 1u));
+    uint8_t g[16];
+    oracle_prg(2, s, g);
+    block_xor_if(g, t, k->cwleaf);
+    return v ^ block_bit(g, (int)(x & 127u));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -469,8 +487,8 @@ void oracle_keygen_range(uint32_t n, uint64_t seed, uint32_t query, uint32_t pre
         oracle_dcf_gen(n, L, l0, l1, &k0[e].lower, &k1[e].lower);
         uint32_t c0 = (uint32_t)block_bit(cb, 0);
         uint32_t c1 = c0 ^ (L > U ? 1u : 0u);
-        k0[e].upper.fin |= c0 << 31;
-        k1[e].upper.fin |= c1 << 31;
+        k0[e].upper.vcw |= c0 << 31;
+        k1[e].upper.vcw |= c1 << 31;
     }
 }
 
@@ -490,7 +508,7 @@ void oracle_eval_range(uint32_t n, int party, const oracle_range_key *k, const u
     for (long long e = 0; e < (long long)count; e++) {
         int yu = oracle_dcf_eval(party, &k[e].upper, n, xhat[e]);
         int yl = oracle_dcf_eval(party, &k[e].lower, n, xhat[e]);
-        int c = (int)(k[e].upper.fin >> 31);
+        int c = (int)(k[e].upper.vcw >> 31);
         out[e] = (uint8_t)(yu ^ yl ^ c);
     }
 }

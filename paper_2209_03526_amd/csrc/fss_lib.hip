@@ -89,14 +89,14 @@ struct DpfPlanes {
 
 struct DcfPlanes {
     uint64_t np;
-    uint32_t n;
+    uint32_t nu;            // levels walked: nbits - 7
     __host__ __device__ uint64_t root() const { return 0; }
     __host__ __device__ uint64_t scw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
-    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)n); }
+    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)nu); }
     __host__ __device__ uint64_t tr() const { return tl() + 4 * np; }
-    __host__ __device__ uint64_t vcw() const { return tl() + 8 * np; }
-    __host__ __device__ uint64_t fin() const { return tl() + 12 * np; }
-    __host__ __device__ uint64_t bytes() const { return tl() + 16 * np; }
+    __host__ __device__ uint64_t vcw() const { return tl() + 8 * np; }       // bit 31: wrap share c_b
+    __host__ __device__ uint64_t cwleaf() const { return tl() + 12 * np; }
+    __host__ __device__ uint64_t bytes() const { return cwleaf() + 16 * np; }
 };
 
 template <class T>
@@ -140,21 +140,29 @@ __device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, ui
     return (word >> (idx & 31u)) & 1u;
 }
 
-// Party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in step.
+// Bit idx (0..127) of a 128-bit block.
+__device__ __forceinline__ uint32_t block_bit(uint4 g, uint32_t idx) {
+    const uint32_t word = idx < 64 ? (idx < 32 ? g.x : g.y) : (idx < 96 ? g.z : g.w);
+    return (word >> (idx & 31u)) & 1u;
+}
+
+// Party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in step
+// over the nu = nbits - 7 high bits, then each DCF's 128-bit leaf answers the
+// low 7 bits.
 __device__ __forceinline__ uint32_t range_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
                                                uint32_t party, uint32_t x, const uint32_t* tab,
                                                LaneOff loff) {
-    const DcfPlanes P{np, nbits};
+    const DcfPlanes P{np, nbits - 7};
     const uint8_t* ku = key;
     const uint8_t* kl = key + P.bytes();
     uint4 su = at<uint4>(ku, P.root(), row);
     uint4 sl = at<uint4>(kl, P.root(), row);
     const uint32_t tlu = at<uint32_t>(ku, P.tl(), row), tru = at<uint32_t>(ku, P.tr(), row);
-    const uint32_t vcu = at<uint32_t>(ku, P.vcw(), row), finu = at<uint32_t>(ku, P.fin(), row);
+    const uint32_t vcu = at<uint32_t>(ku, P.vcw(), row);
     const uint32_t tll = at<uint32_t>(kl, P.tl(), row), trl = at<uint32_t>(kl, P.tr(), row);
-    const uint32_t vcl = at<uint32_t>(kl, P.vcw(), row), finl = at<uint32_t>(kl, P.fin(), row);
+    const uint32_t vcl = at<uint32_t>(kl, P.vcw(), row);
     uint32_t tu = party, tv = party, vu = 0, vl = 0;
-    for (uint32_t i = 0; i < nbits; i++) {
+    for (uint32_t i = 0; i < P.nu; i++) {
         const uint4 cwu = at<uint4>(ku, P.scw(i), row);
         const uint4 cwl = at<uint4>(kl, P.scw(i), row);
         const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
@@ -167,9 +175,10 @@ __device__ __forceinline__ uint32_t range_eval(const uint8_t* key, uint64_t np, 
         tu = ((wu.x ^ (tu & ((xi ? tru : tlu) >> i))) & 1u);
         tv = ((wl.x ^ (tv & ((xi ? trl : tll) >> i))) & 1u);
     }
-    const uint32_t yu = vu ^ (su.x >> 2) ^ (tu & finu);
-    const uint32_t yl = vl ^ (sl.x >> 2) ^ (tv & finl);
-    return (yu ^ yl ^ (finu >> 31)) & 1u;
+    const uint4 gu = xor4(prg(su, 2u, tab, loff), and4(at<uint4>(ku, P.cwleaf(), row), 0u - tu));
+    const uint4 gl = xor4(prg(sl, 2u, tab, loff), and4(at<uint4>(kl, P.cwleaf(), row), 0u - tv));
+    const uint32_t idx = x & 127u;
+    return (vu ^ vl ^ block_bit(gu, idx) ^ block_bit(gl, idx) ^ (vcu >> 31)) & 1u;
 }
 
 struct EvalDesc {
@@ -314,14 +323,16 @@ __device__ __forceinline__ void dpf_gen(uint8_t* k, uint64_t np, uint64_t row, u
     at_w<uint4>(k, P.cwout(), row) = cw;
 }
 
-// DCF Gen for [x < alpha] over nbits (Z_2 values), this lane's party b; `wrap`
-// is the party's wrap share, stored in fin bit 31.
+// DCF Gen for [x < alpha] over nbits (Z_2 values), this lane's party b: the
+// tree over the nu = nbits - 7 high bits, then the 128-bit leaf correction
+// word (bit j = bit j of G_C(s_0) ^ G_C(s_1), ^ [j < alpha mod 128], ^ V_alpha).
+// `wrap` is the party's wrap share, stored in vcw bit 31.
 __device__ __forceinline__ void dcf_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
                                         uint32_t b, uint4 s, uint32_t wrap, const uint32_t* tab, LaneOff loff) {
-    const DcfPlanes P{np, nbits};
+    const DcfPlanes P{np, nbits - 7};
     at_w<uint4>(k, P.root(), row) = s;
     uint32_t t = b, va = 0, tlw = 0, trw = 0, vw = 0;
-    for (uint32_t i = 0; i < nbits; i++) {
+    for (uint32_t i = 0; i < P.nu; i++) {
         const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
         uint4 wl, wr;
         prg_pair(s, tab, loff, wl, wr);
@@ -346,12 +357,20 @@ __device__ __forceinline__ void dcf_gen(uint8_t* k, uint64_t np, uint64_t row, u
         trw |= trcw << i;
         vw |= vcw << i;
     }
-    const uint32_t c = (s.x >> 2) & 1u;
-    const uint32_t fin = (c ^ partner(c) ^ va) & 1u;
+    const uint4 g = prg(s, 2u, tab, loff);
+    uint4 cw = xor4(g, partner4(g));
+    // [j < low] for j = 0..127 as a 128-bit mask, flipped when V_alpha = 1
+    const uint32_t low = alpha & 127u;
+    const uint32_t flip = 0u - va;
+    const uint32_t m0 = low >= 32 ? ~0u : (1u << low) - 1u;
+    const uint32_t m1 = low >= 64 ? ~0u : (low <= 32 ? 0u : (1u << (low - 32)) - 1u);
+    const uint32_t m2 = low >= 96 ? ~0u : (low <= 64 ? 0u : (1u << (low - 64)) - 1u);
+    const uint32_t m3 = low <= 96 ? 0u : (1u << (low - 96)) - 1u;
+    cw = xor4(cw, make_uint4(m0 ^ flip, m1 ^ flip, m2 ^ flip, m3 ^ flip));
     at_w<uint32_t>(k, P.tl(), row) = tlw;
     at_w<uint32_t>(k, P.tr(), row) = trw;
-    at_w<uint32_t>(k, P.vcw(), row) = vw;
-    at_w<uint32_t>(k, P.fin(), row) = fin | (wrap << 31);
+    at_w<uint32_t>(k, P.vcw(), row) = vw | (wrap << 31);
+    at_w<uint4>(k, P.cwleaf(), row) = cw;
 }
 
 // Both lanes of row `row`'s pair (b = party of this lane); KIND is the key kind.
@@ -377,7 +396,7 @@ __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, ui
         uint4 sl = clear_tv(rng_block(A.rk, 3, 3 + b, A.query, A.pred, e, tab, loff));
         pin_in_vgprs(sl);
         dcf_gen(key, np, row, A.nbits, U, b, s, cb, tab, loff);
-        dcf_gen(key + DcfPlanes{np, A.nbits}.bytes(), np, row, A.nbits, L, b, sl, 0u, tab, loff);
+        dcf_gen(key + DcfPlanes{np, A.nbits - 7}.bytes(), np, row, A.nbits, L, b, sl, 0u, tab, loff);
     }
 }
 
@@ -803,7 +822,7 @@ bool valid_nbits(uint32_t nbits) { return nbits >= 8 && nbits <= 32; }
 uint64_t key_bytes(int32_t kind, uint32_t nbits) {
     if (!valid_nbits(nbits)) return 0;
     if (kind == FSS_EQ) return 16ull * nbits - 72;
-    if (kind == FSS_RANGE) return 2ull * (16ull * nbits + 32);
+    if (kind == FSS_RANGE) return 2ull * (16ull * nbits - 68);
     return 0;
 }
 

@@ -11,12 +11,13 @@ def pad_rows(n):
 
 
 def _dcf_planes(np_, nbits):
+    nu = nbits - 7
     off = {"root": 0}
-    for i in range(nbits):
+    for i in range(nu):
         off[("scw", i)] = 16 * np_ * (1 + i)
-    base = 16 * np_ * (1 + nbits)
-    off["tl"], off["tr"], off["vcw"], off["fin"] = base, base + 4 * np_, base + 8 * np_, base + 12 * np_
-    return off, base + 16 * np_
+    base = 16 * np_ * (1 + nu)
+    off["tl"], off["tr"], off["vcw"], off["cwleaf"] = base, base + 4 * np_, base + 8 * np_, base + 12 * np_
+    return off, base + 12 * np_ + 16 * np_
 
 
 def _dpf_planes(np_, nbits):
@@ -41,20 +42,22 @@ def _enc_dcf(buf, base, np_, nbits, k):
     off, size = _dcf_planes(np_, nbits)
     n = k.size
     _put(buf, base + off["root"], n, k["root"], 16)
-    for i in range(nbits):
+    for i in range(nbits - 7):
         _put(buf, base + off[("scw", i)], n, k["scw"][:, i, :], 16)
-    for f in ("tl", "tr", "vcw", "fin"):
+    for f in ("tl", "tr", "vcw"):
         _put(buf, base + off[f], n, k[f].astype("<u4"), 4)
+    _put(buf, base + off["cwleaf"], n, k["cwleaf"], 16)
     return size
 
 
 def _dec_dcf(buf, base, np_, nbits, n, out):
     off, size = _dcf_planes(np_, nbits)
     out["root"] = _get(buf, base + off["root"], n, 16).reshape(n, 16)
-    for i in range(nbits):
+    for i in range(nbits - 7):
         out["scw"][:, i, :] = _get(buf, base + off[("scw", i)], n, 16).reshape(n, 16)
-    for f in ("tl", "tr", "vcw", "fin"):
+    for f in ("tl", "tr", "vcw"):
         out[f] = _get(buf, base + off[f], n, 4).view("<u4")
+    out["cwleaf"] = _get(buf, base + off["cwleaf"], n, 16).reshape(n, 16)
     return size
 
 

@@ -33,12 +33,12 @@ def test_every_declared_symbol_is_exported(fss):
 
 def test_key_sizes(fss):
     assert fss.fss_key_bytes(fss.EQ, 32) == 440
-    assert fss.fss_key_bytes(fss.RANGE, 32) == 1088
+    assert fss.fss_key_bytes(fss.RANGE, 32) == 888
     assert fss.fss_key_bytes(fss.EQ, 8) == 16 * 8 - 72
-    assert fss.fss_key_bytes(fss.RANGE, 12) == 2 * (16 * 12 + 32)
+    assert fss.fss_key_bytes(fss.RANGE, 12) == 2 * (16 * 12 - 68)
     assert fss.fss_key_bytes(fss.EQ, 7) == 0 and fss.fss_key_bytes(fss.RANGE, 33) == 0
     assert fss.fss_key_bytes(5, 32) == 0
-    assert fss.fss_keybatch_bytes(fss.RANGE, 32, 65) == 1088 * 128
+    assert fss.fss_keybatch_bytes(fss.RANGE, 32, 65) == 888 * 128
     assert fss.fss_keybatch_bytes(fss.EQ, 32, 0) == 0
 
 

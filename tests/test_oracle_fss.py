@@ -89,9 +89,8 @@ def test_single_share_is_not_the_function():
 
 def test_correction_words_common_roots_distinct():
     _, (k0, k1) = _dcf_recon(12, 777, 51, np.arange(4, dtype=np.uint32))
-    for f in ("scw", "tl", "tr", "vcw"):
+    for f in ("scw", "tl", "tr", "vcw", "cwleaf"):
         np.testing.assert_array_equal(k0[f], k1[f])
-    assert (k0["fin"] & 1) == (k1["fin"] & 1)
     assert not np.array_equal(k0["root"], k1["root"])
     # seeds carry no t/v bits: bits 0 and 1 of every seed byte 0 are zero
     assert (k0["root"][:, 0] & 3).max() == 0 and (k0["scw"][:, :12, 0] & 3).max() == 0
