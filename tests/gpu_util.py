@@ -77,3 +77,23 @@ def T_off(a, dtype=np.uint32):
 def empty_off(n):
     """An uninitialised int32 device view of n words, 4 bytes past a 16-byte boundary."""
     return torch.empty(n + 1, dtype=torch.int32, device=DEV)[1:]
+
+
+def job_inputs(fss, view, q, vsh, masks, seed):
+    """A runner QueryJob for query q over a candidate view: masks and opened
+    values on the device (one fss_mask_open per predicate)."""
+    from paper_2209_03526_amd.runner import QueryJob
+    preds = []
+    for k, p in enumerate(q.preds):
+        on_edge = p.target >= q.n_qv
+        x0, x1 = vsh[("e:" if on_edge else "") + p.column]
+        rows = view.n_edges if on_edge else view.n_vertices
+        r = T(masks[k]) if rows else torch.zeros(1, dtype=torch.int32, device=DEV)
+        xhat = torch.empty(max(rows, 1), dtype=torch.int32, device=DEV)
+        if rows:
+            fss.fss_mask_open(T(x0), T(x1), r, xhat)
+        preds.append(dict(target=p.target, kind=fss.EQ if p.kind == "eq" else fss.RANGE, rows=rows,
+                          a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
+    src = T(view.src) if view.n_edges else None
+    dst = T(view.dst) if view.n_edges else None
+    return QueryJob(seed, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds, src, dst)

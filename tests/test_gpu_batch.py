@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import DEV, B, T, U, column_shares, plan_outputs
+from gpu_util import DEV, B, T, U, column_shares, job_inputs, plan_outputs
 from oracle import fss as ofss
 from oracle import match as omatch
 
@@ -164,24 +164,6 @@ def test_uneven_query_batch(fss):
     assert checked >= 2
 
 
-def _job_inputs(fss, view, q, vsh, masks, seed):
-    from paper_2209_03526_amd.runner import QueryJob
-    preds = []
-    for k, p in enumerate(q.preds):
-        on_edge = p.target >= q.n_qv
-        x0, x1 = vsh[("e:" if on_edge else "") + p.column]
-        rows = view.n_edges if on_edge else view.n_vertices
-        r = T(masks[k]) if rows else torch.zeros(1, dtype=torch.int32, device=DEV)
-        xhat = torch.empty(max(rows, 1), dtype=torch.int32, device=DEV)
-        if rows:
-            fss.fss_mask_open(T(x0), T(x1), r, xhat)
-        preds.append(dict(target=p.target, kind=fss.EQ if p.kind == "eq" else fss.RANGE, rows=rows,
-                          a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
-    src = T(view.src) if view.n_edges else None
-    dst = T(view.dst) if view.n_edges else None
-    return QueryJob(seed, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds, src, dst)
-
-
 def test_chunked_runner_matches_whole_table(fss):
     """Waves of 4,096-row chunks under a key budget smaller than the jobs' keys
     give the same shares as whole-table calls (dealer randomness is addressed by
@@ -198,7 +180,7 @@ def test_chunked_runner_matches_whole_table(fss):
     tsh = column_shares(tiny, 7)
     tm = synth.pred_masks(7, tq, tiny)
     twant = omatch.run_plan(32, 7, tiny, tq, tsh, tm)
-    jobs = [_job_inputs(fss, g, q, shares, masks, seed), _job_inputs(fss, tiny, tq, tsh, tm, 7)]
+    jobs = [job_inputs(fss, g, q, shares, masks, seed), job_inputs(fss, tiny, tq, tsh, tm, 7)]
     # the budget holds the largest chunk's keys (both parties) but well under
     # half of all keys, so the run needs several waves
     chunk_keys = [2 * fss.fss_keybatch_bytes(p["kind"], 32, min(4096, p["rows"] - c0))

@@ -92,3 +92,50 @@ def test_full_path_query_2p22_2p25(fss):
         for b, s in ((0, s0), (1, s1)):
             np.testing.assert_array_equal(ofss.unpack_bits(s, g.n_edges)[rows], want[j, b])
     assert total > 0
+
+
+def test_batch64_full_mix(fss):
+    """The 64-query mix over the 2^22 / 2^25 Chung-Lu graph through the chunked
+    runner (persistent dealer and eval launches, waves under a 32 GB key
+    budget), as bench.py --workload batch64 runs it: every query's output
+    reconstructs to the plaintext filter / join on its candidate view, and both
+    parties' bits at sampled rows equal the oracle's."""
+    from paper_2209_03526_amd.runner import ChunkedRunner
+    from gpu_util import job_inputs
+    seed = 999
+    g, _ = synth.config3(3)
+    shares = column_shares(g, seed)
+    mix = synth.batch_queries(4, g, count=64)
+    views, jobs = [], []
+    for q, rows in mix:
+        view, erows = synth.candidate_view(g, rows)
+        vsh = synth.view_shares(shares, g, view, erows)
+        masks = synth.pred_masks(seed, q, view)
+        views.append((q, view, vsh, masks))
+        jobs.append(job_inputs(fss, view, q, vsh, masks, seed))
+    runner = ChunkedRunner(32 * 10**9, chunk_rows=1 << 20)
+    runner.run(jobs)
+    torch.cuda.synchronize()
+    assert runner.waves >= 2
+    checked = 0
+    for i, ((q, view, vsh, masks), job) in enumerate(zip(views, jobs)):
+        outs = plan_outputs(job.plan, q, view)
+        m = [_plain_vertex(view, q, v) for v in range(q.n_qv)]
+        if q.n_qv == 1:
+            nrows, truths = view.n_vertices, [m[0]]
+        else:
+            nrows = view.n_edges
+            truths = [m[j][view.src] & m[j + 1][view.dst] & _plain_edge(view, q, j) for j in range(q.n_qv - 1)]
+        if nrows == 0:
+            continue
+        rows = _sample_rows(nrows, 100 + i, k=6)
+        rows = rows[rows < nrows]
+        want = omatch.sampled_outputs(32, seed, view, q, vsh, masks, rows)
+        for j, ((s0, s1), truth) in enumerate(zip(outs, truths)):
+            recon = ofss.unpack_bits(s0 ^ s1, nrows).astype(bool)
+            np.testing.assert_array_equal(recon, truth, err_msg=f"query {i} output {j}")
+            for b, s in ((0, s0), (1, s1)):
+                np.testing.assert_array_equal(ofss.unpack_bits(s, nrows)[rows], want[j, b],
+                                              err_msg=f"query {i} output {j} party {b}")
+        checked += 1
+    assert checked >= 60
