@@ -140,7 +140,9 @@ int fss_eval_lt(int32_t party, const fss_keybatch* k, const uint32_t* d_xhat, ui
  *
  * ss_triples: dealer's triples for AND number `and_id` of query `query_id`:
  *   d_trip0 / d_trip1 receive 3*nwords words a_b | b_b | c_b (party 0 / 1),
- *   with (a0^a1) & (b0^b1) = c0^c1, from the counter-mode generator (domain 4).
+ *   with (a0^a1) & (b0^b1) = c0^c1, from the counter-mode generator (domain 4);
+ *   nwords at most 4 * floor(2^32 / 5) (the block counter is 32-bit), else
+ *   EUNSUPPORTED.
  * ss_and, phase SS_AND_OPEN:  out = d_b | e_b (2*nwords words),
  *   d_b = x ^ a_b, e_b = y ^ b_b.
  * ss_and, phase SS_AND_CLOSE: de_open = d | e (2*nwords words, the XOR of the

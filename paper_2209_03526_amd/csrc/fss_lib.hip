@@ -1012,7 +1012,8 @@ int ss_triples(uint64_t seed, uint32_t query_id, uint32_t and_id, uint64_t nword
     ogm::last_error().clear();
     if (nwords == 0) return FSS_OK;
     if (!d_trip0 || !d_trip1) return fail(FSS_EINVAL, "ss_triples: NULL buffer");
-    if (nwords > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "ss_triples: too many words");
+    // four triple words take five generator blocks, counted in 32 bits
+    if ((nwords + 3) / 4 * 5 > (1ull << 32)) return fail(FSS_EUNSUPPORTED, "ss_triples: too many words");
     return launch_triples(seed, query_id, and_id, nwords, d_trip0, d_trip1, (hipStream_t)stream);
 }
 

@@ -111,3 +111,10 @@ def test_eval_all_batch_argument_errors(fss):
     assert fss.LIB.fss_eval_all_batch(ctypes.byref(bad), 1, None) == fss.EINVAL and b"row" in fss.LIB.fss_last_error()
     bad = fss.fss_eval_all_req(0, 0, ctypes.pointer(kb), 0, 4097, 4096)
     assert fss.LIB.fss_eval_all_batch(ctypes.byref(bad), 1, None) == fss.EINVAL and b"points" in fss.LIB.fss_last_error()
+
+
+def test_triples_counter_limit(fss):
+    """The Beaver stream's 32-bit block counter bounds the triple words."""
+    p = ctypes.c_void_p(4096)
+    assert fss.LIB.ss_triples(1, 1, 0, (1 << 32) // 5 * 4 + 4, p, p, None) == fss.EUNSUPPORTED
+    assert b"too many" in fss.LIB.fss_last_error()
