@@ -14,7 +14,6 @@ wait for a staging buffer inside the library.
 """
 from __future__ import annotations
 
-import ctypes
 from dataclasses import dataclass, field
 
 import torch
