@@ -42,7 +42,8 @@ def test_mask_open(fss, n):
 # --------------------------------------------------------------------------- dealer keygen
 
 KG_CASES = [(kind, nbits, n) for kind in (0, 1) for nbits in (8, 12, 32) for n in (1, 65, 1000)] + \
-           [(0, 32, 4099), (1, 32, 4099), (0, 20, 2048), (1, 17, 333)]
+           [(0, 32, 4099), (1, 32, 4099), (0, 20, 2048), (1, 17, 333), (0, 9, 64), (1, 9, 70), (1, 25, 129),
+            (0, 31, 100), (1, 31, 100)]
 
 
 @pytest.mark.parametrize("kind,nbits,n", KG_CASES)
@@ -167,6 +168,23 @@ def test_32bit_edges(fss):
             s0, s1 = _gpu_pred(fss, 0, 32, a, 0, x, r, 12, 10 * i + j)
             np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, n), (x == a).astype(np.uint8),
                                           err_msg=f"a={a} r#{j}")
+
+
+@pytest.mark.parametrize("nbits", [9, 17, 25, 31])
+def test_odd_domain_widths(fss, nbits):
+    """Masked equality and range at widths between the workloads' 8, 12 and 32:
+    points at and around the bounds and the domain ends, random masks."""
+    top = (1 << nbits) - 1
+    rng = np.random.default_rng(nbits)
+    lo, hi = int(rng.integers(0, top // 2)), int(rng.integers(top // 2, top))
+    pts = {0, 1, top - 1, top} | {(b + d) % (1 << nbits) for b in (lo, hi) for d in (-1, 0, 1)}
+    pts |= {int(v) for v in rng.integers(0, top + 1, 200, dtype=np.uint64)}
+    x = np.array(sorted(pts), dtype=np.uint32)
+    r = _rand_u32(5000 + nbits, x.size)
+    s0, s1 = _gpu_pred(fss, 1, nbits, lo, hi, x, r, 13, nbits)
+    np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, x.size), ((x >= lo) & (x < hi)).astype(np.uint8))
+    s0, s1 = _gpu_pred(fss, 0, nbits, lo, 0, x, r, 14, nbits)
+    np.testing.assert_array_equal(ofss.unpack_bits(s0 ^ s1, x.size), (x == lo).astype(np.uint8))
 
 
 def test_small_domain_ignores_high_bits(fss):

@@ -193,3 +193,20 @@ def test_mask_open_identity():
     r = rng.integers(0, 2**32, 1000, dtype=np.uint64).astype(np.uint32)
     xhat = fss.mask_open(x0, x1, r)
     assert ((xhat.astype(np.int64) - r.astype(np.int64)) % 2**32 == x).all()
+
+
+@pytest.mark.parametrize("n", [9, 13, 17, 21, 25, 29, 31])
+def test_all_domain_widths(n):
+    """Every width nu = n - 7 of the early-terminated trees: points at, around
+    and far from alpha, and the domain ends."""
+    rng = np.random.default_rng(n)
+    top = (1 << n) - 1
+    for alpha in [0, 1, top, 1 << (n - 1), int(rng.integers(0, top))]:
+        pts = {0, top, alpha, (alpha - 1) % (1 << n), (alpha + 1) % (1 << n), alpha ^ 127, alpha ^ 128,
+               (alpha & ~127) % (1 << n), (alpha | 127) % (1 << n)}
+        pts |= {int(v) for v in rng.integers(0, top + 1, 40, dtype=np.uint64)}
+        xs = np.array(sorted(pts), dtype=np.uint32)
+        y, _ = _dpf_recon(n, alpha, 7 * n, xs)
+        np.testing.assert_array_equal(y, (xs == alpha).astype(np.uint8))
+        y, _ = _dcf_recon(n, alpha, 7 * n + 1, xs)
+        np.testing.assert_array_equal(y, (xs < alpha).astype(np.uint8))
