@@ -82,6 +82,12 @@ const char* fss_last_error(void);
 /* Library version string. */
 const char* fss_version(void);
 
+/* Release what the library holds on its own: the pinned staging buffers of
+ * the batch calls (waiting for their last copies first).  Call it when no call
+ * is in flight on any thread; the library stays usable (buffers are re-created
+ * on demand).  FSS_EDEVICE if the runtime reports an error while releasing. */
+int fss_shutdown(void);
+
 /*
  * Open the masked value (Sec. V-B additive shares, Sec. V-C masked input):
  *   d_xhat[i] = d_x0[i] + d_x1[i] + d_r[i]  (mod 2^32),  i < n.

@@ -826,6 +826,8 @@ uint64_t key_bytes(int32_t kind, uint32_t nbits) {
     return 0;
 }
 
+int staging_release();      // the batch calls' staging ring (defined with it below)
+
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -932,6 +934,13 @@ uint64_t fss_keybatch_bytes(int32_t kind, uint32_t nbits, uint64_t n) { return k
 const char* fss_last_error(void) { return ogm::last_error().c_str(); }
 
 const char* fss_version(void) { return "oblivgm-fss 0.1 gfx950 lds-ttable"; }
+
+int fss_shutdown(void) {
+    ogm::last_error().clear();
+    const int rc = staging_release();
+    if (rc) return fail(rc, "fss_shutdown: a staging buffer could not be released");
+    return FSS_OK;
+}
 
 int fss_mask_open(uint64_t n, const uint32_t* d_x0, const uint32_t* d_x1, const uint32_t* d_r, uint32_t* d_xhat,
                   void* stream) {
@@ -1293,6 +1302,22 @@ int upload(const void* src, size_t bytes, void* d_dst, hipStream_t s) {
         return fail(FSS_EDEVICE, "batch: descriptor upload failed");
     sl.pending = true;
     return FSS_OK;
+}
+
+// Release the ring: wait for each slot's last copy, then free its pinned
+// buffer and event.  Slots are re-created on demand afterwards.
+int staging_release() {
+    std::lock_guard<std::mutex> lock(g_staging.mu);
+    int rc = FSS_OK;
+    for (StagingSlot& sl : g_staging.slot) {
+        if (sl.pending && hipEventSynchronize(sl.done) != hipSuccess) rc = FSS_EDEVICE;
+        sl.pending = false;
+        if (sl.host && hipHostFree(sl.host) != hipSuccess) rc = FSS_EDEVICE;
+        if (sl.done && hipEventDestroy(sl.done) != hipSuccess) rc = FSS_EDEVICE;
+        sl = StagingSlot{};
+    }
+    g_staging.next = 0;
+    return rc;
 }
 
 constexpr uint64_t kQueueHeader = 256;   // the tile counter

@@ -73,6 +73,7 @@ def _load():
         "fss_keybatch_bytes": ([i32, u32, u64], u64),
         "fss_last_error": ([], ctypes.c_char_p),
         "fss_version": ([], ctypes.c_char_p),
+        "fss_shutdown": ([], ctypes.c_int),
         "fss_mask_open": ([u64, P, P, P, P, P], ctypes.c_int),
         "fss_keygen": ([u64, u32, u32, u32, u32, P, ctypes.POINTER(fss_keybatch), P], ctypes.c_int),
         "fss_eval_eq": ([i32, ctypes.POINTER(fss_keybatch), P, P, P], ctypes.c_int),
@@ -108,7 +109,7 @@ def _load():
 
 
 LIB = _load()
-EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_mask_open",
+EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_shutdown", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
            "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
@@ -143,6 +144,11 @@ def words(rows: int) -> int:
 
 def version() -> str:
     return LIB.fss_version().decode()
+
+
+def shutdown():
+    """Release the library's own buffers (they are re-created on demand)."""
+    _check(LIB.fss_shutdown())
 
 
 def fss_key_bytes(kind: int, nbits: int) -> int:

@@ -196,3 +196,20 @@ def test_chunked_runner_matches_whole_table(fss):
         for j, (a, b) in enumerate(zip(got, ww)):
             np.testing.assert_array_equal(a[0], b[0])
             np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_shutdown_releases_and_library_stays_usable(fss):
+    """fss_shutdown frees the staging ring; the next batch call re-creates it
+    and gives the same keys (the rows' keys: pad rows are never written)."""
+    from keylayout import from_device
+    n = 3000
+    r = T(np.random.default_rng(5).integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32))
+    q = fss.Queue(8, DEV)
+    outs = []
+    for i in range(2):
+        kb = fss.KeyBatch(fss.RANGE, 32, n, DEV)
+        fss.fss_keygen_batch([(11, 1, 0, 5, 7000, r, kb, 0)], q)
+        torch.cuda.synchronize()
+        outs.append(from_device(1, 32, n, B(kb.key[0], kb.bytes_per_party)).tobytes())
+        fss.shutdown()
+    assert outs[0] == outs[1]
