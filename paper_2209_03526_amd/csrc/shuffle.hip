@@ -14,6 +14,8 @@
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/oblivgm_fss.h"
 #include "aes_gfx950.hpp"
 #include "common.hpp"
@@ -351,6 +353,20 @@ int gather2(uint64_t nrows, uint32_t nwords, const uint32_t* p_out, const uint32
     return check_launch("k_gather2_xor");
 }
 
+// A second stream of the library's own (default priority, non-blocking) on
+// which the mask tables are made while the permutations are sorted on the
+// caller's stream: the first is AES work, the second memory-bound, and
+// nothing joins them before the gathers.  Created once; ordered against the
+// caller's stream with events only.
+hipStream_t side_stream() {
+    static hipStream_t side = nullptr;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) side = nullptr;
+    });
+    return side;
+}
+
 // Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
@@ -372,15 +388,36 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     void* temp = ws.take<uint8_t>(tb);
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
     int rc = FSS_OK;
-    // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1
+    // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1.
+    // Masks on the side stream (after everything already on s), permutations
+    // on s; s waits for the masks before the first gather.
+    hipStream_t ms = side_stream();
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool forked = false;
+    if (ms && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess && hipEventRecord(fork, s) == hipSuccess &&
+        hipStreamWaitEvent(ms, fork, 0) == hipSuccess)
+        forked = true;
+    const hipStream_t mstream = forked ? ms : s;       // without a side stream, all on s
+    if (!rc) rc = mask(k12, kT12, nrows, nwords, t12, mstream);
+    if (!rc) rc = mask(k12, kR2, nrows, nwords, out[1], mstream);       // R2
+    if (!rc) rc = mask(k23, kT23, nrows, nwords, t23, mstream);
+    if (!rc) rc = mask(k31, kT31, nrows, nwords, t31, mstream);
+    if (!rc) rc = mask(k31, kR1, nrows, nwords, out[0], mstream);       // R1
+    const bool recorded = forked && hipEventRecord(join, ms) == hipSuccess;
+    // the permutations on the caller's stream, side by side with the masks
     if (!rc) rc = make_perm(k12, kP12, nrows, keys, keys_sorted, idx, p12, temp, tb, s);
     if (!rc) rc = make_perm(k23, kP23, nrows, keys, keys_sorted, idx, p23, temp, tb, s);
     if (!rc) rc = make_perm(k31, kP31, nrows, keys, keys_sorted, idx, p31, temp, tb, s);
-    if (!rc) rc = mask(k12, kT12, nrows, nwords, t12, s);
-    if (!rc) rc = mask(k12, kR2, nrows, nwords, out[1], s);       // R2
-    if (!rc) rc = mask(k23, kT23, nrows, nwords, t23, s);
-    if (!rc) rc = mask(k31, kT31, nrows, nwords, t31, s);
-    if (!rc) rc = mask(k31, kR1, nrows, nwords, out[0], s);       // R1
+    // the join is waited for whatever happened above, so that no work queued on
+    // the side stream outlives the caller's view of this call
+    const bool joined = !forked || (recorded && hipStreamWaitEvent(s, join, 0) == hipSuccess);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (!joined) {
+        (void)hipStreamSynchronize(ms);       // the side stream drains before the failure is reported
+        if (!rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
+    }
     // CS1: X1 = pi31[pi12(D1 ^ D2 ^ T12) ^ T31]  (both permutations in one pass)
     if (!rc) rc = gather2(nrows, nwords, p31, p12, d[0], d[1], t12, t31, nullptr, nullptr, x1, s);
     // CS2: Y1 = pi12(D3 ^ T12); C1 = pi23(X1 ^ T23) ^ R2
