@@ -8,7 +8,7 @@ Plan semantics (what both the oracle and the product compute):
    the dealer makes per-row keys with ``pred = k`` (Sec. V-C token generation,
    masked-input form), the servers open xhat = x0 + x1 + r (Sec. V-C), and each
    party evaluates its keys on xhat, giving one packed share bit per row
-   (Alg. 3 line "evaluate" in its masked-input form; bits packed as in
+   (the evaluation step of Alg. 3, in its masked-input form; bits packed as in
    Sec. VII-A).
 2. Per query vertex, then per query edge, its predicates are combined by AND
    (Sec. V-D, multi-predicate aggregation) as a left fold in plan order.  A
