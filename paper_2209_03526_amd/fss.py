@@ -65,7 +65,7 @@ class fss_eval_all_req(ctypes.Structure):
 
 def _load():
     if not os.path.exists(_build.LIB):
-        raise ImportError(f"HIP library not built: {_build.LIB} (run __graft_entry__.build())")
+        raise ImportError(f"HIP library not built: {_build.LIB} (build it: python paper_2209_03526_amd/build.py)")
     lib = ctypes.CDLL(_build.LIB)
     P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
     sigs = {
