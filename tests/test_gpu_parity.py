@@ -276,6 +276,34 @@ def test_match_er_1024(fss):
     assert res == omatch.brute_force_pairs(g, q) and len(res) > 0
 
 
+def test_match_many_predicates(fss):
+    """More predicate-party evaluations than one launch carries (12 predicates
+    on a 3-vertex path: 24 evaluations): shares equal the oracle's, and the
+    reconstruction equals brute force."""
+    g = synth.tiny_graph(8, n_vertices=40, n_edges=400, label_range=3, attr_range=64)
+    preds = []
+    for k in range(12):
+        t = k % 5                      # vertices 0..2 and both query edges; predicates on one
+        if t < 3:                      # target agree (same label, overlapping ranges)
+            preds.append(synth.Pred(t, "range", "attr", lo=k // 3, hi=60 - k) if k >= 5 else
+                         synth.Pred(t, "eq", "label", a=t % 3))
+        else:
+            preds.append(synth.Pred(t, "range", "weight", lo=k // 4, hi=62 - k) if k >= 5 else
+                         synth.Pred(t, "eq", "label", a=t % 2))
+    q = synth.Query(77, 3, preds)
+    seed = 99
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    plan = run_query_gpu(fss, g, q, shares, masks, seed)
+    got = plan_outputs(plan, q, g)
+    want = omatch.run_plan(32, seed, g, q, shares, masks)
+    for j in range(q.n_qv - 1):
+        for b in range(2):
+            np.testing.assert_array_equal(got[j][b], want[j][b])
+    res = omatch.results_from_bits(g, q, omatch.reconstruct(got, g.n_edges))
+    assert res == omatch.brute_force(g, q) and len(res) > 0
+
+
 def test_match_rejects_bad_plans(fss):
     g, q = synth.config1(1)
     kb = fss.KeyBatch(fss.EQ, 32, g.n_vertices)
