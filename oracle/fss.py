@@ -65,6 +65,7 @@ def lib():
             "oracle_aes128_encrypt": ([P, P, P], None),
             "oracle_prg": ([i32, P, P], None),
             "oracle_rng_block": ([u64, u32, u32, u32, u32, u32, P], None),
+            "oracle_rng_blocks": ([u64, u32, u32, u32, u32, u32, sz, P], None),
             "oracle_dpf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
             "oracle_dcf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
             "oracle_dpf_eval_points": ([i32, P, u32, P, sz, P], None),
@@ -131,6 +132,15 @@ def rng_block(seed: int, domain: int, j: int, query: int, pred: int, elem: int) 
     out = np.zeros(16, np.uint8)
     lib().oracle_rng_block(seed, domain, j, query, pred, elem, _p(out))
     return out.tobytes()
+
+
+def rng_blocks(seed: int, domain: int, j: int, query: int, pred: int, elem0: int, count: int) -> np.ndarray:
+    """Blocks (domain, j, query, pred, elem0 + i) for i < count, as a (count, 16)
+    uint8 array: rng_block for consecutive counters."""
+    out = np.zeros((count, 16), np.uint8)
+    if count:
+        lib().oracle_rng_blocks(seed, domain, j, query, pred, elem0, count, _p(out))
+    return out
 
 
 # --------------------------------------------------------------------------- DPF / DCF

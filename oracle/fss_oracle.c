@@ -602,6 +602,19 @@ void oracle_masks(uint64_t seed, uint32_t query, uint32_t pred, uint32_t row_off
     }
 }
 
+/* Consecutive counter blocks: out[16*i ..] = block (domain, j, query, pred,
+ * elem0 + i) under K_seed, i = 0 .. count-1 (the same blocks as
+ * oracle_rng_block, one key schedule for all of them). */
+void oracle_rng_blocks(uint64_t seed, uint32_t domain, uint32_t j, uint32_t query, uint32_t pred, uint32_t elem0,
+                       size_t count, uint8_t *out)
+{
+    uint8_t rk[176];
+    oracle_rng_key(seed, rk);
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < (long long)count; i++)
+        oracle_rng_block_rk(rk, domain, j, query, pred, elem0 + (uint32_t)i, out + 16 * i);
+}
+
 size_t oracle_sizeof_dpf_key(void) { return sizeof(oracle_dpf_key); }
 size_t oracle_sizeof_dcf_key(void) { return sizeof(oracle_dcf_key); }
 size_t oracle_sizeof_range_key(void) { return sizeof(oracle_range_key); }

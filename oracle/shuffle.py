@@ -35,22 +35,18 @@ P12, P23, P31 = 0, 1, 2
 
 
 def mask_table(seed: int, table: int, nrows: int, nwords: int) -> np.ndarray:
+    """Word k = r * W + w is little-endian word (k mod 4) of block k div 4."""
     total = nrows * nwords
-    out = np.zeros(total, np.uint32)
-    for blk in range((total + 3) // 4):
-        b = fss.rng_block(seed, 6, table, nwords, 0, blk)
-        for q in range(4):
-            k = 4 * blk + q
-            if k < total:
-                out[k] = int.from_bytes(b[4 * q:4 * q + 4], "little")
-    return out.reshape(nrows, nwords)
+    blocks = fss.rng_blocks(seed, 6, table, nwords, 0, 0, (total + 3) // 4)
+    words = blocks.view("<u4").reshape(-1)          # block m -> words 4m .. 4m + 3
+    return words[:total].astype(np.uint32).reshape(nrows, nwords)
 
 
 def permutation(seed: int, perm_id: int, nrows: int) -> np.ndarray:
-    keys = np.zeros(nrows, np.uint64)
-    for r in range(nrows):
-        b = fss.rng_block(seed, 6, 16 + perm_id, 0, 0, r)
-        keys[r] = int.from_bytes(b[:8], "little")
+    """Stable argsort of the rows' keys: key of row r = bytes 0-7 of its block,
+    little-endian."""
+    blocks = fss.rng_blocks(seed, 6, 16 + perm_id, 0, 0, 0, nrows)
+    keys = blocks[:, :8].copy().view("<u8").reshape(-1)
     return np.argsort(keys, kind="stable")
 
 

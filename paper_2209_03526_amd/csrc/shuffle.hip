@@ -5,16 +5,17 @@
 // Each pair of servers derives from its seed, with the counter-mode generator
 // (domain 6), its permutations (stable sort of one 64-bit key per row) and
 // mask tables (one AES block per four words); applying a permutation is the
-// row gather out[i] = in[perm[i]].  The sequence of Alg. 5 is kept: X1, Y1
-// and C1 are stored as the messages one server computes and sends; a message
-// built with two permutations (X1, C2) is gathered through both in one pass,
-// and C2 is folded into CS2's R3 = C1 ^ C2 as it is formed.
+// row gather out[i] = in[perm[i]].  The servers' steps of Alg. 5 are grouped
+// by the pair permutation they apply: one launch per round (pi12, pi31, pi23)
+// forms every table that pair permutes in that round, with the pair's mask
+// computed where it is XORed, so that each mask word is made once, no mask
+// table is stored, and the AES overlaps with the rounds' random-row reads.
+// The messages X1 and Y1 are stored between rounds; C1 and C2 meet in R3 =
+// C1 ^ C2 as they are formed.
 
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
-
-#include <mutex>
 
 #include "../../include/oblivgm_fss.h"
 #include "aes_gfx950.hpp"
@@ -48,31 +49,12 @@ unsigned aes_grid(uint64_t items) {
     return (unsigned)(need < 1 ? 1 : (need < cap ? need : cap));
 }
 
-// Mask table `table` of the pair seed: word k = r*W + w is word (k mod 4) of
-// block (6, table, W, 0, k div 4).  Block m gives words 4m .. 4m+3.
-__global__ __launch_bounds__(kBlock) void k_mask_table(RoundKeys rk, uint32_t table, uint32_t nwords, uint64_t total,
-                                                      uint32_t vec, uint32_t* __restrict__ out) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tab.t0);
-    __syncthreads();
-    const LaneOff lo = lane_offset();
-    const uint64_t nblk = (total + 3) / 4;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x; m < nblk; m += stride) {
-        const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, (uint32_t)m), ArgKey{rk}, tab, lo);
-        if (vec && 4 * m + 4 <= total) {
-            *(uint4*)(out + 4 * m) = b;
-        } else {
-            const uint32_t v[4] = {b.x, b.y, b.z, b.w};
-            for (int q = 0; q < 4; q++)
-                if (4 * m + q < total) out[4 * m + q] = v[q];
-        }
-    }
-}
-
 // Sort keys of permutation p: row r -> words 0-1 of block (6, 16 + p, 0, 0, r).
-__global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, uint64_t nrows,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+// Besides the key, each row gets its run id (the key's top hb bits, in bits
+// 0 .. hb-1) and its row number, the pair the radix pass sorts.
+__global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, uint64_t nrows, uint32_t hb,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                     uint32_t* __restrict__ idx) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tab.t0);
     __syncthreads();
@@ -81,77 +63,170 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, 
     for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += stride) {
         const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab, lo);
         keys[r] = (uint64_t)b.x | ((uint64_t)b.y << 32);
+        ids[r] = hb ? b.y >> (32 - hb) : 0u;
         idx[r] = (uint32_t)r;
     }
 }
 
-// out[i] = a[p] ^ b[p] ^ c[p] ^ post[i], p = perm[i] (absent tables skipped).
-// With vec (record width a multiple of 4 words, every table 16-byte aligned)
-// one thread moves 4 words with 16-byte loads and stores, else one word; row
-// and word come from 32-bit division (rows < 2^31, checked by the callers).
-__global__ void k_gather_xor(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ perm,
-                             const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
-                             const uint32_t* __restrict__ c, const uint32_t* __restrict__ post,
-                             uint32_t* __restrict__ out) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    if (vec) {
-        const uint32_t q = nwords >> 2;                 // uint4 per record
-        const uint64_t total = nrows * q;
-        for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
-            const uint32_t i = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)i * q);
-            const uint64_t src = (uint64_t)perm[i] * q + w;
-            uint4 v = ((const uint4*)a)[src];
-            if (b) v = xor4(v, ((const uint4*)b)[src]);
-            if (c) v = xor4(v, ((const uint4*)c)[src]);
-            if (post) v = xor4(v, ((const uint4*)post)[k]);
-            ((uint4*)out)[k] = v;
-        }
-        return;
+// The permutation is the stable argsort of the 64-bit keys.  It is made in two
+// steps: a stable radix sort of the rows by run id (the top hb key bits, hb =
+// ceil(log2 n) - 6, so that a run holds 64 rows on average), then each run
+// ordered by its full keys.  Inside a run the radix sort has kept the rows in
+// their original order, so "equal key, earlier position" is "equal key,
+// smaller row" and the result is the full stable argsort.
+
+// starts[b] = first position of run b in the sorted run ids (lower bound by
+// binary search), b = 0 .. 2^hb; starts[2^hb] = n.  A lower bound is
+// non-decreasing in b over any array, so the runs always partition [0, n):
+// the ranking below stays in bounds whatever the ids hold.
+__global__ void k_run_starts(uint64_t n, uint32_t hb, const uint32_t* __restrict__ ids,
+                             uint32_t* __restrict__ starts) {
+    const uint32_t nruns = 1u << hb;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nruns) return;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (ids[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    const uint64_t total = nrows * nwords;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
-        const uint32_t i = (uint32_t)(k / nwords), w = (uint32_t)(k - (uint64_t)i * nwords);
-        const uint64_t src = (uint64_t)perm[i] * nwords + w;
-        uint32_t v = a[src];
-        if (b) v ^= b[src];
-        if (c) v ^= c[src];
-        if (post) v ^= post[k];
-        out[k] = v;
+    starts[b] = (uint32_t)lo;
+}
+
+// One wavefront per run: row e of the run goes to position start + rank(e),
+// rank = number of rows of the run with a smaller key, or an equal key at an
+// earlier position.  The rows' keys are read through their row numbers,
+// taken 64 at a time into the lanes and broadcast with readlane, so any run
+// length is ordered exactly (the cost grows as the square of the length; the
+// runs of uniform keys are short).
+__global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, const uint32_t* __restrict__ starts,
+                                                   const uint64_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ rows, uint32_t* __restrict__ perm) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nruns = 1u << hb;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    // the run number is the same on every lane of the wavefront; saying so
+    // keeps the run bounds and loop counters in scalar registers
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (uint32_t b = blockIdx.x * (blockDim.x >> 6) + wave; b < nruns; b += waves) {
+        const uint32_t s = starts[b], m = starts[b + 1] - s;
+        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+            const uint32_t e = c0 + lane;
+            const bool has = e < m;
+            const uint32_t row = has ? rows[s + e] : 0u;
+            const uint64_t ke = has ? keys[row] : 0ull;
+            uint32_t rank = 0;
+            for (uint32_t j0 = 0; j0 < m; j0 += 64) {
+                const uint64_t kj = j0 + lane < m ? keys[rows[s + j0 + lane]] : 0ull;
+                const uint32_t lo = (uint32_t)kj, hi = (uint32_t)(kj >> 32);
+                const uint32_t cnt = m - j0 < 64 ? m - j0 : 64;
+                for (uint32_t t = 0; t < cnt; t++) {
+                    const uint64_t kt = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, (int)t) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)t);
+                    // no short-circuit: three compares and no branch per row
+                    rank += (uint32_t)(kt < ke) | ((uint32_t)(kt == ke) & (uint32_t)(j0 + t < e));
+                }
+            }
+            if (has) perm[s + rank] = row;
+        }
     }
 }
 
-// Two permutations in one pass: out[i] = A[q] ^ mid[p] ^ post[i] ^ post2[i]
-// with p = p_out[i], q = p_in[p] and A = a ^ b ^ c (absent tables skipped):
-// pi_out(pi_in(A) ^ mid) ^ post ^ post2 without writing pi_in(A) ^ mid.
-// vec as in k_gather_xor.
-__global__ void k_gather2_xor(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ p_out,
-                              const uint32_t* __restrict__ p_in, const uint32_t* __restrict__ a,
-                              const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
-                              const uint32_t* __restrict__ mid, const uint32_t* __restrict__ post,
-                              const uint32_t* __restrict__ post2, uint32_t* __restrict__ out) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint32_t q = vec ? nwords >> 2 : nwords;       // units (uint4 or word) per record
+// Mask of one unit of table `table` under the pair key rk: with VEC the
+// 16-byte unit u is block u of the table (the record width is a multiple of 4
+// words, so units and blocks coincide); else word u is word (u mod 4) of
+// block u div 4.
+template <bool VEC>
+__device__ __forceinline__ uint4 mask_unit(const RoundKeys& rk, uint32_t table, uint32_t nwords, uint64_t u,
+                                           const uint32_t* tab, LaneOff lo) {
+    const uint32_t blk = (uint32_t)(VEC ? u : u >> 2);
+    const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, blk), ArgKey{rk}, tab, lo);
+    if (VEC) return b;
+    const uint32_t q = (uint32_t)u & 3u;
+    return make_uint4(q == 0 ? b.x : q == 1 ? b.y : q == 2 ? b.z : b.w, 0u, 0u, 0u);
+}
+
+// An empty asm statement that the value passes through: its block is complete
+// here, in registers, and the next block's work does not move across this
+// point (two mask blocks side by side would need more than 64 VGPRs, which
+// would leave room for one workgroup per CU instead of two).  It also keeps
+// the compiler from cancelling a mask that two messages share (C1 and C2).
+__device__ __forceinline__ void pin(uint4& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w) : : "memory");
+}
+
+template <bool VEC>
+__device__ __forceinline__ uint4 load_unit(const uint32_t* __restrict__ t, uint64_t u) {
+    if (VEC) return ((const uint4*)t)[u];
+    return make_uint4(t[u], 0u, 0u, 0u);
+}
+
+template <bool VEC>
+__device__ __forceinline__ void store_unit(uint32_t* __restrict__ t, uint64_t u, uint4 v) {
+    if (VEC)
+        ((uint4*)t)[u] = v;
+    else
+        t[u] = v.x;
+}
+
+// One round of Alg. 5: the permutation of one pair of servers applied, with
+// that pair's mask T, to every table the pair permutes in that round; the
+// mask words are computed where they are XORed (a mask word is a
+// counter-mode block of its table), so no mask table is stored and the AES
+// overlaps with the random-row reads of other waves.  With p = perm[i] and
+// u the unit w of row p (k the unit w of output row i):
+//   kRound12: o0 = (g0 ^ g1 ^ T12)[p], o1 = (g2 ^ T12)[p], rout = R2
+//             (CS1's pi12(D1 ^ D2 ^ T12) and CS2's Y1 = pi12(D3 ^ T12))
+//   kRound31: o0 = (g0 ^ T31)[p], o1 = (g1 ^ T31)[p], rout = R1
+//             (CS1's X1 and CS3's pi31(Y1 ^ T31))
+//   kRound23: o0 = C1 ^ C2 with C1 = (g0 ^ T23)[p] ^ s0, C2 = (g1 ^ T23)[p] ^ s1
+//             (CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2, and R3 = C1 ^ C2)
+// Units are 16-byte quarters of a record with VEC (width a multiple of 4
+// words, every table 16-byte aligned), else words.
+enum { kRound12 = 0, kRound31 = 1, kRound23 = 2 };
+
+template <int ROUND, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_shuffle_round(uint64_t nrows, uint32_t nwords, RoundKeys rk,
+                                                        uint32_t t_mask, uint32_t r_mask,
+                                                        const uint32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ g0,
+                                                        const uint32_t* __restrict__ g1,
+                                                        const uint32_t* __restrict__ g2,
+                                                        const uint32_t* __restrict__ s0,
+                                                        const uint32_t* __restrict__ s1, uint32_t* __restrict__ o0,
+                                                        uint32_t* __restrict__ o1, uint32_t* __restrict__ rout) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tab.t0);
+    __syncthreads();
+    const LaneOff lo = lane_offset();
+    const uint32_t q = VEC ? nwords >> 2 : nwords;       // units per record
     const uint64_t total = nrows * q;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += stride) {
         const uint32_t i = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)i * q);
-        const uint32_t p = p_out[i];
-        const uint64_t sp = (uint64_t)p * q + w, sq = (uint64_t)p_in[p] * q + w;
-        if (vec) {
-            uint4 v = ((const uint4*)a)[sq];
-            if (b) v = xor4(v, ((const uint4*)b)[sq]);
-            if (c) v = xor4(v, ((const uint4*)c)[sq]);
-            if (mid) v = xor4(v, ((const uint4*)mid)[sp]);
-            if (post) v = xor4(v, ((const uint4*)post)[k]);
-            if (post2) v = xor4(v, ((const uint4*)post2)[k]);
-            ((uint4*)out)[k] = v;
+        const uint64_t u = (uint64_t)perm[i] * q + w;
+        const uint4 a = load_unit<VEC>(g0, u), b = load_unit<VEC>(g1, u);
+        uint4 t = mask_unit<VEC>(rk, t_mask, nwords, u, tab, lo);
+        pin(t);
+        if (ROUND == kRound12) {
+            const uint4 c = load_unit<VEC>(g2, u);
+            store_unit<VEC>(o0, k, xor4(xor4(a, b), t));
+            store_unit<VEC>(o1, k, xor4(c, t));
+        } else if (ROUND == kRound31) {
+            store_unit<VEC>(o0, k, xor4(a, t));
+            store_unit<VEC>(o1, k, xor4(b, t));
         } else {
-            uint32_t v = a[sq];
-            if (b) v ^= b[sq];
-            if (c) v ^= c[sq];
-            if (mid) v ^= mid[sp];
-            if (post) v ^= post[k];
-            if (post2) v ^= post2[k];
-            out[k] = v;
+            uint4 c1 = xor4(xor4(a, t), load_unit<VEC>(s0, k));
+            pin(c1);
+            const uint4 c2 = xor4(xor4(b, t), load_unit<VEC>(s1, k));
+            store_unit<VEC>(o0, k, xor4(c1, c2));
+        }
+        if (ROUND != kRound23) {
+            uint4 r = mask_unit<VEC>(rk, r_mask, nwords, k, tab, lo);
+            pin(r);
+            store_unit<VEC>(rout, k, r);
         }
     }
 }
@@ -299,133 +374,134 @@ struct Carve {
     }
 };
 
+// Top key bits the radix pass sorts: ceil(log2 n) - 6, at least 0.
+// Run-id bits the radix pass sorts: ceil(log2 n) - 6, at least 0 (at most 25
+// for n < 2^31).  The ids sit in bits 0 .. hb-1 of a 32-bit word, so the sort
+// asks for bits [0, hb): a range that ends at the top bit of the key type
+// makes rocPRIM's merge-sort path (1 Ki - 1 Mi items) build its comparison
+// mask with a full-width shift, which compares the wrong bits.
+uint32_t run_bits(uint64_t nrows) {
+    uint32_t lg = 0;
+    while ((1ull << lg) < nrows) lg++;
+    return lg > 6 ? lg - 6 : 0;
+}
+
 size_t sort_temp_bytes(uint64_t nrows) {
+    const uint32_t hb = run_bits(nrows);
+    if (!hb) return 0;
     size_t b = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nrows);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nrows, 0, (int)hb);
     return b;
 }
 
 uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
     auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
     const uint64_t tw = nrows * nwords * 4;
-    // tables T12 T23 T31 X1 Y1 C1; three permutations; sort keys in and out;
-    // the identity index; the sort's temporary storage
-    return 6 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + r(nrows * 4) + r(sort_temp_bytes(nrows)) + 4096;
+    // pi12(D1^D2^T12), Y1, X1, pi31(Y1^T31); three permutations; sort keys;
+    // run ids in and out; row numbers in and out; run starts; the sort's
+    // temporary storage
+    return 4 * r(tw) + 3 * r(nrows * 4) + r(nrows * 8) + 4 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
+           r(sort_temp_bytes(nrows)) + 4096;
 }
 
-// perm = stable argsort of the pair seed's row keys.
-int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, uint64_t* keys, uint64_t* keys_sorted,
-              uint32_t* idx, uint32_t* perm, void* temp, size_t temp_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, keys, idx);
+// perm = stable argsort of the pair seed's row keys: radix sort by run id,
+// then each run ordered by rank.
+struct PermScratch {
+    uint64_t* keys;
+    uint32_t* ids;
+    uint32_t* ids_sorted;
+    uint32_t* idx;
+    uint32_t* idx_sorted;
+    uint32_t* starts;
+    void* temp;
+    size_t temp_bytes;
+};
+
+int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch& w, uint32_t* perm, hipStream_t s) {
+    const uint32_t hb = run_bits(nrows);
+    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, hb, w.keys, w.ids,
+                       w.idx);
     int rc = check_launch("k_perm_keys");
     if (rc) return rc;
-    if (hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, perm, (int)nrows, 0, 64, s) !=
-        hipSuccess)
-        return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
-    return FSS_OK;
+    const uint32_t* ids = w.ids;
+    const uint32_t* rows = w.idx;
+    if (hb) {          // with no run-id bits there is one run, already in row order
+        size_t temp_bytes = w.temp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(w.temp, temp_bytes, w.ids, w.ids_sorted, w.idx, w.idx_sorted,
+                                               (int)nrows, 0, (int)hb, s) != hipSuccess)
+            return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
+        ids = w.ids_sorted;
+        rows = w.idx_sorted;
+    }
+    const uint64_t nruns = 1ull << hb;
+    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, s, nrows, hb, ids,
+                       w.starts);
+    rc = check_launch("k_run_starts");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, w.starts, w.keys, rows, perm);
+    return check_launch("k_rank_runs");
 }
 
-int mask(const RoundKeys& rk, uint32_t table, uint64_t nrows, uint32_t nwords, uint32_t* out, hipStream_t s) {
-    const uint64_t total = nrows * nwords;
-    const uint64_t blocks = (total + 3) / 4;
-    hipLaunchKernelGGL(k_mask_table, dim3(aes_grid(blocks)), dim3(kBlock), 0, s, rk, table, nwords, total,
-                       (uint32_t)aligned16(out), out);
-    return check_launch("k_mask_table");
+// One round of the shuffle (k_shuffle_round); the 16-byte path when the
+// width is a multiple of 4 words and every table is 16-byte aligned.
+template <int ROUND>
+int shuffle_round(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, uint32_t r_mask,
+                  const uint32_t* perm, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2,
+                  const uint32_t* s0, const uint32_t* s1, uint32_t* o0, uint32_t* o1, uint32_t* rout, hipStream_t s) {
+    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(g2) && aligned16(s0) &&
+                     aligned16(s1) && aligned16(o0) && aligned16(o1) && aligned16(rout);
+    const uint64_t units = vec ? nrows * (nwords >> 2) : nrows * nwords;
+    if (vec)
+        hipLaunchKernelGGL((k_shuffle_round<ROUND, true>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
+                           rk, t_mask, r_mask, perm, g0, g1, g2, s0, s1, o0, o1, rout);
+    else
+        hipLaunchKernelGGL((k_shuffle_round<ROUND, false>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
+                           rk, t_mask, r_mask, perm, g0, g1, g2, s0, s1, o0, o1, rout);
+    return check_launch("k_shuffle_round");
 }
 
-int gather(uint64_t nrows, uint32_t nwords, const uint32_t* perm, const uint32_t* a, const uint32_t* b,
-           const uint32_t* c, const uint32_t* post, uint32_t* out, hipStream_t s) {
-    const bool vec = (nwords & 3u) == 0 && aligned16(a) && aligned16(b) && aligned16(c) && aligned16(post) &&
-                     aligned16(out);
-    hipLaunchKernelGGL(k_gather_xor, dim3(grid_of(vec ? nrows * nwords / 4 : nrows * nwords, 256)), dim3(256), 0, s,
-                       nrows, nwords, (uint32_t)vec, perm, a, b, c, post, out);
-    return check_launch("k_gather_xor");
-}
-
-int gather2(uint64_t nrows, uint32_t nwords, const uint32_t* p_out, const uint32_t* p_in, const uint32_t* a,
-            const uint32_t* b, const uint32_t* c, const uint32_t* mid, const uint32_t* post, const uint32_t* post2,
-            uint32_t* out, hipStream_t s) {
-    const bool vec = (nwords & 3u) == 0 && aligned16(a) && aligned16(b) && aligned16(c) && aligned16(mid) &&
-                     aligned16(post) && aligned16(post2) && aligned16(out);
-    hipLaunchKernelGGL(k_gather2_xor, dim3(grid_of(vec ? nrows * nwords / 4 : nrows * nwords, 256)), dim3(256), 0, s,
-                       nrows, nwords, (uint32_t)vec, p_out, p_in, a, b, c, mid, post, post2, out);
-    return check_launch("k_gather2_xor");
-}
-
-// A second stream of the library's own (default priority, non-blocking) on
-// which the mask tables are made while the permutations are sorted on the
-// caller's stream: the first is AES work, the second memory-bound, and
-// nothing joins them before the gathers.  Created once; ordered against the
-// caller's stream with events only.
-hipStream_t side_stream() {
-    static hipStream_t side = nullptr;
-    static std::once_flag once;
-    std::call_once(once, [] {
-        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) side = nullptr;
-    });
-    return side;
-}
-
-// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
+// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.  The
+// servers' steps are grouped by the pair permutation they apply, one launch
+// per round: pi12 (CS1, CS2), pi31 (CS1, CS3), pi23 (CS2, CS3).
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
     const uint64_t tw = nrows * nwords;
     const RoundKeys k12 = seed_key(seeds[0]), k23 = seed_key(seeds[1]), k31 = seed_key(seeds[2]);
-    uint32_t* t12 = ws.take<uint32_t>(tw);
-    uint32_t* t23 = ws.take<uint32_t>(tw);
-    uint32_t* t31 = ws.take<uint32_t>(tw);
-    uint32_t* x1 = ws.take<uint32_t>(tw);
-    uint32_t* y1 = ws.take<uint32_t>(tw);
-    uint32_t* c1 = ws.take<uint32_t>(tw);
+    uint32_t* z = ws.take<uint32_t>(tw);       // CS1: pi12(D1 ^ D2 ^ T12)
+    uint32_t* y1 = ws.take<uint32_t>(tw);      // CS2 -> CS3: Y1
+    uint32_t* x1 = ws.take<uint32_t>(tw);      // CS1 -> CS2: X1
+    uint32_t* v = ws.take<uint32_t>(tw);       // CS3: pi31(Y1 ^ T31)
     uint32_t* p12 = ws.take<uint32_t>(nrows);
     uint32_t* p23 = ws.take<uint32_t>(nrows);
     uint32_t* p31 = ws.take<uint32_t>(nrows);
-    uint64_t* keys = ws.take<uint64_t>(nrows);
-    uint64_t* keys_sorted = ws.take<uint64_t>(nrows);
-    uint32_t* idx = ws.take<uint32_t>(nrows);
-    const size_t tb = sort_temp_bytes(nrows);
-    void* temp = ws.take<uint8_t>(tb);
+    PermScratch pw;
+    pw.keys = ws.take<uint64_t>(nrows);
+    pw.ids = ws.take<uint32_t>(nrows);
+    pw.ids_sorted = ws.take<uint32_t>(nrows);
+    pw.idx = ws.take<uint32_t>(nrows);
+    pw.idx_sorted = ws.take<uint32_t>(nrows);
+    pw.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
+    pw.temp_bytes = sort_temp_bytes(nrows);
+    pw.temp = ws.take<uint8_t>(pw.temp_bytes);
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
-    int rc = FSS_OK;
     // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1.
-    // Masks on the side stream (after everything already on s), permutations
-    // on s; s waits for the masks before the first gather.
-    hipStream_t ms = side_stream();
-    hipEvent_t fork = nullptr, join = nullptr;
-    bool forked = false;
-    if (ms && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
-        hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess && hipEventRecord(fork, s) == hipSuccess &&
-        hipStreamWaitEvent(ms, fork, 0) == hipSuccess)
-        forked = true;
-    const hipStream_t mstream = forked ? ms : s;       // without a side stream, all on s
-    if (!rc) rc = mask(k12, kT12, nrows, nwords, t12, mstream);
-    if (!rc) rc = mask(k12, kR2, nrows, nwords, out[1], mstream);       // R2
-    if (!rc) rc = mask(k23, kT23, nrows, nwords, t23, mstream);
-    if (!rc) rc = mask(k31, kT31, nrows, nwords, t31, mstream);
-    if (!rc) rc = mask(k31, kR1, nrows, nwords, out[0], mstream);       // R1
-    const bool recorded = forked && hipEventRecord(join, ms) == hipSuccess;
-    // the permutations on the caller's stream, side by side with the masks
-    if (!rc) rc = make_perm(k12, kP12, nrows, keys, keys_sorted, idx, p12, temp, tb, s);
-    if (!rc) rc = make_perm(k23, kP23, nrows, keys, keys_sorted, idx, p23, temp, tb, s);
-    if (!rc) rc = make_perm(k31, kP31, nrows, keys, keys_sorted, idx, p31, temp, tb, s);
-    // the join is waited for whatever happened above, so that no work queued on
-    // the side stream outlives the caller's view of this call
-    const bool joined = !forked || (recorded && hipStreamWaitEvent(s, join, 0) == hipSuccess);
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
-    if (!joined) {
-        (void)hipStreamSynchronize(ms);       // the side stream drains before the failure is reported
-        if (!rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
-    }
-    // CS1: X1 = pi31[pi12(D1 ^ D2 ^ T12) ^ T31]  (both permutations in one pass)
-    if (!rc) rc = gather2(nrows, nwords, p31, p12, d[0], d[1], t12, t31, nullptr, nullptr, x1, s);
-    // CS2: Y1 = pi12(D3 ^ T12); C1 = pi23(X1 ^ T23) ^ R2
-    if (!rc) rc = gather(nrows, nwords, p12, d[2], t12, nullptr, nullptr, y1, s);
-    if (!rc) rc = gather(nrows, nwords, p23, x1, t23, nullptr, out[1], c1, s);
-    // CS3: C2 = pi23[pi31(Y1 ^ T31) ^ T23] ^ R1, and CS2's R3 = C1 ^ C2, in one
-    // pass (with the servers simulated together, C2 need not be stored)
-    if (!rc) rc = gather2(nrows, nwords, p23, p31, y1, t31, nullptr, t23, out[0], c1, out[2], s);
+    int rc = make_perm(k12, kP12, nrows, pw, p12, s);
+    if (!rc) rc = make_perm(k23, kP23, nrows, pw, p23, s);
+    if (!rc) rc = make_perm(k31, kP31, nrows, pw, p31, s);
+    // pi12: CS1 forms pi12(D1 ^ D2 ^ T12), CS2 forms Y1 = pi12(D3 ^ T12); R2 drawn
+    if (!rc)
+        rc = shuffle_round<kRound12>(nrows, nwords, k12, kT12, kR2, p12, d[0], d[1], d[2], nullptr, nullptr, z, y1,
+                                     out[1], s);
+    // pi31: CS1 forms X1 = pi31(pi12(...) ^ T31), CS3 forms pi31(Y1 ^ T31); R1 drawn
+    if (!rc)
+        rc = shuffle_round<kRound31>(nrows, nwords, k31, kT31, kR1, p31, z, y1, nullptr, nullptr, nullptr, x1, v,
+                                     out[0], s);
+    // pi23: CS2 forms C1 = pi23(X1 ^ T23) ^ R2, CS3 forms C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
+    // and R3 = C1 ^ C2 (with the servers simulated together, C1 and C2 are not stored)
+    if (!rc)
+        rc = shuffle_round<kRound23>(nrows, nwords, k23, kT23, 0u, p23, x1, v, nullptr, out[1], out[0], out[2],
+                                     nullptr, nullptr, s);
     return rc;
 }
 

@@ -30,7 +30,13 @@ def _rss_table(seed, n, w):
     return d, [s1, s2, d ^ s1 ^ s2]
 
 
-@pytest.mark.parametrize("n,w", [(1, 1), (17, 3), (1000, 8), (3000, 2)])
+# sizes: one run of rows (n <= 64); a few runs; runs longer than one wavefront;
+# 2^12 rows exactly; the word path with thousands of runs; the 16-byte path
+# with 2^11 runs over a ragged 2^16 + 37 rows.  The radix pass takes its
+# single-block path up to 1024 rows, its merge path up to 2^20 and its
+# one-sweep path above: 2^20 + 100 rows cover the last.
+@pytest.mark.parametrize("n,w", [(1, 1), (17, 3), (64, 4), (1000, 8), (3000, 2), (4096, 4), (5000, 3),
+                                 (65573, 4), ((1 << 20) + 100, 4)])
 def test_shuffle_parity(fss, n, w):
     d, sh = _rss_table(n + w, n, w)
     seeds = (101, 202, 303)
@@ -42,6 +48,34 @@ def test_shuffle_parity(fss, n, w):
     for i in range(3):
         np.testing.assert_array_equal(got[i], want[i])
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], d[osh.composed_permutation(*seeds, n)])
+
+
+def test_shuffle_full_size_is_a_permutation(fss):
+    """At 2^22 records of 64 bytes (the measured size), where the oracle's
+    permutations are out of reach: every record comes out whole, each exactly
+    once, in an order that is not the input's, and no share alone is the table."""
+    n, w = 1 << 22, 16
+    g = torch.Generator(device=DEV).manual_seed(5)
+    row = torch.arange(n, dtype=torch.int64, device=DEV)
+    cols = torch.arange(w, dtype=torch.int64, device=DEV)
+    d = (row[:, None] * 0x9E3779B1 + cols[None, :] * 0x85EBCA77) & 0xFFFFFFFF     # word 0: the row number
+    d[:, 0] = row
+    d32 = (d - (d >= 2**31).to(torch.int64) * 2**32).to(torch.int32)
+    del d
+    s1 = torch.randint(-2**31, 2**31, (n, w), dtype=torch.int32, device=DEV, generator=g)
+    s2 = torch.randint(-2**31, 2**31, (n, w), dtype=torch.int32, device=DEV, generator=g)
+    sh = [s1.ravel(), s2.ravel(), (d32 ^ s1 ^ s2).ravel()]
+    del s1, s2
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_shuffle(n, w, sh, (41, 42, 43), out)
+    rec = (out[0] ^ out[1] ^ out[2]).view(n, w)
+    torch.cuda.synchronize()
+    ids = rec[:, 0].to(torch.int64) & 0xFFFFFFFF
+    assert torch.equal(torch.sort(ids).values, row)
+    assert torch.equal(rec, d32[ids])
+    assert (ids != row).float().mean().item() > 0.99
+    for o in out:
+        assert not torch.equal(o.view(n, w), d32)
 
 
 @pytest.mark.parametrize("n,w", [(1000, 8), (513, 4)])

@@ -70,3 +70,23 @@ def test_fetch_case2_all_matches():
     got = fetched[0] ^ fetched[1] ^ fetched[2]
     assert keep.size == x.sum()
     assert sorted(map(tuple, got.tolist())) == sorted(map(tuple, d[x == 1].tolist()))
+
+
+def test_batched_blocks_are_the_single_blocks():
+    """The batched generator returns rng_block's blocks for consecutive
+    counters, so the mask tables and sort keys built from it follow their
+    per-word and per-row definitions."""
+    from oracle import fss as ofss
+    got = ofss.rng_blocks(77, 6, 4, 9, 0, 2**32 - 3, 6)
+    for i in range(6):
+        assert got[i].tobytes() == ofss.rng_block(77, 6, 4, 9, 0, (2**32 - 3 + i) % 2**32)
+    n, w = 7, 3
+    t = osh.mask_table(5, osh.T31, n, w)
+    for r in range(n):
+        for c in range(w):
+            k = r * w + c
+            b = ofss.rng_block(5, 6, osh.T31, w, 0, k // 4)
+            assert int(t[r, c]) == int.from_bytes(b[4 * (k % 4):4 * (k % 4) + 4], "little")
+    keys = [int.from_bytes(ofss.rng_block(5, 6, 16 + osh.P23, 0, 0, r)[:8], "little") for r in range(50)]
+    np.testing.assert_array_equal(osh.permutation(5, osh.P23, 50),
+                                  sorted(range(50), key=lambda r: (keys[r], r)))
