@@ -50,11 +50,11 @@ unsigned aes_grid(uint64_t items) {
 }
 
 // Sort keys of permutation p: row r -> words 0-1 of block (6, 16 + p, 0, 0, r).
-// Besides the key, each row gets its run id (the key's top hb bits, in bits
-// 0 .. hb-1) and its row number, the pair the radix pass sorts.
+// The key is stored rotated left by hb bits, so that its top hb bits (the
+// row's run id) sit in bits 0 .. hb-1, the range the radix pass sorts, and
+// the whole key travels with it; the row number goes beside it.
 __global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, uint64_t nrows, uint32_t hb,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
-                                                     uint32_t* __restrict__ idx) {
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tab.t0);
     __syncthreads();
@@ -62,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, 
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += stride) {
         const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab, lo);
-        keys[r] = (uint64_t)b.x | ((uint64_t)b.y << 32);
-        ids[r] = hb ? b.y >> (32 - hb) : 0u;
+        const uint64_t key = (uint64_t)b.x | ((uint64_t)b.y << 32);
+        keys[r] = hb ? (key << hb) | (key >> (64 - hb)) : key;
         idx[r] = (uint32_t)r;
     }
 }
@@ -75,19 +75,20 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, 
 // their original order, so "equal key, earlier position" is "equal key,
 // smaller row" and the result is the full stable argsort.
 
-// starts[b] = first position of run b in the sorted run ids (lower bound by
-// binary search), b = 0 .. 2^hb; starts[2^hb] = n.  A lower bound is
+// starts[b] = first position of run b in the sorted keys (lower bound of run
+// id b by binary search), b = 0 .. 2^hb; starts[2^hb] = n.  A lower bound is
 // non-decreasing in b over any array, so the runs always partition [0, n):
-// the ranking below stays in bounds whatever the ids hold.
-__global__ void k_run_starts(uint64_t n, uint32_t hb, const uint32_t* __restrict__ ids,
+// the ranking below stays in bounds whatever the sort returned.
+__global__ void k_run_starts(uint64_t n, uint32_t hb, const uint64_t* __restrict__ keys,
                              uint32_t* __restrict__ starts) {
     const uint32_t nruns = 1u << hb;
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nruns) return;
+    const uint32_t id_mask = nruns - 1u;
     uint64_t lo = 0, hi = n;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (ids[mid] < b)
+        if (((uint32_t)keys[mid] & id_mask) < b)
             lo = mid + 1;
         else
             hi = mid;
@@ -95,41 +96,56 @@ __global__ void k_run_starts(uint64_t n, uint32_t hb, const uint32_t* __restrict
     starts[b] = (uint32_t)lo;
 }
 
+// Broadcast of lane t's 64-bit value to the whole wavefront (t uniform).
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t t) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)t);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // One wavefront per run: row e of the run goes to position start + rank(e),
 // rank = number of rows of the run with a smaller key, or an equal key at an
-// earlier position.  The rows' keys are read through their row numbers,
-// taken 64 at a time into the lanes and broadcast with readlane, so any run
-// length is ordered exactly (the cost grows as the square of the length; the
-// runs of uniform keys are short).
+// earlier position.  The run's keys are taken 64 at a time into the lanes and
+// broadcast with readlane, so any run length is ordered exactly (the cost
+// grows as the square of the length; the runs of uniform keys are short).
+// All keys of a run share their id bits (bits 0 .. hb-1 of the rotated key);
+// when the run has at most 2^hb rows those bits are replaced by the row's
+// position in the run, which makes every key of the run distinct and ordered
+// as (key, position), so one compare per row does.
 __global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, const uint32_t* __restrict__ starts,
                                                    const uint64_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ rows, uint32_t* __restrict__ perm) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t nruns = 1u << hb;
+    const uint64_t id_mask = (uint64_t)(nruns - 1u);
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     // the run number is the same on every lane of the wavefront; saying so
     // keeps the run bounds and loop counters in scalar registers
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (uint32_t b = blockIdx.x * (blockDim.x >> 6) + wave; b < nruns; b += waves) {
         const uint32_t s = starts[b], m = starts[b + 1] - s;
+        const bool distinct = m <= nruns;
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const uint32_t e = c0 + lane;
             const bool has = e < m;
-            const uint32_t row = has ? rows[s + e] : 0u;
-            const uint64_t ke = has ? keys[row] : 0ull;
+            uint64_t ke = has ? keys[s + e] : 0ull;
+            if (distinct) ke = (ke & ~id_mask) | e;
             uint32_t rank = 0;
             for (uint32_t j0 = 0; j0 < m; j0 += 64) {
-                const uint64_t kj = j0 + lane < m ? keys[rows[s + j0 + lane]] : 0ull;
-                const uint32_t lo = (uint32_t)kj, hi = (uint32_t)(kj >> 32);
-                const uint32_t cnt = m - j0 < 64 ? m - j0 : 64;
-                for (uint32_t t = 0; t < cnt; t++) {
-                    const uint64_t kt = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, (int)t) << 32) |
-                                        (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)t);
+                uint64_t kj = j0 + lane < m ? keys[s + j0 + lane] : 0ull;
+                const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)(m - j0 < 64 ? m - j0 : 64));
+                if (distinct) {
+                    kj = (kj & ~id_mask) | (j0 + lane);
+                    for (uint32_t t = 0; t < cnt; t++) rank += (uint32_t)(lane_value(kj, t) < ke);
+                } else {
                     // no short-circuit: three compares and no branch per row
-                    rank += (uint32_t)(kt < ke) | ((uint32_t)(kt == ke) & (uint32_t)(j0 + t < e));
+                    for (uint32_t t = 0; t < cnt; t++) {
+                        const uint64_t kt = lane_value(kj, t);
+                        rank += (uint32_t)(kt < ke) | ((uint32_t)(kt == ke) & (uint32_t)(j0 + t < e));
+                    }
                 }
             }
-            if (has) perm[s + rank] = row;
+            if (has) perm[s + rank] = rows[s + e];
         }
     }
 }
@@ -376,8 +392,8 @@ struct Carve {
 
 // Top key bits the radix pass sorts: ceil(log2 n) - 6, at least 0.
 // Run-id bits the radix pass sorts: ceil(log2 n) - 6, at least 0 (at most 25
-// for n < 2^31).  The ids sit in bits 0 .. hb-1 of a 32-bit word, so the sort
-// asks for bits [0, hb): a range that ends at the top bit of the key type
+// for n < 2^31).  The ids are the low hb bits of the rotated keys, so the
+// sort asks for bits [0, hb): a range that ends at the key type's top bit
 // makes rocPRIM's merge-sort path (1 Ki - 1 Mi items) build its comparison
 // mask with a full-width shift, which compares the wrong bits.
 uint32_t run_bits(uint64_t nrows) {
@@ -390,7 +406,7 @@ size_t sort_temp_bytes(uint64_t nrows) {
     const uint32_t hb = run_bits(nrows);
     if (!hb) return 0;
     size_t b = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                              (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nrows, 0, (int)hb);
     return b;
 }
@@ -398,10 +414,10 @@ size_t sort_temp_bytes(uint64_t nrows) {
 uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
     auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
     const uint64_t tw = nrows * nwords * 4;
-    // pi12(D1^D2^T12), Y1, X1, pi31(Y1^T31); three permutations; sort keys;
-    // run ids in and out; row numbers in and out; run starts; the sort's
-    // temporary storage
-    return 4 * r(tw) + 3 * r(nrows * 4) + r(nrows * 8) + 4 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
+    // pi12(D1^D2^T12), Y1, X1, pi31(Y1^T31); three permutations; rotated keys
+    // in and out; row numbers in and out; run starts; the sort's temporary
+    // storage
+    return 4 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + 2 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
            r(sort_temp_bytes(nrows)) + 4096;
 }
 
@@ -409,8 +425,7 @@ uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
 // then each run ordered by rank.
 struct PermScratch {
     uint64_t* keys;
-    uint32_t* ids;
-    uint32_t* ids_sorted;
+    uint64_t* keys_sorted;
     uint32_t* idx;
     uint32_t* idx_sorted;
     uint32_t* starts;
@@ -420,26 +435,25 @@ struct PermScratch {
 
 int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch& w, uint32_t* perm, hipStream_t s) {
     const uint32_t hb = run_bits(nrows);
-    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, hb, w.keys, w.ids,
-                       w.idx);
+    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, hb, w.keys, w.idx);
     int rc = check_launch("k_perm_keys");
     if (rc) return rc;
-    const uint32_t* ids = w.ids;
+    const uint64_t* keys = w.keys;
     const uint32_t* rows = w.idx;
     if (hb) {          // with no run-id bits there is one run, already in row order
         size_t temp_bytes = w.temp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(w.temp, temp_bytes, w.ids, w.ids_sorted, w.idx, w.idx_sorted,
+        if (hipcub::DeviceRadixSort::SortPairs(w.temp, temp_bytes, w.keys, w.keys_sorted, w.idx, w.idx_sorted,
                                                (int)nrows, 0, (int)hb, s) != hipSuccess)
             return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
-        ids = w.ids_sorted;
+        keys = w.keys_sorted;
         rows = w.idx_sorted;
     }
     const uint64_t nruns = 1ull << hb;
-    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, s, nrows, hb, ids,
+    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, s, nrows, hb, keys,
                        w.starts);
     rc = check_launch("k_run_starts");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, w.starts, w.keys, rows, perm);
+    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, w.starts, keys, rows, perm);
     return check_launch("k_rank_runs");
 }
 
@@ -477,8 +491,7 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     uint32_t* p31 = ws.take<uint32_t>(nrows);
     PermScratch pw;
     pw.keys = ws.take<uint64_t>(nrows);
-    pw.ids = ws.take<uint32_t>(nrows);
-    pw.ids_sorted = ws.take<uint32_t>(nrows);
+    pw.keys_sorted = ws.take<uint64_t>(nrows);
     pw.idx = ws.take<uint32_t>(nrows);
     pw.idx_sorted = ws.take<uint32_t>(nrows);
     pw.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
