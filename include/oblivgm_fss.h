@@ -320,6 +320,7 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
  *   taken the other way).
  * rss_and: z = x AND y on RSS shares: P_i forms x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i,
  *   then re-shares as above.
+ * The outputs d_z must not overlap the inputs.
  */
 int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf_keys[3], uint32_t counter,
                 uint32_t* const d_z[3], void* stream);
@@ -352,6 +353,7 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  *   to d_out[i] (capacity ncand x (nwords-1)), their shuffled positions to
  *   d_rows_out, their number to *d_count (device memory; read after the stream
  *   synchronises).  Workspaces: *_workspace_bytes, caller-provided device memory.
+ * Outputs must overlap neither the inputs nor the workspace.
  */
 uint64_t rss_shuffle_workspace_bytes(uint64_t nrows, uint32_t nwords);
 int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],

@@ -757,28 +757,40 @@ __global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
     const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (4 * m >= A.nwords) return;
     const LaneOff loff = lane_offset();
+    const bool whole = A.vec && 4 * m + 4 <= A.nwords;
+    // the shares are loaded before the AES, so that their latency overlaps it
+    uint4 xv[3], yv[3];
+    if (whole) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            xv[i] = ((const uint4*)A.x[i])[m];
+            yv[i] = A.y[0] ? ((const uint4*)A.y[i])[m] : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
     uint4 f[3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
         f[i] = aes128_encrypt(make_uint4(5u, A.counter, 0u, (uint32_t)m), ArgKey{A.prf[i]}, tab, loff);
-    if (A.vec && 4 * m + 4 <= A.nwords) {
+    if (whole) {
         // four whole words: 16-byte loads and stores
         const uint32_t pm[4] = {pad_mask(4 * m, A.nrows), pad_mask(4 * m + 1, A.nrows), pad_mask(4 * m + 2, A.nrows),
                                 pad_mask(4 * m + 3, A.nrows)};
+        uint4 z[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             const int nx = (i + 1) % 3, pv = (i + 2) % 3;
-            const uint4 xi = ((const uint4*)A.x[i])[m];
-            uint4 z = xi;
-            if (A.y[0]) {
-                const uint4 xn = ((const uint4*)A.x[nx])[m];
-                const uint4 yi = ((const uint4*)A.y[i])[m], yn = ((const uint4*)A.y[nx])[m];
-                z = make_uint4((xi.x & yi.x) ^ (xi.x & yn.x) ^ (xn.x & yi.x), (xi.y & yi.y) ^ (xi.y & yn.y) ^ (xn.y & yi.y),
-                               (xi.z & yi.z) ^ (xi.z & yn.z) ^ (xn.z & yi.z), (xi.w & yi.w) ^ (xi.w & yn.w) ^ (xn.w & yi.w));
-            }
-            z = xor4(xor4(z, f[i]), f[pv]);
-            ((uint4*)A.z[i])[m] = make_uint4(z.x & pm[0], z.y & pm[1], z.z & pm[2], z.w & pm[3]);
+            const uint4 xi = xv[i], xn = xv[nx], yi = yv[i], yn = yv[nx];
+            z[i] = xi;
+            if (A.y[0])
+                z[i] = make_uint4((xi.x & yi.x) ^ (xi.x & yn.x) ^ (xn.x & yi.x),
+                                  (xi.y & yi.y) ^ (xi.y & yn.y) ^ (xn.y & yi.y),
+                                  (xi.z & yi.z) ^ (xi.z & yn.z) ^ (xn.z & yi.z),
+                                  (xi.w & yi.w) ^ (xi.w & yn.w) ^ (xn.w & yi.w));
+            z[i] = xor4(xor4(z[i], f[i]), f[pv]);
         }
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+            ((uint4*)A.z[i])[m] = make_uint4(z[i].x & pm[0], z[i].y & pm[1], z[i].z & pm[2], z[i].w & pm[3]);
         return;
     }
 #pragma unroll
