@@ -112,7 +112,9 @@ __device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t t) {
 // when the run has at most 2^hb rows those bits are replaced by the row's
 // position in the run, which makes every key of the run distinct and ordered
 // as (key, position), so one compare per row does.
-__global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, const uint32_t* __restrict__ starts,
+// With `inverse` the kernel writes the inverse permutation instead:
+// out[row] = its position.
+__global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, uint32_t inverse, const uint32_t* __restrict__ starts,
                                                    const uint64_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ rows, uint32_t* __restrict__ perm) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -145,7 +147,12 @@ __global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, const uint32_t* 
                     }
                 }
             }
-            if (has) perm[s + rank] = rows[s + e];
+            if (has) {
+                if (inverse)
+                    perm[rows[s + e]] = s + rank;
+                else
+                    perm[s + rank] = rows[s + e];
+            }
         }
     }
 }
@@ -187,32 +194,71 @@ __device__ __forceinline__ void store_unit(uint32_t* __restrict__ t, uint64_t u,
         t[u] = v.x;
 }
 
-// One round of Alg. 5: the permutation of one pair of servers applied, with
-// that pair's mask T, to every table the pair permutes in that round; the
-// mask words are computed where they are XORed (a mask word is a
+// One round of Alg. 5 is the permutation of one pair of servers applied, with
+// that pair's mask T, to every table the pair permutes in that round.  The
+// kernels compute the mask words where they XOR them (a mask word is a
 // counter-mode block of its table), so no mask table is stored and the AES
-// overlaps with the random-row reads of other waves.  With p = perm[i] and
-// u the unit w of row p (k the unit w of output row i):
-//   kRound12: o0 = (g0 ^ g1 ^ T12)[p], o1 = (g2 ^ T12)[p], rout = R2
-//             (CS1's pi12(D1 ^ D2 ^ T12) and CS2's Y1 = pi12(D3 ^ T12))
-//   kRound31: o0 = (g0 ^ T31)[p], o1 = (g1 ^ T31)[p], rout = R1
-//             (CS1's X1 and CS3's pi31(Y1 ^ T31))
-//   kRound23: o0 = C1 ^ C2 with C1 = (g0 ^ T23)[p] ^ s0, C2 = (g1 ^ T23)[p] ^ s1
-//             (CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2, and R3 = C1 ^ C2)
-// Units are 16-byte quarters of a record with VEC (width a multiple of 4
-// words, every table 16-byte aligned), else words.
-enum { kRound12 = 0, kRound31 = 1, kRound23 = 2 };
+// overlaps with the rounds' random-row traffic.  Units are 16-byte quarters
+// of a record with VEC (width a multiple of 4 words, every table 16-byte
+// aligned), else words.
+enum { kRound12 = 0, kRound31 = 1 };
 
+// Rounds pi12 and pi31 as scatters: source row j of the permuted tables goes
+// to output row inv[j] (inv the inverse permutation), so the tables are read
+// in order and written at random rows; the pair mask T is indexed by the
+// source row and R by the output row:
+//   kRound12: o0[inv[j]] = (g0 ^ g1 ^ T12)[j], o1[inv[j]] = (g2 ^ T12)[j], rout = R2
+//             (CS1's pi12(D1 ^ D2 ^ T12) and CS2's Y1 = pi12(D3 ^ T12))
+//   kRound31: o0[inv[j]] = (g0 ^ T31)[j],      o1[inv[j]] = (g1 ^ T31)[j], rout = R1
+//             (CS1's X1 and CS3's pi31(Y1 ^ T31))
 template <int ROUND, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_shuffle_round(uint64_t nrows, uint32_t nwords, RoundKeys rk,
-                                                        uint32_t t_mask, uint32_t r_mask,
-                                                        const uint32_t* __restrict__ perm,
+__global__ __launch_bounds__(kBlock) void k_shuffle_scatter(uint64_t nrows, uint32_t nwords, RoundKeys rk,
+                                                          uint32_t t_mask, uint32_t r_mask,
+                                                          const uint32_t* __restrict__ inv,
+                                                          const uint32_t* __restrict__ g0,
+                                                          const uint32_t* __restrict__ g1,
+                                                          const uint32_t* __restrict__ g2, uint32_t* __restrict__ o0,
+                                                          uint32_t* __restrict__ o1, uint32_t* __restrict__ rout) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tab.t0);
+    __syncthreads();
+    const LaneOff lo = lane_offset();
+    const uint32_t q = VEC ? nwords >> 2 : nwords;       // units per record
+    const uint64_t total = nrows * q;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += stride) {
+        const uint32_t j = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)j * q);
+        const uint64_t d = (uint64_t)inv[j] * q + w;
+        const uint4 a = load_unit<VEC>(g0, k), b = load_unit<VEC>(g1, k);
+        uint4 t = mask_unit<VEC>(rk, t_mask, nwords, k, tab, lo);
+        pin(t);
+        if (ROUND == kRound12) {
+            const uint4 c = load_unit<VEC>(g2, k);
+            store_unit<VEC>(o0, d, xor4(xor4(a, b), t));
+            store_unit<VEC>(o1, d, xor4(c, t));
+        } else {
+            store_unit<VEC>(o0, d, xor4(a, t));
+            store_unit<VEC>(o1, d, xor4(b, t));
+        }
+        uint4 r = mask_unit<VEC>(rk, r_mask, nwords, k, tab, lo);
+        pin(r);
+        store_unit<VEC>(rout, k, r);
+    }
+}
+
+// Round pi23 as a gather (its outputs are the result shares, written in
+// order): with p = perm[i],
+//   out[i] = C1 ^ C2, C1 = (g0 ^ T23)[p] ^ s0[i], C2 = (g1 ^ T23)[p] ^ s1[i]
+// (CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1
+// and CS2's R3 = C1 ^ C2; with the servers simulated together C1 and C2 are
+// not stored).
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, RoundKeys rk,
+                                                        uint32_t t_mask, const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ g0,
                                                         const uint32_t* __restrict__ g1,
-                                                        const uint32_t* __restrict__ g2,
                                                         const uint32_t* __restrict__ s0,
-                                                        const uint32_t* __restrict__ s1, uint32_t* __restrict__ o0,
-                                                        uint32_t* __restrict__ o1, uint32_t* __restrict__ rout) {
+                                                        const uint32_t* __restrict__ s1, uint32_t* __restrict__ out) {
     __shared__ uint32_t tab[kLdsTableWords];
     lds_table_fill(tab, g_tab.t0);
     __syncthreads();
@@ -226,24 +272,10 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_round(uint64_t nrows, uint32
         const uint4 a = load_unit<VEC>(g0, u), b = load_unit<VEC>(g1, u);
         uint4 t = mask_unit<VEC>(rk, t_mask, nwords, u, tab, lo);
         pin(t);
-        if (ROUND == kRound12) {
-            const uint4 c = load_unit<VEC>(g2, u);
-            store_unit<VEC>(o0, k, xor4(xor4(a, b), t));
-            store_unit<VEC>(o1, k, xor4(c, t));
-        } else if (ROUND == kRound31) {
-            store_unit<VEC>(o0, k, xor4(a, t));
-            store_unit<VEC>(o1, k, xor4(b, t));
-        } else {
-            uint4 c1 = xor4(xor4(a, t), load_unit<VEC>(s0, k));
-            pin(c1);
-            const uint4 c2 = xor4(xor4(b, t), load_unit<VEC>(s1, k));
-            store_unit<VEC>(o0, k, xor4(c1, c2));
-        }
-        if (ROUND != kRound23) {
-            uint4 r = mask_unit<VEC>(rk, r_mask, nwords, k, tab, lo);
-            pin(r);
-            store_unit<VEC>(rout, k, r);
-        }
+        uint4 c1 = xor4(xor4(a, t), load_unit<VEC>(s0, k));
+        pin(c1);
+        const uint4 c2 = xor4(xor4(b, t), load_unit<VEC>(s1, k));
+        store_unit<VEC>(out, k, xor4(c1, c2));
     }
 }
 
@@ -421,8 +453,8 @@ uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
            r(sort_temp_bytes(nrows)) + 4096;
 }
 
-// perm = stable argsort of the pair seed's row keys: radix sort by run id,
-// then each run ordered by rank.
+// perm = stable argsort of the pair seed's row keys (or its inverse): radix
+// sort by run id, then each run ordered by rank.
 struct PermScratch {
     uint64_t* keys;
     uint64_t* keys_sorted;
@@ -433,7 +465,8 @@ struct PermScratch {
     size_t temp_bytes;
 };
 
-int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch& w, uint32_t* perm, hipStream_t s) {
+int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch& w, bool inverse, uint32_t* perm,
+              hipStream_t s) {
     const uint32_t hb = run_bits(nrows);
     hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, hb, w.keys, w.idx);
     int rc = check_launch("k_perm_keys");
@@ -453,26 +486,44 @@ int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch
                        w.starts);
     rc = check_launch("k_run_starts");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, w.starts, keys, rows, perm);
+    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, (uint32_t)inverse, w.starts,
+                       keys, rows, perm);
     return check_launch("k_rank_runs");
 }
 
-// One round of the shuffle (k_shuffle_round); the 16-byte path when the
-// width is a multiple of 4 words and every table is 16-byte aligned.
-template <int ROUND>
-int shuffle_round(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, uint32_t r_mask,
-                  const uint32_t* perm, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2,
-                  const uint32_t* s0, const uint32_t* s1, uint32_t* o0, uint32_t* o1, uint32_t* rout, hipStream_t s) {
-    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(g2) && aligned16(s0) &&
-                     aligned16(s1) && aligned16(o0) && aligned16(o1) && aligned16(rout);
+// Round pi23 (k_shuffle_final); the 16-byte path when the width is a multiple
+// of 4 words and every table is 16-byte aligned.
+int shuffle_final(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, const uint32_t* perm,
+                  const uint32_t* g0, const uint32_t* g1, const uint32_t* s0, const uint32_t* s1, uint32_t* out,
+                  hipStream_t s) {
+    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(s0) && aligned16(s1) &&
+                     aligned16(out);
     const uint64_t units = vec ? nrows * (nwords >> 2) : nrows * nwords;
     if (vec)
-        hipLaunchKernelGGL((k_shuffle_round<ROUND, true>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
-                           rk, t_mask, r_mask, perm, g0, g1, g2, s0, s1, o0, o1, rout);
+        hipLaunchKernelGGL(k_shuffle_final<true>, dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords, rk, t_mask,
+                           perm, g0, g1, s0, s1, out);
     else
-        hipLaunchKernelGGL((k_shuffle_round<ROUND, false>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
-                           rk, t_mask, r_mask, perm, g0, g1, g2, s0, s1, o0, o1, rout);
-    return check_launch("k_shuffle_round");
+        hipLaunchKernelGGL(k_shuffle_final<false>, dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords, rk, t_mask,
+                           perm, g0, g1, s0, s1, out);
+    return check_launch("k_shuffle_final");
+}
+
+// Rounds pi12 / pi31 as scatters (k_shuffle_scatter), with the same 16-byte
+// path condition.
+template <int ROUND>
+int shuffle_scatter(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, uint32_t r_mask,
+                    const uint32_t* inv, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2, uint32_t* o0,
+                    uint32_t* o1, uint32_t* rout, hipStream_t s) {
+    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(g2) && aligned16(o0) &&
+                     aligned16(o1) && aligned16(rout);
+    const uint64_t units = vec ? nrows * (nwords >> 2) : nrows * nwords;
+    if (vec)
+        hipLaunchKernelGGL((k_shuffle_scatter<ROUND, true>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
+                           rk, t_mask, r_mask, inv, g0, g1, g2, o0, o1, rout);
+    else
+        hipLaunchKernelGGL((k_shuffle_scatter<ROUND, false>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
+                           rk, t_mask, r_mask, inv, g0, g1, g2, o0, o1, rout);
+    return check_launch("k_shuffle_scatter");
 }
 
 // Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.  The
@@ -499,22 +550,19 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     pw.temp = ws.take<uint8_t>(pw.temp_bytes);
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
     // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1.
-    int rc = make_perm(k12, kP12, nrows, pw, p12, s);
-    if (!rc) rc = make_perm(k23, kP23, nrows, pw, p23, s);
-    if (!rc) rc = make_perm(k31, kP31, nrows, pw, p31, s);
+    // pi12 and pi31 are applied as scatters (their inverses), pi23 as a gather
+    int rc = make_perm(k12, kP12, nrows, pw, true, p12, s);
+    if (!rc) rc = make_perm(k23, kP23, nrows, pw, false, p23, s);
+    if (!rc) rc = make_perm(k31, kP31, nrows, pw, true, p31, s);
     // pi12: CS1 forms pi12(D1 ^ D2 ^ T12), CS2 forms Y1 = pi12(D3 ^ T12); R2 drawn
     if (!rc)
-        rc = shuffle_round<kRound12>(nrows, nwords, k12, kT12, kR2, p12, d[0], d[1], d[2], nullptr, nullptr, z, y1,
-                                     out[1], s);
+        rc = shuffle_scatter<kRound12>(nrows, nwords, k12, kT12, kR2, p12, d[0], d[1], d[2], z, y1, out[1], s);
     // pi31: CS1 forms X1 = pi31(pi12(...) ^ T31), CS3 forms pi31(Y1 ^ T31); R1 drawn
     if (!rc)
-        rc = shuffle_round<kRound31>(nrows, nwords, k31, kT31, kR1, p31, z, y1, nullptr, nullptr, nullptr, x1, v,
-                                     out[0], s);
+        rc = shuffle_scatter<kRound31>(nrows, nwords, k31, kT31, kR1, p31, z, y1, nullptr, x1, v, out[0], s);
     // pi23: CS2 forms C1 = pi23(X1 ^ T23) ^ R2, CS3 forms C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
     // and R3 = C1 ^ C2 (with the servers simulated together, C1 and C2 are not stored)
-    if (!rc)
-        rc = shuffle_round<kRound23>(nrows, nwords, k23, kT23, 0u, p23, x1, v, nullptr, out[1], out[0], out[2],
-                                     nullptr, nullptr, s);
+    if (!rc) rc = shuffle_final(nrows, nwords, k23, kT23, p23, x1, v, out[1], out[0], out[2], s);
     return rc;
 }
 
