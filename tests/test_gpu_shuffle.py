@@ -110,10 +110,13 @@ def test_fetch_unique(fss):
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], d[4321])
 
 
-def test_fetch_many(fss):
-    n, w = 4000, 3
-    rng = np.random.default_rng(11)
-    d, rows = _rss_table(13, n, w)
+@pytest.mark.parametrize("n,w", [(4000, 3), (200003, 4)])
+def test_fetch_many(fss, n, w):
+    """Case II against the oracle: the kept positions, the three shares of the
+    kept records, and their reconstruction.  200003 records put the scan and
+    the compaction over many workgroups and the radix pass on its merge path."""
+    rng = np.random.default_rng(11 + n)
+    d, rows = _rss_table(13 + n, n, w)
     x = (rng.random(n) < 0.1).astype(np.uint8)
     xs1 = rng.integers(0, 2, n, dtype=np.uint8)
     xs2 = rng.integers(0, 2, n, dtype=np.uint8)
@@ -134,6 +137,38 @@ def test_fetch_many(fss):
         np.testing.assert_array_equal(got[i], want[i])
     rec = got[0] ^ got[1] ^ got[2]
     assert sorted(map(tuple, rec.tolist())) == sorted(map(tuple, d[x == 1].tolist()))
+
+
+@pytest.mark.parametrize("n,w", [(999, 2), (131075, 4)])
+def test_compact_valid(fss, n, w):
+    """The secAccess filter against the oracle: records whose bits XOR to 1 are
+    kept in shuffled order (every third record an all-zero dummy), with their
+    shuffled positions, count and shares."""
+    from oracle import access
+    rng = np.random.default_rng(n)
+    recs = rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32)
+    recs[::3] = 0
+    s1 = rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32)
+    s2 = rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32)
+    sh = [s1, s2, recs ^ s1 ^ s2]
+    seeds = (71, 72, 73)
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    pos = torch.empty(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    fss.rss_compact_valid(n, w, [T(t.ravel()) for t in sh], seeds, out, pos, cnt)
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    keep, want = access.compact_valid(sh, seeds)
+    assert k == keep.size
+    np.testing.assert_array_equal(U(pos)[:k], keep)
+    got = [U(o)[:k * w].reshape(k, w) for o in out]
+    for i in range(3):
+        np.testing.assert_array_equal(got[i], want[i])
+    par = np.bitwise_xor.reduce(recs, axis=1)
+    odd = np.array([bin(int(v)).count("1") & 1 for v in par], bool)
+    rec = got[0] ^ got[1] ^ got[2]
+    assert k == int(odd.sum())
+    assert sorted(map(tuple, rec.tolist())) == sorted(map(tuple, recs[odd].tolist()))
 
 
 def test_sec_access_composed(fss):
