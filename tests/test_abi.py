@@ -118,3 +118,31 @@ def test_triples_counter_limit(fss):
     p = ctypes.c_void_p(4096)
     assert fss.LIB.ss_triples(1, 1, 0, (1 << 32) // 5 * 4 + 4, p, p, None) == fss.EUNSUPPORTED
     assert b"too many" in fss.LIB.fss_last_error()
+
+
+def test_shuffle_and_fetch_argument_errors(fss):
+    """The shuffle and fetch calls reject sizes beyond their limits and NULL
+    arguments on the host, before any workspace sizing or launch."""
+    L = fss.LIB
+    fake = ctypes.c_void_p(1 << 20)                         # never dereferenced: rejected first
+    three = (ctypes.c_void_p * 3)(fake, fake, fake)
+    seeds = (ctypes.c_uint64 * 3)(1, 2, 3)
+    # empty work is a no-op
+    assert L.rss_shuffle(0, 4, three, seeds, three, None, 0, None) == fss.OK
+    # row indices are 31-bit
+    assert L.rss_shuffle(1 << 31, 4, three, seeds, three, fake, 1 << 40, None) == fss.EUNSUPPORTED
+    assert b"2^31" in fss.LIB.fss_last_error()
+    assert L.rss_fetch_many(1 << 31, 4, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EUNSUPPORTED
+    assert L.rss_compact_valid(1 << 31, 4, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EUNSUPPORTED
+    # NULL shares, tables and outputs
+    assert L.rss_shuffle(8, 4, None, seeds, three, fake, 1 << 40, None) == fss.EINVAL
+    null_one = (ctypes.c_void_p * 3)(fake, None, fake)
+    assert L.rss_shuffle(8, 4, null_one, seeds, three, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_fetch_many(8, 4, three, seeds, null_one, fake, fake, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_compact_valid(8, 4, three, seeds, three, None, fake, fake, 1 << 40, None) == fss.EINVAL
+    # Case II needs the bit word and at least one more word per record
+    assert L.rss_fetch_many(8, 1, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_compact_valid(8, 0, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EINVAL
+    # Case I words per record
+    assert L.rss_fetch_unique(8, 65536, three, three, three, None) == fss.EUNSUPPORTED
+    assert L.rss_fetch_unique(8, 4, None, three, three, None) == fss.EINVAL
