@@ -38,6 +38,7 @@ SEED = 20220907
 # (64 lane-ops per clock) and one LDS pipe serving 32 random 32-bit reads per
 # clock (128 B), at 2.4 GHz on 256 CUs.
 CUS, CLOCK_HZ = 256, 2.4e9
+HBM_BYTES_PER_S = 8e12                  # MI355X HBM3E, published
 VALU_PER_CLK, LDS_PER_CLK = 64, 32
 PEAK_INT_TOPS = CUS * VALU_PER_CLK * CLOCK_HZ / 1e12
 # (VALU lane-ops, LDS table reads) of one AES-128 block in this design: 9 full
@@ -168,13 +169,19 @@ def main():
     n_rg = len(preds) - n_eq
     evals_per_step = 2 * n * (n_eq + 2 * n_rg)
 
-    ev = {name: [] for name in ("keygen", "match")}
+    ev = {name: [] for name in ("open", "keygen", "match")}
 
     def step(record):
         for d in preds:
             p = d["p"]
+            if record:
+                o0 = torch.cuda.Event(enable_timing=True)
+                o1 = torch.cuda.Event(enable_timing=True)
+                o0.record(stream)
             fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], stream)
             if record:
+                o1.record(stream)
+                ev["open"].append(("open", o0, o1))
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -268,6 +275,11 @@ def main():
                 "frac": dk["frac_of_floor"], "traffic": measured_traffic(dom),
                 "binding_unit": dk["binding_unit"], "valu_frac": dk["valu_frac"], "lds_frac": dk["lds_frac"]}
     eval_evals_per_s = evals_per_step / (match_mean / 1e3)
+    # the open (x0 + x1 + r, HBM stream): 12 bytes read and 4 written per row
+    open_ms = float(np.mean([e0.elapsed_time(e1) for _, e0, e1 in ev["open"]]))
+    hbm_kernels = {"k_mask_open": {"ms": open_ms, "launches_per_step": len(preds), "hbm_bytes": 16 * n,
+                                   "hbm_gb_per_s": round(16 * n / (open_ms / 1e3) / 1e9, 1),
+                                   "frac_of_hbm_peak": round(16 * n / (open_ms / 1e3) / HBM_BYTES_PER_S, 4)}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -293,6 +305,7 @@ def main():
                    "evals_per_step": evals_per_step, "key_gb_both_parties": round(key_gb, 2)},
         "eval_only_evals_per_s": eval_evals_per_s,
         "kernels": kernels,
+        "hbm_kernels": hbm_kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -503,9 +516,6 @@ def run_serve(args, torch, fss, dev):
                      "plain": "one request at a time, results awaited before the next request starts",
                      "plain_pipelined": "one request at a time on one stream, host runs ahead (no wait)"}}
     print(json.dumps(out), flush=True)
-
-
-HBM_BYTES_PER_S = 8e12
 
 
 def run_next(args, torch, fss, dev):
