@@ -9,9 +9,12 @@
 // by the pair permutation they apply: one launch per round (pi12, pi31, pi23)
 // forms every table that pair permutes in that round, with the pair's mask
 // computed where it is XORed, so that each mask word is made once, no mask
-// table is stored, and the AES overlaps with the rounds' random-row reads.
-// The messages X1 and Y1 are stored between rounds; C1 and C2 meet in R3 =
-// C1 ^ C2 as they are formed.
+// table is stored, and the AES overlaps with the rounds' random-row traffic.
+// Rounds pi12 and pi31 run as scatters through the inverse permutation
+// (in-order reads, random writes: a random 64-byte read costs a whole
+// 128-byte line, a random write only its bytes); round pi23, whose outputs
+// are the result shares, is a gather.  The messages X1 and Y1 are stored
+// between rounds; C1 and C2 meet in R3 = C1 ^ C2 as they are formed.
 
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
