@@ -625,10 +625,67 @@ def run_next(args, torch, fss, dev):
     res["rss_compact_valid"] = row("rss_compact_valid", timed(compact), 14 * tbytes + 3 * tbytes // 2,
                                    5 * tbytes / 16 + 3 * nrec,
                                    f"secAccess filter: shuffle {nrec} records of {nwords * 4} B, open parity, compact")
+    del d3, o3, xb
+    if not args.no_cpu_baseline:
+        gpu_rate = {"sec_eval": ncand, "rss_and": nrows, "rss_reshare": nrows, "rss_shuffle": nrec,
+                    "rss_fetch_unique": nrec, "rss_fetch_many": nrec, "rss_compact_valid": nrec}
+        for name, base in next_cpu_baselines().items():
+            res[name]["cpu_baseline"] = base
+            res[name]["gpu_rate"] = round(gpu_rate[name] / (res[name]["ms"] / 1e3), 1)
+            res[name]["gpu_over_cpu"] = round(res[name]["gpu_rate"] / base["value"], 1)
     out = {"metric": "next rows: time per call and fraction of the HBM / AES floor", "value": None, "unit": "ms",
            "n_gpus": 1, "rows": res, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "next: secEval 2^20 x 4096, RSS 2^30 bits, shuffle/fetch 2^22 x 64 B"}}
     print(json.dumps(out), flush=True)
+
+
+def next_cpu_baselines():
+    """The oracle of each row beyond the hot path, as it stands, timed on a
+    bounded sample of the same kind of input (a few seconds each, all of the
+    host's threads for the oracle's OpenMP loops) and reported per unit of the
+    row's work: candidates, shared bits or records per second."""
+    from oracle import access, rss as orss, shuffle as osh
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    _omp_threads(threads)
+    rng = np.random.default_rng(SEED)
+    out = {}
+
+    def rec(name, n, unit, what, fn):
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": round(n / dt, 1), "unit": unit, "cores": threads, "kind": "oracle",
+                     "sample": what, "seconds": round(dt, 3), "cpu": _cpu_model()}
+        log(f"cpu baseline {name}: {out[name]}")
+
+    # secEval: 8,192 candidates x 4,096-position one-hot shares, a range token
+    c, npos = 1 << 13, 4096
+    keys, nb = orss.token("range", npos, SEED, 7, 0, lo=100, hi=3000)
+    sh = rng.integers(0, 2, (3, c, npos), dtype=np.uint8)
+    rec("sec_eval", c, "candidates/s", f"{c} candidates x {npos} positions, range token",
+        lambda: orss.server_shares("range", npos, keys, nb, sh))
+    # RSS AND / re-share: 2^26 shared bits
+    nb_bits = 1 << 26
+    x3 = [rng.integers(0, 2**32, nb_bits // 32, dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    y3 = [rng.integers(0, 2**32, nb_bits // 32, dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    rec("rss_and", nb_bits, "shared bits/s", f"{nb_bits} bits", lambda: orss.rss_and(x3, y3, [11, 22, 33], 5, nb_bits))
+    rec("rss_reshare", nb_bits, "shared bits/s", f"{nb_bits} bits", lambda: orss.reshare(x3, [11, 22, 33], 6, nb_bits))
+    # shuffle and fetches: 2^18 records of 64 B (the selection product: 2^20)
+    n, w = 1 << 18, 16
+    d3 = [rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    xb = [rng.integers(0, 2, n, dtype=np.uint8) for _ in range(3)]
+    rec("rss_shuffle", n, "records/s", f"{n} records x {4 * w} B", lambda: osh.sec_shuffle(d3, 101, 202, 303))
+    nu = 1 << 20
+    du = [rng.integers(0, 2**32, (nu, w), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    xu = [rng.integers(0, 2, nu, dtype=np.uint8) for _ in range(3)]
+    rec("rss_fetch_unique", nu, "candidates/s", f"{nu} candidates x {4 * w} B", lambda: osh.fetch_case1(xu, du))
+    del du, xu
+    rec("rss_fetch_many", n, "records/s", f"{n} records x {4 * w} B",
+        lambda: osh.fetch_case2(xb, [t[:, 1:] for t in d3], 101, 202, 303))
+    rec("rss_compact_valid", n, "records/s", f"{n} records x {4 * w} B",
+        lambda: access.compact_valid(d3, (101, 202, 303)))
+    return out
 
 
 def _cpu_model() -> str:

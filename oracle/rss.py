@@ -80,14 +80,8 @@ def prf_words(key_seed: int, counter: int, nwords: int) -> np.ndarray:
     """F(k, j) on packed words: word w is little-endian word (w mod 4) of
     AES_{LE64(k)||"OBLIVGM1"}(LE16 5 || LE16 0 || LE32 counter || LE32 0 || LE32 (w div 4))
     (the generator's domain 5)."""
-    out = np.zeros(nwords, np.uint32)
-    for blk in range((nwords + 3) // 4):
-        b = fss.rng_block(key_seed, 5, 0, counter, 0, blk)
-        for q in range(4):
-            w = 4 * blk + q
-            if w < nwords:
-                out[w] = int.from_bytes(b[4 * q:4 * q + 4], "little")
-    return out
+    blocks = fss.rng_blocks(key_seed, 5, 0, counter, 0, 0, (nwords + 3) // 4)
+    return blocks.view("<u4").reshape(-1)[:nwords].astype(np.uint32)
 
 
 def zero_shares(prf_keys, counter: int, nwords: int):
