@@ -114,6 +114,7 @@ def parse():
     ap.add_argument("--log-rows", type=int, default=LOG_ROWS)
     ap.add_argument("--cpu-sample-log-rows", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay of the step")
     ap.add_argument("--workload", default="vertex-filter", choices=["vertex-filter", "batch64", "serve", "next"])
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="serve: arrival window per rate")
@@ -171,32 +172,31 @@ def main():
 
     ev = {name: [] for name in ("open", "keygen", "match")}
 
-    def step(record):
+    def step(record, s=stream):
         for d in preds:
             p = d["p"]
             if record:
                 o0 = torch.cuda.Event(enable_timing=True)
                 o1 = torch.cuda.Event(enable_timing=True)
-                o0.record(stream)
-            fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], stream)
+                o0.record(s)
+            fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], s)
             if record:
-                o1.record(stream)
+                o1.record(s)
                 ev["open"].append(("open", o0, o1))
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo, p.hi, d["r"], d["kb"],
-                           stream)
+                e0.record(s)
+            fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo, p.hi, d["r"], d["kb"], s)
             if record:
-                e1.record(stream)
+                e1.record(s)
                 ev["keygen"].append((p.kind, e0, e1))
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        fss.match_query(plan, 3, stream)
+            e0.record(s)
+        fss.match_query(plan, 3, s)
         if record:
-            e1.record(stream)
+            e1.record(s)
             ev["match"].append(("all", e0, e1))
 
     if args.calibrate_copy:
@@ -225,6 +225,37 @@ def main():
     total_s = time.perf_counter() - t0
     ms_per_step = total_s * 1e3 / args.steps
     value = evals_per_step / (ms_per_step / 1e3)
+
+    # The same step captured once into a hipGraph and replayed: the per-call
+    # pipeline holds no memset, host copy or host wait, and a replay redoes the
+    # same work (same seeds, same keys).  A failure is reported, not raised.
+    graph_replay = None
+    if not args.no_graph:
+        try:
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                step(False, side)
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(False, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                g.replay()
+            torch.cuda.synchronize()
+            g_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+            graph_replay = {"ms_per_step": g_ms, "value": evals_per_step / (g_ms / 1e3),
+                            "launches_per_step": 2 * len(preds) + 1}
+            log(f"graph replay: {g_ms:.2f} ms per step")
+            del g
+        except Exception as exc:      # noqa: BLE001 -- the eager result above stands
+            graph_replay = {"error": f"{type(exc).__name__}: {exc}"}
+            log(f"graph replay failed: {exc}")
 
     # per-kernel durations from events on the launch stream
     kg = {"eq": [], "range": []}
@@ -306,6 +337,7 @@ def main():
         "eval_only_evals_per_s": eval_evals_per_s,
         "kernels": kernels,
         "hbm_kernels": hbm_kernels,
+        "graph_replay": graph_replay,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
