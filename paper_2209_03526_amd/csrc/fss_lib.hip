@@ -6,7 +6,7 @@
 //   k_keygen_eq/_range     dealer: DPF / 2xDCF Gen per row             (LDS + VALU, AES)
 //   k_eval                 DPF / 2xDCF Eval per row, ballot            (LDS + VALU, AES)
 //   k_triples              dealer: Beaver triples                      (LDS + VALU, AES)
-//   k_and_open/close, k_and_both, k_gather, k_public_one  ANDs, joins  (HBM stream)
+//   k_and_open/close, k_and_both, k_interleave, k_gather, k_public_one  ANDs, joins  (HBM stream)
 // and the host code of the C ABI (validation, launch, match_query plan).
 //
 // Every AES-using kernel runs 1024-thread workgroups that first fill the
@@ -714,14 +714,27 @@ __global__ void k_and_both(uint64_t nwords, uint64_t nrows, const uint32_t* __re
 
 // out_b[e] = bit idx[e] of m_b (each party gathers its own share at a public
 // index); an index >= nsrc gathers 0 for both parties.
-__global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ m0,
-                         const uint32_t* __restrict__ m1, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
+// The two parties' shares of one vertex bit array side by side: word w of
+// party b at pair[w] component b, so that a gather reads both in one 8-byte
+// load (one L2 request per edge instead of two).
+__global__ void k_interleave(uint64_t nwords, const uint32_t* __restrict__ m0, const uint32_t* __restrict__ m1,
+                             uint2* __restrict__ pair) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride)
+        pair[w] = make_uint2(m0[w], m1[w]);
+}
+
+// Edge e of the join takes the endpoint's bit from both parties' arrays: bit
+// idx[e] of the interleaved vertex bits, packed by ballot into o0 / o1.
+__global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__ idx,
+                         const uint2* __restrict__ pair, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t b0 = 0, b1 = 0;
     if (e < n && idx[e] < nsrc) {
         const uint32_t v = idx[e];
-        b0 = (m0[v >> 5] >> (v & 31u)) & 1u;
-        b1 = (m1[v >> 5] >> (v & 31u)) & 1u;
+        const uint2 w = pair[v >> 5];
+        b0 = (w.x >> (v & 31u)) & 1u;
+        b1 = (w.y >> (v & 31u)) & 1u;
     }
     const uint64_t g0 = __ballot(b0), g1 = __ballot(b1);
     if ((threadIdx.x & 63u) == 0) {
@@ -1096,7 +1109,7 @@ uint64_t plan_workspace(const match_plan* P) {
     uint64_t total = 0;
     for (uint32_t k = 0; k < P->n_pred; k++)
         total += 4 * rnd((uint32_t)P->preds[k].target < P->n_qv ? wv : we);
-    if (P->n_qv > 1) total += 8 * (uint64_t)(P->n_qv - 1) * rnd(we);
+    if (P->n_qv > 1) total += 8 * (uint64_t)(P->n_qv - 1) * rnd(we) + rnd(2 * wv);   // + the interleaved vertex bits
     const uint64_t wmax = wv > we ? wv : we;
     total += 2 * rnd(3 * wmax);
     return total;
@@ -1154,6 +1167,7 @@ struct PlanRun {
     Arena ws;
     uint32_t next_and = 0;
     uint32_t* trip[2] = {nullptr, nullptr};
+    uint2* pair = nullptr;      // interleaved vertex bits of the join, reused by every gather
     Shares pbits[FSS_MAX_PREDS];
 
     // Carve the triple buffers and the predicate-bit buffers; append one eval
@@ -1213,8 +1227,16 @@ struct PlanRun {
         for (int b = 0; b < 2; b++)
             if (!(out->p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
         if (ne == 0) return FSS_OK;
+        const uint64_t nwv = words_of(P->n_vertices);
+        if (!pair && !(pair = (uint2*)ws.take(2 * nwv))) return fail(FSS_ENOMEM, "match_query: workspace too small");
+        if (nwv) {
+            hipLaunchKernelGGL(k_interleave, dim3(grid_for(nwv, 256, 8192)), dim3(256), 0, s, nwv, m.p[0], m.p[1],
+                               pair);
+            int rc = check_launch("k_interleave");
+            if (rc) return rc;
+        }
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, P->n_vertices, idx,
-                           m.p[0], m.p[1], out->p[0], out->p[1]);
+                           (const uint2*)pair, out->p[0], out->p[1]);
         return check_launch("k_gather");
     }
 
