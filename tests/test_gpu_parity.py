@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import DEV, B, T, U, column_shares, plan_outputs, run_query_gpu
+from gpu_util import DEV, B, T, T_off, U, column_shares, empty_off, plan_outputs, run_query_gpu
 from keylayout import from_device, to_device
 from oracle import fss as ofss
 from oracle import match as omatch
@@ -31,11 +31,21 @@ def _rand_u32(seed, n):
 
 # --------------------------------------------------------------------------- masked open
 
-@pytest.mark.parametrize("n", [1, 255, 1024, 1000003])
+@pytest.mark.parametrize("n", [1, 3, 255, 1024, 1000003])
 def test_mask_open(fss, n):
+    """Aligned buffers take the 16-byte path (with a ragged tail of n mod 4 rows)."""
     x0, x1, r = _rand_u32(1, n), _rand_u32(2, n), _rand_u32(3, n)
     out = torch.empty(n, dtype=torch.int32, device=DEV)
     fss.fss_mask_open(T(x0), T(x1), T(r), out)
+    np.testing.assert_array_equal(U(out), ofss.mask_open(x0, x1, r))
+
+
+@pytest.mark.parametrize("n", [5, 100003])
+def test_mask_open_unaligned(fss, n):
+    """A buffer 4 bytes past a 16-byte boundary takes the word path."""
+    x0, x1, r = _rand_u32(4, n), _rand_u32(5, n), _rand_u32(6, n)
+    out = empty_off(n)
+    fss.fss_mask_open(T(x0), T_off(x1), T(r), out)
     np.testing.assert_array_equal(U(out), ofss.mask_open(x0, x1, r))
 
 
