@@ -52,6 +52,10 @@ AES_SINGLE = (9 * 4 * 7 + 4 * 7 + 4 + 4, 10 * 16)
 # terms of every round-2 column (the right child's round 2 is 4 reads, 12 ops);
 # the right child's feed-forward input costs one op.
 AES_PAIR = (2 * AES_SINGLE[0] - 4 - (21 + 4) - 16 + 1, 2 * AES_SINGLE[1] - 15 - 12)
+# VALU lane-ops of one ChaCha12 block (64 bytes): 12 rounds of 4 quarter rounds
+# of 4 adds, 4 xors and 4 rotates, and the 16 adds of the feed-forward.  The
+# shuffle's tables and permutation keys are ChaCha12 output.
+CHACHA_OPS = 12 * 4 * 12 + 16
 # AES work per table row: (single blocks, sibling pairs); eval walks one child
 # per level per party, the dealer expands both children for both parties.
 AES_WORK = {
@@ -640,14 +644,20 @@ def run_next(args, torch, fss, dev):
             ms.append(a.elapsed_time(b))
         return float(np.median(ms))
 
-    def row(name, ms, hbm_bytes, aes_blocks, what):
+    def row(name, ms, hbm_bytes, aes_blocks, what, chacha_blocks=0):
         t = ms / 1e3
         t_hbm = hbm_bytes / HBM_BYTES_PER_S
         t_aes = aes_floor(aes_blocks, 0)["t_floor"]
-        out = {"ms": round(ms, 4), "hbm_gb": round(hbm_bytes / 1e9, 4), "aes_mblocks": round(aes_blocks / 1e6, 3),
-               "hbm_gb_per_s": round(hbm_bytes / t / 1e9, 1), "aes_gblocks_per_s": round(aes_blocks / t / 1e9, 2),
-               "binding": "hbm" if t_hbm >= t_aes else "aes", "frac_of_floor": round(max(t_hbm, t_aes) / t, 4),
-               "work": what}
+        t_cc = chacha_blocks * CHACHA_OPS / (PEAK_INT_TOPS * 1e12)
+        floors = {"hbm": t_hbm, "aes": t_aes, "chacha": t_cc}
+        binding = max(floors, key=floors.get)
+        out = {"ms": round(ms, 4), "hbm_gb": round(hbm_bytes / 1e9, 4), "hbm_gb_per_s": round(hbm_bytes / t / 1e9, 1)}
+        if aes_blocks:
+            out.update(aes_mblocks=round(aes_blocks / 1e6, 3), aes_gblocks_per_s=round(aes_blocks / t / 1e9, 2))
+        if chacha_blocks:
+            out.update(chacha_mblocks=round(chacha_blocks / 1e6, 3),
+                       chacha_gblocks_per_s=round(chacha_blocks / t / 1e9, 2))
+        out.update(binding=binding, frac_of_floor=round(floors[binding] / t, 4), work=what)
         log(f"{name}: {out}")
         return out
 
@@ -695,9 +705,16 @@ def run_next(args, torch, fss, dev):
     def shuffle():
         work["w"] = fss.rss_shuffle(nrec, nwords, d3, seeds, o3, stream)
 
-    res["rss_shuffle"] = row("rss_shuffle", timed(shuffle), 14 * tbytes, 5 * tbytes / 16 + 3 * nrec,
-                             f"{nrec} records x {nwords * 4} B: 3 shares in, messages X1 Y1 C1 C2 written and read, "
-                             "3 shares out; AES for 5 mask tables and 3 permutations' keys (sorts not counted)")
+    # algorithmic work: 3 shares in, the two tables the pi23 gather takes (X1
+    # and pi31(Y1 ^ T31)) written and read, 3 shares out; one ChaCha12 block
+    # per 16-word slice of each of the 5 mask tables and per 8 rows of each of
+    # the 3 permutations' keys (the sorts not counted)
+    slices = nrec * ((nwords + 15) // 16)
+    cc_blocks = 5 * slices + 3 * ((nrec + 7) // 8)
+    res["rss_shuffle"] = row("rss_shuffle", timed(shuffle), 10 * tbytes, 0,
+                             f"{nrec} records x {nwords * 4} B: 3 shares in, X1 and pi31(Y1 ^ T31) written and "
+                             "read, 3 shares out; ChaCha12 for 5 mask tables and 3 permutations' keys (sorts not "
+                             "counted)", cc_blocks)
     xb = [rnd((nrec + 31) // 32) for _ in range(3)]
     f3 = [torch.empty(nwords, dtype=torch.int32, device=dev) for _ in range(3)]
     res["rss_fetch_unique"] = row("rss_fetch_unique",
@@ -710,17 +727,16 @@ def run_next(args, torch, fss, dev):
     def fetch_many():
         work["w"] = fss.rss_fetch_many(nrec, nwords, d3, seeds, o3, rows_out, count, stream)
 
-    res["rss_fetch_many"] = row("rss_fetch_many", timed(fetch_many), 14 * tbytes + 3 * tbytes // 2,
-                                5 * tbytes / 16 + 3 * nrec,
+    res["rss_fetch_many"] = row("rss_fetch_many", timed(fetch_many), 10 * tbytes + 3 * tbytes // 2, 0,
                                 f"shuffle of {nrec} records (bit column + {(nwords - 1) * 4} B), open, compact "
-                                "(about half kept)")
+                                "(about half kept)", cc_blocks)
 
     def compact():
         work["w"] = fss.rss_compact_valid(nrec, nwords, d3, seeds, o3, rows_out, count, stream)
 
-    res["rss_compact_valid"] = row("rss_compact_valid", timed(compact), 14 * tbytes + 3 * tbytes // 2,
-                                   5 * tbytes / 16 + 3 * nrec,
-                                   f"secAccess filter: shuffle {nrec} records of {nwords * 4} B, open parity, compact")
+    res["rss_compact_valid"] = row("rss_compact_valid", timed(compact), 10 * tbytes + 3 * tbytes // 2, 0,
+                                   f"secAccess filter: shuffle {nrec} records of {nwords * 4} B, open parity, compact",
+                                   cc_blocks)
     del d3, o3, xb
     if not args.no_cpu_baseline:
         gpu_rate = {"sec_eval": ncand, "rss_and": nrows, "rss_reshare": nrows, "rss_shuffle": nrec,
@@ -729,7 +745,7 @@ def run_next(args, torch, fss, dev):
             res[name]["cpu_baseline"] = base
             res[name]["gpu_rate"] = round(gpu_rate[name] / (res[name]["ms"] / 1e3), 1)
             res[name]["gpu_over_cpu"] = round(res[name]["gpu_rate"] / base["value"], 1)
-    out = {"metric": "next rows: time per call and fraction of the HBM / AES floor", "value": None, "unit": "ms",
+    out = {"metric": "next rows: time per call and fraction of the HBM / AES / ChaCha floor", "value": None, "unit": "ms",
            "n_gpus": 1, "rows": res, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "next: secEval 2^20 x 4096, RSS 2^30 bits, shuffle/fetch 2^22 x 64 B"}}
     print(json.dumps(out), flush=True)

@@ -333,11 +333,18 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  * of nwords 32-bit words, row-major, in binary RSS: d_in[i] is share i+1 and
  * CS_i holds shares i and i+1.  seeds = {s12, s23, s31}, the pairwise seeds.
  * Each pair derives its permutations (stable sort of one 64-bit key per row)
- * and mask tables from its seed with the counter-mode generator, domain 6:
- *   mask word k = r*nwords + w of table t = word (k mod 4) of block
- *   (6, t, nwords, 0, k div 4), T12 = 1, R2 = 2, T23 = 3, T31 = 4, R1 = 5;
- *   sort key of row r for pi12 / pi23 / pi31 = words 0-1 of block (6, 16+p, 0, 0, r),
- *   p = 0 / 1 / 2; a permutation applied to a table gathers out[i] = in[perm[i]].
+ * and mask tables from its seed s with ChaCha12 (the ChaCha block function of
+ * RFC 8439 with 12 rounds), key words (s mod 2^32, s div 2^32, 6, 0, 0, 0, 0, 0)
+ * and state words 12-15 naming the block; a block's 16 words are read column
+ * by column (slice word 4c + k = state word 4k + c):
+ *   word w of record r of table t = slice word (w mod 16) of block
+ *   (r, w div 16, t, nwords), T12 = 1, R2 = 2, T23 = 3, T31 = 4, R1 = 5;
+ *   sort key of row r for pi12 / pi23 / pi31 = slice words 2e (low) and 2e+1
+ *   (high), e = r mod 8, of block (r div 8, 0, 16+p, 0), p = 0 / 1 / 2;
+ *   a permutation applied to a table gathers out[i] = in[perm[i]].
+ * The permutations are made on two streams of the library's own besides the
+ * caller's, ordered against the caller's stream with events: the call's work
+ * is complete when the caller's stream reaches the call's end.
  * The messages follow the algorithm (its X_2 in CS2's step is the X1 it
  * received): X1 = pi31[pi12(D1^D2^T12)^T31]; Y1 = pi12(D3^T12);
  * C1 = pi23(X1^T23)^R2; C2 = pi23[pi31(Y1^T31)^T23]^R1; R3 = C1^C2.

@@ -17,36 +17,55 @@ and only that reading makes the shares reconstruct -- see the tests.)
 
 Readings where the paper is silent: a permutation pi applied to a table is
 the row gather pi(D)[i] = D[perm[i]]; perm is the stable argsort of 64-bit
-keys drawn per row from the pair's seed; masks and keys come from the
-counter-mode generator under the pair seed (domain 6, j = table id):
-  mask word (r, w) of table t = word (k mod 4) of block (6, t, W, 0, k div 4),
-  k = r * W + w;  sort key of row r for permutation p = words 0-1 of block
-  (6, 16 + p, 0, 0, r).  Table ids: T12 = 1, R2 = 2, T23 = 3, T31 = 4, R1 = 5;
-  permutation ids: pi12 = 0, pi23 = 1, pi31 = 2.
+keys drawn per row from the pair's seed.  Masks and keys are ChaCha12 output
+(``oracle/chacha.py``) under the key (seed mod 2^32, seed div 2^32, 6, 0, 0,
+0, 0, 0), with state words 12-15 naming the block.  A block's 16 output words
+are read column by column: its slice word 4c + k is state word 4k + c.
+  mask word w of record r of table t (W words a record) = slice word (w mod 16)
+  of block (r, w div 16, t, W);  sort key of row r for permutation p = slice
+  words 2e (low) and 2e + 1 (high), e = r mod 8, of block (r div 8, 0, 16 + p, 0).
+Table ids: T12 = 1, R2 = 2, T23 = 3, T31 = 4, R1 = 5; permutation ids:
+pi12 = 0, pi23 = 1, pi31 = 2.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import fss
+from . import chacha
 
 T12, R2, T23, T31, R1 = 1, 2, 3, 4, 5
 P12, P23, P31 = 0, 1, 2
+ROUNDS = 12
+
+
+def pair_key(seed: int):
+    """The eight ChaCha key words of a pair seed (the 6 separates this use)."""
+    seed &= (1 << 64) - 1
+    return [seed & 0xFFFFFFFF, seed >> 32, 6, 0, 0, 0, 0, 0]
+
+
+def _slices(words: np.ndarray) -> np.ndarray:
+    """Blocks (N, 16) in state order -> (N, 16) in slice order: slice word
+    4c + k is state word 4k + c."""
+    return words.reshape(-1, 4, 4).transpose(0, 2, 1).reshape(-1, 16)
 
 
 def mask_table(seed: int, table: int, nrows: int, nwords: int) -> np.ndarray:
-    """Word k = r * W + w is little-endian word (k mod 4) of block k div 4."""
-    total = nrows * nwords
-    blocks = fss.rng_blocks(seed, 6, table, nwords, 0, 0, (total + 3) // 4)
-    words = blocks.view("<u4").reshape(-1)          # block m -> words 4m .. 4m + 3
-    return words[:total].astype(np.uint32).reshape(nrows, nwords)
+    """Record r, word w = slice word (w mod 16) of block (r, w div 16, table, W)."""
+    nb = (nwords + 15) // 16
+    r = np.repeat(np.arange(nrows, dtype=np.uint64), nb)
+    b = np.tile(np.arange(nb, dtype=np.uint64), nrows)
+    words = _slices(chacha.blocks(pair_key(seed), r, b, table, nwords, ROUNDS))      # (nrows * nb, 16)
+    return words.reshape(nrows, nb * 16)[:, :nwords].copy()
 
 
 def permutation(seed: int, perm_id: int, nrows: int) -> np.ndarray:
-    """Stable argsort of the rows' keys: key of row r = bytes 0-7 of its block,
-    little-endian."""
-    blocks = fss.rng_blocks(seed, 6, 16 + perm_id, 0, 0, 0, nrows)
-    keys = blocks[:, :8].copy().view("<u8").reshape(-1)
+    """Stable argsort of the rows' keys: key of row r = slice words 2e (low)
+    and 2e + 1 (high), e = r mod 8, of block (r div 8, 0, 16 + p, 0)."""
+    nblk = (nrows + 7) // 8
+    words = _slices(chacha.blocks(pair_key(seed), np.arange(nblk, dtype=np.uint64), 0, 16 + perm_id, 0, ROUNDS))
+    keys = words.reshape(-1, 2).astype(np.uint64)
+    keys = (keys[:, 0] | (keys[:, 1] << np.uint64(32)))[:nrows]
     return np.argsort(keys, kind="stable")
 
 

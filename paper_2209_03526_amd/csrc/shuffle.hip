@@ -2,72 +2,126 @@
 // of matched records (Alg. 4, Cases I and II), all three servers simulated.
 //
 // Tables are row-major: record r of a W-word table at words [r*W, r*W + W).
-// Each pair of servers derives from its seed, with the counter-mode generator
-// (domain 6), its permutations (stable sort of one 64-bit key per row) and
-// mask tables (one AES block per four words); applying a permutation is the
-// row gather out[i] = in[perm[i]].  The servers' steps of Alg. 5 are grouped
-// by the pair permutation they apply: one launch per round (pi12, pi31, pi23)
-// forms every table that pair permutes in that round, with the pair's mask
-// computed where it is XORed, so that each mask word is made once, no mask
-// table is stored, and the AES overlaps with the rounds' random-row traffic.
-// Rounds pi12 and pi31 run as scatters through the inverse permutation
-// (in-order reads, random writes: a random 64-byte read costs a whole
-// 128-byte line, a random write only its bytes); round pi23, whose outputs
-// are the result shares, is a gather.  The messages X1 and Y1 are stored
-// between rounds; C1 and C2 meet in R3 = C1 ^ C2 as they are formed.
+// Each pair of servers derives from its seed, with ChaCha12, its permutation
+// (stable sort of one 64-bit key per row) and its mask tables; applying a
+// permutation is the row gather out[i] = in[perm[i]].  A thread takes one
+// 16-word slice of a record, which is one ChaCha block of every mask table,
+// so masks are made where they are XORed (VALU only, no table in LDS) and no
+// mask table is stored.
+//
+// Two launches carry the five steps of Alg. 5.  The first reads the input
+// shares in order and scatters each row through both inverse permutations
+// (pi12, then pi31): it forms CS1's X1 (its pi12(D1 ^ D2 ^ T12) never leaves
+// CS1) and CS3's pi31(Y1 ^ T31) (CS2's message Y1 met as it is formed), and
+// draws R2 and R1.  The second, a gather through pi23 because its outputs
+// are the result shares in order, forms C1 and C2 and R3 = C1 ^ C2.  Random
+// 64-byte reads cost a whole 128-byte line and random writes only their
+// bytes, hence scatters where the order allows.
 
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
 
+#include <array>
+#include <initializer_list>
+#include <map>
+#include <mutex>
+
 #include "../../include/oblivgm_fss.h"
-#include "aes_gfx950.hpp"
 #include "common.hpp"
 
 using namespace ogm;
 
 namespace {
 
-constexpr int kBlock = 1024;
-__constant__ AesTables g_tab = kTables;
+constexpr int kBlock = 256;
 
 enum { kT12 = 1, kR2 = 2, kT23 = 3, kT31 = 4, kR1 = 5 };
 enum { kP12 = 0, kP23 = 1, kP31 = 2 };
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }   // NULL counts as aligned
 
-// Number of workgroups for a grid-stride AES kernel: enough to fill every CU
-// twice, never more than the work needs.  A workgroup fills its 64 KiB LDS
-// tables once and then loops, so the fill is spread over many blocks.
-unsigned aes_grid(uint64_t items) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
-    const uint64_t need = (items + kBlock - 1) / kBlock;
-    const uint64_t cap = 2ull * (uint64_t)cus;
-    return (unsigned)(need < 1 ? 1 : (need < cap ? need : cap));
+unsigned slice_grid(uint64_t items) {
+    uint64_t g = (items + kBlock - 1) / kBlock;
+    if (g == 0) g = 1;
+    if (g > (1u << 20)) g = 1u << 20;
+    return (unsigned)g;
 }
 
-// Sort keys of permutation p: row r -> words 0-1 of block (6, 16 + p, 0, 0, r).
-// The key is stored rotated left by hb bits, so that its top hb bits (the
-// row's run id) sit in bits 0 .. hb-1, the range the radix pass sorts, and
-// the whole key travels with it; the row number goes beside it.
-__global__ __launch_bounds__(kBlock) void k_perm_keys(RoundKeys rk, uint32_t p, uint64_t nrows, uint32_t hb,
+// ---------------------------------------------------------------- ChaCha12
+// The block function of ChaCha (Bernstein 2008; RFC 8439 gives the 20-round
+// form) with 12 rounds.  A pair's key is its seed: key words (seed mod 2^32,
+// seed div 2^32, 6, 0, 0, 0, 0, 0); state words 12-15 name the block.
+//
+// Four consecutive lanes make one block together: lane c holds column c of
+// the state (words c, 4 + c, 8 + c, 12 + c) and applies the column round's
+// quarter round to it; for the diagonal round rows 1-3 rotate across the
+// four lanes by 1, 2 and 3 (DPP quad permutations), and back afterwards.  A
+// block's words are read column by column (slice word 4c + k is state word
+// 4k + c), so lane c ends holding slice words 4c .. 4c + 3: the 16-byte
+// quarter it loads and stores, and four lanes move a whole 64-byte slice in
+// one access.  The four lanes of a quad must all be active.
+constexpr int kChachaRounds = 12;
+
+struct PairKey {
+    uint32_t lo, hi;
+};
+
+PairKey pair_key(uint64_t seed) { return PairKey{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
+
+__device__ __forceinline__ void quarter(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
+    a += b; d = __builtin_rotateleft32(d ^ a, 16);
+    c += d; b = __builtin_rotateleft32(b ^ c, 12);
+    a += b; d = __builtin_rotateleft32(d ^ a, 8);
+    c += d; b = __builtin_rotateleft32(b ^ c, 7);
+}
+
+// lane c of the quad takes the value of lane (c + S) mod 4
+template <int S>
+__device__ __forceinline__ uint32_t from_lane(uint32_t v) {
+    constexpr int ctrl = ((0 + S) & 3) | (((1 + S) & 3) << 2) | (((2 + S) & 3) << 4) | (((3 + S) & 3) << 6);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
+}
+
+// Lane c = lane & 3 of each quad: returns slice words 4c .. 4c + 3 of block
+// (w12, w13, w14, w15) under key k.
+__device__ __forceinline__ uint4 chacha_quad(PairKey k, uint32_t w12, uint32_t w13, uint32_t w14, uint32_t w15) {
+    const uint32_t c = threadIdx.x & 3u;
+    const uint32_t a0 = c == 0 ? 0x61707865u : c == 1 ? 0x3320646eu : c == 2 ? 0x79622d32u : 0x6b206574u;
+    const uint32_t b0 = c == 0 ? k.lo : c == 1 ? k.hi : c == 2 ? 6u : 0u;      // key words c; 4 + c are 0
+    const uint32_t d0 = c == 0 ? w12 : c == 1 ? w13 : c == 2 ? w14 : w15;
+    uint32_t x0 = a0, x1 = b0, x2 = 0u, x3 = d0;
+#pragma unroll
+    for (int r = 0; r < kChachaRounds / 2; r++) {
+        quarter(x0, x1, x2, x3);
+        x1 = from_lane<1>(x1), x2 = from_lane<2>(x2), x3 = from_lane<3>(x3);
+        quarter(x0, x1, x2, x3);
+        x1 = from_lane<3>(x1), x2 = from_lane<2>(x2), x3 = from_lane<1>(x3);
+    }
+    return make_uint4(x0 + a0, x1 + b0, x2, x3 + d0);
+}
+
+// Sort keys of permutation p: the key of row r is slice words 2e (low) and
+// 2e + 1 (high), e = r mod 8, of block (r div 8, 0, 16 + p, 0); a quad makes
+// the keys of eight rows, lane c those of rows 2c and 2c + 1.  The key is
+// stored rotated left by hb bits, so that its top hb bits (the row's run id)
+// sit in bits 0 .. hb-1, the range the radix pass sorts, and the whole key
+// travels with it; the row number goes beside it.
+__global__ __launch_bounds__(kBlock) void k_perm_keys(PairKey pk, uint32_t p, uint64_t nrows, uint32_t hb,
                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tab.t0);
-    __syncthreads();
-    const LaneOff lo = lane_offset();
+    const uint64_t total = ((nrows + 7) >> 3) * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += stride) {
-        const uint4 b = aes128_encrypt(make_uint4(6u | ((16u + p) << 16), 0u, 0u, (uint32_t)r), ArgKey{rk}, tab, lo);
-        const uint64_t key = (uint64_t)b.x | ((uint64_t)b.y << 32);
-        keys[r] = hb ? (key << hb) | (key >> (64 - hb)) : key;
-        idx[r] = (uint32_t)r;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride) {
+        const uint4 o = chacha_quad(pk, (uint32_t)(t >> 2), 0u, 16u + p, 0u);
+        const uint64_t r0 = (t >> 2) * 8 + 2 * (t & 3);
+        const uint64_t key[2] = {(uint64_t)o.x | ((uint64_t)o.y << 32), (uint64_t)o.z | ((uint64_t)o.w << 32)};
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            if (r0 + e < nrows) {
+                keys[r0 + e] = hb ? (key[e] << hb) | (key[e] >> (64 - hb)) : key[e];
+                idx[r0 + e] = (uint32_t)(r0 + e);
+            }
+        }
     }
 }
 
@@ -160,125 +214,105 @@ __global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, uint32_t inverse
     }
 }
 
-// Mask of one unit of table `table` under the pair key rk: with VEC the
-// 16-byte unit u is block u of the table (the record width is a multiple of 4
-// words, so units and blocks coincide); else word u is word (u mod 4) of
-// block u div 4.
+// A slice is words [16b, 16b + L) of record r, L = min(16, W - 16b): block
+// (r, b, table, W) of each mask table covers it, and lane c of a quad moves
+// its words 4c .. 4c + 3 (those below L).  VEC: W a multiple of 4 words and
+// every table 16-byte aligned, so a quarter is one 16-byte access.
 template <bool VEC>
-__device__ __forceinline__ uint4 mask_unit(const RoundKeys& rk, uint32_t table, uint32_t nwords, uint64_t u,
-                                           const uint32_t* tab, LaneOff lo) {
-    const uint32_t blk = (uint32_t)(VEC ? u : u >> 2);
-    const uint4 b = aes128_encrypt(make_uint4(6u | (table << 16), nwords, 0u, blk), ArgKey{rk}, tab, lo);
-    if (VEC) return b;
-    const uint32_t q = (uint32_t)u & 3u;
-    return make_uint4(q == 0 ? b.x : q == 1 ? b.y : q == 2 ? b.z : b.w, 0u, 0u, 0u);
+__device__ __forceinline__ uint4 load_quarter(const uint32_t* __restrict__ t, uint64_t base, uint32_t c, uint32_t len) {
+    if (VEC) return 4 * c < len ? *(const uint4*)(t + base + 4 * c) : make_uint4(0u, 0u, 0u, 0u);
+    uint32_t v[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) v[k] = 4 * c + k < len ? t[base + 4 * c + k] : 0u;
+    return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-// An empty asm statement that the value passes through: its block is complete
-// here, in registers, and the next block's work does not move across this
-// point (two mask blocks side by side would need more than 64 VGPRs, which
-// would leave room for one workgroup per CU instead of two).  It also keeps
-// the compiler from cancelling a mask that two messages share (C1 and C2).
+template <bool VEC>
+__device__ __forceinline__ void store_quarter(uint32_t* __restrict__ t, uint64_t base, uint32_t c, uint32_t len,
+                                              uint4 v) {
+    if (VEC) {
+        if (4 * c < len) *(uint4*)(t + base + 4 * c) = v;
+        return;
+    }
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++)
+        if (4 * c + k < len) t[base + 4 * c + k] = w[k];
+}
+
+// An empty asm statement that the words pass through: it keeps the compiler
+// from cancelling the mask T23 that C1 and C2 share (each server forms its
+// own message with it).
 __device__ __forceinline__ void pin(uint4& v) {
-    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w) : : "memory");
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
 }
 
+// Rounds pi12 and pi31 in one pass, as scatters through both inverse
+// permutations: input row i goes to row j = inv12[i] after pi12 and to row
+// l = inv31[j] after pi31, so
+//   o0[l] = (g0 ^ g1 ^ T12)[i] ^ T31[j]   (CS1's X1)
+//   o1[l] = (g2 ^ T12)[i] ^ T31[j]        (CS3's pi31(Y1 ^ T31), Y1 = CS2's pi12(D3 ^ T12))
+//   r12[i] = R2, r31[i] = R1.
+// The masks are indexed by the row they are XORed at: T12 before pi12, T31
+// before pi31.  A quad of lanes takes one slice.
 template <bool VEC>
-__device__ __forceinline__ uint4 load_unit(const uint32_t* __restrict__ t, uint64_t u) {
-    if (VEC) return ((const uint4*)t)[u];
-    return make_uint4(t[u], 0u, 0u, 0u);
-}
-
-template <bool VEC>
-__device__ __forceinline__ void store_unit(uint32_t* __restrict__ t, uint64_t u, uint4 v) {
-    if (VEC)
-        ((uint4*)t)[u] = v;
-    else
-        t[u] = v.x;
-}
-
-// One round of Alg. 5 is the permutation of one pair of servers applied, with
-// that pair's mask T, to every table the pair permutes in that round.  The
-// kernels compute the mask words where they XOR them (a mask word is a
-// counter-mode block of its table), so no mask table is stored and the AES
-// overlaps with the rounds' random-row traffic.  Units are 16-byte quarters
-// of a record with VEC (width a multiple of 4 words, every table 16-byte
-// aligned), else words.
-enum { kRound12 = 0, kRound31 = 1 };
-
-// Rounds pi12 and pi31 as scatters: source row j of the permuted tables goes
-// to output row inv[j] (inv the inverse permutation), so the tables are read
-// in order and written at random rows; the pair mask T is indexed by the
-// source row and R by the output row:
-//   kRound12: o0[inv[j]] = (g0 ^ g1 ^ T12)[j], o1[inv[j]] = (g2 ^ T12)[j], rout = R2
-//             (CS1's pi12(D1 ^ D2 ^ T12) and CS2's Y1 = pi12(D3 ^ T12))
-//   kRound31: o0[inv[j]] = (g0 ^ T31)[j],      o1[inv[j]] = (g1 ^ T31)[j], rout = R1
-//             (CS1's X1 and CS3's pi31(Y1 ^ T31))
-template <int ROUND, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_shuffle_scatter(uint64_t nrows, uint32_t nwords, RoundKeys rk,
-                                                          uint32_t t_mask, uint32_t r_mask,
-                                                          const uint32_t* __restrict__ inv,
-                                                          const uint32_t* __restrict__ g0,
-                                                          const uint32_t* __restrict__ g1,
-                                                          const uint32_t* __restrict__ g2, uint32_t* __restrict__ o0,
-                                                          uint32_t* __restrict__ o1, uint32_t* __restrict__ rout) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tab.t0);
-    __syncthreads();
-    const LaneOff lo = lane_offset();
-    const uint32_t q = VEC ? nwords >> 2 : nwords;       // units per record
-    const uint64_t total = nrows * q;
+__global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k31,
+                                                        const uint32_t* __restrict__ inv12,
+                                                        const uint32_t* __restrict__ inv31,
+                                                        const uint32_t* __restrict__ g0,
+                                                        const uint32_t* __restrict__ g1,
+                                                        const uint32_t* __restrict__ g2, uint32_t* __restrict__ o0,
+                                                        uint32_t* __restrict__ o1, uint32_t* __restrict__ r12,
+                                                        uint32_t* __restrict__ r31) {
+    const uint32_t nb = (nwords + 15) >> 4;
+    const uint64_t total = nrows * nb * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += stride) {
-        const uint32_t j = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)j * q);
-        const uint64_t d = (uint64_t)inv[j] * q + w;
-        const uint4 a = load_unit<VEC>(g0, k), b = load_unit<VEC>(g1, k);
-        uint4 t = mask_unit<VEC>(rk, t_mask, nwords, k, tab, lo);
-        pin(t);
-        if (ROUND == kRound12) {
-            const uint4 c = load_unit<VEC>(g2, k);
-            store_unit<VEC>(o0, d, xor4(xor4(a, b), t));
-            store_unit<VEC>(o1, d, xor4(c, t));
-        } else {
-            store_unit<VEC>(o0, d, xor4(a, t));
-            store_unit<VEC>(o1, d, xor4(b, t));
-        }
-        uint4 r = mask_unit<VEC>(rk, r_mask, nwords, k, tab, lo);
-        pin(r);
-        store_unit<VEC>(rout, k, r);
+    const uint32_t c = threadIdx.x & 3u;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride) {
+        const uint64_t sl = t >> 2;
+        const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
+        const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
+        const uint32_t j = inv12[i];
+        const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)inv31[j] * nwords + 16 * b;
+        const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
+        const uint4 z = load_quarter<VEC>(g2, src, c, len);
+        const uint4 m = xor4(chacha_quad(k12, i, b, kT12, nwords), chacha_quad(k31, j, b, kT31, nwords));
+        store_quarter<VEC>(o0, dst, c, len, xor4(xor4(x, y), m));
+        store_quarter<VEC>(o1, dst, c, len, xor4(z, m));
+        store_quarter<VEC>(r12, src, c, len, chacha_quad(k12, i, b, kR2, nwords));
+        store_quarter<VEC>(r31, src, c, len, chacha_quad(k31, i, b, kR1, nwords));
     }
 }
 
 // Round pi23 as a gather (its outputs are the result shares, written in
 // order): with p = perm[i],
-//   out[i] = C1 ^ C2, C1 = (g0 ^ T23)[p] ^ s0[i], C2 = (g1 ^ T23)[p] ^ s1[i]
+//   out[i] = C1 ^ C2, C1 = (g0 ^ T23)[p] ^ R2[i], C2 = (g1 ^ T23)[p] ^ R1[i]
 // (CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1
 // and CS2's R3 = C1 ^ C2; with the servers simulated together C1 and C2 are
-// not stored).
+// not stored).  R1 and R2 are made again from their pairs' keys rather than
+// read back.
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, RoundKeys rk,
-                                                        uint32_t t_mask, const uint32_t* __restrict__ perm,
+__global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k23,
+                                                        PairKey k31, const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ g0,
-                                                        const uint32_t* __restrict__ g1,
-                                                        const uint32_t* __restrict__ s0,
-                                                        const uint32_t* __restrict__ s1, uint32_t* __restrict__ out) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tab.t0);
-    __syncthreads();
-    const LaneOff lo = lane_offset();
-    const uint32_t q = VEC ? nwords >> 2 : nwords;       // units per record
-    const uint64_t total = nrows * q;
+                                                        const uint32_t* __restrict__ g1, uint32_t* __restrict__ out) {
+    const uint32_t nb = (nwords + 15) >> 4;
+    const uint64_t total = nrows * nb * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += stride) {
-        const uint32_t i = (uint32_t)(k / q), w = (uint32_t)(k - (uint64_t)i * q);
-        const uint64_t u = (uint64_t)perm[i] * q + w;
-        const uint4 a = load_unit<VEC>(g0, u), b = load_unit<VEC>(g1, u);
-        uint4 t = mask_unit<VEC>(rk, t_mask, nwords, u, tab, lo);
-        pin(t);
-        uint4 c1 = xor4(xor4(a, t), load_unit<VEC>(s0, k));
+    const uint32_t c = threadIdx.x & 3u;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride) {
+        const uint64_t sl = t >> 2;
+        const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
+        const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
+        const uint32_t p = perm[i];
+        const uint64_t src = (uint64_t)p * nwords + 16 * b, dst = (uint64_t)i * nwords + 16 * b;
+        const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
+        const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
+        uint4 c1 = xor4(x, m);
         pin(c1);
-        const uint4 c2 = xor4(xor4(b, t), load_unit<VEC>(s1, k));
-        store_unit<VEC>(out, k, xor4(c1, c2));
+        c1 = xor4(c1, chacha_quad(k12, i, b, kR2, nwords));
+        const uint4 c2 = xor4(xor4(y, m), chacha_quad(k31, i, b, kR1, nwords));
+        store_quarter<VEC>(out, dst, c, len, xor4(c1, c2));
     }
 }
 
@@ -449,11 +483,12 @@ size_t sort_temp_bytes(uint64_t nrows) {
 uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
     auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
     const uint64_t tw = nrows * nwords * 4;
-    // pi12(D1^D2^T12), Y1, X1, pi31(Y1^T31); three permutations; rotated keys
-    // in and out; row numbers in and out; run starts; the sort's temporary
-    // storage
-    return 4 * r(tw) + 3 * r(nrows * 4) + 2 * r(nrows * 8) + 2 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
-           r(sort_temp_bytes(nrows)) + 4096;
+    // X1 and pi31(Y1 ^ T31); three permutations; for each permutation (they
+    // are made side by side) rotated keys in and out, row numbers in and out,
+    // run starts and the sort's temporary storage
+    const uint64_t scratch = 2 * r(nrows * 8) + 2 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
+                             r(sort_temp_bytes(nrows));
+    return 2 * r(tw) + 3 * r(nrows * 4) + 3 * scratch + 4096;
 }
 
 // perm = stable argsort of the pair seed's row keys (or its inverse): radix
@@ -468,104 +503,169 @@ struct PermScratch {
     size_t temp_bytes;
 };
 
-int make_perm(const RoundKeys& rk, uint32_t p, uint64_t nrows, const PermScratch& w, bool inverse, uint32_t* perm,
-              hipStream_t s) {
+// One permutation in four steps (keys, radix pass, run starts, ranking), so
+// that the three permutations of a shuffle can be enqueued step by step on
+// their streams: each stream then has work as soon as possible, instead of
+// after the host has enqueued the whole of the ones before it.
+struct PermJob {
+    PairKey pk;
+    uint32_t p;
+    bool inverse;
+    uint32_t* perm;
+    PermScratch w;
+    hipStream_t s;
+};
+
+int perm_step(int step, uint64_t nrows, const PermJob& j) {
     const uint32_t hb = run_bits(nrows);
-    hipLaunchKernelGGL(k_perm_keys, dim3(aes_grid(nrows)), dim3(kBlock), 0, s, rk, p, nrows, hb, w.keys, w.idx);
-    int rc = check_launch("k_perm_keys");
-    if (rc) return rc;
-    const uint64_t* keys = w.keys;
-    const uint32_t* rows = w.idx;
-    if (hb) {          // with no run-id bits there is one run, already in row order
-        size_t temp_bytes = w.temp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(w.temp, temp_bytes, w.keys, w.keys_sorted, w.idx, w.idx_sorted,
-                                               (int)nrows, 0, (int)hb, s) != hipSuccess)
-            return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
-        keys = w.keys_sorted;
-        rows = w.idx_sorted;
-    }
+    const PermScratch& w = j.w;
+    // with no run-id bits there is one run, already in row order: no sort
+    const uint64_t* keys = hb ? w.keys_sorted : w.keys;
+    const uint32_t* rows = hb ? w.idx_sorted : w.idx;
     const uint64_t nruns = 1ull << hb;
-    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, s, nrows, hb, keys,
-                       w.starts);
-    rc = check_launch("k_run_starts");
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, s, hb, (uint32_t)inverse, w.starts,
-                       keys, rows, perm);
-    return check_launch("k_rank_runs");
+    switch (step) {
+        case 0:
+            hipLaunchKernelGGL(k_perm_keys, dim3(slice_grid((nrows + 7) / 8 * 4)), dim3(kBlock), 0, j.s, j.pk, j.p,
+                               nrows, hb, w.keys, w.idx);
+            return check_launch("k_perm_keys");
+        case 1: {
+            if (!hb) return 0;
+            size_t temp_bytes = w.temp_bytes;
+            if (hipcub::DeviceRadixSort::SortPairs(w.temp, temp_bytes, w.keys, w.keys_sorted, w.idx, w.idx_sorted,
+                                                   (int)nrows, 0, (int)hb, j.s) != hipSuccess)
+                return fail(FSS_EDEVICE, "rss_shuffle: radix sort failed");
+            return 0;
+        }
+        case 2:
+            hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, j.s, nrows, hb,
+                               keys, w.starts);
+            return check_launch("k_run_starts");
+        default:
+            hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, j.s, hb,
+                               (uint32_t)j.inverse, w.starts, keys, rows, j.perm);
+            return check_launch("k_rank_runs");
+    }
 }
 
-// Round pi23 (k_shuffle_final); the 16-byte path when the width is a multiple
-// of 4 words and every table is 16-byte aligned.
-int shuffle_final(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, const uint32_t* perm,
-                  const uint32_t* g0, const uint32_t* g1, const uint32_t* s0, const uint32_t* s1, uint32_t* out,
-                  hipStream_t s) {
-    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(s0) && aligned16(s1) &&
-                     aligned16(out);
-    const uint64_t units = vec ? nrows * (nwords >> 2) : nrows * nwords;
-    if (vec)
-        hipLaunchKernelGGL(k_shuffle_final<true>, dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords, rk, t_mask,
-                           perm, g0, g1, s0, s1, out);
+// The 16-byte path needs the width a multiple of 4 words and every table
+// 16-byte aligned.
+bool vec_quarters(uint32_t nwords, std::initializer_list<const void*> tables) {
+    if (nwords & 3u) return false;
+    for (const void* t : tables)
+        if (!aligned16(t)) return false;
+    return true;
+}
+
+int shuffle_first(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k31, const uint32_t* inv12,
+                  const uint32_t* inv31, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2, uint32_t* o0,
+                  uint32_t* o1, uint32_t* r12, uint32_t* r31, hipStream_t s) {
+    const unsigned grid = slice_grid(nrows * ((nwords + 15) / 16) * 4);
+    if (vec_quarters(nwords, {g0, g1, g2, o0, o1, r12, r31}))
+        hipLaunchKernelGGL(k_shuffle_first<true>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k31, inv12,
+                           inv31, g0, g1, g2, o0, o1, r12, r31);
     else
-        hipLaunchKernelGGL(k_shuffle_final<false>, dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords, rk, t_mask,
-                           perm, g0, g1, s0, s1, out);
+        hipLaunchKernelGGL(k_shuffle_first<false>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k31, inv12,
+                           inv31, g0, g1, g2, o0, o1, r12, r31);
+    return check_launch("k_shuffle_first");
+}
+
+int shuffle_final(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k23, PairKey k31, const uint32_t* perm,
+                  const uint32_t* g0, const uint32_t* g1, uint32_t* out, hipStream_t s) {
+    const unsigned grid = slice_grid(nrows * ((nwords + 15) / 16) * 4);
+    if (vec_quarters(nwords, {g0, g1, out}))
+        hipLaunchKernelGGL(k_shuffle_final<true>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k23, k31, perm,
+                           g0, g1, out);
+    else
+        hipLaunchKernelGGL(k_shuffle_final<false>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k23, k31, perm,
+                           g0, g1, out);
     return check_launch("k_shuffle_final");
 }
 
-// Rounds pi12 / pi31 as scatters (k_shuffle_scatter), with the same 16-byte
-// path condition.
-template <int ROUND>
-int shuffle_scatter(uint64_t nrows, uint32_t nwords, const RoundKeys& rk, uint32_t t_mask, uint32_t r_mask,
-                    const uint32_t* inv, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2, uint32_t* o0,
-                    uint32_t* o1, uint32_t* rout, hipStream_t s) {
-    const bool vec = (nwords & 3u) == 0 && aligned16(g0) && aligned16(g1) && aligned16(g2) && aligned16(o0) &&
-                     aligned16(o1) && aligned16(rout);
-    const uint64_t units = vec ? nrows * (nwords >> 2) : nrows * nwords;
-    if (vec)
-        hipLaunchKernelGGL((k_shuffle_scatter<ROUND, true>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
-                           rk, t_mask, r_mask, inv, g0, g1, g2, o0, o1, rout);
-    else
-        hipLaunchKernelGGL((k_shuffle_scatter<ROUND, false>), dim3(aes_grid(units)), dim3(kBlock), 0, s, nrows, nwords,
-                           rk, t_mask, r_mask, inv, g0, g1, g2, o0, o1, rout);
-    return check_launch("k_shuffle_scatter");
+// Two streams of the library's own per device (default priority,
+// non-blocking) on which the permutations pi31 and pi23 are made while pi12
+// is made on the caller's stream: the permutations are independent, and most
+// of their kernels are small or latency-bound.  Ordered against the caller's
+// stream with events only; nullptr if they cannot be created (then all runs
+// on the caller's stream).
+hipStream_t perm_stream(int i) {
+    static std::mutex mu;
+    static std::map<int, std::array<hipStream_t, 2>> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        std::array<hipStream_t, 2> st{nullptr, nullptr};
+        for (auto& x : st)
+            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) x = nullptr;
+        it = streams.emplace(dev, st).first;
+    }
+    return it->second[i];
 }
 
-// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.  The
-// servers' steps are grouped by the pair permutation they apply, one launch
-// per round: pi12 (CS1, CS2), pi31 (CS1, CS3), pi23 (CS2, CS3).
+// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
     const uint64_t tw = nrows * nwords;
-    const RoundKeys k12 = seed_key(seeds[0]), k23 = seed_key(seeds[1]), k31 = seed_key(seeds[2]);
-    uint32_t* z = ws.take<uint32_t>(tw);       // CS1: pi12(D1 ^ D2 ^ T12)
-    uint32_t* y1 = ws.take<uint32_t>(tw);      // CS2 -> CS3: Y1
+    const PairKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
     uint32_t* x1 = ws.take<uint32_t>(tw);      // CS1 -> CS2: X1
     uint32_t* v = ws.take<uint32_t>(tw);       // CS3: pi31(Y1 ^ T31)
     uint32_t* p12 = ws.take<uint32_t>(nrows);
     uint32_t* p23 = ws.take<uint32_t>(nrows);
     uint32_t* p31 = ws.take<uint32_t>(nrows);
-    PermScratch pw;
-    pw.keys = ws.take<uint64_t>(nrows);
-    pw.keys_sorted = ws.take<uint64_t>(nrows);
-    pw.idx = ws.take<uint32_t>(nrows);
-    pw.idx_sorted = ws.take<uint32_t>(nrows);
-    pw.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
-    pw.temp_bytes = sort_temp_bytes(nrows);
-    pw.temp = ws.take<uint8_t>(pw.temp_bytes);
+    PermScratch pw[3];
+    for (PermScratch& w : pw) {
+        w.keys = ws.take<uint64_t>(nrows);
+        w.keys_sorted = ws.take<uint64_t>(nrows);
+        w.idx = ws.take<uint32_t>(nrows);
+        w.idx_sorted = ws.take<uint32_t>(nrows);
+        w.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
+        w.temp_bytes = sort_temp_bytes(nrows);
+        w.temp = ws.take<uint8_t>(w.temp_bytes);
+    }
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
+    // pi12 on the caller's stream, pi31 and pi23 on the library's two streams
+    // (after everything already on the caller's stream); the caller's stream
+    // waits for each before the launch that applies it.
+    hipStream_t side[2] = {perm_stream(0), perm_stream(1)};
+    hipEvent_t fork = nullptr, done[2] = {nullptr, nullptr};
+    bool forked = side[0] && side[1] && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&done[0], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&done[1], hipEventDisableTiming) == hipSuccess &&
+                  hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side[0], fork, 0) == hipSuccess &&
+                  hipStreamWaitEvent(side[1], fork, 0) == hipSuccess;
+    const hipStream_t s31 = forked ? side[0] : s, s23 = forked ? side[1] : s;
     // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1.
     // pi12 and pi31 are applied as scatters (their inverses), pi23 as a gather
-    int rc = make_perm(k12, kP12, nrows, pw, true, p12, s);
-    if (!rc) rc = make_perm(k23, kP23, nrows, pw, false, p23, s);
-    if (!rc) rc = make_perm(k31, kP31, nrows, pw, true, p31, s);
-    // pi12: CS1 forms pi12(D1 ^ D2 ^ T12), CS2 forms Y1 = pi12(D3 ^ T12); R2 drawn
-    if (!rc)
-        rc = shuffle_scatter<kRound12>(nrows, nwords, k12, kT12, kR2, p12, d[0], d[1], d[2], z, y1, out[1], s);
-    // pi31: CS1 forms X1 = pi31(pi12(...) ^ T31), CS3 forms pi31(Y1 ^ T31); R1 drawn
-    if (!rc)
-        rc = shuffle_scatter<kRound31>(nrows, nwords, k31, kT31, kR1, p31, z, y1, nullptr, x1, v, out[0], s);
-    // pi23: CS2 forms C1 = pi23(X1 ^ T23) ^ R2, CS3 forms C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
-    // and R3 = C1 ^ C2 (with the servers simulated together, C1 and C2 are not stored)
-    if (!rc) rc = shuffle_final(nrows, nwords, k23, kT23, p23, x1, v, out[1], out[0], out[2], s);
+    const PermJob jobs[3] = {{k12, kP12, true, p12, pw[0], s},
+                             {k31, kP31, true, p31, pw[1], s31},
+                             {k23, kP23, false, p23, pw[2], s23}};
+    int prc[3] = {0, 0, 0};
+    for (int step = 0; step < 4; step++)
+        for (int q = 0; q < 3; q++)
+            if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q]);
+    int rc = prc[0];
+    const int rc31 = prc[1], rc23 = prc[2];
+    const bool rec31 = !forked || hipEventRecord(done[0], s31) == hipSuccess;
+    const bool rec23 = !forked || hipEventRecord(done[1], s23) == hipSuccess;
+    if (!rc) rc = rc31 ? rc31 : rc23;
+    // every join is enqueued whatever happened, so that no work on the
+    // library's streams outlives the caller's view of this call
+    auto join = [&](int i, bool recorded) {
+        if (!forked) return true;
+        if (recorded && hipStreamWaitEvent(s, done[i], 0) == hipSuccess) return true;
+        (void)hipStreamSynchronize(side[i]);
+        return false;
+    };
+    // pi12 then pi31: CS1's X1, CS3's pi31(Y1 ^ T31); R2 and R1 drawn
+    if (!join(0, rec31) && !rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
+    if (!rc) rc = shuffle_first(nrows, nwords, k12, k31, p12, p31, d[0], d[1], d[2], x1, v, out[1], out[0], s);
+    // pi23: CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
+    // R3 = C1 ^ C2
+    if (!join(1, rec23) && !rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
+    if (!rc) rc = shuffle_final(nrows, nwords, k12, k23, k31, p23, x1, v, out[2], s);
+    for (hipEvent_t e : {fork, done[0], done[1]})
+        if (e) (void)hipEventDestroy(e);
     return rc;
 }
 

@@ -73,20 +73,38 @@ def test_fetch_case2_all_matches():
 
 
 def test_batched_blocks_are_the_single_blocks():
-    """The batched generator returns rng_block's blocks for consecutive
-    counters, so the mask tables and sort keys built from it follow their
-    per-word and per-row definitions."""
+    """The batched AES generator returns rng_block's blocks for consecutive
+    counters."""
     from oracle import fss as ofss
     got = ofss.rng_blocks(77, 6, 4, 9, 0, 2**32 - 3, 6)
     for i in range(6):
         assert got[i].tobytes() == ofss.rng_block(77, 6, 4, 9, 0, (2**32 - 3 + i) % 2**32)
-    n, w = 7, 3
-    t = osh.mask_table(5, osh.T31, n, w)
-    for r in range(n):
-        for c in range(w):
-            k = r * w + c
-            b = ofss.rng_block(5, 6, osh.T31, w, 0, k // 4)
-            assert int(t[r, c]) == int.from_bytes(b[4 * (k % 4):4 * (k % 4) + 4], "little")
-    keys = [int.from_bytes(ofss.rng_block(5, 6, 16 + osh.P23, 0, 0, r)[:8], "little") for r in range(50)]
-    np.testing.assert_array_equal(osh.permutation(5, osh.P23, 50),
+
+
+def test_tables_and_keys_follow_their_definitions():
+    """Mask tables and sort keys, built batched, against one ChaCha12 block per
+    word or row: word w of record r is slice word w mod 16 of block (r, w div
+    16, table, W), slice word 4c + k being state word 4k + c; the key of row r
+    is slice words 2e, 2e + 1 (e = r mod 8) of block (r div 8, 0, 16 + p, 0);
+    the permutation sorts by (key, row)."""
+    from oracle import chacha
+    seed = 0x1234_5678_9ABC_DEF0
+    key = [0x9ABCDEF0, 0x12345678, 6, 0, 0, 0, 0, 0]
+
+    def slice_word(blk, s):
+        return int(blk[4 * (s % 4) + s // 4])
+
+    for n, w in ((7, 3), (3, 37)):
+        t = osh.mask_table(seed, osh.T31, n, w)
+        assert t.shape == (n, w)
+        for r in range(n):
+            for c in range(w):
+                blk = chacha.blocks(key, r, c // 16, osh.T31, w, 12)[0]
+                assert int(t[r, c]) == slice_word(blk, c % 16)
+    keys = []
+    for r in range(50):
+        blk = chacha.blocks(key, r // 8, 0, 16 + osh.P23, 0, 12)[0]
+        e = r % 8
+        keys.append(slice_word(blk, 2 * e) | (slice_word(blk, 2 * e + 1) << 32))
+    np.testing.assert_array_equal(osh.permutation(seed, osh.P23, 50),
                                   sorted(range(50), key=lambda r: (keys[r], r)))
