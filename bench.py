@@ -689,10 +689,11 @@ def run_next(args, torch, fss, dev):
     nw = nrows // 32
     x3, y3, z3 = [rnd(nw) for _ in range(3)], [rnd(nw) for _ in range(3)], [rnd(nw) for _ in range(3)]
     keys = [11, 22, 33]
+    prf_blocks = 3 * ((nw + 15) // 16)              # one ChaCha12 block per 16 words per PRF key
     res["rss_and"] = row("rss_and", timed(lambda: fss.rss_and(nrows, x3, y3, keys, 5, z3, stream)),
-                         9 * 4 * nw, 3 * nw / 4, f"{nrows} bits: 6 shares read, 3 written, 3 PRF streams")
+                         9 * 4 * nw, 0, f"{nrows} bits: 6 shares read, 3 written, 3 PRF streams", prf_blocks)
     res["rss_reshare"] = row("rss_reshare", timed(lambda: fss.rss_reshare(nrows, x3, keys, 6, z3, stream)),
-                             6 * 4 * nw, 3 * nw / 4, f"{nrows} bits: 3 shares read, 3 written, 3 PRF streams")
+                             6 * 4 * nw, 0, f"{nrows} bits: 3 shares read, 3 written, 3 PRF streams", prf_blocks)
     del x3, y3, z3
     # secShuffle of 2^22 records of 64 B, and the fetches
     nrec, nwords = 1 << 22, 16

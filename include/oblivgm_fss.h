@@ -311,9 +311,11 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
  * Three-party binary RSS arithmetic (Sec. III-B), all three parties simulated.
  * Share vectors are packed words (ceil(nrows/32) each); party P_i holds shares
  * i and i+1 (indices mod 3).  Zero sharing: <alpha>_i = F(k_i, j) ^ F(k_{i-1}, j)
- * with F(k, j) word w = little-endian word (w mod 4) of
- * AES_{LE64(k)||"OBLIVGM1"}(LE16 5 || LE16 0 || LE32 j || LE32 0 || LE32 (w div 4)),
- * j = `counter` (fresh per call), k_i = prf_keys[i].  Pad bits are cleared.
+ * with F(k, j) word w = slice word (w mod 16) of the ChaCha12 block (RFC 8439's
+ * block function, 12 rounds) under key words (k mod 2^32, k div 2^32, 5, 0, 0, 0,
+ * 0, 0) with state words 12-15 = (w div 16, j, 0, 0), its words read column by
+ * column (slice word 4c + k = state word 4k + c); j = `counter` (fresh per call),
+ * k_i = prf_keys[i].  Pad bits are cleared.  At most 2^41 rows (FSS_EUNSUPPORTED).
  * rss_reshare: three-out-of-three XOR shares x_i -> RSS shares z_i = x_i ^ <alpha>_i
  *   (P_i keeps z_i and obtains z_{i+1} from P_{i+1}; the paper words this as a
  *   send to P_{i+1}, which under its own holding convention is the same ring

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fss
+from . import chacha, fss
 
 # (party of the key, replica j - 1, share index - 1) for the two terms of CS_1, CS_2, CS_3
 SERVER_TERMS = [
@@ -77,11 +77,16 @@ def server_shares(kind: str, npos: int, keys_pair, nbits: int, shares) -> np.nda
 # --------------------------------------------------------------------------- three-party RSS arithmetic
 
 def prf_words(key_seed: int, counter: int, nwords: int) -> np.ndarray:
-    """F(k, j) on packed words: word w is little-endian word (w mod 4) of
-    AES_{LE64(k)||"OBLIVGM1"}(LE16 5 || LE16 0 || LE32 counter || LE32 0 || LE32 (w div 4))
-    (the generator's domain 5)."""
-    blocks = fss.rng_blocks(key_seed, 5, 0, counter, 0, 0, (nwords + 3) // 4)
-    return blocks.view("<u4").reshape(-1)[:nwords].astype(np.uint32)
+    """F(k, j) on packed words: ChaCha12 (``oracle/chacha.py``) under the key
+    (k mod 2^32, k div 2^32, 5, 0, 0, 0, 0, 0); word w is slice word (w mod 16)
+    of block (w div 16, j, 0, 0), a block's words read column by column (slice
+    word 4c + k = state word 4k + c)."""
+    k = key_seed & ((1 << 64) - 1)
+    nblk = (nwords + 15) // 16
+    words = chacha.blocks([k & 0xFFFFFFFF, k >> 32, 5, 0, 0, 0, 0, 0], np.arange(nblk, dtype=np.uint64), counter, 0,
+                          0, 12)
+    words = words.reshape(-1, 4, 4).transpose(0, 2, 1).reshape(-1)
+    return words[:nwords].astype(np.uint32)
 
 
 def zero_shares(prf_keys, counter: int, nwords: int):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", "fss_lib.hip"), os.path.join(HERE, "csrc", "shuffle.hip")]
 SRC = SRCS[0]
-HEADERS = [os.path.join(HERE, "csrc", "aes_gfx950.hpp"), os.path.join(HERE, "csrc", "common.hpp"),
+HEADERS = [os.path.join(HERE, "csrc", "aes_gfx950.hpp"), os.path.join(HERE, "csrc", "chacha_gfx950.hpp"),
+           os.path.join(HERE, "csrc", "common.hpp"),
            os.path.join(ROOT, "include", "oblivgm_fss.h")]
 LIB = os.path.join(HERE, "liboblivgm_fss.so")
 

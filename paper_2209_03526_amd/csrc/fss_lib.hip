@@ -28,6 +28,7 @@
 
 #include "../../include/oblivgm_fss.h"
 #include "aes_gfx950.hpp"
+#include "chacha_gfx950.hpp"
 #include "common.hpp"
 
 using namespace ogm;
@@ -760,7 +761,7 @@ __global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__
 // ----------------------------------------------------------------- three-party RSS arithmetic
 
 struct RssArgs {
-    RoundKeys prf[3];       // F(k_i, .) = AES under LE64(k_i) || "OBLIVGM1"
+    ChachaKey prf[3];       // F(k_i, .) = ChaCha12 under (k_i, domain 5)
     const uint32_t* x[3];
     const uint32_t* y[3];   // null for a plain re-share
     uint32_t* z[3];
@@ -770,21 +771,19 @@ struct RssArgs {
     uint32_t vec;           // every share buffer 16-byte aligned: 16-byte loads / stores
 };
 
-// Thread m owns words 4m .. 4m+3.  For the AND, party P_i first forms
+constexpr int kRssBlock = 256;
+
+// Thread m owns words 4m .. 4m+3, lane m & 3 of the quad that makes PRF block
+// m div 4 (words 16 (m div 4) .. + 15).  For the AND, party P_i first forms
 // z_i = x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i from the two shares it holds; then
 // z_i ^= F(k_i, j) ^ F(k_{i-1}, j) (a fresh sharing of zero), pad bits cleared.
-__global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
-    __shared__ uint32_t tab[kLdsTableWords];
-    lds_table_fill(tab, g_tables.t0);
-    __syncthreads();
-    // One group of 4 words per thread: with no loop around them, the three
-    // per-party key schedules are read from the kernel arguments where each
-    // block needs them instead of being held in scalar registers together.
-    const uint64_t m = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (4 * m >= A.nwords) return;
-    const LaneOff loff = lane_offset();
+// Every lane of a launched quad makes the PRF blocks; only the loads and
+// stores are bounded by the share length.
+__global__ __launch_bounds__(kRssBlock) void k_rss(RssArgs A) {
+    const uint64_t m = (uint64_t)blockIdx.x * kRssBlock + threadIdx.x;
+    const bool any = 4 * m < A.nwords;
     const bool whole = A.vec && 4 * m + 4 <= A.nwords;
-    // the shares are loaded before the AES, so that their latency overlaps it
+    // the shares are loaded before the PRF, so that their latency overlaps it
     uint4 xv[3], yv[3];
     if (whole) {
 #pragma unroll
@@ -795,8 +794,8 @@ __global__ __launch_bounds__(kBlock) void k_rss(RssArgs A) {
     }
     uint4 f[3];
 #pragma unroll
-    for (int i = 0; i < 3; i++)
-        f[i] = aes128_encrypt(make_uint4(5u, A.counter, 0u, (uint32_t)m), ArgKey{A.prf[i]}, tab, loff);
+    for (int i = 0; i < 3; i++) f[i] = chacha_quad(A.prf[i], (uint32_t)(m >> 2), A.counter, 0u, 0u);
+    if (!any) return;
     if (whole) {
         // four whole words: 16-byte loads and stores
         const uint32_t pm[4] = {pad_mask(4 * m, A.nrows), pad_mask(4 * m + 1, A.nrows), pad_mask(4 * m + 2, A.nrows),
@@ -1503,7 +1502,7 @@ static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* c
     RssArgs A{};
     for (int i = 0; i < 3; i++) {
         if (!d_x[i] || !d_z[i] || (d_y && !d_y[i])) return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
-        A.prf[i] = dealer_key(prf_keys[i]);
+        A.prf[i] = ogm::chacha_key(prf_keys[i], 5);
         A.x[i] = d_x[i];
         A.y[i] = d_y ? d_y[i] : nullptr;
         A.z[i] = d_z[i];
@@ -1515,7 +1514,10 @@ static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* c
     for (int i = 0; i < 3; i++)
         if (!aligned16(A.x[i]) || !aligned16(A.y[i]) || !aligned16(A.z[i])) A.vec = 0;
     const uint64_t groups = (A.nwords + 3) / 4;
-    hipLaunchKernelGGL(k_rss, dim3((unsigned)((groups + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, A);
+    if (A.nwords > (1ull << 36))        // PRF block numbers are 32-bit: 16 words a block
+        return fail(FSS_EUNSUPPORTED, "%s: %llu rows is more than 2^41", who, (unsigned long long)nrows);
+    hipLaunchKernelGGL(k_rss, dim3((unsigned)((groups + kRssBlock - 1) / kRssBlock)), dim3(kRssBlock), 0,
+                       (hipStream_t)stream, A);
     return check_launch("k_rss");
 }
 

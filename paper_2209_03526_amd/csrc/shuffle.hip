@@ -4,10 +4,11 @@
 // Tables are row-major: record r of a W-word table at words [r*W, r*W + W).
 // Each pair of servers derives from its seed, with ChaCha12, its permutation
 // (stable sort of one 64-bit key per row) and its mask tables; applying a
-// permutation is the row gather out[i] = in[perm[i]].  A thread takes one
-// 16-word slice of a record, which is one ChaCha block of every mask table,
-// so masks are made where they are XORed (VALU only, no table in LDS) and no
-// mask table is stored.
+// permutation is the row gather out[i] = in[perm[i]].  A quad of lanes takes
+// one 16-word slice of a record, which is one ChaCha block of every mask
+// table (made by the four lanes together, chacha_gfx950.hpp), each lane one
+// 16-byte quarter of it; so masks are made where they are XORed (VALU only,
+// no table in LDS) and no mask table is stored.
 //
 // Two launches carry the five steps of Alg. 5.  The first reads the input
 // shares in order and scatters each row through both inverse permutations
@@ -28,6 +29,7 @@
 #include <mutex>
 
 #include "../../include/oblivgm_fss.h"
+#include "chacha_gfx950.hpp"
 #include "common.hpp"
 
 using namespace ogm;
@@ -48,58 +50,10 @@ unsigned slice_grid(uint64_t items) {
     return (unsigned)g;
 }
 
-// ---------------------------------------------------------------- ChaCha12
-// The block function of ChaCha (Bernstein 2008; RFC 8439 gives the 20-round
-// form) with 12 rounds.  A pair's key is its seed: key words (seed mod 2^32,
-// seed div 2^32, 6, 0, 0, 0, 0, 0); state words 12-15 name the block.
-//
-// Four consecutive lanes make one block together: lane c holds column c of
-// the state (words c, 4 + c, 8 + c, 12 + c) and applies the column round's
-// quarter round to it; for the diagonal round rows 1-3 rotate across the
-// four lanes by 1, 2 and 3 (DPP quad permutations), and back afterwards.  A
-// block's words are read column by column (slice word 4c + k is state word
-// 4k + c), so lane c ends holding slice words 4c .. 4c + 3: the 16-byte
-// quarter it loads and stores, and four lanes move a whole 64-byte slice in
-// one access.  The four lanes of a quad must all be active.
-constexpr int kChachaRounds = 12;
+// Pair keys: ChaCha key words (seed mod 2^32, seed div 2^32, 6, 0, 0, 0, 0, 0).
+constexpr uint32_t kShuffleDomain = 6;
 
-struct PairKey {
-    uint32_t lo, hi;
-};
-
-PairKey pair_key(uint64_t seed) { return PairKey{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
-
-__device__ __forceinline__ void quarter(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
-    a += b; d = __builtin_rotateleft32(d ^ a, 16);
-    c += d; b = __builtin_rotateleft32(b ^ c, 12);
-    a += b; d = __builtin_rotateleft32(d ^ a, 8);
-    c += d; b = __builtin_rotateleft32(b ^ c, 7);
-}
-
-// lane c of the quad takes the value of lane (c + S) mod 4
-template <int S>
-__device__ __forceinline__ uint32_t from_lane(uint32_t v) {
-    constexpr int ctrl = ((0 + S) & 3) | (((1 + S) & 3) << 2) | (((2 + S) & 3) << 4) | (((3 + S) & 3) << 6);
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
-}
-
-// Lane c = lane & 3 of each quad: returns slice words 4c .. 4c + 3 of block
-// (w12, w13, w14, w15) under key k.
-__device__ __forceinline__ uint4 chacha_quad(PairKey k, uint32_t w12, uint32_t w13, uint32_t w14, uint32_t w15) {
-    const uint32_t c = threadIdx.x & 3u;
-    const uint32_t a0 = c == 0 ? 0x61707865u : c == 1 ? 0x3320646eu : c == 2 ? 0x79622d32u : 0x6b206574u;
-    const uint32_t b0 = c == 0 ? k.lo : c == 1 ? k.hi : c == 2 ? 6u : 0u;      // key words c; 4 + c are 0
-    const uint32_t d0 = c == 0 ? w12 : c == 1 ? w13 : c == 2 ? w14 : w15;
-    uint32_t x0 = a0, x1 = b0, x2 = 0u, x3 = d0;
-#pragma unroll
-    for (int r = 0; r < kChachaRounds / 2; r++) {
-        quarter(x0, x1, x2, x3);
-        x1 = from_lane<1>(x1), x2 = from_lane<2>(x2), x3 = from_lane<3>(x3);
-        quarter(x0, x1, x2, x3);
-        x1 = from_lane<3>(x1), x2 = from_lane<2>(x2), x3 = from_lane<1>(x3);
-    }
-    return make_uint4(x0 + a0, x1 + b0, x2, x3 + d0);
-}
+ChachaKey pair_key(uint64_t seed) { return chacha_key(seed, kShuffleDomain); }
 
 // Sort keys of permutation p: the key of row r is slice words 2e (low) and
 // 2e + 1 (high), e = r mod 8, of block (r div 8, 0, 16 + p, 0); a quad makes
@@ -107,7 +61,7 @@ __device__ __forceinline__ uint4 chacha_quad(PairKey k, uint32_t w12, uint32_t w
 // stored rotated left by hb bits, so that its top hb bits (the row's run id)
 // sit in bits 0 .. hb-1, the range the radix pass sorts, and the whole key
 // travels with it; the row number goes beside it.
-__global__ __launch_bounds__(kBlock) void k_perm_keys(PairKey pk, uint32_t p, uint64_t nrows, uint32_t hb,
+__global__ __launch_bounds__(kBlock) void k_perm_keys(ChachaKey pk, uint32_t p, uint64_t nrows, uint32_t hb,
                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
     const uint64_t total = ((nrows + 7) >> 3) * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -256,7 +210,7 @@ __device__ __forceinline__ void pin(uint4& v) {
 // The masks are indexed by the row they are XORed at: T12 before pi12, T31
 // before pi31.  A quad of lanes takes one slice.
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k31,
+__global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k31,
                                                         const uint32_t* __restrict__ inv12,
                                                         const uint32_t* __restrict__ inv31,
                                                         const uint32_t* __restrict__ g0,
@@ -292,8 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32
 // not stored).  R1 and R2 are made again from their pairs' keys rather than
 // read back.
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k23,
-                                                        PairKey k31, const uint32_t* __restrict__ perm,
+__global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
+                                                        ChachaKey k31, const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ g0,
                                                         const uint32_t* __restrict__ g1, uint32_t* __restrict__ out) {
     const uint32_t nb = (nwords + 15) >> 4;
@@ -508,7 +462,7 @@ struct PermScratch {
 // their streams: each stream then has work as soon as possible, instead of
 // after the host has enqueued the whole of the ones before it.
 struct PermJob {
-    PairKey pk;
+    ChachaKey pk;
     uint32_t p;
     bool inverse;
     uint32_t* perm;
@@ -556,7 +510,7 @@ bool vec_quarters(uint32_t nwords, std::initializer_list<const void*> tables) {
     return true;
 }
 
-int shuffle_first(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k31, const uint32_t* inv12,
+int shuffle_first(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k31, const uint32_t* inv12,
                   const uint32_t* inv31, const uint32_t* g0, const uint32_t* g1, const uint32_t* g2, uint32_t* o0,
                   uint32_t* o1, uint32_t* r12, uint32_t* r31, hipStream_t s) {
     const unsigned grid = slice_grid(nrows * ((nwords + 15) / 16) * 4);
@@ -569,7 +523,7 @@ int shuffle_first(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k31, con
     return check_launch("k_shuffle_first");
 }
 
-int shuffle_final(uint64_t nrows, uint32_t nwords, PairKey k12, PairKey k23, PairKey k31, const uint32_t* perm,
+int shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23, ChachaKey k31, const uint32_t* perm,
                   const uint32_t* g0, const uint32_t* g1, uint32_t* out, hipStream_t s) {
     const unsigned grid = slice_grid(nrows * ((nwords + 15) / 16) * 4);
     if (vec_quarters(nwords, {g0, g1, out}))
@@ -607,7 +561,7 @@ hipStream_t perm_stream(int i) {
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
     const uint64_t tw = nrows * nwords;
-    const PairKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
+    const ChachaKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
     uint32_t* x1 = ws.take<uint32_t>(tw);      // CS1 -> CS2: X1
     uint32_t* v = ws.take<uint32_t>(tw);       // CS3: pi31(Y1 ^ T31)
     uint32_t* p12 = ws.take<uint32_t>(nrows);

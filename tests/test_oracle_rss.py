@@ -105,3 +105,17 @@ def test_sec_eval_then_rss_and_is_the_conjunction():
     z = rss.rss_and(p1, p2, [7, 8, 9], 2, values.size)
     got = ofss.unpack_bits(z[0] ^ z[1] ^ z[2], values.size)
     np.testing.assert_array_equal(got, ((values >= 30) & (values < 40)).astype(np.uint8))
+
+
+def test_prf_words_follow_their_definition():
+    """F(k, j), built batched, against one ChaCha12 block per word: word w is
+    slice word w mod 16 (slice word 4c + k = state word 4k + c) of block
+    (w div 16, j, 0, 0) under the key (k mod 2^32, k div 2^32, 5, 0, ...)."""
+    from oracle import chacha
+    k, j = 0xFEDC_BA98_7654_3210, 11
+    got = rss.prf_words(k, j, 37)
+    assert got.shape == (37,)
+    for w in range(37):
+        blk = chacha.blocks([0x76543210, 0xFEDCBA98, 5, 0, 0, 0, 0, 0], w // 16, j, 0, 0, 12)[0]
+        s = w % 16
+        assert int(got[w]) == int(blk[4 * (s % 4) + s // 4])
