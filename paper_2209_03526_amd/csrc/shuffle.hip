@@ -342,25 +342,33 @@ __global__ void k_open_flags(uint64_t nrows, uint32_t nwords, const uint32_t* __
 }
 
 // secAccess filter: flag of shuffled record i = parity of all bits of R1 ^ R2 ^ R3
-// (1 for a one-hot ID, 0 for a dummy all-zero ID).  With vec (width a
-// multiple of 4 words, tables 16-byte aligned) the loads are 16 bytes.
+// (1 for a one-hot ID, 0 for a dummy all-zero ID).  A quad of lanes takes a
+// record, lane c its 16-byte quarters c, c + 4, ... (with vec: width a
+// multiple of 4 words, tables 16-byte aligned; else its words c, c + 4, ...),
+// so a wavefront reads 16 consecutive 64-byte records in one access; the
+// quad's partial XORs meet through DPP quad moves.
 __global__ void k_open_parity(uint64_t nrows, uint32_t nwords, uint32_t vec, const uint32_t* __restrict__ a,
                               const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
                               uint32_t* __restrict__ flags) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = t >> 2;
+    if (i >= nrows) return;                         // whole quads leave together
+    const uint32_t lane = (uint32_t)t & 3u;
     uint32_t acc = 0;
     if (vec) {
-        const uint64_t base = i * (nwords >> 2);
-        for (uint32_t w = 0; w < (nwords >> 2); w++) {
-            const uint4 v = xor4(xor4(((const uint4*)a)[base + w], ((const uint4*)b)[base + w]),
-                                 ((const uint4*)c)[base + w]);
+        const uint32_t nq = nwords >> 2;
+        const uint64_t base = i * nq;
+        for (uint32_t q = lane; q < nq; q += 4) {
+            const uint4 v = xor4(xor4(((const uint4*)a)[base + q], ((const uint4*)b)[base + q]),
+                                 ((const uint4*)c)[base + q]);
             acc ^= v.x ^ v.y ^ v.z ^ v.w;
         }
     } else {
-        for (uint32_t w = 0; w < nwords; w++) acc ^= a[i * nwords + w] ^ b[i * nwords + w] ^ c[i * nwords + w];
+        for (uint32_t w = lane; w < nwords; w += 4) acc ^= a[i * nwords + w] ^ b[i * nwords + w] ^ c[i * nwords + w];
     }
-    flags[i] = __builtin_popcount(acc) & 1u;
+    acc ^= quad_from<1>(acc);
+    acc ^= quad_from<2>(acc);
+    if (lane == 0) flags[i] = __builtin_popcount(acc) & 1u;
 }
 
 // Copy the kept records (words first..W-1) of the three share tables to their
@@ -382,6 +390,26 @@ __global__ void k_compact(uint64_t nrows, uint32_t nwords, uint32_t first, const
         o1[d * rw + w] = s1[src];
         o2[d * rw + w] = s2[src];
         if (w == 0) rows_out[d] = i;
+    }
+}
+
+// k_compact for whole records (first = 0) of a width that is a multiple of 4
+// words, every table 16-byte aligned: one thread per 16-byte quarter.
+__global__ void k_compact_vec(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ flags,
+                              const uint32_t* __restrict__ pos, const uint4* __restrict__ s0,
+                              const uint4* __restrict__ s1, const uint4* __restrict__ s2, uint4* __restrict__ o0,
+                              uint4* __restrict__ o1, uint4* __restrict__ o2, uint32_t* __restrict__ rows_out) {
+    const uint32_t nq = nwords >> 2;
+    const uint64_t total = nrows * nq;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+        const uint32_t i = (uint32_t)(k / nq), q = (uint32_t)(k - (uint64_t)i * nq);
+        if (!flags[i]) continue;
+        const uint64_t d = (uint64_t)pos[i] * nq + q;
+        o0[d] = s0[k];
+        o1[d] = s1[k];
+        o2[d] = s2[k];
+        if (q == 0) rows_out[pos[i]] = i;
     }
 }
 
@@ -708,7 +736,7 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
     if (rc) return rc;
     if (parity)
-        hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
+        hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((4 * ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
                            (uint32_t)((nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2])),
                            sh[0], sh[1], sh[2], flags);
     else
@@ -718,8 +746,15 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     if (rc) return rc;
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan, flags, pos, (int)ncand, s) != hipSuccess)
         return fail(FSS_EDEVICE, "%s: scan failed", who);
-    hipLaunchKernelGGL(k_compact, dim3(grid_of(ncand * (nwords - (parity ? 0u : 1u)), 256)), dim3(256), 0, s, ncand, nwords,
-                       parity ? 0u : 1u, flags, pos, sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out);
+    if (parity && (nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2]) &&
+        aligned16(d_out[0]) && aligned16(d_out[1]) && aligned16(d_out[2]))
+        hipLaunchKernelGGL(k_compact_vec, dim3(grid_of(ncand * (nwords >> 2), 256)), dim3(256), 0, s, ncand, nwords,
+                           flags, pos, (const uint4*)sh[0], (const uint4*)sh[1], (const uint4*)sh[2],
+                           (uint4*)d_out[0], (uint4*)d_out[1], (uint4*)d_out[2], d_rows_out);
+    else
+        hipLaunchKernelGGL(k_compact, dim3(grid_of(ncand * (nwords - (parity ? 0u : 1u)), 256)), dim3(256), 0, s,
+                           ncand, nwords, parity ? 0u : 1u, flags, pos, sh[0], sh[1], sh[2], d_out[0], d_out[1],
+                           d_out[2], d_rows_out);
     rc = check_launch("k_compact");
     if (rc) return rc;
     hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, ncand, flags, pos, d_count);

@@ -139,7 +139,7 @@ def test_fetch_many(fss, n, w):
     assert sorted(map(tuple, rec.tolist())) == sorted(map(tuple, d[x == 1].tolist()))
 
 
-@pytest.mark.parametrize("n,w", [(999, 2), (131075, 4)])
+@pytest.mark.parametrize("n,w", [(999, 2), (3001, 7), (5003, 20), (70001, 16), (131075, 4)])
 def test_compact_valid(fss, n, w):
     """The secAccess filter against the oracle: records whose bits XOR to 1 are
     kept in shuffled order (every third record an all-zero dummy), with their
