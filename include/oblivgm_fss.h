@@ -346,7 +346,9 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  *   a permutation applied to a table gathers out[i] = in[perm[i]].
  * The permutations are made on two streams of the library's own besides the
  * caller's, ordered against the caller's stream with events: the call's work
- * is complete when the caller's stream reaches the call's end.
+ * is complete when the caller's stream reaches the call's end.  These calls
+ * are not meant for stream capture into a graph: their radix passes clear
+ * buffers with memset operations.
  * The messages follow the algorithm (its X_2 in CS2's step is the X1 it
  * received): X1 = pi31[pi12(D1^D2^T12)^T31]; Y1 = pi12(D3^T12);
  * C1 = pi23(X1^T23)^R2; C2 = pi23[pi31(Y1^T31)^T23]^R1; R3 = C1^C2.

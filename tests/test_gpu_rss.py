@@ -65,7 +65,7 @@ def test_sec_eval_parity(fss, kind, npos, ncand):
     assert (xs[0][-1] >> (ncand % 32 or 32) if ncand % 32 else 0) == 0
 
 
-@pytest.mark.parametrize("nrows", [1, 33, 4096, 100001])
+@pytest.mark.parametrize("nrows", [1, 33, 4096, 100001, (1 << 25) + 77])
 def test_rss_reshare_and_and(fss, nrows):
     nw = (nrows + 31) // 32
     rng = np.random.default_rng(nrows)
