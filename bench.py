@@ -716,6 +716,21 @@ def run_next(args, torch, fss, dev):
                              f"{nrec} records x {nwords * 4} B: 3 shares in, X1 and pi31(Y1 ^ T31) written and "
                              "read, 3 shares out; ChaCha12 for 5 mask tables and 3 permutations' keys (sorts not "
                              "counted)", cc_blocks)
+    # the same shuffle in two parts: the permutations made ahead of the data
+    # (rss_shuffle_prepare, seeds only), then the data-dependent launches
+    perms = torch.empty(3 * nrec, dtype=torch.int32, device=dev)
+    res["rss_shuffle_prepare"] = row("rss_shuffle_prepare",
+                                     timed(lambda: work.__setitem__("p", fss.rss_shuffle_prepare(nrec, seeds, perms,
+                                                                                                 stream))),
+                                     3 * nrec * 4, 0, f"3 permutations of {nrec} rows from the pair seeds (keys "
+                                     "counted; sorts and rankings not)", 3 * ((nrec + 7) // 8))
+    res["rss_shuffle_prepared"] = row("rss_shuffle_prepared",
+                                      timed(lambda: work.__setitem__("w", fss.rss_shuffle_prepared(
+                                          nrec, nwords, d3, seeds, perms, o3, stream))),
+                                      10 * tbytes, 0, f"{nrec} records x {nwords * 4} B with the permutations made: "
+                                      "3 shares in, X1 and pi31(Y1 ^ T31) written and read, 3 shares out; ChaCha12 "
+                                      "for 5 mask tables", 5 * slices)
+    del perms
     xb = [rnd((nrec + 31) // 32) for _ in range(3)]
     f3 = [torch.empty(nwords, dtype=torch.int32, device=dev) for _ in range(3)]
     res["rss_fetch_unique"] = row("rss_fetch_unique",

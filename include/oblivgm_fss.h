@@ -369,6 +369,33 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
 uint64_t rss_shuffle_workspace_bytes(uint64_t nrows, uint32_t nwords);
 int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],
                 uint32_t* const d_out[3], void* d_work, uint64_t work_bytes, void* stream);
+
+/*
+ * The shuffle in two parts (Alg. 5 draws its permutations from the pairwise
+ * seeds alone, before any data is involved): rss_shuffle_prepare makes the
+ * three permutations ahead of the data, rss_shuffle_prepared runs the
+ * data-dependent launches with them.  prepare + prepared = rss_shuffle, bit
+ * for bit.
+ * rss_shuffle_prepare: d_perms (device, 3 x nrows uint32, caller-owned) receives
+ *   [inverse of pi12 | inverse of pi31 | pi23] for `seeds`; the call's work is
+ *   complete when the stream reaches the call's end (it joins the library's
+ *   own streams as rss_shuffle does).  Workspace:
+ *   rss_shuffle_prepare_workspace_bytes(nrows).
+ * rss_shuffle_prepared: as rss_shuffle, with d_perms as made by
+ *   rss_shuffle_prepare for the same nrows and seeds (entries outside
+ *   [0, nrows) leave rows unwritten, never an access out of bounds).
+ *   Workspace: rss_shuffle_prepared_workspace_bytes(nrows, nwords).
+ *   Outputs must overlap neither the inputs, d_perms nor the workspace.
+ * Errors as rss_shuffle: more than 2^31 rows FSS_EUNSUPPORTED, NULL arguments
+ * FSS_EINVAL, a short workspace FSS_ENOMEM.
+ */
+uint64_t rss_shuffle_prepare_workspace_bytes(uint64_t nrows);
+int rss_shuffle_prepare(uint64_t nrows, const uint64_t seeds[3], uint32_t* d_perms, void* d_work,
+                        uint64_t work_bytes, void* stream);
+uint64_t rss_shuffle_prepared_workspace_bytes(uint64_t nrows, uint32_t nwords);
+int rss_shuffle_prepared(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],
+                         const uint32_t* d_perms, uint32_t* const d_out[3], void* d_work, uint64_t work_bytes,
+                         void* stream);
 int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],
                      uint32_t* const d_out[3], void* stream);
 uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords);

@@ -226,8 +226,13 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32
         const uint64_t sl = t >> 2;
         const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
         const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
+        // a quad shares its record, so these exits keep quads whole; they only
+        // matter for permutations that were not made by this library
         const uint32_t j = inv12[i];
-        const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)inv31[j] * nwords + 16 * b;
+        if (j >= nrows) continue;
+        const uint32_t l = inv31[j];
+        if (l >= nrows) continue;
+        const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)l * nwords + 16 * b;
         const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
         const uint4 z = load_quarter<VEC>(g2, src, c, len);
         const uint4 m = xor4(chacha_quad(k12, i, b, kT12, nwords), chacha_quad(k31, j, b, kT31, nwords));
@@ -259,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32
         const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
         const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
         const uint32_t p = perm[i];
+        if (p >= nrows) continue;       // as in k_shuffle_first
         const uint64_t src = (uint64_t)p * nwords + 16 * b, dst = (uint64_t)i * nwords + 16 * b;
         const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
         const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
@@ -462,15 +468,19 @@ size_t sort_temp_bytes(uint64_t nrows) {
     return b;
 }
 
+// Workspace of the permutations' scratch: for each of the three (they are
+// made side by side) rotated keys in and out, row numbers in and out, run
+// starts and the sort's temporary storage.
+uint64_t perm_scratch_bytes(uint64_t nrows) {
+    auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
+    return 3 * (2 * r(nrows * 8) + 2 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
+                r(sort_temp_bytes(nrows)));
+}
+
+// rss_shuffle: X1 and pi31(Y1 ^ T31), three permutations and their scratch.
 uint64_t shuffle_ws(uint64_t nrows, uint32_t nwords) {
     auto r = [](uint64_t b) { return (b + 255) & ~255ull; };
-    const uint64_t tw = nrows * nwords * 4;
-    // X1 and pi31(Y1 ^ T31); three permutations; for each permutation (they
-    // are made side by side) rotated keys in and out, row numbers in and out,
-    // run starts and the sort's temporary storage
-    const uint64_t scratch = 2 * r(nrows * 8) + 2 * r(nrows * 4) + r(((1ull << run_bits(nrows)) + 1) * 4) +
-                             r(sort_temp_bytes(nrows));
-    return 2 * r(tw) + 3 * r(nrows * 4) + 3 * scratch + 4096;
+    return 2 * r(nrows * nwords * 4) + 3 * r(nrows * 4) + perm_scratch_bytes(nrows) + 4096;
 }
 
 // perm = stable argsort of the pair seed's row keys (or its inverse): radix
@@ -585,69 +595,106 @@ hipStream_t perm_stream(int i) {
     return it->second[i];
 }
 
-// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.
+// The three permutations of a shuffle, made side by side: pi12 on the
+// caller's stream, pi31 and pi23 on the library's two streams (after
+// everything already on the caller's stream).  pi12 and pi31 are written as
+// their inverses (the first launch scatters through them), pi23 as is (the
+// final launch gathers through it).  join(i) makes the caller's stream wait
+// for pi31 (i = 0) or pi23 (i = 1); every join is enqueued whatever happened
+// before it, and finish() must follow, so that no work on the library's
+// streams outlives the caller's view of the call.
+struct PermSet {
+    hipStream_t s;
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, done[2] = {nullptr, nullptr};
+    bool forked = false, recorded[2] = {true, true};
+    int rc = 0;
+
+    void begin(uint64_t nrows, const uint64_t seeds[3], uint32_t* inv12, uint32_t* inv31, uint32_t* p23, Carve& ws) {
+        PermScratch pw[3];
+        for (PermScratch& w : pw) {
+            w.keys = ws.take<uint64_t>(nrows);
+            w.keys_sorted = ws.take<uint64_t>(nrows);
+            w.idx = ws.take<uint32_t>(nrows);
+            w.idx_sorted = ws.take<uint32_t>(nrows);
+            w.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
+            w.temp_bytes = sort_temp_bytes(nrows);
+            w.temp = ws.take<uint8_t>(w.temp_bytes);
+        }
+        if (!ws.ok) {
+            rc = fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
+            return;
+        }
+        side[0] = perm_stream(0), side[1] = perm_stream(1);
+        forked = side[0] && side[1] && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&done[0], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&done[1], hipEventDisableTiming) == hipSuccess &&
+                 hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side[0], fork, 0) == hipSuccess &&
+                 hipStreamWaitEvent(side[1], fork, 0) == hipSuccess;
+        const hipStream_t s31 = forked ? side[0] : s, s23 = forked ? side[1] : s;
+        // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1
+        const PermJob jobs[3] = {{pair_key(seeds[0]), kP12, true, inv12, pw[0], s},
+                                 {pair_key(seeds[2]), kP31, true, inv31, pw[1], s31},
+                                 {pair_key(seeds[1]), kP23, false, p23, pw[2], s23}};
+        int prc[3] = {0, 0, 0};
+        for (int step = 0; step < 4; step++)
+            for (int q = 0; q < 3; q++)
+                if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q]);
+        if (forked) {
+            recorded[0] = hipEventRecord(done[0], s31) == hipSuccess;
+            recorded[1] = hipEventRecord(done[1], s23) == hipSuccess;
+        }
+        rc = prc[0] ? prc[0] : prc[1] ? prc[1] : prc[2];
+    }
+
+    void join(int i) {
+        if (!forked) return;
+        if (recorded[i] && hipStreamWaitEvent(s, done[i], 0) == hipSuccess) return;
+        (void)hipStreamSynchronize(side[i]);
+        if (!rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
+    }
+
+    void finish() {
+        for (hipEvent_t e : {fork, done[0], done[1]})
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// The data-dependent part of Alg. 5 (all three servers simulated), given the
+// permutations: out[0..2] = R1, R2, R3.  x1 and v are workspace tables.
+int shuffle_rounds(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
+                   const uint32_t* inv12, const uint32_t* inv31, const uint32_t* p23, uint32_t* x1, uint32_t* v,
+                   uint32_t* const out[3], hipStream_t s, PermSet* pending) {
+    const ChachaKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
+    // pi12 then pi31: CS1's X1, CS3's pi31(Y1 ^ T31); R2 and R1 drawn
+    if (pending) pending->join(0);
+    int rc = pending ? pending->rc : 0;
+    if (!rc) rc = shuffle_first(nrows, nwords, k12, k31, inv12, inv31, d[0], d[1], d[2], x1, v, out[1], out[0], s);
+    // pi23: CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
+    // R3 = C1 ^ C2
+    if (pending) {
+        pending->join(1);
+        if (!rc) rc = pending->rc;
+    }
+    if (!rc) rc = shuffle_final(nrows, nwords, k12, k23, k31, p23, x1, v, out[2], s);
+    return rc;
+}
+
+// Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.  The
+// permutation pi23 is still being made while the first launch runs.
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
     const uint64_t tw = nrows * nwords;
-    const ChachaKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
     uint32_t* x1 = ws.take<uint32_t>(tw);      // CS1 -> CS2: X1
     uint32_t* v = ws.take<uint32_t>(tw);       // CS3: pi31(Y1 ^ T31)
-    uint32_t* p12 = ws.take<uint32_t>(nrows);
+    uint32_t* inv12 = ws.take<uint32_t>(nrows);
+    uint32_t* inv31 = ws.take<uint32_t>(nrows);
     uint32_t* p23 = ws.take<uint32_t>(nrows);
-    uint32_t* p31 = ws.take<uint32_t>(nrows);
-    PermScratch pw[3];
-    for (PermScratch& w : pw) {
-        w.keys = ws.take<uint64_t>(nrows);
-        w.keys_sorted = ws.take<uint64_t>(nrows);
-        w.idx = ws.take<uint32_t>(nrows);
-        w.idx_sorted = ws.take<uint32_t>(nrows);
-        w.starts = ws.take<uint32_t>((1ull << run_bits(nrows)) + 1);
-        w.temp_bytes = sort_temp_bytes(nrows);
-        w.temp = ws.take<uint8_t>(w.temp_bytes);
-    }
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
-    // pi12 on the caller's stream, pi31 and pi23 on the library's two streams
-    // (after everything already on the caller's stream); the caller's stream
-    // waits for each before the launch that applies it.
-    hipStream_t side[2] = {perm_stream(0), perm_stream(1)};
-    hipEvent_t fork = nullptr, done[2] = {nullptr, nullptr};
-    bool forked = side[0] && side[1] && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&done[0], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&done[1], hipEventDisableTiming) == hipSuccess &&
-                  hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side[0], fork, 0) == hipSuccess &&
-                  hipStreamWaitEvent(side[1], fork, 0) == hipSuccess;
-    const hipStream_t s31 = forked ? side[0] : s, s23 = forked ? side[1] : s;
-    // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1.
-    // pi12 and pi31 are applied as scatters (their inverses), pi23 as a gather
-    const PermJob jobs[3] = {{k12, kP12, true, p12, pw[0], s},
-                             {k31, kP31, true, p31, pw[1], s31},
-                             {k23, kP23, false, p23, pw[2], s23}};
-    int prc[3] = {0, 0, 0};
-    for (int step = 0; step < 4; step++)
-        for (int q = 0; q < 3; q++)
-            if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q]);
-    int rc = prc[0];
-    const int rc31 = prc[1], rc23 = prc[2];
-    const bool rec31 = !forked || hipEventRecord(done[0], s31) == hipSuccess;
-    const bool rec23 = !forked || hipEventRecord(done[1], s23) == hipSuccess;
-    if (!rc) rc = rc31 ? rc31 : rc23;
-    // every join is enqueued whatever happened, so that no work on the
-    // library's streams outlives the caller's view of this call
-    auto join = [&](int i, bool recorded) {
-        if (!forked) return true;
-        if (recorded && hipStreamWaitEvent(s, done[i], 0) == hipSuccess) return true;
-        (void)hipStreamSynchronize(side[i]);
-        return false;
-    };
-    // pi12 then pi31: CS1's X1, CS3's pi31(Y1 ^ T31); R2 and R1 drawn
-    if (!join(0, rec31) && !rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
-    if (!rc) rc = shuffle_first(nrows, nwords, k12, k31, p12, p31, d[0], d[1], d[2], x1, v, out[1], out[0], s);
-    // pi23: CS2's C1 = pi23(X1 ^ T23) ^ R2, CS3's C2 = pi23(pi31(Y1 ^ T31) ^ T23) ^ R1,
-    // R3 = C1 ^ C2
-    if (!join(1, rec23) && !rc) rc = fail(FSS_EDEVICE, "rss_shuffle: stream join failed");
-    if (!rc) rc = shuffle_final(nrows, nwords, k12, k23, k31, p23, x1, v, out[2], s);
-    for (hipEvent_t e : {fork, done[0], done[1]})
-        if (e) (void)hipEventDestroy(e);
+    PermSet ps{s};
+    ps.begin(nrows, seeds, inv12, inv31, p23, ws);
+    const int rc = shuffle_rounds(nrows, nwords, d, seeds, inv12, inv31, p23, x1, v, out, s, &ps);
+    ps.finish();
     return rc;
 }
 
@@ -673,6 +720,55 @@ int rss_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], 
                     (unsigned long long)shuffle_ws(nrows, nwords));
     Carve ws{(uint8_t*)d_work, work_bytes};
     return run_shuffle(nrows, nwords, d_in, seeds, d_out, ws, (hipStream_t)stream);
+}
+
+uint64_t rss_shuffle_prepare_workspace_bytes(uint64_t nrows) {
+    if (nrows == 0) return 0;
+    return perm_scratch_bytes(nrows) + 4096;
+}
+
+int rss_shuffle_prepare(uint64_t nrows, const uint64_t seeds[3], uint32_t* d_perms, void* d_work, uint64_t work_bytes,
+                        void* stream) {
+    last_error().clear();
+    if (nrows == 0) return FSS_OK;
+    if (nrows > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_shuffle_prepare: more than 2^31 rows");
+    if (!seeds || !d_perms) return fail(FSS_EINVAL, "rss_shuffle_prepare: NULL argument");
+    if (!d_work || work_bytes < rss_shuffle_prepare_workspace_bytes(nrows))
+        return fail(FSS_ENOMEM, "rss_shuffle_prepare: workspace needs %llu bytes",
+                    (unsigned long long)rss_shuffle_prepare_workspace_bytes(nrows));
+    Carve ws{(uint8_t*)d_work, work_bytes};
+    PermSet ps{(hipStream_t)stream};
+    ps.begin(nrows, seeds, d_perms, d_perms + nrows, d_perms + 2 * nrows, ws);
+    ps.join(0);
+    ps.join(1);
+    ps.finish();
+    return ps.rc;
+}
+
+uint64_t rss_shuffle_prepared_workspace_bytes(uint64_t nrows, uint32_t nwords) {
+    if (nrows == 0 || nwords == 0) return 0;
+    return 2 * ((nrows * nwords * 4 + 255) & ~255ull) + 4096;
+}
+
+int rss_shuffle_prepared(uint64_t nrows, uint32_t nwords, const uint32_t* const d_in[3], const uint64_t seeds[3],
+                         const uint32_t* d_perms, uint32_t* const d_out[3], void* d_work, uint64_t work_bytes,
+                         void* stream) {
+    last_error().clear();
+    if (nrows == 0 || nwords == 0) return FSS_OK;
+    if (nrows > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_shuffle_prepared: more than 2^31 rows");
+    if (!d_in || !d_out || !seeds || !d_perms) return fail(FSS_EINVAL, "rss_shuffle_prepared: NULL argument");
+    for (int i = 0; i < 3; i++)
+        if (!d_in[i] || !d_out[i]) return fail(FSS_EINVAL, "rss_shuffle_prepared: NULL share %d", i);
+    if (!d_work || work_bytes < rss_shuffle_prepared_workspace_bytes(nrows, nwords))
+        return fail(FSS_ENOMEM, "rss_shuffle_prepared: workspace needs %llu bytes",
+                    (unsigned long long)rss_shuffle_prepared_workspace_bytes(nrows, nwords));
+    Carve ws{(uint8_t*)d_work, work_bytes};
+    const uint64_t tw = nrows * nwords;
+    uint32_t* x1 = ws.take<uint32_t>(tw);
+    uint32_t* v = ws.take<uint32_t>(tw);
+    if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle_prepared: workspace too small");
+    return shuffle_rounds(nrows, nwords, d_in, seeds, d_perms, d_perms + nrows, d_perms + 2 * nrows, x1, v, d_out,
+                          (hipStream_t)stream, nullptr);
 }
 
 int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],

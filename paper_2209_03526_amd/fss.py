@@ -94,6 +94,10 @@ def _load():
         "rss_and": ([u64, P, P, P, u32, P, P], ctypes.c_int),
         "rss_shuffle_workspace_bytes": ([u64, u32], u64),
         "rss_shuffle": ([u64, u32, P, P, P, P, u64, P], ctypes.c_int),
+        "rss_shuffle_prepare_workspace_bytes": ([u64], u64),
+        "rss_shuffle_prepare": ([u64, P, P, P, u64, P], ctypes.c_int),
+        "rss_shuffle_prepared_workspace_bytes": ([u64, u32], u64),
+        "rss_shuffle_prepared": ([u64, u32, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_fetch_unique": ([u64, u32, P, P, P, P], ctypes.c_int),
         "rss_fetch_many_workspace_bytes": ([u64, u32], u64),
         "rss_fetch_many": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
@@ -113,7 +117,9 @@ EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
            "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
-           "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_fetch_unique", "rss_fetch_many_workspace_bytes",
+           "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
+           "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
+           "rss_fetch_many_workspace_bytes",
            "rss_fetch_many", "rss_compact_valid")
 
 
@@ -369,6 +375,24 @@ def rss_shuffle(nrows: int, nwords: int, d3, seeds, out3, stream=None):
     work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=d3[0].device)
     _check(LIB.rss_shuffle(nrows, nwords, _ptr3(d3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3), _ptr(work),
                            work.numel(), _stream(stream)))
+    return work
+
+
+def rss_shuffle_prepare(nrows: int, seeds, perms, stream=None):
+    """perms: device int32 tensor of 3 * nrows entries, filled with
+    [inverse of pi12 | inverse of pi31 | pi23]."""
+    nbytes = int(LIB.rss_shuffle_prepare_workspace_bytes(nrows))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=perms.device)
+    _check(LIB.rss_shuffle_prepare(nrows, (ctypes.c_uint64 * 3)(*seeds), _ptr(perms), _ptr(work), work.numel(),
+                                   _stream(stream)))
+    return work
+
+
+def rss_shuffle_prepared(nrows: int, nwords: int, d3, seeds, perms, out3, stream=None):
+    nbytes = int(LIB.rss_shuffle_prepared_workspace_bytes(nrows, nwords))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=d3[0].device)
+    _check(LIB.rss_shuffle_prepared(nrows, nwords, _ptr3(d3), (ctypes.c_uint64 * 3)(*seeds), _ptr(perms),
+                                    _ptr3(out3), _ptr(work), work.numel(), _stream(stream)))
     return work
 
 

@@ -143,6 +143,19 @@ def test_shuffle_and_fetch_argument_errors(fss):
     # Case II needs the bit word and at least one more word per record
     assert L.rss_fetch_many(8, 1, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EINVAL
     assert L.rss_compact_valid(8, 0, three, seeds, three, fake, fake, fake, 1 << 40, None) == fss.EINVAL
+    # the two-part shuffle: the same limits, NULL checks, and a short workspace
+    # for the data-dependent part (its size needs no device query)
+    assert L.rss_shuffle_prepare(0, seeds, None, None, 0, None) == fss.OK
+    assert L.rss_shuffle_prepare(1 << 31, seeds, fake, fake, 1 << 40, None) == fss.EUNSUPPORTED
+    assert L.rss_shuffle_prepare(8, seeds, None, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_shuffle_prepare(8, None, fake, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_shuffle_prepared(0, 4, three, seeds, fake, three, None, 0, None) == fss.OK
+    assert L.rss_shuffle_prepared(1 << 31, 4, three, seeds, fake, three, fake, 1 << 40, None) == fss.EUNSUPPORTED
+    assert L.rss_shuffle_prepared(8, 4, three, seeds, None, three, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_shuffle_prepared(8, 4, null_one, seeds, fake, three, fake, 1 << 40, None) == fss.EINVAL
+    assert L.rss_shuffle_prepared_workspace_bytes(8, 4) == 2 * 256 + 4096
+    assert L.rss_shuffle_prepared(8, 4, three, seeds, fake, three, fake, 2 * 256 + 4095, None) == fss.ENOMEM
+    assert L.rss_shuffle_prepared(8, 4, three, seeds, fake, three, None, 1 << 40, None) == fss.ENOMEM
     # Case I words per record
     assert L.rss_fetch_unique(8, 65536, three, three, three, None) == fss.EUNSUPPORTED
     assert L.rss_fetch_unique(8, 4, None, three, three, None) == fss.EINVAL

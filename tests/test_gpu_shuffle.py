@@ -50,6 +50,32 @@ def test_shuffle_parity(fss, n, w):
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], d[osh.composed_permutation(*seeds, n)])
 
 
+@pytest.mark.parametrize("n,w", [(1, 1), (1000, 8), (3001, 16), (65573, 4)])
+def test_shuffle_in_two_parts(fss, n, w):
+    """rss_shuffle_prepare's permutations are the oracle's (pi12 and pi31 as
+    their inverses, pi23 as is), and rss_shuffle_prepared with them gives the
+    oracle's shares, as the one-call shuffle does; preparing twice gives the
+    same permutations (a second prepare overwrites the first)."""
+    d, sh = _rss_table(3 * n + w, n, w)
+    seeds = (505, 606, 707)
+    perms = torch.full((3 * n,), -1, dtype=torch.int32, device=DEV)
+    fss.rss_shuffle_prepare(n, seeds, perms)
+    fss.rss_shuffle_prepare(n, seeds, perms)
+    torch.cuda.synchronize()
+    got_p = U(perms).reshape(3, n)
+    p12, p23, p31 = (osh.permutation(seeds[0], osh.P12, n), osh.permutation(seeds[1], osh.P23, n),
+                     osh.permutation(seeds[2], osh.P31, n))
+    np.testing.assert_array_equal(got_p[0], np.argsort(p12))
+    np.testing.assert_array_equal(got_p[1], np.argsort(p31))
+    np.testing.assert_array_equal(got_p[2], p23)
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_shuffle_prepared(n, w, [T(s.ravel()) for s in sh], seeds, perms, out)
+    torch.cuda.synchronize()
+    want = osh.sec_shuffle(sh, *seeds)
+    for i in range(3):
+        np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i])
+
+
 def test_shuffle_full_size_is_a_permutation(fss):
     """At 2^22 records of 64 bytes (the measured size), where the oracle's
     permutations are out of reach: every record comes out whole, each exactly
