@@ -228,7 +228,11 @@ int match_query(const match_plan* plan, int32_t party_mask, void* stream);
  * d_queue: caller-provided device memory of fss_queue_workspace_bytes(count)
  * bytes (256-aligned) holding the queue counter and the descriptors.  The
  * descriptors are staged through the library's ring of pinned host buffers
- * (see the conventions above).  Batch calls on one stream run in order;
+ * (see the conventions above); on a stream that is being captured into a
+ * graph they are written by small store kernels whose arguments carry them
+ * (2 KiB per launch), so that a replay reads the descriptors of the captured
+ * call: the batch calls can be captured and replayed (a replay redoes the
+ * same requests).  Batch calls on one stream run in order;
  * batches that share a d_queue must be on one stream.  A keygen batch runs as
  * one launch per key kind present (ranges first), each over its own tiles.
  *

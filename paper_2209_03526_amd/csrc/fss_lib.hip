@@ -1325,7 +1325,37 @@ struct Staging {
 };
 Staging g_staging;
 
+// Under stream capture the ring cannot serve: a captured copy would read its
+// pinned slot at every replay, after later calls have rewritten it, and the
+// slot wait is a host synchronisation.  There the descriptors travel as
+// kernel arguments instead, 2 KiB per launch, which a graph keeps by value.
+constexpr size_t kArgChunk = 2048;
+
+struct ArgChunk {
+    uint32_t w[kArgChunk / 4];
+};
+
+__global__ void k_put_words(uint32_t* __restrict__ dst, uint32_t nwords, ArgChunk c) {
+    for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = c.w[i];
+}
+
+int upload_as_arguments(const void* src, size_t bytes, void* d_dst, hipStream_t s) {
+    for (size_t off = 0; off < bytes; off += kArgChunk) {
+        const size_t n = bytes - off < kArgChunk ? bytes - off : kArgChunk;
+        ArgChunk c{};
+        memcpy(c.w, (const uint8_t*)src + off, n);
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, (uint32_t*)((uint8_t*)d_dst + off),
+                           (uint32_t)((n + 3) / 4), c);
+        const int rc = check_launch("k_put_words");
+        if (rc) return rc;
+    }
+    return FSS_OK;
+}
+
 int upload(const void* src, size_t bytes, void* d_dst, hipStream_t s) {
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &capture) == hipSuccess && capture != hipStreamCaptureStatusNone)
+        return upload_as_arguments(src, bytes, d_dst, s);
     std::lock_guard<std::mutex> lock(g_staging.mu);
     StagingSlot& sl = g_staging.slot[g_staging.next];
     g_staging.next = (g_staging.next + 1) % kStagingSlots;
