@@ -83,9 +83,11 @@ const char* fss_last_error(void);
 const char* fss_version(void);
 
 /* Release what the library holds on its own: the pinned staging buffers of
- * the batch calls (waiting for their last copies first).  Call it when no call
- * is in flight on any thread; the library stays usable (buffers are re-created
- * on demand).  FSS_EDEVICE if the runtime reports an error while releasing. */
+ * the batch calls (waiting for their last copies first) and the two streams
+ * per device on which the shuffle calls make their permutations (drained
+ * first).  Call it when no call is in flight on any thread; the library stays
+ * usable (buffers and streams are re-created on demand).  FSS_EDEVICE if the
+ * runtime reports an error while releasing. */
 int fss_shutdown(void);
 
 /*

@@ -975,7 +975,9 @@ const char* fss_version(void) { return "oblivgm-fss 0.1 gfx950 lds-ttable"; }
 int fss_shutdown(void) {
     ogm::last_error().clear();
     const int rc = staging_release();
+    const int rc_streams = ogm::shuffle_release();
     if (rc) return fail(rc, "fss_shutdown: a staging buffer could not be released");
+    if (rc_streams) return fail(rc_streams, "fss_shutdown: a shuffle stream could not be released");
     return FSS_OK;
 }
 

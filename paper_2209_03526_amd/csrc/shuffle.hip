@@ -579,18 +579,19 @@ int shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
 // of their kernels are small or latency-bound.  Ordered against the caller's
 // stream with events only; nullptr if they cannot be created (then all runs
 // on the caller's stream).
+std::mutex g_stream_mu;
+std::map<int, std::array<hipStream_t, 2>> g_streams;
+
 hipStream_t perm_stream(int i) {
-    static std::mutex mu;
-    static std::map<int, std::array<hipStream_t, 2>> streams;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = streams.find(dev);
-    if (it == streams.end()) {
+    std::lock_guard<std::mutex> lock(g_stream_mu);
+    auto it = g_streams.find(dev);
+    if (it == g_streams.end()) {
         std::array<hipStream_t, 2> st{nullptr, nullptr};
         for (auto& x : st)
             if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) x = nullptr;
-        it = streams.emplace(dev, st).first;
+        it = g_streams.emplace(dev, st).first;
     }
     return it->second[i];
 }
@@ -699,6 +700,24 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
 }
 
 }  // namespace
+
+namespace ogm {
+
+// The shuffle's own streams, for fss_shutdown: each is drained, then
+// destroyed; the next shuffle creates them again.
+int shuffle_release() {
+    std::lock_guard<std::mutex> lock(g_stream_mu);
+    int rc = FSS_OK;
+    for (auto& kv : g_streams)
+        for (hipStream_t& st : kv.second) {
+            if (st && (hipStreamSynchronize(st) != hipSuccess || hipStreamDestroy(st) != hipSuccess)) rc = FSS_EDEVICE;
+            st = nullptr;
+        }
+    g_streams.clear();
+    return rc;
+}
+
+}  // namespace ogm
 
 extern "C" {
 

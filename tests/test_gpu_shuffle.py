@@ -76,6 +76,25 @@ def test_shuffle_in_two_parts(fss, n, w):
         np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i])
 
 
+def test_shutdown_between_shuffles(fss):
+    """fss_shutdown drains and destroys the shuffle's own streams; the next
+    shuffle makes them again and gives the same shares."""
+    n, w = 5000, 4
+    d, sh = _rss_table(17, n, w)
+    seeds = (31, 32, 33)
+    outs = []
+    for _ in range(2):
+        out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+        fss.rss_shuffle(n, w, [T(s.ravel()) for s in sh], seeds, out)
+        assert fss.LIB.fss_shutdown() == fss.OK
+        torch.cuda.synchronize()
+        outs.append([U(o) for o in out])
+    want = osh.sec_shuffle(sh, *seeds)
+    for got in outs:
+        for i in range(3):
+            np.testing.assert_array_equal(got[i].reshape(n, w), want[i])
+
+
 def test_shuffle_full_size_is_a_permutation(fss):
     """At 2^22 records of 64 bytes (the measured size), where the oracle's
     permutations are out of reach: every record comes out whole, each exactly
