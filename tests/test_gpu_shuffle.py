@@ -76,6 +76,20 @@ def test_shuffle_in_two_parts(fss, n, w):
         np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i])
 
 
+def test_prepared_skips_out_of_range_entries(fss):
+    """Permutation entries outside [0, nrows) leave their rows unwritten and
+    are never used as indices: with every entry out of range the outputs keep
+    what they held."""
+    n, w = 3000, 16
+    d, sh = _rss_table(23, n, w)
+    perms = torch.full((3 * n,), -1, dtype=torch.int32, device=DEV)     # 0xffffffff
+    out = [torch.full((n * w,), 7, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_shuffle_prepared(n, w, [T(s.ravel()) for s in sh], (1, 2, 3), perms, out)
+    torch.cuda.synchronize()
+    for o in out:
+        assert bool((o == 7).all())
+
+
 def test_shutdown_between_shuffles(fss):
     """fss_shutdown drains and destroys the shuffle's own streams; the next
     shuffle makes them again and gives the same shares."""
