@@ -135,7 +135,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(a multi-GPU run would shard the rows of each table)"}))
         sys.exit(2)
     import torch

@@ -52,7 +52,7 @@ typedef enum {
     FSS_EINVAL = -1,        /* bad argument (null pointer, size, bound, party ...) */
     FSS_ENOMEM = -2,        /* caller-provided workspace too small */
     FSS_EDEVICE = -3,       /* HIP runtime error while enqueuing */
-    FSS_EUNSUPPORTED = -4   /* valid request this build does not serve */
+    FSS_EUNSUPPORTED = -4   /* valid request the library does not serve */
 } fss_status;
 
 typedef enum {
