@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: tests/, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` use this module.  The product library never
 imports it, and it never imports the product.
 
-The compiled part (``fss_oracle.c``) holds AES-128, the PRG, the DPF/DCF
+The compiled part (``fss_oracle.c``) holds AES-128, the tree hash, the DPF/DCF
 Gen/Eval pairs, masked-input key generation and the dealer's counter-mode
 randomness.  This file adds the pieces that are plain bitwise algebra:
 opening masked values, Beaver AND on packed share words, and bit packing.
@@ -32,62 +32,67 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fss_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-DPF_KEY = np.dtype([("root", "u1", 16), ("scw", "u1", (32, 16)), ("tl", "<u4"), ("tr", "<u4"),
-                    ("cwout", "u1", 16)])
-DCF_KEY = np.dtype([("root", "u1", 16), ("scw", "u1", (32, 16)), ("tl", "<u4"), ("tr", "<u4"),
-                    ("vcw", "<u4"), ("cwleaf", "u1", 16)])
+DPF_KEY = np.dtype([("root", "u1", 16), ("cw", "u1", (32, 16)), ("cwleaf", "u1", 16)])
+DCF_KEY = np.dtype([("root", "u1", 16), ("cw", "u1", (32, 16)), ("vcw", "<u4"), ("cwleaf", "u1", 16)])
 RANGE_KEY = np.dtype([("upper", DCF_KEY), ("lower", DCF_KEY)])
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, OpenMP over rows only)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+def build(force: bool = False, path: str = _LIB_PATH, plant: int = 0) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP over rows only).  ``plant``
+    > 0 builds a copy with one deliberate mistake (for the tests that show the
+    pins catch it) at ``path``."""
+    if force or plant or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+                               "-Wall", "-Wextra", f"-DORACLE_PLANT={int(plant)}", "-o", tmp, _SRC])
+        os.replace(tmp, path)
+    return path
 
 
 _lib = None
 
 
+def load(path: str):
+    """A ctypes handle on a built oracle library with every signature set."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    u32, u64, i32, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "oracle_sbox": ([ctypes.c_uint8], ctypes.c_uint8),
+        "oracle_aes128_expand": ([P, P], None),
+        "oracle_aes128_encrypt": ([P, P, P], None),
+        "oracle_hash": ([P, P], None),
+        "oracle_dcf_path": ([P, u32, u32, P], None),
+        "oracle_rng_block": ([u64, u32, u32, u32, u32, u32, P], None),
+        "oracle_rng_blocks": ([u64, u32, u32, u32, u32, u32, sz, P], None),
+        "oracle_dpf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
+        "oracle_dcf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
+        "oracle_dpf_eval_points": ([i32, P, u32, P, sz, P], None),
+        "oracle_dcf_eval_points": ([i32, P, u32, P, sz, P], None),
+        "oracle_keygen_eq": ([u32, u64, u32, u32, u32, P, P, sz, P, P], None),
+        "oracle_keygen_range": ([u32, u64, u32, u32, u32, u32, P, P, sz, P, P], None),
+        "oracle_eval_eq": ([u32, i32, P, P, sz, P], None),
+        "oracle_eval_range": ([u32, i32, P, P, sz, P], None),
+        "oracle_triples": ([u64, u32, u32, P, sz, P, P, P, P, P, P], None),
+        "oracle_masks": ([u64, u32, u32, u32, sz, P], None),
+        "oracle_sizeof_dpf_key": ([], sz),
+        "oracle_sizeof_dcf_key": ([], sz),
+        "oracle_sizeof_range_key": ([], sz),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    assert L.oracle_sizeof_dpf_key() == DPF_KEY.itemsize
+    assert L.oracle_sizeof_dcf_key() == DCF_KEY.itemsize
+    assert L.oracle_sizeof_range_key() == RANGE_KEY.itemsize
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB_PATH)
-        P = ctypes.c_void_p
-        u32, u64, i32, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
-        sig = {
-            "oracle_sbox": ([ctypes.c_uint8], ctypes.c_uint8),
-            "oracle_aes128_expand": ([P, P], None),
-            "oracle_aes128_encrypt": ([P, P, P], None),
-            "oracle_prg": ([i32, P, P], None),
-            "oracle_rng_block": ([u64, u32, u32, u32, u32, u32, P], None),
-            "oracle_rng_blocks": ([u64, u32, u32, u32, u32, u32, sz, P], None),
-            "oracle_dpf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
-            "oracle_dcf_gen_seeded": ([u32, u32, u64, u32, P, P], None),
-            "oracle_dpf_eval_points": ([i32, P, u32, P, sz, P], None),
-            "oracle_dcf_eval_points": ([i32, P, u32, P, sz, P], None),
-            "oracle_keygen_eq": ([u32, u64, u32, u32, u32, P, P, sz, P, P], None),
-            "oracle_keygen_range": ([u32, u64, u32, u32, u32, u32, P, P, sz, P, P], None),
-            "oracle_eval_eq": ([u32, i32, P, P, sz, P], None),
-            "oracle_eval_range": ([u32, i32, P, P, sz, P], None),
-            "oracle_triples": ([u64, u32, u32, P, sz, P, P, P, P, P, P], None),
-            "oracle_masks": ([u64, u32, u32, u32, sz, P], None),
-            "oracle_sizeof_dpf_key": ([], sz),
-            "oracle_sizeof_dcf_key": ([], sz),
-            "oracle_sizeof_range_key": ([], sz),
-        }
-        for name, (args, res) in sig.items():
-            f = getattr(L, name)
-            f.argtypes = args
-            f.restype = res
-        assert L.oracle_sizeof_dpf_key() == DPF_KEY.itemsize
-        assert L.oracle_sizeof_dcf_key() == DCF_KEY.itemsize
-        assert L.oracle_sizeof_range_key() == RANGE_KEY.itemsize
-        _lib = L
+        _lib = load(build())
     return _lib
 
 
@@ -100,7 +105,7 @@ def _buf(b: bytes) -> np.ndarray:
     return np.frombuffer(bytes(b), dtype=np.uint8).copy()
 
 
-# --------------------------------------------------------------------------- AES / PRG / RNG
+# --------------------------------------------------------------------------- AES / tree hash / RNG
 
 def sbox(x: int) -> int:
     return int(lib().oracle_sbox(x))
@@ -121,10 +126,11 @@ def aes128_encrypt(key: bytes, block: bytes) -> bytes:
     return out.tobytes()
 
 
-def prg(sigma: int, seed: bytes) -> bytes:
-    s = _buf(seed)
+def tree_hash(x: bytes) -> bytes:
+    """H(x) = AES_K(sigma(x)) xor sigma(x), the hash of the half-tree nodes."""
+    s = _buf(x)
     out = np.zeros(16, np.uint8)
-    lib().oracle_prg(sigma, _p(s), _p(out))
+    lib().oracle_hash(_p(s), _p(out))
     return out.tobytes()
 
 
@@ -157,6 +163,13 @@ def dcf_gen(n: int, alpha: int, seed: int, elem: int = 0):
     k1 = np.zeros(1, DCF_KEY)
     lib().oracle_dcf_gen_seeded(n, alpha, seed, elem, _p(k0), _p(k1))
     return k0, k1
+
+
+def dcf_path(key: np.ndarray, n: int, x: int) -> np.ndarray:
+    """Seeds of the nodes the walk of x passes (root first), (n - 6, 16) uint8."""
+    out = np.zeros((n - 6, 16), np.uint8)
+    lib().oracle_dcf_path(_p(key), n, x, _p(out))
+    return out
 
 
 def dpf_eval_points(party: int, key: np.ndarray, n: int, xs) -> np.ndarray:

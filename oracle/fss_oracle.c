@@ -18,13 +18,14 @@
  *   - Security parameter lambda = 128 (seeds and correction words are 128-bit
  *     AES blocks): Sec. VII-A, protocol instantiation.
  *   - AES-128 itself: FIPS-197 (Sec. 5.1 cipher, Sec. 5.2 key expansion).
- * The paper fixes neither the PRG nor the tree construction's bit conventions;
- * the readings taken here form this FSS specification
- * (PRG = fixed-key AES in Matyas-Meyer-Oseas form with the branch tweak XORed
- * into byte 0; tree walk MSB first; t = bit 0, v = bit 1, next seed = block with
- * bits 0 and 1 cleared; DPF and DCF both stop nu = n - 7 levels above the
- * leaves and end in a 128-bit leaf G_C(s) whose correction word answers the
- * last 7 input bits).
+ * The paper fixes neither the PRG nor the tree construction; the readings
+ * taken here form this FSS specification: the tree hash is fixed-key AES made
+ * circular correlation-robust, H(x) = AES_K(sigma(x)) xor sigma(x); the trees
+ * are half-trees (one hash per node, right child = left child xor parent, one
+ * correction word per level); the walk is MSB first; t = bit 0 of a seed,
+ * seeds keep bit 1 clear, v = bit 1 of H(s); DPF and DCF both stop nu = n - 7
+ * levels above the leaves and end in a 128-bit leaf H(s xor 2) whose
+ * correction word answers the last 7 input bits.
  * Share-level values (which random seed, which key bytes) therefore are pinned
  * only through AES and through the reconstruction identities; see the tests.
  *
@@ -144,10 +145,17 @@ static void block_xor_if(uint8_t out[16], int t, const uint8_t cw[16])
 }
 
 /* ------------------------------------------------------------------------ */
-/* PRG: G_sigma(s) = AES_K(u) xor u with u = s xor sigma (sigma in byte 0),  */
-/* fixed key K = 00 01 02 ... 0f.  sigma: 0 = left child, 1 = right child,   */
-/* 2 = leaf/convert.                                                        */
+/* Tree hash.  H(x) = AES_K(sigma(x)) xor sigma(x), K = 00 01 02 ... 0f,     */
+/* with the linear orthomorphism sigma(a || b) = (a xor b) || a on the two   */
+/* 8-byte halves (a = bytes 0..7, b = bytes 8..15): fixed-key AES turned     */
+/* into a circular correlation-robust hash (Guo, Katz, Wang, Yu, IEEE S&P    */
+/* 2020).  The half-tree expansion below needs exactly that property: the    */
+/* two parties' seeds on the special path differ by one secret offset.       */
 /* ------------------------------------------------------------------------ */
+
+#ifndef ORACLE_PLANT          /* tests build copies with a planted mistake (k > 0) */
+#define ORACLE_PLANT 0
+#endif
 
 static uint8_t g_prg_rk[176];
 __attribute__((constructor(200))) static void oracle_build_prg_key(void)
@@ -158,24 +166,31 @@ __attribute__((constructor(200))) static void oracle_build_prg_key(void)
     oracle_aes128_expand(k, g_prg_rk);
 }
 
-void oracle_prg(int sigma, const uint8_t s[16], uint8_t out[16])
+static void sigma_map(const uint8_t x[16], uint8_t out[16])
+{
+    for (int k = 0; k < 8; k++) {
+        out[k] = (uint8_t)(x[k] ^ x[8 + k]);
+        out[8 + k] = x[k];
+        if (ORACLE_PLANT == 5) { out[k] = x[k]; out[8 + k] = x[8 + k]; }   /* sigma = identity */
+    }
+}
+
+void oracle_hash(const uint8_t x[16], uint8_t out[16])
 {
     uint8_t u[16], e[16];
-    memcpy(u, s, 16);
-    u[0] ^= (uint8_t)sigma;
+    sigma_map(x, u);
     oracle_aes128_encrypt(g_prg_rk, u, e);
     block_xor(out, e, u);
 }
 
-/* Expansion of one seed into one child: (next seed with bits 0,1 cleared, t, v). */
-static void expand(int sigma, const uint8_t s[16], uint8_t s_next[16], int *t, int *v)
+/* Leaf value of a node: H(s xor 2).  Tree seeds have bit 1 clear, so this   */
+/* input is never the input of an expansion.                                */
+static void leaf_hash(const uint8_t s[16], uint8_t out[16])
 {
-    uint8_t w[16];
-    oracle_prg(sigma, s, w);
-    *t = block_bit(w, 0);
-    *v = block_bit(w, 1);
-    memcpy(s_next, w, 16);
-    s_next[0] &= (uint8_t)~3u;
+    uint8_t u[16];
+    memcpy(u, s, 16);
+    u[0] ^= 2;
+    oracle_hash(u, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -216,21 +231,28 @@ void oracle_rng_block(uint64_t seed, uint32_t domain, uint32_t j, uint32_t query
 }
 
 /* ------------------------------------------------------------------------ */
-/* Keys.                                                                    */
+/* Keys.  A half-tree (Guo, Yang, Wang, Zhang, Xie, Liu, Zhao, Eurocrypt     */
+/* 2023) with early termination: nu = n - 7 levels, then a 128-bit leaf that */
+/* answers the low 7 input bits.  One correction word per level serves both  */
+/* children, because on the special path the two parties' seeds always       */
+/* differ by the dealer's secret offset Delta (bit 0 set, bit 1 clear).      */
+/*                                                                          */
+/* Node s (bit 1 clear; t(s) = bit 0 of s):                                 */
+/*   h = H(s);  v = bit 1 of h;  h' = h with bit 1 cleared;                 */
+/*   left child  = h' xor t(s)*CW_i;   right child = left child xor s.      */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    uint8_t  root[16];        /* s_b at the root */
-    uint8_t  scw[32][16];     /* seed correction word of level i (i = 0..nu-1) */
-    uint32_t tl, tr;          /* bit i: left / right t-correction bit of level i */
-    uint8_t  cwout[16];       /* leaf correction word (128 outputs) */
+    uint8_t  root[16];        /* this party's root seed */
+    uint8_t  cw[32][16];      /* correction word of level i (i = 0..nu-1) */
+    uint8_t  cwleaf[16];      /* leaf correction word (128 outputs) */
 } oracle_dpf_key;
 
 typedef struct {
     uint8_t  root[16];
-    uint8_t  scw[32][16];     /* level i = 0..nu-1, nu = n - 7 */
-    uint32_t tl, tr, vcw;     /* bit i: t-left, t-right and value correction of level i;
-                                 vcw bit 31: wrap share c_b (upper-bound half of a range key) */
+    uint8_t  cw[32][16];      /* level i = 0..nu-1, nu = n - 7 */
+    uint32_t vcw;             /* bit i: value correction of level i;
+                                 bit 31: wrap share c_b (upper-bound half of a range key) */
     uint8_t  cwleaf[16];      /* leaf correction word: 128 outputs for the last 7 input bits */
 } oracle_dcf_key;
 
@@ -244,203 +266,180 @@ static uint32_t dom_mask(uint32_t n) { return n >= 32 ? 0xffffffffu : ((1u << n)
 /* Bit i (1-based, MSB first) of an n-bit value, as in the tree walk: x_i. */
 static int msb_bit(uint32_t x, uint32_t n, uint32_t i) { return (int)((x >> (n - i)) & 1u); }
 
-/* DPF Gen for f^=_{alpha,1} over n-bit inputs (BGI tree with early termination
- * nu = n - 7 levels, leaf block carrying 128 output bits).  Roots s0, s1 have
- * bits 0,1 cleared; t0 = 0, t1 = 1. */
-void oracle_dpf_gen(uint32_t n, uint32_t alpha, const uint8_t root0[16], const uint8_t root1[16],
+/* Expansion of node s: h' (bit 1 cleared) and v. */
+static void expand_node(const uint8_t s[16], uint8_t h[16], int *v)
+{
+    oracle_hash(s, h);
+    *v = block_bit(h, ORACLE_PLANT == 3 ? 0 : 1);
+    h[0] &= (uint8_t)~2u;
+}
+
+/* The child on side x_i of node s, under correction word cw. */
+static void child(const uint8_t s[16], const uint8_t h[16], const uint8_t cw[16], int xi, uint8_t out[16])
+{
+    int t = block_bit(s, ORACLE_PLANT == 7 ? 1 : 0);
+    uint8_t c[16];
+    memcpy(c, h, 16);
+    block_xor_if(c, t, cw);
+    if (ORACLE_PLANT != 2) block_xor_if(c, xi, s);
+    memcpy(out, c, 16);
+}
+
+/* One level of Gen on the special path of alpha (a = alpha_i): the correction
+ * word makes the children off the path equal for both parties and keeps the
+ * difference Delta on the path; s[0], s[1] move to the path's child. */
+static void gen_level(uint8_t s[2][16], const uint8_t delta[16], int a, uint8_t cw[16], int *vdiff)
+{
+    uint8_t h[2][16];
+    int v[2];
+    expand_node(s[0], h[0], &v[0]);
+    expand_node(s[1], h[1], &v[1]);
+    block_xor(cw, h[0], h[1]);
+    if (!a && ORACLE_PLANT != 1) block_xor(cw, cw, delta);
+    for (int b = 0; b < 2; b++) child(s[b], h[b], cw, a, s[b]);
+    *vdiff = v[0] ^ v[1];
+}
+
+/* Roots: s_0 with bit 1 cleared, Delta with bit 0 set and bit 1 cleared,
+ * s_1 = s_0 xor Delta. */
+static void roots(const uint8_t seed0[16], const uint8_t dseed[16], uint8_t s[2][16], uint8_t delta[16])
+{
+    memcpy(s[0], seed0, 16);
+    s[0][0] &= (uint8_t)~2u;
+    memcpy(delta, dseed, 16);
+    delta[0] = (uint8_t)((delta[0] & ~2u) | 1u);
+    block_xor(s[1], s[0], delta);
+}
+
+/* DPF Gen for f^=_{alpha,1} over n-bit inputs. */
+void oracle_dpf_gen(uint32_t n, uint32_t alpha, const uint8_t seed0[16], const uint8_t dseed[16],
                     oracle_dpf_key *k0, oracle_dpf_key *k1)
 {
     uint32_t nu = n - 7;
-    uint8_t s[2][16];
-    int t[2] = {0, 1};
+    uint8_t s[2][16], delta[16];
     memset(k0, 0, sizeof *k0);
     memset(k1, 0, sizeof *k1);
-    memcpy(s[0], root0, 16);
-    memcpy(s[1], root1, 16);
-    memcpy(k0->root, root0, 16);
-    memcpy(k1->root, root1, 16);
-
+    roots(seed0, dseed, s, delta);
+    memcpy(k0->root, s[0], 16);
+    memcpy(k1->root, s[1], 16);
     for (uint32_t i = 1; i <= nu; i++) {
-        uint8_t sl[2][16], sr[2][16];
-        int tlb[2], trb[2], vdummy;
-        for (int b = 0; b < 2; b++) {
-            expand(0, s[b], sl[b], &tlb[b], &vdummy);
-            expand(1, s[b], sr[b], &trb[b], &vdummy);
-        }
-        int a = msb_bit(alpha, n, i);
-        /* keep the child on alpha's path, correct the other ("lose") one */
-        uint8_t (*keep)[16] = a ? sr : sl;
-        uint8_t (*lose)[16] = a ? sl : sr;
-        int *tkeep = a ? trb : tlb;
-        uint8_t scw[16];
-        block_xor(scw, lose[0], lose[1]);
-        int tlcw = tlb[0] ^ tlb[1] ^ a ^ 1;
-        int trcw = trb[0] ^ trb[1] ^ a;
-        int tkeepcw = a ? trcw : tlcw;
-
-        for (int b = 0; b < 2; b++) {
-            uint8_t ns[16];
-            memcpy(ns, keep[b], 16);
-            block_xor_if(ns, t[b], scw);
-            int nt = tkeep[b] ^ (t[b] & tkeepcw);
-            memcpy(s[b], ns, 16);
-            t[b] = nt;
-        }
-        memcpy(k0->scw[i - 1], scw, 16);
-        memcpy(k1->scw[i - 1], scw, 16);
-        k0->tl |= (uint32_t)tlcw << (i - 1);
-        k0->tr |= (uint32_t)trcw << (i - 1);
+        uint8_t cw[16];
+        int vdiff;
+        gen_level(s, delta, msb_bit(alpha, n, i), cw, &vdiff);
+        memcpy(k0->cw[i - 1], cw, 16);
+        memcpy(k1->cw[i - 1], cw, 16);
     }
-    k1->tl = k0->tl;
-    k1->tr = k0->tr;
-
-    /* Leaf: CW_out = G_C(s_0) xor G_C(s_1) xor e_{alpha mod 128}. */
+    /* Leaf: CW_leaf = L(s_0) xor L(s_1) xor e_{alpha mod 128}. */
     uint8_t g0[16], g1[16], cw[16];
-    oracle_prg(2, s[0], g0);
-    oracle_prg(2, s[1], g1);
+    leaf_hash(s[0], g0);
+    leaf_hash(s[1], g1);
     block_xor(cw, g0, g1);
     uint32_t low = alpha & 127u;
     cw[low >> 3] ^= (uint8_t)(1u << (low & 7));
-    memcpy(k0->cwout, cw, 16);
-    memcpy(k1->cwout, cw, 16);
+    memcpy(k0->cwleaf, cw, 16);
+    memcpy(k1->cwleaf, cw, 16);
 }
 
+/* Eval needs no party index: t is bit 0 of the seed. */
 int oracle_dpf_eval(int party, const oracle_dpf_key *k, uint32_t n, uint32_t x)
 {
+    (void)party;
     uint32_t nu = n - 7;
     uint8_t s[16];
-    int t = party;
     x &= dom_mask(n);
     memcpy(s, k->root, 16);
     for (uint32_t i = 1; i <= nu; i++) {
-        int xi = msb_bit(x, n, i);
-        uint8_t ns[16];
-        int nt, v;
-        expand(xi, s, ns, &nt, &v);
-        block_xor_if(ns, t, k->scw[i - 1]);
-        int tcw = (int)(((xi ? k->tr : k->tl) >> (i - 1)) & 1u);
-        nt ^= t & tcw;
-        memcpy(s, ns, 16);
-        t = nt;
+        uint8_t h[16];
+        int v;
+        expand_node(s, h, &v);
+        child(s, h, k->cw[i - 1], msb_bit(x, n, i), s);
     }
     uint8_t g[16];
-    oracle_prg(2, s, g);
-    block_xor_if(g, t, k->cwout);
+    leaf_hash(s, g);
+    block_xor_if(g, block_bit(s, 0), k->cwleaf);
     return block_bit(g, (int)(x & 127u));
 }
 
-/* DCF Gen for g^<_{alpha,1} over n-bit inputs with output in Z_2.  The tree
- * is walked for the nu = n - 7 high input bits; V_alpha accumulates the value
- * corrections along alpha's path.  The last 7 input bits are answered, as in
- * the DPF, by a 128-bit leaf G_C(s) corrected on alpha's path: once the
- * evaluation path has left alpha's path its two seeds and t bits are equal,
- * the leaves cancel and the value bits already hold [x < alpha]; on alpha's
- * path the leaf must reconstruct to [x_lo < alpha_lo] xor V_alpha. */
-void oracle_dcf_gen(uint32_t n, uint32_t alpha, const uint8_t root0[16], const uint8_t root1[16],
+/* DCF Gen for g^<_{alpha,1} over n-bit inputs with output in Z_2.  Both
+ * children of a node carry the same value bit v (bit 1 of H(s)), so the value
+ * correction of level i is the same whichever way the evaluation goes:
+ *   VCW_i = (v_0 xor v_1) xor V_alpha xor alpha_i,
+ * with V_alpha the XOR of the corrected on-path contributions so far.  A walk
+ * that leaves the path at level i (x_i != alpha_i) then reconstructs alpha_i
+ * = [x < alpha]; afterwards the parties' seeds are equal and everything
+ * cancels.  A walk that stays on the path reaches the leaf with V = V_alpha,
+ * and the leaf is corrected to [x_lo < alpha_lo] xor V_alpha. */
+void oracle_dcf_gen(uint32_t n, uint32_t alpha, const uint8_t seed0[16], const uint8_t dseed[16],
                     oracle_dcf_key *k0, oracle_dcf_key *k1)
 {
     uint32_t nu = n - 7;
-    uint8_t s[2][16];
-    int t[2] = {0, 1};
+    uint8_t s[2][16], delta[16];
     int valpha = 0;
     memset(k0, 0, sizeof *k0);
     memset(k1, 0, sizeof *k1);
-    memcpy(s[0], root0, 16);
-    memcpy(s[1], root1, 16);
-    memcpy(k0->root, root0, 16);
-    memcpy(k1->root, root1, 16);
-
+    roots(seed0, dseed, s, delta);
+    memcpy(k0->root, s[0], 16);
+    memcpy(k1->root, s[1], 16);
     for (uint32_t i = 1; i <= nu; i++) {
-        uint8_t sl[2][16], sr[2][16];
-        int tlb[2], trb[2], vlb[2], vrb[2];
-        for (int b = 0; b < 2; b++) {
-            expand(0, s[b], sl[b], &tlb[b], &vlb[b]);
-            expand(1, s[b], sr[b], &trb[b], &vrb[b]);
-        }
         int a = msb_bit(alpha, n, i);
-        uint8_t (*keep)[16] = a ? sr : sl;
-        uint8_t (*lose)[16] = a ? sl : sr;
-        int *tkeep = a ? trb : tlb;
-        int *vkeep = a ? vrb : vlb;
-        int *vlose = a ? vlb : vrb;
-
-        uint8_t scw[16];
-        block_xor(scw, lose[0], lose[1]);
-        /* Leaving alpha's path to the left at a level where alpha_i = 1 means
-         * x < alpha: that branch must reconstruct to beta = 1. */
-        int vcw = vlose[0] ^ vlose[1] ^ valpha ^ a;
-        valpha = valpha ^ vkeep[0] ^ vkeep[1] ^ vcw;
-        int tlcw = tlb[0] ^ tlb[1] ^ a ^ 1;
-        int trcw = trb[0] ^ trb[1] ^ a;
-        int tkeepcw = a ? trcw : tlcw;
-
-        for (int b = 0; b < 2; b++) {
-            uint8_t ns[16];
-            memcpy(ns, keep[b], 16);
-            block_xor_if(ns, t[b], scw);
-            int nt = tkeep[b] ^ (t[b] & tkeepcw);
-            memcpy(s[b], ns, 16);
-            t[b] = nt;
-        }
-        memcpy(k0->scw[i - 1], scw, 16);
-        memcpy(k1->scw[i - 1], scw, 16);
-        k0->tl |= (uint32_t)tlcw << (i - 1);
-        k0->tr |= (uint32_t)trcw << (i - 1);
+        uint8_t cw[16];
+        int vdiff;
+        gen_level(s, delta, a, cw, &vdiff);
+        int vcw = vdiff ^ (ORACLE_PLANT == 6 ? 0 : valpha) ^ a;
+        valpha = valpha ^ vdiff ^ vcw;
+        memcpy(k0->cw[i - 1], cw, 16);
+        memcpy(k1->cw[i - 1], cw, 16);
         k0->vcw |= (uint32_t)vcw << (i - 1);
     }
-    /* Leaf: bit j of CW = bit j of G_C(s_0) xor G_C(s_1), xor [j < alpha mod 128],
+    k1->vcw = k0->vcw;
+    /* Leaf: bit j of CW = bit j of L(s_0) xor L(s_1), xor [j < alpha mod 128],
      * xor V_alpha. */
     uint8_t g0[16], g1[16], cw[16];
-    oracle_prg(2, s[0], g0);
-    oracle_prg(2, s[1], g1);
+    leaf_hash(s[0], g0);
+    leaf_hash(s[1], g1);
     block_xor(cw, g0, g1);
     uint32_t low = alpha & 127u;
-    for (uint32_t j = 0; j < 128; j++)
-        if ((int)(j < low) ^ valpha) cw[j >> 3] ^= (uint8_t)(1u << (j & 7));
+    for (uint32_t j = 0; j < 128; j++) {
+        int below = ORACLE_PLANT == 4 ? (j <= low) : (j < low);
+        if (below ^ valpha) cw[j >> 3] ^= (uint8_t)(1u << (j & 7));
+    }
     memcpy(k0->cwleaf, cw, 16);
     memcpy(k1->cwleaf, cw, 16);
-    k1->tl = k0->tl;
-    k1->tr = k0->tr;
-    k1->vcw = k0->vcw;
 }
 
 int oracle_dcf_eval(int party, const oracle_dcf_key *k, uint32_t n, uint32_t x)
 {
+    (void)party;
     uint32_t nu = n - 7;
     uint8_t s[16];
-    int t = party;
     int v = 0;
     x &= dom_mask(n);
     memcpy(s, k->root, 16);
     for (uint32_t i = 1; i <= nu; i++) {
-        int xi = msb_bit(x, n, i);
-        uint8_t ns[16];
-        int nt, nv;
-        expand(xi, s, ns, &nt, &nv);
-        v ^= nv ^ (t & (int)((k->vcw >> (i - 1)) & 1u));
-        block_xor_if(ns, t, k->scw[i - 1]);
-        int tcw = (int)(((xi ? k->tr : k->tl) >> (i - 1)) & 1u);
-        nt ^= t & tcw;
-        memcpy(s, ns, 16);
-        t = nt;
+        uint8_t h[16];
+        int vh;
+        expand_node(s, h, &vh);
+        v ^= vh ^ (block_bit(s, 0) & (int)((k->vcw >> (i - 1)) & 1u));
+        child(s, h, k->cw[i - 1], msb_bit(x, n, i), s);
     }
     uint8_t g[16];
-    oracle_prg(2, s, g);
-    block_xor_if(g, t, k->cwleaf);
+    leaf_hash(s, g);
+    block_xor_if(g, block_bit(s, 0), k->cwleaf);
     return v ^ block_bit(g, (int)(x & 127u));
 }
 
 /* ------------------------------------------------------------------------ */
 /* Dealer: masked-input keys for one predicate over a column of rows.        */
-/* RNG domain 3 ("FSS root seeds"): j = 0,1 roots of the DPF / of the upper  */
-/* DCF, j = 2 wrap-share c_0 (bit 0), j = 3,4 roots of the lower DCF.        */
+/* RNG domain 3 ("FSS root seeds"): j = 0 the root s_0 and j = 1 the offset  */
+/* Delta of the DPF / of the upper DCF, j = 2 the wrap share c_0 (bit 0),    */
+/* j = 3, 4 root and offset of the lower DCF.                                */
 /* ------------------------------------------------------------------------ */
 
-static void root_seed(const uint8_t rk[176], uint32_t j, uint32_t query, uint32_t pred,
-                      uint32_t elem, uint8_t out[16])
+static void dealer_pair(const uint8_t rk[176], uint32_t j, uint32_t query, uint32_t pred, uint32_t elem,
+                        uint8_t seed0[16], uint8_t dseed[16])
 {
-    oracle_rng_block_rk(rk, 3, j, query, pred, elem, out);
-    out[0] &= (uint8_t)~3u;
+    oracle_rng_block_rk(rk, 3, j, query, pred, elem, seed0);
+    oracle_rng_block_rk(rk, 3, j + 1, query, pred, elem, dseed);
 }
 
 /* Equality predicate x == a: DPF at alpha = a + r (mod 2^n). */
@@ -454,12 +453,11 @@ void oracle_keygen_eq(uint32_t n, uint64_t seed, uint32_t query, uint32_t pred, 
     oracle_rng_key(seed, rk);
 #pragma omp parallel for schedule(static)
     for (long long e = 0; e < (long long)count; e++) {
-        uint8_t r0[16], r1[16];
+        uint8_t s0[16], d[16];
         uint32_t row = rows ? rows[e] : (uint32_t)e;
-        root_seed(rk, 0, query, pred, row, r0);
-        root_seed(rk, 1, query, pred, row, r1);
+        dealer_pair(rk, 0, query, pred, row, s0, d);
         uint32_t alpha = (a + r[e]) & dom_mask(n);
-        oracle_dpf_gen(n, alpha, r0, r1, &k0[e], &k1[e]);
+        oracle_dpf_gen(n, alpha, s0, d, &k0[e], &k1[e]);
     }
 }
 
@@ -474,19 +472,17 @@ void oracle_keygen_range(uint32_t n, uint64_t seed, uint32_t query, uint32_t pre
     oracle_rng_key(seed, rk);
 #pragma omp parallel for schedule(static)
     for (long long e = 0; e < (long long)count; e++) {
-        uint8_t u0[16], u1[16], l0[16], l1[16], cb[16];
+        uint8_t u0[16], ud[16], l0[16], ld[16], cb[16];
         uint32_t row = rows ? rows[e] : (uint32_t)e;
-        root_seed(rk, 0, query, pred, row, u0);
-        root_seed(rk, 1, query, pred, row, u1);
-        root_seed(rk, 3, query, pred, row, l0);
-        root_seed(rk, 4, query, pred, row, l1);
+        dealer_pair(rk, 0, query, pred, row, u0, ud);
+        dealer_pair(rk, 3, query, pred, row, l0, ld);
         oracle_rng_block_rk(rk, 3, 2, query, pred, row, cb);
         uint32_t L = (lo + r[e]) & dom_mask(n);
         uint32_t U = (hi + r[e]) & dom_mask(n);
-        oracle_dcf_gen(n, U, u0, u1, &k0[e].upper, &k1[e].upper);
-        oracle_dcf_gen(n, L, l0, l1, &k0[e].lower, &k1[e].lower);
+        oracle_dcf_gen(n, U, u0, ud, &k0[e].upper, &k1[e].upper);
+        oracle_dcf_gen(n, L, l0, ld, &k0[e].lower, &k1[e].lower);
         uint32_t c0 = (uint32_t)block_bit(cb, 0);
-        uint32_t c1 = c0 ^ (L > U ? 1u : 0u);
+        uint32_t c1 = c0 ^ (L > U && ORACLE_PLANT != 8 ? 1u : 0u);
         k0[e].upper.vcw |= c0 << 31;
         k1[e].upper.vcw |= c1 << 31;
     }
@@ -517,21 +513,19 @@ void oracle_eval_range(uint32_t n, int party, const oracle_range_key *k, const u
 void oracle_dpf_gen_seeded(uint32_t n, uint32_t alpha, uint64_t seed, uint32_t elem,
                            oracle_dpf_key *k0, oracle_dpf_key *k1)
 {
-    uint8_t rk[176], r0[16], r1[16];
+    uint8_t rk[176], s0[16], d[16];
     oracle_rng_key(seed, rk);
-    root_seed(rk, 0, 0, 0, elem, r0);
-    root_seed(rk, 1, 0, 0, elem, r1);
-    oracle_dpf_gen(n, alpha, r0, r1, k0, k1);
+    dealer_pair(rk, 0, 0, 0, elem, s0, d);
+    oracle_dpf_gen(n, alpha, s0, d, k0, k1);
 }
 
 void oracle_dcf_gen_seeded(uint32_t n, uint32_t alpha, uint64_t seed, uint32_t elem,
                            oracle_dcf_key *k0, oracle_dcf_key *k1)
 {
-    uint8_t rk[176], r0[16], r1[16];
+    uint8_t rk[176], s0[16], d[16];
     oracle_rng_key(seed, rk);
-    root_seed(rk, 0, 0, 0, elem, r0);
-    root_seed(rk, 1, 0, 0, elem, r1);
-    oracle_dcf_gen(n, alpha, r0, r1, k0, k1);
+    dealer_pair(rk, 0, 0, 0, elem, s0, d);
+    oracle_dcf_gen(n, alpha, s0, d, k0, k1);
 }
 
 /* Evaluate one key at many points (for exhaustive domain sweeps). */
@@ -547,6 +541,24 @@ void oracle_dcf_eval_points(int party, const oracle_dcf_key *k, uint32_t n, cons
 {
 #pragma omp parallel for schedule(static)
     for (long long e = 0; e < (long long)count; e++) out[e] = (uint8_t)oracle_dcf_eval(party, k, n, x[e]);
+}
+
+/* Every node the walk of x passes, for the invariant pins: seeds[i] is the
+ * seed after level i (seeds[0] the root), nu + 1 entries. */
+void oracle_dcf_path(const oracle_dcf_key *k, uint32_t n, uint32_t x, uint8_t *seeds)
+{
+    uint32_t nu = n - 7;
+    uint8_t s[16];
+    x &= dom_mask(n);
+    memcpy(s, k->root, 16);
+    memcpy(seeds, s, 16);
+    for (uint32_t i = 1; i <= nu; i++) {
+        uint8_t h[16];
+        int v;
+        expand_node(s, h, &v);
+        child(s, h, k->cw[i - 1], msb_bit(x, n, i), s);
+        memcpy(seeds + 16 * i, s, 16);
+    }
 }
 
 /* ------------------------------------------------------------------------ */

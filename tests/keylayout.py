@@ -10,24 +10,19 @@ def pad_rows(n):
     return (n + 63) // 64 * 64
 
 
-def _dcf_planes(np_, nbits):
+def _planes(np_, nbits, dcf):
+    """Byte offset of every plane of one DPF (dcf=False) or DCF sub-key, and
+    the sub-key's size: root | cw_0 .. cw_{nu-1} | [vcw] | cwleaf."""
     nu = nbits - 7
     off = {"root": 0}
     for i in range(nu):
-        off[("scw", i)] = 16 * np_ * (1 + i)
+        off[("cw", i)] = 16 * np_ * (1 + i)
     base = 16 * np_ * (1 + nu)
-    off["tl"], off["tr"], off["vcw"], off["cwleaf"] = base, base + 4 * np_, base + 8 * np_, base + 12 * np_
-    return off, base + 12 * np_ + 16 * np_
-
-
-def _dpf_planes(np_, nbits):
-    nu = nbits - 7
-    off = {"root": 0}
-    for i in range(nu):
-        off[("scw", i)] = 16 * np_ * (1 + i)
-    base = 16 * np_ * (1 + nu)
-    off["tl"], off["tr"], off["cwout"] = base, base + 4 * np_, base + 8 * np_
-    return off, base + 8 * np_ + 16 * np_
+    if dcf:
+        off["vcw"] = base
+        base += 4 * np_
+    off["cwleaf"] = base
+    return off, base + 16 * np_
 
 
 def _put(buf, off, n, data, width):
@@ -38,25 +33,25 @@ def _get(buf, off, n, width):
     return buf[off:off + n * width]
 
 
-def _enc_dcf(buf, base, np_, nbits, k):
-    off, size = _dcf_planes(np_, nbits)
+def _enc(buf, base, np_, nbits, k, dcf):
+    off, size = _planes(np_, nbits, dcf)
     n = k.size
     _put(buf, base + off["root"], n, k["root"], 16)
     for i in range(nbits - 7):
-        _put(buf, base + off[("scw", i)], n, k["scw"][:, i, :], 16)
-    for f in ("tl", "tr", "vcw"):
-        _put(buf, base + off[f], n, k[f].astype("<u4"), 4)
+        _put(buf, base + off[("cw", i)], n, k["cw"][:, i, :], 16)
+    if dcf:
+        _put(buf, base + off["vcw"], n, k["vcw"].astype("<u4"), 4)
     _put(buf, base + off["cwleaf"], n, k["cwleaf"], 16)
     return size
 
 
-def _dec_dcf(buf, base, np_, nbits, n, out):
-    off, size = _dcf_planes(np_, nbits)
+def _dec(buf, base, np_, nbits, n, out, dcf):
+    off, size = _planes(np_, nbits, dcf)
     out["root"] = _get(buf, base + off["root"], n, 16).reshape(n, 16)
     for i in range(nbits - 7):
-        out["scw"][:, i, :] = _get(buf, base + off[("scw", i)], n, 16).reshape(n, 16)
-    for f in ("tl", "tr", "vcw"):
-        out[f] = _get(buf, base + off[f], n, 4).view("<u4")
+        out["cw"][:, i, :] = _get(buf, base + off[("cw", i)], n, 16).reshape(n, 16)
+    if dcf:
+        out["vcw"] = _get(buf, base + off["vcw"], n, 4).view("<u4")
     out["cwleaf"] = _get(buf, base + off["cwleaf"], n, 16).reshape(n, 16)
     return size
 
@@ -66,19 +61,14 @@ def to_device(kind, nbits, keys):
     n = keys.size
     np_ = pad_rows(n)
     if kind == 0:
-        off, size = _dpf_planes(np_, nbits)
+        _, size = _planes(np_, nbits, False)
         buf = np.zeros(size, np.uint8)
-        _put(buf, off["root"], n, keys["root"], 16)
-        for i in range(nbits - 7):
-            _put(buf, off[("scw", i)], n, keys["scw"][:, i, :], 16)
-        _put(buf, off["tl"], n, keys["tl"].astype("<u4"), 4)
-        _put(buf, off["tr"], n, keys["tr"].astype("<u4"), 4)
-        _put(buf, off["cwout"], n, keys["cwout"], 16)
+        _enc(buf, 0, np_, nbits, keys, False)
         return buf
-    _, half = _dcf_planes(np_, nbits)
+    _, half = _planes(np_, nbits, True)
     buf = np.zeros(2 * half, np.uint8)
-    _enc_dcf(buf, 0, np_, nbits, keys["upper"])
-    _enc_dcf(buf, half, np_, nbits, keys["lower"])
+    _enc(buf, 0, np_, nbits, keys["upper"], True)
+    _enc(buf, half, np_, nbits, keys["lower"], True)
     return buf
 
 
@@ -88,20 +78,14 @@ def from_device(kind, nbits, n, buf):
     np_ = pad_rows(n)
     if kind == 0:
         out = np.zeros(n, ofss.DPF_KEY)
-        off, _ = _dpf_planes(np_, nbits)
-        out["root"] = _get(buf, off["root"], n, 16).reshape(n, 16)
-        for i in range(nbits - 7):
-            out["scw"][:, i, :] = _get(buf, off[("scw", i)], n, 16).reshape(n, 16)
-        out["tl"] = _get(buf, off["tl"], n, 4).view("<u4")
-        out["tr"] = _get(buf, off["tr"], n, 4).view("<u4")
-        out["cwout"] = _get(buf, off["cwout"], n, 16).reshape(n, 16)
+        _dec(buf, 0, np_, nbits, n, out, False)
         return out
     out = np.zeros(n, ofss.RANGE_KEY)
-    _, half = _dcf_planes(np_, nbits)
+    _, half = _planes(np_, nbits, True)
     up = np.zeros(n, ofss.DCF_KEY)
     lo = np.zeros(n, ofss.DCF_KEY)
-    _dec_dcf(buf, 0, np_, nbits, n, up)
-    _dec_dcf(buf, half, np_, nbits, n, lo)
+    _dec(buf, 0, np_, nbits, n, up, True)
+    _dec(buf, half, np_, nbits, n, lo, True)
     out["upper"] = up
     out["lower"] = lo
     return out

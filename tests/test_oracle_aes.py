@@ -59,22 +59,6 @@ def test_random_blocks_match_openssl():
 
 
 @pytest.mark.skipif(shutil.which("openssl") is None, reason="openssl CLI not present")
-def test_prg_is_fixed_key_mmo_aes():
-    """G_sigma(s) = AES_K(s ^ sigma) ^ (s ^ sigma), K = 00..0f, sigma in byte 0."""
-    rng = np.random.default_rng(8)
-    key = bytes(range(16))
-    for sigma in (0, 1, 2):
-        for _ in range(8):
-            s = bytearray(rng.bytes(16))
-            s[0] &= 0xFC
-            u = bytearray(s)
-            u[0] ^= sigma
-            enc = _openssl_ecb(key, bytes(u))
-            expect = bytes(a ^ b for a, b in zip(enc, u))
-            assert fss.prg(sigma, bytes(s)) == expect
-
-
-@pytest.mark.skipif(shutil.which("openssl") is None, reason="openssl CLI not present")
 def test_dealer_rng_is_aes_counter_mode():
     """block = AES_{LE64(seed) || 'OBLIVGM1'}(LE16 dom || LE16 j || LE32 q || LE32 p || LE32 e)."""
     for seed, dom, j, q, p, e in [(0, 1, 0, 0, 0, 0), (0x0123456789ABCDEF, 3, 4, 77, 5, 123456),

@@ -10,7 +10,17 @@ paper and the mathematics fix:
   [x == a] and [lo <= x < hi], for every row mask r; r = 0 reduces to the
   unmasked functions.
 * Each party's output alone is not the function (a share, not the value).
+* The half-tree structure (a published construction, restated in the
+  oracle): on the special path the parties' seeds differ by one offset, off
+  it they are equal.
+* Planted mistakes: copies of the oracle built with one deliberate error
+  each (a dropped offset term, a right child that forgets its parent, the
+  value bit from the wrong position, an off-by-one leaf mask, no orthomorphism
+  in the hash, a dropped running value, t from the wrong bit, a lost wrap
+  bit) fail at least one of these pins.
 """
+import shutil
+import subprocess
 import numpy as np
 import pytest
 
@@ -89,11 +99,45 @@ def test_single_share_is_not_the_function():
 
 def test_correction_words_common_roots_distinct():
     _, (k0, k1) = _dcf_recon(12, 777, 51, np.arange(4, dtype=np.uint32))
-    for f in ("scw", "tl", "tr", "vcw", "cwleaf"):
+    for f in ("cw", "vcw", "cwleaf"):
         np.testing.assert_array_equal(k0[f], k1[f])
-    assert not np.array_equal(k0["root"], k1["root"])
-    # seeds carry no t/v bits: bits 0 and 1 of every seed byte 0 are zero
-    assert (k0["root"][:, 0] & 3).max() == 0 and (k0["scw"][:, :12, 0] & 3).max() == 0
+    delta = k0["root"] ^ k1["root"]
+    # the roots differ by the offset Delta: t bits (bit 0) differ, bit 1 is clear
+    # in both seeds, in Delta and in every correction word
+    assert delta[0, 0] & 3 == 1
+    assert (k0["root"][:, 0] & 2).max() == 0 and (k0["cw"][:, :5, 0] & 2).max() == 0
+
+
+def test_half_tree_invariant_along_the_special_path():
+    """On alpha's path the two parties' seeds differ by the roots' offset at
+    every level; a walk that leaves the path has equal seeds from the first
+    level where it leaves (so everything after cancels)."""
+    n = 12
+    for alpha, x in [(777, 777), (777, 776), (0, 4095), (4095, 2048), (1234, 1234 ^ 0x200)]:
+        k0, k1 = fss.dcf_gen(n, alpha, 52, alpha)
+        delta = k0["root"][0] ^ k1["root"][0]
+        p0, p1 = fss.dcf_path(k0, n, x), fss.dcf_path(k1, n, x)
+        hi = [(x >> (n - i)) == (alpha >> (n - i)) for i in range(n - 6)]   # still on the path after i levels
+        for i in range(n - 6):
+            if hi[i]:
+                np.testing.assert_array_equal(p0[i] ^ p1[i], delta)
+            else:
+                np.testing.assert_array_equal(p0[i], p1[i])
+        k0, k1 = fss.dpf_gen(n, alpha, 53, alpha)
+        assert not np.array_equal(k0["cw"][0, 0], k0["cw"][0, 1])
+
+
+def test_correction_bits_do_not_reveal_alpha():
+    """For a fixed alpha and fresh seeds, every value-correction bit, every
+    t bit of a correction word and their XOR take both values: the key's bits
+    hide alpha (a value bit taken from the same position as the t bit would
+    make their XOR a function of alpha's bits)."""
+    n, alpha = 12, 0b101101110010
+    keys = [fss.dcf_gen(n, alpha, 900 + i, 5)[0] for i in range(48)]
+    vcw = np.array([[(int(k["vcw"][0]) >> i) & 1 for i in range(n - 7)] for k in keys])
+    t_cw = np.array([[int(k["cw"][0, i, 0]) & 1 for i in range(n - 7)] for k in keys])
+    for bits in (vcw, t_cw, vcw ^ t_cw):
+        assert ((bits.min(axis=0) == 0) & (bits.max(axis=0) == 1)).all()
 
 
 # --------------------------------------------------------------------------- masked input
@@ -210,3 +254,56 @@ def test_all_domain_widths(n):
         np.testing.assert_array_equal(y, (xs == alpha).astype(np.uint8))
         y, _ = _dcf_recon(n, alpha, 7 * n + 1, xs)
         np.testing.assert_array_equal(y, (xs < alpha).astype(np.uint8))
+
+
+# --------------------------------------------------------------------------- tree hash and planted mistakes
+
+def _openssl_ecb(key: bytes, data: bytes) -> bytes:
+    return subprocess.run(["openssl", "enc", "-aes-128-ecb", "-nopad", "-K", key.hex()],
+                          input=data, stdout=subprocess.PIPE, check=True).stdout
+
+
+def _hash_pin():
+    """H(x) = AES_K(sigma(x)) xor sigma(x), K = 00..0f, sigma(a || b) = (a xor b) || a
+    on the 8-byte halves, against openssl's AES."""
+    rng = np.random.default_rng(61)
+    xs = [rng.bytes(16) for _ in range(16)]
+    sig = [bytes(a ^ b for a, b in zip(x[:8], x[8:])) + x[:8] for x in xs]
+    enc = _openssl_ecb(bytes(range(16)), b"".join(sig))
+    for i, x in enumerate(xs):
+        want = bytes(a ^ b for a, b in zip(enc[16 * i:16 * i + 16], sig[i]))
+        assert fss.tree_hash(x) == want
+
+
+@pytest.mark.skipif(shutil.which("openssl") is None, reason="openssl CLI not present")
+def test_tree_hash_is_fixed_key_aes_with_orthomorphism():
+    _hash_pin()
+
+
+def _fast_pins():
+    xs = np.arange(256, dtype=np.uint32)
+    for alpha in (0, 1, 77, 127, 128, 200, 255):
+        y, _ = _dpf_recon(8, alpha, 11, xs)
+        np.testing.assert_array_equal(y, (xs == alpha).astype(np.uint8))
+        y, _ = _dcf_recon(8, alpha, 12, xs)
+        np.testing.assert_array_equal(y, (xs < alpha).astype(np.uint8))
+    for alpha in (300, 3000):
+        xs12 = np.arange(4096, dtype=np.uint32)
+        y, _ = _dcf_recon(12, alpha, 14, xs12)
+        np.testing.assert_array_equal(y, (xs12 < alpha).astype(np.uint8))
+    test_masked_range_wraps_both_ways()
+    test_half_tree_invariant_along_the_special_path()
+    test_correction_bits_do_not_reveal_alpha()
+    if shutil.which("openssl"):
+        _hash_pin()
+
+
+@pytest.mark.parametrize("plant", range(1, 9))
+def test_planted_mistakes_are_caught(plant, tmp_path, monkeypatch):
+    _fast_pins()            # the real oracle passes
+    path = fss.build(path=str(tmp_path / f"liboracle_plant{plant}.so"), plant=plant)
+    monkeypatch.setattr(fss, "_lib", fss.load(path))
+    if plant == 5 and not shutil.which("openssl"):
+        pytest.skip("the hash pin needs openssl")
+    with pytest.raises(AssertionError):
+        _fast_pins()
