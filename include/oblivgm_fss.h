@@ -27,15 +27,17 @@
  * Key batch layout (per party), rows padded to Np = round_up(n, 64):
  *   a batch is a sequence of planes; plane p holds one field for every row,
  *   row e at byte offset plane_offset + e * field_size.
- *   DPF (nu = nbits - 7):   root[16] | scw_0[16] .. scw_{nu-1}[16] | tl[4] | tr[4] | cwout[16]
- *   DCF (nu = nbits - 7):   root[16] | scw_0[16] .. scw_{nu-1}[16] | tl[4] | tr[4] | vcw[4] | cwleaf[16]
+ *   DPF (nu = nbits - 7):   root[16] | cw_0[16] .. cw_{nu-1}[16] | cwleaf[16]
+ *   DCF (nu = nbits - 7):   root[16] | cw_0[16] .. cw_{nu-1}[16] | vcw[4] | cwleaf[16]
  *   RANGE key:              DCF at U = hi + r, then DCF at L = lo + r
- *   bit i of tl/tr/vcw belongs to level i (level 0 consumes the most
- *   significant input bit); both trees stop nu levels down and a 128-bit leaf
- *   (cwout / cwleaf corrects G_C of the last seed) answers the low 7 input
- *   bits; bit 31 of the upper DCF's vcw is the party's wrap share c_b.  Per
- *   element and party: DPF 16*nbits - 72 bytes (440 at 32 bits), RANGE
- *   2 * (16*nbits - 68) bytes (888 at 32 bits).
+ *   The trees are half-trees (one hash per node, one correction word per
+ *   level, right child = left child xor parent); bit i of vcw is the value
+ *   correction of level i (level 0 consumes the most significant input bit);
+ *   both trees stop nu levels down and a 128-bit leaf (cwleaf corrects the
+ *   leaf hash of the last seed) answers the low 7 input bits; bit 31 of the
+ *   upper DCF's vcw is the party's wrap share c_b.  Per element and party:
+ *   DPF 16*(nbits - 5) bytes (432 at 32 bits), RANGE 2 * (16*(nbits - 5) + 4)
+ *   bytes (872 at 32 bits).
  */
 #ifndef OBLIVGM_FSS_H
 #define OBLIVGM_FSS_H
@@ -69,7 +71,7 @@ typedef struct fss_keybatch {
     void*    key[2];
 } fss_keybatch;
 
-/* Bytes of one element's key for one party (DPF 440 / RANGE 888 at 32 bits);
+/* Bytes of one element's key for one party (DPF 432 / RANGE 872 at 32 bits);
  * 0 for an invalid kind or nbits. */
 uint64_t fss_key_bytes(int32_t kind, uint32_t nbits);
 

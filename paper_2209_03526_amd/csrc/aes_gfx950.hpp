@@ -1,8 +1,9 @@
 // aes_gfx950.hpp -- AES-128 encryption for gfx950 wavefronts, T-table in LDS.
 //
-// The PRG of the FSS trees is fixed-key AES-128 in Matyas-Meyer-Oseas form
-// (lambda = 128, Sec. VII-A); the dealer's randomness is AES-128 in counter
-// mode under a per-call key.  Both run through aes128_encrypt() below.
+// The tree hash of the FSS keys is fixed-key AES-128 made circular
+// correlation-robust, H(x) = AES_K(sigma(x)) ^ sigma(x) (lambda = 128,
+// Sec. VII-A); the dealer's randomness is AES-128 in counter mode under a
+// per-call key.  Both run through aes128_encrypt() below.
 //
 // Table layout.  T0[x] = (2S(x), S(x), S(x), 3S(x)) (bytes 0..3: the
 // MixColumns image of S(x) in row 0) and T1 = rotl8(T0) sit in LDS as 256 rows
@@ -119,16 +120,16 @@ constexpr RoundKeys expand_key(const uint8_t (&key)[16]) {
     return rk;
 }
 
-constexpr uint8_t kPrgKeyBytes[16] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
-constexpr RoundKeys kPrgKeys = expand_key(kPrgKeyBytes);
+constexpr uint8_t kHashKeyBytes[16] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+constexpr RoundKeys kHashKeys = expand_key(kHashKeyBytes);
 
 // Key sources: k[i] is word i for the whitening (i < 4) and last (i >= 40)
 // round keys, k.mid(i) a word of rounds 1..9, already rotated.
 //
-// The fixed PRG key schedule, folded into instruction constants after unrolling.
-struct FixedPrgKey {
-    __device__ __forceinline__ constexpr uint32_t operator[](int i) const { return kPrgKeys.w[i]; }
-    __device__ __forceinline__ constexpr uint32_t mid(int i) const { return kPrgKeys.w[i]; }
+// The fixed tree-hash key schedule, folded into instruction constants after unrolling.
+struct FixedHashKey {
+    __device__ __forceinline__ constexpr uint32_t operator[](int i) const { return kHashKeys.w[i]; }
+    __device__ __forceinline__ constexpr uint32_t mid(int i) const { return kHashKeys.w[i]; }
 };
 
 // A per-call key schedule held in kernel arguments (scalar registers).
@@ -240,36 +241,16 @@ __device__ __forceinline__ uint4 and4(uint4 a, uint32_t m) {
     return make_uint4(a.x & m, a.y & m, a.z & m, a.w & m);
 }
 
-// G_sigma(s) = AES_K(u) ^ u, u = s ^ sigma (sigma enters byte 0; seeds have
-// bits 0 and 1 clear, so sigma in {0,1,2} never collides).
-__device__ __forceinline__ uint4 prg(uint4 s, uint32_t sigma, const uint32_t* tab, LaneOff lo) {
-    uint4 u = s;
-    u.x ^= sigma;
-    return xor4(aes128_encrypt(u, FixedPrgKey{}, tab, lo), u);
-}
+// The linear orthomorphism sigma(a || b) = (a ^ b) || a on the two 64-bit
+// halves of a block (a = bytes 0..7, words x and y).
+__device__ __forceinline__ uint4 sigma(uint4 s) { return make_uint4(s.x ^ s.z, s.y ^ s.w, s.x, s.y); }
 
-// Both children of one seed, G_0(s) and G_1(s).  Their AES inputs differ only
-// in byte 0, which after ShiftRows feeds column 0 of round 1 alone: columns
-// 1..3 of round 1 are shared, and column 0 of the right child is the left
-// one's with its T0 term swapped (one extra lookup instead of sixteen).
-__device__ __forceinline__ void prg_pair(uint4 s, const uint32_t* tab, LaneOff lo, uint4& wl, uint4& wr) {
-    const FixedPrgKey rk{};
-    const uint32_t s0 = s.x ^ rk[0], s1 = s.y ^ rk[1], s2 = s.z ^ rk[2], s3 = s.w ^ rk[3];
-    const uint32_t a_l = tlook<0>(tab, s0, lo.t0);
-    const uint32_t a_r = tlook<0>(tab, s0 ^ 1u, lo.t0);
-    const uint32_t b = tlook<1>(tab, s1, lo.t1);
-    const uint32_t c = tlook<2>(tab, s2, lo.t0);
-    const uint32_t d = tlook<3>(tab, s3, lo.t1);
-    const uint32_t cd = rotl32(xor3(c, d, rk.mid(4)), 16);
-    const uint32_t n0l = xor3(a_l, b, cd);
-    const uint32_t n0r = xor3(a_r, b, cd);
-    const uint32_t n1 = round_col(tab, lo, s1, s2, s3, s0, rk.mid(5));
-    const uint32_t n2 = round_col(tab, lo, s2, s3, s0, s1, rk.mid(6));
-    const uint32_t n3 = round_col(tab, lo, s3, s0, s1, s2, rk.mid(7));
-    uint4 ur = s;
-    ur.x ^= 1u;
-    wl = xor4(aes128_rounds_2_10(n0l, n1, n2, n3, rk, tab, lo), s);
-    wr = xor4(aes128_rounds_2_10(n0r, n1, n2, n3, rk, tab, lo), ur);
+// H(s) = AES_K(sigma(s)) ^ sigma(s) under the fixed key K = 00 01 .. 0f: one
+// hash per tree node (Guo, Katz, Wang, Yu, IEEE S&P 2020 show fixed-key AES in
+// this form is circular correlation-robust, the property a half-tree needs).
+__device__ __forceinline__ uint4 tree_hash(uint4 s, const uint32_t* tab, LaneOff lo) {
+    const uint4 u = sigma(s);
+    return xor4(aes128_encrypt(u, FixedHashKey{}, tab, lo), u);
 }
 
 }  // namespace ogm

@@ -79,24 +79,20 @@ inline __host__ __device__ uint64_t pad_rows(uint64_t n) { return (n + 63) & ~63
 // Byte offsets of the planes of one DPF / DCF sub-key, relative to its start.
 struct DpfPlanes {
     uint64_t np;
-    uint32_t nu;
+    uint32_t nu;            // levels walked: nbits - 7
     __host__ __device__ uint64_t root() const { return 0; }
-    __host__ __device__ uint64_t scw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
-    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)nu); }
-    __host__ __device__ uint64_t tr() const { return tl() + 4 * np; }
-    __host__ __device__ uint64_t cwout() const { return tl() + 8 * np; }
-    __host__ __device__ uint64_t bytes() const { return cwout() + 16 * np; }
+    __host__ __device__ uint64_t cw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
+    __host__ __device__ uint64_t cwleaf() const { return 16 * np * (1 + (uint64_t)nu); }
+    __host__ __device__ uint64_t bytes() const { return cwleaf() + 16 * np; }
 };
 
 struct DcfPlanes {
     uint64_t np;
-    uint32_t nu;            // levels walked: nbits - 7
+    uint32_t nu;
     __host__ __device__ uint64_t root() const { return 0; }
-    __host__ __device__ uint64_t scw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
-    __host__ __device__ uint64_t tl() const { return 16 * np * (1 + (uint64_t)nu); }
-    __host__ __device__ uint64_t tr() const { return tl() + 4 * np; }
-    __host__ __device__ uint64_t vcw() const { return tl() + 8 * np; }       // bit 31: wrap share c_b
-    __host__ __device__ uint64_t cwleaf() const { return tl() + 12 * np; }
+    __host__ __device__ uint64_t cw(uint32_t i) const { return 16 * np * (1 + (uint64_t)i); }
+    __host__ __device__ uint64_t vcw() const { return 16 * np * (1 + (uint64_t)nu); }   // bit 31: wrap share c_b
+    __host__ __device__ uint64_t cwleaf() const { return vcw() + 4 * np; }
     __host__ __device__ uint64_t bytes() const { return cwleaf() + 16 * np; }
 };
 
@@ -110,35 +106,35 @@ __device__ __forceinline__ T& at_w(uint8_t* base, uint64_t off, uint64_t row) {
     return ((T*)(base + off))[row];
 }
 
-__device__ __forceinline__ uint4 clear_tv(uint4 w) {
-    w.x &= ~3u;
-    return w;
+// ----------------------------------------------------------------- half-tree nodes
+//
+// A node is a 128-bit seed s with bit 1 clear; t(s) = bit 0.  Expanding it
+// costs one hash h = H(s): its bit 1 is the node's value bit v, and with that
+// bit cleared (h') the children are
+//   left  = h' ^ t(s) * CW_i,      right = left ^ s,
+// so one correction word per level serves both children.
+
+// h' (bit 1 of H(s) cleared); v = bit 1 of H(s).
+__device__ __forceinline__ uint4 expand(uint4 s, uint32_t& v, const uint32_t* tab, LaneOff loff) {
+    uint4 h = tree_hash(s, tab, loff);
+    v = (h.x >> 1) & 1u;
+    h.x &= ~2u;
+    return h;
 }
 
-// ----------------------------------------------------------------- Eval (DPF, DCF)
+// The child of s on side xi: h' ^ t(s) * cw ^ xi * s.
+__device__ __forceinline__ uint4 child(uint4 s, uint4 h, uint4 cw, uint32_t xi) {
+    const uint32_t tm = 0u - (s.x & 1u), xm = 0u - xi;
+    return make_uint4(xor3(h.x, cw.x & tm, s.x & xm), xor3(h.y, cw.y & tm, s.y & xm),
+                      xor3(h.z, cw.z & tm, s.z & xm), xor3(h.w, cw.w & tm, s.w & xm));
+}
 
-// Party `party`'s DPF output bit at x (nu = nbits - 7 levels, 128-bit leaf).
-__device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
-                                             uint32_t party, uint32_t x, const uint32_t* tab, LaneOff loff) {
-    const DpfPlanes P{np, nbits - 7};
-    uint4 s = at<uint4>(key, P.root(), row);
-    const uint32_t tlw = at<uint32_t>(key, P.tl(), row);
-    const uint32_t trw = at<uint32_t>(key, P.tr(), row);
-    uint32_t t = party;
-    for (uint32_t i = 0; i < P.nu; i++) {
-        const uint4 cw = at<uint4>(key, P.scw(i), row);
-        const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
-        uint4 w = prg(s, xi, tab, loff);
-        const uint32_t m = 0u - t;
-        s = xor4(clear_tv(w), and4(cw, m));
-        t = (w.x & 1u) ^ (t & ((xi ? trw : tlw) >> i));
-        t &= 1u;
-    }
-    const uint4 cwo = at<uint4>(key, P.cwout(), row);
-    uint4 g = xor4(prg(s, 2u, tab, loff), and4(cwo, 0u - t));
-    const uint32_t idx = x & 127u;
-    const uint32_t word = idx < 64 ? (idx < 32 ? g.x : g.y) : (idx < 96 ? g.z : g.w);
-    return (word >> (idx & 31u)) & 1u;
+// Leaf block of node s under its correction word: H(s ^ 2) ^ t(s) * cwleaf
+// (tree seeds have bit 1 clear, so a leaf input is never an expansion input).
+__device__ __forceinline__ uint4 leaf(uint4 s, uint4 cwleaf, const uint32_t* tab, LaneOff loff) {
+    uint4 u = s;
+    u.x ^= 2u;
+    return xor4(tree_hash(u, tab, loff), and4(cwleaf, 0u - (s.x & 1u)));
 }
 
 // Bit idx (0..127) of a 128-bit block.
@@ -147,39 +143,52 @@ __device__ __forceinline__ uint32_t block_bit(uint4 g, uint32_t idx) {
     return (word >> (idx & 31u)) & 1u;
 }
 
-// Party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in step
-// over the nu = nbits - 7 high bits, then each DCF's 128-bit leaf answers the
-// low 7 bits.
+// ----------------------------------------------------------------- Eval (DPF, DCF)
+
+// A party's DPF output bit at x: nu = nbits - 7 levels, then the 128-bit leaf
+// answers the low 7 bits.  No party index is needed: t is bit 0 of the seed.
+__device__ __forceinline__ uint32_t dpf_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
+                                             uint32_t x, const uint32_t* tab, LaneOff loff) {
+    const DpfPlanes P{np, nbits - 7};
+    uint4 s = at<uint4>(key, P.root(), row);
+    for (uint32_t i = 0; i < P.nu; i++) {
+        const uint4 cw = at<uint4>(key, P.cw(i), row);
+        const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
+        uint32_t v;
+        const uint4 h = expand(s, v, tab, loff);
+        s = child(s, h, cw, xi);
+    }
+    return block_bit(leaf(s, at<uint4>(key, P.cwleaf(), row), tab, loff), x & 127u);
+}
+
+// A party's share of [lo <= x < hi]: DCF_U(x) ^ DCF_L(x) ^ c_b, both walks in
+// step over the nu high bits, each adding v ^ t * VCW_i of the node it leaves;
+// then each DCF's 128-bit leaf answers the low 7 bits.
 __device__ __forceinline__ uint32_t range_eval(const uint8_t* key, uint64_t np, uint64_t row, uint32_t nbits,
-                                               uint32_t party, uint32_t x, const uint32_t* tab,
-                                               LaneOff loff) {
+                                               uint32_t x, const uint32_t* tab, LaneOff loff) {
     const DcfPlanes P{np, nbits - 7};
     const uint8_t* ku = key;
     const uint8_t* kl = key + P.bytes();
     uint4 su = at<uint4>(ku, P.root(), row);
     uint4 sl = at<uint4>(kl, P.root(), row);
-    const uint32_t tlu = at<uint32_t>(ku, P.tl(), row), tru = at<uint32_t>(ku, P.tr(), row);
     const uint32_t vcu = at<uint32_t>(ku, P.vcw(), row);
-    const uint32_t tll = at<uint32_t>(kl, P.tl(), row), trl = at<uint32_t>(kl, P.tr(), row);
     const uint32_t vcl = at<uint32_t>(kl, P.vcw(), row);
-    uint32_t tu = party, tv = party, vu = 0, vl = 0;
+    uint32_t v = 0;
     for (uint32_t i = 0; i < P.nu; i++) {
-        const uint4 cwu = at<uint4>(ku, P.scw(i), row);
-        const uint4 cwl = at<uint4>(kl, P.scw(i), row);
+        const uint4 cwu = at<uint4>(ku, P.cw(i), row);
+        const uint4 cwl = at<uint4>(kl, P.cw(i), row);
         const uint32_t xi = (x >> (nbits - 1 - i)) & 1u;
-        const uint4 wu = prg(su, xi, tab, loff);
-        const uint4 wl = prg(sl, xi, tab, loff);
-        vu ^= (wu.x >> 1) ^ (tu & (vcu >> i));
-        vl ^= (wl.x >> 1) ^ (tv & (vcl >> i));
-        su = xor4(clear_tv(wu), and4(cwu, 0u - tu));
-        sl = xor4(clear_tv(wl), and4(cwl, 0u - tv));
-        tu = ((wu.x ^ (tu & ((xi ? tru : tlu) >> i))) & 1u);
-        tv = ((wl.x ^ (tv & ((xi ? trl : tll) >> i))) & 1u);
+        uint32_t vu, vl;
+        const uint4 hu = expand(su, vu, tab, loff);
+        const uint4 hl = expand(sl, vl, tab, loff);
+        v ^= vu ^ vl ^ (su.x & (vcu >> i)) ^ (sl.x & (vcl >> i));
+        su = child(su, hu, cwu, xi);
+        sl = child(sl, hl, cwl, xi);
     }
-    const uint4 gu = xor4(prg(su, 2u, tab, loff), and4(at<uint4>(ku, P.cwleaf(), row), 0u - tu));
-    const uint4 gl = xor4(prg(sl, 2u, tab, loff), and4(at<uint4>(kl, P.cwleaf(), row), 0u - tv));
+    const uint4 gu = leaf(su, at<uint4>(ku, P.cwleaf(), row), tab, loff);
+    const uint4 gl = leaf(sl, at<uint4>(kl, P.cwleaf(), row), tab, loff);
     const uint32_t idx = x & 127u;
-    return (vu ^ vl ^ block_bit(gu, idx) ^ block_bit(gl, idx) ^ (vcu >> 31)) & 1u;
+    return (v ^ block_bit(gu, idx) ^ block_bit(gl, idx) ^ (vcu >> 31)) & 1u;
 }
 
 struct EvalDesc {
@@ -208,9 +217,9 @@ __device__ __forceinline__ void eval_rows(const EvalDesc& D, uint64_t row0, cons
     if (row < D.n) {
         const uint32_t x = D.xhat[row];
         if (D.kind == FSS_EQ)
-            bit = dpf_eval(D.key, np, row, D.nbits, D.party, x, tab, loff);
+            bit = dpf_eval(D.key, np, row, D.nbits, x, tab, loff);
         else
-            bit = range_eval(D.key, np, row, D.nbits, D.party, x, tab, loff);
+            bit = range_eval(D.key, np, row, D.nbits, x, tab, loff);
     }
     const uint64_t ballot = __ballot(bit);
     if ((threadIdx.x & 63u) == 0) {
@@ -267,15 +276,12 @@ __device__ __forceinline__ void pin_in_vgprs(uint4& v) {
 
 __device__ __forceinline__ void pin_in_vgprs(uint32_t& v) { asm volatile("" : "+v"(v) : : "memory"); }
 
-__device__ __forceinline__ uint32_t sel(uint32_t c, uint32_t a, uint32_t b) { return c ? a : b; }
-__device__ __forceinline__ uint4 sel4(uint32_t c, uint4 a, uint4 b) { return c ? a : b; }
-
 // The dealer's work for one row is split over a lane pair: even lane = party 0,
-// odd lane = party 1.  Each lane expands only its own seed (2 AES per level);
-// what Gen needs of the other party -- its "lose" child and its t / v bits --
-// comes from the partner lane through a DPP quad permutation (lanes 0<->1,
-// 2<->3), so both lanes form the same correction words and each writes them
-// into its own party's key.
+// odd lane = party 1.  Each lane expands only its own seed (one hash per
+// level); what Gen needs of the other party -- its hash and value bit -- comes
+// from the partner lane through a DPP quad permutation (lanes 0<->1, 2<->3),
+// so both lanes form the same correction words and each writes them into its
+// own party's key.
 
 // Value of `v` in the partner lane (lane ^ 1).
 __device__ __forceinline__ uint32_t partner(uint32_t v) {
@@ -286,92 +292,74 @@ __device__ __forceinline__ uint4 partner4(uint4 v) {
     return make_uint4(partner(v.x), partner(v.y), partner(v.z), partner(v.w));
 }
 
-// DPF Gen for alpha over nbits, this lane's party b: writes key `k` of `row`.
-__device__ __forceinline__ void dpf_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
-                                        uint32_t b, uint4 s, const uint32_t* tab, LaneOff loff) {
-    const DpfPlanes P{np, nbits - 7};
-    at_w<uint4>(k, P.root(), row) = s;
-    uint32_t t = b, tlw = 0, trw = 0;
-    for (uint32_t i = 0; i < P.nu; i++) {
+// Gen of one DPF (DCF = false) or DCF tree for alpha over nbits, this lane's
+// party b, whose root is s; delta is the dealer's offset (both lanes hold it).
+// Along alpha's path the parties' seeds differ by delta.  Per level
+//   CW_i = h'_0 ^ h'_1 ^ (1 - alpha_i) * delta
+// makes the off-path children equal and keeps the on-path difference delta;
+// a DCF adds VCW_i = v_0 ^ v_1 ^ V_alpha ^ alpha_i, after which V_alpha is
+// alpha_i.  The leaf word is L(s_0) ^ L(s_1) xor e_{alpha mod 128} (DPF) or
+// xor the 128-bit mask [j < alpha mod 128], flipped when V_alpha = 1 (DCF).
+// `wrap` (DCF only) goes to bit 31 of the VCW word.
+template <bool DCF>
+__device__ __forceinline__ void tree_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
+                                         uint4 s, uint4 delta, uint32_t wrap, const uint32_t* tab, LaneOff loff) {
+    const uint32_t nu = nbits - 7;
+    const DpfPlanes PP{np, nu};
+    const DcfPlanes PC{np, nu};
+    at_w<uint4>(k, PP.root(), row) = s;
+    uint32_t va = 0, vw = 0;
+    for (uint32_t i = 0; i < nu; i++) {
         const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
-        uint4 wl, wr;
-        prg_pair(s, tab, loff, wl, wr);
-        const uint4 keep = clear_tv(sel4(a, wr, wl));
-        const uint4 lose = clear_tv(sel4(a, wl, wr));
-        const uint32_t bits = (wl.x & 1u) | ((wr.x & 1u) << 1);       // t^L, t^R of this party
-        const uint32_t both = bits ^ partner(bits);                   // t^L_0 ^ t^L_1, t^R_0 ^ t^R_1
-        const uint4 scw = xor4(lose, partner4(lose));
-        const uint32_t tlcw = (both ^ a ^ 1u) & 1u;
-        const uint32_t trcw = ((both >> 1) ^ a) & 1u;
-        const uint32_t tkcw = sel(a, trcw, tlcw);
-        const uint32_t tk = (sel(a, wr.x, wl.x)) & 1u;
-        s = xor4(keep, and4(scw, 0u - t));
-        t = tk ^ (t & tkcw);
-        at_w<uint4>(k, P.scw(i), row) = scw;
-        tlw |= tlcw << i;
-        trw |= trcw << i;
+        uint32_t v;
+        const uint4 h = expand(s, v, tab, loff);
+        const uint4 cw = xor4(xor4(h, partner4(h)), and4(delta, a - 1u));   // a - 1: all ones when a = 0
+        if (DCF) {
+            const uint32_t vcw = v ^ partner(v) ^ va ^ a;
+            vw |= vcw << i;
+            va = a;                             // V_alpha ^ (v_0 ^ v_1) ^ VCW_i
+        }
+        s = child(s, h, cw, a);
+        at_w<uint4>(k, PP.cw(i), row) = cw;      // the same offset in both layouts
     }
-    const uint4 g = prg(s, 2u, tab, loff);
+    uint4 u = s;
+    u.x ^= 2u;
+    const uint4 g = tree_hash(u, tab, loff);
     uint4 cw = xor4(g, partner4(g));
     const uint32_t low = alpha & 127u;
-    const uint32_t bit = 1u << (low & 31u);
-    cw.x ^= (low >> 5) == 0 ? bit : 0u;
-    cw.y ^= (low >> 5) == 1 ? bit : 0u;
-    cw.z ^= (low >> 5) == 2 ? bit : 0u;
-    cw.w ^= (low >> 5) == 3 ? bit : 0u;
-    at_w<uint32_t>(k, P.tl(), row) = tlw;
-    at_w<uint32_t>(k, P.tr(), row) = trw;
-    at_w<uint4>(k, P.cwout(), row) = cw;
+    if (DCF) {
+        // [j < low] for j = 0..127 as a 128-bit mask, flipped when V_alpha = 1
+        const uint32_t flip = 0u - va;
+        const uint32_t m0 = low >= 32 ? ~0u : (1u << low) - 1u;
+        const uint32_t m1 = low >= 64 ? ~0u : (low <= 32 ? 0u : (1u << (low - 32)) - 1u);
+        const uint32_t m2 = low >= 96 ? ~0u : (low <= 64 ? 0u : (1u << (low - 64)) - 1u);
+        const uint32_t m3 = low <= 96 ? 0u : (1u << (low - 96)) - 1u;
+        cw = xor4(cw, make_uint4(m0 ^ flip, m1 ^ flip, m2 ^ flip, m3 ^ flip));
+        at_w<uint32_t>(k, PC.vcw(), row) = vw | (wrap << 31);
+    } else {
+        const uint32_t bit = 1u << (low & 31u);
+        cw.x ^= (low >> 5) == 0 ? bit : 0u;
+        cw.y ^= (low >> 5) == 1 ? bit : 0u;
+        cw.z ^= (low >> 5) == 2 ? bit : 0u;
+        cw.w ^= (low >> 5) == 3 ? bit : 0u;
+    }
+    at_w<uint4>(k, DCF ? PC.cwleaf() : PP.cwleaf(), row) = cw;
 }
 
-// DCF Gen for [x < alpha] over nbits (Z_2 values), this lane's party b: the
-// tree over the nu = nbits - 7 high bits, then the 128-bit leaf correction
-// word (bit j = bit j of G_C(s_0) ^ G_C(s_1), ^ [j < alpha mod 128], ^ V_alpha).
-// `wrap` is the party's wrap share, stored in vcw bit 31.
-__device__ __forceinline__ void dcf_gen(uint8_t* k, uint64_t np, uint64_t row, uint32_t nbits, uint32_t alpha,
-                                        uint32_t b, uint4 s, uint32_t wrap, const uint32_t* tab, LaneOff loff) {
-    const DcfPlanes P{np, nbits - 7};
-    at_w<uint4>(k, P.root(), row) = s;
-    uint32_t t = b, va = 0, tlw = 0, trw = 0, vw = 0;
-    for (uint32_t i = 0; i < P.nu; i++) {
-        const uint32_t a = (alpha >> (nbits - 1 - i)) & 1u;
-        uint4 wl, wr;
-        prg_pair(s, tab, loff, wl, wr);
-        const uint4 keep = clear_tv(sel4(a, wr, wl));
-        const uint4 lose = clear_tv(sel4(a, wl, wr));
-        // bit 0: t^L, 1: t^R, 2: v^L, 3: v^R of this party; XOR with the partner's
-        const uint32_t bits = (wl.x & 1u) | ((wr.x & 1u) << 1) | ((wl.x & 2u) << 1) | ((wr.x & 2u) << 2);
-        const uint32_t both = bits ^ partner(bits);
-        const uint4 scw = xor4(lose, partner4(lose));
-        const uint32_t vlose = sel(a, both >> 2, both >> 3) & 1u;
-        const uint32_t vkeep = sel(a, both >> 3, both >> 2) & 1u;
-        const uint32_t vcw = vlose ^ va ^ a;
-        va = va ^ vkeep ^ vcw;
-        const uint32_t tlcw = (both ^ a ^ 1u) & 1u;
-        const uint32_t trcw = ((both >> 1) ^ a) & 1u;
-        const uint32_t tkcw = sel(a, trcw, tlcw);
-        const uint32_t tk = (sel(a, wr.x, wl.x)) & 1u;
-        s = xor4(keep, and4(scw, 0u - t));
-        t = tk ^ (t & tkcw);
-        at_w<uint4>(k, P.scw(i), row) = scw;
-        tlw |= tlcw << i;
-        trw |= trcw << i;
-        vw |= vcw << i;
-    }
-    const uint4 g = prg(s, 2u, tab, loff);
-    uint4 cw = xor4(g, partner4(g));
-    // [j < low] for j = 0..127 as a 128-bit mask, flipped when V_alpha = 1
-    const uint32_t low = alpha & 127u;
-    const uint32_t flip = 0u - va;
-    const uint32_t m0 = low >= 32 ? ~0u : (1u << low) - 1u;
-    const uint32_t m1 = low >= 64 ? ~0u : (low <= 32 ? 0u : (1u << (low - 32)) - 1u);
-    const uint32_t m2 = low >= 96 ? ~0u : (low <= 64 ? 0u : (1u << (low - 64)) - 1u);
-    const uint32_t m3 = low <= 96 ? 0u : (1u << (low - 96)) - 1u;
-    cw = xor4(cw, make_uint4(m0 ^ flip, m1 ^ flip, m2 ^ flip, m3 ^ flip));
-    at_w<uint32_t>(k, P.tl(), row) = tlw;
-    at_w<uint32_t>(k, P.tr(), row) = trw;
-    at_w<uint32_t>(k, P.vcw(), row) = vw | (wrap << 31);
-    at_w<uint4>(k, P.cwleaf(), row) = cw;
+// Roots of one tree: the even lane draws the block of s_0 (generator block
+// j), the odd lane that of delta (block j + 1); the partner exchange gives both
+// lanes both.  s_0 keeps bit 1 clear, delta has bit 0 set and bit 1 clear,
+// and party b's root is s_0 ^ b * delta.
+__device__ __forceinline__ void tree_roots(const DealerArgs& A, uint32_t j, uint32_t e, uint32_t b, uint4& s,
+                                           uint4& delta, const uint32_t* tab, LaneOff loff) {
+    uint4 mine = rng_block(A.rk, 3, j + b, A.query, A.pred, e, tab, loff);
+    pin_in_vgprs(mine);
+    const uint4 other = partner4(mine);
+    uint4 s0 = b ? other : mine;
+    delta = b ? mine : other;
+    s0.x &= ~2u;
+    delta.x = (delta.x & ~2u) | 1u;
+    s = b ? xor4(s0, delta) : s0;
 }
 
 // Both lanes of row `row`'s pair (b = party of this lane); KIND is the key kind.
@@ -383,21 +371,18 @@ __device__ __forceinline__ void keygen_row(const DealerArgs& A, uint64_t row, ui
     const uint32_t r = A.r[row];
     const uint32_t e = (uint32_t)row + A.row_offset;
     uint8_t* key = b ? A.key1 : A.key0;
-    uint4 s = clear_tv(rng_block(A.rk, 3, b, A.query, A.pred, e, tab, loff));
-    pin_in_vgprs(s);
+    uint4 s, delta;
+    tree_roots(A, 0, e, b, s, delta, tab, loff);
     if (KIND == FSS_EQ) {
-        dpf_gen(key, np, row, A.nbits, (A.a_or_lo + r) & mask, b, s, tab, loff);
+        tree_gen<false>(key, np, row, A.nbits, (A.a_or_lo + r) & mask, s, delta, 0u, tab, loff);
     } else {
         const uint32_t U = (A.hi + r) & mask, L = (A.a_or_lo + r) & mask;
         uint32_t c0 = rng_block(A.rk, 3, 2, A.query, A.pred, e, tab, loff).x & 1u;
         pin_in_vgprs(c0);
         const uint32_t cb = c0 ^ (b & (L > U ? 1u : 0u));
-        // all three root blocks are drawn before the first tree walk, so that
-        // nothing of their AES work stays live across it
-        uint4 sl = clear_tv(rng_block(A.rk, 3, 3 + b, A.query, A.pred, e, tab, loff));
-        pin_in_vgprs(sl);
-        dcf_gen(key, np, row, A.nbits, U, b, s, cb, tab, loff);
-        dcf_gen(key + DcfPlanes{np, A.nbits - 7}.bytes(), np, row, A.nbits, L, b, sl, 0u, tab, loff);
+        tree_gen<true>(key, np, row, A.nbits, U, s, delta, cb, tab, loff);
+        tree_roots(A, 3, e, b, s, delta, tab, loff);
+        tree_gen<true>(key + DcfPlanes{np, A.nbits - 7}.bytes(), np, row, A.nbits, L, s, delta, 0u, tab, loff);
     }
 }
 
@@ -578,9 +563,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(const uint8_t* key, uint
     uint32_t bit = 0;
     if (x < npoints) {
         if (kind == FSS_EQ)
-            bit = dpf_eval(key, np, row, nbits, party, (uint32_t)x, tab, loff);
+            bit = dpf_eval(key, np, row, nbits, (uint32_t)x, tab, loff);
         else
-            bit = range_eval(key, np, row, nbits, party, (uint32_t)x, tab, loff);
+            bit = range_eval(key, np, row, nbits, (uint32_t)x, tab, loff);
     }
     const uint64_t ballot = __ballot(bit);
     if ((threadIdx.x & 63u) == 0) {
@@ -623,9 +608,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_points_batch(EvalAllBatch B) {
     uint32_t bit = 0;
     if (x < R.npoints) {
         if (R.kind == FSS_EQ)
-            bit = dpf_eval(R.key, np, R.row, R.nbits, R.party, (uint32_t)x, tab, loff);
+            bit = dpf_eval(R.key, np, R.row, R.nbits, (uint32_t)x, tab, loff);
         else
-            bit = range_eval(R.key, np, R.row, R.nbits, R.party, (uint32_t)x, tab, loff);
+            bit = range_eval(R.key, np, R.row, R.nbits, (uint32_t)x, tab, loff);
     }
     const uint64_t ballot = __ballot(bit);
     if ((threadIdx.x & 63u) == 0) {
@@ -858,8 +843,9 @@ bool valid_nbits(uint32_t nbits) { return nbits >= 8 && nbits <= 32; }
 
 uint64_t key_bytes(int32_t kind, uint32_t nbits) {
     if (!valid_nbits(nbits)) return 0;
-    if (kind == FSS_EQ) return 16ull * nbits - 72;
-    if (kind == FSS_RANGE) return 2ull * (16ull * nbits - 68);
+    const uint64_t tree = 16ull * (nbits - 5);     // root, nbits - 7 correction words, leaf word
+    if (kind == FSS_EQ) return tree;
+    if (kind == FSS_RANGE) return 2 * (tree + 4);  // two DCFs, each with its VCW word
     return 0;
 }
 

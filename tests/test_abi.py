@@ -32,13 +32,13 @@ def test_every_declared_symbol_is_exported(fss):
 
 
 def test_key_sizes(fss):
-    assert fss.fss_key_bytes(fss.EQ, 32) == 440
-    assert fss.fss_key_bytes(fss.RANGE, 32) == 888
-    assert fss.fss_key_bytes(fss.EQ, 8) == 16 * 8 - 72
-    assert fss.fss_key_bytes(fss.RANGE, 12) == 2 * (16 * 12 - 68)
+    assert fss.fss_key_bytes(fss.EQ, 32) == 432
+    assert fss.fss_key_bytes(fss.RANGE, 32) == 872
+    assert fss.fss_key_bytes(fss.EQ, 8) == 16 * (8 - 5)
+    assert fss.fss_key_bytes(fss.RANGE, 12) == 2 * (16 * (12 - 5) + 4)
     assert fss.fss_key_bytes(fss.EQ, 7) == 0 and fss.fss_key_bytes(fss.RANGE, 33) == 0
     assert fss.fss_key_bytes(5, 32) == 0
-    assert fss.fss_keybatch_bytes(fss.RANGE, 32, 65) == 888 * 128
+    assert fss.fss_keybatch_bytes(fss.RANGE, 32, 65) == 872 * 128
     assert fss.fss_keybatch_bytes(fss.EQ, 32, 0) == 0
 
 

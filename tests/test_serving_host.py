@@ -49,7 +49,7 @@ class FakeArena:
 
 def _fake_fss(log):
     f = types.SimpleNamespace(EQ=0, RANGE=1)
-    f.fss_keybatch_bytes = lambda kind, nb, n: n * (440 if kind == 0 else 888)
+    f.fss_keybatch_bytes = lambda kind, nb, n: n * (432 if kind == 0 else 872)
     f.KeyBatch = types.SimpleNamespace(view=lambda kind, nb, n, p0, p1: (kind, n))
     f.Queue = lambda cap, dev: types.SimpleNamespace(capacity=cap)
     f.fss_keygen_batch = lambda kg, q, s: log.append(("keygen", [k[1] for k in kg]))
@@ -108,7 +108,7 @@ def test_memory_bound_admission_completes_in_order(fake):
 @pytest.mark.timeout(30)
 def test_continuous_batching_mixes_arrivals(fake):
     reqs = _reqs([0.0, 0.0, 0.0, 0.02, 0.02, 0.05])
-    arena = 8 * 1000 * 888     # both parties' keys of about four chunks
+    arena = 8 * 1000 * 872     # both parties' keys of about four chunks
     path = serving.ServedPath(None, budget_bytes=1 << 30, key_arena_bytes=arena, chunk_rows=512,
                               device="cpu", stream=object())
     _run(path, reqs)
@@ -168,7 +168,7 @@ def test_resident_edge_prefix_is_the_candidate_view(monkeypatch):
 def test_wave_cap_splits_work(fake):
     """A wave never holds more keys than wave_bytes (beyond its first chunk)."""
     reqs = _reqs([0.0] * 4, rows=4096)
-    chunk_keys = 2 * 512 * 888
+    chunk_keys = 2 * 512 * 872
     path = serving.ServedPath(None, budget_bytes=1 << 30, key_arena_bytes=64 << 20, chunk_rows=512,
                               device="cpu", stream=object(), wave_bytes=3 * chunk_keys)
     sizes = []
