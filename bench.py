@@ -1,20 +1,24 @@
 """Benchmark of the FSS hot path on one MI355X.
 
-Workload: vertex filtering at scale -- 2^22 rows x 4 uint32 attributes (two
-labels uniform in [0,64), two Zipf(1.1) integers over [0,2^32)), one query
-with 2 equality predicates (DPF) and 2 range predicates (2 DCF each), evaluated
-over all rows for both simulated parties, and the 4 shared bits ANDed into one
-match bit per vertex.
+Default workload (the headline line): the full path query over a power-law
+graph -- Chung-Lu (exponent 2.1), 2^22 vertices x 4 uint32 attributes (two
+labels uniform in [0,64), two Zipf(1.1) integers over [0,2^32)), 2^25 edges
+with a label uniform in [0,4) and a weight uniform in [0,2^16).  Query a->b->c
+with 4 vertex predicates (2 equality, 2 range) and 2 edge predicates (1 and 1),
+evaluated by both simulated parties: filter -> shared edge join -> shared
+result bits over every edge.
 
-One step is the whole path over that batch: for each predicate the dealer's
-key generation and the masked open, then match_query (one
-k_eval launch over all predicates and both parties, three Beaver ANDs).  The
-reported value counts DPF and DCF tree walks of both parties (a range is two
-DCF walks) per second of step time, keygen included.
+One step is the whole path over that graph: for each predicate the masked
+open and the dealer's key generation, then one persistent evaluation launch
+over all predicates and both parties, then match_query on the share bits (the
+ANDs of each vertex and edge fold and both hop joins).  The reported value
+counts DPF and DCF tree walks of both parties (a range is two DCF walks) per
+second of step time, keygen included.
 
-Extra fields: the per-kernel durations (HIP events on the launch stream), the
-roofline of the dominant kernel, the oracle timed on a bounded prefix sample
-of the same table (which is also checked bit for bit against the GPU shares).
+Extra fields: per-kernel durations (HIP events on the launch stream), the
+roofline of the dominant kernel, the oracle timed on a bounded sample of edge
+rows (checked bit for bit against the GPU shares at those rows), the vertex
+filter over 2^22 rows, and a bounded served-vs-plain block.
 """
 from __future__ import annotations
 
@@ -41,38 +45,35 @@ CUS, CLOCK_HZ = 256, 2.4e9
 HBM_BYTES_PER_S = 8e12                  # MI355X HBM3E, published
 VALU_PER_CLK, LDS_PER_CLK = 64, 32
 PEAK_INT_TOPS = CUS * VALU_PER_CLK * CLOCK_HZ / 1e12
-# (VALU lane-ops, LDS table reads) of one AES-128 block in this design: 9 full
-# rounds of 4 columns x (4 byte-select perms, 4 reads, 2 xor3, 1 rotate), a last
-# round of 4 x (4 perms, 4 reads, 2 perms, 1 xor3), 4 XORs of the first round key
-# and 4 of the Matyas-Meyer-Oseas feed-forward.
-AES_SINGLE = (9 * 4 * 7 + 4 * 7 + 4 + 4, 10 * 16)
-# Both children G_0(s), G_1(s) of one seed: their inputs differ in byte 0 only,
-# so they share the first round-key XOR, three columns of round 1 (column 0
-# takes one extra read, costs 10 ops instead of 2 x 7) and three of the four
-# terms of every round-2 column (the right child's round 2 is 4 reads, 12 ops);
-# the right child's feed-forward input costs one op.
-AES_PAIR = (2 * AES_SINGLE[0] - 4 - (21 + 4) - 16 + 1, 2 * AES_SINGLE[1] - 15 - 12)
+# (VALU lane-ops, LDS table reads) of one tree hash H(s) = AES(sigma(s)) ^
+# sigma(s) in this design: 9 full rounds of 4 columns x (4 byte-select perms,
+# 4 reads, 2 xor3, 1 rotate), a last round of 4 x (4 perms, 4 reads, 2 perms,
+# 1 xor3), 4 XORs of the first round key, 4 of the feed-forward and 2 for sigma.
+AES_SINGLE = (9 * 4 * 7 + 4 * 7 + 4 + 4 + 2, 10 * 16)
 # VALU lane-ops of one ChaCha12 block (64 bytes): 12 rounds of 4 quarter rounds
 # of 4 adds, 4 xors and 4 rotates, and the 16 adds of the feed-forward.  The
 # shuffle's tables and permutation keys are ChaCha12 output.
 CHACHA_OPS = 12 * 4 * 12 + 16
-# AES work per table row: (single blocks, sibling pairs); eval walks one child
-# per level per party, the dealer expands both children for both parties.
+NU = NBITS - 7                          # tree levels above the 128-bit leaf
+# AES blocks per table row, both parties.  Eval: one hash per level and one
+# leaf hash per walk (a range is two walks).  Dealer (one lane per party):
+# roots (one block per lane per tree, one more for the range's wrap share),
+# one hash per level and one leaf hash per tree.
 AES_WORK = {
-    "eval_eq": (2 * (NBITS - 7 + 1), 0),
-    "eval_range": (2 * 2 * (NBITS - 7 + 1), 0),
-    "keygen_eq": (4, 2 * (NBITS - 7)),
-    "keygen_range": (5 + 4, 2 * 2 * (NBITS - 7)),
+    "eval_eq": 2 * (NU + 1),
+    "eval_range": 2 * 2 * (NU + 1),
+    "keygen_eq": 2 * (1 + NU + 1),
+    "keygen_range": 2 * (3 + 2 * (NU + 1)),
 }
 
 
-def aes_floor(singles: float, pairs: float) -> dict:
-    """Issue-bound time of that much AES work on the whole chip."""
-    valu = singles * AES_SINGLE[0] + pairs * AES_PAIR[0]
-    lds = singles * AES_SINGLE[1] + pairs * AES_PAIR[1]
+def aes_floor(blocks: float) -> dict:
+    """Issue-bound time of that many AES blocks on the whole chip."""
+    valu = blocks * AES_SINGLE[0]
+    lds = blocks * AES_SINGLE[1]
     t_valu = valu / VALU_PER_CLK / CUS / CLOCK_HZ
     t_lds = lds / LDS_PER_CLK / CUS / CLOCK_HZ
-    return {"blocks": singles + 2 * pairs, "valu_ops": valu, "lds_reads": lds, "t_valu": t_valu, "t_lds": t_lds,
+    return {"blocks": blocks, "valu_ops": valu, "lds_reads": lds, "t_valu": t_valu, "t_lds": t_lds,
             "t_floor": max(t_valu, t_lds), "binding": "lds" if t_lds >= t_valu else "valu"}
 
 
@@ -81,10 +82,13 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of every source and header the library is built from."""
     import hashlib
+
+    from paper_2209_03526_amd import build as hip_build
     h = hashlib.sha256()
-    for f in ("paper_2209_03526_amd/csrc/fss_lib.hip", "paper_2209_03526_amd/csrc/aes_gfx950.hpp"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in [*hip_build.SRCS, *hip_build.HEADERS]:
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -113,16 +117,18 @@ def measured_traffic(kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--log-rows", type=int, default=LOG_ROWS)
-    ap.add_argument("--cpu-sample-log-rows", type=int, default=19)
+    ap.add_argument("--cpu-sample-rows", type=int, default=65536,
+                    help="full: edge rows the oracle computes for the CPU baseline (bit-checked vs the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay of the step")
-    ap.add_argument("--workload", default="vertex-filter", choices=["vertex-filter", "full", "batch64", "serve", "next"])
+    ap.add_argument("--no-vertex-filter", action="store_true", help="full: skip the 2^22-row vertex filter key")
+    ap.add_argument("--serve-block", action="store_true", help="full: add the bounded served-vs-plain block")
+    ap.add_argument("--graph", action="store_true", help="full: also replay the step as one hipGraph")
+    ap.add_argument("--log-rows", type=int, default=LOG_ROWS, help="vertex-filter: rows (log2)")
+    ap.add_argument("--workload", default="full", choices=["full", "vertex-filter", "batch64", "serve", "next"])
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates (queries/s)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0, help="serve: arrival window per rate")
-    ap.add_argument("--serve-max", type=int, default=600, help="serve: at most this many requests per rate")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="serve: arrival window per rate")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="batch64: key memory budget of the batched runner")
     ap.add_argument("--wave-gb", type=float, default=0.0,
                     help="serve: cap on the keys of one wave (0: a wave may fill the 48 GB key arena)")
@@ -143,16 +149,230 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of 1 GiB done")
     if args.workload == "batch64":
         return run_batch64(args, torch, fss, dev)
     if args.workload == "serve":
         return run_serve(args, torch, fss, dev)
     if args.workload == "next":
         return run_next(args, torch, fss, dev)
-    if args.workload == "full":
-        return run_full(args, torch, fss, dev)
+    if args.workload == "vertex-filter":
+        out = run_vertex_filter(args, torch, fss, dev, args.steps, args.warmup)
+        print(json.dumps(out), flush=True)
+        return
+    out = run_full(args, torch, fss, dev)
+    if not args.no_vertex_filter:
+        vf = run_vertex_filter(args, torch, fss, dev, 3, 1)
+        out["vertex_filter_2p22"] = {k: vf[k] for k in ("value", "unit", "ms_per_step", "eval_only_evals_per_s",
+                                                         "kernels", "config")}
+    if args.serve_block:
+        out["serving"] = serve_block(args, torch, fss, dev)
+    print(json.dumps(out), flush=True)
+
+
+class Timer:
+    """HIP events around launches on one stream, grouped by name."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.ev = torch, stream, {}
+
+    def __call__(self, name, fn, record=True):
+        if not record:
+            return fn()
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        r = fn()
+        e1.record(self.stream)
+        self.ev.setdefault(name, []).append((e0, e1))
+        return r
+
+    def ms(self, name):
+        """Mean duration of one call of `name` and the number of calls per step."""
+        return float(np.mean([a.elapsed_time(b) for a, b in self.ev[name]]))
+
+
+def kernel_row(ms: float, launches: int, blocks: float, hbm_bytes: float) -> dict:
+    """One AES kernel's figures: `ms` per launch, `blocks` and `hbm_bytes` per launch."""
+    f = aes_floor(blocks)
+    t = ms / 1e3
+    return {"ms": round(ms, 4), "launches_per_step": launches, "aes_blocks": int(blocks),
+            "aes_gblocks_per_s": round(blocks / t / 1e9, 3), "floor_gblocks_per_s": round(blocks / f["t_floor"] / 1e9, 3),
+            "binding_unit": f["binding"], "frac_of_floor": round(f["t_floor"] / t, 4),
+            "valu_frac": round(f["t_valu"] / t, 4), "lds_frac": round(f["t_lds"] / t, 4),
+            "hbm_bytes": int(hbm_bytes), "hbm_gb_per_s": round(hbm_bytes / t / 1e9, 1)}
+
+
+def roofline_of(name: str, k: dict) -> dict:
+    return {"bound": "alu", "kernel": name, "achieved": k["aes_gblocks_per_s"], "peak": k["floor_gblocks_per_s"],
+            "unit": "G AES-128 blocks/s (peak: the LDS-read issue floor of the T-table AES, 32 reads per clock "
+                    "per CU, 160 per block, 256 CUs at 2.4 GHz)",
+            "frac": k["frac_of_floor"], "traffic": measured_traffic(name), "binding_unit": k["binding_unit"],
+            "valu_frac": k["valu_frac"], "lds_frac": k["lds_frac"],
+            "aes_blocks_per_launch": k["aes_blocks"], "ms_per_launch": k["ms"]}
+
+
+def run_full(args, torch, fss, dev):
+    """The full path query a -> b -> c over the Chung-Lu graph (2^22 vertices,
+    2^25 edges), 4 vertex and 2 edge predicates, both parties (Alg. 2)."""
+    from paper_2209_03526_amd import autotune
+
+    log("generating the 2^22 / 2^25 Chung-Lu graph")
+    graph, query = synth.config3(3)
+    shares = synth.share_columns(SEED, graph.vcols)
+    shares.update({"e:" + k: v for k, v in synth.share_columns(SEED + 1, graph.ecols).items()})
+    masks = synth.pred_masks(SEED, query, graph)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
+
+    preds, walks = [], 0
+    for k, p in enumerate(query.preds):
+        on_edge = p.target >= query.n_qv
+        x0, x1 = shares[("e:" if on_edge else "") + p.column]
+        rows = graph.n_edges if on_edge else graph.n_vertices
+        kind = fss.EQ if p.kind == "eq" else fss.RANGE
+        preds.append({"p": p, "k": k, "kind": kind, "rows": rows, "table": "edges" if on_edge else "vertices",
+                      "x0": T(x0), "x1": T(x1), "r": T(masks[k]),
+                      "xhat": torch.empty(rows, dtype=torch.int32, device=dev),
+                      "kb": fss.KeyBatch(kind, NBITS, rows, dev),
+                      "bits": [torch.empty(fss.words(rows), dtype=torch.int32, device=dev) for _ in range(2)]})
+        walks += 2 * rows * (1 if p.kind == "eq" else 2)
+    evreqs = [(b, d["kb"], d["xhat"], d["bits"][b]) for d in preds for b in (0, 1)]
+    queue = fss.Queue(len(evreqs), dev)
+    plan = fss.Plan(SEED, query.query_id, query.n_qv, graph.n_vertices, graph.n_edges,
+                    [(d["p"].target, None, None, tuple(d["bits"])) for d in preds],
+                    T(graph.src), T(graph.dst)).allocate(dev)
+    key_gb = sum(2 * d["kb"].bytes_per_party for d in preds) / 1e9
+    log(f"inputs resident; keys {key_gb:.1f} GB for both parties")
+    stream = torch.cuda.current_stream()
+    tm = Timer(torch, stream)
+
+    def step(record=True):
+        for d in preds:
+            p = d["p"]
+            tm("open", lambda: fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], stream), record)
+            tm(("keygen", p.kind, d["table"]),
+               lambda: fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo, p.hi, d["r"],
+                                      d["kb"], stream), record)
+        tm("eval", lambda: fss.fss_eval_batch(evreqs, queue, stream), record)
+        tm("tail", lambda: fss.match_query(plan, 3, stream), record)
+
+    step(False)
+    torch.cuda.synchronize()
+    tuning = autotune.tune(lambda: fss.fss_eval_batch(evreqs, queue, stream), sum(d["rows"] for d in preds))
+    log(f"evaluation shape chosen: {tuning}")
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+        log(f"step {i + 1}/{args.steps}: {step_ms[-1]:.2f} ms")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    kb_eq, kb_rg = fss.fss_key_bytes(fss.EQ, NBITS), fss.fss_key_bytes(fss.RANGE, NBITS)
+    kernels = {}
+    # dealer launches: one per predicate; blocks and bytes (keys of both parties
+    # written, the mask read) per launch
+    for d in preds:
+        p = d["p"]
+        name = f"k_keygen_{p.kind}[{d['table']} 2^{int(np.log2(d['rows']))}]"
+        if name in kernels:
+            kernels[name]["launches_per_step"] += 1
+            continue
+        kb = kb_eq if p.kind == "eq" else kb_rg
+        kernels[name] = kernel_row(tm.ms(("keygen", p.kind, d["table"])), 1, AES_WORK["keygen_" + p.kind] * d["rows"],
+                                   d["rows"] * (2 * kb + 4))
+    ev_blocks = sum(AES_WORK["eval_" + d["p"].kind] * d["rows"] for d in preds)
+    ev_bytes = sum(2 * d["rows"] * ((kb_eq if d["p"].kind == "eq" else kb_rg) + 4) + 8 * fss.words(d["rows"])
+                   for d in preds)
+    kernels["k_eval_queue"] = kernel_row(tm.ms("eval"), 1, ev_blocks, ev_bytes)
+    share = {k: v["ms"] * v["launches_per_step"] for k, v in kernels.items()}
+    dom = max(share, key=share.get)
+    tail_ms = tm.ms("tail")
+    open_ms = tm.ms("open")
+    open_bytes = 16 * float(np.mean([d["rows"] for d in preds]))
+    out = {
+        "metric": "32-bit DCF/DPF evals/sec (full path query: dealer keygen + open + eval of both parties + ANDs + "
+                  "hop joins)",
+        "value": walks / (ms / 1e3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "full path query a->b->c: Chung-Lu (gamma 2.1) 2^22 vertices / 2^25 edges, "
+                               "4 vertex + 2 edge predicates, 2 parties, 32-bit domain",
+                   "evals_per_step": walks, "key_gb_both_parties": round(key_gb, 2),
+                   "eval_tuning": list(tuning)},
+        "eval_only_evals_per_s": walks / (kernels["k_eval_queue"]["ms"] / 1e3),
+        "kernels": kernels,
+        "tail": {"ms": round(tail_ms, 4), "what": "match_query on evaluated bits: 3 fold ANDs, 2 hop joins "
+                                                  "(gathers of both endpoints and 2 ANDs each)"},
+        "hbm_kernels": {"k_mask_open": {"ms": round(open_ms, 4), "launches_per_step": len(preds),
+                                        "hbm_gb_per_s": round(open_bytes / (open_ms / 1e3) / 1e9, 1),
+                                        "frac_of_hbm_peak": round(open_bytes / (open_ms / 1e3) / HBM_BYTES_PER_S, 4)}},
+        "roofline": roofline_of(dom if dom == "k_eval_queue" else dom.split("[")[0], kernels[dom]),
+        "cpu_baseline": None,
+    }
+    out["roofline"]["kernel_launch"] = dom
+    log(f"{out['value'] / 1e9:.3f} G evals/s, {ms:.2f} ms per step; dominant {dom}: {kernels[dom]}")
+    if args.graph:
+        out["graph_replay"] = graph_replay(torch, step, args.steps, walks)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_full(graph, query, shares, masks, plan, args.cpu_sample_rows)
+    del preds, evreqs, plan, queue
+    torch.cuda.empty_cache()
+    return out
+
+
+def graph_replay(torch, step, steps, walks):
+    """The step captured once into a hipGraph and replayed: the per-call
+    pipeline holds no memset, host copy or host wait, and a replay redoes the
+    same work.  A failure is reported, not raised."""
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(False)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - t1) * 1e3 / steps
+        del g
+        log(f"graph replay: {g_ms:.2f} ms per step")
+        return {"ms_per_step": g_ms, "value": walks / (g_ms / 1e3)}
+    except Exception as exc:      # noqa: BLE001 -- the eager result stands
+        log(f"graph replay failed: {exc}")
+        return {"error": f"{type(exc).__name__}: {exc}"}
+
+
+def run_vertex_filter(args, torch, fss, dev, steps, warmup):
+    """Vertex filtering: 2^log_rows rows x 4 attributes, 2 equality and 2
+    range predicates over all rows, both parties, the 4 bits ANDed into one."""
     n = 1 << args.log_rows
-    log(f"generating {n} rows")
+    log(f"vertex filter: generating {n} rows")
     graph, query = synth.config2(2, n=n)
     shares = synth.share_columns(SEED, graph.vcols)
     masks = synth.pred_masks(SEED, query, graph)
@@ -168,186 +388,50 @@ def main():
                       "xhat": torch.empty(n, dtype=torch.int32, device=dev),
                       "kb": fss.KeyBatch(kind, NBITS, n, dev)})
     plan = fss.Plan(SEED, query.query_id, 1, n, 0, [(0, d["kb"], d["xhat"]) for d in preds]).allocate(dev)
-    key_gb = sum(2 * d["kb"].bytes_per_party for d in preds) / 1e9
-    log(f"inputs resident; keys {key_gb:.1f} GB for both parties")
-
     stream = torch.cuda.current_stream()
+    tm = Timer(torch, stream)
     n_eq = sum(1 for d in preds if d["p"].kind == "eq")
     n_rg = len(preds) - n_eq
-    evals_per_step = 2 * n * (n_eq + 2 * n_rg)
+    walks = 2 * n * (n_eq + 2 * n_rg)
 
-    ev = {name: [] for name in ("open", "keygen", "match")}
-
-    def step(record, s=stream):
+    def step(record=True):
         for d in preds:
             p = d["p"]
-            if record:
-                o0 = torch.cuda.Event(enable_timing=True)
-                o1 = torch.cuda.Event(enable_timing=True)
-                o0.record(s)
-            fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], s)
-            if record:
-                o1.record(s)
-                ev["open"].append(("open", o0, o1))
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(s)
-            fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo, p.hi, d["r"], d["kb"], s)
-            if record:
-                e1.record(s)
-                ev["keygen"].append((p.kind, e0, e1))
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-        fss.match_query(plan, 3, s)
-        if record:
-            e1.record(s)
-            ev["match"].append(("all", e0, e1))
+            tm("open", lambda: fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], stream), record)
+            tm(("keygen", p.kind), lambda: fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo,
+                                                          p.hi, d["r"], d["kb"], stream), record)
+        tm("match", lambda: fss.match_query(plan, 3, stream), record)
 
-    if args.calibrate_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        log("calibration copy of 1 GiB done")
-
-    for i in range(args.warmup):
+    for _ in range(warmup):
         step(False)
         torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-
-    step_ms = []
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        s0 = time.perf_counter()
-        step(True)
+    for _ in range(steps):
+        step()
         torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - s0) * 1e3)
-        log(f"step {i + 1}/{args.steps}: {step_ms[-1]:.2f} ms")
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t0
-    ms_per_step = total_s * 1e3 / args.steps
-    value = evals_per_step / (ms_per_step / 1e3)
-
-    # The same step captured once into a hipGraph and replayed: the per-call
-    # pipeline holds no memset, host copy or host wait, and a replay redoes the
-    # same work (same seeds, same keys).  A failure is reported, not raised.
-    graph_replay = None
-    if not args.no_graph:
-        try:
-            side = torch.cuda.Stream()
-            side.wait_stream(stream)
-            with torch.cuda.stream(side):
-                step(False, side)
-            stream.wait_stream(side)
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                step(False, torch.cuda.current_stream())
-            torch.cuda.synchronize()
-            g.replay()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                g.replay()
-            torch.cuda.synchronize()
-            g_ms = (time.perf_counter() - t1) * 1e3 / args.steps
-            graph_replay = {"ms_per_step": g_ms, "value": evals_per_step / (g_ms / 1e3),
-                            "launches_per_step": 2 * len(preds) + 1}
-            log(f"graph replay: {g_ms:.2f} ms per step")
-            del g
-        except Exception as exc:      # noqa: BLE001 -- the eager result above stands
-            graph_replay = {"error": f"{type(exc).__name__}: {exc}"}
-            log(f"graph replay failed: {exc}")
-
-    # per-kernel durations from events on the launch stream
-    kg = {"eq": [], "range": []}
-    for kind, e0, e1 in ev["keygen"]:
-        kg[kind].append(e0.elapsed_time(e1))
-    match_ms = [e0.elapsed_time(e1) for _, e0, e1 in ev["match"]]
-    kg_eq_ms = float(np.mean(kg["eq"])) if kg["eq"] else 0.0
-    kg_rg_ms = float(np.mean(kg["range"])) if kg["range"] else 0.0
-    match_mean = float(np.mean(match_ms))
-    def work(key, rows):
-        singles, pairs = AES_WORK[key]
-        return aes_floor(singles * rows, pairs * rows)
-
-    ev_eq, ev_rg = work("eval_eq", n * n_eq), work("eval_range", n * n_rg)
-    eval_floor = aes_floor(0, 0)
-    for k in eval_floor:
-        if k != "binding":
-            eval_floor[k] = ev_eq[k] + ev_rg[k]
-    eval_floor["binding"] = "lds" if eval_floor["t_lds"] >= eval_floor["t_valu"] else "valu"
-    # algorithmic HBM bytes per launch: keys written (dealer) or read (eval, both
-    # parties), plus the 4-byte mask or opened value per row
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     kb_eq, kb_rg = fss.fss_key_bytes(fss.EQ, NBITS), fss.fss_key_bytes(fss.RANGE, NBITS)
     kernels = {
-        "k_keygen_range": {"ms": kg_rg_ms, "launches_per_step": n_rg, "floor": work("keygen_range", n),
-                           "hbm_bytes": n * (2 * kb_rg + 4)},
-        "k_keygen_eq": {"ms": kg_eq_ms, "launches_per_step": n_eq, "floor": work("keygen_eq", n),
-                        "hbm_bytes": n * (2 * kb_eq + 4)},
-        "match_query(k_eval+ands)": {"ms": match_mean, "launches_per_step": 1, "floor": eval_floor,
-                                     "hbm_bytes": 2 * n * (n_eq * (kb_eq + 4) + n_rg * (kb_rg + 4))},
+        "k_keygen_range": kernel_row(tm.ms(("keygen", "range")), n_rg, AES_WORK["keygen_range"] * n, n * (2 * kb_rg + 4)),
+        "k_keygen_eq": kernel_row(tm.ms(("keygen", "eq")), n_eq, AES_WORK["keygen_eq"] * n, n * (2 * kb_eq + 4)),
+        "match_query(k_eval+ands)": kernel_row(tm.ms("match"), 1,
+                                               n * (n_eq * AES_WORK["eval_eq"] + n_rg * AES_WORK["eval_range"]),
+                                               2 * n * (n_eq * (kb_eq + 4) + n_rg * (kb_rg + 4))),
     }
     share = {k: v["ms"] * v["launches_per_step"] for k, v in kernels.items()}
     dom = max(share, key=share.get)
-    for k, v in kernels.items():
-        f = v.pop("floor")
-        t = v["ms"] / 1e3
-        v["aes_blocks"] = int(f["blocks"])
-        v["aes_gblocks_per_s"] = round(f["blocks"] / t / 1e9, 3) if t else None
-        v["floor_gblocks_per_s"] = round(f["blocks"] / f["t_floor"] / 1e9, 3)
-        v["binding_unit"] = f["binding"]
-        v["frac_of_floor"] = round(f["t_floor"] / t, 4) if t else None
-        v["valu_frac"] = round(f["t_valu"] / t, 4) if t else None
-        v["lds_frac"] = round(f["t_lds"] / t, 4) if t else None
-        v["hbm_gb_per_s"] = round(v["hbm_bytes"] / t / 1e9, 1) if t else None
-    dk = kernels[dom]
-    roofline = {"bound": "alu", "kernel": dom, "achieved": dk["aes_gblocks_per_s"],
-                "peak": dk["floor_gblocks_per_s"],
-                "unit": "G AES-128 blocks/s (peak: VALU and LDS-read issue floor, 256 CUs at 2.4 GHz)",
-                "frac": dk["frac_of_floor"], "traffic": measured_traffic(dom),
-                "binding_unit": dk["binding_unit"], "valu_frac": dk["valu_frac"], "lds_frac": dk["lds_frac"]}
-    eval_evals_per_s = evals_per_step / (match_mean / 1e3)
-    # the open (x0 + x1 + r, HBM stream): 12 bytes read and 4 written per row
-    open_ms = float(np.mean([e0.elapsed_time(e1) for _, e0, e1 in ev["open"]]))
-    hbm_kernels = {"k_mask_open": {"ms": open_ms, "launches_per_step": len(preds), "hbm_bytes": 16 * n,
-                                   "hbm_gb_per_s": round(16 * n / (open_ms / 1e3) / 1e9, 1),
-                                   "frac_of_hbm_peak": round(16 * n / (open_ms / 1e3) / HBM_BYTES_PER_S, 4)}}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(fss, graph, query, shares, masks, plan, args.cpu_sample_log_rows, evals_per_step / n)
-
-    out = {
-        "metric": "32-bit DCF/DPF evals/sec (whole step: dealer keygen + open + eval of both parties + AND)",
-        "value": value,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "p50_step_ms": float(np.percentile(step_ms, 50)),
-        "p99_step_ms": float(np.percentile(step_ms, 99)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"vertex filtering: 2^{args.log_rows} rows x 4 uint32 attrs, 2 eq + 2 range "
-                               "predicates, 2 parties, 32-bit domain", "rows": n,
-                   "evals_per_step": evals_per_step, "key_gb_both_parties": round(key_gb, 2)},
-        "eval_only_evals_per_s": eval_evals_per_s,
-        "kernels": kernels,
-        "hbm_kernels": hbm_kernels,
-        "graph_replay": graph_replay,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    out = {"metric": "32-bit DCF/DPF evals/sec (vertex filter: dealer keygen + open + eval of both parties + AND)",
+           "value": walks / (ms / 1e3), "unit": "evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": f"vertex filtering: 2^{args.log_rows} rows x 4 uint32 attrs, 2 eq + 2 range "
+                                  "predicates, 2 parties, 32-bit domain", "rows": n, "evals_per_step": walks},
+           "eval_only_evals_per_s": walks / (kernels["match_query(k_eval+ands)"]["ms"] / 1e3),
+           "kernels": kernels, "roofline": roofline_of(dom, kernels[dom]), "cpu_baseline": None}
+    log(f"vertex filter: {out['value'] / 1e9:.3f} G evals/s, {ms:.2f} ms per step")
+    del preds, plan
+    torch.cuda.empty_cache()
+    return out
 
 
 def batch_graph_replay(torch, runner, jobs, plain_out, outputs):
@@ -482,18 +566,15 @@ def run_batch64(args, torch, fss, dev):
     runner.run(jobs, timings)
     torch.cuda.synchronize()
     t_kind = {k: sum(a.elapsed_time(b) for kk, a, b in timings if kk == k) / 1e3 for k in ("keygen", "eval")}
-    singles = {"keygen": 0, "eval": 0}
-    pairs = {"keygen": 0, "eval": 0}
+    blocks = {"keygen": 0, "eval": 0}
     for j in jobs:
         for p in j.preds:
             kind = "eq" if p["kind"] == fss.EQ else "range"
-            s1, p1 = AES_WORK["keygen_" + kind]
-            singles["keygen"] += s1 * p["rows"]
-            pairs["keygen"] += p1 * p["rows"]
-            singles["eval"] += AES_WORK["eval_" + kind][0] * p["rows"]
+            blocks["keygen"] += AES_WORK["keygen_" + kind] * p["rows"]
+            blocks["eval"] += AES_WORK["eval_" + kind] * p["rows"]
     persistent = {}
     for k in ("keygen", "eval"):
-        f = aes_floor(singles[k], pairs[k])
+        f = aes_floor(blocks[k])
         persistent["k_" + k + "_queue"] = {
             "ms_total": round(t_kind[k] * 1e3, 3), "aes_gblocks_per_s": round(f["blocks"] / t_kind[k] / 1e9, 3),
             "floor_gblocks_per_s": round(f["blocks"] / f["t_floor"] / 1e9, 3),
@@ -597,68 +678,6 @@ def run_serve(args, torch, fss, dev):
     print(json.dumps(out), flush=True)
 
 
-def run_full(args, torch, fss, dev):
-    """The full path query over the Chung-Lu graph (2^22 vertices, 2^25 edges):
-    a -> b -> c with 4 vertex and 2 edge predicates.  A step is the dealer
-    keygen and the open of every predicate, then match_query: both parties'
-    evaluation of all predicates, the ANDs and both hop joins."""
-    log("generating the 2^22 / 2^25 Chung-Lu graph")
-    graph, query = synth.config3(3)
-    shares = synth.share_columns(SEED, graph.vcols)
-    shares.update({"e:" + k: v for k, v in synth.share_columns(SEED + 1, graph.ecols).items()})
-    masks = synth.pred_masks(SEED, query, graph)
-
-    def T(a):
-        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
-
-    preds, walks = [], 0
-    for k, p in enumerate(query.preds):
-        on_edge = p.target >= query.n_qv
-        x0, x1 = shares[("e:" if on_edge else "") + p.column]
-        rows = graph.n_edges if on_edge else graph.n_vertices
-        kind = fss.EQ if p.kind == "eq" else fss.RANGE
-        preds.append({"p": p, "k": k, "x0": T(x0), "x1": T(x1), "r": T(masks[k]),
-                      "xhat": torch.empty(rows, dtype=torch.int32, device=dev),
-                      "kb": fss.KeyBatch(kind, NBITS, rows, dev)})
-        walks += 2 * rows * (1 if p.kind == "eq" else 2)
-    plan = fss.Plan(SEED, query.query_id, query.n_qv, graph.n_vertices, graph.n_edges,
-                    [(d["p"].target, d["kb"], d["xhat"]) for d in preds], T(graph.src), T(graph.dst)).allocate(dev)
-    key_gb = sum(2 * d["kb"].bytes_per_party for d in preds) / 1e9
-    log(f"inputs resident; keys {key_gb:.1f} GB for both parties")
-    stream = torch.cuda.current_stream()
-
-    def step():
-        for d in preds:
-            p = d["p"]
-            fss.fss_mask_open(d["x0"], d["x1"], d["r"], d["xhat"], stream)
-            fss.fss_keygen(SEED, query.query_id, d["k"], p.a if p.kind == "eq" else p.lo, p.hi, d["r"], d["kb"],
-                           stream)
-        fss.match_query(plan, 3, stream)
-
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    step_ms = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - s0) * 1e3)
-        log(f"step {i + 1}/{args.steps}: {step_ms[-1]:.2f} ms")
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    out = {"metric": "32-bit DCF/DPF evals/sec (full path query: dealer keygen + open + eval of both parties + "
-                     "ANDs + hop joins)",
-           "value": walks / (ms / 1e3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms, "p50_step_ms": float(np.percentile(step_ms, 50)), "higher_is_better": True,
-           "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "full path query a->b->c: Chung-Lu 2^22 vertices / 2^25 edges, 4 vertex + 2 edge "
-                                  "predicates, 2 parties, 32-bit domain", "evals_per_step": walks,
-                      "key_gb_both_parties": round(key_gb, 2)}}
-    print(json.dumps(out), flush=True)
-
-
 def run_next(args, torch, fss, dev):
     """The rows built beyond the hot path, each timed alone with HIP events on
     the launch stream (median of 5 after one warm-up) against its floor: the
@@ -688,7 +707,7 @@ def run_next(args, torch, fss, dev):
     def row(name, ms, hbm_bytes, aes_blocks, what, chacha_blocks=0):
         t = ms / 1e3
         t_hbm = hbm_bytes / HBM_BYTES_PER_S
-        t_aes = aes_floor(aes_blocks, 0)["t_floor"]
+        t_aes = aes_floor(aes_blocks)["t_floor"]
         t_cc = chacha_blocks * CHACHA_OPS / (PEAK_INT_TOPS * 1e12)
         floors = {"hbm": t_hbm, "aes": t_aes, "chacha": t_cc}
         binding = max(floors, key=floors.get)
@@ -874,38 +893,49 @@ def _omp_threads(n: int):
     ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
 
 
-def cpu_baseline(fss, graph, query, shares, masks, plan, log_sample, evals_per_row):
-    """The oracle, as it stands, on the first 2^log_sample rows of the same
-    table and query (same seeds, so the result is the prefix of the GPU's),
-    with all the host's threads, and on a 16x smaller prefix with one."""
+def cpu_baseline_full(graph, query, shares, masks, plan, nsample):
+    """The oracle, as it stands, on a seeded sample of edge rows of the same
+    graph, query and seeds: per sampled row both parties' keys and walks of
+    every predicate the row's two hops need (source and destination vertex
+    folds, the edge fold), the triple words and the ANDs.  Its shares are
+    compared bit for bit with the GPU's at those rows.  All the host's
+    threads, then one thread on an eighth of the sample."""
+    from oracle import fss as ofss
     from oracle import match as omatch
 
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(SEED)
+    ne = graph.n_edges
+    rows = np.unique(np.concatenate([[0, 1, 31, 32, ne - 2, ne - 1], rng.integers(0, ne, nsample)])).astype(np.int64)
+    w = {"eq": 1, "range": 2}
+    per_target = [sum(w[p.kind] for p in query.preds if p.target == t) for t in range(2 * query.n_qv - 1)]
+    walks_per_row = 2 * sum(per_target[j] + per_target[j + 1] + per_target[query.n_qv + j]
+                            for j in range(query.n_qv - 1))
 
-    def timed(m, nthreads):
-        sub = synth.Graph(m, graph.src, graph.dst, {k: v[:m] for k, v in graph.vcols.items()}, {})
-        sub_sh = {k: (v[0][:m], v[1][:m]) for k, v in shares.items()}
+    def timed(sample, nthreads):
         _omp_threads(nthreads)
-        log(f"cpu baseline: oracle on {m} rows with {nthreads} threads")
+        log(f"cpu baseline: oracle on {sample.size} edge rows with {nthreads} threads")
         t0 = time.perf_counter()
-        want = omatch.run_plan(NBITS, SEED, sub, query, sub_sh, [r[:m] for r in masks])
+        want = omatch.sampled_outputs(NBITS, SEED, graph, query, shares, masks, sample)
         return time.perf_counter() - t0, want
 
-    m = min(1 << log_sample, graph.n_vertices)
-    dt, want = timed(m, threads)
-    w = m // 32        # whole words only
-    got0 = plan.out[0].cpu().numpy().view(np.uint32)[:w]
-    got1 = plan.out[1].cpu().numpy().view(np.uint32)[:w]
-    match = bool(np.array_equal(got0, want[0][0][:w]) and np.array_equal(got1, want[0][1][:w]))
-    log(f"cpu baseline: {dt:.1f} s, prefix shares bit-exact vs GPU: {match}")
-    m1 = max(64, m // 16)
-    dt1, _ = timed(m1, 1)
+    dt, want = timed(rows, threads)
+    we = (ne + 31) // 32
+    exact = True
+    for j in range(query.n_qv - 1):
+        for b in range(2):
+            got = plan.out[b][j * we:(j + 1) * we].cpu().numpy().view(np.uint32)
+            exact &= bool(np.array_equal(ofss.unpack_bits(got, ne)[rows], want[j, b]))
+    log(f"cpu baseline: {dt:.1f} s, sampled shares bit-exact vs GPU: {exact}")
+    small = rows[: max(64, rows.size // 8)]
+    dt1, _ = timed(small, 1)
     _omp_threads(threads)
-    log(f"cpu baseline, one thread: {dt1:.1f} s")
-    return {"value": evals_per_row * m / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {m} of the rows, same query/seeds: keygen + open + eval both parties + AND",
-            "seconds": dt, "prefix_bit_exact_vs_gpu": match, "cpu": _cpu_model(),
-            "one_core": {"value": evals_per_row * m1 / dt1, "rows": m1, "seconds": dt1}}
+    return {"value": walks_per_row * rows.size / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows.size} seeded edge rows of the same graph/query/seeds: per row the keygen, open and "
+                      f"both parties' walks of every predicate its two hops need ({walks_per_row} walks), "
+                      "triples and ANDs",
+            "seconds": round(dt, 3), "sampled_bit_exact_vs_gpu": exact, "cpu": _cpu_model(),
+            "one_core": {"value": walks_per_row * small.size / dt1, "rows": int(small.size), "seconds": round(dt1, 3)}}
 
 
 if __name__ == "__main__":

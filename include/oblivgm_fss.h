@@ -185,9 +185,26 @@ int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, co
  *      takes no number.
  * Output d_out[b] (party b): n_qv == 1 -> m_0, ceil(n_vertices/32) words;
  * else h_0 .. h_{n_qv-2}, each ceil(n_edges/32) words, hop after hop.
- * Workspace: match_workspace_bytes(plan) bytes of device memory, 256-aligned.
- * party_mask must be 3 (both parties simulated); a single party's half of a
- * deployment uses fss_eval_* and ss_and directly.
+ * Workspace: match_workspace_bytes(plan) bytes of device memory, 256-aligned;
+ * the library lays it out the same way on every call with the same plan.
+ *
+ * party_mask 3: both simulated parties at once (every AND opens, exchanges
+ * and closes in one pass).
+ * party_mask 1 / 2: ONE server's half (party 0 / party 1), run in rounds with
+ * the peer.  An AND of level L (step L of a fold; a hop's ANDs come after the
+ * folds they read) opens in round L - 1 and closes in round L.
+ * match_rounds() gives the number of exchange rounds R and the size of each
+ * round's message.  Round r (plan->round = r, r = 0 .. R):
+ *   r == 0: evaluates this party's predicate bits (only key[party] is read);
+ *   r  > 0: closes the ANDs of level r with the peer's message of round r - 1
+ *           (plan->d_peer_msg: d' || e' of each AND, AND-number order);
+ *   r  < R: writes this party's message of round r (plan->d_msg, msg_words[r]
+ *           words: d_b || e_b of each AND of level r + 1, AND-number order);
+ *   outputs are complete in d_out[party] after round R.
+ * The caller carries each message to the peer between calls (both parties'
+ * calls for round r may run in any order).  The result shares are
+ * bit-identical to those of party_mask 3.  Errors: EINVAL for a round beyond
+ * R, a missing d_peer_msg (r > 0) or d_msg (r < R).
  */
 #define FSS_MAX_QV 8
 #define FSS_MAX_PREDS 32
@@ -217,9 +234,17 @@ typedef struct match_plan {
     uint32_t* d_out[2];
     void* d_workspace;
     uint64_t workspace_bytes;
+    /* single-party runs (party_mask 1 or 2) only: */
+    uint32_t round;                 /* round to run, 0 .. R */
+    uint32_t reserved2;
+    const uint32_t* d_peer_msg;     /* the peer's message of round - 1 */
+    uint32_t* d_msg;                /* this party's message of round */
 } match_plan;
 
 uint64_t match_workspace_bytes(const match_plan* plan);
+/* Exchange rounds R of a single-party run and, for r < min(R, cap), the
+ * 32-bit words of round r's message (msg_words may be NULL). */
+int match_rounds(const match_plan* plan, uint32_t* n_rounds, uint64_t* msg_words, uint32_t cap);
 int match_query(const match_plan* plan, int32_t party_mask, void* stream);
 
 /*
@@ -244,9 +269,15 @@ int match_query(const match_plan* plan, int32_t party_mask, void* stream);
  * fss_keygen call (same meaning, same checks).
  * fss_eval_batch (DPF / range evaluation for many predicates, parties, queries): each request
  * is one fss_eval_eq / fss_eval_lt call, chosen by keys->kind.
- * match_query_batch (edge matching for many plans): every predicate of every plan, both
- * parties, in one persistent launch; then each plan's ANDs and joins in plan
- * order.  Each plan has its own outputs and workspace as in match_query.
+ * match_query_batch (edge matching for many plans): every predicate of every plan (of the
+ * parties in party_mask) in one persistent launch; then the plans' ANDs and
+ * joins merged into a few launches -- party_mask 3: one per AND level of the
+ * deepest fold and one for all hop joins; party_mask 1 / 2: the round
+ * plans[i].round of every plan (closes, gathers, openings: three launches).
+ * Each plan has its own outputs, workspace and messages as in match_query.
+ * The tail's descriptors take match_batch_queue_bytes(plans, count) bytes of
+ * d_queue (at least that many must be passed); they are uploaded once per
+ * call after the evaluation launch, in stream order.
  */
 typedef struct fss_keygen_req {
     uint64_t seed;
@@ -275,6 +306,7 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
 int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes, void* stream);
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
                       uint64_t queue_bytes, void* stream);
+uint64_t match_batch_queue_bytes(const match_plan* plans, uint32_t count);
 
 /*
  * The paper's own secure predicate evaluation over one-hot attributes in

@@ -5,8 +5,11 @@
 //   k_mask_open            xhat = x0 + x1 + r                          (HBM stream)
 //   k_keygen_eq/_range     dealer: DPF / 2xDCF Gen per row             (LDS + VALU, AES)
 //   k_eval                 DPF / 2xDCF Eval per row, ballot            (LDS + VALU, AES)
-//   k_triples              dealer: Beaver triples                      (LDS + VALU, AES)
-//   k_and_open/close, k_and_both, k_interleave, k_gather, k_public_one  ANDs, joins  (HBM stream)
+//   k_triples              dealer: Beaver triples (ss_triples)         (LDS + VALU, AES)
+//   k_and_open/close       one party's AND phases (ss_and)             (HBM stream)
+//   k_tail                 a plan's ANDs and hop joins, triples drawn in registers
+//                                                                      (gathers + AES)
+//   k_rss, k_rss_eval, k_eval_points*   the paper's own secEval and RSS arithmetic
 // and the host code of the C ABI (validation, launch, match_query plan).
 //
 // Every AES-using kernel runs 1024-thread workgroups that first fill the
@@ -694,55 +697,6 @@ __global__ void k_and_close(uint64_t nwords, uint64_t nrows, uint32_t party, con
     }
 }
 
-// Both simulated parties at once: open, exchange (an XOR), close.
-__global__ void k_and_both(uint64_t nwords, uint64_t nrows, const uint32_t* __restrict__ x0,
-                           const uint32_t* __restrict__ x1, const uint32_t* __restrict__ y0,
-                           const uint32_t* __restrict__ y1, const uint32_t* __restrict__ t0,
-                           const uint32_t* __restrict__ t1, uint32_t* __restrict__ z0, uint32_t* __restrict__ z1) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
-        const uint32_t a0 = t0[w], b0 = t0[nwords + w], c0 = t0[2 * nwords + w];
-        const uint32_t a1 = t1[w], b1 = t1[nwords + w], c1 = t1[2 * nwords + w];
-        const uint32_t d = (x0[w] ^ a0) ^ (x1[w] ^ a1);
-        const uint32_t e = (y0[w] ^ b0) ^ (y1[w] ^ b1);
-        const uint32_t pm = pad_mask(w, nrows);
-        z0[w] = (c0 ^ (d & b0) ^ (e & a0) ^ (d & e)) & pm;
-        z1[w] = (c1 ^ (d & b1) ^ (e & a1)) & pm;
-    }
-}
-
-// out_b[e] = bit idx[e] of m_b (each party gathers its own share at a public
-// index); an index >= nsrc gathers 0 for both parties.
-// The two parties' shares of one vertex bit array side by side: word w of
-// party b at pair[w] component b, so that a gather reads both in one 8-byte
-// load (one L2 request per edge instead of two).
-__global__ void k_interleave(uint64_t nwords, const uint32_t* __restrict__ m0, const uint32_t* __restrict__ m1,
-                             uint2* __restrict__ pair) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride)
-        pair[w] = make_uint2(m0[w], m1[w]);
-}
-
-// Edge e of the join takes the endpoint's bit from both parties' arrays: bit
-// idx[e] of the interleaved vertex bits, packed by ballot into o0 / o1.
-__global__ void k_gather(uint64_t n, uint64_t nsrc, const uint32_t* __restrict__ idx,
-                         const uint2* __restrict__ pair, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t b0 = 0, b1 = 0;
-    if (e < n && idx[e] < nsrc) {
-        const uint32_t v = idx[e];
-        const uint2 w = pair[v >> 5];
-        b0 = (w.x >> (v & 31u)) & 1u;
-        b1 = (w.y >> (v & 31u)) & 1u;
-    }
-    const uint64_t g0 = __ballot(b0), g1 = __ballot(b1);
-    if ((threadIdx.x & 63u) == 0) {
-        const uint64_t w = e >> 5, nwords = (n + 31) >> 5;
-        if (w < nwords) { o0[w] = (uint32_t)g0; o1[w] = (uint32_t)g1; }
-        if (w + 1 < nwords) { o0[w + 1] = (uint32_t)(g0 >> 32); o1[w + 1] = (uint32_t)(g1 >> 32); }
-    }
-}
-
 // ----------------------------------------------------------------- three-party RSS arithmetic
 
 struct RssArgs {
@@ -825,12 +779,252 @@ __global__ __launch_bounds__(kRssBlock) void k_rss(RssArgs A) {
     }
 }
 
-// Shares of the public constant 1 over nrows rows.
-__global__ void k_public_one(uint64_t nwords, uint64_t nrows, uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
-        o0[w] = pad_mask(w, nrows);
-        o1[w] = 0u;
+// ----------------------------------------------------------------- plan tail: ANDs and hop joins
+//
+// The steps of a plan after its predicate bits exist (the ANDs of each vertex
+// and edge fold, the hop joins) run as tail ops, many ops per launch: op i
+// owns tiles [tile_start_i, tile_start_i + tiles_i) of one global tile range,
+// and each workgroup walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...  A
+// tile is 1024 packed words: one word per thread for the word ops, one wave
+// per 64 words (2048 edges) for the gathering ops.  The Beaver triple words
+// an AND consumes are drawn in registers from the dealer's generator, so no
+// triple buffer exists.
+
+enum TailKind : uint32_t {
+    TK_AND = 0,         // both parties: z = x AND y
+    TK_AND_OPEN = 1,    // one party: msg = (x_b ^ a_b) || (y_b ^ b_b)
+    TK_AND_CLOSE = 2,   // one party: z_b from d = x_b ^ a_b ^ d', e = y_b ^ b_b ^ e' (peer message d' || e')
+    TK_PAIR = 3,        // both parties: pair[w] = (m_0[w], m_1[w])
+    TK_HOP = 4,         // both parties: z = (m_j[src] AND m_j+1[dst]) AND q_j (public operands skipped)
+    TK_GATHER = 5,      // one party: z_b = bits of m_b at the public indices
+    TK_COPY = 6,        // the parties in `party`: z_b = x_b
+    TK_ONE = 7,         // the parties in `party`: their shares of the public constant 1
+};
+
+constexpr uint32_t kTailTileWords = 1024;
+constexpr uint32_t kNoAnd = 0xFFFFFFFFu;
+// TK_HOP flags
+constexpr uint32_t kHopSrc = 1, kHopDst = 2, kHopQ = 4;
+
+struct TailOp {
+    uint32_t kind;
+    uint32_t party;         // single-party kinds: 0 / 1; COPY / ONE: bit mask of parties; AND: 1 = pairs
+                            // out; HOP: flags
+    uint32_t query;
+    uint32_t and1;          // AND number of the (first) AND
+    uint32_t and2;          // TK_HOP: number of the AND with q_j
+    uint32_t rk;            // dealer key schedule (index into the launch's table)
+    uint32_t tile_start;
+    uint32_t pad;
+    uint64_t nrows;         // rows of the output table
+    uint64_t nsrc;          // gathering ops: rows of the vertex table
+    const uint32_t* x[2];   // AND: x; PAIR / COPY / GATHER: the source; HOP: q_j
+    const uint32_t* y[2];   // AND: y; AND_CLOSE: y[1] = the peer message d' || e'
+    uint32_t* z[2];         // outputs (AND_OPEN: z[0] = this party's message; PAIR: z[0] = the pairs)
+    const uint32_t* src;    // gathering ops: public indices (HOP: sources)
+    const uint32_t* dst;    // HOP: destinations
+    const uint2* gsrc;      // HOP: interleaved shares of m_j
+    const uint2* gdst;      // HOP: interleaved shares of m_j+1
+};
+
+constexpr int kTailInline = 24;
+
+struct TailLaunch {
+    const TailOp* ops;      // device array, or nullptr: the inline ops below
+    const RoundKeys* rks;   // device array, or nullptr: the inline key below
+    uint32_t count;
+    uint32_t total_tiles;
+    RoundKeys rk;
+    TailOp op[kTailInline];
+};
+
+__device__ __forceinline__ uint32_t pick4(uint32_t off, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    return off == 0 ? a : off == 1 ? b : off == 2 ? c : d;
+}
+
+// Triple word w of Beaver stream (query, and_id): stream words 5w .. 5w+4 are
+// a0, a1, b0, b1, c0; stream word k is word k mod 4 of generator block
+// (4, 0, query, and_id, k div 4).  Five consecutive words span two blocks.
+struct Triple {
+    uint32_t a0, a1, b0, b1, c0;
+    __device__ uint32_t c1() const { return ((a0 ^ a1) & (b0 ^ b1)) ^ c0; }
+};
+
+__device__ __forceinline__ Triple triple_word(const RoundKeys& rk, uint32_t query, uint32_t and_id, uint64_t w,
+                                              const uint32_t* tab, LaneOff loff) {
+    const uint64_t k0 = 5 * w;
+    const uint32_t blk = (uint32_t)(k0 >> 2), off = (uint32_t)(k0 & 3u);
+    uint4 p = rng_block(rk, 4, 0, query, and_id, blk, tab, loff);
+    pin_in_vgprs(p);
+    const uint4 q = rng_block(rk, 4, 0, query, and_id, blk + 1, tab, loff);
+    const uint32_t s0 = p.x, s1 = p.y, s2 = p.z, s3 = p.w, s4 = q.x, s5 = q.y, s6 = q.z, s7 = q.w;
+    Triple t;
+    t.a0 = pick4(off, s0, s1, s2, s3);
+    t.a1 = pick4(off, s1, s2, s3, s4);
+    t.b0 = pick4(off, s2, s3, s4, s5);
+    t.b1 = pick4(off, s3, s4, s5, s6);
+    t.c0 = pick4(off, s4, s5, s6, s7);
+    return t;
+}
+
+// Both parties' AND of one word (open, exchange and close at once).
+__device__ __forceinline__ void and_both(const Triple& t, uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1,
+                                         uint32_t pm, uint32_t& z0, uint32_t& z1) {
+    const uint32_t d = x0 ^ t.a0 ^ x1 ^ t.a1;
+    const uint32_t e = y0 ^ t.b0 ^ y1 ^ t.b1;
+    z0 = (t.c0 ^ (d & t.b0) ^ (e & t.a0) ^ (d & e)) & pm;
+    z1 = (t.c1() ^ (d & t.b1) ^ (e & t.a1)) & pm;
+}
+
+// The bits of the 64 rows [row0, row0 + 64) of one wave, gathered at the
+// public indices, become words row0 / 32 and row0 / 32 + 1: lane 2k + h of the
+// wave keeps half h of iteration k's ballot.
+struct WaveWords {
+    uint32_t lane;
+    uint32_t w[2];
+    __device__ __forceinline__ void keep(uint32_t it, uint32_t k, uint64_t ballot) {
+        if (lane == 2 * it) w[k] = (uint32_t)ballot;
+        if (lane == 2 * it + 1) w[k] = (uint32_t)(ballot >> 32);
+    }
+};
+
+// One tile (1024 words) of op o; `tile` counts from the op's first tile.
+__device__ __forceinline__ void tail_tile(const TailOp& o, const RoundKeys& rk, uint64_t tile, const uint32_t* tab,
+                                          LaneOff loff) {
+    const uint64_t nwords = (o.nrows + 31) >> 5;
+    if (o.kind == TK_HOP || o.kind == TK_GATHER) {
+        // wave v of the workgroup owns words [w0, w0 + 64); lane l ends with word w0 + l
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint64_t w0 = tile * kTailTileWords + (threadIdx.x & ~63u);
+        if (w0 >= nwords) return;                    // whole waves leave
+        WaveWords g{lane, {0u, 0u}}, h{lane, {0u, 0u}};
+        const bool hop = o.kind == TK_HOP;
+        const uint32_t fl = o.party;
+        const bool gs = hop ? (fl & kHopSrc) != 0 : true, gd = hop && (fl & kHopDst) != 0;
+#pragma unroll 4
+        for (uint32_t it = 0; it < 32; it++) {
+            const uint64_t e = (w0 + 2 * it) * 32 + lane;
+            uint32_t bs0 = 0, bs1 = 0, bd0 = 0, bd1 = 0;
+            if (e < o.nrows) {
+                if (gs) {
+                    const uint32_t v = o.src[e];
+                    if (v < o.nsrc) {
+                        if (hop) {
+                            const uint2 p = o.gsrc[v >> 5];
+                            bs0 = (p.x >> (v & 31u)) & 1u;
+                            bs1 = (p.y >> (v & 31u)) & 1u;
+                        } else {
+                            bs0 = (o.x[0][v >> 5] >> (v & 31u)) & 1u;
+                        }
+                    }
+                }
+                if (gd) {
+                    const uint32_t v = o.dst[e];
+                    if (v < o.nsrc) {
+                        const uint2 p = o.gdst[v >> 5];
+                        bd0 = (p.x >> (v & 31u)) & 1u;
+                        bd1 = (p.y >> (v & 31u)) & 1u;
+                    }
+                }
+            }
+            if (gs) g.keep(it, 0, __ballot(bs0));
+            if (gs && hop) g.keep(it, 1, __ballot(bs1));
+            if (gd) h.keep(it, 0, __ballot(bd0));
+            if (gd) h.keep(it, 1, __ballot(bd1));
+        }
+        const uint64_t w = w0 + lane;
+        if (w >= nwords) return;
+        const uint32_t pm = pad_mask(w, o.nrows);
+        if (!hop) {
+            o.z[0][w] = g.w[0];
+            return;
+        }
+        // r1 = g AND h (or the one gathered, or public 1); out = r1 AND q (or r1, or q, or public 1)
+        bool r1pub = false;
+        uint32_t r0, r1;
+        if (gs && gd) {
+            and_both(triple_word(rk, o.query, o.and1, w, tab, loff), g.w[0], g.w[1], h.w[0], h.w[1], pm, r0, r1);
+        } else if (gs) {
+            r0 = g.w[0]; r1 = g.w[1];
+        } else if (gd) {
+            r0 = h.w[0]; r1 = h.w[1];
+        } else {
+            r0 = pm; r1 = 0u; r1pub = true;
+        }
+        if (fl & kHopQ) {
+            const uint32_t q0 = o.x[0][w], q1 = o.x[1][w];
+            if (r1pub) {
+                r0 = q0; r1 = q1;
+            } else {
+                and_both(triple_word(rk, o.query, o.and2, w, tab, loff), r0, r1, q0, q1, pm, r0, r1);
+            }
+        }
+        o.z[0][w] = r0;
+        o.z[1][w] = r1;
+        return;
+    }
+    const uint64_t w = tile * kTailTileWords + threadIdx.x;
+    if (w >= nwords) return;
+    const uint32_t pm = pad_mask(w, o.nrows);
+    switch (o.kind) {
+    case TK_AND: {
+        uint32_t z0, z1;
+        and_both(triple_word(rk, o.query, o.and1, w, tab, loff), o.x[0][w], o.x[1][w], o.y[0][w], o.y[1][w], pm, z0,
+                 z1);
+        if (o.party & 1u) {                              // the fold's last AND: pairs for the join
+            ((uint2*)o.z[0])[w] = make_uint2(z0, z1);
+        } else {
+            o.z[0][w] = z0;
+            o.z[1][w] = z1;
+        }
+        break;
+    }
+    case TK_AND_OPEN: {
+        const Triple t = triple_word(rk, o.query, o.and1, w, tab, loff);
+        const uint32_t b = o.party;
+        o.z[0][w] = o.x[0][w] ^ (b ? t.a1 : t.a0);
+        o.z[0][nwords + w] = o.y[0][w] ^ (b ? t.b1 : t.b0);
+        break;
+    }
+    case TK_AND_CLOSE: {
+        const Triple t = triple_word(rk, o.query, o.and1, w, tab, loff);
+        const uint32_t b = o.party;
+        const uint32_t ab = b ? t.a1 : t.a0, bb = b ? t.b1 : t.b0, cb = b ? t.c1() : t.c0;
+        const uint32_t d = o.x[0][w] ^ ab ^ o.y[1][w];
+        const uint32_t e = o.y[0][w] ^ bb ^ o.y[1][nwords + w];
+        uint32_t z = cb ^ (d & bb) ^ (e & ab);
+        if (b == 0) z ^= d & e;
+        o.z[0][w] = z & pm;
+        break;
+    }
+    case TK_PAIR:
+        ((uint2*)o.z[0])[w] = make_uint2(o.x[0][w], o.x[1][w]);
+        break;
+    case TK_COPY:
+        if (o.party & 1u) o.z[0][w] = o.x[0][w];
+        if (o.party & 2u) o.z[1][w] = o.x[1][w];
+        break;
+    case TK_ONE:
+        if (o.party & 1u) o.z[0][w] = pm;
+        if (o.party & 2u) o.z[1][w] = 0u;
+        break;
+    default:
+        break;
+    }
+}
+
+// Ops in tile order; a workgroup fills the AES tables once, then takes every
+// gridDim.x-th tile.
+__global__ __launch_bounds__(kBlock) void k_tail(TailLaunch L) {
+    __shared__ uint32_t tab[kLdsTableWords];
+    lds_table_fill(tab, g_tables.t0);
+    __syncthreads();
+    const LaneOff loff = lane_offset();
+    const TailOp* ops = L.ops ? L.ops : L.op;
+    for (uint32_t tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const uint32_t di = find_desc(L.count, tile, [&](uint32_t i) { return ops[i].tile_start; });
+        const TailOp& o = ops[di];
+        tail_tile(o, L.rks ? L.rks[o.rk] : L.rk, tile - o.tile_start, tab, loff);
     }
 }
 
@@ -1086,6 +1280,8 @@ struct Shares {
     bool is_public() const { return p[0] == nullptr; }
 };
 
+// Carves 256-byte aligned pieces off the workspace.  measuring() gives an
+// arena that only counts bytes (its pointers are never dereferenced).
 struct Arena {
     uint8_t* base;
     uint64_t size;
@@ -1097,42 +1293,345 @@ struct Arena {
         used += bytes;
         return p;
     }
+    bool take2(uint64_t words, Shares& s) { return (s.p[0] = take(words)) && (s.p[1] = take(words)); }
+    static Arena measuring() { return Arena{(uint8_t*)(uintptr_t)256, ~0ull >> 1, 0}; }
 };
 
 uint64_t words_of(uint64_t rows) { return (rows + 31) / 32; }
 
-// Workspace bytes the plan needs (an upper bound): predicate bits and at most
-// one AND result per predicate, per hop two gathers and two AND results, and
-// one triple buffer -- per party.
+// The plan's steps after evaluation, laid out in the workspace -- a pure
+// function of the plan, so every call on the same plan finds the same
+// buffers (the single-party rounds rely on it).
+//   folds: per target t (query vertices 0..n_qv-1, then query edges) its
+//          predicates ANDed as a left fold; step s of a fold is AND level s;
+//   hops:  h_j = (m_j[src] AND m_j+1[dst]) AND q_j;
+// AND numbers follow that order (vertex folds, edge folds, then per hop the
+// AND of the endpoints and the AND with q_j); an AND with a public operand is
+// skipped and takes no number.  Level L of an AND: in a single-party run it
+// is opened in round L - 1 and closed in round L.
+struct TailPlan {
+    struct And {
+        uint32_t id, level;
+        uint64_t nrows;
+        Shares x, y, z;
+        int32_t vertex;     // fold AND: the query vertex whose fold it ends, else -1
+        bool hop;           // an AND of a hop join
+    };
+    struct Hop {
+        bool g, h, q;               // m_j, m_j+1, q_j not public
+        int32_t a1 = -1, a2 = -1;   // indices into ands
+        uint32_t lg = 0;            // round in which the gathers run (single party)
+        uint32_t lq = 0;            // round from which q_j is ready
+        Shares gs, hs, r1;          // single party: gathered endpoint bits, g AND h
+        uint32_t* out[2];
+    };
+    const match_plan* P = nullptr;
+    uint32_t n_qv = 0, ntarget = 0;
+    uint64_t wv = 0, we = 0;
+    Shares pbits[FSS_MAX_PREDS];
+    Shares fold[2 * FSS_MAX_QV];
+    uint32_t depth[2 * FSS_MAX_QV] = {};
+    uint32_t npred_of[2 * FSS_MAX_QV] = {};
+    uint32_t first_pred[2 * FSS_MAX_QV] = {};
+    uint2* pair[FSS_MAX_QV] = {};
+    std::vector<And> ands;          // in AND-number order
+    Hop hop[FSS_MAX_QV];
+    uint32_t rounds = 0;            // single-party exchange rounds
+
+    uint64_t rows_of(uint32_t t) const { return t < n_qv ? P->n_vertices : P->n_edges; }
+
+    int build(const match_plan* plan, Arena& ws) {
+        P = plan;
+        n_qv = P->n_qv;
+        ntarget = 2 * n_qv - 1;
+        wv = words_of(P->n_vertices);
+        we = words_of(P->n_edges);
+        auto nomem = [] { return fail(FSS_ENOMEM, "match_query: workspace too small"); };
+        for (uint32_t k = 0; k < P->n_pred; k++) {
+            const fss_pred& p = P->preds[k];
+            if (p.d_bits[0]) {
+                pbits[k].p[0] = const_cast<uint32_t*>(p.d_bits[0]);
+                pbits[k].p[1] = const_cast<uint32_t*>(p.d_bits[1]);
+            } else if (!ws.take2(words_of(rows_of((uint32_t)p.target)), pbits[k])) {
+                return nomem();
+            }
+        }
+        for (uint32_t t = 0; t < ntarget; t++) {
+            Shares acc;
+            for (uint32_t k = 0; k < P->n_pred; k++) {
+                if ((uint32_t)P->preds[k].target != t) continue;
+                if (npred_of[t]++ == 0) {
+                    acc = pbits[k];
+                    first_pred[t] = k;
+                    continue;
+                }
+                And a{};
+                a.id = (uint32_t)ands.size();
+                a.level = ++depth[t];
+                a.nrows = rows_of(t);
+                a.x = acc;
+                a.y = pbits[k];
+                a.vertex = -1;
+                a.hop = false;
+                if (!ws.take2(words_of(a.nrows), a.z)) return nomem();
+                acc = a.z;
+                ands.push_back(a);
+            }
+            fold[t] = acc;
+            // the fold's last AND ends query vertex t (pairs for the joins)
+            if (t < n_qv && depth[t] > 0) ands.back().vertex = (int32_t)t;
+        }
+        if (n_qv == 1) {
+            // the output is m_0: its last AND writes it
+            if (depth[0] > 0) {
+                ands.back().z.p[0] = P->d_out[0];
+                ands.back().z.p[1] = P->d_out[1];
+            }
+        } else {
+            for (uint32_t i = 0; i < n_qv; i++)
+                if (!fold[i].is_public() && !(pair[i] = (uint2*)ws.take(2 * wv))) return nomem();
+        }
+        for (uint32_t j = 0; j + 1 < n_qv; j++) {
+            Hop& H = hop[j];
+            H.g = !fold[j].is_public();
+            H.h = !fold[j + 1].is_public();
+            H.q = !fold[n_qv + j].is_public();
+            H.out[0] = P->d_out[0] + (uint64_t)j * we;
+            H.out[1] = P->d_out[1] + (uint64_t)j * we;
+            H.lg = std::max(H.g ? depth[j] : 0u, H.h ? depth[j + 1] : 0u);
+            H.lq = depth[n_qv + j];
+            if (H.g && !ws.take2(we, H.gs)) return nomem();
+            if (H.h && !ws.take2(we, H.hs)) return nomem();
+            uint32_t ready = H.lg;          // round in which r1 is ready
+            Shares r1 = H.g ? H.gs : H.hs;  // public if neither
+            if (H.g && H.h) {
+                And a{};
+                a.id = (uint32_t)ands.size();
+                a.level = H.lg + 1;
+                a.nrows = P->n_edges;
+                a.x = H.gs;
+                a.y = H.hs;
+                a.vertex = -1;
+                a.hop = true;
+                if (!ws.take2(we, H.r1)) return nomem();
+                a.z = H.r1;
+                H.a1 = (int32_t)ands.size();
+                ands.push_back(a);
+                ready = a.level;
+                r1 = H.r1;
+            }
+            if (!r1.is_public() && H.q) {
+                And a{};
+                a.id = (uint32_t)ands.size();
+                a.level = std::max(ready, H.lq) + 1;
+                a.nrows = P->n_edges;
+                a.x = r1;
+                a.y = fold[n_qv + j];
+                a.z.p[0] = H.out[0];
+                a.z.p[1] = H.out[1];
+                a.vertex = -1;
+                a.hop = true;
+                H.a2 = (int32_t)ands.size();
+                ands.push_back(a);
+            } else if (H.a1 >= 0) {
+                ands[H.a1].z.p[0] = H.out[0];   // g AND h is the hop's result
+                ands[H.a1].z.p[1] = H.out[1];
+            }
+        }
+        for (const And& a : ands) rounds = std::max(rounds, a.level);
+        return FSS_OK;
+    }
+
+    // 32-bit words of the message of round r (the openings of the ANDs of level r + 1).
+    uint64_t msg_words(uint32_t r) const {
+        uint64_t n = 0;
+        for (const And& a : ands)
+            if (a.level == r + 1) n += 2 * words_of(a.nrows);
+        return n;
+    }
+};
+
+// Workspace bytes of the plan (at least 256, so that 0 can mean "invalid").
 uint64_t plan_workspace(const match_plan* P) {
-    auto rnd = [](uint64_t words) { return (words * 4 + 255) & ~255ull; };
-    const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
-    uint64_t total = 0;
-    for (uint32_t k = 0; k < P->n_pred; k++)
-        total += 4 * rnd((uint32_t)P->preds[k].target < P->n_qv ? wv : we);
-    if (P->n_qv > 1) total += 8 * (uint64_t)(P->n_qv - 1) * rnd(we) + rnd(2 * wv);   // + the interleaved vertex bits
-    const uint64_t wmax = wv > we ? wv : we;
-    total += 2 * rnd(3 * wmax);
-    return total;
+    Arena measure = Arena::measuring();
+    TailPlan T;
+    if (T.build(P, measure)) return 0;
+    return std::max<uint64_t>(measure.used, 256);
 }
 
-__global__ void k_copy_words(uint64_t nwords, const uint32_t* __restrict__ a0, const uint32_t* __restrict__ a1,
-                             uint32_t* __restrict__ o0, uint32_t* __restrict__ o1) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
-        o0[w] = a0[w];
-        o1[w] = a1[w];
+// Number of tail tiles of an op over `nrows` rows.
+uint32_t tail_tiles(uint64_t nrows) { return (uint32_t)((words_of(nrows) + kTailTileWords - 1) / kTailTileWords); }
+
+TailOp tail_op(uint32_t kind, const match_plan* P, uint64_t nrows) {
+    TailOp o{};
+    o.kind = kind;
+    o.query = P->query_id;
+    o.and1 = o.and2 = kNoAnd;
+    o.nrows = nrows;
+    return o;
+}
+
+// Both parties at once: per AND level the fold ANDs (a vertex's last AND
+// writes its pairs for the joins), with the pairs of one-predicate vertices
+// and the output of a one-vertex query in the first level, then one level of
+// hop joins.  Level i of the result holds the ops of launch i.
+void fused_levels(const TailPlan& T, uint32_t rk, std::vector<std::vector<TailOp>>& levels) {
+    const match_plan* P = T.P;
+    uint32_t nlev = 0;
+    for (const auto& a : T.ands) nlev = std::max(nlev, a.level);
+    const uint32_t first = 0, hops = std::max(nlev, 1u);
+    if (levels.size() < hops + 1) levels.resize(hops + 1);
+    auto put = [&](uint32_t lev, TailOp o) { o.rk = rk; levels[lev].push_back(o); };
+    for (const auto& a : T.ands) {
+        if (a.hop) continue;
+        TailOp o = tail_op(TK_AND, P, a.nrows);
+        o.and1 = a.id;
+        o.x[0] = a.x.p[0]; o.x[1] = a.x.p[1];
+        o.y[0] = a.y.p[0]; o.y[1] = a.y.p[1];
+        o.z[0] = a.z.p[0]; o.z[1] = a.z.p[1];
+        if (T.n_qv > 1 && a.vertex >= 0) {
+            o.party = 1;                           // pairs out
+            o.z[0] = (uint32_t*)T.pair[a.vertex];
+            o.z[1] = nullptr;
+        }
+        put(a.level - 1, o);
+    }
+    if (T.n_qv == 1) {
+        if (T.npred_of[0] == 0) {
+            TailOp o = tail_op(TK_ONE, P, P->n_vertices);
+            o.party = 3;
+            o.z[0] = P->d_out[0]; o.z[1] = P->d_out[1];
+            put(first, o);
+        } else if (T.depth[0] == 0) {
+            TailOp o = tail_op(TK_COPY, P, P->n_vertices);
+            o.party = 3;
+            o.x[0] = T.fold[0].p[0]; o.x[1] = T.fold[0].p[1];
+            o.z[0] = P->d_out[0]; o.z[1] = P->d_out[1];
+            put(first, o);
+        }
+        return;
+    }
+    for (uint32_t i = 0; i < T.n_qv; i++) {
+        if (T.fold[i].is_public() || T.depth[i] > 0) continue;
+        TailOp o = tail_op(TK_PAIR, P, P->n_vertices);
+        o.x[0] = T.fold[i].p[0]; o.x[1] = T.fold[i].p[1];
+        o.z[0] = (uint32_t*)T.pair[i];
+        put(first, o);
+    }
+    for (uint32_t j = 0; j + 1 < T.n_qv; j++) {
+        const TailPlan::Hop& H = T.hop[j];
+        TailOp o = tail_op(TK_HOP, P, P->n_edges);
+        o.party = (H.g ? kHopSrc : 0) | (H.h ? kHopDst : 0) | (H.q ? kHopQ : 0);
+        o.nsrc = P->n_vertices;
+        o.src = P->d_src;
+        o.dst = P->d_dst;
+        o.gsrc = T.pair[j];
+        o.gdst = T.pair[j + 1];
+        if (H.q) { o.x[0] = T.fold[T.n_qv + j].p[0]; o.x[1] = T.fold[T.n_qv + j].p[1]; }
+        if (H.a1 >= 0) o.and1 = T.ands[H.a1].id;
+        if (H.a2 >= 0) o.and2 = T.ands[H.a2].id;
+        o.z[0] = H.out[0]; o.z[1] = H.out[1];
+        put(hops, o);
     }
 }
 
-int validate_plan(const match_plan* P, const char* who) {
+// Party b, round r: the closes of level r (peer: the other party's message of
+// round r - 1), then the gathers and copies that become ready in round r, then
+// the openings of level r + 1 (msg: this party's message of round r).  The
+// three phases are three launches (phase[0..2]).
+void party_round(const TailPlan& T, uint32_t b, uint32_t r, const uint32_t* peer, uint32_t* msg, uint32_t rk,
+                 std::vector<TailOp> phase[3]) {
+    const match_plan* P = T.P;
+    uint64_t off = 0;
+    for (const auto& a : T.ands) {                 // closes: offsets in round r - 1's message
+        if (r == 0 || a.level != r) continue;
+        TailOp o = tail_op(TK_AND_CLOSE, P, a.nrows);
+        o.party = b;
+        o.rk = rk;
+        o.and1 = a.id;
+        o.x[0] = a.x.p[b];
+        o.y[0] = a.y.p[b];
+        o.y[1] = peer + off;
+        o.z[0] = a.z.p[b];
+        phase[0].push_back(o);
+        off += 2 * words_of(a.nrows);
+    }
+    // this party's copy of a share (or of the public 1) into an output
+    auto copy = [&](const Shares& from, uint32_t* to0, uint32_t* to1, uint64_t nrows) {
+        TailOp o = tail_op(from.is_public() ? TK_ONE : TK_COPY, P, nrows);
+        o.party = 1u << b;
+        o.rk = rk;
+        o.x[0] = from.p[0]; o.x[1] = from.p[1];
+        o.z[0] = to0; o.z[1] = to1;
+        phase[1].push_back(o);
+    };
+    if (T.n_qv == 1) {
+        if (r == 0 && T.depth[0] == 0) {
+            if (T.npred_of[0] == 0) {
+                TailOp o = tail_op(TK_ONE, P, P->n_vertices);
+                o.rk = rk;
+                o.party = 1u << b;
+                o.z[0] = P->d_out[0]; o.z[1] = P->d_out[1];
+                phase[1].push_back(o);
+            } else {
+                copy(T.fold[0], P->d_out[0], P->d_out[1], P->n_vertices);
+            }
+        }
+    } else {
+        for (uint32_t j = 0; j + 1 < T.n_qv; j++) {
+            const TailPlan::Hop& H = T.hop[j];
+            const bool final_gather = H.a1 < 0 && H.a2 < 0;   // the gathered bits are the result
+            if (H.lg == r) {
+                for (int side = 0; side < 2; side++) {
+                    if (!(side ? H.h : H.g)) continue;
+                    TailOp o = tail_op(TK_GATHER, P, P->n_edges);
+                    o.party = b;
+                    o.rk = rk;
+                    o.nsrc = P->n_vertices;
+                    o.src = side ? P->d_dst : P->d_src;
+                    o.x[0] = T.fold[j + side].p[b];
+                    o.z[0] = final_gather ? H.out[b] : (side ? H.hs.p[b] : H.gs.p[b]);
+                    phase[1].push_back(o);
+                }
+            }
+            if (!H.g && !H.h) {                    // r1 public: the result is q_j, or the public 1
+                if (H.lq == r && H.q) copy(T.fold[T.n_qv + j], H.out[0], H.out[1], P->n_edges);
+                if (r == 0 && !H.q) {
+                    TailOp o = tail_op(TK_ONE, P, P->n_edges);
+                    o.rk = rk;
+                    o.party = 1u << b;
+                    o.z[0] = H.out[0]; o.z[1] = H.out[1];
+                    phase[1].push_back(o);
+                }
+            }
+        }
+    }
+    off = 0;
+    for (const auto& a : T.ands) {                 // openings of level r + 1
+        if (a.level != r + 1) continue;
+        TailOp o = tail_op(TK_AND_OPEN, P, a.nrows);
+        o.party = b;
+        o.rk = rk;
+        o.and1 = a.id;
+        o.x[0] = a.x.p[b];
+        o.y[0] = a.y.p[b];
+        o.z[0] = msg + off;
+        phase[2].push_back(o);
+        off += 2 * words_of(a.nrows);
+    }
+}
+
+int validate_plan(const match_plan* P, int32_t party_mask, const char* who) {
     if (!P) return fail(FSS_EINVAL, "%s: plan is NULL", who);
+    if (party_mask < 1 || party_mask > 3) return fail(FSS_EINVAL, "%s: party_mask %d is not 1, 2 or 3", who, party_mask);
     if (P->n_qv == 0 || P->n_qv > FSS_MAX_QV) return fail(FSS_EINVAL, "%s: n_qv %u outside 1..%d", who, P->n_qv, FSS_MAX_QV);
     if (P->n_pred > FSS_MAX_PREDS) return fail(FSS_EINVAL, "%s: more than %d predicates", who, FSS_MAX_PREDS);
     if (P->n_pred && !P->preds) return fail(FSS_EINVAL, "%s: preds is NULL", who);
     if (P->n_vertices > 0xFFFFFFFFull || P->n_edges > 0xFFFFFFFFull)
         return fail(FSS_EUNSUPPORTED, "%s: more than 2^32 rows", who);
-    if (!P->d_out[0] || !P->d_out[1]) return fail(FSS_EINVAL, "%s: NULL output", who);
+    for (int b = 0; b < 2; b++)
+        if ((party_mask >> b & 1) && !P->d_out[b]) return fail(FSS_EINVAL, "%s: NULL output of party %d", who, b);
+    if (party_mask == 3 && (!P->d_out[0] || !P->d_out[1])) return fail(FSS_EINVAL, "%s: NULL output", who);
     if (P->n_qv > 1 && P->n_edges && (!P->d_src || !P->d_dst)) return fail(FSS_EINVAL, "%s: NULL edge endpoints", who);
     const uint32_t ntarget = 2 * P->n_qv - 1;
     for (uint32_t k = 0; k < P->n_pred; k++) {
@@ -1141,7 +1640,10 @@ int validate_plan(const match_plan* P, const char* who) {
             return fail(FSS_EINVAL, "%s: predicate %u targets %d (of %u)", who, k, p.target, ntarget);
         const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
         if (p.d_bits[0] || p.d_bits[1]) {
-            if (!p.d_bits[0] || !p.d_bits[1]) return fail(FSS_EINVAL, "%s: predicate %u has one bit pointer", who, k);
+            if (party_mask == 3 && (!p.d_bits[0] || !p.d_bits[1]))
+                return fail(FSS_EINVAL, "%s: predicate %u has one bit pointer", who, k);
+            if (party_mask != 3 && !p.d_bits[party_mask - 1])
+                return fail(FSS_EINVAL, "%s: predicate %u has no bits of party %d", who, k, party_mask - 1);
             continue;   // share bits already evaluated: keys and d_xhat are not used
         }
         if (!p.keys || (p.keys->kind != FSS_EQ && p.keys->kind != FSS_RANGE))
@@ -1151,10 +1653,12 @@ int validate_plan(const match_plan* P, const char* who) {
         if (p.keys->n != rows)
             return fail(FSS_EINVAL, "%s: predicate %u keys cover %llu rows, table has %llu", who, k,
                         (unsigned long long)p.keys->n, (unsigned long long)rows);
-        if (rows && (!p.d_xhat || !p.keys->key[0] || !p.keys->key[1]))
-            return fail(FSS_EINVAL, "%s: predicate %u has a NULL buffer", who, k);
-        if (rows && (!aligned256(p.keys->key[0]) || !aligned256(p.keys->key[1])))
-            return fail(FSS_EINVAL, "%s: predicate %u key buffers not 256-byte aligned", who, k);
+        for (int b = 0; b < 2; b++) {
+            if (!(party_mask >> b & 1) || !rows) continue;
+            if (!p.d_xhat || !p.keys->key[b]) return fail(FSS_EINVAL, "%s: predicate %u has a NULL buffer", who, k);
+            if (!aligned256(p.keys->key[b]))
+                return fail(FSS_EINVAL, "%s: predicate %u key buffers not 256-byte aligned", who, k);
+        }
     }
     const uint64_t need = plan_workspace(P);
     if (!P->d_workspace || P->workspace_bytes < need)
@@ -1162,127 +1666,59 @@ int validate_plan(const match_plan* P, const char* who) {
     return FSS_OK;
 }
 
-struct PlanRun {
-    const match_plan* P;
-    hipStream_t s;
-    Arena ws;
-    uint32_t next_and = 0;
-    uint32_t* trip[2] = {nullptr, nullptr};
-    uint2* pair = nullptr;      // interleaved vertex bits of the join, reused by every gather
-    Shares pbits[FSS_MAX_PREDS];
-
-    // Carve the triple buffers and the predicate-bit buffers; append one eval
-    // descriptor per (predicate, party) with rows to `out`.
-    int setup(std::vector<EvalDesc>& out) {
-        const uint64_t wv = words_of(P->n_vertices), we = words_of(P->n_edges);
-        const uint64_t wmax = wv > we ? wv : we;
-        for (int b = 0; b < 2; b++)
-            if (!(trip[b] = ws.take(3 * wmax))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-        for (uint32_t k = 0; k < P->n_pred; k++) {
-            const fss_pred& p = P->preds[k];
-            const uint64_t rows = (uint32_t)p.target < P->n_qv ? P->n_vertices : P->n_edges;
-            if (p.d_bits[0]) {       // evaluated by the caller
-                pbits[k].p[0] = const_cast<uint32_t*>(p.d_bits[0]);
-                pbits[k].p[1] = const_cast<uint32_t*>(p.d_bits[1]);
-                continue;
-            }
-            for (int b = 0; b < 2; b++) {
-                if (!(pbits[k].p[b] = ws.take(words_of(rows))))
-                    return fail(FSS_ENOMEM, "match_query: workspace too small");
-                if (rows == 0) continue;
-                EvalDesc d{};
-                d.key = (const uint8_t*)p.keys->key[b];
-                d.xhat = p.d_xhat;
-                d.out = pbits[k].p[b];
-                d.n = rows;
-                d.kind = (uint32_t)p.keys->kind;
-                d.nbits = p.keys->nbits;
-                d.party = (uint32_t)b;
-                out.push_back(d);
-            }
+// Eval descriptors of the plan's predicates for the parties in mask (the
+// bits of predicates evaluated by the caller are left alone).
+void plan_evals(const TailPlan& T, int32_t mask, std::vector<EvalDesc>& out) {
+    const match_plan* P = T.P;
+    for (uint32_t k = 0; k < P->n_pred; k++) {
+        const fss_pred& p = P->preds[k];
+        if (p.d_bits[0] || p.d_bits[1]) continue;
+        const uint64_t rows = T.rows_of((uint32_t)p.target);
+        if (rows == 0) continue;
+        for (int b = 0; b < 2; b++) {
+            if (!(mask >> b & 1)) continue;
+            EvalDesc d{};
+            d.key = (const uint8_t*)p.keys->key[b];
+            d.xhat = p.d_xhat;
+            d.out = T.pbits[k].p[b];
+            d.n = rows;
+            d.kind = (uint32_t)p.keys->kind;
+            d.nbits = p.keys->nbits;
+            d.party = (uint32_t)b;
+            out.push_back(d);
         }
-        return FSS_OK;
     }
+}
 
-    int AND(const Shares& x, const Shares& y, uint64_t nrows, Shares* z) {
-        if (x.is_public()) { *z = y; return FSS_OK; }
-        if (y.is_public()) { *z = x; return FSS_OK; }
-        const uint64_t nw = words_of(nrows);
-        Shares out;
-        for (int b = 0; b < 2; b++)
-            if (!(out.p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-        int rc = launch_triples(P->seed, P->query_id, next_and++, nw, trip[0], trip[1], s);
+// Workgroups of a tail launch: two per CU at most (the LDS holds two tables).
+unsigned tail_grid(uint32_t tiles) {
+    const uint32_t cap = 2u * (uint32_t)device_cus();
+    return tiles < 1 ? 1u : (tiles < cap ? tiles : cap);
+}
+
+// One launch per kTailInline ops, all carried in kernel arguments (one plan:
+// its key schedule rides along).
+int launch_tail_inline(const std::vector<TailOp>& ops, const RoundKeys& rk, hipStream_t s) {
+    for (size_t i0 = 0; i0 < ops.size(); i0 += kTailInline) {
+        TailLaunch L{};
+        L.rk = rk;
+        uint32_t tiles = 0;
+        const size_t n = std::min<size_t>(kTailInline, ops.size() - i0);
+        for (size_t i = 0; i < n; i++) {
+            L.op[i] = ops[i0 + i];
+            L.op[i].rk = 0;
+            L.op[i].tile_start = tiles;
+            tiles += tail_tiles(L.op[i].nrows);
+        }
+        L.count = (uint32_t)n;
+        L.total_tiles = tiles;
+        if (tiles == 0) continue;
+        hipLaunchKernelGGL(k_tail, dim3(tail_grid(tiles)), dim3(kBlock), 0, s, L);
+        int rc = check_launch("k_tail");
         if (rc) return rc;
-        if (nw) {
-            hipLaunchKernelGGL(k_and_both, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, x.p[0],
-                               x.p[1], y.p[0], y.p[1], trip[0], trip[1], out.p[0], out.p[1]);
-            rc = check_launch("k_and_both");
-        }
-        *z = out;
-        return rc;
     }
-
-    int gather(const Shares& m, const uint32_t* idx, Shares* out) {
-        if (m.is_public()) { *out = m; return FSS_OK; }
-        const uint64_t ne = P->n_edges, nw = words_of(ne);
-        for (int b = 0; b < 2; b++)
-            if (!(out->p[b] = ws.take(nw))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-        if (ne == 0) return FSS_OK;
-        const uint64_t nwv = words_of(P->n_vertices);
-        if (!pair && !(pair = (uint2*)ws.take(2 * nwv))) return fail(FSS_ENOMEM, "match_query: workspace too small");
-        if (nwv) {
-            hipLaunchKernelGGL(k_interleave, dim3(grid_for(nwv, 256, 8192)), dim3(256), 0, s, nwv, m.p[0], m.p[1],
-                               pair);
-            int rc = check_launch("k_interleave");
-            if (rc) return rc;
-        }
-        hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, P->n_vertices, idx,
-                           (const uint2*)pair, out->p[0], out->p[1]);
-        return check_launch("k_gather");
-    }
-
-    int emit(const Shares& m, uint64_t nrows, uint64_t word_offset) {
-        const uint64_t nw = words_of(nrows);
-        if (nw == 0) return FSS_OK;
-        uint32_t* o0 = P->d_out[0] + word_offset;
-        uint32_t* o1 = P->d_out[1] + word_offset;
-        if (m.is_public()) {
-            hipLaunchKernelGGL(k_public_one, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, nrows, o0, o1);
-            return check_launch("k_public_one");
-        }
-        hipLaunchKernelGGL(k_copy_words, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, nw, m.p[0], m.p[1], o0, o1);
-        return check_launch("k_copy_words");
-    }
-
-    // Steps 2 and 3 of the plan, after the predicate bits exist.
-    int finish() {
-        Shares m[FSS_MAX_QV], q[FSS_MAX_QV];
-        for (uint32_t i = 0; i < P->n_qv; i++)
-            for (uint32_t k = 0; k < P->n_pred; k++)
-                if ((uint32_t)P->preds[k].target == i) {
-                    int rc = AND(m[i], pbits[k], P->n_vertices, &m[i]);
-                    if (rc) return rc;
-                }
-        for (uint32_t j = 0; j + 1 < P->n_qv; j++)
-            for (uint32_t k = 0; k < P->n_pred; k++)
-                if ((uint32_t)P->preds[k].target == P->n_qv + j) {
-                    int rc = AND(q[j], pbits[k], P->n_edges, &q[j]);
-                    if (rc) return rc;
-                }
-        if (P->n_qv == 1) return emit(m[0], P->n_vertices, 0);
-        const uint64_t we = words_of(P->n_edges);
-        for (uint32_t j = 0; j + 1 < P->n_qv; j++) {
-            Shares g, h, r1, r2;
-            int rc = gather(m[j], P->d_src, &g);
-            if (!rc) rc = gather(m[j + 1], P->d_dst, &h);
-            if (!rc) rc = AND(g, h, P->n_edges, &r1);
-            if (!rc) rc = AND(r1, q[j], P->n_edges, &r2);
-            if (!rc) rc = emit(r2, P->n_edges, (uint64_t)j * we);
-            if (rc) return rc;
-        }
-        return FSS_OK;
-    }
-};
+    return FSS_OK;
+}
 
 // ----------------------------------------------------------------- batch queue plumbing
 
@@ -1423,6 +1859,55 @@ int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_byte
     return check_launch("k_eval_queue");
 }
 
+// Device image of a batch's tail: the plans' key schedules, then the ops of
+// every launch, one upload for all launches.
+uint64_t tail_queue_bytes(uint64_t nplans, uint64_t nops) {
+    return kQueueHeader + ((nplans * sizeof(RoundKeys) + 255) & ~255ull) + nops * sizeof(TailOp);
+}
+
+int launch_tail_queue(const match_plan* plans, uint32_t count, const std::vector<std::vector<TailOp>>& levels,
+                      void* d_ws, uint64_t ws_bytes, hipStream_t s) {
+    uint64_t nops = 0;
+    for (const auto& l : levels) nops += l.size();
+    if (nops == 0) return FSS_OK;
+    const uint64_t need = tail_queue_bytes(count, nops);
+    if (!d_ws || ws_bytes < need)
+        return fail(FSS_ENOMEM, "match_query_batch: queue workspace needs %llu bytes (match_batch_queue_bytes)",
+                    (unsigned long long)need);
+    const uint64_t rk_bytes = (count * sizeof(RoundKeys) + 255) & ~255ull;
+    std::vector<uint8_t> img(rk_bytes + nops * sizeof(TailOp));
+    RoundKeys* rks = (RoundKeys*)img.data();
+    for (uint32_t i = 0; i < count; i++) rks[i] = dealer_key(plans[i].seed);
+    TailOp* ops = (TailOp*)(img.data() + rk_bytes);
+    struct Launch { uint64_t first; uint32_t n, tiles; };
+    std::vector<Launch> launches;
+    uint64_t k = 0;
+    for (const auto& l : levels) {
+        Launch ln{k, (uint32_t)l.size(), 0};
+        for (const TailOp& o : l) {
+            ops[k] = o;
+            ops[k].tile_start = ln.tiles;
+            ln.tiles += tail_tiles(o.nrows);
+            k++;
+        }
+        if (ln.tiles) launches.push_back(ln);
+    }
+    uint8_t* dbase = (uint8_t*)d_ws + kQueueHeader;
+    int rc = upload(img.data(), img.size(), dbase, s);
+    if (rc) return rc;
+    for (const Launch& ln : launches) {
+        TailLaunch L{};
+        L.ops = (const TailOp*)(dbase + rk_bytes) + ln.first;
+        L.rks = (const RoundKeys*)dbase;
+        L.count = ln.n;
+        L.total_tiles = ln.tiles;
+        hipLaunchKernelGGL(k_tail, dim3(tail_grid(ln.tiles)), dim3(kBlock), 0, s, L);
+        rc = check_launch("k_tail");
+        if (rc) return rc;
+    }
+    return FSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1430,24 +1915,70 @@ extern "C" {
 uint64_t match_workspace_bytes(const match_plan* plan) {
     if (!plan || plan->n_qv == 0 || plan->n_qv > FSS_MAX_QV || plan->n_pred > FSS_MAX_PREDS) return 0;
     if (plan->n_pred && !plan->preds) return 0;
+    for (uint32_t k = 0; k < plan->n_pred; k++)
+        if (plan->preds[k].target < 0 || (uint32_t)plan->preds[k].target >= 2 * plan->n_qv - 1) return 0;
     return plan_workspace(plan);
+}
+
+int match_rounds(const match_plan* plan, uint32_t* n_rounds, uint64_t* msg_words, uint32_t cap) {
+    ogm::last_error().clear();
+    if (!n_rounds) return fail(FSS_EINVAL, "match_rounds: n_rounds is NULL");
+    if (!match_workspace_bytes(plan)) return fail(FSS_EINVAL, "match_rounds: invalid plan");
+    Arena measure = Arena::measuring();
+    TailPlan T;
+    int rc = T.build(plan, measure);
+    if (rc) return rc;
+    *n_rounds = T.rounds;
+    if (msg_words)
+        for (uint32_t r = 0; r < T.rounds && r < cap; r++) msg_words[r] = T.msg_words(r);
+    return FSS_OK;
 }
 
 int match_query(const match_plan* P, int32_t party_mask, void* stream) {
     ogm::last_error().clear();
-    if (party_mask != 3) return fail(FSS_EUNSUPPORTED, "match_query: party_mask must be 3 (both parties simulated)");
-    int rc = validate_plan(P, "match_query");
+    int rc = validate_plan(P, party_mask, "match_query");
     if (rc) return rc;
-    PlanRun R{P, (hipStream_t)stream, Arena{(uint8_t*)P->d_workspace, P->workspace_bytes, 0}};
-    std::vector<EvalDesc> descs;
-    rc = R.setup(descs);
+    hipStream_t s = (hipStream_t)stream;
+    Arena ws{(uint8_t*)P->d_workspace, P->workspace_bytes, 0};
+    TailPlan T;
+    rc = T.build(P, ws);
     if (rc) return rc;
-    // every predicate, both parties, in launches of up to kEvalInline descriptors
-    for (size_t i = 0; i < descs.size(); i += kEvalInline) {
-        rc = launch_eval(descs.data() + i, (uint32_t)std::min<size_t>(kEvalInline, descs.size() - i), R.s);
+    const RoundKeys rk = dealer_key(P->seed);
+    if (party_mask == 3) {
+        std::vector<EvalDesc> descs;
+        plan_evals(T, 3, descs);
+        for (size_t i = 0; i < descs.size(); i += kEvalInline) {
+            rc = launch_eval(descs.data() + i, (uint32_t)std::min<size_t>(kEvalInline, descs.size() - i), s);
+            if (rc) return rc;
+        }
+        std::vector<std::vector<TailOp>> levels;
+        fused_levels(T, 0, levels);
+        for (const auto& ops : levels) {
+            rc = launch_tail_inline(ops, rk, s);
+            if (rc) return rc;
+        }
+        return FSS_OK;
+    }
+    // one party, one round
+    const uint32_t b = (uint32_t)party_mask - 1, r = P->round;
+    if (r > T.rounds) return fail(FSS_EINVAL, "match_query: round %u of %u", r, T.rounds);
+    if (r > 0 && !P->d_peer_msg) return fail(FSS_EINVAL, "match_query: round %u needs the peer's message", r);
+    if (r < T.rounds && !P->d_msg) return fail(FSS_EINVAL, "match_query: round %u writes a message; d_msg is NULL", r);
+    if (r == 0) {
+        std::vector<EvalDesc> descs;
+        plan_evals(T, party_mask, descs);
+        for (size_t i = 0; i < descs.size(); i += kEvalInline) {
+            rc = launch_eval(descs.data() + i, (uint32_t)std::min<size_t>(kEvalInline, descs.size() - i), s);
+            if (rc) return rc;
+        }
+    }
+    std::vector<TailOp> phase[3];
+    party_round(T, b, r, P->d_peer_msg, P->d_msg, 0, phase);
+    for (auto& ops : phase) {
+        rc = launch_tail_inline(ops, rk, s);
         if (rc) return rc;
     }
-    return R.finish();
+    return FSS_OK;
 }
 
 uint64_t fss_queue_workspace_bytes(uint64_t count) { return queue_bytes(count); }
@@ -1694,29 +2225,62 @@ int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mas
     ogm::last_error().clear();
     if (count == 0) return FSS_OK;
     if (!plans) return fail(FSS_EINVAL, "match_query_batch: plans is NULL");
-    if (party_mask != 3)
-        return fail(FSS_EUNSUPPORTED, "match_query_batch: party_mask must be 3 (both parties simulated)");
     for (uint32_t i = 0; i < count; i++) {
-        int rc = validate_plan(&plans[i], "match_query_batch");
+        int rc = validate_plan(&plans[i], party_mask, "match_query_batch");
         if (rc) return rc;
+        if (party_mask != 3) {
+            const match_plan& P = plans[i];
+            uint32_t R = 0;
+            rc = match_rounds(&P, &R, nullptr, 0);
+            if (rc) return rc;
+            if (P.round > R) return fail(FSS_EINVAL, "match_query_batch: plan %u round %u of %u", i, P.round, R);
+            if (P.round > 0 && !P.d_peer_msg) return fail(FSS_EINVAL, "match_query_batch: plan %u needs the peer's message", i);
+            if (P.round < R && !P.d_msg) return fail(FSS_EINVAL, "match_query_batch: plan %u d_msg is NULL", i);
+        }
     }
     hipStream_t s = (hipStream_t)stream;
-    std::vector<PlanRun> runs;
-    runs.reserve(count);
+    std::vector<TailPlan> tails(count);
     std::vector<EvalDesc> descs;
     for (uint32_t i = 0; i < count; i++) {
         const match_plan* P = &plans[i];
-        runs.push_back(PlanRun{P, s, Arena{(uint8_t*)P->d_workspace, P->workspace_bytes, 0}});
-        int rc = runs.back().setup(descs);
+        Arena ws{(uint8_t*)P->d_workspace, P->workspace_bytes, 0};
+        int rc = tails[i].build(P, ws);
         if (rc) return rc;
+        if (party_mask == 3 || P->round == 0) plan_evals(tails[i], party_mask, descs);
     }
     int rc = launch_eval_queue(descs, d_queue, queue_bytes_avail, s);
     if (rc) return rc;
-    for (auto& R : runs) {
-        rc = R.finish();
-        if (rc) return rc;
+    // the tail: ops of every plan merged per launch, with one key schedule per plan
+    std::vector<std::vector<TailOp>> levels;
+    for (uint32_t i = 0; i < count; i++) {
+        if (party_mask == 3) {
+            fused_levels(tails[i], i, levels);
+        } else {
+            std::vector<TailOp> phase[3];
+            const match_plan& P = plans[i];
+            party_round(tails[i], (uint32_t)party_mask - 1, P.round, P.d_peer_msg, P.d_msg, i, phase);
+            if (levels.size() < 3) levels.resize(3);
+            for (int k = 0; k < 3; k++) levels[k].insert(levels[k].end(), phase[k].begin(), phase[k].end());
+        }
     }
-    return FSS_OK;
+    return launch_tail_queue(plans, count, levels, d_queue, queue_bytes_avail, s);
+}
+
+uint64_t match_batch_queue_bytes(const match_plan* plans, uint32_t count) {
+    if (!plans) return 0;
+    uint64_t nevals = 0, nops = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if (!match_workspace_bytes(&plans[i])) return 0;
+        Arena measure = Arena::measuring();
+        TailPlan T;
+        if (T.build(&plans[i], measure)) return 0;
+        std::vector<EvalDesc> d;
+        plan_evals(T, 3, d);
+        nevals += d.size();
+        // every AND, two gathers per hop and one copy per output, at most, in any launch
+        nops += T.ands.size() + 3 * (uint64_t)T.n_qv + 2;
+    }
+    return std::max(queue_bytes(nevals), tail_queue_bytes(count, nops));
 }
 
 }  // extern "C"

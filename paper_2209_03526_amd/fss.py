@@ -43,7 +43,9 @@ class match_plan(ctypes.Structure):
                 ("n_vertices", ctypes.c_uint64), ("n_edges", ctypes.c_uint64),
                 ("d_src", ctypes.c_void_p), ("d_dst", ctypes.c_void_p),
                 ("preds", ctypes.POINTER(fss_pred)), ("d_out", ctypes.c_void_p * 2),
-                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("round", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
+                ("d_peer_msg", ctypes.c_void_p), ("d_msg", ctypes.c_void_p)]
 
 
 class fss_keygen_req(ctypes.Structure):
@@ -82,6 +84,8 @@ def _load():
         "ss_and": ([i32, i32, u64, P, P, P, P, P, P], ctypes.c_int),
         "match_workspace_bytes": ([ctypes.POINTER(match_plan)], u64),
         "match_query": ([ctypes.POINTER(match_plan), i32, P], ctypes.c_int),
+        "match_rounds": ([ctypes.POINTER(match_plan), ctypes.POINTER(u32), ctypes.POINTER(u64), u32], ctypes.c_int),
+        "match_batch_queue_bytes": ([ctypes.POINTER(match_plan), u32], u64),
         "fss_queue_workspace_bytes": ([u64], u64),
         "fss_keygen_batch": ([ctypes.POINTER(fss_keygen_req), u32, P, u64, P], ctypes.c_int),
         "fss_eval_batch": ([ctypes.POINTER(fss_eval_req), u32, P, u64, P], ctypes.c_int),
@@ -115,7 +119,7 @@ def _load():
 LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_shutdown", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
-           "match_query", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
+           "match_query", "match_rounds", "match_batch_queue_bytes", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
            "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
@@ -277,7 +281,21 @@ def match_workspace_bytes(plan: Plan) -> int:
     return int(LIB.match_workspace_bytes(ctypes.byref(plan.c)))
 
 
-def match_query(plan: Plan, party_mask: int = 3, stream=None):
+def match_rounds(plan: Plan) -> list:
+    """Message words of each exchange round of a single-party run (its length is R)."""
+    n = ctypes.c_uint32()
+    _check(LIB.match_rounds(ctypes.byref(plan.c), ctypes.byref(n), None, 0))
+    words_ = (ctypes.c_uint64 * max(1, n.value))()
+    _check(LIB.match_rounds(ctypes.byref(plan.c), ctypes.byref(n), words_, n.value))
+    return [int(words_[r]) for r in range(n.value)]
+
+
+def match_query(plan: Plan, party_mask: int = 3, stream=None, round: int = 0, peer_msg=None, msg=None):
+    """party_mask 3: both parties.  1 / 2: party 0 / 1, round `round`, with the
+    peer's message of round - 1 (peer_msg) and this party's message (msg)."""
+    plan.c.round = round
+    plan.c.d_peer_msg = _ptr(peer_msg)
+    plan.c.d_msg = _ptr(msg)
     _check(LIB.match_query(ctypes.byref(plan.c), party_mask, _stream(stream)))
 
 
@@ -294,6 +312,12 @@ class Queue:
         self.capacity = capacity
         nbytes = fss_queue_workspace_bytes(max(1, capacity))
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device or torch.device("cuda"))
+
+    def reserve(self, nbytes: int):
+        """Grow to at least nbytes (the old buffer's uses are all enqueued on
+        the stream that allocated it, which the caching allocator respects)."""
+        if nbytes > self.buf.numel():
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.buf.device)
 
     def ptr(self):
         return self.buf.data_ptr(), self.buf.numel()
@@ -319,12 +343,30 @@ def fss_eval_batch(reqs, queue: Queue, stream=None):
     _check(LIB.fss_eval_batch(arr, len(reqs), d, nbytes, _stream(stream)))
 
 
-def match_query_batch(plans, queue: Queue, party_mask: int = 3, stream=None):
+def _plan_array(plans):
     arr = (match_plan * max(1, len(plans)))()
     for i, p in enumerate(plans):
         arr[i] = p.c
+    return arr
+
+
+def match_batch_queue_bytes(plans) -> int:
+    return int(LIB.match_batch_queue_bytes(_plan_array(plans), len(plans)))
+
+
+def match_query_batch(plans, queue: Queue, party_mask: int = 3, stream=None):
+    """party_mask 1 / 2: each plan runs its own round (plan.c.round, messages set
+    beforehand, e.g. with set_round)."""
+    arr = _plan_array(plans)
+    queue.reserve(int(LIB.match_batch_queue_bytes(arr, len(plans))))
     d, nbytes = queue.ptr()
     _check(LIB.match_query_batch(arr, len(plans), party_mask, d, nbytes, _stream(stream)))
+
+
+def set_round(plan: Plan, round: int, peer_msg=None, msg=None):
+    plan.c.round = round
+    plan.c.d_peer_msg = _ptr(peer_msg)
+    plan.c.d_msg = _ptr(msg)
 
 
 def set_tuning(rows_per_thread: int, wg_per_cu: int):

@@ -88,7 +88,8 @@ def test_match_plan_validation(fss):
     plan.n_qv = 9
     assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL
     plan.n_qv = 1
-    assert L.match_query(ctypes.byref(plan), 1, None) == fss.EUNSUPPORTED
+    assert L.match_query(ctypes.byref(plan), 0, None) == fss.EINVAL     # party_mask outside 1..3
+    assert L.match_query(ctypes.byref(plan), 4, None) == fss.EINVAL
     assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL     # no outputs
     plan.d_out[0] = 256
     plan.d_out[1] = 512
@@ -98,6 +99,50 @@ def test_match_plan_validation(fss):
     plan.n_qv = 2
     plan.n_edges = 10
     assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL     # no endpoints
+
+
+def _two_vertex_plan(fss, keep):
+    """Query vertex 0 with two predicates (share bits given: fake, aligned,
+    never dereferenced), vertex 1 and the edge without: one AND, then a hop
+    whose result is the gathered bits of m_0."""
+    preds = (fss.fss_pred * 2)()
+    for k in range(2):
+        preds[k] = fss.fss_pred(0, 0, None, None, (ctypes.c_void_p * 2)(1 << 20, 1 << 21))
+    plan = fss.match_plan()
+    plan.n_qv, plan.n_pred = 2, 2
+    plan.preds = ctypes.cast(preds, ctypes.POINTER(fss.fss_pred))
+    plan.n_vertices, plan.n_edges = 100, 50
+    plan.d_src, plan.d_dst = 1 << 22, 1 << 23
+    plan.d_out[0], plan.d_out[1] = 1 << 24, 1 << 25
+    plan.d_workspace = 1 << 26
+    plan.workspace_bytes = fss.LIB.match_workspace_bytes(ctypes.byref(plan))
+    keep.append(preds)
+    return plan
+
+
+def test_match_single_party_arguments(fss):
+    """Single-party (party_mask 1 / 2) rounds: schedule and argument errors,
+    all caught before anything is enqueued."""
+    L = fss.LIB
+    keep = []
+    plan = _two_vertex_plan(fss, keep)
+    assert plan.workspace_bytes > 0
+    n = ctypes.c_uint32()
+    words = (ctypes.c_uint64 * 4)()
+    assert L.match_rounds(ctypes.byref(plan), ctypes.byref(n), words, 4) == fss.OK
+    assert n.value == 1 and words[0] == 2 * ((100 + 31) // 32)     # one AND over 100 vertex rows: d || e
+    assert L.match_rounds(ctypes.byref(plan), None, None, 0) == fss.EINVAL
+    assert L.match_rounds(None, ctypes.byref(n), None, 0) == fss.EINVAL
+    plan.round = 2
+    assert L.match_query(ctypes.byref(plan), 1, None) == fss.EINVAL and b"round" in L.fss_last_error()
+    plan.round, plan.d_peer_msg, plan.d_msg = 1, None, None
+    assert L.match_query(ctypes.byref(plan), 2, None) == fss.EINVAL and b"peer" in L.fss_last_error()
+    plan.round = 0
+    assert L.match_query(ctypes.byref(plan), 1, None) == fss.EINVAL and b"d_msg" in L.fss_last_error()
+    # one party's bits missing
+    keep[0][1].d_bits[1] = None
+    assert L.match_query(ctypes.byref(plan), 2, None) == fss.EINVAL and b"bits of party 1" in L.fss_last_error()
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL
 
 
 def test_eval_all_batch_argument_errors(fss):

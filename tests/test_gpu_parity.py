@@ -327,8 +327,8 @@ def test_match_rejects_bad_plans(fss):
         fss.match_query(plan)
     plan = fss.Plan(1, 1, 1, g.n_vertices, 0, [(0, kb, xhat)]).allocate()
     with pytest.raises(fss.FssError) as e:
-        fss.match_query(plan, party_mask=1)
-    assert e.value.code == fss.EUNSUPPORTED
+        fss.match_query(plan, party_mask=4)
+    assert e.value.code == fss.EINVAL
 
 
 def test_empty_inputs_are_noops(fss):
