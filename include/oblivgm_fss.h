@@ -304,6 +304,21 @@ typedef struct fss_eval_req {
 uint64_t fss_queue_workspace_bytes(uint64_t count);
 int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes, void* stream);
 int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes, void* stream);
+
+/*
+ * fss_eval_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * requests, checks and results, but no d_queue argument and no allocation of
+ * any kind -- the queue (tile counter and descriptors) lives in a file-scope
+ * device array of the library, 64 KiB per GPU, held until the process ends,
+ * and the descriptors reach it as kernel arguments (no pinned staging).
+ * At most FSS_NOALLOC_EVAL_MAX requests per call, else EINVAL.  The array is
+ * the current device's; `stream` must belong to that device.  Every call on
+ * one GPU shares the array: calls that overlap on one GPU (other streams,
+ * other threads) race -- serialise them.
+ */
+#define FSS_NOALLOC_EVAL_MAX 1360
+int fss_eval_batch_noalloc(const fss_eval_req* reqs, uint32_t count, void* stream);
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,
                       uint64_t queue_bytes, void* stream);
 uint64_t match_batch_queue_bytes(const match_plan* plans, uint32_t count);

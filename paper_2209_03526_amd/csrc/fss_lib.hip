@@ -1828,8 +1828,10 @@ uint64_t queue_bytes(uint64_t count) {
     return kQueueHeader + ((count * per + 255) & ~255ull);
 }
 
-// Heaviest descriptors first (ranges, then larger tables), tile offsets, one launch.
-int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_bytes, hipStream_t s) {
+// Heaviest descriptors first (ranges, then larger tables), tile offsets, one
+// launch.  as_args: the descriptors travel as kernel arguments (no staging).
+int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_bytes, hipStream_t s,
+                      bool as_args = false) {
     std::vector<QEval> q;
     q.reserve(descs.size());
     for (int pass = 0; pass < 2; pass++)
@@ -1846,11 +1848,13 @@ int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_byte
         tiles += (e.d.n + tile_rows - 1) / tile_rows;
     }
     if (tiles > 0xFFFFFFF0ull) return fail(FSS_EUNSUPPORTED, "batch: too many tiles");
-    if (!d_ws || ws_bytes < queue_bytes(q.size()))
-        return fail(FSS_ENOMEM, "batch: queue workspace needs %llu bytes", (unsigned long long)queue_bytes(q.size()));
+    const uint64_t need = kQueueHeader + q.size() * sizeof(QEval);
+    if (!d_ws || ws_bytes < need)
+        return fail(FSS_ENOMEM, "batch: queue workspace needs %llu bytes", (unsigned long long)need);
     uint32_t* counter = (uint32_t*)d_ws;
     QEval* dq = (QEval*)((uint8_t*)d_ws + kQueueHeader);
-    int rc = upload(q.data(), q.size() * sizeof(QEval), dq, s);
+    int rc = as_args ? upload_as_arguments(q.data(), q.size() * sizeof(QEval), dq, s)
+                     : upload(q.data(), q.size() * sizeof(QEval), dq, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
     const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
@@ -1905,6 +1909,61 @@ int launch_tail_queue(const match_plan* plans, uint32_t count, const std::vector
         rc = check_launch("k_tail");
         if (rc) return rc;
     }
+    return FSS_OK;
+}
+
+// Requests of a batch evaluation -> descriptors (same checks as the single calls).
+int eval_requests(const fss_eval_req* reqs, uint32_t count, std::vector<EvalDesc>& descs, const char* who) {
+    if (!reqs) return fail(FSS_EINVAL, "%s: reqs is NULL", who);
+    descs.reserve(count);
+    for (uint32_t i = 0; i < count; i++) {
+        const fss_eval_req& r = reqs[i];
+        if (!r.keys) return fail(FSS_EINVAL, "%s: request %u has no keys", who, i);
+        int rc = check_batch(r.keys, r.keys->kind, who);
+        if (rc) return rc;
+        if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "%s: request %u party", who, i);
+        if (r.keys->n == 0) continue;
+        if (!r.d_xhat || !r.d_out_bits || !r.keys->key[r.party] || !aligned256(r.keys->key[r.party]))
+            return fail(FSS_EINVAL, "%s: request %u buffers", who, i);
+        EvalDesc d{};
+        d.key = (const uint8_t*)r.keys->key[r.party];
+        d.xhat = r.d_xhat;
+        d.out = r.d_out_bits;
+        d.n = r.keys->n;
+        d.kind = (uint32_t)r.keys->kind;
+        d.nbits = r.keys->nbits;
+        d.party = (uint32_t)r.party;
+        descs.push_back(d);
+    }
+    return FSS_OK;
+}
+
+// The allocation-free batch evaluation keeps its queue (tile counter and up
+// to FSS_NOALLOC_EVAL_MAX descriptors) in this file-scope device array: one
+// copy per GPU, alive until the process ends, shared by every call on that GPU.
+constexpr uint64_t kScratchBytes = 64 * 1024;
+static_assert(kQueueHeader + FSS_NOALLOC_EVAL_MAX * sizeof(QEval) <= kScratchBytes, "scratch too small");
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current (the array's name is a host-side
+// stand-in, not a device address).
+int scratch_ptr(void** out, const char* who) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FSS_EDEVICE, "%s: no current device", who);
+    if (dev < 0 || dev >= kMaxDevices) return fail(FSS_EUNSUPPORTED, "%s: device %d", who, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(FSS_EDEVICE, "%s: scratch address: %s", who, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return FSS_OK;
 }
 
@@ -2195,29 +2254,24 @@ int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint
                    void* stream) {
     ogm::last_error().clear();
     if (count == 0) return FSS_OK;
-    if (!reqs) return fail(FSS_EINVAL, "fss_eval_batch: reqs is NULL");
     std::vector<EvalDesc> descs;
-    descs.reserve(count);
-    for (uint32_t i = 0; i < count; i++) {
-        const fss_eval_req& r = reqs[i];
-        if (!r.keys) return fail(FSS_EINVAL, "fss_eval_batch: request %u has no keys", i);
-        int rc = check_batch(r.keys, r.keys->kind, "fss_eval_batch");
-        if (rc) return rc;
-        if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "fss_eval_batch: request %u party", i);
-        if (r.keys->n == 0) continue;
-        if (!r.d_xhat || !r.d_out_bits || !r.keys->key[r.party] || !aligned256(r.keys->key[r.party]))
-            return fail(FSS_EINVAL, "fss_eval_batch: request %u buffers", i);
-        EvalDesc d{};
-        d.key = (const uint8_t*)r.keys->key[r.party];
-        d.xhat = r.d_xhat;
-        d.out = r.d_out_bits;
-        d.n = r.keys->n;
-        d.kind = (uint32_t)r.keys->kind;
-        d.nbits = r.keys->nbits;
-        d.party = (uint32_t)r.party;
-        descs.push_back(d);
-    }
+    int rc = eval_requests(reqs, count, descs, "fss_eval_batch");
+    if (rc) return rc;
     return launch_eval_queue(descs, d_queue, queue_bytes_avail, (hipStream_t)stream);
+}
+
+int fss_eval_batch_noalloc(const fss_eval_req* reqs, uint32_t count, void* stream) {
+    ogm::last_error().clear();
+    if (count == 0) return FSS_OK;
+    if (count > FSS_NOALLOC_EVAL_MAX)
+        return fail(FSS_EINVAL, "fss_eval_batch_noalloc: %u requests, at most %d", count, FSS_NOALLOC_EVAL_MAX);
+    std::vector<EvalDesc> descs;
+    int rc = eval_requests(reqs, count, descs, "fss_eval_batch_noalloc");
+    if (rc) return rc;
+    void* d_scratch = nullptr;
+    rc = scratch_ptr(&d_scratch, "fss_eval_batch_noalloc");
+    if (rc) return rc;
+    return launch_eval_queue(descs, d_scratch, kScratchBytes, (hipStream_t)stream, true);
 }
 
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,

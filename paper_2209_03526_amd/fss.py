@@ -89,6 +89,7 @@ def _load():
         "fss_queue_workspace_bytes": ([u64], u64),
         "fss_keygen_batch": ([ctypes.POINTER(fss_keygen_req), u32, P, u64, P], ctypes.c_int),
         "fss_eval_batch": ([ctypes.POINTER(fss_eval_req), u32, P, u64, P], ctypes.c_int),
+        "fss_eval_batch_noalloc": ([ctypes.POINTER(fss_eval_req), u32, P], ctypes.c_int),
         "match_query_batch": ([ctypes.POINTER(match_plan), u32, i32, P, u64, P], ctypes.c_int),
         "fss_set_tuning": ([u32, u32], ctypes.c_int),
         "fss_eval_all": ([i32, ctypes.POINTER(fss_keybatch), u64, u64, P, P], ctypes.c_int),
@@ -119,7 +120,7 @@ def _load():
 LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_shutdown", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
-           "match_query", "match_rounds", "match_batch_queue_bytes", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "match_query_batch",
+           "match_query", "match_rounds", "match_batch_queue_bytes", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "fss_eval_batch_noalloc", "match_query_batch",
            "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
@@ -352,6 +353,21 @@ def _plan_array(plans):
 
 def match_batch_queue_bytes(plans) -> int:
     return int(LIB.match_batch_queue_bytes(_plan_array(plans), len(plans)))
+
+
+NOALLOC_EVAL_MAX = 1360
+
+
+def _eval_reqs(reqs):
+    arr = (fss_eval_req * max(1, len(reqs)))()
+    for i, (party, kb, xhat, out) in enumerate(reqs):
+        arr[i] = fss_eval_req(party, 0, ctypes.pointer(kb.c), _ptr(xhat), _ptr(out))
+    return arr
+
+
+def fss_eval_batch_noalloc(reqs, stream=None):
+    """fss_eval_batch with the library's own per-GPU queue (no allocation)."""
+    _check(LIB.fss_eval_batch_noalloc(_eval_reqs(reqs), len(reqs), _stream(stream)))
 
 
 def match_query_batch(plans, queue: Queue, party_mask: int = 3, stream=None):
