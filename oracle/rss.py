@@ -105,6 +105,14 @@ def reshare(x3, prf_keys, counter: int, nrows: int):
     return [(x3[i] ^ a[i]) & vm for i in range(3)]
 
 
+def from_two_party(y0, y1, prf_keys, counter: int, nrows: int):
+    """Two-party XOR shares of the masked-input path (party 0 held by server
+    P_1, party 1 by P_2) -> three-party RSS shares: (y0, y1, 0) is a
+    three-out-of-three XOR sharing of the same bits, which the re-share of
+    Sec. III-B turns into RSS (P_3 contributes only its zero share)."""
+    return reshare([y0, y1, np.zeros_like(y0)], prf_keys, counter, nrows)
+
+
 def rss_and(x, y, prf_keys, counter: int, nrows: int):
     """AND of two RSS-shared packed bit vectors (Sec. III-B): P_i forms
     z_i = x_i y_i ^ x_i y_{i+1} ^ x_{i+1} y_i from the shares it holds, then

@@ -119,3 +119,41 @@ def test_prf_words_follow_their_definition():
         blk = chacha.blocks([0x76543210, 0xFEDCBA98, 5, 0, 0, 0, 0, 0], w // 16, j, 0, 0, 12)[0]
         s = w % 16
         assert int(got[w]) == int(blk[4 * (s % 4) + s // 4])
+
+
+def test_two_party_fss_bits_to_rss_then_and():
+    """The masked-input path's two-party predicate shares, converted to RSS
+    and ANDed in RSS, reconstruct to the conjunction of the plaintext
+    predicates; each converted share alone, and any two servers' shares
+    together short of all three, look random (Sec. III-B re-share)."""
+    from oracle import fss as ofss
+    n, seed = 3000, 77
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 1 << 12, n).astype(np.uint32)
+    r1 = ofss.masks(seed, 1, 0, n)
+    r2 = ofss.masks(seed, 1, 1, n)
+    xh1 = (x + r1).astype(np.uint32)
+    xh2 = (x + r2).astype(np.uint32)
+    k1 = ofss.keygen_range(32, seed, 1, 0, 100, 2500, r1)
+    k2b = ofss.keygen_range(32, seed, 1, 1, 2000, 4000, r2)
+    y1 = [ofss.pack_bits(ofss.eval_range(32, b, k1[b], xh1)) for b in range(2)]
+    y2 = [ofss.pack_bits(ofss.eval_range(32, b, k2b[b], xh2)) for b in range(2)]
+    keys = [91, 92, 93]
+    p1 = rss.from_two_party(y1[0], y1[1], keys, 0, n)
+    p2 = rss.from_two_party(y2[0], y2[1], keys, 1, n)
+    want1 = ((x >= 100) & (x < 2500)).astype(np.uint8)
+    want2 = ((x >= 2000) & (x < 4000)).astype(np.uint8)
+    np.testing.assert_array_equal(ofss.unpack_bits(p1[0] ^ p1[1] ^ p1[2], n), want1)
+    np.testing.assert_array_equal(ofss.unpack_bits(p2[0] ^ p2[1] ^ p2[2], n), want2)
+    z = rss.rss_and(p1, p2, keys, 2, n)
+    np.testing.assert_array_equal(ofss.unpack_bits(z[0] ^ z[1] ^ z[2], n), want1 & want2)
+    for i in range(3):
+        bits = ofss.unpack_bits(p1[i], n)
+        assert 0.4 < bits.mean() < 0.6
+        pair = ofss.unpack_bits(p1[i] ^ p1[(i + 1) % 3], n)
+        assert 0.4 < pair.mean() < 0.6
+    # a conversion that forgets the zero share of P_3 (z_3 = 0) is caught:
+    # the third share would then be constant
+    bad = [y1[0], y1[1], np.zeros_like(y1[0])]
+    assert not ofss.unpack_bits(bad[2], n).any()
+    assert ofss.unpack_bits(p1[2], n).any()
