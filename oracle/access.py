@@ -1,6 +1,7 @@
 """Oracle for secure neighbouring-vertex access (Alg. 6) over a graph encoded
 as in Sec. V-B / Alg. 1: one-hot IDs in binary RSS, posting lists padded with
-0-vectors (dummy IDs) to a common length.
+0-vectors (dummy IDs) -- per group of k same-type vertices of similar list
+length (Alg. 1), or to one common length (the dense special case).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/fss.py``).
 
@@ -90,18 +91,99 @@ def sec_access(idm_shares, posting_shares, attr_shares, x_count: int, prf_keys, 
     """Alg. 6 for one matched vertex.  idm_shares: three (C,) 0/1 vectors;
     posting_shares: three (C, L_max, Wx) tables; attr_shares: three (X, Wd)
     tables.  Returns (ID record shares, attribute record shares), both lists
-    of three arrays (one row per kept neighbour)."""
+    of three arrays (one row per kept neighbour).
+      1. P_m[l] = XOR_c id_m[c] AND id_{c,l}, re-shared (counter counter0);
+      2. shuffle, open the XOR of each record's bits, keep y = 1;
+      3. per kept ID, d = XOR_x id[x] AND d_x; the kept IDs' attribute
+         records re-shared together (counter counter0 + 1)."""
     c, lmax, wx = posting_shares[0].shape
     rows = [p.reshape(c, lmax * wx) for p in posting_shares]
     pm = selection(idm_shares, rows, prf_keys, counter0)
     table = [p.reshape(lmax, wx) for p in pm]
     keep, ids = compact_valid(table, seeds)
-    attrs = [[], [], []]
+    wd = attr_shares[0].shape[1]
+    if keep.size == 0:
+        return ids, [np.zeros((0, wd), np.uint32) for _ in range(3)]
+    add = [np.zeros((keep.size, wd), np.uint32) for _ in range(3)]
     for k in range(keep.size):
         xb = [np.unpackbits(ids[i][k].astype("<u4").view(np.uint8), bitorder="little")[:x_count]
               for i in range(3)]
-        d = selection(xb, attr_shares, prf_keys, counter0 + 1 + k)
+        d = shuffle.fetch_case1(xb, attr_shares)
         for i in range(3):
-            attrs[i].append(d[i])
-    wd = attr_shares[0].shape[1]
-    return ids, [np.array(a, np.uint32).reshape(keep.size, wd) for a in attrs]
+            add[i][k] = d[i]
+    attrs = rss.reshare([a.reshape(-1) for a in add], prf_keys, counter0 + 1, 32 * keep.size * wd)
+    return ids, [a.reshape(keep.size, wd) for a in attrs]
+
+
+# --------------------------------------------------------------------------- Alg. 1 with k-groups
+
+def group_k(lengths, types, k: int):
+    """Alg. 1's degree protection: the vertices of each type are taken k at a
+    time in order of posting-list length (ties by vertex ID), so that each
+    group holds vertices of similar length, and every list of a group is
+    padded to the group's longest.  A type whose vertex count is not a
+    multiple of k puts the remainder into its last group (a group of at least
+    k whenever the type has k vertices).  Returns (padded lengths, group of
+    each vertex)."""
+    lengths = np.asarray(lengths, np.int64)
+    types = np.asarray(types)
+    padded = np.zeros(lengths.size, np.int64)
+    group = np.full(lengths.size, -1, np.int64)
+    gid = 0
+    for t in np.unique(types):
+        members = np.flatnonzero(types == t)
+        order = members[np.lexsort((members, lengths[members]))]
+        ngroups = max(1, order.size // k)
+        for g in range(ngroups):
+            sel = order[g * k:(g + 1) * k] if g < ngroups - 1 else order[g * k:]
+            padded[sel] = lengths[sel].max()
+            group[sel] = gid
+            gid += 1
+    return padded, group
+
+
+def csr_offsets(padded) -> np.ndarray:
+    return np.concatenate([[0], np.cumsum(np.asarray(padded, np.int64))]).astype(np.int64)
+
+
+def encode_posting_lists_k(adj, x_count: int, padded, slots):
+    """The padded posting lists as one-hot records in CSR order: vertex v's
+    padded[v] records start at offset off[v]; its i-th true neighbour adj[v][i]
+    is the one-hot record at slot slots[v][i] (flat, CSR-aligned), every other
+    record of its list an all-zero dummy ID.  Returns (records (nrec, Wx), off)."""
+    off = csr_offsets(padded)
+    table = np.zeros((int(off[-1]), x_count), np.uint8)
+    at = 0
+    for v, nbrs in enumerate(adj):
+        for i, x in enumerate(nbrs):
+            table[off[v] + int(slots[at + i]), int(x)] = 1
+        at += len(nbrs)
+    return pack_rows(table), off
+
+
+def rss_split_prf(table: np.ndarray, key_a: int, key_b: int, counter: int):
+    """Binary RSS of a table of words (row-major): share 1 = F(key_a, counter)
+    and share 2 = F(key_b, counter) over the table's words (the ChaCha12 PRF of
+    the re-share), share 3 = table ^ share 1 ^ share 2."""
+    n = table.size
+    s1 = rss.prf_words(key_a, counter, n).reshape(table.shape)
+    s2 = rss.prf_words(key_b, counter, n).reshape(table.shape)
+    return [s1, s2, table ^ s1 ^ s2]
+
+
+def sec_access_csr(idm_shares, post_shares, off, attr_shares, x_count: int, prf_keys, seeds, counter0: int = 0):
+    """Alg. 6 over the Alg. 1 encoding (CSR lists of per-group lengths): the
+    selection of step 1 runs over slots l < L_max, where L_max is the longest
+    padded list; a candidate whose list is shorter contributes nothing to the
+    slots beyond it -- the same as padding it with zero records to L_max."""
+    c = off.size - 1
+    lens = np.diff(off)
+    lmax = max(1, int(lens.max()) if c else 1)
+    wx = post_shares[0].shape[1]
+    dense = []
+    for sh in post_shares:
+        d = np.zeros((c, lmax, wx), np.uint32)
+        for v in range(c):
+            d[v, :lens[v]] = sh[off[v]:off[v + 1]]
+        dense.append(d)
+    return sec_access(idm_shares, dense, attr_shares, x_count, prf_keys, seeds, counter0)

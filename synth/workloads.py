@@ -199,6 +199,34 @@ def pack_word_major(bits: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(words.T).astype(np.uint32)
 
 
+def posting_slots(seed: int, lengths: np.ndarray, padded: np.ndarray) -> np.ndarray:
+    """The data owner's random placement of true IDs among the dummy IDs of a
+    padded posting list: for vertex v, the first lengths[v] entries of a
+    seeded permutation of range(padded[v]).  Flat, aligned with the
+    adjacency's CSR order (slot of each true neighbour)."""
+    out = np.zeros(int(np.sum(lengths)), np.uint32)
+    at = 0
+    for v, (n, p) in enumerate(zip(lengths, padded)):
+        if n:
+            out[at:at + n] = _rng(seed, 131, v).permutation(int(p))[:n]
+        at += n
+    return out
+
+
+def posting_graph(seed: int, n: int, x_count: int, max_degree: int, n_types: int = 2) -> tuple:
+    """A candidate table for secAccess: n vertices of n_types types, each with
+    a posting list of distinct neighbour IDs in [0, x_count) (lengths uniform
+    in [0, max_degree], power-law-ish: a few long lists), and one 64-bit
+    attribute record per neighbour ID.  Returns (types, adjacency lists,
+    attributes (x_count, 2) uint32)."""
+    rng = _rng(seed, 141)
+    types = rng.integers(0, n_types, n).astype(np.uint32)
+    deg = np.minimum(rng.zipf(1.8, n) - 1, max_degree)
+    adj = [np.sort(rng.choice(x_count, int(d), replace=False)).astype(np.uint32) for d in deg]
+    attr = rng.integers(0, 2**32, (x_count, 2), dtype=np.uint64).astype(np.uint32)
+    return types, adj, attr
+
+
 # --------------------------------------------------------------------------- workloads
 
 def tiny_graph(seed: int, n_vertices: int = 12, n_edges: int = 30, label_range: int = 4,
