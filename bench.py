@@ -123,15 +123,21 @@ def parse():
                     help="full: edge rows the oracle computes for the CPU baseline (bit-checked vs the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-vertex-filter", action="store_true", help="full: skip the 2^22-row vertex filter key")
-    ap.add_argument("--serve-block", action="store_true", help="full: add the bounded served-vs-plain block")
+    ap.add_argument("--no-serve", action="store_true", help="full: skip the bounded served-vs-plain block")
     ap.add_argument("--graph", action="store_true", help="full: also replay the step as one hipGraph")
     ap.add_argument("--log-rows", type=int, default=LOG_ROWS, help="vertex-filter: rows (log2)")
     ap.add_argument("--workload", default="full", choices=["full", "vertex-filter", "batch64", "serve", "next"])
-    ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates (queries/s)")
+    ap.add_argument("--sweep-rates", default="50,100,200,250,300,350,400,450",
+                    help="serve: offered rates (queries/s) of the token-given sweep")
+    ap.add_argument("--keygen-rates", default="50,200", help="serve: rates of the keygen-included runs ('' = none)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="serve: arrival window per rate")
-    ap.add_argument("--budget-gb", type=float, default=96.0, help="batch64: key memory budget of the batched runner")
-    ap.add_argument("--wave-gb", type=float, default=0.0,
-                    help="serve: cap on the keys of one wave (0: a wave may fill the 48 GB key arena)")
+    ap.add_argument("--slo-ms", default="50,100,250",
+                    help="serve: p99 latency objectives (ms); the sweep of a path stops past the largest")
+    ap.add_argument("--block-rates", default="100,400", help="full: rates of the bounded serving block")
+    ap.add_argument("--block-seconds", type=float, default=15.0, help="full: arrival window per rate of the block")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="batch64: key memory budget of the batched runner (0: 96 GB); serve: admission budget "
+                         "(0: 64 GB)")
     ap.add_argument("--chunk-log-rows", type=int, default=20, help="batch64: rows per keygen/eval chunk (log2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
@@ -166,13 +172,15 @@ def main():
         out = run_vertex_filter(args, torch, fss, dev, args.steps, args.warmup)
         print(json.dumps(out), flush=True)
         return
-    out = run_full(args, torch, fss, dev)
+    log("generating the 2^22 / 2^25 Chung-Lu graph")
+    graph3, query3 = synth.config3(3)
+    out = run_full(args, torch, fss, dev, graph3, query3)
     if not args.no_vertex_filter:
         vf = run_vertex_filter(args, torch, fss, dev, 3, 1)
         out["vertex_filter_2p22"] = {k: vf[k] for k in ("value", "unit", "ms_per_step", "eval_only_evals_per_s",
                                                          "kernels", "config")}
-    if args.serve_block:
-        out["serving"] = serve_block(args, torch, fss, dev)
+    if not args.no_serve:
+        out["serving"] = serve_block(args, torch, fss, dev, graph3)
     print(json.dumps(out), flush=True)
 
 
@@ -218,13 +226,11 @@ def roofline_of(name: str, k: dict) -> dict:
             "aes_blocks_per_launch": k["aes_blocks"], "ms_per_launch": k["ms"]}
 
 
-def run_full(args, torch, fss, dev):
+def run_full(args, torch, fss, dev, graph, query):
     """The full path query a -> b -> c over the Chung-Lu graph (2^22 vertices,
     2^25 edges), 4 vertex and 2 edge predicates, both parties (Alg. 2)."""
     from paper_2209_03526_amd import autotune
 
-    log("generating the 2^22 / 2^25 Chung-Lu graph")
-    graph, query = synth.config3(3)
     shares = synth.share_columns(SEED, graph.vcols)
     shares.update({"e:" + k: v for k, v in synth.share_columns(SEED + 1, graph.ecols).items()})
     masks = synth.pred_masks(SEED, query, graph)
@@ -534,7 +540,8 @@ def run_batch64(args, torch, fss, dev):
             del kbs
         return res
 
-    runner = ChunkedRunner(int(args.budget_gb * 1e9), chunk_rows=1 << args.chunk_log_rows, device=dev)
+    budget_gb = args.budget_gb or 96.0
+    runner = ChunkedRunner(int(budget_gb * 1e9), chunk_rows=1 << args.chunk_log_rows, device=dev)
     # autotune the persistent evaluation shape on one representative wave
     probe = [j for j in jobs if any(p["rows"] >= 1 << 20 for p in j.preds)][:1] or jobs[:1]
     autotune.tune(lambda: runner.run(probe), sum(p["rows"] for j in probe for p in j.preds))
@@ -587,7 +594,7 @@ def run_batch64(args, torch, fss, dev):
         "plain_qps": 64 / times["plain"], "speedup_vs_plain": times["plain"] / times["batched"],
         "batched_ms": times["batched"] * 1e3, "plain_ms": times["plain"] * 1e3,
         "walks": walks, "batched_evals_per_s_incl_keygen": walks / times["batched"],
-        "waves": waves_per_pass, "budget_gb": args.budget_gb, "chunk_rows": 1 << args.chunk_log_rows,
+        "waves": waves_per_pass, "budget_gb": budget_gb, "chunk_rows": 1 << args.chunk_log_rows,
         "tuning": {str(k): v for k, v in autotune.chosen().items()},
         "bit_exact_batched_vs_plain": bool(exact), "graph_replay": graph_replay, "dtype": "u32", "data": "synthetic",
         "persistent_kernels": persistent,
@@ -596,23 +603,196 @@ def run_batch64(args, torch, fss, dev):
     print(json.dumps(out), flush=True)
 
 
+class ServeEnv:
+    """The resident Chung-Lu graph (2^22 vertices, 2^25 edges), the 64-shape
+    query mix and, for the token-given protocol, every mix entry's token dealt
+    before the run."""
+
+    def __init__(self, torch, fss, dev, graph=None, pool=True):
+        from paper_2209_03526_amd import serving
+        self.torch, self.fss, self.dev, self.serving = torch, fss, dev, serving
+        if graph is None:
+            log("generating the 2^22 / 2^25 Chung-Lu graph")
+            graph, _ = synth.config3(3)
+        self.g = graph
+        self.vsh = synth.share_columns(SEED, graph.vcols)
+        self.esh = synth.share_columns(SEED + 1, graph.ecols)
+        self.rg = serving.resident_graph(graph.n_vertices, graph.n_edges, graph.src, graph.dst, self.vsh, self.esh,
+                                         dev)
+        self.mix = synth.batch_queries(4, graph, count=64)
+        self.pool = None
+        if pool:
+            t0 = time.perf_counter()
+            self.pool = serving.TokenPool(self.rg, self.mix, SEED, dev)
+            log(f"tokens of the 64 mix entries dealt: {self.pool.key_bytes / 1e9:.1f} GB of keys in "
+                f"{time.perf_counter() - t0:.1f} s")
+
+    def free(self):
+        self.pool = None
+        self.rg = None
+        self.torch.cuda.empty_cache()
+
+    def requests(self, rate, seconds, seed):
+        n = max(8, int(round(rate * seconds)))
+        arrivals = self.serving.poisson_arrivals(rate, n, seed)
+        entries = np.random.default_rng([seed, 1]).integers(0, len(self.mix), n)
+        return [self.serving.GivenRequest(i, float(t), int(e)) for i, (t, e) in enumerate(zip(arrivals, entries))]
+
+    def make(self, name, budget):
+        s = self.serving
+        if name == "served":
+            return s.GivenServedPath(self.rg, self.pool, budget, device=self.dev)
+        return s.GivenPlainPath(self.rg, self.pool, device=self.dev, sync=(name == "plain"))
+
+    def run(self, name, rate, seconds, seed, budget, keep=None):
+        """One path at one offered rate; `keep` (dict) receives the first output
+        of each mix entry.  The run is cut (the rest counted as never served)
+        once it is twice its arrival window plus 10 s old."""
+        torch = self.torch
+        reqs = self.requests(rate, seconds, seed)
+        path = self.make(name, budget)
+        seen = set()
+        for r in reqs:
+            r.keep = r.entry not in seen
+            seen.add(r.entry)
+        start = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        path.run(reqs, start, t0, deadline_s=2 * seconds + 10)
+        wall = time.perf_counter() - t0
+        res = self.serving.summarize(reqs, wall)
+        res["offered_qps"] = rate
+        if name == "served":
+            res.update(waves=path.waves, batches=path.batches, max_wave=path.max_wave, max_in_flight=path.max_in_flight,
+                       peak_admitted_gb=round(path.max_used / 1e9, 3))
+        if keep is not None:
+            for r in reqs:
+                if r.keep and r.done_event is not None and r.entry not in keep:
+                    keep[r.entry] = self.serving.given_outputs(r, self.pool)
+        log(f"{name} at {rate:g} q/s: {res}")
+        return res
+
+    def oracle_check(self, outs, rows_per_entry=8):
+        """Sampled rows of each kept output against the oracle (same tokens:
+        same seeds, masks from the dealer's generator)."""
+        from oracle import fss as ofss
+        from oracle import match as omatch
+        ok = True
+        for e, out in sorted(outs.items()):
+            q, rows = self.mix[e]
+            view, erows = synth.candidate_view(self.g, rows)
+            sh = {k: v for k, v in self.vsh.items()}
+            sh.update({"e:" + k: v for k, v in self.esh.items()})
+            vsh = synth.view_shares(sh, self.g, view, erows)
+            masks = [ofss.masks(SEED, q.query_id, k, synth.rows_of_target(view, q, p.target))
+                     for k, p in enumerate(q.preds)]
+            nrows = view.n_vertices if q.n_qv == 1 else view.n_edges
+            if nrows == 0:
+                continue
+            sample = np.unique(np.random.default_rng([SEED, e]).integers(0, nrows, rows_per_entry))
+            want = omatch.sampled_outputs(NBITS, SEED, view, q, vsh, masks, sample)
+            w = (nrows + 31) // 32
+            for j in range(want.shape[0]):
+                for b in range(2):
+                    got = ofss.unpack_bits(out[b][j * w:(j + 1) * w], nrows)[sample]
+                    ok &= bool(np.array_equal(got, want[j, b]))
+        return ok
+
+
+def max_rate_within(results, slo_ms):
+    """Highest offered rate whose p99 meets the SLO (and all requests served)."""
+    best = None
+    for r in results:
+        if r["p99_ms"] <= slo_ms and r["served"] == r["requests"]:
+            best = r if best is None or r["offered_qps"] > best["offered_qps"] else best
+    return best
+
+
+def serve_sweep(env, names, rates, seconds, slos, budget, keep):
+    """Each path at increasing offered rates until its p99 misses the largest
+    SLO; per SLO, the highest rate within it."""
+    out = {}
+    for name in names:
+        res = []
+        for i, rate in enumerate(rates):
+            res.append(env.run(name, rate, seconds, 1000 + i, budget, keep.setdefault(name, {})))
+            env.torch.cuda.empty_cache()
+            if res[-1]["p99_ms"] > max(slos) or res[-1]["served"] < res[-1]["requests"]:
+                break
+        out[name] = {"sweep": res, "at_slo": {}}
+        for slo in slos:
+            best = max_rate_within(res, slo)
+            out[name]["at_slo"][str(int(slo))] = {
+                "max_qps": best["qps"] if best else 0.0, "offered_qps": best["offered_qps"] if best else None,
+                "p50_ms": best["p50_ms"] if best else None, "p99_ms": best["p99_ms"] if best else None}
+    return out
+
+
+def compare_outputs(keep):
+    """Every path's kept output of a mix entry equals the served path's."""
+    ref = keep.get("served", {})
+    same = True
+    for name, outs in keep.items():
+        for e, o in outs.items():
+            if e in ref:
+                same &= all(np.array_equal(o[b], ref[e][b]) for b in range(2))
+    return same
+
+
 def run_serve(args, torch, fss, dev):
-    """Serving over the resident 2^22 / 2^25 power-law graph: Poisson arrivals
-    of the 64-shape mix (fresh query id, masks and keys per request), served
-    path (continuous batching, admission by a 64 GB budget of keys and
-    intermediate shares) against the plain one-at-a-time path; p50 / p99 and
-    queries/s per rate, and a bit-exact comparison of every request's shares."""
+    """Serving over the resident 2^22 / 2^25 Chung-Lu graph, Poisson arrivals
+    of the 64-shape mix.  Token given (primary): each path swept over offered
+    rates (args.serve_seconds of arrivals each) up to the first whose p99
+    misses the SLO; the ratio of the served path's highest rate within the SLO
+    to the plain path's.  Then the keygen-inclusive protocol at the configured
+    rates."""
+    env = ServeEnv(torch, fss, dev)
+    rates = [float(r) for r in args.sweep_rates.split(",")]
+    budget = int(args.budget_gb * 1e9) if args.budget_gb else 64 * 10**9
+    for name in ("plain", "served"):           # warm-up (allocator pools, first launches)
+        env.run(name, 200.0, 1.0, 999, budget)
+    keep = {}
+    slos = [float(x) for x in args.slo_ms.split(",")]
+    sweep = serve_sweep(env, ["plain", "served", "plain_pipelined"], rates, args.serve_seconds, slos, budget, keep)
+    exact = compare_outputs(keep)
+    oracle_ok = env.oracle_check(keep.get("served", {}))
+    ratios = {}
+    for slo in sweep["plain"]["at_slo"]:
+        p = sweep["plain"]["at_slo"][slo]["max_qps"]
+        pp = sweep["plain_pipelined"]["at_slo"][slo]["max_qps"]
+        sv = sweep["served"]["at_slo"][slo]["max_qps"]
+        ratios[slo] = {"served_qps": sv, "plain_qps": p, "plain_pipelined_qps": pp,
+                       "served_vs_plain": (sv / p) if p else None, "served_vs_plain_pipelined": (sv / pp) if pp else None}
+    main_slo = str(int(slos[len(slos) // 2]))
+    out = {"metric": "served vs plain queries/s at equal p99 (token given), Poisson arrivals",
+           "value": ratios[main_slo]["served_qps"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "slo_p99_ms": float(main_slo), "seconds_per_rate": args.serve_seconds, "at_equal_p99": ratios,
+           "token_given": sweep, "bit_exact_across_paths": bool(exact), "oracle_sampled_rows_ok": bool(oracle_ok),
+           "token_pool_gb": round(env.pool.key_bytes / 1e9, 1), "budget_gb": budget / 1e9,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "serve: Chung-Lu 2^22 vertices / 2^25 edges resident, 64-shape query mix "
+                                  "(1-5 predicates, 1-4 query vertices, 2^12..2^22 candidate rows)"},
+           "paths": {"served": "continuous batching: the requests that arrive while <= 2 waves run form the next "
+                               "wave (one persistent evaluation launch + one match_query_batch)",
+                     "plain": "one request at a time, results awaited before the next request starts",
+                     "plain_pipelined": "one request at a time on one stream, host runs ahead (no wait)"}}
+    if args.keygen_rates:
+        env.free()
+        out["keygen_included"] = serve_keygen_included(args, torch, fss, dev, env.g)
+    print(json.dumps(out), flush=True)
+
+
+def serve_keygen_included(args, torch, fss, dev, graph):
+    """Each request's token dealt on arrival, inside its latency: served
+    (chunked waves over a 48 GB key arena) vs plain, at the given rates."""
     import copy
 
     from paper_2209_03526_amd import serving
-
-    log("generating the 2^22 / 2^25 power-law graph")
-    g, _ = synth.config3(3)
-    vsh = synth.share_columns(SEED, g.vcols)
-    esh = synth.share_columns(SEED + 1, g.ecols)
-    rg = serving.resident_graph(g.n_vertices, g.n_edges, g.src, g.dst, vsh, esh, dev)
-    mix = synth.batch_queries(4, g, count=64)
-    log("graph resident")
+    vsh = synth.share_columns(SEED, graph.vcols)
+    esh = synth.share_columns(SEED + 1, graph.ecols)
+    rg = serving.resident_graph(graph.n_vertices, graph.n_edges, graph.src, graph.dst, vsh, esh, dev)
+    mix = synth.batch_queries(4, graph, count=64)
 
     def requests(arrivals, base):
         out = []
@@ -629,53 +809,42 @@ def run_serve(args, torch, fss, dev):
         t0 = time.perf_counter()
         start.record()
         path.run(reqs, start, t0)
-        wall = time.perf_counter() - t0
-        return serving.summarize(reqs, wall), [serving.outputs(r) for r in reqs]
+        return serving.summarize(reqs, time.perf_counter() - t0)
 
-    budget = 64 * 10**9
-
-    def served_path():
-        return serving.ServedPath(rg, budget, key_arena_bytes=48 * 10**9, chunk_rows=1 << 20, device=dev,
-                                  wave_bytes=int(args.wave_gb * 1e9) if args.wave_gb else None)
-
-    paths = {"served": served_path,
-             "plain": lambda: serving.PlainPath(rg, device=dev, sync=True),
-             "plain_pipelined": lambda: serving.PlainPath(rg, device=dev, sync=False)}
-    # untimed warm-up of every path (allocator pools, first launches)
+    paths = {"served": lambda: serving.ServedPath(rg, 64 * 10**9, key_arena_bytes=48 * 10**9, chunk_rows=1 << 20,
+                                                  device=dev),
+             "plain": lambda: serving.PlainPath(rg, device=dev, sync=True)}
     for name, make in paths.items():
-        run(make(), requests(np.zeros(min(16, len(mix))), 90000))
+        run(make(), requests(np.zeros(8), 90000))
         torch.cuda.empty_cache()
-        log(f"warm-up of the {name} path done")
+    res = {}
+    for rate in [float(r) for r in args.keygen_rates.split(",")]:
+        arrivals = serving.poisson_arrivals(rate, max(8, int(rate * args.serve_seconds)), int(rate))
+        res[str(int(rate))] = {name: run(make(), requests(arrivals, 100000)) for name, make in paths.items()}
+        log(f"keygen included, {rate:g} q/s: {res[str(int(rate))]}")
+        torch.cuda.empty_cache()
+    return res
 
-    results = {}
-    exact = True
-    for rate in [float(r) for r in args.rates.split(",")]:
-        count = int(min(args.serve_max, max(8, rate * args.serve_seconds)))
-        arrivals = serving.poisson_arrivals(rate, count, int(rate))
-        res, outs = {}, {}
-        for name, make in paths.items():
-            p = make()
-            res[name], outs[name] = run(p, requests(arrivals, 100000))
-            if name == "served":
-                res[name].update(waves=p.waves, max_in_flight=p.max_in_flight)
-            log(f"rate {rate:.0f}: {name} {res[name]}")
-            torch.cuda.empty_cache()
-        same = all(np.array_equal(outs["served"][i][b], outs[n][i][b])
-                   for n in ("plain", "plain_pipelined") for i in range(count) for b in range(2))
-        exact &= same
-        res["qps_ratio_vs_plain"] = res["served"]["qps"] / res["plain"]["qps"]
-        res["qps_ratio_vs_plain_pipelined"] = res["served"]["qps"] / res["plain_pipelined"]["qps"]
-        res["bit_exact"] = same
-        results[str(int(rate))] = res
-    out = {"metric": "served vs plain queries/s and p50/p99 latency (ms), Poisson arrivals",
-           "value": max(v["served"]["qps"] for v in results.values()), "unit": "queries/s", "n_gpus": 1,
-           "higher_is_better": True, "rates": results, "bit_exact_served_vs_plain": bool(exact),
-           "budget_gb": 64, "wave_gb": args.wave_gb or None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "serve: Chung-Lu 2^22 vertices / 2^25 edges resident, 64-shape query mix"},
-           "paths": {"served": "continuous batching, admission by memory (64 GB: 48 GB key arena + intermediates)",
-                     "plain": "one request at a time, results awaited before the next request starts",
-                     "plain_pipelined": "one request at a time on one stream, host runs ahead (no wait)"}}
-    print(json.dumps(out), flush=True)
+
+def serve_block(args, torch, fss, dev, graph=None):
+    """Bounded served-vs-plain block for the headline line (token given): both
+    paths at one offered rate below the plain path's saturation and one at it,
+    args.block_seconds of arrivals each."""
+    env = ServeEnv(torch, fss, dev, graph)
+    budget = 64 * 10**9
+    for name in ("plain", "served"):
+        env.run(name, 200.0, 1.0, 999, budget)
+    keep, res = {}, {}
+    for rate in [float(r) for r in args.block_rates.split(",")]:
+        res[str(int(rate))] = {name: env.run(name, rate, args.block_seconds, 2000 + int(rate), budget,
+                                             keep.setdefault(name, {})) for name in ("plain", "served")}
+        res[str(int(rate))]["qps_ratio"] = res[str(int(rate))]["served"]["qps"] / res[str(int(rate))]["plain"]["qps"]
+    out = {"protocol": "token given (keys dealt before arrival; latency from arrival to result shares)",
+           "rates": res, "bit_exact_across_paths": bool(compare_outputs(keep)),
+           "oracle_sampled_rows_ok": bool(env.oracle_check(keep.get("served", {}), 4)),
+           "seconds_per_rate": args.block_seconds, "token_pool_gb": round(env.pool.key_bytes / 1e9, 1)}
+    env.free()
+    return out
 
 
 def run_next(args, torch, fss, dev):

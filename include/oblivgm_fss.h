@@ -379,6 +379,16 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
  *   then re-shares as above.
  * The outputs d_z must not overlap the inputs.
  */
+/*
+ * rss_from_fss: the masked-input path's two-party XOR shares -> RSS (the
+ *   re-share of Sec. III-B applied to (y0, y1, 0)): the two FSS parties are
+ *   servers P_1 (d_y[0], party 0's packed bits) and P_2 (d_y[1]); P_3's
+ *   three-out-of-three share is zero, so z_1 = y0 ^ <alpha>_1,
+ *   z_2 = y1 ^ <alpha>_2, z_3 = <alpha>_3 with <alpha>_i = F(k_i, j) ^ F(k_{i-1}, j)
+ *   (j = counter), pad bits cleared.  XOR of the z_i = XOR of the y_b.
+ */
+int rss_from_fss(uint64_t nrows, const uint32_t* const d_y[2], const uint64_t prf_keys[3], uint32_t counter,
+                 uint32_t* const d_z[3], void* stream);
 int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf_keys[3], uint32_t counter,
                 uint32_t* const d_z[3], void* stream);
 int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],
@@ -470,6 +480,60 @@ int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_tabl
  * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */
 int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu);
 int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu);
+
+/*
+ * The paper's graph encoding with k-groups (Alg. 1) and secure neighbouring-
+ * vertex access (Alg. 6) over it.  IDs of the neighbour type are 0 .. X-1
+ * (x_bits = X) and travel as one-hot records of ceil(X/32) words; posting
+ * lists are stored in CSR order, vertex v's padded list at records
+ * [off[v], off[v+1]).
+ *
+ * rss_group_k (host arrays): Alg. 1's degree protection for one posting-list
+ *   type.  The vertices of each type are taken k at a time in order of list
+ *   length (ties by vertex ID), the remainder joining the type's last group
+ *   (every group holds at least k vertices when the type has k); each list is
+ *   padded to its group's longest: padded[v] receives that length, group[v]
+ *   (NULL: not written) the group number (types in increasing order, groups
+ *   in length order).  EINVAL for NULL arguments or k = 0.
+ * rss_enc_posting_lists (device): the padded lists as binary RSS of one-hot
+ *   records.  d_adj_off (n+1) / d_adj: the true neighbour IDs of each vertex
+ *   in CSR order; d_slot: the slot of each true ID within its padded list (the
+ *   data owner's random placement); d_off (n+1): prefix sums of the padded
+ *   lengths, nrec = off[n] records.  Every other record is the all-zero dummy
+ *   ID.  Share 1 = F(split_keys[0], counter) and share 2 = F(split_keys[1],
+ *   counter) over the table's words (row-major; F is the PRF of rss_reshare),
+ *   share 3 = records ^ share 1 ^ share 2.  Workspace: 4 * nrec bytes.  A slot
+ *   outside its padded list or an ID >= x_bits is skipped (no access out of
+ *   bounds).
+ * rss_sec_access (device, Alg. 6 for one matched vertex): d_idm: the three RSS
+ *   shares of the matched vertex's one-hot ID over the ncand candidates (packed
+ *   bits); d_off / d_post: the candidates' padded posting lists (as made
+ *   above); lmax: the longest padded list (public); d_attr: the three shares of
+ *   the X attribute records of the neighbour type (attr_words words each).
+ *     1. P_m[l] = XOR_c id_m[c] AND id_{c,l} for l < lmax (a list shorter than l
+ *        adds nothing), re-shared into RSS (prf_keys, counter);
+ *     2. the lmax records shuffled (seeds, Alg. 5), the XOR of each record's bits
+ *        opened, the records with 1 (valid IDs) kept in shuffled order:
+ *        d_ids[i] (capacity lmax x ceil(X/32)), their shuffled positions
+ *        d_rows_out, their number *d_count (device memory);
+ *     3. per kept ID, d = XOR_x id[x] AND d_x; the kept IDs' attribute records
+ *        re-shared together (counter + 1) into d_attrs[i] (capacity lmax x
+ *        attr_words; rows beyond *d_count are shares of zero).
+ *   Workspace: rss_sec_access_workspace_bytes(lmax, x_bits, attr_words).  lmax
+ *   is 1..65535.  The shuffle takes the library's own streams as rss_shuffle
+ *   does (not for graph capture).
+ */
+int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint32_t k, uint32_t* padded,
+                uint32_t* group);
+int rss_enc_posting_lists(uint64_t n, uint32_t x_bits, const uint32_t* d_adj_off, const uint32_t* d_adj,
+                          const uint32_t* d_slot, const uint32_t* d_off, uint64_t nrec, const uint64_t split_keys[2],
+                          uint32_t counter, uint32_t* const d_out[3], void* d_work, uint64_t work_bytes, void* stream);
+uint64_t rss_sec_access_workspace_bytes(uint32_t lmax, uint32_t x_bits, uint32_t attr_words);
+int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[3], const uint32_t* d_off,
+                   uint32_t lmax, const uint32_t* const d_post[3], uint32_t attr_words,
+                   const uint32_t* const d_attr[3], const uint64_t prf_keys[3], uint32_t counter,
+                   const uint64_t seeds[3], uint32_t* const d_ids[3], uint32_t* const d_attrs[3],
+                   uint32_t* d_rows_out, uint32_t* d_count, void* d_work, uint64_t work_bytes, void* stream);
 
 #ifdef __cplusplus
 }

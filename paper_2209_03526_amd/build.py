@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "fss_lib.hip"), os.path.join(HERE, "csrc", "shuffle.hip")]
+SRCS = [os.path.join(HERE, "csrc", "fss_lib.hip"), os.path.join(HERE, "csrc", "shuffle.hip"),
+        os.path.join(HERE, "csrc", "access.hip")]
 SRC = SRCS[0]
 HEADERS = [os.path.join(HERE, "csrc", "aes_gfx950.hpp"), os.path.join(HERE, "csrc", "chacha_gfx950.hpp"),
            os.path.join(HERE, "csrc", "common.hpp"),

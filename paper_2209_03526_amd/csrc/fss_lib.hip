@@ -701,7 +701,7 @@ __global__ void k_and_close(uint64_t nwords, uint64_t nrows, uint32_t party, con
 
 struct RssArgs {
     ChachaKey prf[3];       // F(k_i, .) = ChaCha12 under (k_i, domain 5)
-    const uint32_t* x[3];
+    const uint32_t* x[3];   // re-share: x[2] may be null (a share of zero: the two-party conversion)
     const uint32_t* y[3];   // null for a plain re-share
     uint32_t* z[3];
     uint64_t nrows;
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kRssBlock) void k_rss(RssArgs A) {
     if (whole) {
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            xv[i] = ((const uint4*)A.x[i])[m];
+            xv[i] = A.x[i] ? ((const uint4*)A.x[i])[m] : make_uint4(0u, 0u, 0u, 0u);   // null: a zero share
             yv[i] = A.y[0] ? ((const uint4*)A.y[i])[m] : make_uint4(0u, 0u, 0u, 0u);
         }
     }
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(kRssBlock) void k_rss(RssArgs A) {
                 const uint32_t xi = A.x[i][w], xn = A.x[nx][w], yi = A.y[i][w], yn = A.y[nx][w];
                 zi = (xi & yi) ^ (xi & yn) ^ (xn & yi);
             } else {
-                zi = A.x[i][w];
+                zi = A.x[i] ? A.x[i][w] : 0u;
             }
             const uint32_t fi = q == 0 ? f[i].x : q == 1 ? f[i].y : q == 2 ? f[i].z : f[i].w;
             const uint32_t fp = q == 0 ? f[pv].x : q == 1 ? f[pv].y : q == 2 ? f[pv].z : f[pv].w;
@@ -2103,13 +2103,14 @@ int fss_eval_all_batch(const fss_eval_all_req* reqs, uint32_t count, void* strea
 }
 
 static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* const* d_y, const uint64_t* prf_keys,
-            uint32_t counter, uint32_t* const* d_z, void* stream, const char* who) {
+            uint32_t counter, uint32_t* const* d_z, void* stream, const char* who, bool third_zero = false) {
     ogm::last_error().clear();
     if (nrows == 0) return FSS_OK;
     if (!d_x || !d_z || !prf_keys) return fail(FSS_EINVAL, "%s: NULL argument", who);
     RssArgs A{};
     for (int i = 0; i < 3; i++) {
-        if (!d_x[i] || !d_z[i] || (d_y && !d_y[i])) return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
+        if ((!d_x[i] && !(third_zero && i == 2)) || !d_z[i] || (d_y && !d_y[i]))
+            return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
         A.prf[i] = ogm::chacha_key(prf_keys[i], 5);
         A.x[i] = d_x[i];
         A.y[i] = d_y ? d_y[i] : nullptr;
@@ -2133,6 +2134,13 @@ static int rss_run(uint64_t nrows, const uint32_t* const* d_x, const uint32_t* c
 int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf_keys[3], uint32_t counter,
                 uint32_t* const d_z[3], void* stream) {
     return rss_run(nrows, d_x, nullptr, prf_keys, counter, d_z, stream, "rss_reshare");
+}
+
+int rss_from_fss(uint64_t nrows, const uint32_t* const d_y[2], const uint64_t prf_keys[3], uint32_t counter,
+                 uint32_t* const d_z[3], void* stream) {
+    if (!d_y) { ogm::last_error() = "rss_from_fss: NULL y"; return FSS_EINVAL; }
+    const uint32_t* x[3] = {d_y[0], d_y[1], nullptr};
+    return rss_run(nrows, x, nullptr, prf_keys, counter, d_z, stream, "rss_from_fss", true);
 }
 
 int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const d_y[3], const uint64_t prf_keys[3],

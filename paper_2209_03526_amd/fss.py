@@ -96,6 +96,7 @@ def _load():
         "fss_eval_all_batch": ([ctypes.POINTER(fss_eval_all_req), u32, P], ctypes.c_int),
         "fss_dealer_masks": ([u64, u32, u32, u32, u64, P, P], ctypes.c_int),
         "rss_reshare": ([u64, P, P, u32, P, P], ctypes.c_int),
+        "rss_from_fss": ([u64, P, P, u32, P, P], ctypes.c_int),
         "rss_and": ([u64, P, P, P, u32, P, P], ctypes.c_int),
         "rss_shuffle_workspace_bytes": ([u64, u32], u64),
         "rss_shuffle": ([u64, u32, P, P, P, P, u64, P], ctypes.c_int),
@@ -109,6 +110,10 @@ def _load():
         "rss_compact_valid": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
+        "rss_group_k": ([u64, P, P, u32, P, P], ctypes.c_int),
+        "rss_enc_posting_lists": ([u64, u32, P, P, P, P, u64, P, u32, P, P, u64, P], ctypes.c_int),
+        "rss_sec_access_workspace_bytes": ([u32, u32, u32], u64),
+        "rss_sec_access": ([u64, u32, P, P, u32, P, u32, P, P, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -121,11 +126,12 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_shutdown", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "match_rounds", "match_batch_queue_bytes", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "fss_eval_batch_noalloc", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_and",
+           "fss_set_tuning", "fss_get_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_from_fss", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
            "rss_fetch_many_workspace_bytes",
-           "rss_fetch_many", "rss_compact_valid")
+           "rss_fetch_many", "rss_compact_valid", "rss_group_k", "rss_enc_posting_lists",
+           "rss_sec_access_workspace_bytes", "rss_sec_access")
 
 
 def _check(rc: int):
@@ -423,6 +429,13 @@ def rss_reshare(nrows: int, x3, prf_keys, counter: int, z3, stream=None):
     _check(LIB.rss_reshare(nrows, _ptr3(x3), keys, counter, _ptr3(z3), _stream(stream)))
 
 
+def rss_from_fss(nrows: int, y2, prf_keys, counter: int, z3, stream=None):
+    """y2: (party 0 bits, party 1 bits) of the masked-input path -> RSS z3."""
+    keys = (ctypes.c_uint64 * 3)(*prf_keys)
+    _check(LIB.rss_from_fss(nrows, (ctypes.c_void_p * 2)(*[_ptr(t) for t in y2]), keys, counter, _ptr3(z3),
+                            _stream(stream)))
+
+
 def rss_and(nrows: int, x3, y3, prf_keys, counter: int, z3, stream=None):
     keys = (ctypes.c_uint64 * 3)(*prf_keys)
     _check(LIB.rss_and(nrows, _ptr3(x3), _ptr3(y3), keys, counter, _ptr3(z3), _stream(stream)))
@@ -471,4 +484,37 @@ def rss_compact_valid(nrec: int, nwords: int, table3, seeds, out3, rows_out, cou
     work = torch.empty(max(nbytes, 256), dtype=torch.int8, device=table3[0].device)
     _check(LIB.rss_compact_valid(nrec, nwords, _ptr3(table3), (ctypes.c_uint64 * 3)(*seeds), _ptr3(out3),
                                  _ptr(rows_out), _ptr(count), _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+# --------------------------------------------------------------------------- Alg. 1 / Alg. 6
+
+def rss_group_k(lengths, types, k: int):
+    """Host arrays in, (padded lengths, group numbers) out (numpy uint32)."""
+    import numpy as np
+    lengths = np.ascontiguousarray(lengths, np.uint32)
+    types = np.ascontiguousarray(types, np.uint32)
+    padded = np.zeros(lengths.size, np.uint32)
+    group = np.zeros(lengths.size, np.uint32)
+    _check(LIB.rss_group_k(lengths.size, lengths.ctypes.data, types.ctypes.data, k, padded.ctypes.data,
+                           group.ctypes.data))
+    return padded, group
+
+
+def rss_enc_posting_lists(n: int, x_bits: int, adj_off, adj, slot, off, nrec: int, split_keys, counter: int, out3,
+                          stream=None):
+    work = torch.empty(max(4 * nrec, 256), dtype=torch.uint8, device=out3[0].device)
+    _check(LIB.rss_enc_posting_lists(n, x_bits, _ptr(adj_off), _ptr(adj), _ptr(slot), _ptr(off), nrec,
+                                     (ctypes.c_uint64 * 2)(*split_keys), counter, _ptr3(out3), _ptr(work),
+                                     work.numel(), _stream(stream)))
+    return work
+
+
+def rss_sec_access(ncand: int, x_bits: int, idm3, off, lmax: int, post3, attr_words: int, attr3, prf_keys,
+                   counter: int, seeds, ids3, attrs3, rows_out, count, stream=None):
+    nbytes = int(LIB.rss_sec_access_workspace_bytes(lmax, x_bits, attr_words))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=ids3[0].device)
+    _check(LIB.rss_sec_access(ncand, x_bits, _ptr3(idm3), _ptr(off), lmax, _ptr3(post3), attr_words, _ptr3(attr3),
+                              (ctypes.c_uint64 * 3)(*prf_keys), counter, (ctypes.c_uint64 * 3)(*seeds), _ptr3(ids3),
+                              _ptr3(attrs3), _ptr(rows_out), _ptr(count), _ptr(work), work.numel(), _stream(stream)))
     return work

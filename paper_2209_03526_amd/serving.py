@@ -1,20 +1,31 @@
 """Serving loop over a graph resident in HBM.
 
 Requests (path queries over candidate tables of the resident graph) arrive
-over time.  The served path admits them in arrival order while the device
-memory they need (masks, opened values, share bits, plan workspace, candidate
-edge tables) fits the budget left next to the key arena, and runs continuous
-batching: every wave takes the not-yet-evaluated row chunks of all admitted
-requests, in arrival order, up to the key arena -- so requests that arrived
-while others were on the GPU join the next wave -- as one persistent dealer
-launch and one persistent evaluation launch.  A request whose predicate bits
-are complete is finished (ANDs, joins) right after that wave.  The plain path
-serves one request at a time with the per-request calls.
+over time.  Two protocols:
+
+* token given (the primary one; the paper measures query latency from a
+  query token the client has already made, Sec. VII): the tokens of the
+  query mix -- the dealer's masks and both parties' keys of every predicate --
+  are dealt before the run and stay resident; a request names its mix entry,
+  and serving it is the servers' whole work: the masked opens, both parties'
+  evaluation of every row of every predicate, the ANDs and the joins.
+  GivenServedPath runs continuous batching: while the GPU runs a wave, the
+  requests that arrive are admitted (in arrival order, while the device memory
+  of their intermediates fits the budget) and form the next wave -- one
+  persistent evaluation launch over all their predicates and parties, then one
+  match_query_batch for their tails; at most two waves are in flight.
+  GivenPlainPath serves one request at a time.
+* keygen included: each request's token is dealt on arrival, inside its
+  latency (ServedPath and PlainPath): the served path cuts every request's
+  rows into chunks and runs each wave as one persistent dealer launch and one
+  persistent evaluation launch over a key arena.
 
 Latency is arrival -> result shares in device memory, timed by HIP events on
 the serving stream against an event recorded when the clock starts.  Results
-are bit-identical on both paths (every kernel is a pure function of its rows),
-which the tests check request by request.
+are bit-identical on every path (every kernel is a pure function of its
+rows), which the tests check request by request.  Every allocation of a path
+is made on its own stream (the caching allocator then reuses freed memory in
+that stream's order).
 """
 from __future__ import annotations
 
@@ -122,6 +133,8 @@ def _plan(req: Request, bits_given: bool, device):
 
 
 class ServedPath:
+    """Keygen included: continuous batching over a key arena (see the module notes)."""
+
     def __init__(self, graph: ResidentGraph, budget_bytes: int, key_arena_bytes: int, chunk_rows: int = 1 << 20,
                  device=None, stream=None, wave_bytes: int = None):
         """wave_bytes caps the keys (both parties) of one wave, i.e. its work:
@@ -138,9 +151,14 @@ class ServedPath:
         self.queue = fss.Queue(2048, self.device)
         self.waves = 0
         self.max_in_flight = 0
+        self.max_used = 0           # peak admitted bytes (outside the key arena)
 
     def run(self, requests, clock_start_event, t0):
         """Serve `requests` (sorted by arrival) in real time from host time t0."""
+        with torch.cuda.stream(self.stream):
+            return self._run(requests, clock_start_event, t0)
+
+    def _run(self, requests, clock_start_event, t0):
         pending = deque(requests)
         admitted = []           # requests with chunks left: (req, deque of chunk items)
         in_mem = []             # admitted, not released
@@ -173,6 +191,7 @@ class ServedPath:
                 admitted.append((req, items))
                 in_mem.append(req)
                 used += req.mem
+                self.max_used = max(self.max_used, used)
             self.max_in_flight = max(self.max_in_flight, len(admitted))
             if not admitted:
                 wait = pending[0].arrival - (time.perf_counter() - t0)
@@ -231,7 +250,7 @@ class ServedPath:
 
 
 class PlainPath:
-    """One request at a time: masks, open, per-predicate keygen, match_query.
+    """Keygen included, one request at a time: masks, open, per-predicate keygen, match_query.
 
     sync=True waits for each request's results before taking the next (a
     server that answers one query before it starts another); sync=False only
@@ -244,6 +263,10 @@ class PlainPath:
         self.sync = sync
 
     def run(self, requests, clock_start_event, t0):
+        with torch.cuda.stream(self.stream):
+            return self._run(requests, clock_start_event, t0)
+
+    def _run(self, requests, clock_start_event, t0):
         for req in requests:
             wait = req.arrival - (time.perf_counter() - t0)
             if wait > 0:
@@ -267,6 +290,281 @@ class PlainPath:
         return requests
 
 
+# --------------------------------------------------------------------------- token given
+
+@dataclass
+class Token:
+    """One mix entry's query token as the servers hold it: the candidate view
+    and, per predicate, the dealer's masks and both parties' keys."""
+    query: object
+    rows: int
+    seed: int
+    view: dict
+    preds: list             # dicts: target, kind, rows, r, kb
+    key_bytes: int = 0
+
+
+class TokenPool:
+    """The tokens of a query mix, dealt before the run (dealer masks with
+    fss_dealer_masks, keys with fss_keygen) and kept in device memory."""
+
+    def __init__(self, graph: ResidentGraph, mix, seed: int, device=None, stream=None):
+        self.device = device or torch.device("cuda")
+        s = stream or torch.cuda.current_stream()
+        self.tokens = []
+        with torch.cuda.stream(s):
+            for q, rows in mix:
+                req = Request(-1, 0.0, q, rows, seed)
+                view = _view(req, graph)
+                preds = []
+                for k, p in enumerate(q.preds):
+                    n = view["n_edges"] if p.target >= q.n_qv else view["n_vertices"]
+                    kind = fss.EQ if p.kind == "eq" else fss.RANGE
+                    r = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+                    kb = fss.KeyBatch(kind, 32, n, self.device)
+                    if n:
+                        fss.fss_dealer_masks(seed, q.query_id, k, n, r, stream=s)
+                        fss.fss_keygen(seed, q.query_id, k, p.a if p.kind == "eq" else p.lo, p.hi, r, kb, s)
+                    preds.append(dict(target=p.target, kind=kind, rows=n, r=r, kb=kb))
+                self.tokens.append(Token(q, rows, seed, view, preds,
+                                         sum(2 * d["kb"].bytes_per_party for d in preds)))
+        s.synchronize()
+
+    @property
+    def key_bytes(self) -> int:
+        return sum(t.key_bytes for t in self.tokens)
+
+
+@dataclass
+class GivenRequest:
+    rid: int
+    arrival: float          # seconds after the start
+    entry: int              # mix entry whose token the request carries
+    keep: bool = True       # keep the result shares after completion (else they are dropped)
+    # filled while served
+    xhat: list = field(default_factory=list)
+    bits: list = field(default_factory=list)
+    plan: object = None
+    mem: int = 0
+    done_event: object = None
+    latency_ms: float = 0.0
+
+
+def _view(req, g: ResidentGraph) -> dict:
+    """Candidate vertices [0, rows) and the edges among them (a prefix of the
+    resident edge order)."""
+    q = req.query
+    r_v = min(req.rows, g.n_vertices)
+    if q.n_qv > 1:
+        # the bound in the keys' own dtype: a Python int would make numpy
+        # convert the whole key array before searching
+        n_e = min(req.rows, int(np.searchsorted(g.edge_keys, g.edge_keys.dtype.type(r_v), side="left")))
+        return dict(n_vertices=r_v, n_edges=n_e, src=g.src[:n_e], dst=g.dst[:n_e])
+    return dict(n_vertices=r_v, n_edges=0, src=None, dst=None)
+
+
+def token_walks(tok: Token) -> int:
+    """Tree walks of a token's evaluation (both parties; a range is two)."""
+    return sum(2 * d["rows"] * (1 if d["kind"] == fss.EQ else 2) for d in tok.preds)
+
+
+def given_memory(tok: Token) -> int:
+    """Device bytes a token-given request allocates while admitted: opened
+    values, both parties' share bits, the plan's workspace and outputs
+    (bounded with every table at the token's largest row count)."""
+    rows = max([d["rows"] for d in tok.preds] + [tok.view["n_vertices"], tok.view["n_edges"], 1])
+    npred = len(tok.preds)
+    n_qv = tok.query.n_qv
+    return 4 * rows * npred + 8 * _words(rows) * (2 * npred + 4 * n_qv + 4) + 4096 * (npred + 2)
+
+
+def _open_given(req: GivenRequest, tok: Token, g: ResidentGraph, device, stream):
+    """The request's masked opens: x0 + x1 + r per predicate, with the token's masks."""
+    q = tok.query
+    req.xhat = []
+    for k, p in enumerate(q.preds):
+        d = tok.preds[k]
+        n = d["rows"]
+        xhat = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        if n:
+            cols = g.eshares if p.target >= q.n_qv else g.vshares
+            x0, x1 = (t[:n] for t in cols[p.column])
+            fss.fss_mask_open(x0, x1, d["r"], xhat, stream)
+        req.xhat.append(xhat)
+
+
+def _given_plan_with_keys(req: GivenRequest, tok: Token, device):
+    q, v = tok.query, tok.view
+    preds = [(d["target"], d["kb"], req.xhat[k]) for k, d in enumerate(tok.preds)]
+    return fss.Plan(tok.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
+                    v["dst"]).allocate(device)
+
+
+def _given_plan_with_bits(req: GivenRequest, tok: Token, device):
+    q, v = tok.query, tok.view
+    req.bits = [tuple(torch.empty(max(1, _words(d["rows"])), dtype=torch.int32, device=device) for _ in range(2))
+                for d in tok.preds]
+    preds = [(d["target"], None, None, req.bits[k]) for k, d in enumerate(tok.preds)]
+    return fss.Plan(tok.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
+                    v["dst"]).allocate(device)
+
+
+class GivenServedPath:
+    """Token given, continuous batching (see the module notes)."""
+
+    def __init__(self, graph: ResidentGraph, pool: TokenPool, budget_bytes: int, device=None, stream=None,
+                 max_waves_in_flight: int = 2, batch_walks: int = 4 << 20):
+        """batch_walks: a wave is cut, in arrival order, into batches of at most
+        this many tree walks (a request larger than that is a batch of its
+        own); each batch is one evaluation launch and one match_query_batch
+        with its own completion event, so a request completes no later than
+        the requests that arrived after it."""
+        self.g, self.pool = graph, pool
+        self.batch_walks = batch_walks
+        self.device = device or torch.device("cuda")
+        self.stream = stream or torch.cuda.current_stream()
+        self.budget = budget_bytes
+        self.max_waves = max_waves_in_flight
+        self.queue = fss.Queue(4096, self.device)
+        self.waves = 0
+        self.batches = 0
+        self.max_in_flight = 0
+        self.max_used = 0
+        self.max_wave = 0
+
+    def run(self, requests, clock_start_event, t0, deadline_s: float = None):
+        with torch.cuda.stream(self.stream):
+            return self._run(requests, clock_start_event, t0, deadline_s)
+
+    def _run(self, requests, clock_start_event, t0, deadline_s):
+        pending = deque(requests)
+        in_mem = []             # admitted, results not yet in device memory
+        waves = deque()         # completion events of the waves in flight
+        used = 0
+        while pending:
+            if deadline_s is not None and time.perf_counter() - t0 > deadline_s:
+                break           # overloaded: the rest is never served (reported as missing)
+            keep = []
+            for req in in_mem:
+                if req.done_event.query():
+                    used -= req.mem
+                else:
+                    keep.append(req)
+            in_mem = keep
+            while waves and waves[0].query():
+                waves.popleft()
+            now = time.perf_counter() - t0
+            if len(waves) >= self.max_waves or not pending or pending[0].arrival > now:
+                # nothing to start: wait for a wave to end or the next arrival
+                if waves and len(waves) >= self.max_waves:
+                    time.sleep(0.0002)
+                elif pending and pending[0].arrival > now:
+                    time.sleep(min(pending[0].arrival - now, 0.001))
+                continue
+            wave = []
+            while pending and pending[0].arrival <= now:
+                req = pending[0]
+                tok = self.pool.tokens[req.entry]
+                req.mem = given_memory(tok)
+                if (in_mem or wave) and used + req.mem > self.budget:
+                    break      # admitted once memory frees up (arrival order is kept)
+                pending.popleft()
+                wave.append(req)
+                used += req.mem
+                self.max_used = max(self.max_used, used)
+            if not wave:
+                in_mem[0].done_event.synchronize()      # the head request waits for memory
+                continue
+            batches, cur, walks = [], [], 0
+            for req in wave:
+                w = token_walks(self.pool.tokens[req.entry])
+                if cur and walks + w > self.batch_walks:
+                    batches.append(cur)
+                    cur, walks = [], 0
+                cur.append(req)
+                walks += w
+            batches.append(cur)
+            for batch in batches:
+                ev, plans = [], []
+                for req in batch:
+                    tok = self.pool.tokens[req.entry]
+                    _open_given(req, tok, self.g, self.device, self.stream)
+                    req.plan = _given_plan_with_bits(req, tok, self.device)
+                    for k, d in enumerate(tok.preds):
+                        if d["rows"]:
+                            for b in range(2):
+                                ev.append((b, d["kb"], req.xhat[k], req.bits[k][b]))
+                    plans.append(req.plan)
+                self.queue.reserve(fss.fss_queue_workspace_bytes(len(ev)))
+                if ev:
+                    fss.fss_eval_batch(ev, self.queue, self.stream)
+                fss.match_query_batch(plans, self.queue, 3, self.stream)
+                done = torch.cuda.Event(enable_timing=True)
+                done.record(self.stream)
+                for req in batch:
+                    req.done_event = done
+                    req.xhat, req.bits = [], []
+                    req.plan.release_inputs()
+                    if not req.keep:
+                        req.plan = None
+                self.batches += 1
+            in_mem.extend(wave)
+            waves.append(done)
+            self.waves += 1
+            self.max_wave = max(self.max_wave, len(wave))
+            self.max_in_flight = max(self.max_in_flight, len(in_mem))
+        torch.cuda.synchronize()
+        for req in requests:
+            req.latency_ms = (clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival
+                              if req.done_event is not None else float("inf"))
+        return requests
+
+
+class GivenPlainPath:
+    """Token given, one request at a time: the opens, then match_query (both
+    parties' evaluation, the ANDs, the joins).  sync=True waits for each
+    request's results before taking the next; sync=False only enqueues."""
+
+    def __init__(self, graph: ResidentGraph, pool: TokenPool, device=None, stream=None, sync: bool = True):
+        self.g, self.pool = graph, pool
+        self.device = device or torch.device("cuda")
+        self.stream = stream or torch.cuda.current_stream()
+        self.sync = sync
+
+    def run(self, requests, clock_start_event, t0, deadline_s: float = None):
+        with torch.cuda.stream(self.stream):
+            for req in requests:
+                if deadline_s is not None and time.perf_counter() - t0 > deadline_s:
+                    break
+                wait = req.arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                tok = self.pool.tokens[req.entry]
+                _open_given(req, tok, self.g, self.device, self.stream)
+                req.plan = _given_plan_with_keys(req, tok, self.device)
+                fss.match_query(req.plan, 3, self.stream)
+                req.done_event = torch.cuda.Event(enable_timing=True)
+                req.done_event.record(self.stream)
+                req.xhat = []
+                req.plan.release_inputs()
+                if not req.keep:
+                    req.plan = None
+                if self.sync:
+                    req.done_event.synchronize()
+        torch.cuda.synchronize()
+        for req in requests:
+            req.latency_ms = (clock_start_event.elapsed_time(req.done_event) - 1e3 * req.arrival
+                              if req.done_event is not None else float("inf"))
+        return requests
+
+
+def given_outputs(req: GivenRequest, pool: TokenPool):
+    tok = pool.tokens[req.entry]
+    v = tok.view
+    w = _words(v["n_vertices"]) if tok.query.n_qv == 1 else (tok.query.n_qv - 1) * _words(v["n_edges"])
+    return [req.plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
+
+
 def _drop_intermediates(req: Request):
     """Release everything but the result shares (their last use is enqueued)."""
     req.preds = [dict(target=p["target"], rows=p["rows"], kind=p["kind"]) for p in req.preds]
@@ -288,9 +586,13 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
 
 
 def summarize(requests, wall_s: float) -> dict:
+    """Requests served per second of wall time and latency percentiles; a
+    request never served (run cut at its deadline) counts as infinitely late."""
     lat = np.array([r.latency_ms for r in requests])
-    return {"requests": len(requests), "qps": len(requests) / wall_s, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "wall_s": wall_s}
+    done = np.isfinite(lat)
+    return {"requests": len(requests), "served": int(done.sum()), "qps": float(done.sum()) / wall_s,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat[done].mean()) if done.any() else float("inf"), "wall_s": wall_s}
 
 
 def resident_graph(n_vertices, n_edges, src, dst, vshares, eshares, device) -> ResidentGraph:

@@ -1,0 +1,36 @@
+"""Alg. 1's grouping as the library computes it on the host (rss_group_k)
+against the oracle's, and its k-anonymity: every padded length is shared by
+at least k vertices of the type."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import access
+
+
+@pytest.fixture(scope="module")
+def fss():
+    from paper_2209_03526_amd import fss as f
+    return f
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 6, 50])
+def test_group_k_equals_oracle(fss, k):
+    types, adj, _ = synth.posting_graph(11, 4000, 500, 30, n_types=3)
+    lengths = np.array([len(a) for a in adj], np.uint32)
+    padded, group = fss.rss_group_k(lengths, types, k)
+    want_p, want_g = access.group_k(lengths, types, k)
+    np.testing.assert_array_equal(padded, want_p)
+    np.testing.assert_array_equal(group, want_g)
+    for t in np.unique(types):
+        _, counts = np.unique(padded[types == t], return_counts=True)
+        assert counts.min() >= k
+
+
+def test_group_k_small_types_and_errors(fss):
+    padded, group = fss.rss_group_k([3, 1, 2], [0, 0, 1], 4)      # fewer than k: one group per type
+    assert padded.tolist() == [3, 3, 2] and group[0] == group[1] != group[2]
+    assert fss.LIB.rss_group_k(3, None, None, 2, None, None) == fss.EINVAL
+    lengths = np.array([1, 2], np.uint32)
+    with pytest.raises(fss.FssError):
+        fss.rss_group_k(lengths, lengths, 0)

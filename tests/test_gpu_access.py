@@ -1,0 +1,98 @@
+"""Alg. 1 encoding and Alg. 6 secAccess on the GPU over 12,000 candidates:
+the encoder's three RSS shares equal the oracle's share for share; for matched
+vertices with short, long and empty posting lists, the kept ID records, their
+shuffled positions, their count and the attribute records equal the oracle's
+share for share, and they reconstruct to the vertex's true neighbours and
+their attributes."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import DEV, T, U
+from oracle import access
+
+pytestmark = pytest.mark.gpu
+
+NC, X, KGROUP = 12000, 2000, 4
+WX = (X + 31) // 32
+
+
+@pytest.fixture(scope="module")
+def fss():
+    from paper_2209_03526_amd import fss as f
+    return f
+
+
+@pytest.fixture(scope="module")
+def enc(fss):
+    types, adj, attr = synth.posting_graph(21, NC, X, 24, n_types=2)
+    lengths = np.array([len(a) for a in adj], np.uint32)
+    padded, _ = fss.rss_group_k(lengths, types, KGROUP)
+    slots = synth.posting_slots(22, lengths, padded)
+    rec, off = access.encode_posting_lists_k(adj, X, padded, slots)
+    want = access.rss_split_prf(rec, 1001, 1002, 4)
+    adj_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
+    flat = np.concatenate(adj).astype(np.uint32)
+    nrec = int(off[-1])
+    out = [torch.full((nrec * WX,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    d_off = T(off.astype(np.uint32))
+    fss.rss_enc_posting_lists(NC, X, T(adj_off), T(flat), T(slots), d_off, nrec, (1001, 1002), 4, out)
+    torch.cuda.synchronize()
+    return dict(types=types, adj=adj, attr=attr, padded=padded, off=off, d_off=d_off, nrec=nrec, want=want, out=out)
+
+
+def test_encoding_shares_equal_oracle(fss, enc):
+    for i in range(3):
+        np.testing.assert_array_equal(U(enc["out"][i]).reshape(enc["nrec"], WX), enc["want"][i],
+                                      err_msg=f"share {i + 1}")
+    for t in np.unique(enc["types"]):                   # k-anonymity of the padded lengths
+        _, counts = np.unique(enc["padded"][enc["types"] == t], return_counts=True)
+        assert counts.min() >= KGROUP
+
+
+def _split_bits(rng, bits):
+    s1 = rng.integers(0, 2, bits.size, dtype=np.uint8)
+    s2 = rng.integers(0, 2, bits.size, dtype=np.uint8)
+    return [s1, s2, bits ^ s1 ^ s2]
+
+
+def _pack(bits):
+    from oracle import fss as ofss
+    return ofss.pack_bits(bits)
+
+
+@pytest.mark.parametrize("pick", ["long", "short", "empty", "middle"])
+def test_sec_access_equals_oracle(fss, enc, pick):
+    lens = np.array([len(a) for a in enc["adj"]])
+    m = {"long": int(np.argmax(lens)), "short": int(np.flatnonzero(lens == 1)[0]),
+         "empty": int(np.flatnonzero(lens == 0)[0]), "middle": int(np.flatnonzero(lens == 5)[0])}[pick]
+    rng = np.random.default_rng(m)
+    idm = np.zeros(NC, np.uint8)
+    idm[m] = 1
+    idm_sh = _split_bits(rng, idm)
+    attr_sh = access.rss_split(enc["attr"], 31 + m)
+    keys, seeds, counter = [51, 52, 53], (61 + m, 62, 63), 9
+    lmax = int(enc["padded"].max())
+    want_ids, want_attrs = access.sec_access_csr(idm_sh, enc["want"], enc["off"], attr_sh, X, keys, seeds, counter)
+    kept = want_ids[0].shape[0]
+    ids = [torch.full((lmax * WX,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    attrs = [torch.full((lmax * 2,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    rows = torch.full((lmax,), -1, dtype=torch.int32, device=DEV)
+    count = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    post = [t for t in enc["out"]]
+    fss.rss_sec_access(NC, X, [T(_pack(b)) for b in idm_sh], enc["d_off"], lmax, post, 2, [T(a) for a in attr_sh],
+                       keys, counter, seeds, ids, attrs, rows, count)
+    torch.cuda.synchronize()
+    assert int(U(count)[0]) == kept == lens[m]
+    got_ids = [U(t).reshape(lmax, WX)[:kept] for t in ids]
+    got_attrs = [U(t).reshape(lmax, 2)[:kept] for t in attrs]
+    for i in range(3):
+        np.testing.assert_array_equal(got_ids[i], want_ids[i], err_msg=f"ID share {i + 1}")
+        np.testing.assert_array_equal(got_attrs[i], want_attrs[i], err_msg=f"attribute share {i + 1}")
+    rec = got_ids[0] ^ got_ids[1] ^ got_ids[2]
+    nb = sorted(int(access.unpack_onehot(r, X)[0]) for r in rec)
+    assert nb == enc["adj"][m].tolist()
+    at = got_attrs[0] ^ got_attrs[1] ^ got_attrs[2]
+    for r, a in zip(rec, at):
+        np.testing.assert_array_equal(a, enc["attr"][int(access.unpack_onehot(r, X)[0])])

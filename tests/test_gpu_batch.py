@@ -71,6 +71,43 @@ def test_keygen_batch_equals_single(fss):
             assert k1.tobytes() == k2.tobytes()
 
 
+def test_keygen_and_eval_batch_equal_oracle(fss):
+    """The batch calls against the oracle directly (not only through the
+    single calls): keys of every request, in row chunks with row offsets (the
+    serving runner's form), byte for byte equal to the oracle's keygen of the
+    same table rows, and each party's evaluation words equal to the oracle's."""
+    from keylayout import from_device
+    reqs = _requests(fss)
+    kg, ev, checks = [], [], []
+    for rq in reqs:
+        n = rq["n"]
+        cut = n // 2 // 64 * 64 if n > 128 else 0     # two chunks where the table allows (offsets keep 64-row pads)
+        for c0, c1 in ((0, cut), (cut, n)) if cut else ((0, n),):
+            kb = fss.KeyBatch(rq["kind"], rq["nbits"], c1 - c0)
+            kg.append((rq["seed"], rq["q"], rq["p"], rq["a"], rq["hi"], rq["r"][c0:c1], kb, c0))
+            outs = [torch.full(((c1 - c0 + 31) // 32,), -1, dtype=torch.int32, device=DEV) for _ in range(2)]
+            for b in range(2):
+                ev.append((b, kb, rq["xhat"][c0:c1], outs[b]))
+            checks.append((rq, c0, c1, kb, outs))
+    fss.fss_keygen_batch(kg, fss.Queue(len(kg)))
+    fss.fss_eval_batch(ev, fss.Queue(len(ev)))
+    torch.cuda.synchronize()
+    for rq, c0, c1, kb, outs in checks:
+        r = U(rq["r"])[c0:c1]
+        xh = U(rq["xhat"])[c0:c1]
+        rows = np.arange(c0, c1, dtype=np.uint32)
+        if rq["kind"] == 0:
+            want = ofss.keygen_eq(rq["nbits"], rq["seed"], rq["q"], rq["p"], rq["a"], r, rows=rows)
+            ev_fn = ofss.eval_eq
+        else:
+            want = ofss.keygen_range(rq["nbits"], rq["seed"], rq["q"], rq["p"], rq["a"], rq["hi"], r, rows=rows)
+            ev_fn = ofss.eval_range
+        for b in range(2):
+            got = from_device(rq["kind"], rq["nbits"], c1 - c0, B(kb.key[b], kb.bytes_per_party))
+            assert got.tobytes() == want[b].tobytes(), f"request {rq['p']} rows {c0}..{c1} party {b} keys"
+            np.testing.assert_array_equal(U(outs[b]), ofss.pack_bits(ev_fn(rq["nbits"], b, want[b], xh)))
+
+
 @pytest.mark.parametrize("tuning", TUNINGS)
 def test_eval_batch_equals_single(fss, tuning):
     reqs = _requests(fss)

@@ -129,3 +129,92 @@ def test_eval_all_batch_matches_oracle(fss):
         got = U(out)
         np.testing.assert_array_equal(ofss.unpack_bits(got, npos), w)
         assert npos % 32 == 0 or (got[-1] >> (npos % 32)) == 0
+
+
+@pytest.mark.parametrize("n", [1, 3000, 70001, (1 << 20) + 13])
+def test_fss_to_rss_then_and_chain(fss, n):
+    """The masked-input path on the GPU (dealer keygen, open, both parties'
+    evaluation of two range predicates), its two-party bits converted to RSS
+    (rss_from_fss) and ANDed in RSS (rss_and): every server's share equals the
+    oracle's at each step, and the reconstruction is the plaintext conjunction."""
+    seed, q = 55, 3
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 1 << 20, n).astype(np.uint32)
+    x0 = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    x1 = (x - x0).astype(np.uint32)
+    bounds = [(1000, 700000), (500000, 1 << 20)]
+    keys = [41, 42, 43]
+    nw = (n + 31) // 32
+    conv, oconv = [], []
+    for k, (lo, hi) in enumerate(bounds):
+        r = ofss.masks(seed, q, k, n)
+        xhat = torch.empty(n, dtype=torch.int32, device=DEV)
+        fss.fss_mask_open(T(x0), T(x1), T(r), xhat)
+        kb = fss.KeyBatch(fss.RANGE, 32, n)
+        fss.fss_keygen(seed, q, k, lo, hi, T(r), kb)
+        y = [torch.empty(nw, dtype=torch.int32, device=DEV) for _ in range(2)]
+        for b in range(2):
+            fss.fss_eval_lt(b, kb, xhat, y[b])
+        z = [torch.full((nw,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+        fss.rss_from_fss(n, y, keys, k, z)
+        ok = ofss.keygen_range(32, seed, q, k, lo, hi, r)
+        xh = (x + r).astype(np.uint32)
+        oy = [ofss.pack_bits(ofss.eval_range(32, b, ok[b], xh)) for b in range(2)]
+        for b in range(2):
+            np.testing.assert_array_equal(U(y[b]), oy[b], err_msg=f"predicate {k} party {b}")
+        want = orss.from_two_party(oy[0], oy[1], keys, k, n)
+        for i in range(3):
+            np.testing.assert_array_equal(U(z[i]), want[i], err_msg=f"predicate {k} server {i}")
+        conv.append(z)
+        oconv.append(want)
+    out = [torch.full((nw,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_and(n, conv[0], conv[1], keys, 7, out)
+    want = orss.rss_and(oconv[0], oconv[1], keys, 7, n)
+    got = [U(t) for t in out]
+    for i in range(3):
+        np.testing.assert_array_equal(got[i], want[i], err_msg=f"AND server {i}")
+    truth = ((x >= bounds[0][0]) & (x < bounds[0][1]) & (x >= bounds[1][0]) & (x < bounds[1][1])).astype(np.uint8)
+    np.testing.assert_array_equal(ofss.unpack_bits(got[0] ^ got[1] ^ got[2], n), truth)
+
+
+def test_sec_eval_reshare_and_chain(fss):
+    """The paper's own chain on the GPU: two predicates by secEval (Eq.
+    predEval, three-out-of-three shares), each re-shared into RSS, then ANDed:
+    share for share equal to the oracle's chain; reconstruction = conjunction."""
+    npos, ncand = 64, 50001
+    values = np.random.default_rng(12).integers(0, npos, ncand).astype(np.uint32)
+    shares = synth.onehot_rss(12, values, npos)
+    dev_sh = [T(synth.pack_word_major(shares[j])) for j in range(3)]
+    nw = (ncand + 31) // 32
+    keys = [5, 6, 7]
+    rss_dev, rss_or = [], []
+    for p, (lo, hi) in enumerate([(10, 40), (30, 60)]):
+        okeys, nb = orss.token("range", npos, 19, 2, p, lo=lo, hi=hi)
+        kb, _ = _gpu_token(fss, "range", npos, 19, 2, p, lo=lo, hi=hi)
+        ev = {}
+        for party in (0, 1):
+            for rep in range(3):
+                o = torch.zeros((npos + 31) // 32, dtype=torch.int32, device=DEV)
+                fss.fss_eval_all(party, kb, rep, npos, o)
+                ev[(party, rep)] = o
+        xs = []
+        for (pa, ra, ja), (pb, rb, jb) in orss.SERVER_TERMS:
+            o = torch.empty(nw, dtype=torch.int32, device=DEV)
+            fss.rss_sec_eval(ncand, npos, ev[(pa, ra)], ev[(pb, rb)], dev_sh[ja], dev_sh[jb], o)
+            xs.append(o)
+        z = [torch.empty(nw, dtype=torch.int32, device=DEV) for _ in range(3)]
+        fss.rss_reshare(ncand, xs, keys, p, z)
+        ox = orss.server_shares("range", npos, okeys, nb, shares)
+        want = orss.reshare([ofss.pack_bits(ox[i]) for i in range(3)], keys, p, ncand)
+        for i in range(3):
+            np.testing.assert_array_equal(U(z[i]), want[i], err_msg=f"predicate {p} server {i}")
+        rss_dev.append(z)
+        rss_or.append(want)
+    out = [torch.empty(nw, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_and(ncand, rss_dev[0], rss_dev[1], keys, 9, out)
+    want = orss.rss_and(rss_or[0], rss_or[1], keys, 9, ncand)
+    got = [U(t) for t in out]
+    for i in range(3):
+        np.testing.assert_array_equal(got[i], want[i])
+    truth = ((values >= 30) & (values < 40)).astype(np.uint8)
+    np.testing.assert_array_equal(ofss.unpack_bits(got[0] ^ got[1] ^ got[2], ncand), truth)
