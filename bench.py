@@ -119,7 +119,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample-rows", type=int, default=65536,
+    ap.add_argument("--cpu-sample-rows", type=int, default=262144,
                     help="full: edge rows the oracle computes for the CPU baseline (bit-checked vs the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-vertex-filter", action="store_true", help="full: skip the 2^22-row vertex filter key")
@@ -983,9 +983,58 @@ def run_next(args, torch, fss, dev):
                                    f"secAccess filter: shuffle {nrec} records of {nwords * 4} B, open parity, compact",
                                    cc_blocks)
     del d3, o3, xb
+    # two-party FSS bits -> RSS: 2^30 rows (2^25 words per share)
+    y2 = [rnd(nw) for _ in range(2)]
+    z3 = [torch.empty(nw, dtype=torch.int32, device=dev) for _ in range(3)]
+    res["rss_from_fss"] = row("rss_from_fss", timed(lambda: fss.rss_from_fss(nrows, y2, keys, 3, z3, stream)),
+                              5 * 4 * nw, 0, f"{nrows} bits: 2 shares read, 3 written, 3 PRF streams", prf_blocks)
+    del y2, z3
+    # Alg. 1 encoding and Alg. 6 over k-grouped posting lists: 65,536 candidates,
+    # 16,384 neighbour IDs (2 KB one-hot records), lists of 0..24 IDs, k = 4
+    nc, xbits = 1 << 16, 1 << 14
+    wx = xbits // 32
+    types, adj, attr = synth.posting_graph(SEED, nc, xbits, 24, n_types=2)
+    lengths = np.array([len(a) for a in adj], np.uint32)
+    padded, _ = fss.rss_group_k(lengths, types, 4)
+    slots = synth.posting_slots(SEED, lengths, padded)
+    off = np.concatenate([[0], np.cumsum(padded)]).astype(np.uint32)
+    nrec, lmax = int(off[-1]), int(padded.max())
+    adj_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
+
+    def Tu(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
+
+    d_off, d_adj_off, d_adj, d_slot = Tu(off), Tu(adj_off), Tu(np.concatenate(adj)), Tu(slots)
+    post = [torch.empty(nrec * wx, dtype=torch.int32, device=dev) for _ in range(3)]
+    res["rss_enc_posting_lists"] = row(
+        "rss_enc_posting_lists",
+        timed(lambda: work.__setitem__("w", fss.rss_enc_posting_lists(nc, xbits, d_adj_off, d_adj, d_slot, d_off, nrec,
+                                                                      (71, 72), 0, post, stream))),
+        3 * 4 * nrec * wx + 4 * nrec, 0, f"{nrec} one-hot records of {4 * wx} B (k = 4 groups): 3 shares written",
+        2 * nrec * wx // 16)
+    m = int(np.argmax(lengths))
+    idm = [rnd((nc + 31) // 32) for _ in range(2)]
+    onehot = np.zeros((nc + 31) // 32, np.uint32)
+    onehot[m // 32] = 1 << (m % 32)
+    idm.append(torch.bitwise_xor(torch.bitwise_xor(idm[0], idm[1]), Tu(onehot)))
+    attr3 = [rnd(xbits * 2) for _ in range(3)]
+    ids3 = [torch.empty(lmax * wx, dtype=torch.int32, device=dev) for _ in range(3)]
+    attrs3 = [torch.empty(lmax * 2, dtype=torch.int32, device=dev) for _ in range(3)]
+    rows_o = torch.empty(lmax, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    res["rss_sec_access"] = row(
+        "rss_sec_access",
+        timed(lambda: work.__setitem__("w", fss.rss_sec_access(nc, xbits, idm, d_off, lmax, post, 2, attr3, keys, 5,
+                                                               seeds, ids3, attrs3, rows_o, cnt, stream))),
+        3 * 4 * nrec * wx + 3 * 12 * lmax * wx + 3 * 4 * xbits * 2 * lmax, 0,
+        f"one matched vertex over {nc} candidates ({nrec} records of {4 * wx} B): selection over all 3 shares, "
+        f"re-share, shuffle/open/compact of {lmax} records, attribute selection over {xbits} records per kept ID",
+        2 * 3 * lmax * wx // 16)
+    del post, ids3, attrs3
     if not args.no_cpu_baseline:
-        gpu_rate = {"sec_eval": ncand, "rss_and": nrows, "rss_reshare": nrows, "rss_shuffle": nrec,
-                    "rss_fetch_unique": nrec, "rss_fetch_many": nrec, "rss_compact_valid": nrec}
+        gpu_rate = {"sec_eval": ncand, "rss_and": nrows, "rss_reshare": nrows, "rss_shuffle": 1 << 22,
+                    "rss_fetch_unique": 1 << 22, "rss_fetch_many": 1 << 22, "rss_compact_valid": 1 << 22,
+                    "rss_from_fss": nrows, "rss_enc_posting_lists": nrec, "rss_sec_access": nc}
         for name, base in next_cpu_baselines().items():
             res[name]["cpu_baseline"] = base
             res[name]["gpu_rate"] = round(gpu_rate[name] / (res[name]["ms"] / 1e3), 1)
@@ -1042,6 +1091,26 @@ def next_cpu_baselines():
         lambda: osh.fetch_case2(xb, [t[:, 1:] for t in d3], 101, 202, 303))
     rec("rss_compact_valid", n, "records/s", f"{n} records x {4 * w} B",
         lambda: access.compact_valid(d3, (101, 202, 303)))
+    y0, y1 = x3[0], x3[1]
+    rec("rss_from_fss", nb_bits, "shared bits/s", f"{nb_bits} bits", lambda: orss.from_two_party(y0, y1, [11, 22, 33], 3,
+                                                                                                    nb_bits))
+    # Alg. 1 encoding and Alg. 6 over 4,096 candidates, 2,048 neighbour IDs
+    types, adj, attr = synth.posting_graph(SEED, 4096, 2048, 24, n_types=2)
+    lengths = np.array([len(a) for a in adj])
+    padded, _ = access.group_k(lengths, types, 4)
+    slots = synth.posting_slots(SEED, lengths, padded)
+    enc = {}
+    rec("rss_enc_posting_lists", int(padded.sum()), "records/s", f"{int(padded.sum())} records of 256 B",
+        lambda: enc.update(r=access.rss_split_prf(access.encode_posting_lists_k(adj, 2048, padded, slots)[0], 71, 72, 0)))
+    off = access.csr_offsets(padded)
+    m = int(np.argmax(lengths))
+    idm = np.zeros(4096, np.uint8)
+    idm[m] = 1
+    s1 = rng.integers(0, 2, 4096, dtype=np.uint8)
+    s2 = rng.integers(0, 2, 4096, dtype=np.uint8)
+    attr_sh = access.rss_split(attr, 5)
+    rec("rss_sec_access", 4096, "candidates/s", "one matched vertex over 4,096 candidates, 2,048 IDs",
+        lambda: access.sec_access_csr([s1, s2, idm ^ s1 ^ s2], enc["r"], off, attr_sh, 2048, [3, 4, 5], (7, 8, 9)))
     return out
 
 
