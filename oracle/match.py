@@ -2,7 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/fss.py``).
 
-Plan semantics (what both the oracle and the product compute):
+Plan semantics (what both the oracle and the product compute).  The query
+graph (Def. 2) has vertices 0 .. n_qv-1 and directed edges (a_j, b_j),
+j = 0 .. n_qe-1 (a path v_0 -> v_1 -> ... unless given otherwise):
 
 1. Predicate k of the query (plan order) on a column of the target table:
    the dealer makes per-row keys with ``pred = k`` (Sec. V-C token generation,
@@ -13,20 +15,21 @@ Plan semantics (what both the oracle and the product compute):
 2. Per query vertex, then per query edge, its predicates are combined by AND
    (Sec. V-D, multi-predicate aggregation) as a left fold in plan order.  A
    vertex or edge with no predicate contributes the public constant 1.
-3. Per hop j (query edge v_j -> v_{j+1}), each party gathers its share bits of
-   v_j's result at the public ``src`` of every edge row and of v_{j+1}'s result
-   at ``dst``; then h_j = (m_j[src] AND m_{j+1}[dst]) AND q_j over edge rows.
+3. Per query edge j, each party gathers its share bits of a_j's result m_{a_j}
+   at the public ``src`` of every edge row and of b_j's result m_{b_j} at
+   ``dst``; then h_j = (m_{a_j}[src] AND m_{b_j}[dst]) AND q_j over edge rows.
    (Alg. 2 matches vertex by vertex and follows neighbours; here endpoints are
    public row indices -- a documented deviation -- so following a neighbour is
    a gather.)
 4. ANDs are numbered 0, 1, 2, ... in the order they are performed (vertex folds
-   in vertex order, edge folds in edge order, then two per hop); AND number i
-   consumes the Beaver triple stream (seed, query_id, and_id = i).  An AND with
-   a public-1 operand is the other operand and consumes no number.
+   in vertex order, edge folds in edge order, then two per query edge); AND
+   number i consumes the Beaver triple stream (seed, query_id, and_id = i).  An
+   AND with a public-1 operand is the other operand and consumes no number.
 5. Pad bits (rows beyond the table in the last word) are zero in every share.
 
-The result is h_0 .. h_{k-2} over edge rows (for a one-vertex query: m_0 over
-vertex rows), as the two parties' packed shares.
+The result is h_0 .. h_{n_qe-1} over edge rows (for a one-vertex query: m_0
+over vertex rows), as the two parties' packed shares.  The client joins the
+h_j on their shared query vertices (``results_from_bits``).
 """
 from __future__ import annotations
 
@@ -96,15 +99,41 @@ def materialize(m, nrows):
     return m
 
 
+def check_query(query):
+    """The query graphs the plan accepts: no edge for one vertex; otherwise
+    edges between distinct query vertices, no ordered pair twice, and every
+    query vertex on some edge (its matches appear only through the edges)."""
+    qe = query.qedges
+    if query.n_qv < 1:
+        raise ValueError("a query has at least one vertex")
+    if query.n_qv == 1:
+        if qe:
+            raise ValueError("a one-vertex query has no edges")
+        return
+    if not qe:
+        raise ValueError("a query of several vertices needs edges")
+    seen = set()
+    for a, b in qe:
+        if not (0 <= a < query.n_qv and 0 <= b < query.n_qv) or a == b:
+            raise ValueError(f"query edge ({a}, {b}) is not between two distinct query vertices")
+        if (a, b) in seen:
+            raise ValueError(f"query edge ({a}, {b}) given twice")
+        seen.add((a, b))
+    if {v for e in qe for v in e} != set(range(query.n_qv)):
+        raise ValueError("a query vertex is on no edge")
+
+
 def run_plan(nbits, seed, graph, query, shares, masks):
     """Both parties' shares of the query result (semantics in the module doc).
 
     ``shares``: column name -> (x0, x1) for vertex columns, "e:" + name for edge
     columns; ``masks``: one uint32 array per predicate."""
+    check_query(query)
     pred_bits = [predicate_shares(nbits, seed, graph, query, shares, masks, k)
                  for k in range(len(query.preds))]
     AND = _AndCounter(seed, query.query_id)
     n_qv = query.n_qv
+    qedges = query.qedges
     m = []
     for i in range(n_qv):
         acc = PUBLIC_ONE
@@ -113,7 +142,7 @@ def run_plan(nbits, seed, graph, query, shares, masks):
                 acc = pred_bits[k] if acc is PUBLIC_ONE else AND(acc, pred_bits[k], graph.n_vertices)
         m.append(acc)
     q = []
-    for j in range(n_qv - 1):
+    for j in range(len(qedges)):
         acc = PUBLIC_ONE
         for k, p in enumerate(query.preds):
             if p.target == n_qv + j:
@@ -122,9 +151,9 @@ def run_plan(nbits, seed, graph, query, shares, masks):
     if n_qv == 1:
         return [materialize(m[0], graph.n_vertices)]
     hops = []
-    for j in range(n_qv - 1):
-        g = gather_shares(m[j], graph.src, graph.n_vertices)
-        h = gather_shares(m[j + 1], graph.dst, graph.n_vertices)
+    for j, (a, b) in enumerate(qedges):
+        g = gather_shares(m[a], graph.src, graph.n_vertices)
+        h = gather_shares(m[b], graph.dst, graph.n_vertices)
         r1 = AND(g, h, graph.n_edges)
         r2 = AND(r1, q[j], graph.n_edges)
         hops.append(materialize(r2, graph.n_edges))
@@ -139,41 +168,78 @@ def reconstruct(outputs, nrows):
 def results_from_bits(graph, query, bits):
     """Client side: turn reconstructed bits into matched subgraphs.
 
-    One-vertex query: the set of matching vertex ids.  Path query: every chain
-    of edge rows (e_0, ..., e_{k-2}) with h_j[e_j] = 1, dst[e_j] = src[e_{j+1}]
-    and pairwise distinct vertices (Def. 2 asks for a bijection)."""
+    One-vertex query: the set of matching vertex ids.  Otherwise every tuple of
+    edge rows (e_0, ..., e_{n_qe-1}) with h_j[e_j] = 1 such that one injective
+    map f of query vertices to graph vertices has src[e_j] = f(a_j) and
+    dst[e_j] = f(b_j) for every query edge j (Def. 2 asks for a bijection).
+    The edges are joined in an order in which each one after the first shares
+    a query vertex with an earlier one, where the query graph allows it."""
     if query.n_qv == 1:
         return {(int(v),) for v in np.flatnonzero(bits[0])}
+    qe = query.qedges
     src, dst = graph.src, graph.dst
-    out_edges = {}
-    for j in range(1, len(bits)):
-        d = {}
-        for e in np.flatnonzero(bits[j]).tolist():
-            d.setdefault(int(src[e]), []).append(e)
-        out_edges[j] = d
+    rows = [np.flatnonzero(b).tolist() for b in bits]
+    by_src = [{} for _ in qe]
+    by_dst = [{} for _ in qe]
+    for j, rj in enumerate(rows):
+        for e in rj:
+            by_src[j].setdefault(int(src[e]), []).append(e)
+            by_dst[j].setdefault(int(dst[e]), []).append(e)
+    order, seen = [], set()
+    while len(order) < len(qe):
+        rest = [j for j in range(len(qe)) if j not in order]
+        touch = [j for j in rest if qe[j][0] in seen or qe[j][1] in seen]
+        j = (touch or rest)[0]
+        order.append(j)
+        seen.update(qe[j])
     results = set()
-    for e0 in np.flatnonzero(bits[0]).tolist():
-        chains = [([e0], [int(src[e0]), int(dst[e0])])]
-        for j in range(1, len(bits)):
-            nxt = []
-            for edges, verts in chains:
-                for e in out_edges[j].get(verts[-1], []):
-                    nxt.append((edges + [e], verts + [int(dst[e])]))
-            chains = nxt
-        for edges, verts in chains:
-            if len(set(verts)) == len(verts):
-                results.add(tuple(edges))
+    chosen = [None] * len(qe)
+
+    def extend(i, f, used):
+        if i == len(order):
+            results.add(tuple(chosen))
+            return
+        j = order[i]
+        a, b = qe[j]
+        if a in f:
+            cands = by_src[j].get(f[a], [])
+        elif b in f:
+            cands = by_dst[j].get(f[b], [])
+        else:
+            cands = rows[j]
+        for e in cands:
+            u, w = int(src[e]), int(dst[e])
+            if (a in f and f[a] != u) or (b in f and f[b] != w):
+                continue
+            new = {}
+            if a not in f:
+                new[a] = u
+            if b not in f:
+                new[b] = w
+            vals = list(new.values())
+            if len(set(vals)) < len(vals) or any(v in used for v in vals):
+                continue                      # f must stay injective
+            chosen[j] = e
+            f.update(new)
+            extend(i + 1, f, used | set(vals))
+            for k in new:
+                del f[k]
+
+    extend(0, {}, frozenset())
     return results
 
 
 def brute_force(graph, query):
     """Plaintext attributed subgraph matching by enumeration (Def. 2): every
     injective map of query vertices to graph vertices whose attribute
-    predicates hold, combined with every choice of edge rows between mapped
-    consecutive vertices whose edge predicates hold.  Only for tiny graphs."""
+    predicates hold, combined with every choice, per query edge (a, b), of an
+    edge row from the image of a to the image of b whose edge predicates hold.
+    Only for tiny graphs."""
+    check_query(query)
     n_qv = query.n_qv
+    qe = query.qedges
     vpreds = [[p for p in query.preds if p.target == i] for i in range(n_qv)]
-    epreds = [[p for p in query.preds if p.target == n_qv + j] for j in range(n_qv - 1)]
+    epreds = [[p for p in query.preds if p.target == n_qv + j] for j in range(len(qe))]
 
     def vertex_ok(i, v):
         return all(bool(p.holds(np.array([graph.vcols[p.column][v]]))[0]) for p in vpreds[i])
@@ -193,8 +259,8 @@ def brute_force(graph, query):
             results.add((vmap[0],))
             continue
         choices = []
-        for j in range(n_qv - 1):
-            ok = [e for e in edges_between.get((vmap[j], vmap[j + 1]), []) if edge_ok(j, e)]
+        for j, (a, b) in enumerate(qe):
+            ok = [e for e in edges_between.get((vmap[a], vmap[b]), []) if edge_ok(j, e)]
             choices.append(ok)
         for combo in itertools.product(*choices):
             results.add(tuple(combo))
@@ -205,7 +271,7 @@ def brute_force_pairs(graph, query):
     """Def. 2 by enumeration for a two-vertex path on a graph too large for the
     generic enumerator: all ordered pairs (u, w), u != w, tested as a boolean
     matrix, then all edge rows u -> w whose predicates hold."""
-    assert query.n_qv == 2
+    assert query.n_qv == 2 and query.qedges == [(0, 1)]
     nv = graph.n_vertices
     ok0 = np.ones(nv, bool)
     ok1 = np.ones(nv, bool)
@@ -234,9 +300,10 @@ def _and_schedule(query, n_vertices, n_edges):
     """The and_id of every AND the plan performs, found by walking the plan
     with public-ness only (no data): returns (vertex_fold, edge_fold, hop)
     where vertex_fold[i] / edge_fold[j] list (pred index, and_id or None) in
-    fold order and hop[j] = (and_id of m_j[src] AND m_{j+1}[dst] or None,
+    fold order and hop[j] = (and_id of m_{a_j}[src] AND m_{b_j}[dst] or None,
     and_id of that AND q_j or None)."""
     n_qv = query.n_qv
+    qe = query.qedges
     next_id = [0]
 
     def take():
@@ -252,7 +319,7 @@ def _and_schedule(query, n_vertices, n_edges):
                 pub = False
         vertex_fold.append(steps)
         public_v.append(pub)
-    for j in range(n_qv - 1):
+    for j in range(len(qe)):
         steps, pub = [], True
         for k, p in enumerate(query.preds):
             if p.target == n_qv + j:
@@ -261,9 +328,9 @@ def _and_schedule(query, n_vertices, n_edges):
         edge_fold.append(steps)
         public_e.append(pub)
     hop = []
-    for j in range(n_qv - 1):
-        gh_public = public_v[j] and public_v[j + 1]
-        a1 = take() if (not public_v[j] and not public_v[j + 1]) else None
+    for j, (a, b) in enumerate(qe):
+        gh_public = public_v[a] and public_v[b]
+        a1 = take() if (not public_v[a] and not public_v[b]) else None
         a2 = take() if (not gh_public and not public_e[j]) else None
         hop.append((a1, a2))
     return vertex_fold, edge_fold, hop, public_v, public_e
@@ -314,22 +381,23 @@ def sampled_outputs(nbits, seed, graph, query, shares, masks, out_rows):
             acc = pb if and_id is None else and_bits(acc, pb, and_id, rows)
         return acc
 
+    check_query(query)
     out_rows = np.asarray(out_rows, dtype=np.int64)
     if n_qv == 1:
         return fold(vfold[0], out_rows, public_v[0])[None]
     outs = []
-    for j in range(n_qv - 1):
+    for j, (a, b) in enumerate(query.qedges):
         src = graph.src[out_rows].astype(np.int64)
         dst = graph.dst[out_rows].astype(np.int64)
-        g = fold(vfold[j], src, public_v[j])
-        h = fold(vfold[j + 1], dst, public_v[j + 1])
+        g = fold(vfold[a], src, public_v[a])
+        h = fold(vfold[b], dst, public_v[b])
         q = fold(efold[j], out_rows, public_e[j])
         a1, a2 = hop[j]
         if a1 is not None:
             r1 = and_bits(g, h, a1, out_rows)
         else:
-            r1 = h if public_v[j] else g
-        r1_public = public_v[j] and public_v[j + 1]
+            r1 = h if public_v[a] else g
+        r1_public = public_v[a] and public_v[b]
         if a2 is not None:
             r2 = and_bits(r1, q, a2, out_rows)
         else:

@@ -3,10 +3,11 @@
 Graph model: a directed attributed graph (Def. 1) given as a vertex table and an
 edge table.  Vertex ``i`` has uint32 attribute columns ``vcols[name][i]``; edge
 row ``e`` goes from ``src[e]`` to ``dst[e]`` and has columns ``ecols[name][e]``.
-A query is a path v_0 -> v_1 -> ... -> v_{k-1}; each predicate targets one query
-vertex (``target < n_qv``) or one query edge (``target = n_qv + j`` for the
-edge v_j -> v_{j+1}), and is an equality ``x == a`` or a half-open range
-``lo <= x < hi`` on one column.
+A query graph (Def. 2) has query vertices 0 .. n_qv-1 and directed query edges
+``qedges[j] = (a_j, b_j)``; by default it is the path v_0 -> v_1 -> ... ->
+v_{k-1} (edge j = (j, j+1)).  Each predicate targets one query vertex
+(``target < n_qv``) or one query edge (``target = n_qv + j``), and is an
+equality ``x == a`` or a half-open range ``lo <= x < hi`` on one column.
 """
 from __future__ import annotations
 
@@ -42,6 +43,17 @@ class Query:
     query_id: int
     n_qv: int
     preds: list = field(default_factory=list)
+    edges: list = None      # [(a_j, b_j), ...]; None: the path (j, j+1)
+
+    @property
+    def qedges(self) -> list:
+        if self.edges is None:
+            return [(j, j + 1) for j in range(self.n_qv - 1)]
+        return [(int(a), int(b)) for a, b in self.edges]
+
+    @property
+    def n_qe(self) -> int:
+        return len(self.qedges)
 
 
 @dataclass

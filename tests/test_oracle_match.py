@@ -84,3 +84,90 @@ def test_sampled_rows_equal_full_plan(qi):
     for j, o in enumerate(full):
         for b in range(2):
             np.testing.assert_array_equal(match.fss.unpack_bits(o[b], nrows)[rows], samp[j, b])
+
+
+# --------------------------------------------------------------------------- query graphs beyond paths (Def. 2)
+
+SHAPES = [
+    # out-star: one vertex with two out-edges
+    synth.Query(21, 3, [P(0, "range", "attr", lo=2, hi=14), P(1, "eq", "label", a=1),
+                        P(4, "range", "weight", lo=0, hi=12)], edges=[(0, 1), (0, 2)]),
+    # in-star, edge predicates only on the first edge
+    synth.Query(22, 3, [P(0, "eq", "label", a=2), P(3, "range", "weight", lo=3, hi=16),
+                        P(3, "eq", "label", a=0)], edges=[(1, 0), (2, 0)]),
+    # directed triangle (a cycle: the last edge closes on a joined vertex)
+    synth.Query(23, 3, [P(0, "range", "attr", lo=0, hi=12)], edges=[(0, 1), (1, 2), (2, 0)]),
+    # diamond, with a reversed edge order
+    synth.Query(24, 4, [P(3, "range", "attr", lo=4, hi=16), P(1, "eq", "label", a=1),
+                        P(2, "range", "attr", lo=0, hi=10)], edges=[(2, 3), (1, 3), (0, 2), (0, 1)]),
+    # no predicate at all on a branching query
+    synth.Query(25, 3, [], edges=[(1, 0), (1, 2)]),
+    # two-edge cycle between the same pair, both directions
+    synth.Query(26, 2, [P(0, "eq", "label", a=1), P(3, "range", "weight", lo=0, hi=8)], edges=[(0, 1), (1, 0)]),
+]
+
+
+@pytest.mark.parametrize("gseed", [0, 3])
+@pytest.mark.parametrize("qi", range(len(SHAPES)))
+def test_query_graphs_match_brute_force(gseed, qi):
+    """Stars, a triangle, a diamond and a two-cycle: the reconstructed matches
+    are the injective maps found by enumeration (Def. 2)."""
+    q = SHAPES[qi]
+    g = synth.tiny_graph(gseed + 10 * qi, n_vertices=9 if q.n_qv == 4 else 10, n_edges=40)
+    want = match.brute_force(g, q)
+    assert _run(g, q, seed=gseed * 11 + qi) == want
+    if qi != 4:
+        assert len(want) < len(match.brute_force(g, synth.Query(q.query_id, q.n_qv, [], edges=q.edges)))
+
+
+def test_fig1_worked_example():
+    """Sec. II-A, Fig. 1: exactly the two subgraphs the paper prints, by
+    enumeration and through the shares."""
+    from fixtures import fig1_example
+    g, q, expected, names = fig1_example()
+    assert len(expected) == 2
+    assert match.brute_force(g, q) == expected
+    assert _run(g, q, seed=2209) == expected
+    for nbits in (8, 12):
+        assert _run(g, q, nbits=nbits, seed=3526) == expected
+
+
+def test_path_edges_are_the_default():
+    """A query given the path's edges explicitly is the same plan: same ANDs,
+    same share bits."""
+    g = synth.tiny_graph(7)
+    q = QUERIES[5]
+    q2 = synth.Query(q.query_id, q.n_qv, q.preds, edges=[(0, 1), (1, 2)])
+    sh = _shares(g, 3)
+    masks = synth.pred_masks(3, q, g)
+    a = match.run_plan(32, 1, g, q, sh, masks)
+    b = match.run_plan(32, 1, g, q2, sh, masks)
+    for x, y in zip(a, b):
+        for p in range(2):
+            np.testing.assert_array_equal(x[p], y[p])
+
+
+@pytest.mark.parametrize("edges", [[], [(0, 0)], [(0, 1), (0, 1)], [(0, 3)], [(0, 1)]])
+def test_rejected_query_graphs(edges):
+    """No edge for several vertices, a self loop, an edge given twice, an
+    endpoint outside the query, a vertex on no edge (n_qv = 3)."""
+    q = synth.Query(30, 3, [], edges=edges)
+    with pytest.raises(ValueError):
+        match.check_query(q)
+    with pytest.raises(ValueError):
+        match.check_query(synth.Query(31, 1, [], edges=[(0, 1)]))
+
+
+@pytest.mark.parametrize("qi", range(len(SHAPES)))
+def test_sampled_rows_equal_full_plan_shapes(qi):
+    q = SHAPES[qi]
+    g = synth.tiny_graph(qi + 40, n_vertices=9, n_edges=40)
+    sh = _shares(g, 6)
+    masks = synth.pred_masks(6, q, g)
+    full = match.run_plan(32, 8, g, q, sh, masks)
+    rows = np.arange(g.n_edges)[::-1]
+    samp = match.sampled_outputs(32, 8, g, q, sh, masks, rows)
+    assert len(full) == q.n_qe
+    for j, o in enumerate(full):
+        for b in range(2):
+            np.testing.assert_array_equal(match.fss.unpack_bits(o[b], g.n_edges)[rows], samp[j, b])
