@@ -79,6 +79,47 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(ChachaKey pk, uint32_t p, 
     }
 }
 
+// Small tables (at most kSmallPerm rows, as in secAccess, which shuffles one
+// fetched posting list): the three permutations of a shuffle in one launch,
+// one workgroup each.  The workgroup makes its rows' keys into LDS (the same
+// keys as k_perm_keys, not rotated), then row i's position is its rank: the
+// rows with a smaller key, or an equal key and a smaller row number -- the
+// stable argsort, as the sort path makes it.  Every lane of the wave reads the
+// same key at a time (an LDS broadcast).
+constexpr uint32_t kSmallPerm = 1024;
+
+struct SmallPerms {
+    ChachaKey pk[3];
+    uint32_t p[3];
+    uint32_t inverse[3];
+    uint32_t* out[3];
+};
+
+__global__ __launch_bounds__(1024) void k_perm_small(uint32_t n, SmallPerms J) {
+    __shared__ uint64_t key[kSmallPerm];
+    const uint32_t q = blockIdx.x;
+    const uint32_t lanes = (n + 7) / 8 * 4;              // whole quads: a quad makes the keys of 8 rows
+    for (uint32_t t = threadIdx.x; t < lanes; t += blockDim.x) {
+        const uint4 o = chacha_quad(J.pk[q], t >> 2, 0u, 16u + J.p[q], 0u);
+        const uint32_t r0 = (t >> 2) * 8 + 2 * (t & 3);
+        if (r0 < n) key[r0] = (uint64_t)o.x | ((uint64_t)o.y << 32);
+        if (r0 + 1 < n) key[r0 + 1] = (uint64_t)o.z | ((uint64_t)o.w << 32);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint64_t ki = key[i];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; j++) {
+            const uint64_t kj = key[j];
+            rank += (kj < ki || (kj == ki && j < i)) ? 1u : 0u;
+        }
+        if (J.inverse[q])
+            J.out[q][i] = rank;
+        else
+            J.out[q][rank] = i;
+    }
+}
+
 // The permutation is the stable argsort of the 64-bit keys.  It is made in two
 // steps: a stable radix sort of the rows by run id (the top hb key bits, hb =
 // ceil(log2 n) - 6, so that a run holds 64 rows on average), then each run
@@ -624,6 +665,22 @@ struct PermSet {
         }
         if (!ws.ok) {
             rc = fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
+            return;
+        }
+        if (nrows <= kSmallPerm) {
+            // one launch on the caller's stream: no sort, no side streams
+            SmallPerms J{};
+            const uint64_t sd[3] = {seeds[0], seeds[2], seeds[1]};
+            const uint32_t pid[3] = {kP12, kP31, kP23}, inv[3] = {1, 1, 0};
+            uint32_t* outs[3] = {inv12, inv31, p23};
+            for (int q = 0; q < 3; q++) {
+                J.pk[q] = pair_key(sd[q]);
+                J.p[q] = pid[q];
+                J.inverse[q] = inv[q];
+                J.out[q] = outs[q];
+            }
+            hipLaunchKernelGGL(k_perm_small, dim3(3), dim3(1024), 0, s, (uint32_t)nrows, J);
+            rc = check_launch("k_perm_small");
             return;
         }
         side[0] = perm_stream(0), side[1] = perm_stream(1);

@@ -37,8 +37,8 @@ def _rss_table(seed, n, w):
 # one-sweep path above: 2^20 + 100 rows cover the last.  Widths of 48, 33 and
 # 17 words take three, three and two 16-word slices per record (ChaCha blocks),
 # the last ones partial.
-@pytest.mark.parametrize("n,w", [(1, 1), (17, 3), (64, 4), (1000, 8), (3000, 2), (4096, 4), (5000, 3),
-                                 (65573, 4), ((1 << 20) + 100, 4), (2, 48), (777, 33), (4099, 17)])
+@pytest.mark.parametrize("n,w", [(1, 1), (17, 3), (64, 4), (1000, 8), (1024, 2), (1025, 2), (3000, 2), (4096, 4),
+                                 (5000, 3), (65573, 4), ((1 << 20) + 100, 4), (2, 48), (777, 33), (4099, 17)])
 def test_shuffle_parity(fss, n, w):
     d, sh = _rss_table(n + w, n, w)
     seeds = (101, 202, 303)
