@@ -254,7 +254,7 @@ def run_full(args, torch, fss, dev, graph, query):
     queue = fss.Queue(len(evreqs), dev)
     plan = fss.Plan(SEED, query.query_id, query.n_qv, graph.n_vertices, graph.n_edges,
                     [(d["p"].target, None, None, tuple(d["bits"])) for d in preds],
-                    T(graph.src), T(graph.dst)).allocate(dev)
+                    T(graph.src), T(graph.dst), query.edges).allocate(dev)
     key_gb = sum(2 * d["kb"].bytes_per_party for d in preds) / 1e9
     log(f"inputs resident; keys {key_gb:.1f} GB for both parties")
     stream = torch.cuda.current_stream()
@@ -514,12 +514,14 @@ def run_batch64(args, torch, fss, dev):
             preds.append(dict(target=p.target, kind=fss.EQ if p.kind == "eq" else fss.RANGE, rows=nrow,
                               a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
         jobs.append(QueryJob(SEED, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds,
-                             T(view.src) if view.n_edges else None, T(view.dst) if view.n_edges else None))
+                             T(view.src) if view.n_edges else None, T(view.dst) if view.n_edges else None,
+                             edges=q.edges))
     torch.cuda.synchronize()
     log(f"64 queries ready: {walks / 1e6:.1f} M tree walks (both parties)")
 
     def outputs(plan, job):
-        w = (job.n_vertices + 31) // 32 if job.n_qv == 1 else (job.n_qv - 1) * ((job.n_edges + 31) // 32)
+        n_qe = len(job.edges) if job.edges is not None else job.n_qv - 1
+        w = (job.n_vertices + 31) // 32 if job.n_qv == 1 else n_qe * ((job.n_edges + 31) // 32)
         return [plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
 
     # plain: one query at a time
@@ -533,7 +535,7 @@ def run_batch64(args, torch, fss, dev):
                     fss.fss_keygen(job.seed, job.query_id, k, p["a_or_lo"], p["hi"], p["r"], kb)
                 kbs.append((p["target"], kb, p["xhat"]))
             plan = fss.Plan(job.seed, job.query_id, job.n_qv, job.n_vertices, job.n_edges, kbs, job.src,
-                            job.dst).allocate(dev)
+                            job.dst, job.edges).allocate(dev)
             fss.match_query(plan)
             plan.release_inputs()      # the keys are not needed once match_query is enqueued
             res.append(plan)
@@ -1146,9 +1148,9 @@ def cpu_baseline_full(graph, query, shares, masks, plan, nsample):
     ne = graph.n_edges
     rows = np.unique(np.concatenate([[0, 1, 31, 32, ne - 2, ne - 1], rng.integers(0, ne, nsample)])).astype(np.int64)
     w = {"eq": 1, "range": 2}
-    per_target = [sum(w[p.kind] for p in query.preds if p.target == t) for t in range(2 * query.n_qv - 1)]
-    walks_per_row = 2 * sum(per_target[j] + per_target[j + 1] + per_target[query.n_qv + j]
-                            for j in range(query.n_qv - 1))
+    per_target = [sum(w[p.kind] for p in query.preds if p.target == t) for t in range(query.n_qv + query.n_qe)]
+    walks_per_row = 2 * sum(per_target[a] + per_target[b] + per_target[query.n_qv + j]
+                            for j, (a, b) in enumerate(query.qedges))
 
     def timed(sample, nthreads):
         _omp_threads(nthreads)
@@ -1160,7 +1162,7 @@ def cpu_baseline_full(graph, query, shares, masks, plan, nsample):
     dt, want = timed(rows, threads)
     we = (ne + 31) // 32
     exact = True
-    for j in range(query.n_qv - 1):
+    for j in range(query.n_qe):
         for b in range(2):
             got = plan.out[b][j * we:(j + 1) * we].cpu().numpy().view(np.uint32)
             exact &= bool(np.array_equal(ofss.unpack_bits(got, ne)[rows], want[j, b]))

@@ -167,32 +167,40 @@ int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, co
            const uint32_t* d_triple, const uint32_t* d_de_open, uint32_t* d_out, void* stream);
 
 /*
- * Edge matching -- a whole path query v_0 -> v_1 -> ... -> v_{n_qv-1} (Alg. 2, secMatch,
- * with public edge endpoints) for BOTH simulated parties.
+ * Edge matching -- a whole query graph (Def. 2; Alg. 2, secMatch, with public
+ * edge endpoints).  The query has vertices 0 .. n_qv-1 and n_qe directed query
+ * edges j = (a_j, b_j) given in q_edges as a_0, b_0, a_1, b_1, ...; n_qe == 0
+ * with n_qv > 1 means the path v_0 -> v_1 -> ... -> v_{n_qv-1} (edge j =
+ * (j, j+1)).  Query edges join distinct query vertices, no ordered pair comes
+ * twice, every query vertex of a query of several lies on an edge, and a
+ * one-vertex query has none (else EINVAL).
  *
  * Predicate k targets query vertex `target` (< n_qv; rows = vertex table) or
- * query edge target - n_qv (edge v_j -> v_{j+1}; rows = edge table).  Its keys
- * must have been made with pred_id = k, and d_xhat holds the target table's
- * opened values.  Semantics:
+ * query edge target - n_qv (rows = edge table).  Its keys must have been made
+ * with pred_id = k, and d_xhat holds the target table's opened values.
+ * Semantics:
  *   1. each party evaluates every predicate (DPF / range) on its rows;
  *   2. per query vertex, then per query edge, its predicate bits are ANDed as
  *      a left fold in plan order (none: the public constant 1);
- *   3. per hop j: h_j = (m_j[src] AND m_{j+1}[dst]) AND q_j over edge rows,
- *      where m[src] gathers each party's own share bit at the public index;
+ *   3. per query edge j: h_j = (m_{a_j}[src] AND m_{b_j}[dst]) AND q_j over
+ *      edge rows, where m[src] gathers each party's own share bit at the
+ *      public index;
  *   4. ANDs are numbered 0,1,... in execution order (step 2 vertex folds, then
- *      edge folds, then two per hop) and AND i uses the Beaver triple stream
- *      (seed, query_id, i); an AND with a public-1 operand is skipped and
- *      takes no number.
+ *      edge folds, then two per query edge) and AND i uses the Beaver triple
+ *      stream (seed, query_id, i); an AND with a public-1 operand is skipped
+ *      and takes no number.
  * Output d_out[b] (party b): n_qv == 1 -> m_0, ceil(n_vertices/32) words;
- * else h_0 .. h_{n_qv-2}, each ceil(n_edges/32) words, hop after hop.
+ * else h_0 .. h_{n_qe-1} (n_qv - 1 of them for the path), each
+ * ceil(n_edges/32) words, query edge after query edge.  The client joins the
+ * h_j on their shared query vertices to list the matched subgraphs.
  * Workspace: match_workspace_bytes(plan) bytes of device memory, 256-aligned;
  * the library lays it out the same way on every call with the same plan.
  *
  * party_mask 3: both simulated parties at once (every AND opens, exchanges
  * and closes in one pass).
  * party_mask 1 / 2: ONE server's half (party 0 / party 1), run in rounds with
- * the peer.  An AND of level L (step L of a fold; a hop's ANDs come after the
- * folds they read) opens in round L - 1 and closes in round L.
+ * the peer.  An AND of level L (step L of a fold; a query edge's ANDs come
+ * after the folds they read) opens in round L - 1 and closes in round L.
  * match_rounds() gives the number of exchange rounds R and the size of each
  * round's message.  Round r (plan->round = r, r = 0 .. R):
  *   r == 0: evaluates this party's predicate bits (only key[party] is read);
@@ -207,6 +215,7 @@ int ss_and(int32_t phase, int32_t party, uint64_t nrows, const uint32_t* d_x, co
  * R, a missing d_peer_msg (r > 0) or d_msg (r < R).
  */
 #define FSS_MAX_QV 8
+#define FSS_MAX_QE 16
 #define FSS_MAX_PREDS 32
 
 typedef struct fss_pred {
@@ -225,12 +234,13 @@ typedef struct match_plan {
     uint32_t query_id;
     uint32_t n_qv;                  /* 1 .. FSS_MAX_QV */
     uint32_t n_pred;                /* 0 .. FSS_MAX_PREDS */
-    uint32_t reserved;
+    uint32_t n_qe;                  /* 0 (the path, or no edge for n_qv == 1) .. FSS_MAX_QE */
     uint64_t n_vertices;
     uint64_t n_edges;
     const uint32_t* d_src;          /* public endpoints (n_edges each); unused when n_qv == 1 */
     const uint32_t* d_dst;
     const fss_pred* preds;          /* host array of n_pred predicates */
+    const uint32_t* q_edges;        /* host array of 2 * n_qe query-edge ends; NULL if n_qe == 0 */
     uint32_t* d_out[2];
     void* d_workspace;
     uint64_t workspace_bytes;

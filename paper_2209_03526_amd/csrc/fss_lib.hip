@@ -1299,12 +1299,36 @@ struct Arena {
 
 uint64_t words_of(uint64_t rows) { return (rows + 31) / 32; }
 
+// The plan's query edges (a_j, b_j): q_edges, or the path (j, j + 1) when n_qe
+// is 0.  Returns nullptr when they are valid, else what is wrong with them.
+const char* query_edges(const match_plan* P, uint32_t* qa, uint32_t* qb, uint32_t* n_qe) {
+    if (P->n_qe > FSS_MAX_QE) return "more query edges than FSS_MAX_QE";
+    if (P->n_qe && !P->q_edges) return "q_edges is NULL";
+    *n_qe = 0;
+    if (P->n_qv <= 1) return P->n_qe ? "a one-vertex query has no edges" : nullptr;
+    const uint32_t n = P->n_qe ? P->n_qe : P->n_qv - 1;
+    uint32_t covered = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        const uint32_t a = P->n_qe ? P->q_edges[2 * j] : j;
+        const uint32_t b = P->n_qe ? P->q_edges[2 * j + 1] : j + 1;
+        if (a >= P->n_qv || b >= P->n_qv || a == b) return "a query edge does not join two distinct query vertices";
+        for (uint32_t i = 0; i < j; i++)
+            if (qa[i] == a && qb[i] == b) return "a query edge is given twice";
+        qa[j] = a;
+        qb[j] = b;
+        covered |= 1u << a | 1u << b;
+    }
+    if (covered != (1u << P->n_qv) - 1) return "a query vertex is on no query edge";
+    *n_qe = n;
+    return nullptr;
+}
+
 // The plan's steps after evaluation, laid out in the workspace -- a pure
 // function of the plan, so every call on the same plan finds the same
 // buffers (the single-party rounds rely on it).
 //   folds: per target t (query vertices 0..n_qv-1, then query edges) its
 //          predicates ANDed as a left fold; step s of a fold is AND level s;
-//   hops:  h_j = (m_j[src] AND m_j+1[dst]) AND q_j;
+//   hops:  per query edge j = (a_j, b_j), h_j = (m_a[src] AND m_b[dst]) AND q_j;
 // AND numbers follow that order (vertex folds, edge folds, then per hop the
 // AND of the endpoints and the AND with q_j); an AND with a public operand is
 // skipped and takes no number.  Level L of an AND: in a single-party run it
@@ -1318,7 +1342,7 @@ struct TailPlan {
         bool hop;           // an AND of a hop join
     };
     struct Hop {
-        bool g, h, q;               // m_j, m_j+1, q_j not public
+        bool g, h, q;               // m_a, m_b, q_j not public
         int32_t a1 = -1, a2 = -1;   // indices into ands
         uint32_t lg = 0;            // round in which the gathers run (single party)
         uint32_t lq = 0;            // round from which q_j is ready
@@ -1326,16 +1350,17 @@ struct TailPlan {
         uint32_t* out[2];
     };
     const match_plan* P = nullptr;
-    uint32_t n_qv = 0, ntarget = 0;
+    uint32_t n_qv = 0, n_qe = 0, ntarget = 0;
+    uint32_t qa[FSS_MAX_QE] = {}, qb[FSS_MAX_QE] = {};     // query edge j = (qa[j], qb[j])
     uint64_t wv = 0, we = 0;
     Shares pbits[FSS_MAX_PREDS];
-    Shares fold[2 * FSS_MAX_QV];
-    uint32_t depth[2 * FSS_MAX_QV] = {};
-    uint32_t npred_of[2 * FSS_MAX_QV] = {};
-    uint32_t first_pred[2 * FSS_MAX_QV] = {};
+    Shares fold[FSS_MAX_QV + FSS_MAX_QE];
+    uint32_t depth[FSS_MAX_QV + FSS_MAX_QE] = {};
+    uint32_t npred_of[FSS_MAX_QV + FSS_MAX_QE] = {};
+    uint32_t first_pred[FSS_MAX_QV + FSS_MAX_QE] = {};
     uint2* pair[FSS_MAX_QV] = {};
     std::vector<And> ands;          // in AND-number order
-    Hop hop[FSS_MAX_QV];
+    Hop hop[FSS_MAX_QE];
     uint32_t rounds = 0;            // single-party exchange rounds
 
     uint64_t rows_of(uint32_t t) const { return t < n_qv ? P->n_vertices : P->n_edges; }
@@ -1343,7 +1368,8 @@ struct TailPlan {
     int build(const match_plan* plan, Arena& ws) {
         P = plan;
         n_qv = P->n_qv;
-        ntarget = 2 * n_qv - 1;
+        if (const char* bad = query_edges(P, qa, qb, &n_qe)) return fail(FSS_EINVAL, "match_query: %s", bad);
+        ntarget = n_qv + n_qe;
         wv = words_of(P->n_vertices);
         we = words_of(P->n_edges);
         auto nomem = [] { return fail(FSS_ENOMEM, "match_query: workspace too small"); };
@@ -1391,14 +1417,14 @@ struct TailPlan {
             for (uint32_t i = 0; i < n_qv; i++)
                 if (!fold[i].is_public() && !(pair[i] = (uint2*)ws.take(2 * wv))) return nomem();
         }
-        for (uint32_t j = 0; j + 1 < n_qv; j++) {
+        for (uint32_t j = 0; j < n_qe; j++) {
             Hop& H = hop[j];
-            H.g = !fold[j].is_public();
-            H.h = !fold[j + 1].is_public();
+            H.g = !fold[qa[j]].is_public();
+            H.h = !fold[qb[j]].is_public();
             H.q = !fold[n_qv + j].is_public();
             H.out[0] = P->d_out[0] + (uint64_t)j * we;
             H.out[1] = P->d_out[1] + (uint64_t)j * we;
-            H.lg = std::max(H.g ? depth[j] : 0u, H.h ? depth[j + 1] : 0u);
+            H.lg = std::max(H.g ? depth[qa[j]] : 0u, H.h ? depth[qb[j]] : 0u);
             H.lq = depth[n_qv + j];
             if (H.g && !ws.take2(we, H.gs)) return nomem();
             if (H.h && !ws.take2(we, H.hs)) return nomem();
@@ -1518,15 +1544,15 @@ void fused_levels(const TailPlan& T, uint32_t rk, std::vector<std::vector<TailOp
         o.z[0] = (uint32_t*)T.pair[i];
         put(first, o);
     }
-    for (uint32_t j = 0; j + 1 < T.n_qv; j++) {
+    for (uint32_t j = 0; j < T.n_qe; j++) {
         const TailPlan::Hop& H = T.hop[j];
         TailOp o = tail_op(TK_HOP, P, P->n_edges);
         o.party = (H.g ? kHopSrc : 0) | (H.h ? kHopDst : 0) | (H.q ? kHopQ : 0);
         o.nsrc = P->n_vertices;
         o.src = P->d_src;
         o.dst = P->d_dst;
-        o.gsrc = T.pair[j];
-        o.gdst = T.pair[j + 1];
+        o.gsrc = T.pair[T.qa[j]];
+        o.gdst = T.pair[T.qb[j]];
         if (H.q) { o.x[0] = T.fold[T.n_qv + j].p[0]; o.x[1] = T.fold[T.n_qv + j].p[1]; }
         if (H.a1 >= 0) o.and1 = T.ands[H.a1].id;
         if (H.a2 >= 0) o.and2 = T.ands[H.a2].id;
@@ -1578,7 +1604,7 @@ void party_round(const TailPlan& T, uint32_t b, uint32_t r, const uint32_t* peer
             }
         }
     } else {
-        for (uint32_t j = 0; j + 1 < T.n_qv; j++) {
+        for (uint32_t j = 0; j < T.n_qe; j++) {
             const TailPlan::Hop& H = T.hop[j];
             const bool final_gather = H.a1 < 0 && H.a2 < 0;   // the gathered bits are the result
             if (H.lg == r) {
@@ -1589,7 +1615,7 @@ void party_round(const TailPlan& T, uint32_t b, uint32_t r, const uint32_t* peer
                     o.rk = rk;
                     o.nsrc = P->n_vertices;
                     o.src = side ? P->d_dst : P->d_src;
-                    o.x[0] = T.fold[j + side].p[b];
+                    o.x[0] = T.fold[side ? T.qb[j] : T.qa[j]].p[b];
                     o.z[0] = final_gather ? H.out[b] : (side ? H.hs.p[b] : H.gs.p[b]);
                     phase[1].push_back(o);
                 }
@@ -1633,7 +1659,9 @@ int validate_plan(const match_plan* P, int32_t party_mask, const char* who) {
         if ((party_mask >> b & 1) && !P->d_out[b]) return fail(FSS_EINVAL, "%s: NULL output of party %d", who, b);
     if (party_mask == 3 && (!P->d_out[0] || !P->d_out[1])) return fail(FSS_EINVAL, "%s: NULL output", who);
     if (P->n_qv > 1 && P->n_edges && (!P->d_src || !P->d_dst)) return fail(FSS_EINVAL, "%s: NULL edge endpoints", who);
-    const uint32_t ntarget = 2 * P->n_qv - 1;
+    uint32_t qa[FSS_MAX_QE], qb[FSS_MAX_QE], n_qe = 0;
+    if (const char* bad = query_edges(P, qa, qb, &n_qe)) return fail(FSS_EINVAL, "%s: %s", who, bad);
+    const uint32_t ntarget = P->n_qv + n_qe;
     for (uint32_t k = 0; k < P->n_pred; k++) {
         const fss_pred& p = P->preds[k];
         if (p.target < 0 || (uint32_t)p.target >= ntarget)
@@ -1974,8 +2002,10 @@ extern "C" {
 uint64_t match_workspace_bytes(const match_plan* plan) {
     if (!plan || plan->n_qv == 0 || plan->n_qv > FSS_MAX_QV || plan->n_pred > FSS_MAX_PREDS) return 0;
     if (plan->n_pred && !plan->preds) return 0;
+    uint32_t qa[FSS_MAX_QE], qb[FSS_MAX_QE], n_qe = 0;
+    if (query_edges(plan, qa, qb, &n_qe)) return 0;
     for (uint32_t k = 0; k < plan->n_pred; k++)
-        if (plan->preds[k].target < 0 || (uint32_t)plan->preds[k].target >= 2 * plan->n_qv - 1) return 0;
+        if (plan->preds[k].target < 0 || (uint32_t)plan->preds[k].target >= plan->n_qv + n_qe) return 0;
     return plan_workspace(plan);
 }
 
@@ -2138,7 +2168,9 @@ int rss_reshare(uint64_t nrows, const uint32_t* const d_x[3], const uint64_t prf
 
 int rss_from_fss(uint64_t nrows, const uint32_t* const d_y[2], const uint64_t prf_keys[3], uint32_t counter,
                  uint32_t* const d_z[3], void* stream) {
-    if (!d_y) { ogm::last_error() = "rss_from_fss: NULL y"; return FSS_EINVAL; }
+    ogm::last_error().clear();
+    if (nrows == 0) return FSS_OK;
+    if (!d_y) return fail(FSS_EINVAL, "rss_from_fss: NULL y");
     const uint32_t* x[3] = {d_y[0], d_y[1], nullptr};
     return rss_run(nrows, x, nullptr, prf_keys, counter, d_z, stream, "rss_from_fss", true);
 }
@@ -2339,8 +2371,9 @@ uint64_t match_batch_queue_bytes(const match_plan* plans, uint32_t count) {
         std::vector<EvalDesc> d;
         plan_evals(T, 3, d);
         nevals += d.size();
-        // every AND, two gathers per hop and one copy per output, at most, in any launch
-        nops += T.ands.size() + 3 * (uint64_t)T.n_qv + 2;
+        // every AND, two gathers per hop, one pair op per vertex and one copy per output, at most,
+        // in any launch
+        nops += T.ands.size() + 3 * (uint64_t)T.n_qe + T.n_qv + 2;
     }
     return std::max(queue_bytes(nevals), tail_queue_bytes(count, nops));
 }

@@ -15,7 +15,7 @@ from . import build as _build
 
 EQ, RANGE = 0, 1
 SS_AND_OPEN, SS_AND_CLOSE = 0, 1
-MAX_QV, MAX_PREDS = 8, 32
+MAX_QV, MAX_QE, MAX_PREDS = 8, 16, 32
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 
@@ -39,10 +39,11 @@ class fss_pred(ctypes.Structure):
 
 class match_plan(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("query_id", ctypes.c_uint32), ("n_qv", ctypes.c_uint32),
-                ("n_pred", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n_pred", ctypes.c_uint32), ("n_qe", ctypes.c_uint32),
                 ("n_vertices", ctypes.c_uint64), ("n_edges", ctypes.c_uint64),
                 ("d_src", ctypes.c_void_p), ("d_dst", ctypes.c_void_p),
-                ("preds", ctypes.POINTER(fss_pred)), ("d_out", ctypes.c_void_p * 2),
+                ("preds", ctypes.POINTER(fss_pred)), ("q_edges", ctypes.POINTER(ctypes.c_uint32)),
+                ("d_out", ctypes.c_void_p * 2),
                 ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("round", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
                 ("d_peer_msg", ctypes.c_void_p), ("d_msg", ctypes.c_void_p)]
@@ -235,9 +236,10 @@ def ss_and(phase: int, party: int, nrows: int, x, y, triple, de_open, out, strea
 class Plan:
     """A match_plan with its ctypes storage kept alive."""
 
-    def __init__(self, seed, query_id, n_qv, n_vertices, n_edges, preds, src=None, dst=None):
+    def __init__(self, seed, query_id, n_qv, n_vertices, n_edges, preds, src=None, dst=None, edges=None):
         """preds: list of (target, KeyBatch, xhat tensor) -- evaluated by match_query --
-        or (target, None, None, (bits0, bits1)) -- share bits already evaluated."""
+        or (target, None, None, (bits0, bits1)) -- share bits already evaluated.
+        edges: the query edges [(a, b), ...]; None: the path (j, j + 1)."""
         self._preds = (fss_pred * max(1, len(preds)))()
         self._keep = []
         for i, pr in enumerate(preds):
@@ -257,13 +259,18 @@ class Plan:
         self.c.d_dst = _ptr(dst)
         self.c.preds = ctypes.cast(self._preds, ctypes.POINTER(fss_pred))
         self._keep.append((src, dst))
+        flat = [int(v) for e in (edges or []) for v in e]
+        self._qedges = (ctypes.c_uint32 * max(1, len(flat)))(*flat)    # read on every call: kept
+        self.c.n_qe = len(flat) // 2
+        self.c.q_edges = ctypes.cast(self._qedges, ctypes.POINTER(ctypes.c_uint32)) if flat else None
         self.out = None
         self.workspace = None
 
     def out_words(self) -> int:
         if self.c.n_qv == 1:
             return words(self.c.n_vertices)
-        return (self.c.n_qv - 1) * words(self.c.n_edges)
+        n_qe = self.c.n_qe or self.c.n_qv - 1
+        return n_qe * words(self.c.n_edges)
 
     def allocate(self, device=None):
         dev = device or torch.device("cuda")

@@ -38,6 +38,7 @@ class QueryJob:
     nbits: int = 32
     bits: list = field(default_factory=list)      # per predicate: (bits0, bits1) tensors
     plan: object = None
+    edges: list = None                            # query edges; None: the path
 
 
 def _key_bytes(kind, nbits, rows):
@@ -160,7 +161,7 @@ class ChunkedRunner:
         for job in jobs:
             preds = [(p["target"], None, None, job.bits[k]) for k, p in enumerate(job.preds)]
             plan = fss.Plan(job.seed, job.query_id, job.n_qv, job.n_vertices, job.n_edges, preds, job.src,
-                            job.dst).allocate(self.device)
+                            job.dst, job.edges).allocate(self.device)
             job.plan = plan
             plans.append(plan)
         fss.match_query_batch(plans, self.queue, 3, self.stream)

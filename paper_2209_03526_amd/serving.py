@@ -115,7 +115,8 @@ def memory_bound(req: Request) -> int:
     rows = req.rows
     npred = len(req.query.preds)
     per_table = 8 * rows + 16 * _words(rows)
-    return 16 * rows + npred * (per_table + 16 * rows) + 32 * _words(rows) * (2 * npred + 8 * req.query.n_qv)
+    width = max(req.query.n_qv, req.query.n_qe + 1)     # n_qv for a path
+    return 16 * rows + npred * (per_table + 16 * rows) + 32 * _words(rows) * (2 * npred + 8 * width)
 
 
 def request_key_bytes(req: Request) -> int:
@@ -129,7 +130,7 @@ def _plan(req: Request, bits_given: bool, device):
     else:
         preds = [(p["target"], p["kb"], p["xhat"]) for p in req.preds]
     return fss.Plan(req.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
-                    v["dst"]).allocate(device)
+                    v["dst"], q.edges).allocate(device)
 
 
 class ServedPath:
@@ -374,8 +375,8 @@ def given_memory(tok: Token) -> int:
     (bounded with every table at the token's largest row count)."""
     rows = max([d["rows"] for d in tok.preds] + [tok.view["n_vertices"], tok.view["n_edges"], 1])
     npred = len(tok.preds)
-    n_qv = tok.query.n_qv
-    return 4 * rows * npred + 8 * _words(rows) * (2 * npred + 4 * n_qv + 4) + 4096 * (npred + 2)
+    width = max(tok.query.n_qv, tok.query.n_qe + 1)     # n_qv for a path
+    return 4 * rows * npred + 8 * _words(rows) * (2 * npred + 4 * width + 4) + 4096 * (npred + 2)
 
 
 def _open_given(req: GivenRequest, tok: Token, g: ResidentGraph, device, stream):
@@ -397,7 +398,7 @@ def _given_plan_with_keys(req: GivenRequest, tok: Token, device):
     q, v = tok.query, tok.view
     preds = [(d["target"], d["kb"], req.xhat[k]) for k, d in enumerate(tok.preds)]
     return fss.Plan(tok.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
-                    v["dst"]).allocate(device)
+                    v["dst"], q.edges).allocate(device)
 
 
 def _given_plan_with_bits(req: GivenRequest, tok: Token, device):
@@ -406,7 +407,7 @@ def _given_plan_with_bits(req: GivenRequest, tok: Token, device):
                 for d in tok.preds]
     preds = [(d["target"], None, None, req.bits[k]) for k, d in enumerate(tok.preds)]
     return fss.Plan(tok.seed, q.query_id, q.n_qv, v["n_vertices"], v["n_edges"], preds, v["src"],
-                    v["dst"]).allocate(device)
+                    v["dst"], q.edges).allocate(device)
 
 
 class GivenServedPath:
@@ -561,7 +562,7 @@ class GivenPlainPath:
 def given_outputs(req: GivenRequest, pool: TokenPool):
     tok = pool.tokens[req.entry]
     v = tok.view
-    w = _words(v["n_vertices"]) if tok.query.n_qv == 1 else (tok.query.n_qv - 1) * _words(v["n_edges"])
+    w = _words(v["n_vertices"]) if tok.query.n_qv == 1 else tok.query.n_qe * _words(v["n_edges"])
     return [req.plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
 
 
@@ -576,7 +577,7 @@ def _drop_intermediates(req: Request):
 
 def outputs(req: Request):
     v = req.view
-    w = _words(v["n_vertices"]) if req.query.n_qv == 1 else (req.query.n_qv - 1) * _words(v["n_edges"])
+    w = _words(v["n_vertices"]) if req.query.n_qv == 1 else req.query.n_qe * _words(v["n_edges"])
     return [req.plan.out[b][:w].cpu().numpy().copy() for b in range(2)]
 
 

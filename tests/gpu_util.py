@@ -48,7 +48,8 @@ def run_query_gpu(fss, graph, query, shares, masks, seed, nbits=32):
         preds.append((p.target, kb, xhat))
     src = T(graph.src) if graph.n_edges else None
     dst = T(graph.dst) if graph.n_edges else None
-    plan = fss.Plan(seed, query.query_id, query.n_qv, graph.n_vertices, graph.n_edges, preds, src, dst)
+    plan = fss.Plan(seed, query.query_id, query.n_qv, graph.n_vertices, graph.n_edges, preds, src, dst,
+                    query.edges)
     plan.allocate()
     fss.match_query(plan)
     torch.cuda.synchronize()
@@ -62,7 +63,7 @@ def plan_outputs(plan, query, graph):
         return [(U(plan.out[0], w), U(plan.out[1], w))]
     we = (graph.n_edges + 31) // 32
     o0, o1 = U(plan.out[0]), U(plan.out[1])
-    return [(o0[j * we:(j + 1) * we], o1[j * we:(j + 1) * we]) for j in range(query.n_qv - 1)]
+    return [(o0[j * we:(j + 1) * we], o1[j * we:(j + 1) * we]) for j in range(query.n_qe)]
 
 
 def T_off(a, dtype=np.uint32):
@@ -96,4 +97,4 @@ def job_inputs(fss, view, q, vsh, masks, seed):
                           a_or_lo=p.a if p.kind == "eq" else p.lo, hi=p.hi, r=r, xhat=xhat))
     src = T(view.src) if view.n_edges else None
     dst = T(view.dst) if view.n_edges else None
-    return QueryJob(seed, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds, src, dst)
+    return QueryJob(seed, q.query_id, q.n_qv, view.n_vertices, view.n_edges, preds, src, dst, edges=q.edges)

@@ -204,3 +204,109 @@ def test_shuffle_and_fetch_argument_errors(fss):
     # Case I words per record
     assert L.rss_fetch_unique(8, 65536, three, three, three, None) == fss.EUNSUPPORTED
     assert L.rss_fetch_unique(8, 4, None, three, three, None) == fss.EINVAL
+
+
+def test_access_and_conversion_argument_errors(fss):
+    """The Alg. 1 / Alg. 6 calls and the two-party conversion reject bad
+    arguments on the host, before anything is enqueued."""
+    L = fss.LIB
+    fake = 1 << 20
+    three = (ctypes.c_void_p * 3)(fake, fake, fake)
+    two = (ctypes.c_void_p * 2)(fake, fake)
+    keys3 = (ctypes.c_uint64 * 3)(1, 2, 3)
+    keys2 = (ctypes.c_uint64 * 2)(1, 2)
+    # rss_from_fss
+    assert L.rss_from_fss(64, None, keys3, 0, three, None) == fss.EINVAL
+    assert L.rss_from_fss(64, two, keys3, 0, (ctypes.c_void_p * 3)(fake, None, fake), None) == fss.EINVAL
+    assert L.rss_from_fss(0, None, None, 0, None, None) == fss.OK           # nothing to do
+    # rss_enc_posting_lists
+    assert L.rss_enc_posting_lists(4, 0, fake, fake, fake, fake, 8, keys2, 0, three, fake, 1 << 20, None) == fss.EINVAL
+    assert L.rss_enc_posting_lists(4, 64, None, fake, fake, fake, 8, keys2, 0, three, fake, 1 << 20, None) == fss.EINVAL
+    assert L.rss_enc_posting_lists(4, 64, fake, fake, fake, fake, 8, keys2, 0, three, fake, 16, None) == fss.ENOMEM
+    # rss_sec_access
+    ws = L.rss_sec_access_workspace_bytes(24, 2000, 2)
+    assert ws > 0
+    args = dict(ncand=100, x_bits=2000, idm=three, off=fake, lmax=24, post=three, aw=2, attr=three, keys=keys3,
+                counter=0, seeds=keys3, ids=three, attrs=three, rows=fake, count=fake, work=fake, wbytes=ws)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.rss_sec_access(a["ncand"], a["x_bits"], a["idm"], a["off"], a["lmax"], a["post"], a["aw"],
+                                a["attr"], a["keys"], a["counter"], a["seeds"], a["ids"], a["attrs"], a["rows"],
+                                a["count"], a["work"], a["wbytes"], None)
+
+    assert call(lmax=0) == fss.EINVAL and b"lmax" in L.fss_last_error()
+    assert call(lmax=70000) == fss.EINVAL
+    assert call(x_bits=0) == fss.EINVAL
+    assert call(off=None) == fss.EINVAL
+    assert call(attrs=(ctypes.c_void_p * 3)(fake, fake, None)) == fss.EINVAL
+    assert call(wbytes=ws - 1) == fss.ENOMEM
+
+
+def _star_plan(fss, keep, edges):
+    """Three query vertices: two predicates on vertex 0, one on each of 1 and 2
+    (share bits given: fake, aligned, never dereferenced); query edges as
+    given (None: the path)."""
+    preds = (fss.fss_pred * 4)()
+    for k, t in enumerate((0, 0, 1, 2)):
+        preds[k] = fss.fss_pred(t, 0, None, None, (ctypes.c_void_p * 2)(1 << 20, 1 << 21))
+    plan = fss.match_plan()
+    plan.n_qv, plan.n_pred = 3, 4
+    plan.preds = ctypes.cast(preds, ctypes.POINTER(fss.fss_pred))
+    plan.n_vertices, plan.n_edges = 100, 50
+    plan.d_src, plan.d_dst = 1 << 22, 1 << 23
+    plan.d_out[0], plan.d_out[1] = 1 << 24, 1 << 25
+    plan.d_workspace = 1 << 26
+    if edges is not None:
+        flat = (ctypes.c_uint32 * max(1, 2 * len(edges)))(*[v for e in edges for v in e])
+        plan.n_qe = len(edges)
+        plan.q_edges = ctypes.cast(flat, ctypes.POINTER(ctypes.c_uint32))
+        keep.append(flat)
+    plan.workspace_bytes = fss.LIB.match_workspace_bytes(ctypes.byref(plan))
+    keep.append(preds)
+    return plan
+
+
+def _rounds(fss, plan):
+    n = ctypes.c_uint32()
+    words = (ctypes.c_uint64 * 8)()
+    assert fss.LIB.match_rounds(ctypes.byref(plan), ctypes.byref(n), words, 8) == fss.OK
+    return [int(words[r]) for r in range(n.value)]
+
+
+def test_query_edges_schedule_and_errors(fss):
+    """Query graphs (Def. 2): the AND levels follow the query edges given, and
+    malformed query graphs are refused before anything is enqueued."""
+    L = fss.LIB
+    keep = []
+    wv, we = (100 + 31) // 32, (50 + 31) // 32
+    # path 0 -> 1 -> 2: the hop 1 -> 2 is ready in round 0, the hop 0 -> 1 after m_0's fold
+    assert _rounds(fss, _star_plan(fss, keep, None)) == [2 * wv + 2 * we, 2 * we]
+    assert _rounds(fss, _star_plan(fss, keep, [(0, 1), (1, 2)])) == [2 * wv + 2 * we, 2 * we]
+    # out-star 0 -> 1, 0 -> 2: both hops wait for m_0's fold
+    star = _star_plan(fss, keep, [(0, 1), (0, 2)])
+    assert _rounds(fss, star) == [2 * wv, 4 * we]
+    assert star.workspace_bytes > 0
+    # a triangle has three hops
+    assert _rounds(fss, _star_plan(fss, keep, [(0, 1), (1, 2), (2, 0)])) == [2 * wv + 2 * we, 4 * we]
+    bad = [[(0, 0), (1, 2)], [(0, 1), (0, 1), (1, 2)], [(0, 3), (1, 2)], [(0, 1)], [(0, 1)] * 17]
+    for edges in bad:
+        plan = _star_plan(fss, keep, edges)
+        assert plan.workspace_bytes == 0, edges
+        plan.workspace_bytes = 1 << 20
+        assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL, edges
+        assert L.match_rounds(ctypes.byref(plan), ctypes.byref(ctypes.c_uint32()), None, 0) == fss.EINVAL
+    plan = _star_plan(fss, keep, [(0, 1), (0, 2)])
+    plan.q_edges = None
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL and b"q_edges" in L.fss_last_error()
+    # a predicate on query edge 2 of a two-edge query
+    plan = _star_plan(fss, keep, [(0, 1), (0, 2)])
+    keep[-1][3].target = 5
+    assert L.match_workspace_bytes(ctypes.byref(plan)) == 0
+    assert L.match_query(ctypes.byref(plan), 3, None) == fss.EINVAL and b"targets" in L.fss_last_error()
+    # one vertex with an edge
+    one = fss.match_plan()
+    one.n_qv, one.n_vertices, one.n_qe = 1, 10, 1
+    one.q_edges = ctypes.cast((ctypes.c_uint32 * 2)(0, 0), ctypes.POINTER(ctypes.c_uint32))
+    one.d_out[0], one.d_out[1] = 256, 512
+    assert L.match_workspace_bytes(ctypes.byref(one)) == 0

@@ -153,7 +153,8 @@ def _setup_query(fss, graph, q, shares, masks, seed):
         preds.append((p.target, kb, xhat))
     src = T(graph.src) if graph.n_edges else None
     dst = T(graph.dst) if graph.n_edges else None
-    plan = fss.Plan(seed, q.query_id, q.n_qv, graph.n_vertices, graph.n_edges, preds, src, dst).allocate()
+    plan = fss.Plan(seed, q.query_id, q.n_qv, graph.n_vertices, graph.n_edges, preds, src, dst,
+                    q.edges).allocate()
     return plan, kg
 
 

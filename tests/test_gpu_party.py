@@ -40,7 +40,7 @@ def _inputs(fss, g, q, shares, masks, seed):
 def _plan(fss, g, q, preds, seed):
     src = T(g.src) if g.n_edges else None
     dst = T(g.dst) if g.n_edges else None
-    return fss.Plan(seed, q.query_id, q.n_qv, g.n_vertices, g.n_edges, preds, src, dst).allocate()
+    return fss.Plan(seed, q.query_id, q.n_qv, g.n_vertices, g.n_edges, preds, src, dst, q.edges).allocate()
 
 
 def _run_parties(fss, plans):

@@ -1,0 +1,107 @@
+"""Query graphs beyond paths (Def. 2) on the HIP path: stars, a triangle, a
+diamond, a two-cycle and the Sec. II-A example (Fig. 1).  The result shares of
+every query edge equal the oracle's bit for bit -- both simulated parties at
+once, one party at a time in rounds, and many plans in one batched call -- and
+the client's join of the reconstructed bits equals brute-force enumeration."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from fixtures import fig1_example
+from gpu_util import DEV, column_shares, plan_outputs, run_query_gpu
+from oracle import fss as ofss
+from oracle import match as omatch
+from test_gpu_batch import _setup_query
+from test_gpu_party import _check as _check_parties
+from test_oracle_match import SHAPES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_03526_amd import fss as lib
+    torch.cuda.set_device(0)
+    return lib
+
+
+def _compare(got, want, what):
+    assert len(got) == len(want)
+    for j, (gw, ww) in enumerate(zip(got, want)):
+        for b in range(2):
+            np.testing.assert_array_equal(gw[b], ww[b], err_msg=f"{what}: query edge {j} party {b}")
+
+
+@pytest.mark.parametrize("qi", range(len(SHAPES)))
+def test_shapes_tiny(fss, qi):
+    q = SHAPES[qi]
+    g = synth.tiny_graph(qi + 50, n_vertices=9 if q.n_qv == 4 else 10, n_edges=40)
+    seed = 800 + qi
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    print(f"shape {qi} edges {q.qedges}", flush=True)
+    got = plan_outputs(run_query_gpu(fss, g, q, shares, masks, seed), q, g)
+    _compare(got, omatch.run_plan(32, seed, g, q, shares, masks), f"shape {qi}")
+    assert omatch.results_from_bits(g, q, omatch.reconstruct(got, g.n_edges)) == omatch.brute_force(g, q)
+
+
+@pytest.mark.parametrize("qi", [0, 2, 3])
+def test_shapes_several_tiles(fss, qi):
+    """Edge tables of several tail tiles and a ragged tail: every word equals
+    the oracle's."""
+    q = SHAPES[qi]
+    g = synth.tiny_graph(qi + 60, n_vertices=2000, n_edges=3 * 32768 + 77, label_range=3, attr_range=16)
+    seed = 900 + qi
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    print(f"shape {qi} over {g.n_edges} edges", flush=True)
+    got = plan_outputs(run_query_gpu(fss, g, q, shares, masks, seed), q, g)
+    _compare(got, omatch.run_plan(32, seed, g, q, shares, masks), f"shape {qi}")
+
+
+def test_fig1_example(fss):
+    """Sec. II-A, Fig. 1: the two subgraphs the paper prints, through the HIP
+    path, at 32 bits."""
+    g, q, expected, names = fig1_example()
+    seed = 2209
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    got = plan_outputs(run_query_gpu(fss, g, q, shares, masks, seed), q, g)
+    _compare(got, omatch.run_plan(32, seed, g, q, shares, masks), "fig1")
+    assert omatch.results_from_bits(g, q, omatch.reconstruct(got, g.n_edges)) == expected
+
+
+@pytest.mark.parametrize("qi", range(len(SHAPES)))
+def test_shapes_single_party_rounds(fss, qi):
+    q = SHAPES[qi]
+    g = synth.tiny_graph(qi + 70, n_vertices=9 if q.n_qv == 4 else 10, n_edges=40)
+    print(f"shape {qi} single party", flush=True)
+    _check_parties(fss, g, q, 1000 + qi)
+
+
+def test_shapes_batch(fss):
+    """Paths and query graphs mixed in one keygen batch and one
+    match_query_batch: each plan's shares equal the oracle's."""
+    g = synth.tiny_graph(80, n_vertices=300, n_edges=5000, label_range=3, attr_range=16)
+    fig_g, fig_q, expected, _ = fig1_example()
+    seed = 4321
+    cases = [(g, q) for q in SHAPES] + [(g, synth.Query(40, 3, SHAPES[0].preds))] + [(fig_g, fig_q)]
+    plans, kgs, want = [], [], []
+    for gi, q in cases:
+        shares = column_shares(gi, seed)
+        masks = synth.pred_masks(seed, q, gi)
+        plan, kg = _setup_query(fss, gi, q, shares, masks, seed)
+        plans.append(plan)
+        kgs.extend(kg)
+        want.append(omatch.run_plan(32, seed, gi, q, shares, masks))
+    print(f"{len(plans)} plans, {len(kgs)} keygen requests", flush=True)
+    fss.fss_keygen_batch(kgs, fss.Queue(len(kgs)))
+    fss.match_query_batch(plans, fss.Queue(sum(2 * p.c.n_pred for p in plans) + 64))
+    torch.cuda.synchronize()
+    for i, ((gi, q), plan) in enumerate(zip(cases, plans)):
+        _compare(plan_outputs(plan, q, gi), want[i], f"plan {i}")
+    got = plan_outputs(plans[-1], fig_q, fig_g)
+    assert omatch.results_from_bits(fig_g, fig_q, omatch.reconstruct(got, fig_g.n_edges)) == expected

@@ -78,7 +78,7 @@ def fake(monkeypatch):
 
 
 def _reqs(arrivals, rows=1000):
-    return [serving.Request(i, float(t), types.SimpleNamespace(query_id=100 + i, n_qv=1, preds=[None, None]),
+    return [serving.Request(i, float(t), types.SimpleNamespace(query_id=100 + i, n_qv=1, n_qe=0, edges=None, preds=[None, None]),
                             rows, 7) for i, t in enumerate(arrivals)]
 
 
