@@ -5,7 +5,7 @@
 //   k_place_ids,
 //   k_split_records        one-hot posting records in CSR order, split into
 //                          binary RSS with the ChaCha12 PRF     (HBM stream)
-//   k_csr_select           P_m[l] = XOR_c id_m[c] AND id_{c,l}  (HBM stream, XOR atomics)
+//   k_csr_select           P_m[l] = XOR_c id_m[c] AND id_{c,l}  (HBM stream, 16-byte loads, XOR atomics)
 //   k_attr_select          d = XOR_x id[x] AND d_x per kept ID  (HBM stream, XOR atomics)
 // rss_sec_access chains the selection, the RSS re-share, the shuffle with the
 // parity open and compaction (shuffle.hip) and the attribute selection.
@@ -118,34 +118,132 @@ struct Out3 {
 
 // Slot l = blockIdx.y of the fetched list: XOR over this block's candidates c
 // with l < len_c of id_m[c] AND record (off_c + l), into out[.][l * wx + w].
+// First the block lists in LDS the candidates whose (public, padded) list
+// reaches slot l, with their three mask bits; then its threads stream those
+// records, V words (16 bytes for V = 4) per load and two records per step, so
+// that each lane keeps six loads in flight.  At most kSelCand candidates per
+// block (the host sizes the grid for it).
+constexpr uint32_t kSelCand = 512;
+
+template <int V>
+struct SelVec;
+template <>
+struct SelVec<1> {
+    using T = uint32_t;
+    static __device__ __forceinline__ T zero() { return 0u; }
+    static __device__ __forceinline__ void prod(const uint32_t m[3], const T r[3], T acc[3]) { rss_product(m, r, acc); }
+    static __device__ __forceinline__ uint32_t word(const T& v, int) { return v; }
+};
+template <>
+struct SelVec<4> {
+    using T = uint4;
+    static __device__ __forceinline__ T zero() { return make_uint4(0u, 0u, 0u, 0u); }
+    static __device__ __forceinline__ void prod(const uint32_t m[3], const T r[3], T acc[3]) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int j = (i + 1) % 3;
+            acc[i].x ^= (r[i].x & m[i]) ^ (r[j].x & m[i]) ^ (r[i].x & m[j]);
+            acc[i].y ^= (r[i].y & m[i]) ^ (r[j].y & m[i]) ^ (r[i].y & m[j]);
+            acc[i].z ^= (r[i].z & m[i]) ^ (r[j].z & m[i]) ^ (r[i].z & m[j]);
+            acc[i].w ^= (r[i].w & m[i]) ^ (r[j].w & m[i]) ^ (r[i].w & m[j]);
+        }
+    }
+    static __device__ __forceinline__ uint32_t word(const T& v, int q) {
+        return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+    }
+};
+
+template <int V>
 __global__ __launch_bounds__(kSelBlock) void k_csr_select(uint64_t ncand, uint32_t wx, Shares3 idm,
                                                           const uint32_t* __restrict__ off, Shares3 post, Out3 out) {
-    __shared__ uint32_t part[3][kSelBlock];
+    using S = SelVec<V>;
+    using T = typename S::T;
+    __shared__ uint32_t rec[kSelCand];
+    __shared__ uint32_t msk[kSelCand];
+    __shared__ uint32_t nsel;
+    __shared__ T part[3][kSelBlock];
     const uint32_t l = blockIdx.y;
     const uint64_t per = (ncand + gridDim.x - 1) / gridDim.x;
     const uint64_t c0 = (uint64_t)blockIdx.x * per;
     const uint64_t c1 = c0 + per < ncand ? c0 + per : ncand;
     const uint32_t t = threadIdx.x;
-    for (uint32_t w0 = 0; w0 < wx; w0 += kSelBlock) {
-        const uint32_t tw = wx - w0 < kSelBlock ? wx - w0 : kSelBlock;
+    if (t == 0) nsel = 0;
+    __syncthreads();
+    for (uint64_t c = c0 + t; c < c1; c += kSelBlock) {
+        const uint32_t o = off[c];
+        if (l >= off[c + 1] - o) continue;              // the list ends before slot l
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++) m |= ((idm.p[i][c >> 5] >> (c & 31)) & 1u) << i;
+        const uint32_t k = atomicAdd(&nsel, 1u);         // order-free: the products are XORed
+        if (k < kSelCand) {
+            rec[k] = o + l;
+            msk[k] = m;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = nsel < kSelCand ? nsel : kSelCand;
+    const uint32_t nv = wx / V;                          // loads per record
+    const T* src[3] = {(const T*)post.p[0], (const T*)post.p[1], (const T*)post.p[2]};
+    for (uint32_t v0 = 0; v0 < nv; v0 += kSelBlock) {
+        const uint32_t tw = nv - v0 < kSelBlock ? nv - v0 : kSelBlock;
         const uint32_t lanes = kSelBlock / tw;
         const uint32_t w = t % tw, g = t / tw;
-        uint32_t acc[3] = {0, 0, 0};
+        T acc[3] = {S::zero(), S::zero(), S::zero()};
         if (g < lanes) {
-            for (uint64_t c = c0 + g; c < c1; c += lanes) {
-                const uint32_t o = off[c];
-                if (l >= off[c + 1] - o) continue;              // the list ends before slot l
-                const uint64_t at = (uint64_t)(o + l) * wx + w0 + w;
-                uint32_t m[3], r[3];
+            uint32_t k = g;
+            for (; k + lanes < n; k += 2 * lanes) {
+                const uint64_t a = (uint64_t)rec[k] * nv + v0 + w, b = (uint64_t)rec[k + lanes] * nv + v0 + w;
+                T ra[3], rb[3];
 #pragma unroll
                 for (int i = 0; i < 3; i++) {
-                    m[i] = 0u - ((idm.p[i][c >> 5] >> (c & 31)) & 1u);
-                    r[i] = post.p[i][at];
+                    ra[i] = src[i][a];
+                    rb[i] = src[i][b];
                 }
-                rss_product(m, r, acc);
+                uint32_t ma[3], mb[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    ma[i] = 0u - ((msk[k] >> i) & 1u);
+                    mb[i] = 0u - ((msk[k + lanes] >> i) & 1u);
+                }
+                S::prod(ma, ra, acc);
+                S::prod(mb, rb, acc);
+            }
+            if (k < n) {
+                const uint64_t a = (uint64_t)rec[k] * nv + v0 + w;
+                T ra[3];
+                uint32_t ma[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    ra[i] = src[i][a];
+                    ma[i] = 0u - ((msk[k] >> i) & 1u);
+                }
+                S::prod(ma, ra, acc);
             }
         }
-        reduce_out(part, acc, tw, lanes, out.p, (uint64_t)l * wx + w0);
+#pragma unroll
+        for (int i = 0; i < 3; i++) part[i][t] = acc[i];
+        __syncthreads();
+        if (t < tw) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                T v = S::zero();
+                for (uint32_t k = 0; k < lanes; k++) {
+                    const T p = part[i][k * tw + t];
+                    if constexpr (V == 4) {
+                        v.x ^= p.x; v.y ^= p.y; v.z ^= p.z; v.w ^= p.w;
+                    } else {
+                        v ^= p;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < V; q++) {
+                    const uint32_t x = S::word(v, q);
+                    if (x) atomicXor(&out.p[i][(uint64_t)l * wx + (uint64_t)(v0 + t) * V + q], x);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -301,10 +399,19 @@ int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[
     for (int i = 0; i < 3; i++)
         hipLaunchKernelGGL(k_fill, dim3(blocks_for(tw, 256, 4096)), dim3(256), 0, s, tw, 0u, add[i]);
     if (ncand) {
-        const uint64_t chunks = std::max<uint64_t>(1, std::min<uint64_t>((ncand + 63) / 64, 4096 / lmax + 1));
-        hipLaunchKernelGGL(k_csr_select, dim3((unsigned)chunks, lmax), dim3(kSelBlock), 0, s, ncand, wx,
-                           Shares3{{d_idm[0], d_idm[1], d_idm[2]}}, d_off, Shares3{{d_post[0], d_post[1], d_post[2]}},
-                           Out3{{add[0], add[1], add[2]}});
+        // enough chunks to fill the chip over lmax slots, and at most kSelCand candidates per chunk
+        const uint64_t chunks = std::max<uint64_t>((ncand + kSelCand - 1) / kSelCand,
+                                                   std::min<uint64_t>((ncand + 63) / 64, 4096 / lmax + 1));
+        const Shares3 idm{{d_idm[0], d_idm[1], d_idm[2]}}, post{{d_post[0], d_post[1], d_post[2]}};
+        const Out3 o{{add[0], add[1], add[2]}};
+        bool vec = wx % 4 == 0;
+        for (int i = 0; i < 3; i++) vec = vec && ((uintptr_t)d_post[i] & 15) == 0;
+        if (vec)
+            hipLaunchKernelGGL(k_csr_select<4>, dim3((unsigned)chunks, lmax), dim3(kSelBlock), 0, s, ncand, wx, idm,
+                               d_off, post, o);
+        else
+            hipLaunchKernelGGL(k_csr_select<1>, dim3((unsigned)chunks, lmax), dim3(kSelBlock), 0, s, ncand, wx, idm,
+                               d_off, post, o);
     }
     int rc = check_launch("k_csr_select");
     if (rc) return rc;

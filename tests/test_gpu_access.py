@@ -1,4 +1,5 @@
-"""Alg. 1 encoding and Alg. 6 secAccess on the GPU over 12,000 candidates:
+"""Alg. 1 encoding and Alg. 6 secAccess on the GPU over 12,000 candidates,
+with ID records of 63 words (4-byte loads) and of 64 words (16-byte loads):
 the encoder's three RSS shares equal the oracle's share for share; for matched
 vertices with short, long and empty posting lists, the kept ID records, their
 shuffled positions, their count and the attribute records equal the oracle's
@@ -14,8 +15,7 @@ from oracle import access
 
 pytestmark = pytest.mark.gpu
 
-NC, X, KGROUP = 12000, 2000, 4
-WX = (X + 31) // 32
+NC, KGROUP = 12000, 4
 
 
 @pytest.fixture(scope="module")
@@ -24,8 +24,10 @@ def fss():
     return f
 
 
-@pytest.fixture(scope="module")
-def enc(fss):
+@pytest.fixture(scope="module", params=[2000, 2048])
+def enc(fss, request):
+    X = request.param
+    WX = (X + 31) // 32
     types, adj, attr = synth.posting_graph(21, NC, X, 24, n_types=2)
     lengths = np.array([len(a) for a in adj], np.uint32)
     padded, _ = fss.rss_group_k(lengths, types, KGROUP)
@@ -39,10 +41,12 @@ def enc(fss):
     d_off = T(off.astype(np.uint32))
     fss.rss_enc_posting_lists(NC, X, T(adj_off), T(flat), T(slots), d_off, nrec, (1001, 1002), 4, out)
     torch.cuda.synchronize()
-    return dict(types=types, adj=adj, attr=attr, padded=padded, off=off, d_off=d_off, nrec=nrec, want=want, out=out)
+    return dict(types=types, adj=adj, attr=attr, padded=padded, off=off, d_off=d_off, nrec=nrec, want=want, out=out,
+                X=X, WX=WX)
 
 
 def test_encoding_shares_equal_oracle(fss, enc):
+    WX = enc["WX"]
     for i in range(3):
         np.testing.assert_array_equal(U(enc["out"][i]).reshape(enc["nrec"], WX), enc["want"][i],
                                       err_msg=f"share {i + 1}")
@@ -64,6 +68,7 @@ def _pack(bits):
 
 @pytest.mark.parametrize("pick", ["long", "short", "empty", "middle"])
 def test_sec_access_equals_oracle(fss, enc, pick):
+    X, WX = enc["X"], enc["WX"]
     lens = np.array([len(a) for a in enc["adj"]])
     m = {"long": int(np.argmax(lens)), "short": int(np.flatnonzero(lens == 1)[0]),
          "empty": int(np.flatnonzero(lens == 0)[0]), "middle": int(np.flatnonzero(lens == 5)[0])}[pick]
