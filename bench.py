@@ -546,8 +546,10 @@ def run_batch64(args, torch, fss, dev):
     runner = ChunkedRunner(int(budget_gb * 1e9), chunk_rows=1 << args.chunk_log_rows, device=dev)
     # autotune the persistent evaluation shape on one representative wave
     probe = [j for j in jobs if any(p["rows"] >= 1 << 20 for p in j.preds)][:1] or jobs[:1]
-    autotune.tune(lambda: runner.run(probe), sum(p["rows"] for j in probe for p in j.preds))
-    log(f"tuning chosen: {autotune.chosen()}")
+    probe_rows = sum(p["rows"] for j in probe for p in j.preds)
+    autotune.tune(lambda: runner.run(probe), probe_rows)
+    autotune.tune_keygen(lambda: runner.run(probe), probe_rows)
+    log(f"tuning chosen: {autotune.chosen()}, keygen tile x{autotune.chosen_keygen()}")
 
     times = {}
     for name in ("plain", "batched"):
@@ -598,6 +600,7 @@ def run_batch64(args, torch, fss, dev):
         "walks": walks, "batched_evals_per_s_incl_keygen": walks / times["batched"],
         "waves": waves_per_pass, "budget_gb": budget_gb, "chunk_rows": 1 << args.chunk_log_rows,
         "tuning": {str(k): v for k, v in autotune.chosen().items()},
+        "keygen_tile_mult": {str(k): v for k, v in autotune.chosen_keygen().items()},
         "bit_exact_batched_vs_plain": bool(exact), "graph_replay": graph_replay, "dtype": "u32", "data": "synthetic",
         "persistent_kernels": persistent,
         "config": {"workload": "batch64: Chung-Lu 2^22 vertices / 2^25 edges, 64 queries"},

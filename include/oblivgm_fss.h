@@ -487,9 +487,14 @@ int rss_fetch_many(uint64_t ncand, uint32_t nwords, const uint32_t* const d_tabl
 
 /* Tile / occupancy shape of the persistent launches (process-wide):
  * rows_per_thread 1..8 (evaluation tile = 1024 * rows_per_thread rows),
- * wg_per_cu 1..2.  Chosen by the package's autotuner; never changes results. */
+ * wg_per_cu 1..2 (both the evaluation and the keygen queue), and the keygen
+ * tile, 512 * tile_mult rows (tile_mult 1..8).  Chosen by the package's
+ * autotuner; never changes results.  Not for use while another thread
+ * enqueues batch calls. */
 int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu);
 int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu);
+int fss_set_keygen_tuning(uint32_t tile_mult);
+int fss_get_keygen_tuning(uint32_t* tile_mult);
 
 /*
  * The paper's graph encoding with k-groups (Alg. 1) and secure neighbouring-

@@ -448,9 +448,10 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* counter, uint32_t* s_til
 
 // One key kind per launch (the host splits a batch by kind), so each kernel
 // holds one Gen's registers.
+// A tile is tile_mult groups of kBlock / 2 rows (a lane pair per row).
 template <int KIND>
 __device__ __forceinline__ void keygen_queue(const QKeygen* __restrict__ q, uint32_t count, uint32_t total_tiles,
-                                             uint32_t* counter) {
+                                             uint32_t tile_mult, uint32_t* counter) {
     __shared__ uint32_t tab[kLdsTableWords];
     __shared__ uint32_t s_tile;
     lds_table_fill(tab, g_tables.t0);
@@ -460,19 +461,24 @@ __device__ __forceinline__ void keygen_queue(const QKeygen* __restrict__ q, uint
         if (tile >= total_tiles) break;
         const uint32_t di = find_desc(count, tile, [&](uint32_t i) { return q[i].tile_start; });
         const DealerArgs& A = q[di].a;
-        const uint64_t row = (uint64_t)(tile - q[di].tile_start) * (kBlock / 2) + (threadIdx.x >> 1);
-        if (row < A.n) keygen_row<KIND>(A, row, threadIdx.x & 1u, tab, loff);
+        const uint64_t row0 = (uint64_t)(tile - q[di].tile_start) * tile_mult * (kBlock / 2) + (threadIdx.x >> 1);
+        for (uint32_t k = 0; k < tile_mult; k++) {
+            const uint64_t row = row0 + (uint64_t)k * (kBlock / 2);
+            if (row < A.n) keygen_row<KIND>(A, row, threadIdx.x & 1u, tab, loff);
+        }
     }
 }
 
 __global__ __launch_bounds__(kBlock, 8) void k_keygen_queue_eq(const QKeygen* __restrict__ q, uint32_t count,
-                                                           uint32_t total_tiles, uint32_t* counter) {
-    keygen_queue<FSS_EQ>(q, count, total_tiles, counter);
+                                                           uint32_t total_tiles, uint32_t tile_mult,
+                                                           uint32_t* counter) {
+    keygen_queue<FSS_EQ>(q, count, total_tiles, tile_mult, counter);
 }
 
 __global__ __launch_bounds__(kBlock, 8) void k_keygen_queue_range(const QKeygen* __restrict__ q, uint32_t count,
-                                                              uint32_t total_tiles, uint32_t* counter) {
-    keygen_queue<FSS_RANGE>(q, count, total_tiles, counter);
+                                                              uint32_t total_tiles, uint32_t tile_mult,
+                                                              uint32_t* counter) {
+    keygen_queue<FSS_RANGE>(q, count, total_tiles, tile_mult, counter);
 }
 
 __global__ __launch_bounds__(kBlock, 8) void k_eval_queue(const QEval* __restrict__ q, uint32_t count,
@@ -1753,6 +1759,7 @@ int launch_tail_inline(const std::vector<TailOp>& ops, const RoundKeys& rk, hipS
 struct Tuning {
     uint32_t rows_per_thread = 1;   // eval tile = 1024 * rows_per_thread rows
     uint32_t wg_per_cu = 2;         // persistent grid = wg_per_cu * CUs
+    uint32_t keygen_tile_mult = 1;  // keygen tile = 512 * keygen_tile_mult rows
 };
 Tuning g_tuning;
 
@@ -2208,6 +2215,18 @@ int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu) {
     return FSS_OK;
 }
 
+int fss_set_keygen_tuning(uint32_t tile_mult) {
+    ogm::last_error().clear();
+    if (tile_mult < 1 || tile_mult > 8) return fail(FSS_EINVAL, "fss_set_keygen_tuning: tile_mult 1..8");
+    g_tuning.keygen_tile_mult = tile_mult;
+    return FSS_OK;
+}
+
+int fss_get_keygen_tuning(uint32_t* tile_mult) {
+    if (tile_mult) *tile_mult = g_tuning.keygen_tile_mult;
+    return FSS_OK;
+}
+
 int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, uint64_t queue_bytes_avail,
                      void* stream) {
     ogm::last_error().clear();
@@ -2255,11 +2274,13 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
     const size_t n_range = (size_t)(std::find_if(q.begin(), q.end(),
                                                  [](const QKeygen& e) { return e.a.kind != FSS_RANGE; }) -
                                     q.begin());
+    const uint32_t mult = g_tuning.keygen_tile_mult;
+    const uint64_t tile_rows = (uint64_t)mult * (kBlock / 2);
     uint64_t tiles[2] = {0, 0};
     for (size_t i = 0; i < q.size(); i++) {
         uint64_t& t = tiles[i < n_range ? 0 : 1];
         q[i].tile_start = (uint32_t)t;
-        t += (q[i].a.n + kBlock / 2 - 1) / (kBlock / 2);
+        t += (q[i].a.n + tile_rows - 1) / tile_rows;
     }
     if (tiles[0] > 0xFFFFFFF0ull || tiles[1] > 0xFFFFFFF0ull)
         return fail(FSS_EUNSUPPORTED, "fss_keygen_batch: too many tiles");
@@ -2277,14 +2298,14 @@ int fss_keygen_batch(const fss_keygen_req* reqs, uint32_t count, void* d_queue, 
     if (tiles[0]) {
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
         hipLaunchKernelGGL(k_keygen_queue_range, dim3((unsigned)std::min(tiles[0], slots)), dim3(kBlock), 0, s,
-                           dq, (uint32_t)n_range, (uint32_t)tiles[0], counter);
+                           dq, (uint32_t)n_range, (uint32_t)tiles[0], mult, counter);
         rc = check_launch("k_keygen_queue_range");
         if (rc) return rc;
     }
     if (tiles[1]) {
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
         hipLaunchKernelGGL(k_keygen_queue_eq, dim3((unsigned)std::min(tiles[1], slots)), dim3(kBlock), 0, s,
-                           dq + n_range, (uint32_t)(q.size() - n_range), (uint32_t)tiles[1], counter);
+                           dq + n_range, (uint32_t)(q.size() - n_range), (uint32_t)tiles[1], mult, counter);
         rc = check_launch("k_keygen_queue_eq");
     }
     return rc;

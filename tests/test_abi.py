@@ -310,3 +310,11 @@ def test_query_edges_schedule_and_errors(fss):
     one.q_edges = ctypes.cast((ctypes.c_uint32 * 2)(0, 0), ctypes.POINTER(ctypes.c_uint32))
     one.d_out[0], one.d_out[1] = 256, 512
     assert L.match_workspace_bytes(ctypes.byref(one)) == 0
+
+
+def test_tuning_limits(fss):
+    L = fss.LIB
+    assert L.fss_set_keygen_tuning(0) == fss.EINVAL and L.fss_set_keygen_tuning(9) == fss.EINVAL
+    assert L.fss_set_keygen_tuning(4) == fss.OK and fss.get_keygen_tuning() == 4
+    assert L.fss_set_keygen_tuning(1) == fss.OK and fss.get_keygen_tuning() == 1
+    assert L.fss_set_tuning(0, 1) == fss.EINVAL and L.fss_set_tuning(1, 3) == fss.EINVAL

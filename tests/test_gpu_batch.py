@@ -24,6 +24,7 @@ def fss():
     torch.cuda.set_device(0)
     yield lib
     lib.set_tuning(1, 2)
+    lib.set_keygen_tuning(1)
 
 
 def _rand_u32(seed, n):
@@ -49,7 +50,11 @@ def _requests(fss):
     return out
 
 
-def test_keygen_batch_equals_single(fss):
+@pytest.mark.parametrize("tile_mult", [1, 3, 8])
+@pytest.mark.parametrize("wg_per_cu", [1, 2])
+def test_keygen_batch_equals_single(fss, tile_mult, wg_per_cu):
+    """Keygen batches equal the per-request calls at every keygen tile size
+    (512 to 4096 rows, requests of 1 to 70,000 rows) and grid size."""
     reqs = _requests(fss)
     single, batch = [], []
     for rq in reqs:
@@ -58,9 +63,13 @@ def test_keygen_batch_equals_single(fss):
         single.append(kb)
         batch.append(fss.KeyBatch(rq["kind"], rq["nbits"], rq["n"]))
     queue = fss.Queue(len(reqs))
+    fss.set_keygen_tuning(tile_mult)
+    fss.set_tuning(1, wg_per_cu)
     fss.fss_keygen_batch([(rq["seed"], rq["q"], rq["p"], rq["a"], rq["hi"], rq["r"], kb)
                           for rq, kb in zip(reqs, batch)], queue)
     torch.cuda.synchronize()
+    fss.set_keygen_tuning(1)
+    fss.set_tuning(1, 2)
     # compare the rows' keys (pad rows up to the next multiple of 64 are never written)
     from keylayout import from_device
     for rq, kb1, kb2 in zip(reqs, single, batch):
