@@ -3,7 +3,8 @@ times (dealer keygen per predicate, open, one match_query):
 
 * vertex filtering, 2^22 rows x 4 attributes, 2 equality + 2 range predicates;
 * full path query, Chung-Lu graph of 2^22 vertices and 2^25 edges,
-  4 vertex + 2 edge predicates.
+  4 vertex + 2 edge predicates;
+* a star-shaped query graph (one vertex with two out-edges) over the same graph.
 
 Checked: (1) the reconstruction of every output row equals the plaintext
 predicate / join evaluated on the plaintext columns (a property that holds at
@@ -92,6 +93,37 @@ def test_full_path_query_2p22_2p25(fss):
         for b, s in ((0, s0), (1, s1)):
             np.testing.assert_array_equal(ofss.unpack_bits(s, g.n_edges)[rows], want[j, b])
     assert total > 0
+
+
+def test_star_query_2p22_2p25(fss):
+    """A query graph that is not a path (Def. 2): vertex a with out-edges to b
+    and to c, over the same 2^22 / 2^25 graph, in one match_query.  Every
+    output row reconstructs to m_a[src] & m_b[dst] & q_j (m_a[src] & m_c[dst]
+    & q_j for the second edge), and sampled rows equal the oracle's shares."""
+    seed = 889
+    g, path = synth.config3(3)
+    P = synth.Pred
+    pa, pb, pc = path.preds[0], path.preds[1], path.preds[2]
+    q = synth.Query(query_id=33, n_qv=3, edges=[(0, 1), (0, 2)], preds=[
+        P(0, "range", "z0", lo=pb.lo, hi=pb.hi), P(1, "eq", "l0", a=pa.a), P(2, "eq", "l1", a=pc.a),
+        P(3, "eq", "label", a=path.preds[4].a), P(4, "range", "weight", lo=path.preds[5].lo, hi=path.preds[5].hi)])
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    plan = run_query_gpu(fss, g, q, shares, masks, seed)
+    outs = plan_outputs(plan, q, g)
+    del plan
+    torch.cuda.empty_cache()
+    assert len(outs) == 2
+    m = [_plain_vertex(g, q, i) for i in range(q.n_qv)]
+    rows = _sample_rows(g.n_edges, 3)
+    want = omatch.sampled_outputs(32, seed, g, q, shares, masks, rows)
+    for j, ((a, b), (s0, s1)) in enumerate(zip(q.qedges, outs)):
+        recon = ofss.unpack_bits(s0 ^ s1, g.n_edges).astype(bool)
+        truth = m[a][g.src] & m[b][g.dst] & _plain_edge(g, q, j)
+        np.testing.assert_array_equal(recon, truth, err_msg=f"query edge {j}")
+        assert truth.sum() > 0
+        for p, s in ((0, s0), (1, s1)):
+            np.testing.assert_array_equal(ofss.unpack_bits(s, g.n_edges)[rows], want[j, p])
 
 
 def test_batch64_full_mix(fss):
