@@ -1,0 +1,207 @@
+"""Oracle for the paper's whole secure matching protocol, Alg. 2 (secMatch),
+over the paper's own encoding, for path queries V_1 -> V_2 -> ... -> V_q.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/fss.py``).
+
+Alg. 2 composed from the rows the oracle already pins:
+- secEval (Alg. 3, Eq. predEval; ``rss.server_shares`` with the replicated
+  token ``rss.token``), then the re-share of its three-out-of-three bits into
+  RSS (``rss.reshare``);
+- secFetch Case II (Alg. 4): the table {x || id || d} shuffled (Alg. 5), the
+  shuffled x opened, the rows with 1 kept (``shuffle.fetch_case2``);
+- secAccess (Alg. 6) over the posting lists of Alg. 1 (``access.sec_access_csr``):
+  the matched vertex's neighbours of the next target's type, with their
+  one-hot IDs and the one-hot value of the attribute the next predicate reads.
+
+Readings (Alg. 2 leaves these open):
+1. Hop i's candidates come in groups.  Hop 1 is one group, every vertex of
+   type T_1.  Every vertex kept at hop i < q gives one group at hop i + 1:
+   the neighbours secAccess returns for it.  secEval runs per group, and
+   secFetch once per group, so a kept vertex stays tied to the kept vertex
+   whose neighbour it is (its parent) -- the reorganisation into subgraphs at
+   the end of Alg. 2 needs that tie.
+2. Randomness: the re-shares take PRF counters in order from ``counter0``
+   (secEval's re-share one, secAccess two); the shuffles take seed triples in
+   order from ``seed0``, the s-th shuffle (secFetch's and secAccess's alike)
+   the triple (seed0 + 3s, seed0 + 3s + 1, seed0 + 3s + 2).  Predicate i's
+   token is made with pred = i.
+3. Order: hop by hop; within a hop, group by group in order of creation, each
+   group's secEval, re-share and secFetch; then, for each kept vertex in kept
+   order, its secAccess.  An empty group takes no randomness.
+4. The result is every chain of kept vertices, one per hop, each the parent of
+   the next, as the three shares of each hop's one-hot ID record.  The client
+   reconstructs the IDs and drops chains that visit a vertex twice (Def. 2
+   asks for a bijection).
+
+The encoded graph (``synth.typed_shares``: one-hot IDs and attribute values
+in binary RSS) and the posting lists' placement of true IDs
+(``synth.posting_slots``) are inputs; the posting lists are encoded here with
+Alg. 1's k-groups (``access.group_k``, ``access.encode_posting_lists_k``,
+``access.rss_split_prf``).
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import synth
+
+from . import access, fss, rss, shuffle
+
+
+@dataclass
+class Encoded:
+    """The servers' view of a typed graph: shares[("id", T)] and
+    shares[("attr", T, name)] (3, n_T, words) record-major; per type pair
+    (T, T2) the posting lists' three shares (CSR records of ceil(n_T2/32)
+    words) and their offsets."""
+    shares: dict
+    post: dict = field(default_factory=dict)
+    off: dict = field(default_factory=dict)
+
+
+def encode(tg, shares: dict, k: int, slot_seed: int, split_keys=(1001, 1002), counter: int = 4) -> Encoded:
+    """Alg. 1 for every edge type of the typed graph (in sorted order, the
+    e-th with slot seed slot_seed + e): each type's vertices grouped k at a
+    time, posting lists padded per group, true IDs at the seeded slots, split
+    into binary RSS with the PRF."""
+    enc = Encoded(dict(shares))
+    for e, ((t, t2), lists) in enumerate(sorted(tg.adj.items())):
+        lengths = np.array([len(a) for a in lists], np.uint32)
+        padded, _ = access.group_k(lengths, np.zeros(lengths.size, np.uint32), k)
+        slots = synth.posting_slots(slot_seed + e, lengths, padded)
+        rec, off = access.encode_posting_lists_k(lists, tg.n[t2], padded, slots)
+        enc.post[(t, t2)] = access.rss_split_prf(rec, split_keys[0], split_keys[1], counter)
+        enc.off[(t, t2)] = off
+    return enc
+
+
+@dataclass
+class _Group:
+    parent: object        # (hop, group, kept row) of the parent, None at hop 0
+    ids: list             # three (n, wi) share tables of one-hot ID records
+    vals: list            # three (n, wv) share tables of one-hot attribute records
+    kept_ids: list = None # after secFetch: three (k, wi) tables
+
+
+def _unpack(records: np.ndarray, nbits: int) -> np.ndarray:
+    """(R, W) uint32 -> (R, nbits) 0/1."""
+    return np.unpackbits(records.astype("<u4").view(np.uint8).reshape(records.shape[0], -1), axis=1,
+                         bitorder="little")[:, :nbits]
+
+
+def sec_match(tg, enc: Encoded, query, tok_seed: int, prf_keys, counter0: int, seed0: int):
+    """Alg. 2 for a path query (readings in the module doc).  Returns
+    (chains, groups): chains is a list over results of per-hop lists of three
+    (wi,) share records; groups the per-hop groups (for tests)."""
+    counter, step = counter0, 0
+    tg_n = tg.n
+    t1 = query.targets[0]
+    hops = [[_Group(None, [enc.shares[("id", t1.vtype)][j] for j in range(3)],
+                    [enc.shares[("attr", t1.vtype, t1.attr)][j] for j in range(3)])]]
+    for i, tgt in enumerate(query.targets):
+        npos = tg.attrs[tgt.vtype][tgt.attr][1]
+        keys, nb = rss.token(tgt.kind, npos, tok_seed, query.query_id, i, a=tgt.a, lo=tgt.lo, hi=tgt.hi)
+        nxt = []
+        for gi, g in enumerate(hops[i]):
+            n = g.ids[0].shape[0]
+            if n == 0:
+                g.kept_ids = [np.zeros((0, g.ids[0].shape[1]), np.uint32) for _ in range(3)]
+                continue
+            # secEval: each server's additive share, re-shared into RSS
+            bits = np.stack([_unpack(g.vals[j], npos) for j in range(3)])
+            x3 = rss.server_shares(tgt.kind, npos, keys, nb, bits)
+            z = rss.reshare([fss.pack_bits(x3[j]) for j in range(3)], prf_keys, counter, n)
+            counter += 1
+            zb = [fss.unpack_bits(z[j], n) for j in range(3)]
+            # secFetch Case II on {x || id || d}
+            wi = g.ids[0].shape[1]
+            rows = [np.concatenate([g.ids[j], g.vals[j]], axis=1) for j in range(3)]
+            _, kept = shuffle.fetch_case2(zb, rows, seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+            step += 1
+            g.kept_ids = [kept[j][:, :wi] for j in range(3)]
+            if i + 1 == len(query.targets):
+                continue
+            nt = query.targets[i + 1]
+            pair = (tgt.vtype, nt.vtype)
+            attr_sh = [enc.shares[("attr", nt.vtype, nt.attr)][j] for j in range(3)]
+            for r in range(g.kept_ids[0].shape[0]):
+                idm = [_unpack(g.kept_ids[j][r:r + 1], tg_n[tgt.vtype])[0] for j in range(3)]
+                seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+                ids_ne, vals_ne = access.sec_access_csr(idm, enc.post[pair], enc.off[pair], attr_sh, tg_n[nt.vtype],
+                                                        prf_keys, seeds, counter)
+                counter += 2
+                step += 1
+                nxt.append(_Group((i, gi, r), list(ids_ne), list(vals_ne)))
+        if i + 1 < len(query.targets):
+            hops.append(nxt)
+    return _chains(hops), hops
+
+
+def _chains(hops):
+    """Every chain of kept vertices, one per hop, each the parent of the next."""
+    out = []
+
+    def walk(i, gi, prefix):
+        g = hops[i][gi]
+        for r in range(g.kept_ids[0].shape[0]):
+            rec = [g.kept_ids[j][r] for j in range(3)]
+            if i + 1 == len(hops):
+                out.append(prefix + [rec])
+                continue
+            for gj, h in enumerate(hops[i + 1]):
+                if h.parent == (i, gi, r):
+                    walk(i + 1, gj, prefix + [rec])
+
+    walk(0, 0, [])
+    return out
+
+
+def reconstruct(tg, query, chains) -> set:
+    """Client side: the vertex ID of every hop of every chain (the one set bit
+    of the XOR of the three shares), chains visiting a vertex twice dropped."""
+    out = set()
+    for ch in chains:
+        ids = []
+        for tgt, rec in zip(query.targets, ch):
+            bits = _unpack((rec[0] ^ rec[1] ^ rec[2])[None, :], tg.n[tgt.vtype])[0]
+            pos = np.flatnonzero(bits)
+            assert pos.size == 1, "a kept record is not one-hot"
+            ids.append(int(pos[0]))
+        verts = [(t.vtype, v) for t, v in zip(query.targets, ids)]
+        if len(set(verts)) == len(verts):
+            out.add(tuple(ids))
+    return out
+
+
+def brute_force(tg, query) -> set:
+    """Plaintext matching (Def. 2) of a path query over the typed graph: every
+    chain v_1, ..., v_q with v_i of type T_i, its predicate holding on v_i's
+    attribute, v_{i+1} a neighbour of v_i, and no vertex visited twice."""
+    t = query.targets
+    ok = [[v for v in range(tg.n[x.vtype]) if x.holds(tg.attrs[x.vtype][x.attr][0][v])] for x in t]
+    out = set()
+    for combo in itertools.product(*ok):
+        if any(combo[i + 1] not in set(tg.adj[(t[i].vtype, t[i + 1].vtype)][combo[i]].tolist())
+               for i in range(len(t) - 1)):
+            continue
+        verts = [(x.vtype, v) for x, v in zip(t, combo)]
+        if len(set(verts)) == len(verts):
+            out.add(tuple(combo))
+    return out
+
+
+def join_on_first(a: set, b: set, types_a, types_b) -> set:
+    """Client-side join of two path results that share their first query
+    vertex (a tree query split into root-to-leaf paths, as Fig. 1's): every
+    pair with the same root and no other vertex in common (vertices compared
+    by type and ID), as the root, then a's other vertices, then b's."""
+    out = set()
+    for x in a:
+        va = {(t, v) for t, v in zip(types_a[1:], x[1:])}
+        for y in b:
+            if x[0] == y[0] and not va & {(t, v) for t, v in zip(types_b[1:], y[1:])}:
+                out.add(x + y[1:])
+    return out

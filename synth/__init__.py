@@ -12,5 +12,6 @@ from .workloads import (  # noqa: F401
     Graph, Pred, Query, er_graph, chung_lu_graph, zipf_column, vertex_table,
     share_column, share_columns, pred_masks, tiny_graph, config1, config2, config3,
     batch_queries, rows_of_target, candidate_view, view_shares, onehot_rss, pack_word_major,
-    posting_slots, posting_graph,
+    posting_slots, posting_graph, TypedGraph, TypedTarget, TypedQuery, typed_graph, typed_shares,
+    pack_records,
 )

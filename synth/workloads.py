@@ -390,3 +390,86 @@ def batch_queries(seed: int, graph: Graph, count: int = 64, min_log_rows: int = 
                 preds.append(Pred(target, "range", col, lo=lo, hi=hi))
         out.append((Query(query_id=1000 + i, n_qv=n_qv, preds=preds), rows))
     return out
+
+
+# --------------------------------------------------------------------------- typed graphs (the paper's own encoding)
+
+@dataclass
+class TypedGraph:
+    """Def. 1 with vertex types: type T has n[T] vertices, IDs 0 .. n[T]-1 per
+    type; attrs[T][name] = (values uint32[n[T]], domain size) is an attribute
+    of the type's vertices (values below the domain size, for one-hot
+    encoding); adj[(T, T2)] lists, per vertex of type T, the sorted IDs of its
+    neighbours of type T2 (one edge type per ordered pair of vertex types)."""
+    n: dict
+    attrs: dict
+    adj: dict
+
+
+@dataclass
+class TypedTarget:
+    """One target vertex of a path query in the paper's form (Sec. V-C): its
+    type, the attribute its predicate reads, and the predicate on that
+    attribute's value (equality, or a half-open range)."""
+    vtype: str
+    attr: str
+    kind: str            # "eq" | "range"
+    a: int = 0
+    lo: int = 0
+    hi: int = 0
+
+    def holds(self, x) -> bool:
+        x = int(x)
+        return x == self.a if self.kind == "eq" else self.lo <= x < self.hi
+
+
+@dataclass
+class TypedQuery:
+    """A path query V_1 -> V_2 -> ... over a typed graph: target i + 1 is a
+    neighbour (of its type) of target i."""
+    query_id: int
+    targets: list
+
+
+def typed_graph(seed: int, n: dict, domains: dict, degrees: dict) -> TypedGraph:
+    """Random typed graph: per type T, n[T] vertices and one attribute per
+    (name, domain size) in domains[T], uniform over the domain; per ordered
+    type pair (T, T2) in degrees, each vertex of T gets a uniform number in
+    [0, degrees[(T, T2)]] of distinct neighbours of type T2 (no self loop when
+    T == T2)."""
+    rng = _rng(seed, 151)
+    attrs = {t: {name: (rng.integers(0, dom, n[t]).astype(U32), int(dom)) for name, dom in sorted(domains[t].items())}
+             for t in sorted(n)}
+    adj = {}
+    for (t, t2), dmax in sorted(degrees.items()):
+        lists = []
+        for v in range(n[t]):
+            pool = np.array([u for u in range(n[t2]) if not (t == t2 and u == v)], np.int64)
+            d = int(rng.integers(0, dmax + 1))
+            lists.append(np.sort(rng.choice(pool, min(d, pool.size), replace=False)).astype(U32))
+        adj[(t, t2)] = lists
+    return TypedGraph(dict(n), attrs, adj)
+
+
+def typed_shares(seed: int, tg: TypedGraph) -> dict:
+    """The data owner's one-hot binary RSS of the typed graph's IDs and
+    attributes (Sec. V-B), packed record-major (one record of ceil(n/32)
+    words per vertex): {("id", T): (3, n_T, words), ("attr", T, name): (3,
+    n_T, words)}; shares 1 and 2 uniform, share 3 the one-hot ^ both."""
+    out = {}
+    for i, t in enumerate(sorted(tg.n)):
+        out[("id", t)] = pack_records(onehot_rss(seed * 1000 + i, np.arange(tg.n[t], dtype=U32), tg.n[t]))
+        for j, (name, (vals, dom)) in enumerate(sorted(tg.attrs[t].items())):
+            out[("attr", t, name)] = pack_records(onehot_rss(seed * 1000 + 100 + 10 * i + j, vals, dom))
+    return out
+
+
+def pack_records(bits: np.ndarray) -> np.ndarray:
+    """(..., R, npos) 0/1 -> (..., R, ceil(npos/32)) uint32, position p of a
+    record at bit p % 32 of word p // 32."""
+    *lead, npos = bits.shape
+    nw = (npos + 31) // 32
+    padded = np.zeros((*lead, nw * 32), np.uint8)
+    padded[..., :npos] = bits
+    return np.packbits(padded.reshape(*lead, nw, 32), axis=-1, bitorder="little").view("<u4").reshape(
+        *lead, nw).astype(U32)

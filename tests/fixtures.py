@@ -42,3 +42,27 @@ def fig1_example():
         f = {qv[k]: vid[v] for k, v in m.items()}
         expected.add(tuple(row[(f[a], f[b])] for a, b in qedges))
     return g, q, expected, names
+
+
+def fig1_typed():
+    """The same example as a typed graph in the paper's own model (Sec. V-A):
+    types U, P, C with IDs per type in the order of the fixture, attributes
+    U.city, P.age, C.industry, and edge types graduate_from (U -> P), work_at
+    (P -> C) and friend (P -> P).  Returns (typed graph, names per type)."""
+    with open(os.path.join(GOLDEN, "fig1_university_query.json")) as f:
+        d = json.load(f)
+    tname = {v: k for k, v in d["codes"]["type"].items()}
+    per = {"U": [], "P": [], "C": []}
+    for v in d["vertices"]:
+        per[tname[v["type"]]].append(v)
+    idx = {v["name"]: (t, i) for t, vs in per.items() for i, v in enumerate(vs)}
+    field = {"U": ("city", 4), "P": ("age", 64), "C": ("industry", 4)}
+    attrs = {t: {field[t][0]: (np.array([v[field[t][0]] for v in vs], np.uint32), field[t][1])}
+             for t, vs in per.items()}
+    adj = {}
+    for a, b, et in d["edges"]:
+        (ta, ia), (tb, ib) = idx[a], idx[b]
+        adj.setdefault((ta, tb), [[] for _ in per[ta]])[ia].append(ib)
+    adj = {k: [np.array(sorted(x), np.uint32) for x in v] for k, v in adj.items()}
+    tg = synth.TypedGraph({t: len(vs) for t, vs in per.items()}, attrs, adj)
+    return tg, {t: [v["name"] for v in vs] for t, vs in per.items()}
