@@ -373,6 +373,16 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
                  const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream);
 
 /*
+ * rss_sec_eval_records: rss_sec_eval with candidate-major shares -- word w of
+ *   candidate c at [c * ceil(npos/32) + w] -- the one-hot records that
+ *   rss_fetch_many and rss_sec_access return (Alg. 2 evaluates the next
+ *   target's predicate on the neighbours secAccess fetched).  Same output and
+ *   errors; at most 2^32 candidates (FSS_EUNSUPPORTED).
+ */
+int rss_sec_eval_records(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
+                         const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream);
+
+/*
  * Three-party binary RSS arithmetic (Sec. III-B), all three parties simulated.
  * Share vectors are packed words (ceil(nrows/32) each); party P_i holds shares
  * i and i+1 (indices mod 3).  Zero sharing: <alpha>_i = F(k_i, j) ^ F(k_{i-1}, j)
@@ -473,6 +483,18 @@ int rss_shuffle_prepared(uint64_t nrows, uint32_t nwords, const uint32_t* const 
                          void* stream);
 int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[3], const uint32_t* const d_rows[3],
                      uint32_t* const d_out[3], void* stream);
+/*
+ * rss_fetch_table: secFetch's input table {x || id || d} (Alg. 4), for each
+ *   of the three shares i: record c (1 + id_words + val_words words) holds bit
+ *   c of d_bits[i] (packed, ceil(ncand/32) words) in bit 0 of word 0 (bits
+ *   1..31 zero), then record c of d_ids[i] (id_words words, candidate-major),
+ *   then record c of d_vals[i] (val_words words).  d_ids / d_vals may be NULL
+ *   when their width is 0.  The table is the d_table of rss_fetch_many.
+ *   Errors: EINVAL for a NULL buffer; EUNSUPPORTED beyond 65535 words per
+ *   record or 2^32 candidates.
+ */
+int rss_fetch_table(uint64_t ncand, const uint32_t* const d_bits[3], uint32_t id_words, const uint32_t* const d_ids[3],
+                    uint32_t val_words, const uint32_t* const d_vals[3], uint32_t* const d_out[3], void* stream);
 uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords);
 /* secAccess filter (Alg. 6): shuffle the fetched posting-list records, open
  * y = XOR of all bits of each record (1 for a one-hot ID, 0 for a dummy

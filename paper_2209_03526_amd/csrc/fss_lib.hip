@@ -654,6 +654,29 @@ __global__ void k_rss_eval(uint64_t ncand, uint32_t nwords_pos, const uint32_t* 
     }
 }
 
+// The same with candidate-major shares (word w of candidate c at
+// [c * nwords_pos + w]): the one-hot records that secFetch and secAccess hand
+// over.  One thread per candidate reads its record's words in turn.
+__global__ void k_rss_eval_rec(uint64_t ncand, uint32_t nwords_pos, const uint32_t* __restrict__ eval_a,
+                               const uint32_t* __restrict__ eval_b, const uint32_t* __restrict__ share_a,
+                               const uint32_t* __restrict__ share_b, uint32_t* __restrict__ out) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    if (c < ncand) {
+        const uint64_t base = c * nwords_pos;
+        for (uint32_t w = 0; w < nwords_pos; w++) {
+            acc = __builtin_amdgcn_bitop3_b32(acc, share_a[base + w], eval_a[w], 0x78);
+            acc = __builtin_amdgcn_bitop3_b32(acc, share_b[base + w], eval_b[w], 0x78);
+        }
+    }
+    const uint64_t ballot = __ballot(__builtin_popcount(acc) & 1u);
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t w = c >> 5, nw = (ncand + 31) >> 5;
+        if (w < nw) out[w] = (uint32_t)ballot;
+        if (w + 1 < nw) out[w + 1] = (uint32_t)(ballot >> 32);
+    }
+}
+
 // ----------------------------------------------------------------- streaming kernels (open, ANDs, joins)
 
 // xhat = x0 + x1 + r mod 2^32.  With vec (all four buffers 16-byte aligned) a
@@ -2198,6 +2221,19 @@ int rss_sec_eval(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const 
     hipLaunchKernelGGL(k_rss_eval, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, (hipStream_t)stream, ncand,
                        (npos + 31) / 32, d_eval_a, d_eval_b, d_share_a, d_share_b, d_out_bits);
     return check_launch("k_rss_eval");
+}
+
+int rss_sec_eval_records(uint64_t ncand, uint32_t npos, const uint32_t* d_eval_a, const uint32_t* d_eval_b,
+                         const uint32_t* d_share_a, const uint32_t* d_share_b, uint32_t* d_out_bits, void* stream) {
+    ogm::last_error().clear();
+    if (ncand == 0) return FSS_OK;
+    if (npos == 0) return fail(FSS_EINVAL, "rss_sec_eval_records: no positions");
+    if (ncand > 0xFFFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_sec_eval_records: more than 2^32 candidates");
+    if (!d_eval_a || !d_eval_b || !d_share_a || !d_share_b || !d_out_bits)
+        return fail(FSS_EINVAL, "rss_sec_eval_records: NULL buffer");
+    hipLaunchKernelGGL(k_rss_eval_rec, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       ncand, (npos + 31) / 32, d_eval_a, d_eval_b, d_share_a, d_share_b, d_out_bits);
+    return check_launch("k_rss_eval_rec");
 }
 
 int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu) {

@@ -776,6 +776,40 @@ int shuffle_release() {
 
 }  // namespace ogm
 
+namespace {
+
+// secFetch's table {x || id || d} (Alg. 4): record c of share i is the
+// predicate bit c of share i in bit 0 of word 0, then id record c (wi words),
+// then value record c (wv words).  One thread per output word.
+struct FetchTableArgs {
+    const uint32_t* bits[3];
+    const uint32_t* ids[3];
+    const uint32_t* vals[3];
+    uint32_t* out[3];
+};
+
+__global__ void k_fetch_table(uint64_t ncand, uint32_t wi, uint32_t wv, FetchTableArgs A) {
+    const uint64_t W = 1ull + wi + wv, total = ncand * W;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        const uint64_t c = g / W;
+        const uint32_t w = (uint32_t)(g - c * W);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            uint32_t v;
+            if (w == 0)
+                v = (A.bits[i][c >> 5] >> (c & 31u)) & 1u;
+            else if (w <= wi)
+                v = A.ids[i][c * wi + (w - 1)];
+            else
+                v = A.vals[i][c * wv + (w - 1 - wi)];
+            A.out[i][g] = v;
+        }
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 uint64_t rss_shuffle_workspace_bytes(uint64_t nrows, uint32_t nwords) {
@@ -867,6 +901,30 @@ int rss_fetch_unique(uint64_t ncand, uint32_t nwords, const uint32_t* const d_x[
     hipLaunchKernelGGL(k_fetch_unique, dim3(grid), dim3(kFetchBlock), 0, s, ncand, nwords, d_x[0], d_x[1], d_x[2], d_rows[0],
                        d_rows[1], d_rows[2], d_out[0], d_out[1], d_out[2]);
     return check_launch("k_fetch_unique");
+}
+
+int rss_fetch_table(uint64_t ncand, const uint32_t* const d_bits[3], uint32_t id_words, const uint32_t* const d_ids[3],
+                    uint32_t val_words, const uint32_t* const d_vals[3], uint32_t* const d_out[3], void* stream) {
+    last_error().clear();
+    if (ncand == 0) return FSS_OK;
+    if (!d_bits || !d_out || (id_words && !d_ids) || (val_words && !d_vals))
+        return fail(FSS_EINVAL, "rss_fetch_table: NULL argument");
+    if ((uint64_t)id_words + val_words + 1 > 65535)
+        return fail(FSS_EUNSUPPORTED, "rss_fetch_table: more than 65535 words per record");
+    if (ncand > 0xFFFFFFFFull) return fail(FSS_EUNSUPPORTED, "rss_fetch_table: more than 2^32 candidates");
+    FetchTableArgs A{};
+    for (int i = 0; i < 3; i++) {
+        if (!d_bits[i] || !d_out[i] || (id_words && !d_ids[i]) || (val_words && !d_vals[i]))
+            return fail(FSS_EINVAL, "rss_fetch_table: NULL share %d", i);
+        A.bits[i] = d_bits[i];
+        A.ids[i] = id_words ? d_ids[i] : nullptr;
+        A.vals[i] = val_words ? d_vals[i] : nullptr;
+        A.out[i] = d_out[i];
+    }
+    const uint64_t total = ncand * (1ull + id_words + val_words);
+    hipLaunchKernelGGL(k_fetch_table, dim3(grid_of(total, 256)), dim3(256), 0, (hipStream_t)stream, ncand, id_words,
+                       val_words, A);
+    return check_launch("k_fetch_table");
 }
 
 uint64_t rss_fetch_many_workspace_bytes(uint64_t ncand, uint32_t nwords) {

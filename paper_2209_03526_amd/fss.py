@@ -110,6 +110,8 @@ def _load():
         "rss_fetch_many": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_compact_valid": ([u64, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
         "rss_sec_eval": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
+        "rss_sec_eval_records": ([u64, u32, P, P, P, P, P, P], ctypes.c_int),
+        "rss_fetch_table": ([u64, P, u32, P, u32, P, P, P], ctypes.c_int),
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
         "fss_set_keygen_tuning": ([u32], ctypes.c_int),
         "fss_get_keygen_tuning": ([ctypes.POINTER(u32)], ctypes.c_int),
@@ -133,7 +135,7 @@ EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
            "rss_fetch_many_workspace_bytes",
-           "rss_fetch_many", "rss_compact_valid", "rss_group_k", "rss_enc_posting_lists",
+           "rss_fetch_many", "rss_compact_valid", "rss_sec_eval_records", "rss_fetch_table", "rss_group_k", "rss_enc_posting_lists",
            "rss_sec_access_workspace_bytes", "rss_sec_access")
 
 
@@ -441,6 +443,16 @@ def rss_sec_eval(ncand: int, npos: int, eval_a, eval_b, share_a, share_b, out_bi
 
 def _ptr3(ts):
     return (ctypes.c_void_p * 3)(*[_ptr(t) for t in ts])
+
+
+def rss_sec_eval_records(ncand: int, npos: int, eval_a, eval_b, share_a, share_b, out_bits, stream=None):
+    _check(LIB.rss_sec_eval_records(ncand, npos, _ptr(eval_a), _ptr(eval_b), _ptr(share_a), _ptr(share_b),
+                                    _ptr(out_bits), _stream(stream)))
+
+
+def rss_fetch_table(ncand: int, bits3, id_words: int, ids3, val_words: int, vals3, out3, stream=None):
+    _check(LIB.rss_fetch_table(ncand, _ptr3(bits3), id_words, _ptr3(ids3) if ids3 is not None else None, val_words,
+                               _ptr3(vals3) if vals3 is not None else None, _ptr3(out3), _stream(stream)))
 
 
 def rss_reshare(nrows: int, x3, prf_keys, counter: int, z3, stream=None):

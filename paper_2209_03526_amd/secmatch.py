@@ -1,0 +1,220 @@
+"""The paper's whole secure matching protocol, Alg. 2 (secMatch), over its own
+encoding, on the GPU: for a path query V_1 -> V_2 -> ... -> V_q over a typed
+graph, hop by hop
+
+  secEval (Alg. 3: full-domain evaluations of the replicated token,
+           `fss_eval_all`; each server's two terms, `rss_sec_eval_records`),
+  the re-share of its three-out-of-three bits into RSS (`rss_reshare`),
+  secFetch Case II (Alg. 4: the table {x || id || d}, `rss_fetch_table`;
+           shuffle, open, keep, `rss_fetch_many`),
+  secAccess (Alg. 6, `rss_sec_access`) of every kept vertex's neighbours of
+           the next target's type, over the k-grouped posting lists of Alg. 1
+           (`rss_enc_posting_lists`).
+
+All three servers are simulated on one device.  Every step runs in the
+library's kernels; this module only orders the calls and reads the counts
+that the opens of secFetch and secAccess reveal (one synchronisation per
+open, as in the protocol, where the count decides the next step's size).
+
+Readings where Alg. 2 leaves the order open: hop i + 1's candidates are
+grouped by the kept vertex whose neighbours they are, and secFetch runs once
+per group, so each kept vertex keeps its parent (the final reorganisation into
+subgraphs needs that tie); re-shares take PRF counters in order from
+`counter0` (secEval's re-share one, secAccess two); the s-th shuffle
+(secFetch's and secAccess's alike) takes the seeds (seed0 + 3s, +1, +2);
+predicate i's token is made with pred = i; an empty group takes no
+randomness.  The result is every chain of kept vertices, one per hop, each
+the parent of the next, as the three shares of each hop's one-hot ID record;
+the client reconstructs and drops chains that visit a vertex twice.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import fss
+
+# The token's replicated key pairs (Sec. V-C): server CS_1 holds (k_1^1, k_1^2),
+# CS_2 (k_2^2, k_1^3), CS_3 (k_2^3, k_2^1); with the one-hot shares (<e>_i,
+# <e>_{i+1}) each evaluates Eq. predEval's two terms.  Entries: (party of the
+# key, replica j - 1, share index - 1) of each term.
+SERVER_TERMS = (((0, 0, 0), (0, 1, 1)),
+                ((1, 1, 1), (0, 2, 2)),
+                ((1, 2, 2), (1, 0, 0)))
+
+
+def words(bits: int) -> int:
+    return (bits + 31) // 32
+
+
+def domain_bits(npos: int) -> int:
+    """Input width of the token's keys for positions 0 .. npos - 1 (at least 8)."""
+    return max(8, int(np.ceil(np.log2(max(npos, 2)))))
+
+
+@dataclass
+class EncodedGraph:
+    """A typed graph as the servers hold it, resident on one device: per type
+    its vertex count; per attribute its domain size; the three shares of the
+    one-hot ID and attribute records (record-major, ceil(n/32) words each);
+    per edge type (T, T2) the posting lists (CSR, k-grouped) and offsets."""
+    n: dict
+    domains: dict
+    shares: dict = field(default_factory=dict)
+    post: dict = field(default_factory=dict)
+    off: dict = field(default_factory=dict)
+    lmax: dict = field(default_factory=dict)
+
+
+def _dev(a: np.ndarray, device):
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)
+
+
+def encode_graph(n: dict, domains: dict, shares: dict, adj: dict, slots: dict, k: int, split_keys=(1001, 1002),
+                 counter: int = 4, device=None) -> EncodedGraph:
+    """The data owner's upload: the one-hot RSS records of IDs and attributes
+    (`shares`: {("id", T) | ("attr", T, name): (3, n_T, words) uint32}) moved
+    to the device, and Alg. 1 for every edge type (T, T2) of `adj` (lists of
+    neighbour IDs per vertex of T): lengths grouped k at a time
+    (`rss_group_k`), true IDs at the owner's slots (`slots[(T, T2)]`, flat in
+    adjacency order), one-hot records split into RSS with the PRF
+    (`rss_enc_posting_lists`)."""
+    dev = device or torch.device("cuda")
+    eg = EncodedGraph(dict(n), dict(domains))
+    for key, sh in shares.items():
+        eg.shares[key] = [_dev(sh[j].ravel(), dev) for j in range(3)]
+    for (t, t2), lists in sorted(adj.items()):
+        lengths = np.array([len(a) for a in lists], np.uint32)
+        padded, _ = fss.rss_group_k(lengths, np.zeros(lengths.size, np.uint32), k)
+        off = np.concatenate([[0], np.cumsum(padded, dtype=np.uint64)]).astype(np.uint32)
+        adj_off = np.concatenate([[0], np.cumsum(lengths, dtype=np.uint64)]).astype(np.uint32)
+        flat = np.concatenate([np.asarray(a, np.uint32) for a in lists]) if lengths.sum() else np.zeros(1, np.uint32)
+        nrec = int(off[-1])
+        wx = words(n[t2])
+        out = [torch.empty(max(1, nrec * wx), dtype=torch.int32, device=dev) for _ in range(3)]
+        d_off = _dev(off, dev)
+        if nrec:
+            fss.rss_enc_posting_lists(len(lists), n[t2], _dev(adj_off, dev), _dev(flat, dev),
+                                      _dev(np.asarray(slots[(t, t2)], np.uint32) if lengths.sum() else flat, dev),
+                                      d_off, nrec, split_keys, counter, out)
+        eg.post[(t, t2)] = out
+        eg.off[(t, t2)] = d_off
+        eg.lmax[(t, t2)] = max(1, int(padded.max()) if padded.size else 1)
+    torch.cuda.synchronize(dev)
+    return eg
+
+
+@dataclass
+class _Group:
+    parent: object        # (hop, group, kept row) of the parent; None at hop 0
+    n: int                # candidates
+    ids: list             # three device tensors, n one-hot ID records
+    vals: list            # three device tensors, n one-hot attribute records
+    kept: list = None     # three device tensors of kept {id || d} records
+    nkept: int = 0
+
+
+def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, seed0: int, device=None):
+    """Alg. 2 for a path query (``query.targets``: vertex type, attribute,
+    predicate per hop; readings in the module doc).  Returns the chains, each
+    a list over hops of the three shares (numpy uint32 records) of the hop's
+    one-hot ID."""
+    dev = device or torch.device("cuda")
+    counter, step = counter0, 0
+    t1 = query.targets[0]
+    hops = [[_Group(None, eg.n[t1.vtype], eg.shares[("id", t1.vtype)], eg.shares[("attr", t1.vtype, t1.attr)])]]
+    zero3 = torch.zeros(3, dtype=torch.int32, device=dev)
+    for i, tgt in enumerate(query.targets):
+        npos = eg.domains[(tgt.vtype, tgt.attr)]
+        nb = domain_bits(npos)
+        kind = fss.EQ if tgt.kind == "eq" else fss.RANGE
+        kb = fss.KeyBatch(kind, nb, 3, dev)
+        fss.fss_keygen(tok_seed, query.query_id, i, tgt.a if tgt.kind == "eq" else tgt.lo, tgt.hi, zero3, kb)
+        ev = {}
+        for party in (0, 1):
+            for rep in range(3):
+                ev[(party, rep)] = torch.empty(words(npos), dtype=torch.int32, device=dev)
+                fss.fss_eval_all(party, kb, rep, npos, ev[(party, rep)])
+        wi, wv = words(eg.n[tgt.vtype]), words(npos)
+        nxt = []
+        for gi, g in enumerate(hops[i]):
+            if g.n == 0:
+                continue
+            # secEval, then the re-share into RSS
+            x3 = [torch.empty(words(g.n), dtype=torch.int32, device=dev) for _ in range(3)]
+            for s, ((pa, ra, ja), (pb, rb, jb)) in enumerate(SERVER_TERMS):
+                fss.rss_sec_eval_records(g.n, npos, ev[(pa, ra)], ev[(pb, rb)], g.vals[ja], g.vals[jb], x3[s])
+            z3 = [torch.empty(words(g.n), dtype=torch.int32, device=dev) for _ in range(3)]
+            fss.rss_reshare(g.n, x3, prf_keys, counter, z3)
+            counter += 1
+            # secFetch Case II on {x || id || d}
+            rec = 1 + wi + wv
+            table = [torch.empty(g.n * rec, dtype=torch.int32, device=dev) for _ in range(3)]
+            fss.rss_fetch_table(g.n, z3, wi, g.ids, wv, g.vals, table)
+            g.kept = [torch.empty(g.n * (rec - 1), dtype=torch.int32, device=dev) for _ in range(3)]
+            pos = torch.empty(g.n, dtype=torch.int32, device=dev)
+            cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+            work = fss.rss_fetch_many(g.n, rec, table, (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2),
+                                      g.kept, pos, cnt)
+            step += 1
+            g.nkept = int(cnt.item())            # the open reveals how many candidates match
+            del work, table
+            if i + 1 == len(query.targets):
+                continue
+            nt = query.targets[i + 1]
+            pair = (tgt.vtype, nt.vtype)
+            wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
+            lmax = eg.lmax[pair]
+            for r in range(g.nkept):
+                idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
+                ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
+                vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
+                rows = torch.empty(lmax, dtype=torch.int32, device=dev)
+                c2 = torch.zeros(1, dtype=torch.int32, device=dev)
+                seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+                work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax, eg.post[pair],
+                                          wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys, counter, seeds,
+                                          ids3, vals3, rows, c2)
+                counter += 2
+                step += 1
+                m = int(c2.item())               # the validity open reveals the list's true length
+                del work
+                nxt.append(_Group((i, gi, r), m, ids3, vals3))
+        if i + 1 < len(query.targets):
+            hops.append(nxt)
+    return _chains(hops, query, eg)
+
+
+def _chains(hops, query, eg):
+    out = []
+    host = {}
+
+    def kept_ids(i, gi):
+        if (i, gi) not in host:
+            g = hops[i][gi]
+            t = query.targets[i]
+            wi, wv = words(eg.n[t.vtype]), words(eg.domains[(t.vtype, t.attr)])
+            arr = [g.kept[j][:g.nkept * (wi + wv)].cpu().numpy().view(np.uint32).reshape(g.nkept, wi + wv)[:, :wi]
+                   for j in range(3)] if g.nkept else [np.zeros((0, wi), np.uint32)] * 3
+            host[(i, gi)] = arr
+        return host[(i, gi)]
+
+    def walk(i, gi, prefix):
+        g = hops[i][gi]
+        if g.nkept == 0:
+            return
+        ids = kept_ids(i, gi)
+        for r in range(g.nkept):
+            rec = [ids[j][r] for j in range(3)]
+            if i + 1 == len(hops):
+                out.append(prefix + [rec])
+                continue
+            for gj, h in enumerate(hops[i + 1]):
+                if h.parent == (i, gi, r):
+                    walk(i + 1, gj, prefix + [rec])
+
+    if hops and hops[0]:
+        walk(0, 0, [])
+    return out

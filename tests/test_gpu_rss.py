@@ -218,3 +218,31 @@ def test_sec_eval_reshare_and_chain(fss):
         np.testing.assert_array_equal(got[i], want[i])
     truth = ((values >= 30) & (values < 40)).astype(np.uint8)
     np.testing.assert_array_equal(ofss.unpack_bits(got[0] ^ got[1] ^ got[2], ncand), truth)
+
+
+@pytest.mark.parametrize("kind,npos,ncand", [("eq", 64, 5003), ("range", 100, 777), ("eq", 8, 1), ("range", 33, 64)])
+def test_sec_eval_records_parity(fss, kind, npos, ncand):
+    """secEval on candidate-major one-hot records (the layout secFetch and
+    secAccess return) equals the oracle's server shares."""
+    rng = np.random.default_rng(npos * 7 + ncand)
+    values = rng.integers(0, npos, ncand).astype(np.uint32)
+    shares = synth.onehot_rss(npos + 11, values, npos)
+    a, lo, hi = int(values[-1]), npos // 4, npos - npos // 3
+    okeys, nb = orss.token(kind, npos, 91, 6, 2, a=a, lo=lo, hi=hi)
+    kb, _ = _gpu_token(fss, kind, npos, 91, 6, 2, a=a, lo=lo, hi=hi)
+    nw = (npos + 31) // 32
+    ev = {}
+    for party in (0, 1):
+        for rep in range(3):
+            ev[(party, rep)] = torch.zeros(nw, dtype=torch.int32, device=DEV)
+            fss.fss_eval_all(party, kb, rep, npos, ev[(party, rep)])
+    rec = [T(synth.pack_records(shares[j]).ravel()) for j in range(3)]
+    want = orss.server_shares(kind, npos, okeys, nb, shares)
+    xs = []
+    for i, ((pa, ra, ja), (pb, rb, jb)) in enumerate(orss.SERVER_TERMS):
+        out = torch.full(((ncand + 31) // 32,), -1, dtype=torch.int32, device=DEV)
+        fss.rss_sec_eval_records(ncand, npos, ev[(pa, ra)], ev[(pb, rb)], rec[ja], rec[jb], out)
+        np.testing.assert_array_equal(ofss.unpack_bits(U(out), ncand), want[i])
+        xs.append(U(out))
+    truth = (values == a) if kind == "eq" else ((values >= lo) & (values < hi))
+    np.testing.assert_array_equal(ofss.unpack_bits(xs[0] ^ xs[1] ^ xs[2], ncand), truth.astype(np.uint8))

@@ -281,3 +281,19 @@ def test_sec_access_composed(fss):
             np.testing.assert_array_equal(U(d[i]), want_attrs[i][j])
     rec = got_ids[0] ^ got_ids[1] ^ got_ids[2]
     assert sorted(int(access.unpack_onehot(r, x_count)[0]) for r in rec) == adj[m]
+
+
+@pytest.mark.parametrize("ncand,wi,wv", [(1, 1, 1), (37, 3, 2), (5000, 2, 0), (1025, 0, 4)])
+def test_fetch_table(fss, ncand, wi, wv):
+    """secFetch's table {x || id || d}: the predicate bit in bit 0 of word 0,
+    then the id and value records, for each share."""
+    rng = np.random.default_rng(ncand + wi)
+    bits = [rng.integers(0, 2, ncand, dtype=np.uint8) for _ in range(3)]
+    ids = [rng.integers(0, 2**32, (ncand, wi), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    vals = [rng.integers(0, 2**32, (ncand, wv), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+    out = [torch.full((ncand * (1 + wi + wv),), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_fetch_table(ncand, [T(ofss.pack_bits(b)) for b in bits], wi, [T(x.ravel()) for x in ids] if wi else None,
+                        wv, [T(x.ravel()) for x in vals] if wv else None, out)
+    for j in range(3):
+        want = np.concatenate([bits[j].astype(np.uint32)[:, None], ids[j], vals[j]], axis=1)
+        np.testing.assert_array_equal(U(out[j]).reshape(ncand, 1 + wi + wv), want)
