@@ -1036,6 +1036,7 @@ def run_next(args, torch, fss, dev):
         f"re-share, shuffle/open/compact of {lmax} records, attribute selection over {xbits} records per kept ID",
         2 * 3 * lmax * wx // 16)
     del post, ids3, attrs3
+    res["sec_match"] = sec_match_row(args, torch, dev)
     if not args.no_cpu_baseline:
         gpu_rate = {"sec_eval": ncand, "rss_and": nrows, "rss_reshare": nrows, "rss_shuffle": 1 << 22,
                     "rss_fetch_unique": 1 << 22, "rss_fetch_many": 1 << 22, "rss_compact_valid": 1 << 22,
@@ -1048,6 +1049,67 @@ def run_next(args, torch, fss, dev):
            "n_gpus": 1, "rows": res, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "next: secEval 2^20 x 4096, RSS 2^30 bits, shuffle/fetch 2^22 x 64 B"}}
     print(json.dumps(out), flush=True)
+
+
+def sec_match_row(args, torch, dev):
+    """The paper's whole secMatch (Alg. 2) for one path query U -> P -> C over a
+    typed graph (200 U, 8,000 P, 1,000 C vertices; up to 40 P neighbours per U
+    and 3 C neighbours per P, k = 2 groups), all three servers on the GPU:
+    wall-clock time of the call (its opens synchronise the host once per
+    secFetch and per secAccess), beside the oracle on the same instance on
+    one core."""
+    from oracle import secmatch as osm
+    from paper_2209_03526_amd import fss as lib
+    from paper_2209_03526_amd import secmatch
+
+    T = synth.TypedTarget
+    n = {"U": 200, "P": 8000, "C": 1000}
+    domains = {"U": {"city": 40}, "P": {"age": 100}, "C": {"industry": 16}}
+    tg = synth.typed_graph(SEED, n, domains, {("U", "P"): 40, ("P", "C"): 3})
+    q = synth.TypedQuery(31, [T("U", "city", "range", lo=3, hi=8), T("P", "age", "range", lo=25, hi=60),
+                              T("C", "industry", "eq", a=5)])
+    shares = synth.typed_shares(SEED, tg)
+    slots = {}
+    for e, ((t, t2), lists) in enumerate(sorted(tg.adj.items())):
+        lengths = np.array([len(a) for a in lists], np.uint32)
+        padded, _ = lib.rss_group_k(lengths, np.zeros(lengths.size, np.uint32), 2)
+        slots[(t, t2)] = synth.posting_slots(SEED + e, lengths, padded)
+    dom = {(t, a): d for t, v in tg.attrs.items() for a, (_, d) in v.items()}
+    eg = secmatch.encode_graph(tg.n, dom, shares, tg.adj, slots, 2, device=dev)
+    prf, c0, s0 = (41, 42, 43), 3, 900
+
+    def once():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch = secmatch.sec_match(eg, q, SEED, prf, c0, s0, device=dev)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ch
+
+    once()
+    runs = [once() for _ in range(5)]
+    ms = float(np.median([r[0] for r in runs])) * 1e3
+    chains = runs[-1][1]
+    found = osm.reconstruct(tg, q, chains)
+    ok = found == osm.brute_force(tg, q)
+    out = {"ms": round(ms, 3), "binding": "host-ordered steps: one open per secFetch and per secAccess",
+           "results": len(found), "plaintext_match": ok,
+           "work": "one 3-hop path query (Alg. 2: secEval, re-share, secFetch, secAccess per kept vertex) over "
+                   f"{n['U']} U / {n['P']} P / {n['C']} C typed vertices, one-hot IDs, k = 2 posting lists"}
+    if not args.no_cpu_baseline:
+        enc = osm.encode(tg, shares, 2, SEED)
+        _omp_threads(1)                       # the oracle's OpenMP loops on one core, like its numpy steps
+        t0 = time.perf_counter()
+        want, _ = osm.sec_match(tg, enc, q, SEED, prf, c0, s0)
+        dt = time.perf_counter() - t0
+        _omp_threads(int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))))
+        exact = len(want) == len(chains) and all(
+            np.array_equal(a[j], b[j]) for x, y in zip(want, chains) for a, b in zip(x, y) for j in range(3))
+        out["cpu_baseline"] = {"value": round(dt * 1e3, 1), "unit": "ms per query", "cores": 1, "kind": "oracle",
+                               "sample": "the same query on the same typed graph", "cpu": _cpu_model()}
+        out["gpu_over_cpu"] = round(dt * 1e3 / ms, 1)
+        out["shares_bit_exact_vs_oracle"] = exact
+    log(f"sec_match: {out}")
+    return out
 
 
 def next_cpu_baselines():
