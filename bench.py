@@ -93,13 +93,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading), or
-    None if there is none or the kernel sources changed since it was taken."""
+def measured_record(kernel: str) -> dict:
+    """The committed rocprofv3 counter summary of `kernel`
+    (profiles/<kernel>.traffic.txt: HBM bytes per launch from FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy's reading, and the clock and pipe busy
+    fractions of the same launch from the SQ counters), or {} if there is none
+    or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}.traffic.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as fh:
         for ln in fh:
@@ -107,11 +109,19 @@ def measured_traffic(kernel: str):
                 k, v = ln.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source_sha256_16") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for key in ("traffic_bytes_per_launch", "clock_ghz", "valu_busy_pct", "lds_busy_pct"):
+        try:
+            out[key] = float(vals[key])
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from measured_record, or None."""
+    return measured_record(kernel).get("traffic_bytes_per_launch")
 
 
 def parse():
@@ -218,12 +228,19 @@ def kernel_row(ms: float, launches: int, blocks: float, hbm_bytes: float) -> dic
 
 
 def roofline_of(name: str, k: dict) -> dict:
-    return {"bound": "alu", "kernel": name, "achieved": k["aes_gblocks_per_s"], "peak": k["floor_gblocks_per_s"],
-            "unit": "G AES-128 blocks/s (peak: the LDS-read issue floor of the T-table AES, 32 reads per clock "
-                    "per CU, 160 per block, 256 CUs at 2.4 GHz)",
-            "frac": k["frac_of_floor"], "traffic": measured_traffic(name), "binding_unit": k["binding_unit"],
-            "valu_frac": k["valu_frac"], "lds_frac": k["lds_frac"],
-            "aes_blocks_per_launch": k["aes_blocks"], "ms_per_launch": k["ms"]}
+    rec = measured_record(name)
+    out = {"bound": "alu", "kernel": name, "achieved": k["aes_gblocks_per_s"], "peak": k["floor_gblocks_per_s"],
+           "unit": "G AES-128 blocks/s (peak: the LDS-read issue floor of the T-table AES, 32 reads per clock "
+                   "per CU, 160 per block, 256 CUs at 2.4 GHz)",
+           "frac": k["frac_of_floor"], "traffic": rec.get("traffic_bytes_per_launch"),
+           "binding_unit": k["binding_unit"], "valu_frac": k["valu_frac"], "lds_frac": k["lds_frac"],
+           "aes_blocks_per_launch": k["aes_blocks"], "ms_per_launch": k["ms"]}
+    if "clock_ghz" in rec:
+        # the same floor at the clock the counters measured for this kernel
+        clk = rec["clock_ghz"]
+        out.update(measured_clock_ghz=clk, frac_at_measured_clock=round(k["frac_of_floor"] * 2.4 / clk, 4),
+                   valu_busy_pct=rec.get("valu_busy_pct"), lds_busy_pct=rec.get("lds_busy_pct"))
+    return out
 
 
 def run_full(args, torch, fss, dev, graph, query):
