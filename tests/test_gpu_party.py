@@ -139,3 +139,29 @@ def test_single_party_batch(fss):
             got = plan_outputs(plans[b][i], q, g)
             for j in range(len(want[i])):
                 np.testing.assert_array_equal(got[j][b], want[i][j][b], err_msg=f"plan {i} party {b} output {j}")
+
+
+def test_single_party_rounds_full_size(fss):
+    """One server's half at the full path query's size (Chung-Lu 2^22 vertices /
+    2^25 edges, 4 vertex + 2 edge predicates): each party run alone in rounds
+    gives the same shares as both at once, and sampled rows equal the
+    oracle's."""
+    from oracle import fss as ofss
+    g, q = synth.config3(3)
+    seed = 4244
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    preds = _inputs(fss, g, q, shares, masks, seed)
+    both = _plan(fss, g, q, preds, seed)
+    fss.match_query(both, 3)
+    parties = [_plan(fss, g, q, preds, seed) for _ in range(2)]
+    R = _run_parties(fss, parties)
+    assert R == 3          # c's fold at level 1; hop b -> c ANDs its endpoints at 2 and q_1 at 3
+    rows = np.unique(np.concatenate([[0, 31, g.n_edges - 1], np.random.default_rng(7).integers(0, g.n_edges, 40)]))
+    want = omatch.sampled_outputs(32, seed, g, q, shares, masks, rows)
+    got3 = plan_outputs(both, q, g)
+    for b in range(2):
+        got = plan_outputs(parties[b], q, g)
+        for j in range(len(got3)):
+            np.testing.assert_array_equal(got[j][b], got3[j][b], err_msg=f"party {b} output {j}")
+            np.testing.assert_array_equal(ofss.unpack_bits(got[j][b], g.n_edges)[rows], want[j, b])
