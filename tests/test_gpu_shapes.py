@@ -105,3 +105,41 @@ def test_shapes_batch(fss):
         _compare(plan_outputs(plan, q, gi), want[i], f"plan {i}")
     got = plan_outputs(plans[-1], fig_q, fig_g)
     assert omatch.results_from_bits(fig_g, fig_q, omatch.reconstruct(got, fig_g.n_edges)) == expected
+
+
+def _max_query():
+    """The largest plan the boundary takes: 8 query vertices, 16 query edges
+    (a cycle through all vertices, chords and two reversed edges), 32
+    predicates spread over vertices and edges, some targets with none."""
+    P = synth.Pred
+    edges = [(i, (i + 1) % 8) for i in range(8)] + [(0, 2), (2, 4), (4, 6), (6, 0), (1, 5), (3, 7), (2, 1), (5, 4)]
+    preds = []
+    for k in range(32):
+        t = (k * 5) % 24                       # 0..7 vertices, 8..23 edges
+        if t == 3 or t == 17:
+            t = 0                              # leave vertex 3 and query edge 9 without predicates
+        if t < 8:
+            preds.append(P(t, "range", "attr", lo=k % 5, hi=16 - k % 3) if k % 2 else P(t, "eq", "label", a=k % 3))
+        else:
+            preds.append(P(t, "range", "weight", lo=k % 4, hi=15) if k % 2 else P(t, "eq", "label", a=k % 4))
+    return synth.Query(91, 8, preds, edges=edges)
+
+
+def test_largest_query_graph(fss):
+    """8 vertices, 16 edges, 32 predicates over a graph of several tail tiles:
+    both parties at once, one party in rounds, and batched, all equal to the
+    oracle's shares."""
+    q = _max_query()
+    g = synth.tiny_graph(93, n_vertices=3000, n_edges=40001, label_range=3, attr_range=16)
+    seed = 9393
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    want = omatch.run_plan(32, seed, g, q, shares, masks)
+    got = plan_outputs(run_query_gpu(fss, g, q, shares, masks, seed), q, g)
+    _compare(got, want, "max query, both parties")
+    _check_parties(fss, g, q, seed)
+    plan, kg = _setup_query(fss, g, q, shares, masks, seed)
+    fss.fss_keygen_batch(kg, fss.Queue(len(kg)))
+    fss.match_query_batch([plan], fss.Queue(64))
+    torch.cuda.synchronize()
+    _compare(plan_outputs(plan, q, g), want, "max query, batched")
