@@ -123,23 +123,35 @@ def group_k(lengths, types, k: int):
     group holds vertices of similar length, and every list of a group is
     padded to the group's longest.  A type whose vertex count is not a
     multiple of k puts the remainder into its last group (a group of at least
-    k whenever the type has k vertices).  Returns (padded lengths, group of
-    each vertex)."""
+    k whenever the type has k vertices).
+
+    With several posting-list types per vertex (``lengths`` of shape (L, n),
+    row l the lengths of list type l), Alg. 1 picks ONE group for a vertex
+    and pads each of its list types within that group, so that every vertex
+    shares its whole vector of padded lengths with at least k - 1 others: the
+    order is then by the length vector, list type 0 first, ties by vertex ID.
+    Returns (padded lengths, of the shape of ``lengths``; group of each
+    vertex)."""
     lengths = np.asarray(lengths, np.int64)
+    one = lengths.ndim == 1
+    lv = lengths[None, :] if one else lengths
     types = np.asarray(types)
-    padded = np.zeros(lengths.size, np.int64)
-    group = np.full(lengths.size, -1, np.int64)
+    n = lv.shape[1]
+    padded = np.zeros(lv.shape, np.int64)
+    group = np.full(n, -1, np.int64)
     gid = 0
     for t in np.unique(types):
         members = np.flatnonzero(types == t)
-        order = members[np.lexsort((members, lengths[members]))]
+        # np.lexsort sorts by its last key first: list type 0, then 1, ..., then the ID
+        order = members[np.lexsort((members,) + tuple(lv[l][members] for l in reversed(range(lv.shape[0]))))]
         ngroups = max(1, order.size // k)
         for g in range(ngroups):
             sel = order[g * k:(g + 1) * k] if g < ngroups - 1 else order[g * k:]
-            padded[sel] = lengths[sel].max()
+            for l in range(lv.shape[0]):
+                padded[l, sel] = lv[l, sel].max()
             group[sel] = gid
             gid += 1
-    return padded, group
+    return (padded[0] if one else padded), group
 
 
 def csr_offsets(padded) -> np.ndarray:

@@ -63,14 +63,25 @@ class Encoded:
 
 
 def encode(tg, shares: dict, k: int, slot_seed: int, split_keys=(1001, 1002), counter: int = 4) -> Encoded:
-    """Alg. 1 for every edge type of the typed graph (in sorted order, the
-    e-th with slot seed slot_seed + e): each type's vertices grouped k at a
-    time, posting lists padded per group, true IDs at the seeded slots, split
+    """Alg. 1 over the typed graph: per vertex type, its vertices grouped k at
+    a time by the vector of their posting-list lengths (one group for all
+    the type's list types, in sorted order of the neighbour type), each list
+    padded to its group's longest; true IDs at the seeded slots (the e-th
+    edge type in sorted order with slot seed slot_seed + e), records split
     into binary RSS with the PRF."""
     enc = Encoded(dict(shares))
-    for e, ((t, t2), lists) in enumerate(sorted(tg.adj.items())):
+    pairs = sorted(tg.adj)
+    padded_of = {}
+    for t in sorted({p[0] for p in pairs}):
+        mine = [p for p in pairs if p[0] == t]
+        lengths = np.array([[len(a) for a in tg.adj[p]] for p in mine], np.int64)
+        padded, _ = access.group_k(lengths, np.zeros(lengths.shape[1], np.uint32), k)
+        for row, p in enumerate(mine):
+            padded_of[p] = padded[row]
+    for e, (t, t2) in enumerate(pairs):
+        lists = tg.adj[(t, t2)]
         lengths = np.array([len(a) for a in lists], np.uint32)
-        padded, _ = access.group_k(lengths, np.zeros(lengths.size, np.uint32), k)
+        padded = padded_of[(t, t2)]
         slots = synth.posting_slots(slot_seed + e, lengths, padded)
         rec, off = access.encode_posting_lists_k(lists, tg.n[t2], padded, slots)
         enc.post[(t, t2)] = access.rss_split_prf(rec, split_keys[0], split_keys[1], counter)

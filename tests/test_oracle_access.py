@@ -91,6 +91,48 @@ def test_group_k_properties_on_random_graph():
     assert any(hi1 > lo2 for (lo1, hi1), (lo2, hi2) in zip(spans, spans[1:]))
 
 
+def test_group_k_several_list_types_hand_example():
+    """Two list types per vertex (e.g. friends and employers), one type of
+    vertex, k = 2.  Length vectors (list 0, list 1): v0 (2, 5), v1 (1, 0),
+    v2 (2, 1), v3 (1, 7), v4 (3, 3).  In order of the vector: v1 (1, 0),
+    v3 (1, 7) | v2 (2, 1), v0 (2, 5), v4 (3, 3); each list type pads to its
+    group's longest."""
+    lengths = np.array([[2, 1, 2, 1, 3], [5, 0, 1, 7, 3]])
+    padded, group = access.group_k(lengths, [0] * 5, 2)
+    assert padded[0].tolist() == [3, 1, 3, 1, 3]
+    assert padded[1].tolist() == [5, 7, 5, 7, 5]
+    assert group[1] == group[3] and group[0] == group[2] == group[4] and group[0] != group[1]
+    # one list type in a (1, n) array is the single-list grouping
+    p1, g1 = access.group_k(lengths[:1], [0] * 5, 2)
+    p0, g0 = access.group_k(lengths[0], [0] * 5, 2)
+    assert p1[0].tolist() == p0.tolist() and g1.tolist() == g0.tolist()
+
+
+def test_group_k_several_list_types_is_k_automorphic():
+    """Every vertex shares its whole vector of padded lengths with at least
+    k - 1 others of its type (Alg. 1 picks one group per vertex for all its
+    list types); grouping each list type on its own does not give that."""
+    rng = np.random.default_rng(5)
+    n, k = 400, 4
+    types = rng.integers(0, 2, n)
+    lengths = np.stack([rng.zipf(1.8, n).clip(0, 30), rng.integers(0, 9, n), rng.zipf(2.5, n).clip(0, 12)])
+    padded, group = access.group_k(lengths, types, k)
+    for t in (0, 1):
+        vecs = [tuple(padded[:, v]) for v in np.flatnonzero(types == t)]
+        _, counts = np.unique(np.array(vecs), axis=0, return_counts=True)
+        assert counts.min() >= k
+        for l in range(3):
+            m = types == t
+            for g in set(group[m]):
+                sel = group == g
+                assert (padded[l, sel] == lengths[l, sel].max()).all()
+    # separately per list type: some vertex's vector of padded lengths is unique
+    sep = np.stack([access.group_k(lengths[l], types, k)[0] for l in range(3)])
+    vecs = [tuple(sep[:, v]) for v in np.flatnonzero(types == 0)]
+    _, counts = np.unique(np.array(vecs), axis=0, return_counts=True)
+    assert counts.min() < k
+
+
 def test_encoding_places_true_ids_among_zero_dummies():
     types, adj, _ = synth.posting_graph(4, 300, 90, 12)
     lengths = np.array([len(a) for a in adj])
