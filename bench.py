@@ -1087,11 +1087,9 @@ def sec_match_row(args, torch, dev):
     q = synth.TypedQuery(31, [T("U", "city", "range", lo=3, hi=8), T("P", "age", "range", lo=25, hi=60),
                               T("C", "industry", "eq", a=5)])
     shares = synth.typed_shares(SEED, tg)
-    slots = {}
-    for e, ((t, t2), lists) in enumerate(sorted(tg.adj.items())):
-        lengths = np.array([len(a) for a in lists], np.uint32)
-        padded, _ = lib.rss_group_k(lengths, np.zeros(lengths.size, np.uint32), 2)
-        slots[(t, t2)] = synth.posting_slots(SEED + e, lengths, padded)
+    padded = secmatch.padded_lengths(tg.adj, 2)
+    slots = {pair: synth.posting_slots(SEED + e, np.array([len(a) for a in tg.adj[pair]], np.uint32), padded[pair])
+             for e, pair in enumerate(sorted(tg.adj))}
     dom = {(t, a): d for t, v in tg.attrs.items() for a, (_, d) in v.items()}
     eg = secmatch.encode_graph(tg.n, dom, shares, tg.adj, slots, 2, device=dev)
     prf, c0, s0 = (41, 42, 43), 3, 900

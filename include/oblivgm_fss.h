@@ -532,6 +532,13 @@ int fss_get_keygen_tuning(uint32_t* tile_mult);
  *   padded to its group's longest: padded[v] receives that length, group[v]
  *   (NULL: not written) the group number (types in increasing order, groups
  *   in length order).  EINVAL for NULL arguments or k = 0.
+ * rss_group_k_lists (host arrays): the same for vertices with nlists posting-
+ *   list types (Alg. 1 groups a vertex once and pads each of its list types
+ *   within the group, so every vertex shares its whole vector of padded
+ *   lengths with k - 1 others).  lengths / padded: nlists x n, list type l of
+ *   vertex v at [l * n + v]; the order is by the vector of lengths, list type
+ *   0 first, ties by vertex ID.  rss_group_k is its nlists = 1 case.  EINVAL
+ *   also for nlists = 0.
  * rss_enc_posting_lists (device): the padded lists as binary RSS of one-hot
  *   records.  d_adj_off (n+1) / d_adj: the true neighbour IDs of each vertex
  *   in CSR order; d_slot: the slot of each true ID within its padded list (the
@@ -562,6 +569,8 @@ int fss_get_keygen_tuning(uint32_t* tile_mult);
  */
 int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint32_t k, uint32_t* padded,
                 uint32_t* group);
+int rss_group_k_lists(uint64_t n, uint32_t nlists, const uint32_t* lengths, const uint32_t* types, uint32_t k,
+                      uint32_t* padded, uint32_t* group);
 int rss_enc_posting_lists(uint64_t n, uint32_t x_bits, const uint32_t* d_adj_off, const uint32_t* d_adj,
                           const uint32_t* d_slot, const uint32_t* d_off, uint64_t nrec, const uint64_t split_keys[2],
                           uint32_t counter, uint32_t* const d_out[3], void* d_work, uint64_t work_bytes, void* stream);

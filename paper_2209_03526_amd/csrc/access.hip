@@ -301,18 +301,21 @@ uint64_t rnd(uint64_t words) { return (words * 4 + 255) & ~255ull; }
 
 extern "C" {
 
-int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint32_t k, uint32_t* padded,
-                uint32_t* group) {
+int rss_group_k_lists(uint64_t n, uint32_t nlists, const uint32_t* lengths, const uint32_t* types, uint32_t k,
+                      uint32_t* padded, uint32_t* group) {
     last_error().clear();
     if (n == 0) return FSS_OK;
     if (!lengths || !types || !padded) return fail(FSS_EINVAL, "rss_group_k: NULL argument");
     if (k == 0) return fail(FSS_EINVAL, "rss_group_k: k must be at least 1");
+    if (nlists == 0) return fail(FSS_EINVAL, "rss_group_k: no list types");
+    auto len = [&](uint32_t l, uint64_t v) { return lengths[(uint64_t)l * n + v]; };
     std::vector<uint64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
-    // by type, then length, then vertex ID
+    // by type, then the vector of list lengths (list type 0 first), then vertex ID
     std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
         if (types[a] != types[b]) return types[a] < types[b];
-        if (lengths[a] != lengths[b]) return lengths[a] < lengths[b];
+        for (uint32_t l = 0; l < nlists; l++)
+            if (len(l, a) != len(l, b)) return len(l, a) < len(l, b);
         return a < b;
     });
     uint32_t gid = 0;
@@ -323,17 +326,23 @@ int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint
         const uint64_t ngroups = m / k > 0 ? m / k : 1;
         for (uint64_t g = 0; g < ngroups; g++) {
             const uint64_t lo = s + g * k, hi = g + 1 < ngroups ? lo + k : e;   // the last takes the rest
-            uint32_t mx = 0;
-            for (uint64_t i = lo; i < hi; i++) mx = std::max(mx, lengths[order[i]]);
-            for (uint64_t i = lo; i < hi; i++) {
-                padded[order[i]] = mx;
-                if (group) group[order[i]] = gid;
+            for (uint32_t l = 0; l < nlists; l++) {
+                uint32_t mx = 0;
+                for (uint64_t i = lo; i < hi; i++) mx = std::max(mx, len(l, order[i]));
+                for (uint64_t i = lo; i < hi; i++) padded[(uint64_t)l * n + order[i]] = mx;
             }
+            if (group)
+                for (uint64_t i = lo; i < hi; i++) group[order[i]] = gid;
             gid++;
         }
         s = e;
     }
     return FSS_OK;
+}
+
+int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint32_t k, uint32_t* padded,
+                uint32_t* group) {
+    return rss_group_k_lists(n, 1, lengths, types, k, padded, group);
 }
 
 int rss_enc_posting_lists(uint64_t n, uint32_t x_bits, const uint32_t* d_adj_off, const uint32_t* d_adj,

@@ -116,6 +116,7 @@ def _load():
         "fss_set_keygen_tuning": ([u32], ctypes.c_int),
         "fss_get_keygen_tuning": ([ctypes.POINTER(u32)], ctypes.c_int),
         "rss_group_k": ([u64, P, P, u32, P, P], ctypes.c_int),
+        "rss_group_k_lists": ([u64, u32, P, P, u32, P, P], ctypes.c_int),
         "rss_enc_posting_lists": ([u64, u32, P, P, P, P, u64, P, u32, P, P, u64, P], ctypes.c_int),
         "rss_sec_access_workspace_bytes": ([u32, u32, u32], u64),
         "rss_sec_access": ([u64, u32, P, P, u32, P, u32, P, P, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
@@ -135,7 +136,7 @@ EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
            "rss_fetch_many_workspace_bytes",
-           "rss_fetch_many", "rss_compact_valid", "rss_sec_eval_records", "rss_fetch_table", "rss_group_k", "rss_enc_posting_lists",
+           "rss_fetch_many", "rss_compact_valid", "rss_sec_eval_records", "rss_fetch_table", "rss_group_k", "rss_group_k_lists", "rss_enc_posting_lists",
            "rss_sec_access_workspace_bytes", "rss_sec_access")
 
 
@@ -529,6 +530,20 @@ def rss_group_k(lengths, types, k: int):
     group = np.zeros(lengths.size, np.uint32)
     _check(LIB.rss_group_k(lengths.size, lengths.ctypes.data, types.ctypes.data, k, padded.ctypes.data,
                            group.ctypes.data))
+    return padded, group
+
+
+def rss_group_k_lists(lengths, types, k: int):
+    """Host arrays in: lengths (nlists, n), types (n,); out: (padded lengths
+    (nlists, n), group numbers (n,)), numpy uint32."""
+    import numpy as np
+    lengths = np.ascontiguousarray(np.atleast_2d(lengths), np.uint32)
+    types = np.ascontiguousarray(types, np.uint32)
+    nl, n = lengths.shape
+    padded = np.zeros((nl, n), np.uint32)
+    group = np.zeros(n, np.uint32)
+    _check(LIB.rss_group_k_lists(n, nl, lengths.ctypes.data, types.ctypes.data, k, padded.ctypes.data,
+                                 group.ctypes.data))
     return padded, group
 
 

@@ -72,22 +72,37 @@ def _dev(a: np.ndarray, device):
     return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)
 
 
+def padded_lengths(adj: dict, k: int) -> dict:
+    """Alg. 1's padded list lengths per edge type (T, T2): each vertex type's
+    vertices grouped k at a time over the vector of their list lengths, list
+    types in sorted order of the neighbour type (`rss_group_k_lists`)."""
+    out = {}
+    for t in sorted({p[0] for p in adj}):
+        mine = sorted(p for p in adj if p[0] == t)
+        lengths = np.array([[len(a) for a in adj[p]] for p in mine], np.uint32)
+        padded, _ = fss.rss_group_k_lists(lengths, np.zeros(lengths.shape[1], np.uint32), k)
+        for row, p in enumerate(mine):
+            out[p] = padded[row]
+    return out
+
+
 def encode_graph(n: dict, domains: dict, shares: dict, adj: dict, slots: dict, k: int, split_keys=(1001, 1002),
                  counter: int = 4, device=None) -> EncodedGraph:
     """The data owner's upload: the one-hot RSS records of IDs and attributes
     (`shares`: {("id", T) | ("attr", T, name): (3, n_T, words) uint32}) moved
     to the device, and Alg. 1 for every edge type (T, T2) of `adj` (lists of
-    neighbour IDs per vertex of T): lengths grouped k at a time
-    (`rss_group_k`), true IDs at the owner's slots (`slots[(T, T2)]`, flat in
-    adjacency order), one-hot records split into RSS with the PRF
-    (`rss_enc_posting_lists`)."""
+    neighbour IDs per vertex of T): each vertex type's vertices grouped k at a
+    time over the vector of their list lengths (`rss_group_k_lists`), true
+    IDs at the owner's slots (`slots[(T, T2)]`, flat in adjacency order),
+    one-hot records split into RSS with the PRF (`rss_enc_posting_lists`)."""
     dev = device or torch.device("cuda")
     eg = EncodedGraph(dict(n), dict(domains))
     for key, sh in shares.items():
         eg.shares[key] = [_dev(sh[j].ravel(), dev) for j in range(3)]
+    padded_of = padded_lengths(adj, k)
     for (t, t2), lists in sorted(adj.items()):
         lengths = np.array([len(a) for a in lists], np.uint32)
-        padded, _ = fss.rss_group_k(lengths, np.zeros(lengths.size, np.uint32), k)
+        padded = padded_of[(t, t2)]
         off = np.concatenate([[0], np.cumsum(padded, dtype=np.uint64)]).astype(np.uint32)
         adj_off = np.concatenate([[0], np.cumsum(lengths, dtype=np.uint64)]).astype(np.uint32)
         flat = np.concatenate([np.asarray(a, np.uint32) for a in lists]) if lengths.sum() else np.zeros(1, np.uint32)

@@ -30,11 +30,10 @@ def lib():
 
 def _gpu_graph(lib, tg, shares, slot_seed):
     fss, secmatch = lib
-    slots = {}
-    for e, ((t, t2), lists) in enumerate(sorted(tg.adj.items())):
-        lengths = np.array([len(a) for a in lists], np.uint32)
-        padded, _ = fss.rss_group_k(lengths, np.zeros(lengths.size, np.uint32), K)
-        slots[(t, t2)] = synth.posting_slots(slot_seed + e, lengths, padded)
+    padded = secmatch.padded_lengths(tg.adj, K)
+    slots = {pair: synth.posting_slots(slot_seed + e, np.array([len(a) for a in tg.adj[pair]], np.uint32),
+                                       padded[pair])
+             for e, pair in enumerate(sorted(tg.adj))}
     domains = {(t, name): dom for t, d in tg.attrs.items() for name, (_, dom) in d.items()}
     return secmatch.encode_graph(tg.n, domains, shares, tg.adj, slots, K, device=DEV)
 
