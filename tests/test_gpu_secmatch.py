@@ -86,3 +86,18 @@ def test_fig1_through_the_paper_protocol(lib):
     joined = osm.join_on_first(paths[0], paths[1], "UPC", "UPC")
     got = {tuple(names[t][v] for t, v in zip("UPCPC", r)) for r in joined}
     assert got == {("U1", "P1", "C1", "P3", "C2"), ("U1", "P2", "C1", "P3", "C2")}
+
+
+def test_sec_match_empty_start_and_empty_groups(lib):
+    """No vertex matches the first target: no chain and no secAccess call;
+    a query over a graph where some kept vertices have no neighbours of the
+    next type: their groups are empty and take no randomness, as in the
+    oracle."""
+    tg = synth.typed_graph(3, N, DOMAINS, DEGREES)
+    q = synth.TypedQuery(9, [T("U", "city", "range", lo=2, hi=2), T("P", "age", "range", lo=0, hi=64)])
+    assert _both(lib, tg, q, 3) == set()
+    sparse = synth.typed_graph(4, N, DOMAINS, {("U", "P"): 1, ("P", "C"): 1, ("P", "P"): 1})
+    assert any(len(a) == 0 for a in sparse.adj[("U", "P")])
+    q2 = synth.TypedQuery(10, [T("U", "city", "range", lo=0, hi=4), T("P", "age", "range", lo=0, hi=64),
+                               T("C", "industry", "range", lo=0, hi=4)])
+    assert _both(lib, sparse, q2, 4) == osm.brute_force(sparse, q2)
