@@ -1,5 +1,6 @@
 """Oracle for the paper's whole secure matching protocol, Alg. 2 (secMatch),
-over the paper's own encoding, for path queries V_1 -> V_2 -> ... -> V_q.
+over the paper's own encoding, for tree queries (a path V_1 -> V_2 -> ... ->
+V_q, or targets each hanging off an earlier one, as Fig. 1's).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/fss.py``).
 
@@ -14,24 +15,26 @@ Alg. 2 composed from the rows the oracle already pins:
   one-hot IDs and the one-hot value of the attribute the next predicate reads.
 
 Readings (Alg. 2 leaves these open):
-1. Hop i's candidates come in groups.  Hop 1 is one group, every vertex of
-   type T_1.  Every vertex kept at hop i < q gives one group at hop i + 1:
-   the neighbours secAccess returns for it.  secEval runs per group, and
-   secFetch once per group, so a kept vertex stays tied to the kept vertex
-   whose neighbour it is (its parent) -- the reorganisation into subgraphs at
-   the end of Alg. 2 needs that tie.
+1. Target i's candidates come in groups.  Target 0 has one group, every
+   vertex of type T_0.  Every vertex kept at target p gives one group at each
+   child target i of p (parent(i) = p): the neighbours secAccess returns for
+   it.  secEval runs per group, and secFetch once per group, so a kept vertex
+   stays tied to the kept vertex whose neighbour it is (its parent) -- the
+   reorganisation into subgraphs at the end of Alg. 2 needs that tie.
 2. Randomness: the re-shares take PRF counters in order from ``counter0``
    (secEval's re-share one, secAccess two); the shuffles take seed triples in
    order from ``seed0``, the s-th shuffle (secFetch's and secAccess's alike)
    the triple (seed0 + 3s, seed0 + 3s + 1, seed0 + 3s + 2).  Predicate i's
    token is made with pred = i.
-3. Order: hop by hop; within a hop, group by group in order of creation, each
-   group's secEval, re-share and secFetch; then, for each kept vertex in kept
-   order, its secAccess.  An empty group takes no randomness.
-4. The result is every chain of kept vertices, one per hop, each the parent of
-   the next, as the three shares of each hop's one-hot ID record.  The client
-   reconstructs the IDs and drops chains that visit a vertex twice (Def. 2
-   asks for a bijection).
+3. Order: target by target in index order; within a target, group by group in
+   order of creation: the group's secEval, re-share and secFetch, then, for
+   each child target in index order and each kept vertex in kept order, its
+   secAccess.  An empty group takes no randomness.  (For a path this is hop
+   by hop.)
+4. The result is every assignment of one kept vertex per target, each target's
+   vertex in the group its parent's vertex made, as the three shares of each
+   target's one-hot ID record.  The client reconstructs the IDs and drops
+   results that use a vertex twice (Def. 2 asks for a bijection).
 
 The encoded graph (``synth.typed_shares``: one-hot IDs and attribute values
 in binary RSS) and the posting lists' placement of true IDs
@@ -104,19 +107,21 @@ def _unpack(records: np.ndarray, nbits: int) -> np.ndarray:
 
 
 def sec_match(tg, enc: Encoded, query, tok_seed: int, prf_keys, counter0: int, seed0: int):
-    """Alg. 2 for a path query (readings in the module doc).  Returns
-    (chains, groups): chains is a list over results of per-hop lists of three
-    (wi,) share records; groups the per-hop groups (for tests)."""
+    """Alg. 2 for a tree query (readings in the module doc).  Returns
+    (results, groups): results is a list of per-target lists of three (wi,)
+    share records; groups the per-target groups (for tests)."""
     counter, step = counter0, 0
     tg_n = tg.n
-    t1 = query.targets[0]
-    hops = [[_Group(None, [enc.shares[("id", t1.vtype)][j] for j in range(3)],
-                    [enc.shares[("attr", t1.vtype, t1.attr)][j] for j in range(3)])]]
+    q = len(query.targets)
+    children = [[c for c in range(1, q) if query.parent(c) == i] for i in range(q)]
+    t0 = query.targets[0]
+    groups = [[] for _ in range(q)]
+    groups[0].append(_Group(None, [enc.shares[("id", t0.vtype)][j] for j in range(3)],
+                            [enc.shares[("attr", t0.vtype, t0.attr)][j] for j in range(3)]))
     for i, tgt in enumerate(query.targets):
         npos = tg.attrs[tgt.vtype][tgt.attr][1]
         keys, nb = rss.token(tgt.kind, npos, tok_seed, query.query_id, i, a=tgt.a, lo=tgt.lo, hi=tgt.hi)
-        nxt = []
-        for gi, g in enumerate(hops[i]):
+        for gi, g in enumerate(groups[i]):
             n = g.ids[0].shape[0]
             if n == 0:
                 g.kept_ids = [np.zeros((0, g.ids[0].shape[1]), np.uint32) for _ in range(3)]
@@ -133,46 +138,51 @@ def sec_match(tg, enc: Encoded, query, tok_seed: int, prf_keys, counter0: int, s
             _, kept = shuffle.fetch_case2(zb, rows, seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
             step += 1
             g.kept_ids = [kept[j][:, :wi] for j in range(3)]
-            if i + 1 == len(query.targets):
-                continue
-            nt = query.targets[i + 1]
-            pair = (tgt.vtype, nt.vtype)
-            attr_sh = [enc.shares[("attr", nt.vtype, nt.attr)][j] for j in range(3)]
-            for r in range(g.kept_ids[0].shape[0]):
-                idm = [_unpack(g.kept_ids[j][r:r + 1], tg_n[tgt.vtype])[0] for j in range(3)]
-                seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
-                ids_ne, vals_ne = access.sec_access_csr(idm, enc.post[pair], enc.off[pair], attr_sh, tg_n[nt.vtype],
-                                                        prf_keys, seeds, counter)
-                counter += 2
-                step += 1
-                nxt.append(_Group((i, gi, r), list(ids_ne), list(vals_ne)))
-        if i + 1 < len(query.targets):
-            hops.append(nxt)
-    return _chains(hops), hops
+            # secAccess of every kept vertex, for each child target
+            for c in children[i]:
+                nt = query.targets[c]
+                pair = (tgt.vtype, nt.vtype)
+                attr_sh = [enc.shares[("attr", nt.vtype, nt.attr)][j] for j in range(3)]
+                for r in range(g.kept_ids[0].shape[0]):
+                    idm = [_unpack(g.kept_ids[j][r:r + 1], tg_n[tgt.vtype])[0] for j in range(3)]
+                    seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+                    ids_ne, vals_ne = access.sec_access_csr(idm, enc.post[pair], enc.off[pair], attr_sh,
+                                                            tg_n[nt.vtype], prf_keys, seeds, counter)
+                    counter += 2
+                    step += 1
+                    groups[c].append(_Group((i, gi, r), list(ids_ne), list(vals_ne)))
+    return _results(groups, query), groups
 
 
-def _chains(hops):
-    """Every chain of kept vertices, one per hop, each the parent of the next."""
+def _results(groups, query):
+    """Every assignment of one kept vertex per target, each in the group its
+    parent's vertex made (targets in index order)."""
+    q = len(query.targets)
     out = []
 
-    def walk(i, gi, prefix):
-        g = hops[i][gi]
-        for r in range(g.kept_ids[0].shape[0]):
-            rec = [g.kept_ids[j][r] for j in range(3)]
-            if i + 1 == len(hops):
-                out.append(prefix + [rec])
-                continue
-            for gj, h in enumerate(hops[i + 1]):
-                if h.parent == (i, gi, r):
-                    walk(i + 1, gj, prefix + [rec])
+    def walk(i, chosen):
+        if i == q:
+            out.append([[groups[t][gi].kept_ids[j][r] for j in range(3)] for t, (gi, r) in enumerate(chosen)])
+            return
+        if i == 0:
+            cands = [0]
+        else:
+            p = query.parent(i)
+            cands = [gi for gi, g in enumerate(groups[i]) if g.parent == (p,) + chosen[p]]
+        for gi in cands:
+            g = groups[i][gi]
+            for r in range(g.kept_ids[0].shape[0] if g.kept_ids is not None else 0):
+                walk(i + 1, chosen + [(gi, r)])
 
-    walk(0, 0, [])
+    if groups[0]:
+        walk(0, [])
     return out
 
 
 def reconstruct(tg, query, chains) -> set:
-    """Client side: the vertex ID of every hop of every chain (the one set bit
-    of the XOR of the three shares), chains visiting a vertex twice dropped."""
+    """Client side: the vertex ID of every target of every result (the one
+    set bit of the XOR of the three shares), results using a vertex twice
+    dropped."""
     out = set()
     for ch in chains:
         ids = []
@@ -188,15 +198,22 @@ def reconstruct(tg, query, chains) -> set:
 
 
 def brute_force(tg, query) -> set:
-    """Plaintext matching (Def. 2) of a path query over the typed graph: every
-    chain v_1, ..., v_q with v_i of type T_i, its predicate holding on v_i's
-    attribute, v_{i+1} a neighbour of v_i, and no vertex visited twice."""
+    """Plaintext matching (Def. 2) of a tree query over the typed graph: every
+    assignment v_0, ..., v_{q-1} with v_i of type T_i, its predicate holding on
+    v_i's attribute, v_i a neighbour of v_{parent(i)}, and no vertex used
+    twice."""
     t = query.targets
     ok = [[v for v in range(tg.n[x.vtype]) if x.holds(tg.attrs[x.vtype][x.attr][0][v])] for x in t]
+    nbrs = {pair: [set(a.tolist()) for a in lists] for pair, lists in tg.adj.items()}
+
+    def linked(i, combo):
+        p = query.parent(i)
+        lists = nbrs.get((t[p].vtype, t[i].vtype))
+        return lists is not None and combo[i] in lists[combo[p]]
+
     out = set()
     for combo in itertools.product(*ok):
-        if any(combo[i + 1] not in set(tg.adj[(t[i].vtype, t[i + 1].vtype)][combo[i]].tolist())
-               for i in range(len(t) - 1)):
+        if not all(linked(i, combo) for i in range(1, len(t))):
             continue
         verts = [(x.vtype, v) for x, v in zip(t, combo)]
         if len(set(verts)) == len(verts):

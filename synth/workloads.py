@@ -425,10 +425,17 @@ class TypedTarget:
 
 @dataclass
 class TypedQuery:
-    """A path query V_1 -> V_2 -> ... over a typed graph: target i + 1 is a
-    neighbour (of its type) of target i."""
+    """A tree query over a typed graph: target i > 0 is a neighbour (of its
+    type) of target parents[i] < i; parents None is the path V_1 -> V_2 ->
+    ... (target i's parent is i - 1)."""
     query_id: int
     targets: list
+    parents: list = None
+
+    def parent(self, i: int):
+        if i == 0:
+            return None
+        return i - 1 if self.parents is None else self.parents[i]
 
 
 def typed_graph(seed: int, n: dict, domains: dict, degrees: dict) -> TypedGraph:

@@ -75,3 +75,41 @@ def test_fig1_through_the_paper_protocol():
     joined = secmatch.join_on_first(paths[0], paths[1], "UPC", "UPC")
     got = {tuple(nm(t, v) for t, v in zip("UPCPC", r)) for r in joined}
     assert got == {("U1", "P1", "C1", "P3", "C2"), ("U1", "P2", "C1", "P3", "C2")}
+
+
+TREES = [
+    # a star: U with two P branches
+    synth.TypedQuery(41, [T("U", "city", "range", lo=0, hi=3), T("P", "age", "range", lo=0, hi=40),
+                          T("P", "level", "range", lo=2, hi=8)], parents=[None, 0, 0]),
+    # Fig. 1's shape: U -> P -> C and U -> P -> C
+    synth.TypedQuery(42, [T("U", "city", "range", lo=0, hi=4), T("P", "age", "range", lo=10, hi=60),
+                          T("C", "industry", "range", lo=0, hi=2), T("P", "level", "range", lo=0, hi=6),
+                          T("C", "industry", "range", lo=2, hi=4)], parents=[None, 0, 1, 0, 3]),
+    # a branch below the first hop
+    synth.TypedQuery(43, [T("P", "level", "range", lo=0, hi=6), T("C", "industry", "range", lo=0, hi=3),
+                          T("P", "age", "range", lo=0, hi=50)], parents=[None, 0, 0]),
+]
+
+
+@pytest.mark.parametrize("gseed", [1, 2])
+@pytest.mark.parametrize("qi", range(len(TREES)))
+def test_sec_match_trees_equal_plaintext_matching(gseed, qi):
+    tg = synth.typed_graph(gseed, N, DOMAINS, DEGREES)
+    q = TREES[qi]
+    want = secmatch.brute_force(tg, q)
+    assert _run(tg, q, gseed) == want
+    assert gseed == 2 or len(want) > 0
+
+
+def test_fig1_tree_natively():
+    """Sec. II-A's query as the paper writes its token (Eq. enc_subg): U in
+    Harbin with two branches, P aged 30..40 -> C in software and P aged 30..40
+    -> C in Internet, in one run of Alg. 2: exactly g1 and g2."""
+    tg, names = fig1_typed()
+    q = synth.TypedQuery(13, [T("U", "city", "eq", a=1), T("P", "age", "range", lo=30, hi=41),
+                              T("C", "industry", "eq", a=1), T("P", "age", "range", lo=30, hi=41),
+                              T("C", "industry", "eq", a=2)], parents=[None, 0, 1, 0, 3])
+    got = _run(tg, q, 13)
+    assert got == secmatch.brute_force(tg, q)
+    assert {tuple(names[t][v] for t, v in zip("UPCPC", r)) for r in got} == \
+        {("U1", "P1", "C1", "P3", "C2"), ("U1", "P2", "C1", "P3", "C2")}
