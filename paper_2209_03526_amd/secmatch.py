@@ -1,6 +1,7 @@
 """The paper's whole secure matching protocol, Alg. 2 (secMatch), over its own
-encoding, on the GPU: for a path query V_1 -> V_2 -> ... -> V_q over a typed
-graph, hop by hop
+encoding, on the GPU: for a tree query over a typed graph (a path V_1 -> V_2
+-> ... -> V_q, or targets each hanging off an earlier one, as Fig. 1's),
+target by target
 
   secEval (Alg. 3: full-domain evaluations of the replicated token,
            `fss_eval_all`; each server's two terms, `rss_sec_eval_records`),
@@ -16,16 +17,19 @@ library's kernels; this module only orders the calls and reads the counts
 that the opens of secFetch and secAccess reveal (one synchronisation per
 open, as in the protocol, where the count decides the next step's size).
 
-Readings where Alg. 2 leaves the order open: hop i + 1's candidates are
-grouped by the kept vertex whose neighbours they are, and secFetch runs once
-per group, so each kept vertex keeps its parent (the final reorganisation into
-subgraphs needs that tie); re-shares take PRF counters in order from
-`counter0` (secEval's re-share one, secAccess two); the s-th shuffle
-(secFetch's and secAccess's alike) takes the seeds (seed0 + 3s, +1, +2);
-predicate i's token is made with pred = i; an empty group takes no
-randomness.  The result is every chain of kept vertices, one per hop, each
-the parent of the next, as the three shares of each hop's one-hot ID record;
-the client reconstructs and drops chains that visit a vertex twice.
+Readings where Alg. 2 leaves the order open: a target's candidates are
+grouped by the kept vertex (of its parent target) whose neighbours they are,
+and secFetch runs once per group, so each kept vertex keeps its parent (the
+final reorganisation into subgraphs needs that tie); targets run in index
+order, and within a target each group's secEval, re-share and secFetch come
+before the secAccess calls of its kept vertices for each child target;
+re-shares take PRF counters in order from `counter0` (secEval's re-share one,
+secAccess two); the s-th shuffle (secFetch's and secAccess's alike) takes the
+seeds (seed0 + 3s, +1, +2); predicate i's token is made with pred = i; an
+empty group takes no randomness.  A result is one kept vertex per target,
+each in the group its parent's vertex made, as the three shares of each
+target's one-hot ID record; the client reconstructs and drops results that
+use a vertex twice.
 """
 from __future__ import annotations
 
@@ -132,14 +136,18 @@ class _Group:
 
 
 def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, seed0: int, device=None):
-    """Alg. 2 for a path query (``query.targets``: vertex type, attribute,
-    predicate per hop; readings in the module doc).  Returns the chains, each
-    a list over hops of the three shares (numpy uint32 records) of the hop's
-    one-hot ID."""
+    """Alg. 2 for a tree query (``query.targets``: vertex type, attribute,
+    predicate per target; ``query.parent(i)``: the target that target i hangs
+    off, i - 1 for a path; readings in the module doc).  Returns the results,
+    each a list over targets of the three shares (numpy uint32 records) of the
+    target's one-hot ID."""
     dev = device or torch.device("cuda")
     counter, step = counter0, 0
-    t1 = query.targets[0]
-    hops = [[_Group(None, eg.n[t1.vtype], eg.shares[("id", t1.vtype)], eg.shares[("attr", t1.vtype, t1.attr)])]]
+    q = len(query.targets)
+    children = [[c for c in range(1, q) if query.parent(c) == i] for i in range(q)]
+    t0 = query.targets[0]
+    groups = [[] for _ in range(q)]
+    groups[0].append(_Group(None, eg.n[t0.vtype], eg.shares[("id", t0.vtype)], eg.shares[("attr", t0.vtype, t0.attr)]))
     zero3 = torch.zeros(3, dtype=torch.int32, device=dev)
     for i, tgt in enumerate(query.targets):
         npos = eg.domains[(tgt.vtype, tgt.attr)]
@@ -153,8 +161,7 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
                 ev[(party, rep)] = torch.empty(words(npos), dtype=torch.int32, device=dev)
                 fss.fss_eval_all(party, kb, rep, npos, ev[(party, rep)])
         wi, wv = words(eg.n[tgt.vtype]), words(npos)
-        nxt = []
-        for gi, g in enumerate(hops[i]):
+        for gi, g in enumerate(groups[i]):
             if g.n == 0:
                 continue
             # secEval, then the re-share into RSS
@@ -176,60 +183,59 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
             step += 1
             g.nkept = int(cnt.item())            # the open reveals how many candidates match
             del work, table
-            if i + 1 == len(query.targets):
-                continue
-            nt = query.targets[i + 1]
-            pair = (tgt.vtype, nt.vtype)
-            wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
-            lmax = eg.lmax[pair]
-            for r in range(g.nkept):
-                idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
-                ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
-                vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
-                rows = torch.empty(lmax, dtype=torch.int32, device=dev)
-                c2 = torch.zeros(1, dtype=torch.int32, device=dev)
-                seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
-                work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax, eg.post[pair],
-                                          wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys, counter, seeds,
-                                          ids3, vals3, rows, c2)
-                counter += 2
-                step += 1
-                m = int(c2.item())               # the validity open reveals the list's true length
-                del work
-                nxt.append(_Group((i, gi, r), m, ids3, vals3))
-        if i + 1 < len(query.targets):
-            hops.append(nxt)
-    return _chains(hops, query, eg)
+            # secAccess of every kept vertex, for each child target
+            for c in children[i]:
+                nt = query.targets[c]
+                pair = (tgt.vtype, nt.vtype)
+                wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
+                lmax = eg.lmax[pair]
+                for r in range(g.nkept):
+                    idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
+                    ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
+                    vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
+                    rows = torch.empty(lmax, dtype=torch.int32, device=dev)
+                    c2 = torch.zeros(1, dtype=torch.int32, device=dev)
+                    seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+                    work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax,
+                                              eg.post[pair], wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys,
+                                              counter, seeds, ids3, vals3, rows, c2)
+                    counter += 2
+                    step += 1
+                    m = int(c2.item())           # the validity open reveals the list's true length
+                    del work
+                    groups[c].append(_Group((i, gi, r), m, ids3, vals3))
+    return _results(groups, query, eg)
 
 
-def _chains(hops, query, eg):
+def _results(groups, query, eg):
+    """Every assignment of one kept vertex per target, each in the group its
+    parent's vertex made (targets in index order), as host share records."""
+    q = len(query.targets)
     out = []
     host = {}
 
     def kept_ids(i, gi):
         if (i, gi) not in host:
-            g = hops[i][gi]
+            g = groups[i][gi]
             t = query.targets[i]
             wi, wv = words(eg.n[t.vtype]), words(eg.domains[(t.vtype, t.attr)])
-            arr = [g.kept[j][:g.nkept * (wi + wv)].cpu().numpy().view(np.uint32).reshape(g.nkept, wi + wv)[:, :wi]
-                   for j in range(3)] if g.nkept else [np.zeros((0, wi), np.uint32)] * 3
-            host[(i, gi)] = arr
+            host[(i, gi)] = [g.kept[j][:g.nkept * (wi + wv)].cpu().numpy().view(np.uint32).reshape(
+                g.nkept, wi + wv)[:, :wi] for j in range(3)]
         return host[(i, gi)]
 
-    def walk(i, gi, prefix):
-        g = hops[i][gi]
-        if g.nkept == 0:
+    def walk(i, chosen):
+        if i == q:
+            out.append([[kept_ids(t, gi)[j][r] for j in range(3)] for t, (gi, r) in enumerate(chosen)])
             return
-        ids = kept_ids(i, gi)
-        for r in range(g.nkept):
-            rec = [ids[j][r] for j in range(3)]
-            if i + 1 == len(hops):
-                out.append(prefix + [rec])
-                continue
-            for gj, h in enumerate(hops[i + 1]):
-                if h.parent == (i, gi, r):
-                    walk(i + 1, gj, prefix + [rec])
+        if i == 0:
+            cands = [0]
+        else:
+            p = query.parent(i)
+            cands = [gi for gi, g in enumerate(groups[i]) if g.parent == (p,) + chosen[p]]
+        for gi in cands:
+            for r in range(groups[i][gi].nkept):
+                walk(i + 1, chosen + [(gi, r)])
 
-    if hops and hops[0]:
-        walk(0, 0, [])
+    if groups[0]:
+        walk(0, [])
     return out

@@ -12,7 +12,7 @@ import synth
 from fixtures import fig1_typed
 from gpu_util import DEV
 from oracle import secmatch as osm
-from test_oracle_secmatch import DEGREES, DOMAINS, N, QUERIES
+from test_oracle_secmatch import DEGREES, DOMAINS, N, QUERIES, TREES
 
 pytestmark = pytest.mark.gpu
 T = synth.TypedTarget
@@ -101,3 +101,23 @@ def test_sec_match_empty_start_and_empty_groups(lib):
     q2 = synth.TypedQuery(10, [T("U", "city", "range", lo=0, hi=4), T("P", "age", "range", lo=0, hi=64),
                                T("C", "industry", "range", lo=0, hi=4)])
     assert _both(lib, sparse, q2, 4) == osm.brute_force(sparse, q2)
+
+
+@pytest.mark.parametrize("gseed", [1, 2])
+@pytest.mark.parametrize("qi", range(len(TREES)))
+def test_sec_match_trees_equal_oracle(lib, gseed, qi):
+    tg = synth.typed_graph(gseed, N, DOMAINS, DEGREES)
+    q = TREES[qi]
+    print(f"graph {gseed} tree {qi}", flush=True)
+    assert _both(lib, tg, q, gseed) == osm.brute_force(tg, q)
+
+
+def test_fig1_tree_natively(lib):
+    """Sec. II-A's query as one two-branch tree through Alg. 2 on the GPU."""
+    tg, names = fig1_typed()
+    q = synth.TypedQuery(13, [T("U", "city", "eq", a=1), T("P", "age", "range", lo=30, hi=41),
+                              T("C", "industry", "eq", a=1), T("P", "age", "range", lo=30, hi=41),
+                              T("C", "industry", "eq", a=2)], parents=[None, 0, 1, 0, 3])
+    got = _both(lib, tg, q, 13)
+    assert {tuple(names[t][v] for t, v in zip("UPCPC", r)) for r in got} == \
+        {("U1", "P1", "C1", "P3", "C2"), ("U1", "P2", "C1", "P3", "C2")}
