@@ -221,6 +221,33 @@ def brute_force(tg, query) -> set:
     return out
 
 
+def plaintext_match(tg, query) -> set:
+    """The same matching as ``brute_force``, found by walking the adjacency
+    from each root candidate (target by target in index order, each target's
+    vertex among its parent's neighbours) instead of trying every tuple: for
+    typed graphs too large for the product.  Equal to ``brute_force`` on small
+    graphs (pinned in the tests)."""
+    t = query.targets
+    ok = [{v for v in range(tg.n[x.vtype]) if x.holds(tg.attrs[x.vtype][x.attr][0][v])} for x in t]
+    out = set()
+
+    def walk(i, chosen, used):
+        if i == len(t):
+            out.add(tuple(chosen))
+            return
+        p = query.parent(i)
+        lists = tg.adj.get((t[p].vtype, t[i].vtype))
+        if lists is None:
+            return
+        for v in lists[chosen[p]].tolist():
+            if v in ok[i] and (t[i].vtype, v) not in used:
+                walk(i + 1, chosen + [v], used | {(t[i].vtype, v)})
+
+    for r in sorted(ok[0]):
+        walk(1, [r], {(t[0].vtype, r)})
+    return out
+
+
 def join_on_first(a: set, b: set, types_a, types_b) -> set:
     """Client-side join of two path results that share their first query
     vertex (a tree query split into root-to-leaf paths, as Fig. 1's): every

@@ -113,3 +113,12 @@ def test_fig1_tree_natively():
     assert got == secmatch.brute_force(tg, q)
     assert {tuple(names[t][v] for t, v in zip("UPCPC", r)) for r in got} == \
         {("U1", "P1", "C1", "P3", "C2"), ("U1", "P2", "C1", "P3", "C2")}
+
+
+@pytest.mark.parametrize("gseed", [1, 2, 5])
+def test_plaintext_match_equals_brute_force(gseed):
+    """The adjacency walk used at larger sizes finds exactly the tuples the
+    product enumeration finds, for paths and trees."""
+    tg = synth.typed_graph(gseed, N, DOMAINS, DEGREES)
+    for q in QUERIES + TREES:
+        assert secmatch.plaintext_match(tg, q) == secmatch.brute_force(tg, q)
