@@ -143,3 +143,20 @@ def test_largest_query_graph(fss):
     fss.match_query_batch([plan], fss.Queue(64))
     torch.cuda.synchronize()
     _compare(plan_outputs(plan, q, g), want, "max query, batched")
+
+
+@pytest.mark.parametrize("qseed", range(0, 24, 3))
+def test_random_query_graphs(fss, qseed):
+    """Random valid query graphs (spanning trees with extra and reversed
+    edges, random predicates): shares equal the oracle's, both parties at once
+    and one party in rounds; the reconstruction equals brute force."""
+    from test_oracle_match import random_query
+    q = random_query(qseed)
+    g = synth.tiny_graph(qseed + 500, n_vertices=8, n_edges=28, label_range=3)
+    seed = 1200 + qseed
+    shares = column_shares(g, seed)
+    masks = synth.pred_masks(seed, q, g)
+    got = plan_outputs(run_query_gpu(fss, g, q, shares, masks, seed), q, g)
+    _compare(got, omatch.run_plan(32, seed, g, q, shares, masks), f"random query {qseed}")
+    assert omatch.results_from_bits(g, q, omatch.reconstruct(got, g.n_edges)) == omatch.brute_force(g, q)
+    _check_parties(fss, g, q, seed)

@@ -171,3 +171,37 @@ def test_sampled_rows_equal_full_plan_shapes(qi):
     for j, o in enumerate(full):
         for b in range(2):
             np.testing.assert_array_equal(match.fss.unpack_bits(o[b], g.n_edges)[rows], samp[j, b])
+
+
+def random_query(seed: int):
+    """A random valid query graph (Def. 2): 2-4 vertices, a random spanning
+    tree plus extra edges (cycles, reversed pairs), 0-4 predicates on vertices
+    and edges."""
+    rng = np.random.default_rng(seed)
+    nv = int(rng.integers(2, 5))
+    edges = []
+    for v in range(1, nv):
+        u = int(rng.integers(0, v))
+        edges.append((u, v) if rng.random() < 0.5 else (v, u))
+    for _ in range(int(rng.integers(0, 3))):
+        a, b = (int(x) for x in rng.choice(nv, 2, replace=False))
+        if (a, b) not in edges:
+            edges.append((a, b))
+    preds = []
+    for _ in range(int(rng.integers(0, 5))):
+        t = int(rng.integers(0, nv + len(edges)))
+        if t < nv:
+            preds.append(P(t, "range", "attr", lo=int(rng.integers(0, 8)), hi=int(rng.integers(8, 17)))
+                         if rng.random() < 0.5 else P(t, "eq", "label", a=int(rng.integers(0, 3))))
+        else:
+            preds.append(P(t, "range", "weight", lo=int(rng.integers(0, 8)), hi=int(rng.integers(8, 17)))
+                         if rng.random() < 0.5 else P(t, "eq", "label", a=int(rng.integers(0, 3))))
+    return synth.Query(300 + seed, nv, preds, edges=edges)
+
+
+@pytest.mark.parametrize("qseed", range(24))
+def test_random_query_graphs_match_brute_force(qseed):
+    q = random_query(qseed)
+    match.check_query(q)
+    g = synth.tiny_graph(qseed + 500, n_vertices=8, n_edges=28, label_range=3)
+    assert _run(g, q, seed=qseed) == match.brute_force(g, q)
