@@ -517,6 +517,19 @@ int fss_set_tuning(uint32_t rows_per_thread, uint32_t wg_per_cu);
 int fss_get_tuning(uint32_t* rows_per_thread, uint32_t* wg_per_cu);
 int fss_set_keygen_tuning(uint32_t tile_mult);
 int fss_get_keygen_tuning(uint32_t* tile_mult);
+/* How the shuffle's permutations of tables above 1024 rows are made
+ * (process-wide); every method gives the same permutations (the stable
+ * argsort of Alg. 5's keys), so results never change.  perm_method:
+ *   0  radix pass on the run id, exact comparisons inside every run;
+ *   1  radix pass, sorting networks in the wavefront for runs of <= 128 rows;
+ *   2  (default) buckets of about 2^12 rows ordered in LDS, no sort library
+ *      (tables of at most 2^23 rows; larger ones take method 1);
+ *   3  buckets, exact comparisons inside every run;
+ *   4  buckets, every bucket ordered by comparing every pair (the path of a
+ *      bucket too large for LDS).
+ * EINVAL for a value above 4. */
+int rss_set_shuffle_tuning(uint32_t perm_method);
+int rss_get_shuffle_tuning(uint32_t* perm_method);
 
 /*
  * The paper's graph encoding with k-groups (Alg. 1) and secure neighbouring-

@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include <array>
+#include <atomic>
 #include <initializer_list>
 #include <map>
 #include <mutex>
@@ -49,6 +50,16 @@ unsigned slice_grid(uint64_t items) {
     if (g > (1u << 20)) g = 1u << 20;
     return (unsigned)g;
 }
+
+// How the permutations of tables above 1024 rows are made
+// (rss_set_shuffle_tuning); every method gives the same permutation.
+//   0: radix pass, exact comparisons in every run
+//   1: radix pass, sorting networks where they apply
+//   2: buckets (up to 2^23 rows, else method 1), sorting networks where they apply
+//   3: buckets, exact comparisons in every run
+//   4: buckets, every bucket ordered by comparing every pair
+enum { kPermRadixExact = 0, kPermRadix = 1, kPermBuckets = 2, kPermBucketsExact = 3, kPermBucketsPairs = 4 };
+std::atomic<uint32_t> g_perm_method{kPermBuckets};
 
 // Pair keys: ChaCha key words (seed mod 2^32, seed div 2^32, 6, 0, 0, 0, 0, 0).
 constexpr uint32_t kShuffleDomain = 6;
@@ -127,25 +138,23 @@ __global__ __launch_bounds__(1024) void k_perm_small(uint32_t n, SmallPerms J) {
 // their original order, so "equal key, earlier position" is "equal key,
 // smaller row" and the result is the full stable argsort.
 
-// starts[b] = first position of run b in the sorted keys (lower bound of run
-// id b by binary search), b = 0 .. 2^hb; starts[2^hb] = n.  A lower bound is
-// non-decreasing in b over any array, so the runs always partition [0, n):
-// the ranking below stays in bounds whatever the sort returned.
+// starts[b] = first position of run b in the sorted keys, b = 0 .. 2^hb, and
+// starts[2^hb] = n, in one coalesced pass: position i (0 <= i <= n, position n
+// counting as id 2^hb) writes the entries of the ids after its predecessor's
+// id up to its own.  Over sorted keys each entry is written once.  Whatever
+// the sort returned, every write stays in [0, 2^hb] and each thread's loop is
+// bounded by 2^hb + 1; the ranking clamps the starts to [0, n], so it stays in
+// bounds too.
 __global__ void k_run_starts(uint64_t n, uint32_t hb, const uint64_t* __restrict__ keys,
                              uint32_t* __restrict__ starts) {
-    const uint32_t nruns = 1u << hb;
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > nruns) return;
-    const uint32_t id_mask = nruns - 1u;
-    uint64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (((uint32_t)keys[mid] & id_mask) < b)
-            lo = mid + 1;
-        else
-            hi = mid;
+    const uint64_t nruns = 1ull << hb;
+    const uint64_t id_mask = nruns - 1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+        const uint64_t lo = i == 0 ? 0 : (keys[i - 1] & id_mask) + 1;
+        const uint64_t hi = i == n ? nruns : keys[i] & id_mask;
+        for (uint64_t b = lo; b <= hi; b++) starts[b] = (uint32_t)i;
     }
-    starts[b] = (uint32_t)lo;
 }
 
 // Broadcast of lane t's 64-bit value to the whole wavefront (t uniform).
@@ -155,18 +164,89 @@ __device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t t) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Lane l's copy of the value of lane l ^ J (every lane of the wavefront
+// active): DPP quad permutations for J = 1, 2, a swizzle inside each half of
+// the wavefront for J = 4, 8, 16, a permute across the halves for J = 32.
+template <int J>
+__device__ __forceinline__ uint32_t from_lane_xor(uint32_t v, uint32_t lane) {
+    if constexpr (J == 1)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+    else if constexpr (J == 2)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+    else if constexpr (J < 32)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));     // and 31, or 0, xor J
+    else
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((lane ^ 32u) << 2), (int)v);
+}
+
+// Bitonic sorting network over the wavefront, element i in lane i (register
+// a) or lane i - 64 (register b).  In the stage (K, J) element i meets element
+// i ^ J and keeps the smaller value when bits J and K of i agree, the larger
+// one otherwise; after the stages K = 2, 4, .., N (J = K/2 .. 1 in each) the N
+// elements are in ascending order.
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_stage(uint32_t v, uint32_t i, uint32_t lane) {
+    const uint32_t o = from_lane_xor<J>(v, lane);
+    return (((i / J) ^ (i / K)) & 1u) ? max(o, v) : min(o, v);
+}
+
+template <int K, int J>
+__device__ __forceinline__ void merge64(uint32_t& a, uint32_t lane) {
+    a = bitonic_stage<K, J>(a, lane, lane);
+    if constexpr (J > 1) merge64<K, J / 2>(a, lane);
+}
+
+template <int K>
+__device__ __forceinline__ void sort64(uint32_t& a, uint32_t lane) {
+    merge64<K, K / 2>(a, lane);
+    if constexpr (K < 64) sort64<2 * K>(a, lane);
+}
+
+template <int K, int J>
+__device__ __forceinline__ void merge128(uint32_t& a, uint32_t& b, uint32_t lane) {
+    if constexpr (J == 64) {             // K = 128: the partners share a lane
+        const uint32_t lo = min(a, b), hi = max(a, b);
+        a = lo, b = hi;
+    } else {
+        a = bitonic_stage<K, J>(a, lane, lane);
+        b = bitonic_stage<K, J>(b, lane + 64u, lane);
+    }
+    if constexpr (J > 1) merge128<K, J / 2>(a, b, lane);
+}
+
+template <int K>
+__device__ __forceinline__ void sort128(uint32_t& a, uint32_t& b, uint32_t lane) {
+    merge128<K, K / 2>(a, b, lane);
+    if constexpr (K < 128) sort128<2 * K>(a, b, lane);
+}
+
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+
 // One wavefront per run: row e of the run goes to position start + rank(e),
 // rank = number of rows of the run with a smaller key, or an equal key at an
-// earlier position.  The run's keys are taken 64 at a time into the lanes and
-// broadcast with readlane, so any run length is ordered exactly (the cost
-// grows as the square of the length; the runs of uniform keys are short).
-// All keys of a run share their id bits (bits 0 .. hb-1 of the rotated key);
-// when the run has at most 2^hb rows those bits are replaced by the row's
-// position in the run, which makes every key of the run distinct and ordered
-// as (key, position), so one compare per row does.
+// earlier position (inside a run the radix pass kept the original row order).
 // With `inverse` the kernel writes the inverse permutation instead:
 // out[row] = its position.
-__global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, uint32_t inverse, const uint32_t* __restrict__ starts,
+//
+// Sorting-network path (runs of at most 128 rows, when `fast`): each row
+// becomes the 32-bit value (the 25 key bits after the run id) << 7 | e, with
+// 2^32 - 1 for the lanes past the run; the network sorts the run in the lanes
+// (64 or 128 values), and e is read back from the low bits.  When no two
+// neighbours in that order share their 25 key bits, it is the order of the
+// full keys.  Otherwise -- and for longer runs -- the run takes the exact
+// path.
+//
+// Exact path: the run's keys are taken 64 at a time into the lanes and
+// broadcast with readlane, so any run length is ordered exactly (the cost
+// grows as the square of the length).  All keys of a run share their id bits
+// (bits 0 .. hb-1 of the rotated key); when the run has at most 2^hb rows
+// those bits are replaced by the row's position in the run, which makes every
+// key of the run distinct and ordered as (key, position), so one compare per
+// row does.
+__global__ __launch_bounds__(256) void k_rank_runs(uint64_t n, uint32_t hb, uint32_t inverse, uint32_t fast,
+                                                   const uint32_t* __restrict__ starts,
                                                    const uint64_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ rows, uint32_t* __restrict__ perm) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -176,8 +256,56 @@ __global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, uint32_t inverse
     // the run number is the same on every lane of the wavefront; saying so
     // keeps the run bounds and loop counters in scalar registers
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t n32 = (uint32_t)n;
     for (uint32_t b = blockIdx.x * (blockDim.x >> 6) + wave; b < nruns; b += waves) {
-        const uint32_t s = starts[b], m = starts[b + 1] - s;
+        const uint32_t s = min(starts[b], n32), e_end = min(starts[b + 1], n32);
+        const uint32_t m = e_end > s ? e_end - s : 0u;
+        if (m == 0) continue;
+        bool exact = !fast || m > 128;
+        if (!exact) {
+            const uint32_t pb = lane + 64u;
+            uint32_t a = 0xFFFFFFFFu, bb = 0xFFFFFFFFu, ra = 0u, rb = 0u;
+            if (lane < m) {
+                a = ((uint32_t)(keys[s + lane] >> 39) << 7) | lane;
+                ra = rows[s + lane];
+            }
+            if (pb < m) {
+                bb = ((uint32_t)(keys[s + pb] >> 39) << 7) | pb;
+                rb = rows[s + pb];
+            }
+            if (m <= 64)
+                sort64<2>(a, lane);
+            else
+                sort128<2>(a, bb, lane);
+            // neighbours in sorted order: position lane - 1 for register a
+            // (lane 0 has none), and for register b the last of a at lane 0
+            const uint32_t prev_a = lane_read(a, (lane - 1u) & 63u);
+            const uint32_t prev_b_lane = lane_read(bb, (lane - 1u) & 63u);
+            const uint32_t prev_b = lane == 0 ? prev_a : prev_b_lane;
+            const bool tie = (lane >= 1 && lane < m && (a >> 7) == (prev_a >> 7)) ||
+                             (pb < m && (bb >> 7) == (prev_b >> 7));
+            if (__ballot(tie) != 0) {
+                exact = true;
+            } else {
+                const uint32_t qa = a & 127u, qb = bb & 127u;
+                const uint32_t ya = lane_read(ra, qa & 63u), za = lane_read(rb, qa & 63u);
+                const uint32_t yb = lane_read(ra, qb & 63u), zb = lane_read(rb, qb & 63u);
+                const uint32_t row_a = qa < 64 ? ya : za, row_b = qb < 64 ? yb : zb;
+                if (lane < m) {
+                    if (!inverse)
+                        perm[s + lane] = row_a;
+                    else if (row_a < n32)
+                        perm[row_a] = s + lane;
+                }
+                if (pb < m) {
+                    if (!inverse)
+                        perm[s + pb] = row_b;
+                    else if (row_b < n32)
+                        perm[row_b] = s + pb;
+                }
+            }
+        }
+        if (!exact) continue;
         const bool distinct = m <= nruns;
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const uint32_t e = c0 + lane;
@@ -200,11 +328,330 @@ __global__ __launch_bounds__(256) void k_rank_runs(uint32_t hb, uint32_t inverse
                 }
             }
             if (has) {
-                if (inverse)
-                    perm[rows[s + e]] = s + rank;
-                else
-                    perm[s + rank] = rows[s + e];
+                const uint32_t row = rows[s + e];
+                if (!inverse)
+                    perm[s + rank] = row;
+                else if (row < n32)
+                    perm[row] = s + rank;
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- permutations by buckets
+//
+// Tables of 1025 .. 2^23 rows take the stable argsort of their keys in four
+// launches and no sort library: with hb run-id bits as above, the top
+// d1 = ceil(log2 n) - 12 key bits (at least 0) name the row's bucket (2^11 ..
+// 2^12 rows on average), the next d2 = hb - d1 bits its run in the bucket.
+//   count: each workgroup makes the keys of 8192 rows and counts them per
+//          bucket in LDS: counts[bucket][workgroup];
+//   scan:  per bucket, the workgroups' exclusive offsets and the total; then
+//          the buckets' starts;
+//   place: the workgroups make their keys again, group them by bucket in
+//          LDS and store each row (key and row number) in its bucket's range
+//          (the order inside a bucket follows LDS counters: arbitrary);
+//   rank:  one workgroup per bucket loads it into LDS, groups it by run (LDS
+//          counters again), and orders each run by (key, row number) as the
+//          radix path's ranking does: a sorting network over the wavefront
+//          for runs of at most 128 rows whose leading 25 bits after the run
+//          id differ, exact comparisons otherwise.  A bucket of more than
+//          kBucketCap rows (about 50 standard deviations above the mean for
+//          keys drawn by ChaCha12) is ordered by comparing every pair.
+// Row r's position is its bucket's start + its run's start in the bucket +
+// its rank in the run, and (key, row number) orders bucket, run and rank:
+// the result is the stable argsort whatever order the placing left.
+constexpr uint32_t kChunkRows = 8192;        // rows per counting / placing workgroup
+constexpr uint32_t kMaxBuckets = 2048;       // 2^(23 - 12)
+constexpr uint32_t kBucketCap = 7168;        // rows of a bucket held in LDS
+constexpr uint64_t kBucketMaxRows = 1ull << 23;
+
+__device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t d1) {
+    return d1 ? (uint32_t)(key >> (64 - d1)) : 0u;
+}
+
+// The keys of the block's rows, two per lane (all lanes of each quad active):
+// f(row, key) for every row below n.
+template <class F>
+__device__ __forceinline__ void chunk_keys(ChachaKey pk, uint32_t p, uint64_t n, F f) {
+    const uint64_t q0 = (uint64_t)blockIdx.x * (kChunkRows / 8);
+    for (uint32_t t = threadIdx.x; t < kChunkRows / 2; t += blockDim.x) {
+        const uint64_t q = q0 + (t >> 2);
+        const uint4 o = chacha_quad(pk, (uint32_t)q, 0u, 16u + p, 0u);
+        const uint64_t r0 = q * 8 + 2 * (t & 3);
+        if (r0 < n) f(r0, (uint64_t)o.x | ((uint64_t)o.y << 32));
+        if (r0 + 1 < n) f(r0 + 1, (uint64_t)o.z | ((uint64_t)o.w << 32));
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_perm_count(ChachaKey pk, uint32_t p, uint64_t n, uint32_t d1, uint32_t nblk,
+                                                     uint32_t* __restrict__ counts) {
+    __shared__ uint32_t hist[kMaxBuckets];
+    const uint32_t nb = 1u << d1;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    chunk_keys(pk, p, n, [&](uint64_t, uint64_t key) { atomicAdd(&hist[bucket_of(key, d1)], 1u); });
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) counts[(uint64_t)i * nblk + blockIdx.x] = hist[i];
+}
+
+// Exclusive scan of 256 values in LDS (blockDim.x = 256); returns this
+// thread's exclusive prefix, *total the sum.
+__device__ __forceinline__ uint32_t block_scan256(uint32_t v, uint32_t* sh, uint32_t* total) {
+    const uint32_t t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 256; d <<= 1) {
+        const uint32_t x = t >= d ? sh[t - d] : 0u;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    *total = sh[255];
+    return sh[t] - v;
+}
+
+// One workgroup (256 threads) per bucket: counts[bucket][w] becomes the
+// number of the bucket's rows in workgroups before w; totals[bucket] = all.
+__global__ __launch_bounds__(256) void k_bucket_offsets(uint32_t nblk, uint32_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ totals) {
+    __shared__ uint32_t sh[256];
+    uint32_t* c = counts + (uint64_t)blockIdx.x * nblk;
+    const uint32_t per = (nblk + 255) / 256;       // at most 4 (nblk <= 1024)
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t v[4] = {0, 0, 0, 0}, sum = 0;
+    for (uint32_t k = 0; k < per; k++) {
+        v[k] = b0 + k < nblk ? c[b0 + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t total = 0;
+    uint32_t run = block_scan256(sum, sh, &total);
+    for (uint32_t k = 0; k < per; k++) {
+        if (b0 + k < nblk) c[b0 + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+// One workgroup (256 threads): starts[b] = rows in buckets before b, b = 0 .. nb.
+__global__ __launch_bounds__(256) void k_bucket_starts(uint32_t nb, const uint32_t* __restrict__ totals,
+                                                       uint32_t* __restrict__ starts) {
+    __shared__ uint32_t sh[256];
+    const uint32_t per = (nb + 255) / 256;         // at most 8 (nb <= 2048)
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sum = 0;
+    for (uint32_t k = 0; k < per; k++) {
+        v[k] = b0 + k < nb ? totals[b0 + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t total = 0;
+    uint32_t run = block_scan256(sum, sh, &total);
+    for (uint32_t k = 0; k < per; k++) {
+        if (b0 + k < nb) starts[b0 + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) starts[nb] = total;
+}
+
+// Placing: the workgroup's keys (eight per thread, kept in registers) are
+// counted per bucket and grouped by bucket in LDS first, so that each thread
+// then stores consecutive positions of a bucket's range: the stores of a
+// wavefront cover a few contiguous segments instead of 64 scattered words.
+__global__ __launch_bounds__(1024) void k_perm_place(ChachaKey pk, uint32_t p, uint64_t n, uint32_t d1, uint32_t nblk,
+                                                     const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ starts,
+                                                     uint64_t* __restrict__ skeys, uint32_t* __restrict__ srows) {
+    __shared__ uint64_t lkeys[kChunkRows];
+    __shared__ uint32_t lrows[kChunkRows];
+    __shared__ uint32_t loff[kMaxBuckets];     // the bucket's first slot in the workgroup's group
+    __shared__ uint32_t lcur[kMaxBuckets];     // counts, then slot cursors
+    __shared__ uint32_t gpos[kMaxBuckets];     // the bucket's first position for this workgroup
+    __shared__ uint32_t scan[1024];
+    const uint32_t nb = 1u << d1, tid = threadIdx.x;
+    for (uint32_t i = tid; i < nb; i += 1024) lcur[i] = 0;
+    __syncthreads();
+    uint64_t key[8], row0[4];
+    const uint64_t q0 = (uint64_t)blockIdx.x * (kChunkRows / 8);
+#pragma unroll
+    for (uint32_t it = 0; it < 4; it++) {         // kChunkRows / 2 lanes' worth: 4 x 1024
+        const uint32_t t = tid + 1024u * it;
+        const uint64_t q = q0 + (t >> 2);
+        const uint4 o = chacha_quad(pk, (uint32_t)q, 0u, 16u + p, 0u);
+        row0[it] = q * 8 + 2 * (t & 3);
+        key[2 * it] = (uint64_t)o.x | ((uint64_t)o.y << 32);
+        key[2 * it + 1] = (uint64_t)o.z | ((uint64_t)o.w << 32);
+        if (row0[it] < n) atomicAdd(&lcur[bucket_of(key[2 * it], d1)], 1u);
+        if (row0[it] + 1 < n) atomicAdd(&lcur[bucket_of(key[2 * it + 1], d1)], 1u);
+    }
+    __syncthreads();
+    {   // exclusive scan of the counts, two buckets per thread (nb <= 2048)
+        const uint32_t a = 2 * tid < nb ? lcur[2 * tid] : 0u, b = 2 * tid + 1 < nb ? lcur[2 * tid + 1] : 0u;
+        scan[tid] = a + b;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            const uint32_t x = tid >= d ? scan[tid - d] : 0u;
+            __syncthreads();
+            scan[tid] += x;
+            __syncthreads();
+        }
+        const uint32_t ex = scan[tid] - (a + b);
+        if (2 * tid < nb) loff[2 * tid] = lcur[2 * tid] = ex;
+        if (2 * tid + 1 < nb) loff[2 * tid + 1] = lcur[2 * tid + 1] = ex + a;
+    }
+    for (uint32_t i = tid; i < nb; i += 1024) gpos[i] = starts[i] + counts[(uint64_t)i * nblk + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t it = 0; it < 4; it++)
+#pragma unroll
+        for (uint32_t e = 0; e < 2; e++)
+            if (row0[it] + e < n) {
+                const uint32_t slot = atomicAdd(&lcur[bucket_of(key[2 * it + e], d1)], 1u);
+                lkeys[slot] = key[2 * it + e];
+                lrows[slot] = (uint32_t)(row0[it] + e);
+            }
+    __syncthreads();
+    const uint64_t first = (uint64_t)blockIdx.x * kChunkRows;
+    const uint32_t rows_here = (uint32_t)(n - first < kChunkRows ? n - first : kChunkRows);
+    for (uint32_t i = tid; i < rows_here; i += 1024) {
+        const uint64_t k = lkeys[i];
+        const uint32_t bk = bucket_of(k, d1);
+        const uint32_t dst = gpos[bk] + (i - loff[bk]);
+        if (dst < n) {                            // always, with counts from k_perm_count
+            skeys[dst] = k;
+            srows[dst] = lrows[i];
+        }
+    }
+}
+
+// perm entry of the row at position pos (or its inverse).
+__device__ __forceinline__ void put_position(uint32_t* perm, uint32_t inverse, uint32_t n, uint32_t pos, uint32_t row) {
+    if (!inverse)
+        perm[pos] = row;
+    else if (row < n)
+        perm[row] = pos;
+}
+
+// Bucket ranking; `mode` 0: networks where they apply, 1: exact comparisons
+// for every run, 2: every bucket ordered by comparing every pair.
+__global__ __launch_bounds__(1024) void k_bucket_rank(uint64_t n, uint32_t hb, uint32_t d1, uint32_t inverse,
+                                                      uint32_t mode, const uint32_t* __restrict__ starts,
+                                                      const uint64_t* __restrict__ skeys,
+                                                      const uint32_t* __restrict__ srows, uint32_t* __restrict__ perm) {
+    __shared__ uint32_t part[kBucketCap];     // 25 key bits after the run id << 7 | slot in the run
+    __shared__ uint32_t lrow[kBucketCap];     // row number
+    __shared__ uint16_t sidx[kBucketCap];     // index in the bucket's range
+    __shared__ uint32_t rcount[64];
+    __shared__ uint32_t rstart[65];
+    constexpr uint32_t kPer = (kBucketCap + 1023) / 1024;
+    const uint32_t n32 = (uint32_t)n;
+    const uint32_t s = min(starts[blockIdx.x], n32), e = min(starts[blockIdx.x + 1], n32);
+    const uint32_t size = e > s ? e - s : 0u;
+    if (size == 0) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    if (size > kBucketCap || mode == 2) {
+        // every pair: position = rows of the bucket with a smaller (key, row)
+        for (uint32_t i = tid; i < size; i += blockDim.x) {
+            const uint64_t ki = skeys[s + i];
+            const uint32_t ri = srows[s + i];
+            uint32_t rank = 0;
+            for (uint32_t j = 0; j < size; j++) {
+                const uint64_t kj = skeys[s + j];
+                const uint32_t rj = srows[s + j];
+                rank += (uint32_t)(kj < ki) | ((uint32_t)(kj == ki) & (uint32_t)(rj < ri));
+            }
+            put_position(perm, inverse, n32, s + rank, ri);
+        }
+        return;
+    }
+    const uint32_t d2 = hb - d1, nr = 1u << d2;
+    const uint32_t run_mask = nr - 1u;
+    for (uint32_t i = tid; i < nr; i += blockDim.x) rcount[i] = 0;
+    __syncthreads();
+    uint64_t key[kPer];
+    uint32_t slot[kPer], row[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        const uint32_t i = tid + 1024u * k;
+        key[k] = 0;
+        row[k] = 0;
+        if (i < size) {
+            key[k] = skeys[s + i];
+            row[k] = srows[s + i];
+        }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        slot[k] = 0;
+        if (tid + 1024u * k < size) slot[k] = atomicAdd(&rcount[(uint32_t)(key[k] >> (64 - hb)) & run_mask], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t r = 0; r < nr; r++) {
+            rstart[r] = acc;
+            acc += rcount[r];
+        }
+        rstart[nr] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        const uint32_t i = tid + 1024u * k;
+        if (i < size) {
+            const uint32_t pos = rstart[(uint32_t)(key[k] >> (64 - hb)) & run_mask] + slot[k];
+            part[pos] = (((uint32_t)(key[k] >> (39 - hb)) & 0x1FFFFFFu) << 7) | (slot[k] & 127u);
+            lrow[pos] = row[k];
+            sidx[pos] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    for (uint32_t r = wave; r < nr; r += blockDim.x >> 6) {
+        const uint32_t rs = rstart[r], m = rstart[r + 1] - rs;
+        if (m == 0) continue;
+        const uint32_t base = s + rs;              // the run's first position
+        bool exact = mode == 1 || m > 128;
+        if (!exact) {
+            const uint32_t pb = lane + 64u;
+            uint32_t a = lane < m ? part[rs + lane] : 0xFFFFFFFFu;
+            uint32_t bb = pb < m ? part[rs + pb] : 0xFFFFFFFFu;
+            if (m <= 64)
+                sort64<2>(a, lane);
+            else
+                sort128<2>(a, bb, lane);
+            const uint32_t prev_a = lane_read(a, (lane - 1u) & 63u);
+            const uint32_t prev_b_lane = lane_read(bb, (lane - 1u) & 63u);
+            const uint32_t prev_b = lane == 0 ? prev_a : prev_b_lane;
+            const bool tie = (lane >= 1 && lane < m && (a >> 7) == (prev_a >> 7)) ||
+                             (pb < m && (bb >> 7) == (prev_b >> 7));
+            if (__ballot(tie) != 0) {
+                exact = true;
+            } else {
+                if (lane < m) put_position(perm, inverse, n32, base + lane, lrow[rs + (a & 127u)]);
+                if (pb < m) put_position(perm, inverse, n32, base + pb, lrow[rs + (bb & 127u)]);
+            }
+        }
+        if (!exact) continue;
+        // exact: rank = members with a smaller (key, row), keys from the
+        // bucket's range, 64 at a time broadcast with readlane
+        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+            const uint32_t ei = c0 + lane;
+            const bool has = ei < m;
+            const uint64_t ke = has ? skeys[s + sidx[rs + ei]] : 0ull;
+            const uint32_t re = has ? lrow[rs + ei] : 0u;
+            uint32_t rank = 0;
+            for (uint32_t j0 = 0; j0 < m; j0 += 64) {
+                const bool hj = j0 + lane < m;
+                const uint64_t kj = hj ? skeys[s + sidx[rs + j0 + lane]] : 0ull;
+                const uint32_t rj = hj ? lrow[rs + j0 + lane] : 0u;
+                const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)(m - j0 < 64 ? m - j0 : 64));
+                for (uint32_t t = 0; t < cnt; t++) {
+                    const uint64_t kt = lane_value(kj, t);
+                    const uint32_t rt = (uint32_t)__builtin_amdgcn_readlane((int)rj, (int)t);
+                    rank += (uint32_t)(kt < ke) | ((uint32_t)(kt == ke) & (uint32_t)(rt < re));
+                }
+            }
+            if (has) put_position(perm, inverse, n32, base + rank, re);
         }
     }
 }
@@ -549,7 +996,60 @@ struct PermJob {
     hipStream_t s;
 };
 
-int perm_step(int step, uint64_t nrows, const PermJob& j) {
+uint32_t ceil_log2(uint64_t n) {
+    uint32_t lg = 0;
+    while ((1ull << lg) < n) lg++;
+    return lg;
+}
+
+// Bucket bits d1 of the bucket method: 2^11 .. 2^12 rows per bucket on average.
+uint32_t bucket_bits(uint64_t nrows) {
+    const uint32_t lg = ceil_log2(nrows);
+    return lg > 12 ? lg - 12 : 0;
+}
+
+// The method a permutation of nrows rows takes (tables of at most 1024 rows
+// take k_perm_small whatever it is).
+uint32_t perm_method(uint64_t nrows, uint32_t m) {
+    if (m >= kPermBuckets && nrows > kBucketMaxRows) return kPermRadix;
+    return m;
+}
+
+int perm_step_buckets(int step, uint64_t nrows, const PermJob& j, uint32_t method) {
+    const uint32_t hb = run_bits(nrows), d1 = bucket_bits(nrows), nb = 1u << d1;
+    const uint32_t nblk = (uint32_t)((nrows + kChunkRows - 1) / kChunkRows);
+    const PermScratch& w = j.w;
+    // scratch: keys and rows placed by bucket in keys / idx, per-workgroup
+    // counts in keys_sorted, bucket totals and starts in idx_sorted
+    uint32_t* counts = (uint32_t*)w.keys_sorted;
+    uint32_t* totals = w.idx_sorted;
+    uint32_t* starts = w.idx_sorted + nb;
+    // the counts fit keys_sorted (8 bytes a row) and the totals and starts
+    // idx_sorted (4 bytes a row) for every table the method takes
+    if ((uint64_t)nb * nblk > 2 * nrows || 2ull * nb + 1 > nrows || nblk > 1024)
+        return fail(FSS_EDEVICE, "rss_shuffle: bucket scratch does not fit");
+    switch (step) {
+        case 0:
+            hipLaunchKernelGGL(k_perm_count, dim3(nblk), dim3(1024), 0, j.s, j.pk, j.p, nrows, d1, nblk, counts);
+            return check_launch("k_perm_count");
+        case 1:
+            hipLaunchKernelGGL(k_bucket_offsets, dim3(nb), dim3(256), 0, j.s, nblk, counts, totals);
+            if (int rc = check_launch("k_bucket_offsets")) return rc;
+            hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(256), 0, j.s, nb, totals, starts);
+            return check_launch("k_bucket_starts");
+        case 2:
+            hipLaunchKernelGGL(k_perm_place, dim3(nblk), dim3(1024), 0, j.s, j.pk, j.p, nrows, d1, nblk, counts, starts,
+                               w.keys, w.idx);
+            return check_launch("k_perm_place");
+        default:
+            hipLaunchKernelGGL(k_bucket_rank, dim3(nb), dim3(1024), 0, j.s, nrows, hb, d1, (uint32_t)j.inverse,
+                               method - kPermBuckets, starts, w.keys, w.idx, j.perm);
+            return check_launch("k_bucket_rank");
+    }
+}
+
+int perm_step(int step, uint64_t nrows, const PermJob& j, uint32_t method) {
+    if (method >= kPermBuckets) return perm_step_buckets(step, nrows, j, method);
     const uint32_t hb = run_bits(nrows);
     const PermScratch& w = j.w;
     // with no run-id bits there is one run, already in row order: no sort
@@ -570,12 +1070,12 @@ int perm_step(int step, uint64_t nrows, const PermJob& j) {
             return 0;
         }
         case 2:
-            hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((nruns + 1 + 255) / 256)), dim3(256), 0, j.s, nrows, hb,
-                               keys, w.starts);
+            hipLaunchKernelGGL(k_run_starts, dim3(grid_of(nrows + 1, 256)), dim3(256), 0, j.s, nrows, hb, keys,
+                               w.starts);
             return check_launch("k_run_starts");
         default:
-            hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, j.s, hb,
-                               (uint32_t)j.inverse, w.starts, keys, rows, j.perm);
+            hipLaunchKernelGGL(k_rank_runs, dim3(grid_of(nruns * 64, 256)), dim3(256), 0, j.s, nrows, hb,
+                               (uint32_t)j.inverse, (uint32_t)(method == kPermRadix), w.starts, keys, rows, j.perm);
             return check_launch("k_rank_runs");
     }
 }
@@ -695,9 +1195,10 @@ struct PermSet {
                                  {pair_key(seeds[2]), kP31, true, inv31, pw[1], s31},
                                  {pair_key(seeds[1]), kP23, false, p23, pw[2], s23}};
         int prc[3] = {0, 0, 0};
+        const uint32_t method = perm_method(nrows, g_perm_method.load());
         for (int step = 0; step < 4; step++)
             for (int q = 0; q < 3; q++)
-                if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q]);
+                if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q], method);
         if (forked) {
             recorded[0] = hipEventRecord(done[0], s31) == hipSuccess;
             recorded[1] = hipEventRecord(done[1], s23) == hipSuccess;
@@ -1003,6 +1504,19 @@ int rss_compact_valid(uint64_t nrec, uint32_t nwords, const uint32_t* const d_ta
                       uint64_t work_bytes, void* stream) {
     return shuffle_open_compact(nrec, nwords, d_table, seeds, d_out, d_rows_out, d_count, d_work, work_bytes, stream,
                                 true, "rss_compact_valid");
+}
+
+int rss_set_shuffle_tuning(uint32_t perm_method) {
+    last_error().clear();
+    if (perm_method > kPermBucketsPairs) return fail(FSS_EINVAL, "rss_set_shuffle_tuning: perm_method is 0 .. 4");
+    g_perm_method.store(perm_method);
+    return FSS_OK;
+}
+
+int rss_get_shuffle_tuning(uint32_t* perm_method) {
+    last_error().clear();
+    if (perm_method) *perm_method = g_perm_method.load();
+    return FSS_OK;
 }
 
 }  // extern "C"

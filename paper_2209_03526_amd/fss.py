@@ -115,6 +115,8 @@ def _load():
         "fss_get_tuning": ([ctypes.POINTER(u32), ctypes.POINTER(u32)], ctypes.c_int),
         "fss_set_keygen_tuning": ([u32], ctypes.c_int),
         "fss_get_keygen_tuning": ([ctypes.POINTER(u32)], ctypes.c_int),
+        "rss_set_shuffle_tuning": ([u32], ctypes.c_int),
+        "rss_get_shuffle_tuning": ([ctypes.POINTER(u32)], ctypes.c_int),
         "rss_group_k": ([u64, P, P, u32, P, P], ctypes.c_int),
         "rss_group_k_lists": ([u64, u32, P, P, u32, P, P], ctypes.c_int),
         "rss_enc_posting_lists": ([u64, u32, P, P, P, P, u64, P, u32, P, P, u64, P], ctypes.c_int),
@@ -132,7 +134,8 @@ LIB = _load()
 EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version", "fss_shutdown", "fss_mask_open",
            "fss_keygen", "fss_eval_eq", "fss_eval_lt", "ss_triples", "ss_and", "match_workspace_bytes",
            "match_query", "match_rounds", "match_batch_queue_bytes", "fss_queue_workspace_bytes", "fss_keygen_batch", "fss_eval_batch", "fss_eval_batch_noalloc", "match_query_batch",
-           "fss_set_tuning", "fss_get_tuning", "fss_set_keygen_tuning", "fss_get_keygen_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_from_fss", "rss_and",
+           "fss_set_tuning", "fss_get_tuning", "fss_set_keygen_tuning", "fss_get_keygen_tuning",
+           "rss_set_shuffle_tuning", "rss_get_shuffle_tuning", "fss_eval_all", "fss_eval_all_batch", "rss_sec_eval", "fss_dealer_masks", "rss_reshare", "rss_from_fss", "rss_and",
            "rss_shuffle_workspace_bytes", "rss_shuffle", "rss_shuffle_prepare_workspace_bytes", "rss_shuffle_prepare",
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
            "rss_fetch_many_workspace_bytes",
@@ -420,6 +423,16 @@ def set_keygen_tuning(tile_mult: int):
 def get_keygen_tuning() -> int:
     a = ctypes.c_uint32()
     LIB.fss_get_keygen_tuning(ctypes.byref(a))
+    return a.value
+
+
+def set_shuffle_tuning(perm_method: int):
+    _check(LIB.rss_set_shuffle_tuning(perm_method))
+
+
+def get_shuffle_tuning() -> int:
+    a = ctypes.c_uint32()
+    LIB.rss_get_shuffle_tuning(ctypes.byref(a))
     return a.value
 
 

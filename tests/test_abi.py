@@ -317,4 +317,7 @@ def test_tuning_limits(fss):
     assert L.fss_set_keygen_tuning(0) == fss.EINVAL and L.fss_set_keygen_tuning(9) == fss.EINVAL
     assert L.fss_set_keygen_tuning(4) == fss.OK and fss.get_keygen_tuning() == 4
     assert L.fss_set_keygen_tuning(1) == fss.OK and fss.get_keygen_tuning() == 1
+    assert L.rss_set_shuffle_tuning(5) == fss.EINVAL and fss.get_shuffle_tuning() == 2
+    assert L.rss_set_shuffle_tuning(0) == fss.OK and fss.get_shuffle_tuning() == 0
+    assert L.rss_set_shuffle_tuning(2) == fss.OK and fss.get_shuffle_tuning() == 2
     assert L.fss_set_tuning(0, 1) == fss.EINVAL and L.fss_set_tuning(1, 3) == fss.EINVAL

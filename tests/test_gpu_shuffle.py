@@ -78,6 +78,33 @@ def test_shuffle_in_two_parts(fss, n, w):
         np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i])
 
 
+@pytest.mark.parametrize("method", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1025, 5000, 65573, (1 << 20) + 100])
+def test_permutations_by_every_method(fss, n, method):
+    """Every way the library has of making a permutation gives the oracle's:
+    the radix pass with exact comparisons in each run (0) or with sorting
+    networks in the lanes (1); buckets ordered in LDS with networks (2, the
+    default), with exact comparisons in each run (3), or by comparing every
+    pair of a bucket (4, the path of a bucket too large for LDS).  Exact
+    comparisons are what a network falls back on (two rows of a run sharing
+    their leading 25 key bits, runs longer than 128 rows), which random keys
+    at these sizes almost never produce, so they are checked on their own."""
+    seeds = (11 * n, 12 * n + 1, 13 * n + 2)
+    perms = torch.full((3 * n,), -1, dtype=torch.int32, device=DEV)
+    fss.set_shuffle_tuning(method)
+    try:
+        fss.rss_shuffle_prepare(n, seeds, perms)
+        torch.cuda.synchronize()
+    finally:
+        fss.set_shuffle_tuning(2)
+    got = U(perms).reshape(3, n)
+    p12, p23, p31 = (osh.permutation(seeds[0], osh.P12, n), osh.permutation(seeds[1], osh.P23, n),
+                     osh.permutation(seeds[2], osh.P31, n))
+    np.testing.assert_array_equal(got[0], np.argsort(p12))
+    np.testing.assert_array_equal(got[1], np.argsort(p31))
+    np.testing.assert_array_equal(got[2], p23)
+
+
 def test_prepared_skips_out_of_range_entries(fss):
     """Permutation entries outside [0, nrows) leave their rows unwritten and
     are never used as indices: with every entry out of range the outputs keep
