@@ -431,9 +431,15 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  *   a permutation applied to a table gathers out[i] = in[perm[i]].
  * The permutations are made on two streams of the library's own besides the
  * caller's, ordered against the caller's stream with events: the call's work
- * is complete when the caller's stream reaches the call's end.  These calls
- * are not meant for stream capture into a graph: their radix passes clear
- * buffers with memset operations.
+ * is complete when the caller's stream reaches the call's end.  On a stream
+ * being captured into a graph, all of it stays on the caller's stream and
+ * holds no memset, host copy or host wait, so rss_shuffle, rss_shuffle_prepare
+ * and rss_shuffle_prepared can be captured and replayed (same seeds, same
+ * permutations) for tables of at most 2^23 rows; beyond that, or with a
+ * radix permutation method (rss_set_shuffle_tuning), they return
+ * FSS_EUNSUPPORTED under capture (their radix passes clear buffers with
+ * memset operations).  rss_fetch_many, rss_compact_valid and rss_sec_access
+ * are not for capture.
  * The messages follow the algorithm (its X_2 in CS2's step is the X1 it
  * received): X1 = pi31[pi12(D1^D2^T12)^T31]; Y1 = pi12(D3^T12);
  * C1 = pi23(X1^T23)^R2; C2 = pi23[pi31(Y1^T31)^T23]^R1; R3 = C1^C2.

@@ -1183,7 +1183,17 @@ struct PermSet {
             rc = check_launch("k_perm_small");
             return;
         }
-        side[0] = perm_stream(0), side[1] = perm_stream(1);
+        const uint32_t method = perm_method(nrows, g_perm_method.load());
+        // Under stream capture everything stays on the caller's stream, and
+        // only the bucket method (no sort library, so no memset nodes) runs.
+        hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+        const bool capturing =
+            s && hipStreamIsCapturing(s, &capture) == hipSuccess && capture != hipStreamCaptureStatusNone;
+        if (capturing && method < kPermBuckets) {
+            rc = fail(FSS_EUNSUPPORTED, "rss_shuffle: under stream capture at most 2^23 rows (bucket permutations)");
+            return;
+        }
+        if (!capturing) side[0] = perm_stream(0), side[1] = perm_stream(1);
         forked = side[0] && side[1] && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&done[0], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&done[1], hipEventDisableTiming) == hipSuccess &&
@@ -1195,7 +1205,6 @@ struct PermSet {
                                  {pair_key(seeds[2]), kP31, true, inv31, pw[1], s31},
                                  {pair_key(seeds[1]), kP23, false, p23, pw[2], s23}};
         int prc[3] = {0, 0, 0};
-        const uint32_t method = perm_method(nrows, g_perm_method.load());
         for (int step = 0; step < 4; step++)
             for (int q = 0; q < 3; q++)
                 if (!prc[q]) prc[q] = perm_step(step, nrows, jobs[q], method);

@@ -4,12 +4,14 @@ the ANDs) -- and its replay.  The pipeline holds no memset, no host copy and
 no host wait, so it can be captured whole; a replay redoes the same work
 (same seeds, so the same keys) and must give the eager result bit for bit,
 every time, with eager work and synchronisations between the replays."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
 
 import synth
-from gpu_util import DEV
+from gpu_util import DEV, U
 
 pytestmark = pytest.mark.gpu
 
@@ -217,3 +219,80 @@ def test_captured_query_batch_replays_bit_exact(fss):
             for j, (a, b) in enumerate(zip(got, want[i])):
                 np.testing.assert_array_equal(a[0], b[0], err_msg=f"replay {rep} query {i} output {j}")
                 np.testing.assert_array_equal(a[1], b[1], err_msg=f"replay {rep} query {i} output {j}")
+
+
+@pytest.mark.parametrize("n,w", [(5000, 4), ((1 << 16) + 37, 16)])
+def test_captured_shuffle_replays_bit_exact(fss, n, w):
+    """rss_shuffle and its two parts (prepare, prepared) captured into one
+    graph: under capture the permutations stay on the caller's stream and use
+    no memset, so every replay -- with eager shuffles of another table and
+    synchronisations between the replays -- gives the oracle's shares."""
+    from oracle import shuffle as osh
+    rng = np.random.default_rng(n + w)
+    sh = [rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(DEV)
+
+    d3 = [T(x.ravel()) for x in sh]
+    seeds = (71, 72, 73)
+    want = osh.sec_shuffle(sh, *seeds)
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    out2 = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    perms = torch.empty(3 * n, dtype=torch.int32, device=DEV)
+    m, mw = 3001, 3
+    other = [T(rng.integers(0, 2**32, m * mw, dtype=np.uint64).astype(np.uint32)) for _ in range(3)]
+    other_out = [torch.empty(m * mw, dtype=torch.int32, device=DEV) for _ in range(3)]
+    other_want = osh.sec_shuffle([U(o).reshape(m, mw) for o in other], 5, 6, 7)
+
+    def step():
+        fss.rss_shuffle(n, w, d3, seeds, out)
+        fss.rss_shuffle_prepare(n, seeds, perms)
+        fss.rss_shuffle_prepared(n, w, d3, seeds, perms, out2)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in out + out2:
+            o.zero_()
+        perms.zero_()
+        fss.rss_shuffle(m, mw, other, (5, 6, 7), other_out)     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(3):
+            np.testing.assert_array_equal(U(out[i]).reshape(n, w), want[i], err_msg=f"replay {rep}")
+            np.testing.assert_array_equal(U(out2[i]).reshape(n, w), want[i], err_msg=f"replay {rep}")
+            np.testing.assert_array_equal(U(other_out[i]).reshape(m, mw), other_want[i])
+
+
+def test_shuffle_capture_refuses_radix_permutations(fss):
+    """With a radix permutation method the shuffle would record memset nodes:
+    under capture it returns FSS_EUNSUPPORTED and enqueues nothing."""
+    n, w = 5000, 2
+    d3 = [torch.zeros(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    work = torch.empty(int(fss.LIB.rss_shuffle_workspace_bytes(n, w)), dtype=torch.uint8, device=DEV)
+    marker = torch.zeros(1, dtype=torch.int32, device=DEV)
+    seeds = (ctypes.c_uint64 * 3)(1, 2, 3)
+    fss.set_shuffle_tuning(1)
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            rc = fss.LIB.rss_shuffle(n, w, fss._ptr3(d3), seeds, fss._ptr3(out), work.data_ptr(), work.numel(),
+                                     torch.cuda.current_stream().cuda_stream)
+            marker.add_(1)
+        assert rc == fss.EUNSUPPORTED and b"capture" in fss.LIB.fss_last_error()
+    finally:
+        fss.set_shuffle_tuning(2)
+    g.replay()
+    torch.cuda.synchronize()
+    assert int(marker.item()) == 1
