@@ -14,8 +14,10 @@ target by target
 
 All three servers are simulated on one device.  Every step runs in the
 library's kernels; this module only orders the calls and reads the counts
-that the opens of secFetch and secAccess reveal (one synchronisation per
-open, as in the protocol, where the count decides the next step's size).
+that the opens of secFetch and secAccess reveal: one synchronisation per
+secFetch open (its count decides how many secAccess calls follow), and one
+per group of secAccess calls (they are enqueued back to back, each with its
+lmax-row capacity, and their counts read together).
 
 Readings where Alg. 2 leaves the order open: a target's candidates are
 grouped by the kept vertex (of its parent target) whose neighbours they are,
@@ -189,21 +191,26 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
                 pair = (tgt.vtype, nt.vtype)
                 wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
                 lmax = eg.lmax[pair]
+                # the kept vertices' secAccess calls are enqueued back to back;
+                # their opened list lengths (the validity opens reveal them) are
+                # read once, after the last
+                counts = torch.zeros(max(g.nkept, 1), dtype=torch.int32, device=dev)
+                made = []
                 for r in range(g.nkept):
                     idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
                     ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
                     vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
                     rows = torch.empty(lmax, dtype=torch.int32, device=dev)
-                    c2 = torch.zeros(1, dtype=torch.int32, device=dev)
                     seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
                     work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax,
                                               eg.post[pair], wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys,
-                                              counter, seeds, ids3, vals3, rows, c2)
+                                              counter, seeds, ids3, vals3, rows, counts[r:r + 1])
                     counter += 2
                     step += 1
-                    m = int(c2.item())           # the validity open reveals the list's true length
-                    del work
-                    groups[c].append(_Group((i, gi, r), m, ids3, vals3))
+                    del work                     # stream-ordered: reused only after this call's kernels
+                    made.append((ids3, vals3))
+                for r, m in enumerate(counts.cpu().tolist()[:g.nkept]):
+                    groups[c].append(_Group((i, gi, r), m, *made[r]))
     return _results(groups, query, eg)
 
 
