@@ -116,6 +116,16 @@ struct Out3 {
     uint32_t* p[3];
 };
 
+// Zeroes n words of each of three buffers (one launch for the three shares).
+__global__ void k_zero3(uint64_t n, Out3 o) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        o.p[0][k] = 0u;
+        o.p[1][k] = 0u;
+        o.p[2][k] = 0u;
+    }
+}
+
 // Slot l = blockIdx.y of the fetched list: XOR over this block's candidates c
 // with l < len_c of id_m[c] AND record (off_c + l), into out[.][l * wx + w].
 // First the block lists in LDS the candidates whose (public, padded) list
@@ -405,8 +415,7 @@ int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[
     uint8_t* cwork = (uint8_t*)ws.take((cws + 3) / 4);
     if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
     // 1. P_m[l] = XOR_c id_m[c] AND id_{c,l}: additive shares
-    for (int i = 0; i < 3; i++)
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(tw, 256, 4096)), dim3(256), 0, s, tw, 0u, add[i]);
+    hipLaunchKernelGGL(k_zero3, dim3(blocks_for(tw, 256, 4096)), dim3(256), 0, s, tw, Out3{{add[0], add[1], add[2]}});
     if (ncand) {
         // enough chunks to fill the chip over lmax slots, and at most kSelCand candidates per chunk
         const uint64_t chunks = std::max<uint64_t>((ncand + kSelCand - 1) / kSelCand,
@@ -433,8 +442,7 @@ int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[
     rc = rss_compact_valid(lmax, wx, r3, seeds, d_ids, d_rows_out, d_count, cwork, cws, stream);
     if (rc) return rc;
     // 3. the attribute record of every kept ID, then one re-share of them all
-    for (int i = 0; i < 3; i++)
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(ta, 256, 4096)), dim3(256), 0, s, ta, 0u, att[i]);
+    hipLaunchKernelGGL(k_zero3, dim3(blocks_for(ta, 256, 4096)), dim3(256), 0, s, ta, Out3{{att[0], att[1], att[2]}});
     const uint64_t xchunks = std::max<uint64_t>(1, std::min<uint64_t>((x_bits + 255) / 256, 2048 / lmax + 1));
     hipLaunchKernelGGL(k_attr_select, dim3((unsigned)xchunks, lmax), dim3(kSelBlock), 0, s, x_bits, wx, wd, d_count,
                        Shares3{{d_ids[0], d_ids[1], d_ids[2]}}, Shares3{{d_attr[0], d_attr[1], d_attr[2]}},

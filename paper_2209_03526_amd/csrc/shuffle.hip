@@ -907,6 +907,60 @@ __global__ void k_compact_vec(uint64_t nrows, uint32_t nwords, const uint32_t* _
     }
 }
 
+// Tables of at most kSmallPerm records (secAccess shuffles one posting list):
+// the open, the exclusive scan of the flags, the compaction and the count in
+// one workgroup of 1024 threads.  A wavefront opens a record at a time, its
+// lanes over the record's words (the parity of all bits for the secAccess
+// filter, bit 0 of word 0 for secFetch); then the kept records' words
+// [first, nwords) go to their positions in shuffled order.
+__global__ __launch_bounds__(1024) void k_open_compact_small(uint32_t n, uint32_t nwords, uint32_t parity,
+                                                             const uint32_t* __restrict__ a,
+                                                             const uint32_t* __restrict__ b,
+                                                             const uint32_t* __restrict__ c, uint32_t* __restrict__ o0,
+                                                             uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
+                                                             uint32_t* __restrict__ rows_out,
+                                                             uint32_t* __restrict__ count) {
+    __shared__ uint32_t flag[kSmallPerm];
+    __shared__ uint32_t incl[kSmallPerm];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    flag[t] = 0;
+    __syncthreads();
+    for (uint32_t i = wave; i < n; i += blockDim.x >> 6) {
+        const uint64_t base = (uint64_t)i * nwords;
+        uint32_t acc = 0;
+        if (parity) {
+            for (uint32_t w = lane; w < nwords; w += 64) acc ^= a[base + w] ^ b[base + w] ^ c[base + w];
+            for (uint32_t d = 32; d > 0; d >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, (int)d);
+            acc = __builtin_popcount(acc) & 1u;
+        } else {
+            acc = (a[base] ^ b[base] ^ c[base]) & 1u;
+        }
+        if (lane == 0) flag[i] = acc;
+    }
+    __syncthreads();
+    const uint32_t f = flag[t];
+    incl[t] = f;
+    __syncthreads();
+    for (uint32_t d = 1; d < kSmallPerm; d <<= 1) {
+        const uint32_t x = t >= d ? incl[t - d] : 0u;
+        __syncthreads();
+        incl[t] += x;
+        __syncthreads();
+    }
+    if (t < n && f) rows_out[incl[t] - 1] = t;
+    if (t == 0) *count = incl[kSmallPerm - 1];
+    const uint32_t first = parity ? 0u : 1u, ow = nwords - first;
+    const uint64_t total = (uint64_t)n * ow;
+    for (uint64_t k = t; k < total; k += blockDim.x) {
+        const uint32_t i = (uint32_t)(k / ow), w = (uint32_t)(k - (uint64_t)i * ow);
+        if (!flag[i]) continue;
+        const uint64_t src = (uint64_t)i * nwords + first + w, dst = (uint64_t)(incl[i] - 1) * ow + w;
+        o0[dst] = a[src];
+        o1[dst] = b[src];
+        o2[dst] = c[src];
+    }
+}
+
 // count of kept records = last exclusive prefix + last flag
 __global__ void k_count(uint64_t n, const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
                         uint32_t* __restrict__ count) {
@@ -1458,9 +1512,11 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
         if (!d_table[i] || !d_out[i]) return fail(FSS_EINVAL, "%s: NULL share %d", who, i);
     if (ncand > 0x7FFFFFFFull) return fail(FSS_EUNSUPPORTED, "%s: more than 2^31 rows", who);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (uint64_t)1, d_count);
-    int rc = check_launch("k_zero");
-    if (rc || ncand == 0) return rc;
+    int rc = 0;
+    if (ncand == 0) {
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (uint64_t)1, d_count);
+        return check_launch("k_zero");
+    }
     if (!d_work || work_bytes < rss_fetch_many_workspace_bytes(ncand, nwords))
         return fail(FSS_ENOMEM, "%s: workspace needs %llu bytes", who,
                     (unsigned long long)rss_fetch_many_workspace_bytes(ncand, nwords));
@@ -1475,6 +1531,11 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
     rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
     if (rc) return rc;
+    if (ncand <= kSmallPerm) {
+        hipLaunchKernelGGL(k_open_compact_small, dim3(1), dim3(kSmallPerm), 0, s, (uint32_t)ncand, nwords,
+                           (uint32_t)parity, sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out, d_count);
+        return check_launch("k_open_compact_small");
+    }
     if (parity)
         hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((4 * ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
                            (uint32_t)((nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2])),

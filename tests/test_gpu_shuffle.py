@@ -198,11 +198,12 @@ def test_fetch_unique(fss):
     np.testing.assert_array_equal(got[0] ^ got[1] ^ got[2], d[4321])
 
 
-@pytest.mark.parametrize("n,w", [(4000, 3), (200003, 4)])
+@pytest.mark.parametrize("n,w", [(1, 2), (1000, 5), (1024, 3), (1025, 3), (4000, 3), (200003, 4)])
 def test_fetch_many(fss, n, w):
     """Case II against the oracle: the kept positions, the three shares of the
-    kept records, and their reconstruction.  200003 records put the scan and
-    the compaction over many workgroups and the radix pass on its merge path."""
+    kept records, their number (written over whatever the count held) and
+    their reconstruction.  Up to 1024 records the open, scan and compaction
+    run in one workgroup; 200003 records put them over many workgroups."""
     rng = np.random.default_rng(11 + n)
     d, rows = _rss_table(13 + n, n, w)
     x = (rng.random(n) < 0.1).astype(np.uint8)
@@ -213,7 +214,7 @@ def test_fetch_many(fss, n, w):
     seeds = (5, 6, 7)
     out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
     pos = torch.empty(n, dtype=torch.int32, device=DEV)
-    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), -1, dtype=torch.int32, device=DEV)
     fss.rss_fetch_many(n, w + 1, [T(t.ravel()) for t in table], seeds, out, pos, cnt)
     torch.cuda.synchronize()
     k = int(cnt.item())
@@ -227,7 +228,7 @@ def test_fetch_many(fss, n, w):
     assert sorted(map(tuple, rec.tolist())) == sorted(map(tuple, d[x == 1].tolist()))
 
 
-@pytest.mark.parametrize("n,w", [(999, 2), (3001, 7), (5003, 20), (70001, 16), (131075, 4)])
+@pytest.mark.parametrize("n,w", [(1, 3), (999, 2), (1024, 70), (3001, 7), (5003, 20), (70001, 16), (131075, 4)])
 def test_compact_valid(fss, n, w):
     """The secAccess filter against the oracle: records whose bits XOR to 1 are
     kept in shuffled order (every third record an all-zero dummy), with their
@@ -242,7 +243,7 @@ def test_compact_valid(fss, n, w):
     seeds = (71, 72, 73)
     out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
     pos = torch.empty(n, dtype=torch.int32, device=DEV)
-    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), -1, dtype=torch.int32, device=DEV)
     fss.rss_compact_valid(n, w, [T(t.ravel()) for t in sh], seeds, out, pos, cnt)
     torch.cuda.synchronize()
     k = int(cnt.item())
