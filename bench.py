@@ -964,13 +964,13 @@ def run_next(args, torch, fss, dev):
     # algorithmic work: 3 shares in, the two tables the pi23 gather takes (X1
     # and pi31(Y1 ^ T31)) written and read, 3 shares out; one ChaCha12 block
     # per 16-word slice of each of the 5 mask tables and per 8 rows of each of
-    # the 3 permutations' keys (the sorts not counted)
+    # the 3 permutations' keys (their bucket placing and ranking not counted)
     slices = nrec * ((nwords + 15) // 16)
     cc_blocks = 5 * slices + 3 * ((nrec + 7) // 8)
     res["rss_shuffle"] = row("rss_shuffle", timed(shuffle), 10 * tbytes, 0,
                              f"{nrec} records x {nwords * 4} B: 3 shares in, X1 and pi31(Y1 ^ T31) written and "
-                             "read, 3 shares out; ChaCha12 for 5 mask tables and 3 permutations' keys (sorts not "
-                             "counted)", cc_blocks)
+                             "read, 3 shares out; ChaCha12 for 5 mask tables and 3 permutations' keys (their "
+                             "placing and ranking not counted)", cc_blocks)
     # the same shuffle in two parts: the permutations made ahead of the data
     # (rss_shuffle_prepare, seeds only), then the data-dependent launches
     perms = torch.empty(3 * nrec, dtype=torch.int32, device=dev)
@@ -978,7 +978,7 @@ def run_next(args, torch, fss, dev):
                                      timed(lambda: work.__setitem__("p", fss.rss_shuffle_prepare(nrec, seeds, perms,
                                                                                                  stream))),
                                      3 * nrec * 4, 0, f"3 permutations of {nrec} rows from the pair seeds (keys "
-                                     "counted; sorts and rankings not)", 3 * ((nrec + 7) // 8))
+                                     "counted; their placing and ranking not)", 3 * ((nrec + 7) // 8))
     res["rss_shuffle_prepared"] = row("rss_shuffle_prepared",
                                       timed(lambda: work.__setitem__("w", fss.rss_shuffle_prepared(
                                           nrec, nwords, d3, seeds, perms, o3, stream))),
