@@ -105,6 +105,21 @@ def test_permutations_by_every_method(fss, n, method):
     np.testing.assert_array_equal(got[2], p23)
 
 
+@pytest.mark.parametrize("n", [1 << 23, (1 << 23) + 5])
+def test_permutations_at_the_bucket_limit(fss, n):
+    """The default method at its largest table (2^23 rows: 2048 buckets, 1024
+    counting workgroups) and just past it, where the radix method takes over:
+    both permutations equal the oracle's."""
+    seeds = (n, n + 1, n + 2)
+    perms = torch.full((3 * n,), -1, dtype=torch.int32, device=DEV)
+    fss.rss_shuffle_prepare(n, seeds, perms)
+    torch.cuda.synchronize()
+    got = U(perms).reshape(3, n)
+    np.testing.assert_array_equal(got[0], np.argsort(osh.permutation(seeds[0], osh.P12, n)))
+    np.testing.assert_array_equal(got[1], np.argsort(osh.permutation(seeds[2], osh.P31, n)))
+    np.testing.assert_array_equal(got[2], osh.permutation(seeds[1], osh.P23, n))
+
+
 def test_prepared_skips_out_of_range_entries(fss):
     """Permutation entries outside [0, nrows) leave their rows unwritten and
     are never used as indices: with every entry out of range the outputs keep
