@@ -1076,9 +1076,9 @@ def sec_match_row(args, torch, dev):
     """The paper's whole secMatch (Alg. 2) for one path query U -> P -> C over a
     typed graph (200 U, 8,000 P, 1,000 C vertices; up to 40 P neighbours per U
     and 3 C neighbours per P, k = 2 groups), all three servers on the GPU:
-    wall-clock time of the call (its opens synchronise the host once per
-    secFetch and once per group of secAccess calls), beside the oracle on the
-    same instance on one core."""
+    wall-clock time of the call (its opens synchronise the host twice per
+    target: after its secFetch calls and after its secAccess calls), beside
+    the oracle on the same instance on one core."""
     from oracle import secmatch as osm
     from paper_2209_03526_amd import fss as lib
     from paper_2209_03526_amd import secmatch
@@ -1110,7 +1110,7 @@ def sec_match_row(args, torch, dev):
     chains = runs[-1][1]
     found = osm.reconstruct(tg, q, chains)
     ok = found == osm.plaintext_match(tg, q)
-    out = {"ms": round(ms, 3), "binding": "host-ordered steps: one synchronisation per secFetch and per group of secAccess calls",
+    out = {"ms": round(ms, 3), "binding": "launch-bound steps: two synchronisations per target (after its secFetch and its secAccess calls)",
            "results": len(found), "plaintext_match": ok,
            "work": "one 3-hop path query (Alg. 2: secEval, re-share, secFetch, secAccess per kept vertex) over "
                    f"{n['U']} U / {n['P']} P / {n['C']} C typed vertices, one-hot IDs, k = 2 posting lists"}

@@ -26,11 +26,14 @@ Readings (Alg. 2 leaves these open):
    order from ``seed0``, the s-th shuffle (secFetch's and secAccess's alike)
    the triple (seed0 + 3s, seed0 + 3s + 1, seed0 + 3s + 2).  Predicate i's
    token is made with pred = i.
-3. Order: target by target in index order; within a target, group by group in
-   order of creation: the group's secEval, re-share and secFetch, then, for
-   each child target in index order and each kept vertex in kept order, its
-   secAccess.  An empty group takes no randomness.  (For a path this is hop
-   by hop.)
+3. Order: target by target in index order; within a target, first every
+   group's secEval, re-share and secFetch, group by group in order of
+   creation; then, group by group, for each child target in index order and
+   each kept vertex in kept order, its secAccess.  An empty group takes no
+   randomness.  (For a path this is hop by hop.)  Taking a target's secFetch
+   steps before its secAccess steps lets the servers run all of a target's
+   fetches before they learn any group's count, and all of its secAccess
+   calls after.
 4. The result is every assignment of one kept vertex per target, each target's
    vertex in the group its parent's vertex made, as the three shares of each
    target's one-hot ID record.  The client reconstructs the IDs and drops
@@ -138,7 +141,8 @@ def sec_match(tg, enc: Encoded, query, tok_seed: int, prf_keys, counter0: int, s
             _, kept = shuffle.fetch_case2(zb, rows, seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
             step += 1
             g.kept_ids = [kept[j][:, :wi] for j in range(3)]
-            # secAccess of every kept vertex, for each child target
+        # secAccess of every kept vertex of every group, for each child target
+        for gi, g in enumerate(groups[i]):
             for c in children[i]:
                 nt = query.targets[c]
                 pair = (tgt.vtype, nt.vtype)

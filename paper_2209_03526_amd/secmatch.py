@@ -14,17 +14,19 @@ target by target
 
 All three servers are simulated on one device.  Every step runs in the
 library's kernels; this module only orders the calls and reads the counts
-that the opens of secFetch and secAccess reveal: one synchronisation per
-secFetch open (its count decides how many secAccess calls follow), and one
-per group of secAccess calls (they are enqueued back to back, each with its
-lmax-row capacity, and their counts read together).
+that the opens of secFetch and secAccess reveal, two synchronisations per
+target: one after all of the target's secFetch calls (their counts decide
+how many secAccess calls follow), one after all of its secAccess calls (each
+with its lmax-row capacity); between them the calls are enqueued back to
+back.
 
 Readings where Alg. 2 leaves the order open: a target's candidates are
 grouped by the kept vertex (of its parent target) whose neighbours they are,
 and secFetch runs once per group, so each kept vertex keeps its parent (the
 final reorganisation into subgraphs needs that tie); targets run in index
-order, and within a target each group's secEval, re-share and secFetch come
-before the secAccess calls of its kept vertices for each child target;
+order, and within a target every group's secEval, re-share and secFetch come
+first (group order), then the secAccess calls of the kept vertices (group by
+group, child target by child target);
 re-shares take PRF counters in order from `counter0` (secEval's re-share one,
 secAccess two); the s-th shuffle (secFetch's and secAccess's alike) takes the
 seeds (seed0 + 3s, +1, +2); predicate i's token is made with pred = i; an
@@ -163,9 +165,12 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
                 ev[(party, rep)] = torch.empty(words(npos), dtype=torch.int32, device=dev)
                 fss.fss_eval_all(party, kb, rep, npos, ev[(party, rep)])
         wi, wv = words(eg.n[tgt.vtype]), words(npos)
-        for gi, g in enumerate(groups[i]):
-            if g.n == 0:
-                continue
+        rec = 1 + wi + wv
+        live = [gi for gi, g in enumerate(groups[i]) if g.n > 0]
+        # every group's secEval, re-share and secFetch, enqueued without waiting
+        fetched = torch.zeros(max(len(live), 1), dtype=torch.int32, device=dev)
+        for k, gi in enumerate(live):
+            g = groups[i][gi]
             # secEval, then the re-share into RSS
             x3 = [torch.empty(words(g.n), dtype=torch.int32, device=dev) for _ in range(3)]
             for s, ((pa, ra, ja), (pb, rb, jb)) in enumerate(SERVER_TERMS):
@@ -174,43 +179,43 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
             fss.rss_reshare(g.n, x3, prf_keys, counter, z3)
             counter += 1
             # secFetch Case II on {x || id || d}
-            rec = 1 + wi + wv
             table = [torch.empty(g.n * rec, dtype=torch.int32, device=dev) for _ in range(3)]
             fss.rss_fetch_table(g.n, z3, wi, g.ids, wv, g.vals, table)
             g.kept = [torch.empty(g.n * (rec - 1), dtype=torch.int32, device=dev) for _ in range(3)]
             pos = torch.empty(g.n, dtype=torch.int32, device=dev)
-            cnt = torch.zeros(1, dtype=torch.int32, device=dev)
             work = fss.rss_fetch_many(g.n, rec, table, (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2),
-                                      g.kept, pos, cnt)
+                                      g.kept, pos, fetched[k:k + 1])
             step += 1
-            g.nkept = int(cnt.item())            # the open reveals how many candidates match
-            del work, table
-            # secAccess of every kept vertex, for each child target
-            for c in children[i]:
-                nt = query.targets[c]
-                pair = (tgt.vtype, nt.vtype)
-                wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
-                lmax = eg.lmax[pair]
-                # the kept vertices' secAccess calls are enqueued back to back;
-                # their opened list lengths (the validity opens reveal them) are
-                # read once, after the last
-                counts = torch.zeros(max(g.nkept, 1), dtype=torch.int32, device=dev)
-                made = []
-                for r in range(g.nkept):
-                    idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
-                    ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
-                    vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
-                    rows = torch.empty(lmax, dtype=torch.int32, device=dev)
-                    seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
-                    work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax,
-                                              eg.post[pair], wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys,
-                                              counter, seeds, ids3, vals3, rows, counts[r:r + 1])
-                    counter += 2
-                    step += 1
-                    del work                     # stream-ordered: reused only after this call's kernels
-                    made.append((ids3, vals3))
-                for r, m in enumerate(counts.cpu().tolist()[:g.nkept]):
-                    groups[c].append(_Group((i, gi, r), m, *made[r]))
+            del work, table, pos, x3, z3         # stream-ordered: reused only after these calls' kernels
+        # the opens reveal how many candidates of each group match
+        for k, m in enumerate(fetched.cpu().tolist()[:len(live)]):
+            groups[i][live[k]].nkept = m
+        # secAccess of every kept vertex of every group, for each child target,
+        # enqueued without waiting; the validity opens' counts read together
+        calls = [(gi, c, r) for gi in live for c in children[i] for r in range(groups[i][gi].nkept)]
+        counts = torch.zeros(max(len(calls), 1), dtype=torch.int32, device=dev)
+        made = []
+        for k, (gi, c, r) in enumerate(calls):
+            g, nt = groups[i][gi], query.targets[c]
+            pair = (tgt.vtype, nt.vtype)
+            wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
+            lmax = eg.lmax[pair]
+            idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
+            ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
+            vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
+            rows = torch.empty(lmax, dtype=torch.int32, device=dev)
+            seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
+            work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax, eg.post[pair], wv2,
+                                      eg.shares[("attr", nt.vtype, nt.attr)], prf_keys, counter, seeds, ids3, vals3,
+                                      rows, counts[k:k + 1])
+            counter += 2
+            step += 1
+            del work, rows
+            made.append((ids3, vals3))
+        if calls:
+            for k, m in enumerate(counts.cpu().tolist()[:len(calls)]):
+                gi, c, r = calls[k]
+                groups[c].append(_Group((i, gi, r), m, *made[k]))
     return _results(groups, query, eg)
 
 
