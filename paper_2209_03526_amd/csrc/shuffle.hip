@@ -106,12 +106,15 @@ struct SmallPerms {
     uint32_t* out[3];
 };
 
-__global__ __launch_bounds__(1024) void k_perm_small(uint32_t n, SmallPerms J) {
-    __shared__ uint64_t key[kSmallPerm];
-    const uint32_t q = blockIdx.x;
+// One permutation of n <= kSmallPerm rows made by the whole workgroup: keys
+// into `key` (LDS), then each row's rank; `out` gets the permutation (or its
+// inverse).  Every thread of the workgroup calls it; `key` is free again when
+// it returns.
+__device__ __forceinline__ void small_perm(ChachaKey pk, uint32_t p, uint32_t inverse, uint32_t n, uint64_t* key,
+                                           uint32_t* out) {
     const uint32_t lanes = (n + 7) / 8 * 4;              // whole quads: a quad makes the keys of 8 rows
     for (uint32_t t = threadIdx.x; t < lanes; t += blockDim.x) {
-        const uint4 o = chacha_quad(J.pk[q], t >> 2, 0u, 16u + J.p[q], 0u);
+        const uint4 o = chacha_quad(pk, t >> 2, 0u, 16u + p, 0u);
         const uint32_t r0 = (t >> 2) * 8 + 2 * (t & 3);
         if (r0 < n) key[r0] = (uint64_t)o.x | ((uint64_t)o.y << 32);
         if (r0 + 1 < n) key[r0 + 1] = (uint64_t)o.z | ((uint64_t)o.w << 32);
@@ -124,11 +127,18 @@ __global__ __launch_bounds__(1024) void k_perm_small(uint32_t n, SmallPerms J) {
             const uint64_t kj = key[j];
             rank += (kj < ki || (kj == ki && j < i)) ? 1u : 0u;
         }
-        if (J.inverse[q])
-            J.out[q][i] = rank;
+        if (inverse)
+            out[i] = rank;
         else
-            J.out[q][rank] = i;
+            out[rank] = i;
     }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_perm_small(uint32_t n, SmallPerms J) {
+    __shared__ uint64_t key[kSmallPerm];
+    const uint32_t q = blockIdx.x;
+    small_perm(J.pk[q], J.p[q], J.inverse[q], n, key, J.out[q]);
 }
 
 // The permutation is the stable argsort of the 64-bit keys.  It is made in two
@@ -698,6 +708,34 @@ __device__ __forceinline__ void pin(uint4& v) {
 // The masks are indexed by the row they are XORed at: T12 before pi12, T31
 // before pi31.  A quad of lanes takes one slice.
 template <bool VEC>
+__device__ __forceinline__ void first_slice(uint64_t t, uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k31,
+                                            const uint32_t* __restrict__ inv12, const uint32_t* __restrict__ inv31,
+                                            const uint32_t* __restrict__ g0, const uint32_t* __restrict__ g1,
+                                            const uint32_t* __restrict__ g2, uint32_t* __restrict__ o0,
+                                            uint32_t* __restrict__ o1, uint32_t* __restrict__ r12,
+                                            uint32_t* __restrict__ r31) {
+    const uint32_t nb = (nwords + 15) >> 4;
+    const uint32_t c = threadIdx.x & 3u;
+    const uint64_t sl = t >> 2;
+    const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
+    const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
+    // a quad shares its record, so these exits keep quads whole; they only
+    // matter for permutations that were not made by this library
+    const uint32_t j = inv12[i];
+    if (j >= nrows) return;
+    const uint32_t l = inv31[j];
+    if (l >= nrows) return;
+    const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)l * nwords + 16 * b;
+    const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
+    const uint4 z = load_quarter<VEC>(g2, src, c, len);
+    const uint4 m = xor4(chacha_quad(k12, i, b, kT12, nwords), chacha_quad(k31, j, b, kT31, nwords));
+    store_quarter<VEC>(o0, dst, c, len, xor4(xor4(x, y), m));
+    store_quarter<VEC>(o1, dst, c, len, xor4(z, m));
+    store_quarter<VEC>(r12, src, c, len, chacha_quad(k12, i, b, kR2, nwords));
+    store_quarter<VEC>(r31, src, c, len, chacha_quad(k31, i, b, kR1, nwords));
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k31,
                                                         const uint32_t* __restrict__ inv12,
                                                         const uint32_t* __restrict__ inv31,
@@ -706,29 +744,10 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32
                                                         const uint32_t* __restrict__ g2, uint32_t* __restrict__ o0,
                                                         uint32_t* __restrict__ o1, uint32_t* __restrict__ r12,
                                                         uint32_t* __restrict__ r31) {
-    const uint32_t nb = (nwords + 15) >> 4;
-    const uint64_t total = nrows * nb * 4;
+    const uint64_t total = nrows * ((nwords + 15) >> 4) * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const uint32_t c = threadIdx.x & 3u;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride) {
-        const uint64_t sl = t >> 2;
-        const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
-        const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
-        // a quad shares its record, so these exits keep quads whole; they only
-        // matter for permutations that were not made by this library
-        const uint32_t j = inv12[i];
-        if (j >= nrows) continue;
-        const uint32_t l = inv31[j];
-        if (l >= nrows) continue;
-        const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)l * nwords + 16 * b;
-        const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
-        const uint4 z = load_quarter<VEC>(g2, src, c, len);
-        const uint4 m = xor4(chacha_quad(k12, i, b, kT12, nwords), chacha_quad(k31, j, b, kT31, nwords));
-        store_quarter<VEC>(o0, dst, c, len, xor4(xor4(x, y), m));
-        store_quarter<VEC>(o1, dst, c, len, xor4(z, m));
-        store_quarter<VEC>(r12, src, c, len, chacha_quad(k12, i, b, kR2, nwords));
-        store_quarter<VEC>(r31, src, c, len, chacha_quad(k31, i, b, kR1, nwords));
-    }
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride)
+        first_slice<VEC>(t, nrows, nwords, k12, k31, inv12, inv31, g0, g1, g2, o0, o1, r12, r31);
 }
 
 // Round pi23 as a gather (its outputs are the result shares, written in
@@ -739,29 +758,36 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32
 // not stored).  R1 and R2 are made again from their pairs' keys rather than
 // read back.
 template <bool VEC>
+__device__ __forceinline__ void final_slice(uint64_t t, uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
+                                            ChachaKey k31, const uint32_t* __restrict__ perm,
+                                            const uint32_t* __restrict__ g0, const uint32_t* __restrict__ g1,
+                                            uint32_t* __restrict__ out) {
+    const uint32_t nb = (nwords + 15) >> 4;
+    const uint32_t c = threadIdx.x & 3u;
+    const uint64_t sl = t >> 2;
+    const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
+    const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
+    const uint32_t p = perm[i];
+    if (p >= nrows) return;          // as in first_slice
+    const uint64_t src = (uint64_t)p * nwords + 16 * b, dst = (uint64_t)i * nwords + 16 * b;
+    const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
+    const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
+    uint4 c1 = xor4(x, m);
+    pin(c1);
+    c1 = xor4(c1, chacha_quad(k12, i, b, kR2, nwords));
+    const uint4 c2 = xor4(xor4(y, m), chacha_quad(k31, i, b, kR1, nwords));
+    store_quarter<VEC>(out, dst, c, len, xor4(c1, c2));
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
                                                         ChachaKey k31, const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ g0,
                                                         const uint32_t* __restrict__ g1, uint32_t* __restrict__ out) {
-    const uint32_t nb = (nwords + 15) >> 4;
-    const uint64_t total = nrows * nb * 4;
+    const uint64_t total = nrows * ((nwords + 15) >> 4) * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const uint32_t c = threadIdx.x & 3u;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride) {
-        const uint64_t sl = t >> 2;
-        const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
-        const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
-        const uint32_t p = perm[i];
-        if (p >= nrows) continue;       // as in k_shuffle_first
-        const uint64_t src = (uint64_t)p * nwords + 16 * b, dst = (uint64_t)i * nwords + 16 * b;
-        const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
-        const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
-        uint4 c1 = xor4(x, m);
-        pin(c1);
-        c1 = xor4(c1, chacha_quad(k12, i, b, kR2, nwords));
-        const uint4 c2 = xor4(xor4(y, m), chacha_quad(k31, i, b, kR1, nwords));
-        store_quarter<VEC>(out, dst, c, len, xor4(c1, c2));
-    }
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride)
+        final_slice<VEC>(t, nrows, nwords, k12, k23, k31, perm, g0, g1, out);
 }
 
 // Case I: XOR over candidates of (r_i & m_i) ^ (r_j & m_i) ^ (r_i & m_j), the
@@ -913,15 +939,12 @@ __global__ void k_compact_vec(uint64_t nrows, uint32_t nwords, const uint32_t* _
 // lanes over the record's words (the parity of all bits for the secAccess
 // filter, bit 0 of word 0 for secFetch); then the kept records' words
 // [first, nwords) go to their positions in shuffled order.
-__global__ __launch_bounds__(1024) void k_open_compact_small(uint32_t n, uint32_t nwords, uint32_t parity,
-                                                             const uint32_t* __restrict__ a,
-                                                             const uint32_t* __restrict__ b,
-                                                             const uint32_t* __restrict__ c, uint32_t* __restrict__ o0,
-                                                             uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
-                                                             uint32_t* __restrict__ rows_out,
-                                                             uint32_t* __restrict__ count) {
-    __shared__ uint32_t flag[kSmallPerm];
-    __shared__ uint32_t incl[kSmallPerm];
+__device__ __forceinline__ void open_compact_block(uint32_t n, uint32_t nwords, uint32_t parity,
+                                                   const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                                                   const uint32_t* __restrict__ c, uint32_t* __restrict__ o0,
+                                                   uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
+                                                   uint32_t* __restrict__ rows_out, uint32_t* __restrict__ count,
+                                                   uint32_t* flag, uint32_t* incl) {
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
     flag[t] = 0;
     __syncthreads();
@@ -959,6 +982,61 @@ __global__ __launch_bounds__(1024) void k_open_compact_small(uint32_t n, uint32_
         o1[dst] = b[src];
         o2[dst] = c[src];
     }
+}
+
+__global__ __launch_bounds__(1024) void k_open_compact_small(uint32_t n, uint32_t nwords, uint32_t parity,
+                                                             const uint32_t* __restrict__ a,
+                                                             const uint32_t* __restrict__ b,
+                                                             const uint32_t* __restrict__ c, uint32_t* __restrict__ o0,
+                                                             uint32_t* __restrict__ o1, uint32_t* __restrict__ o2,
+                                                             uint32_t* __restrict__ rows_out,
+                                                             uint32_t* __restrict__ count) {
+    __shared__ uint32_t flag[kSmallPerm];
+    __shared__ uint32_t incl[kSmallPerm];
+    open_compact_block(n, nwords, parity, a, b, c, o0, o1, o2, rows_out, count, flag, incl);
+}
+
+// A whole shuffle of a small table (at most kSmallPerm records and
+// kFusedSlices 16-word slices) in one workgroup: the three permutations into
+// LDS, the first round (first_slice), the final round (final_slice), and,
+// with compact = 1 (secFetch: bit 0 of word 0) or 2 (secAccess filter: parity
+// of all bits), the open and compaction of the shuffled table.  The same
+// per-slice code as the multi-workgroup launches, so the same shares; the
+// rounds meet through global memory (x1, v, out) behind workgroup barriers.
+constexpr uint32_t kFusedSlices = 1024;
+
+struct SmallShuffle {
+    ChachaKey k12, k23, k31;
+    const uint32_t* g[3];
+    uint32_t* x1;
+    uint32_t* v;
+    uint32_t* out[3];              // R1, R2, R3
+    uint32_t compact;
+    uint32_t* kept[3];
+    uint32_t* rows_out;
+    uint32_t* count;
+};
+
+template <bool VEC>
+__global__ __launch_bounds__(1024) void k_shuffle_small(uint32_t n, uint32_t nwords, SmallShuffle A) {
+    __shared__ uint64_t key[kSmallPerm];
+    __shared__ uint32_t perm[3][kSmallPerm];     // inverse of pi12, inverse of pi31, pi23
+    __shared__ uint32_t flag[kSmallPerm];
+    __shared__ uint32_t incl[kSmallPerm];
+    small_perm(A.k12, kP12, 1u, n, key, perm[0]);
+    small_perm(A.k31, kP31, 1u, n, key, perm[1]);
+    small_perm(A.k23, kP23, 0u, n, key, perm[2]);
+    const uint64_t total = (uint64_t)n * ((nwords + 15) >> 4) * 4;
+    for (uint64_t t = threadIdx.x; t < total; t += blockDim.x)
+        first_slice<VEC>(t, n, nwords, A.k12, A.k31, perm[0], perm[1], A.g[0], A.g[1], A.g[2], A.x1, A.v, A.out[1],
+                         A.out[0]);
+    __syncthreads();
+    for (uint64_t t = threadIdx.x; t < total; t += blockDim.x)
+        final_slice<VEC>(t, n, nwords, A.k12, A.k23, A.k31, perm[2], A.x1, A.v, A.out[2]);
+    if (!A.compact) return;
+    __syncthreads();
+    open_compact_block(n, nwords, A.compact == 2, A.out[0], A.out[1], A.out[2], A.kept[0], A.kept[1], A.kept[2],
+                       A.rows_out, A.count, flag, incl);
 }
 
 // count of kept records = last exclusive prefix + last flag
@@ -1304,6 +1382,31 @@ int shuffle_rounds(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], 
 
 // Alg. 5 with all three servers simulated; out[0..2] = R1, R2, R3.  The
 // permutation pi23 is still being made while the first launch runs.
+// Whether a shuffle runs in one workgroup (k_shuffle_small).
+bool fused_shuffle(uint64_t nrows, uint32_t nwords) {
+    return nrows <= kSmallPerm && nrows * ((nwords + 15) / 16) <= kFusedSlices;
+}
+
+// The one-workgroup shuffle; compact: 0 none, 1 secFetch's open, 2 the
+// secAccess filter's (then kept / rows_out / count receive the compaction).
+int launch_fused(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
+                 uint32_t* const out[3], uint32_t* x1, uint32_t* v, uint32_t compact, uint32_t* const kept[3],
+                 uint32_t* rows_out, uint32_t* count, hipStream_t s) {
+    SmallShuffle A{};
+    A.k12 = pair_key(seeds[0]), A.k23 = pair_key(seeds[1]), A.k31 = pair_key(seeds[2]);
+    for (int i = 0; i < 3; i++) {
+        A.g[i] = d[i];
+        A.out[i] = out[i];
+        A.kept[i] = kept ? kept[i] : nullptr;
+    }
+    A.x1 = x1, A.v = v, A.compact = compact, A.rows_out = rows_out, A.count = count;
+    if (vec_quarters(nwords, {d[0], d[1], d[2], x1, v, out[0], out[1], out[2]}))
+        hipLaunchKernelGGL(k_shuffle_small<true>, dim3(1), dim3(1024), 0, s, (uint32_t)nrows, nwords, A);
+    else
+        hipLaunchKernelGGL(k_shuffle_small<false>, dim3(1), dim3(1024), 0, s, (uint32_t)nrows, nwords, A);
+    return check_launch("k_shuffle_small");
+}
+
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                 uint32_t* const out[3], Carve& ws, hipStream_t s) {
     const uint64_t tw = nrows * nwords;
@@ -1313,6 +1416,7 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     uint32_t* inv31 = ws.take<uint32_t>(nrows);
     uint32_t* p23 = ws.take<uint32_t>(nrows);
     if (!ws.ok) return fail(FSS_ENOMEM, "rss_shuffle: workspace too small");
+    if (fused_shuffle(nrows, nwords)) return launch_fused(nrows, nwords, d, seeds, out, x1, v, 0, nullptr, nullptr, nullptr, s);
     PermSet ps{s};
     ps.begin(nrows, seeds, inv12, inv31, p23, ws);
     const int rc = shuffle_rounds(nrows, nwords, d, seeds, inv12, inv31, p23, x1, v, out, s, &ps);
@@ -1529,6 +1633,14 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)ncand);
     void* scan_tmp = ws.take<uint8_t>(scan);
     if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
+    if (fused_shuffle(ncand, nwords)) {
+        // the shuffle, the open and the compaction in one workgroup
+        const uint64_t tw = ncand * nwords;
+        uint32_t* x1 = ws.take<uint32_t>(tw);
+        uint32_t* v = ws.take<uint32_t>(tw);
+        if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
+        return launch_fused(ncand, nwords, d_table, seeds, sh, x1, v, parity ? 2u : 1u, d_out, d_rows_out, d_count, s);
+    }
     rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
     if (rc) return rc;
     if (ncand <= kSmallPerm) {

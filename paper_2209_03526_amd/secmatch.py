@@ -168,25 +168,28 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
         rec = 1 + wi + wv
         live = [gi for gi, g in enumerate(groups[i]) if g.n > 0]
         # every group's secEval, re-share and secFetch, enqueued without waiting
+        # (the temporaries are shared by the groups: one stream orders their uses)
         fetched = torch.zeros(max(len(live), 1), dtype=torch.int32, device=dev)
+        nmax = max([groups[i][gi].n for gi in live], default=1)
+        x3 = [torch.empty(words(nmax), dtype=torch.int32, device=dev) for _ in range(3)]
+        z3 = [torch.empty(words(nmax), dtype=torch.int32, device=dev) for _ in range(3)]
+        table = [torch.empty(nmax * rec, dtype=torch.int32, device=dev) for _ in range(3)]
         for k, gi in enumerate(live):
             g = groups[i][gi]
             # secEval, then the re-share into RSS
-            x3 = [torch.empty(words(g.n), dtype=torch.int32, device=dev) for _ in range(3)]
             for s, ((pa, ra, ja), (pb, rb, jb)) in enumerate(SERVER_TERMS):
                 fss.rss_sec_eval_records(g.n, npos, ev[(pa, ra)], ev[(pb, rb)], g.vals[ja], g.vals[jb], x3[s])
-            z3 = [torch.empty(words(g.n), dtype=torch.int32, device=dev) for _ in range(3)]
             fss.rss_reshare(g.n, x3, prf_keys, counter, z3)
             counter += 1
             # secFetch Case II on {x || id || d}
-            table = [torch.empty(g.n * rec, dtype=torch.int32, device=dev) for _ in range(3)]
             fss.rss_fetch_table(g.n, z3, wi, g.ids, wv, g.vals, table)
             g.kept = [torch.empty(g.n * (rec - 1), dtype=torch.int32, device=dev) for _ in range(3)]
             pos = torch.empty(g.n, dtype=torch.int32, device=dev)
             work = fss.rss_fetch_many(g.n, rec, table, (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2),
                                       g.kept, pos, fetched[k:k + 1])
             step += 1
-            del work, table, pos, x3, z3         # stream-ordered: reused only after these calls' kernels
+            del work, pos                        # stream-ordered: reused only after these calls' kernels
+        del x3, z3, table
         # the opens reveal how many candidates of each group match
         for k, m in enumerate(fetched.cpu().tolist()[:len(live)]):
             groups[i][live[k]].nkept = m
