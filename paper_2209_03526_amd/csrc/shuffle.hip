@@ -757,18 +757,27 @@ __global__ __launch_bounds__(kBlock) void k_shuffle_first(uint64_t nrows, uint32
 // and CS2's R3 = C1 ^ C2; with the servers simulated together C1 and C2 are
 // not stored).  R1 and R2 are made again from their pairs' keys rather than
 // read back.
+// open: 0 none; 1 secFetch's flag of each record (bit 0 of word 0); 2 the
+// secAccess filter's flag (parity of all bits) of records of at most 16
+// words (one slice).  The opened record is R1 ^ R2 ^ R3 = x ^ y, which the
+// three servers' exchange reconstructs; the flag of output row i goes to
+// flags[i].
 template <bool VEC>
 __device__ __forceinline__ void final_slice(uint64_t t, uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
                                             ChachaKey k31, const uint32_t* __restrict__ perm,
                                             const uint32_t* __restrict__ g0, const uint32_t* __restrict__ g1,
-                                            uint32_t* __restrict__ out) {
+                                            uint32_t* __restrict__ out, uint32_t open = 0,
+                                            uint32_t* __restrict__ flags = nullptr) {
     const uint32_t nb = (nwords + 15) >> 4;
     const uint32_t c = threadIdx.x & 3u;
     const uint64_t sl = t >> 2;
     const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
     const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
     const uint32_t p = perm[i];
-    if (p >= nrows) return;          // as in first_slice
+    if (p >= nrows) {                // as in first_slice
+        if (open && b == 0 && c == 0) flags[i] = 0u;
+        return;
+    }
     const uint64_t src = (uint64_t)p * nwords + 16 * b, dst = (uint64_t)i * nwords + 16 * b;
     const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
     const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
@@ -777,17 +786,26 @@ __device__ __forceinline__ void final_slice(uint64_t t, uint64_t nrows, uint32_t
     c1 = xor4(c1, chacha_quad(k12, i, b, kR2, nwords));
     const uint4 c2 = xor4(xor4(y, m), chacha_quad(k31, i, b, kR1, nwords));
     store_quarter<VEC>(out, dst, c, len, xor4(c1, c2));
+    if (open == 1) {
+        if (b == 0 && c == 0) flags[i] = (x.x ^ y.x) & 1u;
+    } else if (open == 2) {
+        uint32_t acc = (x.x ^ y.x) ^ (x.y ^ y.y) ^ (x.z ^ y.z) ^ (x.w ^ y.w);
+        acc ^= quad_from<1>(acc);
+        acc ^= quad_from<2>(acc);
+        if (c == 0) flags[i] = __builtin_popcount(acc) & 1u;
+    }
 }
 
 template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23,
                                                         ChachaKey k31, const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ g0,
-                                                        const uint32_t* __restrict__ g1, uint32_t* __restrict__ out) {
+                                                        const uint32_t* __restrict__ g1, uint32_t* __restrict__ out,
+                                                        uint32_t open, uint32_t* __restrict__ flags) {
     const uint64_t total = nrows * ((nwords + 15) >> 4) * 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += stride)
-        final_slice<VEC>(t, nrows, nwords, k12, k23, k31, perm, g0, g1, out);
+        final_slice<VEC>(t, nrows, nwords, k12, k23, k31, perm, g0, g1, out, open, flags);
 }
 
 // Case I: XOR over candidates of (r_i & m_i) ^ (r_j & m_i) ^ (r_i & m_j), the
@@ -851,14 +869,6 @@ __global__ __launch_bounds__(kFetchBlock) void k_fetch_unique(
 __global__ void k_zero(uint64_t n, uint32_t* __restrict__ p) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0u;
-}
-
-// Case II: flag of shuffled record i = bit 0 of word 0 of R1 ^ R2 ^ R3 (the opened x).
-__global__ void k_open_flags(uint64_t nrows, uint32_t nwords, const uint32_t* __restrict__ a,
-                             const uint32_t* __restrict__ b, const uint32_t* __restrict__ c,
-                             uint32_t* __restrict__ flags) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nrows) flags[i] = (a[i * nwords] ^ b[i * nwords] ^ c[i * nwords]) & 1u;
 }
 
 // secAccess filter: flag of shuffled record i = parity of all bits of R1 ^ R2 ^ R3
@@ -1235,14 +1245,15 @@ int shuffle_first(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k31,
 }
 
 int shuffle_final(uint64_t nrows, uint32_t nwords, ChachaKey k12, ChachaKey k23, ChachaKey k31, const uint32_t* perm,
-                  const uint32_t* g0, const uint32_t* g1, uint32_t* out, hipStream_t s) {
+                  const uint32_t* g0, const uint32_t* g1, uint32_t* out, uint32_t open, uint32_t* flags,
+                  hipStream_t s) {
     const unsigned grid = slice_grid(nrows * ((nwords + 15) / 16) * 4);
     if (vec_quarters(nwords, {g0, g1, out}))
         hipLaunchKernelGGL(k_shuffle_final<true>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k23, k31, perm,
-                           g0, g1, out);
+                           g0, g1, out, open, flags);
     else
         hipLaunchKernelGGL(k_shuffle_final<false>, dim3(grid), dim3(kBlock), 0, s, nrows, nwords, k12, k23, k31, perm,
-                           g0, g1, out);
+                           g0, g1, out, open, flags);
     return check_launch("k_shuffle_final");
 }
 
@@ -1362,9 +1373,11 @@ struct PermSet {
 
 // The data-dependent part of Alg. 5 (all three servers simulated), given the
 // permutations: out[0..2] = R1, R2, R3.  x1 and v are workspace tables.
+// open / flags: the final round's optional open (final_slice).
 int shuffle_rounds(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
                    const uint32_t* inv12, const uint32_t* inv31, const uint32_t* p23, uint32_t* x1, uint32_t* v,
-                   uint32_t* const out[3], hipStream_t s, PermSet* pending) {
+                   uint32_t* const out[3], hipStream_t s, PermSet* pending, uint32_t open = 0,
+                   uint32_t* flags = nullptr) {
     const ChachaKey k12 = pair_key(seeds[0]), k23 = pair_key(seeds[1]), k31 = pair_key(seeds[2]);
     // pi12 then pi31: CS1's X1, CS3's pi31(Y1 ^ T31); R2 and R1 drawn
     if (pending) pending->join(0);
@@ -1376,7 +1389,7 @@ int shuffle_rounds(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], 
         pending->join(1);
         if (!rc) rc = pending->rc;
     }
-    if (!rc) rc = shuffle_final(nrows, nwords, k12, k23, k31, p23, x1, v, out[2], s);
+    if (!rc) rc = shuffle_final(nrows, nwords, k12, k23, k31, p23, x1, v, out[2], open, flags, s);
     return rc;
 }
 
@@ -1408,7 +1421,7 @@ int launch_fused(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], co
 }
 
 int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], const uint64_t seeds[3],
-                uint32_t* const out[3], Carve& ws, hipStream_t s) {
+                uint32_t* const out[3], Carve& ws, hipStream_t s, uint32_t open = 0, uint32_t* flags = nullptr) {
     const uint64_t tw = nrows * nwords;
     uint32_t* x1 = ws.take<uint32_t>(tw);      // CS1 -> CS2: X1
     uint32_t* v = ws.take<uint32_t>(tw);       // CS3: pi31(Y1 ^ T31)
@@ -1419,7 +1432,7 @@ int run_shuffle(uint64_t nrows, uint32_t nwords, const uint32_t* const d[3], con
     if (fused_shuffle(nrows, nwords)) return launch_fused(nrows, nwords, d, seeds, out, x1, v, 0, nullptr, nullptr, nullptr, s);
     PermSet ps{s};
     ps.begin(nrows, seeds, inv12, inv31, p23, ws);
-    const int rc = shuffle_rounds(nrows, nwords, d, seeds, inv12, inv31, p23, x1, v, out, s, &ps);
+    const int rc = shuffle_rounds(nrows, nwords, d, seeds, inv12, inv31, p23, x1, v, out, s, &ps, open, flags);
     ps.finish();
     return rc;
 }
@@ -1641,22 +1654,24 @@ static int shuffle_open_compact(uint64_t ncand, uint32_t nwords, const uint32_t*
         if (!ws.ok) return fail(FSS_ENOMEM, "%s: workspace too small", who);
         return launch_fused(ncand, nwords, d_table, seeds, sh, x1, v, parity ? 2u : 1u, d_out, d_rows_out, d_count, s);
     }
-    rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s);
+    const bool small = ncand <= kSmallPerm;
+    // the final round opens secFetch's bit, and the secAccess filter's parity
+    // of records of one slice; wider records are opened by k_open_parity
+    const uint32_t open = small ? 0u : !parity ? 1u : nwords <= 16 ? 2u : 0u;
+    rc = run_shuffle(ncand, nwords, d_table, seeds, sh, ws, s, open, flags);
     if (rc) return rc;
-    if (ncand <= kSmallPerm) {
+    if (small) {
         hipLaunchKernelGGL(k_open_compact_small, dim3(1), dim3(kSmallPerm), 0, s, (uint32_t)ncand, nwords,
                            (uint32_t)parity, sh[0], sh[1], sh[2], d_out[0], d_out[1], d_out[2], d_rows_out, d_count);
         return check_launch("k_open_compact_small");
     }
-    if (parity)
+    if (!open) {
         hipLaunchKernelGGL(k_open_parity, dim3((unsigned)((4 * ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
                            (uint32_t)((nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2])),
                            sh[0], sh[1], sh[2], flags);
-    else
-        hipLaunchKernelGGL(k_open_flags, dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s, ncand, nwords,
-                           sh[0], sh[1], sh[2], flags);
-    rc = check_launch("k_open");
-    if (rc) return rc;
+        rc = check_launch("k_open_parity");
+        if (rc) return rc;
+    }
     if (hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan, flags, pos, (int)ncand, s) != hipSuccess)
         return fail(FSS_EDEVICE, "%s: scan failed", who);
     if (parity && (nwords & 3u) == 0 && aligned16(sh[0]) && aligned16(sh[1]) && aligned16(sh[2]) &&
