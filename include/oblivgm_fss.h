@@ -602,6 +602,23 @@ int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[
                    const uint32_t* const d_attr[3], const uint64_t prf_keys[3], uint32_t counter,
                    const uint64_t seeds[3], uint32_t* const d_ids[3], uint32_t* const d_attrs[3],
                    uint32_t* d_rows_out, uint32_t* d_count, void* d_work, uint64_t work_bytes, void* stream);
+/* rss_sec_access_batch: `count` independent rss_sec_access calls over the
+ * same posting lists and attributes (Alg. 2 runs one per kept vertex),
+ * enqueued on `stream` in order c = 0 .. count-1, one call of the library
+ * instead of count.  Call c takes d_idm[3c .. 3c+2] (host array of device
+ * pointers), counters[c] and seeds[3c .. 3c+2] (host arrays), and writes
+ * d_ids[i] + c * lmax * ceil(x_bits/32), d_attrs[i] + c * lmax * attr_words,
+ * d_rows_out + c * lmax and d_count + c; its results are those of the single
+ * call with the same arguments.  One workspace of
+ * rss_sec_access_workspace_bytes(lmax, x_bits, attr_words) serves every call
+ * (they run in stream order).  count = 0 enqueues nothing.  EINVAL for a NULL
+ * array or pointer, and the errors of rss_sec_access (returned by the first
+ * call, before anything is enqueued). */
+int rss_sec_access_batch(uint32_t count, uint64_t ncand, uint32_t x_bits, const uint32_t* const* d_idm,
+                         const uint32_t* d_off, uint32_t lmax, const uint32_t* const d_post[3], uint32_t attr_words,
+                         const uint32_t* const d_attr[3], const uint64_t prf_keys[3], const uint32_t* counters,
+                         const uint64_t* seeds, uint32_t* const d_ids[3], uint32_t* const d_attrs[3],
+                         uint32_t* d_rows_out, uint32_t* d_count, void* d_work, uint64_t work_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -453,4 +453,36 @@ int rss_sec_access(uint64_t ncand, uint32_t x_bits, const uint32_t* const d_idm[
     return rss_reshare(32 * ta, t3, prf_keys, counter + 1, d_attrs, stream);
 }
 
+int rss_sec_access_batch(uint32_t count, uint64_t ncand, uint32_t x_bits, const uint32_t* const* d_idm,
+                         const uint32_t* d_off, uint32_t lmax, const uint32_t* const d_post[3], uint32_t attr_words,
+                         const uint32_t* const d_attr[3], const uint64_t prf_keys[3], const uint32_t* counters,
+                         const uint64_t* seeds, uint32_t* const d_ids[3], uint32_t* const d_attrs[3],
+                         uint32_t* d_rows_out, uint32_t* d_count, void* d_work, uint64_t work_bytes, void* stream) {
+    last_error().clear();
+    const char* who = "rss_sec_access_batch";
+    if (count == 0) return FSS_OK;
+    if (!d_idm || !counters || !seeds || !d_ids || !d_attrs || !d_rows_out || !d_count)
+        return fail(FSS_EINVAL, "%s: NULL argument", who);
+    for (uint64_t k = 0; k < 3ull * count; k++)
+        if (!d_idm[k]) return fail(FSS_EINVAL, "%s: NULL matched-ID share %llu", who, (unsigned long long)k);
+    for (int i = 0; i < 3; i++)
+        if (!d_ids[i] || !d_attrs[i]) return fail(FSS_EINVAL, "%s: NULL output share %d", who, i);
+    const uint64_t wx = (x_bits + 31) / 32;
+    for (uint32_t c = 0; c < count; c++) {
+        uint32_t* ids[3];
+        uint32_t* attrs[3];
+        for (int i = 0; i < 3; i++) {
+            ids[i] = d_ids[i] + (uint64_t)c * lmax * wx;
+            attrs[i] = d_attrs[i] + (uint64_t)c * lmax * attr_words;
+        }
+        // the shared arguments are checked by the first call; the rest differ
+        // only in pointers checked above
+        const int rc = rss_sec_access(ncand, x_bits, d_idm + 3ull * c, d_off, lmax, d_post, attr_words, d_attr,
+                                      prf_keys, counters[c], seeds + 3ull * c, ids, attrs,
+                                      d_rows_out + (uint64_t)c * lmax, d_count + c, d_work, work_bytes, stream);
+        if (rc) return rc;
+    }
+    return FSS_OK;
+}
+
 }  // extern "C"

@@ -122,6 +122,8 @@ def _load():
         "rss_enc_posting_lists": ([u64, u32, P, P, P, P, u64, P, u32, P, P, u64, P], ctypes.c_int),
         "rss_sec_access_workspace_bytes": ([u32, u32, u32], u64),
         "rss_sec_access": ([u64, u32, P, P, u32, P, u32, P, P, u32, P, P, P, P, P, P, u64, P], ctypes.c_int),
+        "rss_sec_access_batch": ([u32, u64, u32, P, P, u32, P, u32, P, P, P, P, P, P, P, P, P, u64, P],
+                                 ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -140,7 +142,7 @@ EXPORTS = ("fss_key_bytes", "fss_keybatch_bytes", "fss_last_error", "fss_version
            "rss_shuffle_prepared_workspace_bytes", "rss_shuffle_prepared", "rss_fetch_unique",
            "rss_fetch_many_workspace_bytes",
            "rss_fetch_many", "rss_compact_valid", "rss_sec_eval_records", "rss_fetch_table", "rss_group_k", "rss_group_k_lists", "rss_enc_posting_lists",
-           "rss_sec_access_workspace_bytes", "rss_sec_access")
+           "rss_sec_access_workspace_bytes", "rss_sec_access", "rss_sec_access_batch")
 
 
 def _check(rc: int):
@@ -569,6 +571,22 @@ def rss_enc_posting_lists(n: int, x_bits: int, adj_off, adj, slot, off, nrec: in
     _check(LIB.rss_enc_posting_lists(n, x_bits, _ptr(adj_off), _ptr(adj), _ptr(slot), _ptr(off), nrec,
                                      (ctypes.c_uint64 * 2)(*split_keys), counter, _ptr3(out3), _ptr(work),
                                      work.numel(), _stream(stream)))
+    return work
+
+
+def rss_sec_access_batch(ncand: int, x_bits: int, idm_ptrs, off, lmax: int, post3, attr_words: int, attr3,
+                         prf_keys, counters, seeds, ids3, attrs3, rows_out, count, stream=None):
+    """len(counters) secAccess calls in one library call: idm_ptrs holds the
+    3 device addresses of each call's matched-ID shares, seeds 3 values per
+    call; call c's outputs sit at offset c times one call's capacity."""
+    n = len(counters)
+    nbytes = int(LIB.rss_sec_access_workspace_bytes(lmax, x_bits, attr_words))
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=ids3[0].device)
+    _check(LIB.rss_sec_access_batch(n, ncand, x_bits, (ctypes.c_void_p * (3 * n))(*idm_ptrs), _ptr(off), lmax,
+                                    _ptr3(post3), attr_words, _ptr3(attr3), (ctypes.c_uint64 * 3)(*prf_keys),
+                                    (ctypes.c_uint32 * n)(*counters), (ctypes.c_uint64 * (3 * n))(*seeds),
+                                    _ptr3(ids3), _ptr3(attrs3), _ptr(rows_out), _ptr(count), _ptr(work),
+                                    work.numel(), _stream(stream)))
     return work
 
 

@@ -193,32 +193,47 @@ def sec_match(eg: EncodedGraph, query, tok_seed: int, prf_keys, counter0: int, s
         # the opens reveal how many candidates of each group match
         for k, m in enumerate(fetched.cpu().tolist()[:len(live)]):
             groups[i][live[k]].nkept = m
-        # secAccess of every kept vertex of every group, for each child target,
-        # enqueued without waiting; the validity opens' counts read together
+        # secAccess of every kept vertex of every group, for each child target:
+        # call k (in this order) takes counter + 2k and shuffle step + k; the
+        # calls of one child target go to the library as one batch, and the
+        # validity opens' counts are read together
         calls = [(gi, c, r) for gi in live for c in children[i] for r in range(groups[i][gi].nkept)]
-        counts = torch.zeros(max(len(calls), 1), dtype=torch.int32, device=dev)
-        made = []
-        for k, (gi, c, r) in enumerate(calls):
-            g, nt = groups[i][gi], query.targets[c]
+        made, batches = [None] * len(calls), []
+        for c in children[i]:
+            ks = [k for k, call in enumerate(calls) if call[1] == c]
+            if not ks:
+                continue
+            nt = query.targets[c]
             pair = (tgt.vtype, nt.vtype)
             wx2, wv2 = words(eg.n[nt.vtype]), words(eg.domains[(nt.vtype, nt.attr)])
             lmax = eg.lmax[pair]
-            idm = [g.kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
-            ids3 = [torch.empty(lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
-            vals3 = [torch.empty(lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
-            rows = torch.empty(lmax, dtype=torch.int32, device=dev)
-            seeds = (seed0 + 3 * step, seed0 + 3 * step + 1, seed0 + 3 * step + 2)
-            work = fss.rss_sec_access(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax, eg.post[pair], wv2,
-                                      eg.shares[("attr", nt.vtype, nt.attr)], prf_keys, counter, seeds, ids3, vals3,
-                                      rows, counts[k:k + 1])
-            counter += 2
-            step += 1
+            nc = len(ks)
+            idm, counters, seeds = [], [], []
+            for k in ks:
+                gi, _, r = calls[k]
+                idm += [groups[i][gi].kept[j].data_ptr() + 4 * r * (rec - 1) for j in range(3)]
+                counters.append(counter + 2 * k)
+                seeds += [seed0 + 3 * (step + k) + j for j in range(3)]
+            ids3 = [torch.empty(nc * lmax * wx2, dtype=torch.int32, device=dev) for _ in range(3)]
+            vals3 = [torch.empty(nc * lmax * wv2, dtype=torch.int32, device=dev) for _ in range(3)]
+            rows = torch.empty(nc * lmax, dtype=torch.int32, device=dev)
+            cnt = torch.empty(nc, dtype=torch.int32, device=dev)
+            work = fss.rss_sec_access_batch(eg.n[tgt.vtype], eg.n[nt.vtype], idm, eg.off[pair], lmax, eg.post[pair],
+                                            wv2, eg.shares[("attr", nt.vtype, nt.attr)], prf_keys, counters, seeds,
+                                            ids3, vals3, rows, cnt)
+            batches.append((ks, cnt))
             del work, rows
-            made.append((ids3, vals3))
-        if calls:
-            for k, m in enumerate(counts.cpu().tolist()[:len(calls)]):
-                gi, c, r = calls[k]
-                groups[c].append(_Group((i, gi, r), m, *made[k]))
+            for q_, k in enumerate(ks):
+                made[k] = ([t[q_ * lmax * wx2:(q_ + 1) * lmax * wx2] for t in ids3],
+                           [t[q_ * lmax * wv2:(q_ + 1) * lmax * wv2] for t in vals3])
+        counter += 2 * len(calls)
+        step += len(calls)
+        opened = [0] * len(calls)
+        for ks, cnt in batches:              # the first read waits for all of them
+            for k, m in zip(ks, cnt.cpu().tolist()):
+                opened[k] = m
+        for k, (gi, c, r) in enumerate(calls):
+            groups[c].append(_Group((i, gi, r), opened[k], *made[k]))
     return _results(groups, query, eg)
 
 

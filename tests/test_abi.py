@@ -312,6 +312,23 @@ def test_query_edges_schedule_and_errors(fss):
     assert L.match_workspace_bytes(ctypes.byref(one)) == 0
 
 
+def test_sec_access_batch_arguments(fss):
+    """The batch form rejects NULL arrays before anything is enqueued and
+    takes count 0 as nothing to do."""
+    L = fss.LIB
+    three = (ctypes.c_void_p * 3)(16, 32, 48)
+    keys = (ctypes.c_uint64 * 3)(1, 2, 3)
+    assert L.rss_sec_access_batch(0, 10, 64, None, None, 4, None, 1, None, None, None, None, None, None, None, None,
+                                  None, 0, None) == fss.OK
+    assert L.rss_sec_access_batch(2, 10, 64, None, 8, 4, three, 1, three, keys, (ctypes.c_uint32 * 2)(1, 3),
+                                  (ctypes.c_uint64 * 6)(*range(6)), three, three, 64, 72, 256, 1 << 20,
+                                  None) == fss.EINVAL and b"NULL" in L.fss_last_error()
+    idm = (ctypes.c_void_p * 6)(16, 32, 48, 16, None, 48)
+    assert L.rss_sec_access_batch(2, 10, 64, idm, 8, 4, three, 1, three, keys, (ctypes.c_uint32 * 2)(1, 3),
+                                  (ctypes.c_uint64 * 6)(*range(6)), three, three, 64, 72, 256, 1 << 20,
+                                  None) == fss.EINVAL and b"matched-ID share 4" in L.fss_last_error()
+
+
 def test_tuning_limits(fss):
     L = fss.LIB
     assert L.fss_set_keygen_tuning(0) == fss.EINVAL and L.fss_set_keygen_tuning(9) == fss.EINVAL

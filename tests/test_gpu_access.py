@@ -101,3 +101,47 @@ def test_sec_access_equals_oracle(fss, enc, pick):
     at = got_attrs[0] ^ got_attrs[1] ^ got_attrs[2]
     for r, a in zip(rec, at):
         np.testing.assert_array_equal(a, enc["attr"][int(access.unpack_onehot(r, X)[0])])
+
+
+def test_sec_access_batch_equals_oracle_per_call(fss, enc):
+    """rss_sec_access_batch over four matched vertices (long, short, empty and
+    middle lists), each call with its own counter and seeds: call c's slots
+    of the outputs equal the oracle's single secAccess with those arguments,
+    share for share."""
+    X, WX = enc["X"], enc["WX"]
+    lens = np.array([len(a) for a in enc["adj"]])
+    picks = [int(np.argmax(lens)), int(np.flatnonzero(lens == 1)[0]), int(np.flatnonzero(lens == 0)[0]),
+             int(np.flatnonzero(lens == 5)[0])]
+    rng = np.random.default_rng(77)
+    attr_sh = access.rss_split(enc["attr"], 88)
+    keys, lmax = [51, 52, 53], int(enc["padded"].max())
+    idm_t, idm_ptrs, counters, seeds, wants = [], [], [], [], []
+    for c, m in enumerate(picks):
+        idm = np.zeros(NC, np.uint8)
+        idm[m] = 1
+        sh = _split_bits(rng, idm)
+        ts = [T(_pack(b)) for b in sh]
+        idm_t.append(ts)
+        idm_ptrs += [t.data_ptr() for t in ts]
+        counters.append(20 + 2 * c)
+        sd = (300 + 3 * c, 301 + 3 * c, 302 + 3 * c)
+        seeds += list(sd)
+        wants.append(access.sec_access_csr(sh, enc["want"], enc["off"], attr_sh, X, keys, sd, 20 + 2 * c))
+    n = len(picks)
+    ids = [torch.full((n * lmax * WX,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    attrs = [torch.full((n * lmax * 2,), -1, dtype=torch.int32, device=DEV) for _ in range(3)]
+    rows = torch.full((n * lmax,), -1, dtype=torch.int32, device=DEV)
+    count = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    fss.rss_sec_access_batch(NC, X, idm_ptrs, enc["d_off"], lmax, list(enc["out"]), 2, [T(a) for a in attr_sh],
+                             keys, counters, seeds, ids, attrs, rows, count)
+    torch.cuda.synchronize()
+    got_count = U(count)
+    for c, m in enumerate(picks):
+        want_ids, want_attrs = wants[c]
+        kept = want_ids[0].shape[0]
+        assert int(got_count[c]) == kept == lens[m]
+        for i in range(3):
+            gi = U(ids[i]).reshape(n, lmax, WX)[c, :kept]
+            ga = U(attrs[i]).reshape(n, lmax, 2)[c, :kept]
+            np.testing.assert_array_equal(gi, want_ids[i], err_msg=f"call {c} ID share {i + 1}")
+            np.testing.assert_array_equal(ga, want_attrs[i], err_msg=f"call {c} attribute share {i + 1}")
