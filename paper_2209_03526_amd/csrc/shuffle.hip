@@ -482,6 +482,8 @@ __global__ __launch_bounds__(1024) void k_perm_place(ChachaKey pk, uint32_t p, u
     __syncthreads();
     uint64_t key[8], row0[4];
     const uint64_t q0 = (uint64_t)blockIdx.x * (kChunkRows / 8);
+    // the rows and keys of chunk_keys (which k_perm_count counts), unrolled
+    // so that the eight keys stay in registers
 #pragma unroll
     for (uint32_t it = 0; it < 4; it++) {         // kChunkRows / 2 lanes' worth: 4 x 1024
         const uint32_t t = tid + 1024u * it;
