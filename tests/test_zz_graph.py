@@ -221,12 +221,14 @@ def test_captured_query_batch_replays_bit_exact(fss):
                 np.testing.assert_array_equal(a[1], b[1], err_msg=f"replay {rep} query {i} output {j}")
 
 
-@pytest.mark.parametrize("n,w", [(5000, 4), ((1 << 16) + 37, 16)])
+@pytest.mark.parametrize("n,w", [(1000, 4), (5000, 4), ((1 << 16) + 37, 16)])
 def test_captured_shuffle_replays_bit_exact(fss, n, w):
     """rss_shuffle and its two parts (prepare, prepared) captured into one
     graph: under capture the permutations stay on the caller's stream and use
     no memset, so every replay -- with eager shuffles of another table and
-    synchronisations between the replays -- gives the oracle's shares."""
+    synchronisations between the replays -- gives the oracle's shares.  1000
+    records of 4 words take the one-workgroup shuffle, the others the wide
+    launches with bucket permutations."""
     from oracle import shuffle as osh
     rng = np.random.default_rng(n + w)
     sh = [rng.integers(0, 2**32, (n, w), dtype=np.uint64).astype(np.uint32) for _ in range(3)]
