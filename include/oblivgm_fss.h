@@ -429,12 +429,13 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  *   sort key of row r for pi12 / pi23 / pi31 = slice words 2e (low) and 2e+1
  *   (high), e = r mod 8, of block (r div 8, 0, 16+p, 0), p = 0 / 1 / 2;
  *   a permutation applied to a table gathers out[i] = in[perm[i]].
- * Tables of more than 1024 rows have their permutations made on two streams
- * of the library's own besides the caller's, ordered against the caller's
- * stream with events; smaller ones stay on the caller's stream (a table of at
- * most 1024 rows and 1024 16-word slices is shuffled by one workgroup).  Either
- * way the call's work is complete when the caller's stream reaches the call's
- * end.  On a stream
+ * Up to 2^23 rows the whole call runs on the caller's stream (a table of at
+ * most 1024 rows and 1024 16-word slices is shuffled by one workgroup); with
+ * more rows, or a radix permutation method (rss_set_shuffle_tuning), the
+ * permutations are made on two streams of the library's own besides the
+ * caller's, ordered against the caller's stream with events.  Either way the
+ * call's work is complete when the caller's stream reaches the call's end.
+ * On a stream
  * being captured into a graph, all of it stays on the caller's stream and
  * holds no memset, host copy or host wait, so rss_shuffle, rss_shuffle_prepare
  * and rss_shuffle_prepared can be captured and replayed (same seeds, same

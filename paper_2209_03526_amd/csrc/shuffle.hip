@@ -376,6 +376,18 @@ constexpr uint32_t kMaxBuckets = 2048;       // 2^(23 - 12)
 constexpr uint32_t kBucketCap = 7168;        // rows of a bucket held in LDS
 constexpr uint64_t kBucketMaxRows = 1ull << 23;
 
+// The three permutations of a shuffle, made together: blockIdx.y picks one.
+struct BucketSet {
+    ChachaKey pk[3];
+    uint32_t p[3], inverse[3];
+    uint32_t* perm[3];          // output: the permutation or its inverse
+    uint64_t* skeys[3];         // keys placed by bucket
+    uint32_t* srows[3];         // their row numbers
+    uint32_t* counts[3];        // per bucket and counting workgroup
+    uint32_t* totals[3];        // per bucket
+    uint32_t* starts[3];        // bucket starts, nb + 1
+};
+
 __device__ __forceinline__ uint32_t bucket_of(uint64_t key, uint32_t d1) {
     return d1 ? (uint32_t)(key >> (64 - d1)) : 0u;
 }
@@ -394,9 +406,12 @@ __device__ __forceinline__ void chunk_keys(ChachaKey pk, uint32_t p, uint64_t n,
     }
 }
 
-__global__ __launch_bounds__(1024) void k_perm_count(ChachaKey pk, uint32_t p, uint64_t n, uint32_t d1, uint32_t nblk,
-                                                     uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(1024) void k_perm_count(uint64_t n, uint32_t d1, uint32_t nblk, BucketSet S) {
     __shared__ uint32_t hist[kMaxBuckets];
+    const uint32_t q = blockIdx.y;
+    const ChachaKey pk = S.pk[q];
+    const uint32_t p = S.p[q];
+    uint32_t* __restrict__ counts = S.counts[q];
     const uint32_t nb = 1u << d1;
     for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
     __syncthreads();
@@ -423,10 +438,10 @@ __device__ __forceinline__ uint32_t block_scan256(uint32_t v, uint32_t* sh, uint
 
 // One workgroup (256 threads) per bucket: counts[bucket][w] becomes the
 // number of the bucket's rows in workgroups before w; totals[bucket] = all.
-__global__ __launch_bounds__(256) void k_bucket_offsets(uint32_t nblk, uint32_t* __restrict__ counts,
-                                                        uint32_t* __restrict__ totals) {
+__global__ __launch_bounds__(256) void k_bucket_offsets(uint32_t nblk, BucketSet S) {
     __shared__ uint32_t sh[256];
-    uint32_t* c = counts + (uint64_t)blockIdx.x * nblk;
+    uint32_t* __restrict__ totals = S.totals[blockIdx.y];
+    uint32_t* c = S.counts[blockIdx.y] + (uint64_t)blockIdx.x * nblk;
     const uint32_t per = (nblk + 255) / 256;       // at most 4 (nblk <= 1024)
     const uint32_t b0 = threadIdx.x * per;
     uint32_t v[4] = {0, 0, 0, 0}, sum = 0;
@@ -444,9 +459,10 @@ __global__ __launch_bounds__(256) void k_bucket_offsets(uint32_t nblk, uint32_t*
 }
 
 // One workgroup (256 threads): starts[b] = rows in buckets before b, b = 0 .. nb.
-__global__ __launch_bounds__(256) void k_bucket_starts(uint32_t nb, const uint32_t* __restrict__ totals,
-                                                       uint32_t* __restrict__ starts) {
+__global__ __launch_bounds__(256) void k_bucket_starts(uint32_t nb, BucketSet S) {
     __shared__ uint32_t sh[256];
+    const uint32_t* __restrict__ totals = S.totals[blockIdx.y];
+    uint32_t* __restrict__ starts = S.starts[blockIdx.y];
     const uint32_t per = (nb + 255) / 256;         // at most 8 (nb <= 2048)
     const uint32_t b0 = threadIdx.x * per;
     uint32_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sum = 0;
@@ -467,10 +483,14 @@ __global__ __launch_bounds__(256) void k_bucket_starts(uint32_t nb, const uint32
 // counted per bucket and grouped by bucket in LDS first, so that each thread
 // then stores consecutive positions of a bucket's range: the stores of a
 // wavefront cover a few contiguous segments instead of 64 scattered words.
-__global__ __launch_bounds__(1024) void k_perm_place(ChachaKey pk, uint32_t p, uint64_t n, uint32_t d1, uint32_t nblk,
-                                                     const uint32_t* __restrict__ counts,
-                                                     const uint32_t* __restrict__ starts,
-                                                     uint64_t* __restrict__ skeys, uint32_t* __restrict__ srows) {
+__global__ __launch_bounds__(1024) void k_perm_place(uint64_t n, uint32_t d1, uint32_t nblk, BucketSet S) {
+    const uint32_t q = blockIdx.y;
+    const ChachaKey pk = S.pk[q];
+    const uint32_t p = S.p[q];
+    const uint32_t* __restrict__ counts = S.counts[q];
+    const uint32_t* __restrict__ starts = S.starts[q];
+    uint64_t* __restrict__ skeys = S.skeys[q];
+    uint32_t* __restrict__ srows = S.srows[q];
     __shared__ uint64_t lkeys[kChunkRows];
     __shared__ uint32_t lrows[kChunkRows];
     __shared__ uint32_t loff[kMaxBuckets];     // the bucket's first slot in the workgroup's group
@@ -545,10 +565,14 @@ __device__ __forceinline__ void put_position(uint32_t* perm, uint32_t inverse, u
 
 // Bucket ranking; `mode` 0: networks where they apply, 1: exact comparisons
 // for every run, 2: every bucket ordered by comparing every pair.
-__global__ __launch_bounds__(1024) void k_bucket_rank(uint64_t n, uint32_t hb, uint32_t d1, uint32_t inverse,
-                                                      uint32_t mode, const uint32_t* __restrict__ starts,
-                                                      const uint64_t* __restrict__ skeys,
-                                                      const uint32_t* __restrict__ srows, uint32_t* __restrict__ perm) {
+__global__ __launch_bounds__(1024) void k_bucket_rank(uint64_t n, uint32_t hb, uint32_t d1, uint32_t mode,
+                                                      BucketSet S) {
+    const uint32_t q = blockIdx.y;
+    const uint32_t inverse = S.inverse[q];
+    const uint32_t* __restrict__ starts = S.starts[q];
+    const uint64_t* __restrict__ skeys = S.skeys[q];
+    const uint32_t* __restrict__ srows = S.srows[q];
+    uint32_t* __restrict__ perm = S.perm[q];
     __shared__ uint32_t part[kBucketCap];     // 25 key bits after the run id << 7 | slot in the run
     __shared__ uint32_t lrow[kBucketCap];     // row number
     __shared__ uint16_t sidx[kBucketCap];     // index in the bucket's range
@@ -1159,41 +1183,42 @@ uint32_t perm_method(uint64_t nrows, uint32_t m) {
     return m;
 }
 
-int perm_step_buckets(int step, uint64_t nrows, const PermJob& j, uint32_t method) {
+// The bucket method for all three permutations at once, five launches on
+// stream s (blockIdx.y picks the permutation).
+int bucket_perms(uint64_t nrows, const PermJob (&jobs)[3], uint32_t method, hipStream_t s) {
     const uint32_t hb = run_bits(nrows), d1 = bucket_bits(nrows), nb = 1u << d1;
     const uint32_t nblk = (uint32_t)((nrows + kChunkRows - 1) / kChunkRows);
-    const PermScratch& w = j.w;
-    // scratch: keys and rows placed by bucket in keys / idx, per-workgroup
-    // counts in keys_sorted, bucket totals and starts in idx_sorted
-    uint32_t* counts = (uint32_t*)w.keys_sorted;
-    uint32_t* totals = w.idx_sorted;
-    uint32_t* starts = w.idx_sorted + nb;
-    // the counts fit keys_sorted (8 bytes a row) and the totals and starts
-    // idx_sorted (4 bytes a row) for every table the method takes
+    // scratch of each permutation: keys and rows placed by bucket in keys /
+    // idx, per-workgroup counts in keys_sorted, bucket totals and starts in
+    // idx_sorted; they fit for every table the method takes
     if ((uint64_t)nb * nblk > 2 * nrows || 2ull * nb + 1 > nrows || nblk > 1024)
         return fail(FSS_EDEVICE, "rss_shuffle: bucket scratch does not fit");
-    switch (step) {
-        case 0:
-            hipLaunchKernelGGL(k_perm_count, dim3(nblk), dim3(1024), 0, j.s, j.pk, j.p, nrows, d1, nblk, counts);
-            return check_launch("k_perm_count");
-        case 1:
-            hipLaunchKernelGGL(k_bucket_offsets, dim3(nb), dim3(256), 0, j.s, nblk, counts, totals);
-            if (int rc = check_launch("k_bucket_offsets")) return rc;
-            hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(256), 0, j.s, nb, totals, starts);
-            return check_launch("k_bucket_starts");
-        case 2:
-            hipLaunchKernelGGL(k_perm_place, dim3(nblk), dim3(1024), 0, j.s, j.pk, j.p, nrows, d1, nblk, counts, starts,
-                               w.keys, w.idx);
-            return check_launch("k_perm_place");
-        default:
-            hipLaunchKernelGGL(k_bucket_rank, dim3(nb), dim3(1024), 0, j.s, nrows, hb, d1, (uint32_t)j.inverse,
-                               method - kPermBuckets, starts, w.keys, w.idx, j.perm);
-            return check_launch("k_bucket_rank");
+    BucketSet S{};
+    for (int q = 0; q < 3; q++) {
+        const PermScratch& w = jobs[q].w;
+        S.pk[q] = jobs[q].pk;
+        S.p[q] = jobs[q].p;
+        S.inverse[q] = jobs[q].inverse ? 1u : 0u;
+        S.perm[q] = jobs[q].perm;
+        S.skeys[q] = w.keys;
+        S.srows[q] = w.idx;
+        S.counts[q] = (uint32_t*)w.keys_sorted;
+        S.totals[q] = w.idx_sorted;
+        S.starts[q] = w.idx_sorted + nb;
     }
+    hipLaunchKernelGGL(k_perm_count, dim3(nblk, 3), dim3(1024), 0, s, nrows, d1, nblk, S);
+    if (int rc = check_launch("k_perm_count")) return rc;
+    hipLaunchKernelGGL(k_bucket_offsets, dim3(nb, 3), dim3(256), 0, s, nblk, S);
+    if (int rc = check_launch("k_bucket_offsets")) return rc;
+    hipLaunchKernelGGL(k_bucket_starts, dim3(1, 3), dim3(256), 0, s, nb, S);
+    if (int rc = check_launch("k_bucket_starts")) return rc;
+    hipLaunchKernelGGL(k_perm_place, dim3(nblk, 3), dim3(1024), 0, s, nrows, d1, nblk, S);
+    if (int rc = check_launch("k_perm_place")) return rc;
+    hipLaunchKernelGGL(k_bucket_rank, dim3(nb, 3), dim3(1024), 0, s, nrows, hb, d1, method - kPermBuckets, S);
+    return check_launch("k_bucket_rank");
 }
 
 int perm_step(int step, uint64_t nrows, const PermJob& j, uint32_t method) {
-    if (method >= kPermBuckets) return perm_step_buckets(step, nrows, j, method);
     const uint32_t hb = run_bits(nrows);
     const PermScratch& w = j.w;
     // with no run-id bits there is one run, already in row order: no sort
@@ -1282,14 +1307,15 @@ hipStream_t perm_stream(int i) {
     return it->second[i];
 }
 
-// The three permutations of a shuffle, made side by side: pi12 on the
-// caller's stream, pi31 and pi23 on the library's two streams (after
-// everything already on the caller's stream).  pi12 and pi31 are written as
-// their inverses (the first launch scatters through them), pi23 as is (the
-// final launch gathers through it).  join(i) makes the caller's stream wait
-// for pi31 (i = 0) or pi23 (i = 1); every join is enqueued whatever happened
-// before it, and finish() must follow, so that no work on the library's
-// streams outlives the caller's view of the call.
+// The three permutations of a shuffle.  pi12 and pi31 are written as their
+// inverses (the first launch scatters through them), pi23 as is (the final
+// launch gathers through it).  The bucket method makes all three in one
+// launch sequence on the caller's stream.  The radix methods make them side
+// by side: pi12 on the caller's stream, pi31 and pi23 on the library's two
+// streams (after everything already on the caller's stream); join(i) makes
+// the caller's stream wait for pi31 (i = 0) or pi23 (i = 1), every join is
+// enqueued whatever happened before it, and finish() must follow, so that no
+// work on the library's streams outlives the caller's view of the call.
 struct PermSet {
     hipStream_t s;
     hipStream_t side[2] = {nullptr, nullptr};
@@ -1329,23 +1355,31 @@ struct PermSet {
             return;
         }
         const uint32_t method = perm_method(nrows, g_perm_method.load());
-        // Under stream capture everything stays on the caller's stream, and
-        // only the bucket method (no sort library, so no memset nodes) runs.
+        // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1
+        if (method >= kPermBuckets) {
+            // the three permutations together, on the caller's stream (so also
+            // under stream capture: no sort library, no memset nodes)
+            const PermJob jobs[3] = {{pair_key(seeds[0]), kP12, true, inv12, pw[0], s},
+                                     {pair_key(seeds[2]), kP31, true, inv31, pw[1], s},
+                                     {pair_key(seeds[1]), kP23, false, p23, pw[2], s}};
+            rc = bucket_perms(nrows, jobs, method, s);
+            return;
+        }
+        // the radix methods: one permutation per stream, the caller's and the
+        // library's two; not under stream capture (their radix passes clear
+        // buffers with memset operations)
         hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
-        const bool capturing =
-            s && hipStreamIsCapturing(s, &capture) == hipSuccess && capture != hipStreamCaptureStatusNone;
-        if (capturing && method < kPermBuckets) {
+        if (s && hipStreamIsCapturing(s, &capture) == hipSuccess && capture != hipStreamCaptureStatusNone) {
             rc = fail(FSS_EUNSUPPORTED, "rss_shuffle: under stream capture at most 2^23 rows (bucket permutations)");
             return;
         }
-        if (!capturing) side[0] = perm_stream(0), side[1] = perm_stream(1);
+        side[0] = perm_stream(0), side[1] = perm_stream(1);
         forked = side[0] && side[1] && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&done[0], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&done[1], hipEventDisableTiming) == hipSuccess &&
                  hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side[0], fork, 0) == hipSuccess &&
                  hipStreamWaitEvent(side[1], fork, 0) == hipSuccess;
         const hipStream_t s31 = forked ? side[0] : s, s23 = forked ? side[1] : s;
-        // pair seeds: s12 -> pi12, T12, R2; s23 -> pi23, T23; s31 -> pi31, T31, R1
         const PermJob jobs[3] = {{pair_key(seeds[0]), kP12, true, inv12, pw[0], s},
                                  {pair_key(seeds[2]), kP31, true, inv31, pw[1], s31},
                                  {pair_key(seeds[1]), kP23, false, p23, pw[2], s23}};
