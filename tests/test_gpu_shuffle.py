@@ -181,6 +181,38 @@ def test_shuffle_full_size_is_a_permutation(fss):
         assert not torch.equal(o.view(n, w), d32)
 
 
+def test_shuffle_full_size_shares_equal_oracle_at_sampled_rows(fss):
+    """At 2^22 records of 64 bytes, all three output shares equal the oracle's
+    at 514 sampled rows (the first, the last and 512 at random): R1 and R2 are
+    the pairs' ChaCha12 mask words of those rows, and R3 = D[pi(i)] ^ R1 ^ R2
+    with pi the oracle's composed permutation (its T masks cancel)."""
+    from oracle import chacha
+    n, w = 1 << 22, 16
+    seeds = (51, 52, 53)
+    g = torch.Generator(device=DEV).manual_seed(6)
+    sh = [torch.randint(-2**31, 2**31, (n * w,), dtype=torch.int32, device=DEV, generator=g) for _ in range(3)]
+    out = [torch.empty(n * w, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_shuffle(n, w, sh, seeds, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(10)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 512, replace=False)])).astype(np.int64)
+    comp = osh.composed_permutation(*seeds, n)
+    idx = torch.from_numpy(rows).to(DEV)
+    src = torch.from_numpy(comp[rows].astype(np.int64)).to(DEV)
+    d_at = U(sh[0].view(n, w)[src] ^ sh[1].view(n, w)[src] ^ sh[2].view(n, w)[src])
+
+    def masks(seed, table):
+        r = rows.astype(np.uint64)
+        blk = osh._slices(chacha.blocks(osh.pair_key(seed), r, np.zeros_like(r), table, w, osh.ROUNDS))
+        return blk.reshape(len(rows), 16)[:, :w]
+
+    r1, r2 = masks(seeds[2], osh.R1), masks(seeds[0], osh.R2)
+    got = [U(o.view(n, w)[idx]) for o in out]
+    np.testing.assert_array_equal(got[0], r1)
+    np.testing.assert_array_equal(got[1], r2)
+    np.testing.assert_array_equal(got[2], d_at ^ r1 ^ r2)
+
+
 @pytest.mark.parametrize("n,w", [(1000, 8), (513, 4)])
 def test_shuffle_unaligned_buffers(fss, n, w):
     """Inputs and outputs 4 bytes past a 16-byte boundary: the gathers and the
