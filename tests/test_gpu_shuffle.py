@@ -213,6 +213,58 @@ def test_shuffle_full_size_shares_equal_oracle_at_sampled_rows(fss):
     np.testing.assert_array_equal(got[2], d_at ^ r1 ^ r2)
 
 
+def test_fetch_many_full_size(fss):
+    """secFetch Case II at the measured size (2^22 records: the bit word and 15
+    words, about half kept): the count is the number of set bits, the kept
+    records are exactly those rows' records (word 1 carries the row number)
+    in increasing shuffled position, and at 256 sampled kept records the three
+    shares equal the oracle's shuffle output at that position (R1, R2 from the
+    pairs' masks, R3 = D[pi(i)] ^ R1 ^ R2)."""
+    from oracle import chacha
+    n, w = 1 << 22, 16
+    seeds = (61, 62, 63)
+    g = torch.Generator(device=DEV).manual_seed(7)
+    row = torch.arange(n, dtype=torch.int32, device=DEV)
+    d = torch.randint(-2**31, 2**31, (n, w), dtype=torch.int32, device=DEV, generator=g)
+    d[:, 0] &= 1                                          # the predicate bit
+    d[:, 1] = row
+    s1 = torch.randint(-2**31, 2**31, (n, w), dtype=torch.int32, device=DEV, generator=g)
+    s2 = torch.randint(-2**31, 2**31, (n, w), dtype=torch.int32, device=DEV, generator=g)
+    sh = [s1.ravel(), s2.ravel(), (d ^ s1 ^ s2).ravel()]
+    out = [torch.empty(n * (w - 1), dtype=torch.int32, device=DEV) for _ in range(3)]
+    pos = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    fss.rss_fetch_many(n, w, sh, seeds, out, pos, cnt)
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    bits = d[:, 0].cpu().numpy()
+    assert k == int(bits.sum())
+    got_pos = U(pos)[:k].astype(np.int64)
+    assert np.all(np.diff(got_pos) > 0)
+    rec = (out[0][:k * (w - 1)] ^ out[1][:k * (w - 1)] ^ out[2][:k * (w - 1)]).view(k, w - 1)
+    ids = rec[:, 0].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(np.sort(ids), np.flatnonzero(bits == 1))
+    assert torch.equal(rec, d[torch.from_numpy(ids).to(DEV), 1:])
+    # the shares of sampled kept records against the oracle's shuffle output
+    comp = osh.composed_permutation(*seeds, n)
+    rng = np.random.default_rng(11)
+    ks = np.sort(rng.choice(k, 256, replace=False))
+    at = got_pos[ks]
+
+    def masks(seed, table):
+        r = at.astype(np.uint64)
+        blk = osh._slices(chacha.blocks(osh.pair_key(seed), r, np.zeros_like(r), table, w, osh.ROUNDS))
+        return blk.reshape(len(at), 16)[:, :w]
+
+    r1, r2 = masks(seeds[2], osh.R1), masks(seeds[0], osh.R2)
+    src = torch.from_numpy(comp[at].astype(np.int64)).to(DEV)
+    r3 = U(d[src]) ^ r1 ^ r2
+    kidx = torch.from_numpy(ks.astype(np.int64)).to(DEV)
+    got = [U(o.view(-1, w - 1)[:k][kidx]) for o in out]
+    for j, want in enumerate((r1, r2, r3)):
+        np.testing.assert_array_equal(got[j], want[:, 1:], err_msg=f"share {j + 1}")
+
+
 @pytest.mark.parametrize("n,w", [(1000, 8), (513, 4)])
 def test_shuffle_unaligned_buffers(fss, n, w):
     """Inputs and outputs 4 bytes past a 16-byte boundary: the gathers and the
