@@ -246,3 +246,52 @@ def test_sec_eval_records_parity(fss, kind, npos, ncand):
         xs.append(U(out))
     truth = (values == a) if kind == "eq" else ((values >= lo) & (values < hi))
     np.testing.assert_array_equal(ofss.unpack_bits(xs[0] ^ xs[1] ^ xs[2], ncand), truth.astype(np.uint8))
+
+
+def test_sec_eval_full_size(fss):
+    """secEval at the measured size (2^20 candidates, 4096 positions, a range
+    predicate): the three servers' bits XOR to the plaintext predicate for
+    every candidate, and at 256 sampled candidates each server's bit equals
+    the oracle's Eq. predEval on those candidates' shares."""
+    ncand, npos, kind = 1 << 20, 4096, "range"
+    nw = npos // 32
+    rng = np.random.default_rng(12)
+    values = rng.integers(0, npos, ncand).astype(np.int64)
+    lo, hi = 1000, 3100
+    seed, q, p = 78, 6, 2
+    g = torch.Generator(device=DEV).manual_seed(8)
+    s1 = torch.randint(-2**31, 2**31, (nw, ncand), dtype=torch.int32, device=DEV, generator=g)
+    s2 = torch.randint(-2**31, 2**31, (nw, ncand), dtype=torch.int32, device=DEV, generator=g)
+    s3 = s1 ^ s2
+    v = torch.from_numpy(values).to(DEV)
+    flat = s3.view(-1)
+    idx = (v >> 5) * ncand + torch.arange(ncand, device=DEV)
+    bit = torch.bitwise_left_shift(torch.ones_like(v), v & 31).to(torch.int64)
+    bit = (bit - (bit >= 2**31).to(torch.int64) * 2**32).to(torch.int32)
+    flat[idx] = flat[idx] ^ bit                         # one-hot word-major, candidate c at column c
+    dev_sh = [s1.ravel(), s2.ravel(), s3.ravel()]
+    kb, nb = _gpu_token(fss, kind, npos, seed, q, p, lo=lo, hi=hi)
+    ev = {}
+    for party in (0, 1):
+        for rep in range(3):
+            ev[(party, rep)] = torch.zeros(nw, dtype=torch.int32, device=DEV)
+            fss.fss_eval_all(party, kb, rep, npos, ev[(party, rep)])
+    xs = []
+    for i, ((pa, ra, ja), (pb, rb, jb)) in enumerate(orss.SERVER_TERMS):
+        out = torch.full((ncand // 32,), -1, dtype=torch.int32, device=DEV)
+        fss.rss_sec_eval(ncand, npos, ev[(pa, ra)], ev[(pb, rb)], dev_sh[ja], dev_sh[jb], out)
+        xs.append(U(out))
+    truth = ((values >= lo) & (values < hi)).astype(np.uint8)
+    np.testing.assert_array_equal(ofss.unpack_bits(xs[0] ^ xs[1] ^ xs[2], ncand), truth)
+    # sampled candidates against the oracle
+    okeys, nb_o = orss.token(kind, npos, seed, q, p, lo=lo, hi=hi)
+    assert nb_o == nb
+    cs = np.sort(rng.choice(ncand, 256, replace=False))
+    cidx = torch.from_numpy(cs).to(DEV)
+    sub = []
+    for sj in (s1, s2, s3):
+        words = U(sj[:, cidx].contiguous()).reshape(nw, len(cs)).T.copy()      # (256, nw)
+        sub.append(np.unpackbits(words.view(np.uint8).reshape(len(cs), nw * 4), axis=1, bitorder="little"))
+    want = orss.server_shares(kind, npos, okeys, nb, np.stack(sub))
+    for i in range(3):
+        np.testing.assert_array_equal(ofss.unpack_bits(xs[i], ncand)[cs], want[i], err_msg=f"server {i + 1}")
