@@ -89,6 +89,17 @@ def prf_words(key_seed: int, counter: int, nwords: int) -> np.ndarray:
     return words[:nwords].astype(np.uint32)
 
 
+def prf_words_at(key_seed: int, counter: int, idx) -> np.ndarray:
+    """Words idx (any indices) of F(k, j) as ``prf_words`` defines them, making
+    only the blocks that hold them (for samples of very long streams)."""
+    k = key_seed & ((1 << 64) - 1)
+    idx = np.asarray(idx, dtype=np.int64)
+    blk = np.unique(idx // 16)
+    words = chacha.blocks([k & 0xFFFFFFFF, k >> 32, 5, 0, 0, 0, 0, 0], blk.astype(np.uint64), counter, 0, 0, 12)
+    words = words.reshape(-1, 4, 4).transpose(0, 2, 1).reshape(-1, 16)
+    return words[np.searchsorted(blk, idx // 16), idx % 16].astype(np.uint32)
+
+
 def zero_shares(prf_keys, counter: int, nwords: int):
     """<alpha>_i = F(k_i, j) ^ F(k_{i-1}, j): three shares of 0 (Sec. III-B)."""
     f = [prf_words(k, counter, nwords) for k in prf_keys]

@@ -145,3 +145,54 @@ def test_sec_access_batch_equals_oracle_per_call(fss, enc):
             ga = U(attrs[i]).reshape(n, lmax, 2)[c, :kept]
             np.testing.assert_array_equal(gi, want_ids[i], err_msg=f"call {c} ID share {i + 1}")
             np.testing.assert_array_equal(ga, want_attrs[i], err_msg=f"call {c} attribute share {i + 1}")
+
+
+def test_sec_access_measured_size(fss):
+    """secAccess at the measured size (65,536 candidates, 16,384 neighbour IDs:
+    2 KB one-hot records, lists of 0..24 IDs, k = 4): for the vertex with the
+    longest list, the opened count is its true length, the kept ID records
+    reconstruct to its neighbours and the attribute records to theirs; and the
+    encoder's first two shares equal the oracle's PRF words at 64 sampled
+    records (the third is the records XOR both)."""
+    from oracle import rss as orss
+    nc, xbits = 1 << 16, 1 << 14
+    wx = xbits // 32
+    types, adj, attr = synth.posting_graph(33, nc, xbits, 24, n_types=2)
+    lengths = np.array([len(a) for a in adj], np.uint32)
+    padded, _ = fss.rss_group_k(lengths, types, 4)
+    slots = synth.posting_slots(34, lengths, padded)
+    off = np.concatenate([[0], np.cumsum(padded)]).astype(np.uint32)
+    nrec, lmax = int(off[-1]), int(padded.max())
+    adj_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
+    d_off = T(off)
+    post = [torch.empty(nrec * wx, dtype=torch.int32, device=DEV) for _ in range(3)]
+    fss.rss_enc_posting_lists(nc, xbits, T(adj_off), T(np.concatenate(adj).astype(np.uint32)), T(slots), d_off, nrec,
+                              (91, 92), 7, post)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(35)
+    recs = np.sort(rng.choice(nrec, 64, replace=False))
+    for j, key in enumerate((91, 92)):
+        words = (recs[:, None] * wx + np.arange(wx)[None, :]).ravel()
+        want = orss.prf_words_at(key, 7, words).reshape(len(recs), wx)
+        got = U(post[j]).reshape(nrec, wx)[recs]
+        np.testing.assert_array_equal(got, want, err_msg=f"share {j + 1}")
+    m = int(np.argmax(lengths))
+    idm = np.zeros(nc, np.uint8)
+    idm[m] = 1
+    idm_sh = _split_bits(rng, idm)
+    attr_sh = access.rss_split(attr, 36)
+    ids = [torch.empty(lmax * wx, dtype=torch.int32, device=DEV) for _ in range(3)]
+    attrs = [torch.empty(lmax * 2, dtype=torch.int32, device=DEV) for _ in range(3)]
+    rows = torch.empty(lmax, dtype=torch.int32, device=DEV)
+    count = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    fss.rss_sec_access(nc, xbits, [T(_pack(b)) for b in idm_sh], d_off, lmax, post, 2, [T(a) for a in attr_sh],
+                       [51, 52, 53], 9, (61, 62, 63), ids, attrs, rows, count)
+    torch.cuda.synchronize()
+    kept = int(U(count)[0])
+    assert kept == lengths[m]
+    rec = U(ids[0]).reshape(lmax, wx)[:kept] ^ U(ids[1]).reshape(lmax, wx)[:kept] ^ U(ids[2]).reshape(lmax, wx)[:kept]
+    nb = [int(access.unpack_onehot(r, xbits)[0]) for r in rec]
+    assert sorted(nb) == adj[m].tolist()
+    at = U(attrs[0]).reshape(lmax, 2)[:kept] ^ U(attrs[1]).reshape(lmax, 2)[:kept] ^ U(attrs[2]).reshape(lmax, 2)[:kept]
+    for v, a in zip(nb, at):
+        np.testing.assert_array_equal(a, attr[v])

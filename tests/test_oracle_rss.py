@@ -121,6 +121,15 @@ def test_prf_words_follow_their_definition():
         assert int(got[w]) == int(blk[4 * (s % 4) + s // 4])
 
 
+def test_prf_words_at_equals_the_stream():
+    """The sampled accessor gives the stream's own words, in any order and
+    with repeats, across block boundaries."""
+    k, j = 0x0123_4567_89AB_CDEF, 4
+    full = rss.prf_words(k, j, 1000)
+    idx = np.array([999, 0, 15, 16, 17, 500, 15, 31, 32, 733])
+    np.testing.assert_array_equal(rss.prf_words_at(k, j, idx), full[idx])
+
+
 def test_two_party_fss_bits_to_rss_then_and():
     """The masked-input path's two-party predicate shares, converted to RSS
     and ANDed in RSS, reconstruct to the conjunction of the plaintext
