@@ -435,15 +435,12 @@ int rss_and(uint64_t nrows, const uint32_t* const d_x[3], const uint32_t* const 
  * permutations are made on two streams of the library's own besides the
  * caller's, ordered against the caller's stream with events.  Either way the
  * call's work is complete when the caller's stream reaches the call's end.
- * On a stream
- * being captured into a graph, all of it stays on the caller's stream and
- * holds no memset, host copy or host wait, so rss_shuffle, rss_shuffle_prepare
- * and rss_shuffle_prepared can be captured and replayed (same seeds, same
- * permutations) for tables of at most 2^23 rows; beyond that, or with a
- * radix permutation method (rss_set_shuffle_tuning), they return
- * FSS_EUNSUPPORTED under capture (their radix passes clear buffers with
- * memset operations).  rss_fetch_many, rss_compact_valid and rss_sec_access
- * are not for capture.
+ * Up to 2^23 rows the calls hold no memset, host copy or host wait, so
+ * rss_shuffle, rss_shuffle_prepare and rss_shuffle_prepared can be captured
+ * into a graph and replayed (same seeds, same permutations); beyond that, or
+ * with a radix permutation method, they return FSS_EUNSUPPORTED on a stream
+ * being captured (their radix passes clear buffers with memset operations).
+ * rss_fetch_many, rss_compact_valid and rss_sec_access are not for capture.
  * The messages follow the algorithm (its X_2 in CS2's step is the X1 it
  * received): X1 = pi31[pi12(D1^D2^T12)^T31]; Y1 = pi12(D3^T12);
  * C1 = pi23(X1^T23)^R2; C2 = pi23[pi31(Y1^T31)^T23]^R1; R3 = C1^C2.
@@ -587,8 +584,8 @@ int rss_get_shuffle_tuning(uint32_t* perm_method);
  *        re-shared together (counter + 1) into d_attrs[i] (capacity lmax x
  *        attr_words; rows beyond *d_count are shares of zero).
  *   Workspace: rss_sec_access_workspace_bytes(lmax, x_bits, attr_words).  lmax
- *   is 1..65535.  The shuffle takes the library's own streams as rss_shuffle
- *   does (not for graph capture).
+ *   is 1..65535.  Its shuffle runs as rss_shuffle's does (on the caller's
+ *   stream at these sizes); not for graph capture.
  */
 int rss_group_k(uint64_t n, const uint32_t* lengths, const uint32_t* types, uint32_t k, uint32_t* padded,
                 uint32_t* group);
