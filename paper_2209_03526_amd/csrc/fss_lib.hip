@@ -1886,17 +1886,30 @@ uint64_t queue_bytes(uint64_t count) {
     return kQueueHeader + ((count * per + 255) & ~255ull);
 }
 
-// Heaviest descriptors first (ranges, then larger tables), tile offsets, one
-// launch.  as_args: the descriptors travel as kernel arguments (no staging).
-int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_bytes, hipStream_t s,
-                      bool as_args = false) {
+// Queue order of two requests: ranges before equalities, larger tables first;
+// equal keys keep their request order (the sort is stable).
+bool eval_before(uint32_t kind_a, uint64_t n_a, uint32_t kind_b, uint64_t n_b) {
+    const bool ra = kind_a == FSS_RANGE, rb = kind_b == FSS_RANGE;
+    return ra != rb ? ra : n_a > n_b;
+}
+
+// The persistent evaluation over a queue already in device memory.
+int launch_eval_kernel(const QEval* dq, uint32_t n, uint64_t tiles, uint32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
+    hipLaunchKernelGGL(k_eval_queue, dim3((unsigned)grid), dim3(kBlock), 0, s, dq, n, (uint32_t)tiles,
+                       g_tuning.rows_per_thread, counter);
+    return check_launch("k_eval_queue");
+}
+
+// Heaviest descriptors first, tile offsets, one upload, one launch.
+int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_bytes, hipStream_t s) {
     std::vector<QEval> q;
     q.reserve(descs.size());
-    for (int pass = 0; pass < 2; pass++)
-        for (auto& d : descs)
-            if ((pass == 0) == (d.kind == FSS_RANGE) && d.n > 0) q.push_back(QEval{d});
+    for (auto& d : descs)
+        if (d.n > 0) q.push_back(QEval{d});
     std::stable_sort(q.begin(), q.end(), [](const QEval& a, const QEval& b) {
-        return (a.d.kind == FSS_RANGE) != (b.d.kind == FSS_RANGE) ? a.d.kind == FSS_RANGE : a.d.n > b.d.n;
+        return eval_before(a.d.kind, a.d.n, b.d.kind, b.d.n);
     });
     if (q.empty()) return FSS_OK;
     const uint64_t tile_rows = (uint64_t)kBlock * g_tuning.rows_per_thread;
@@ -1911,14 +1924,9 @@ int launch_eval_queue(std::vector<EvalDesc>& descs, void* d_ws, uint64_t ws_byte
         return fail(FSS_ENOMEM, "batch: queue workspace needs %llu bytes", (unsigned long long)need);
     uint32_t* counter = (uint32_t*)d_ws;
     QEval* dq = (QEval*)((uint8_t*)d_ws + kQueueHeader);
-    int rc = as_args ? upload_as_arguments(q.data(), q.size() * sizeof(QEval), dq, s)
-                     : upload(q.data(), q.size() * sizeof(QEval), dq, s);
+    const int rc = upload(q.data(), q.size() * sizeof(QEval), dq, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
-    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)g_tuning.wg_per_cu * device_cus());
-    hipLaunchKernelGGL(k_eval_queue, dim3((unsigned)grid), dim3(kBlock), 0, s, dq, (uint32_t)q.size(),
-                       (uint32_t)tiles, g_tuning.rows_per_thread, counter);
-    return check_launch("k_eval_queue");
+    return launch_eval_kernel(dq, (uint32_t)q.size(), tiles, counter, s);
 }
 
 // Device image of a batch's tail: the plans' key schedules, then the ops of
@@ -1971,27 +1979,34 @@ int launch_tail_queue(const match_plan* plans, uint32_t count, const std::vector
 }
 
 // Requests of a batch evaluation -> descriptors (same checks as the single calls).
+// One request's checks; *d gets its descriptor (d->n == 0: nothing to evaluate).
+int eval_request(const fss_eval_req& r, uint32_t i, const char* who, EvalDesc* d) {
+    if (!r.keys) return fail(FSS_EINVAL, "%s: request %u has no keys", who, i);
+    int rc = check_batch(r.keys, r.keys->kind, who);
+    if (rc) return rc;
+    if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "%s: request %u party", who, i);
+    *d = EvalDesc{};
+    if (r.keys->n == 0) return FSS_OK;
+    if (!r.d_xhat || !r.d_out_bits || !r.keys->key[r.party] || !aligned256(r.keys->key[r.party]))
+        return fail(FSS_EINVAL, "%s: request %u buffers", who, i);
+    d->key = (const uint8_t*)r.keys->key[r.party];
+    d->xhat = r.d_xhat;
+    d->out = r.d_out_bits;
+    d->n = r.keys->n;
+    d->kind = (uint32_t)r.keys->kind;
+    d->nbits = r.keys->nbits;
+    d->party = (uint32_t)r.party;
+    return FSS_OK;
+}
+
 int eval_requests(const fss_eval_req* reqs, uint32_t count, std::vector<EvalDesc>& descs, const char* who) {
     if (!reqs) return fail(FSS_EINVAL, "%s: reqs is NULL", who);
     descs.reserve(count);
     for (uint32_t i = 0; i < count; i++) {
-        const fss_eval_req& r = reqs[i];
-        if (!r.keys) return fail(FSS_EINVAL, "%s: request %u has no keys", who, i);
-        int rc = check_batch(r.keys, r.keys->kind, who);
+        EvalDesc d;
+        const int rc = eval_request(reqs[i], i, who, &d);
         if (rc) return rc;
-        if (r.party != 0 && r.party != 1) return fail(FSS_EINVAL, "%s: request %u party", who, i);
-        if (r.keys->n == 0) continue;
-        if (!r.d_xhat || !r.d_out_bits || !r.keys->key[r.party] || !aligned256(r.keys->key[r.party]))
-            return fail(FSS_EINVAL, "%s: request %u buffers", who, i);
-        EvalDesc d{};
-        d.key = (const uint8_t*)r.keys->key[r.party];
-        d.xhat = r.d_xhat;
-        d.out = r.d_out_bits;
-        d.n = r.keys->n;
-        d.kind = (uint32_t)r.keys->kind;
-        d.nbits = r.keys->nbits;
-        d.party = (uint32_t)r.party;
-        descs.push_back(d);
+        if (d.n) descs.push_back(d);
     }
     return FSS_OK;
 }
@@ -2359,16 +2374,70 @@ int fss_eval_batch(const fss_eval_req* reqs, uint32_t count, void* d_queue, uint
 
 int fss_eval_batch_noalloc(const fss_eval_req* reqs, uint32_t count, void* stream) {
     ogm::last_error().clear();
+    const char* who = "fss_eval_batch_noalloc";
     if (count == 0) return FSS_OK;
     if (count > FSS_NOALLOC_EVAL_MAX)
-        return fail(FSS_EINVAL, "fss_eval_batch_noalloc: %u requests, at most %d", count, FSS_NOALLOC_EVAL_MAX);
-    std::vector<EvalDesc> descs;
-    int rc = eval_requests(reqs, count, descs, "fss_eval_batch_noalloc");
-    if (rc) return rc;
+        return fail(FSS_EINVAL, "%s: %u requests, at most %d", who, count, FSS_NOALLOC_EVAL_MAX);
+    if (!reqs) return fail(FSS_EINVAL, "%s: reqs is NULL", who);
+    // Host side without allocation: the queue order (as fss_eval_batch's) is a
+    // stable bottom-up merge of 16-bit request indices on the stack, and the
+    // descriptors go out as kernel arguments, one chunk at a time.
+    static_assert(FSS_NOALLOC_EVAL_MAX <= 65536, "indices are 16-bit");
+    uint16_t idx[2][FSS_NOALLOC_EVAL_MAX];
+    uint32_t m = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        EvalDesc d;
+        const int rc = eval_request(reqs[i], i, who, &d);
+        if (rc) return rc;
+        if (d.n) idx[0][m++] = (uint16_t)i;
+    }
+    if (m == 0) return FSS_OK;
+    auto before = [&](uint16_t a, uint16_t b) {
+        return eval_before((uint32_t)reqs[a].keys->kind, reqs[a].keys->n, (uint32_t)reqs[b].keys->kind,
+                           reqs[b].keys->n);
+    };
+    int cur = 0;
+    for (uint32_t w = 1; w < m; w *= 2, cur ^= 1) {
+        const uint16_t* src = idx[cur];
+        uint16_t* dst = idx[cur ^ 1];
+        for (uint32_t lo = 0; lo < m; lo += 2 * w) {
+            const uint32_t mid = std::min(lo + w, m), hi = std::min(lo + 2 * w, m);
+            uint32_t a = lo, b = mid, o = lo;
+            while (a < mid && b < hi) dst[o++] = before(src[b], src[a]) ? src[b++] : src[a++];
+            while (a < mid) dst[o++] = src[a++];
+            while (b < hi) dst[o++] = src[b++];
+        }
+    }
+    const uint16_t* order = idx[cur];
+    const uint64_t tile_rows = (uint64_t)kBlock * g_tuning.rows_per_thread;
+    uint64_t tiles = 0;
+    for (uint32_t j = 0; j < m; j++) tiles += (reqs[order[j]].keys->n + tile_rows - 1) / tile_rows;
+    if (tiles > 0xFFFFFFF0ull) return fail(FSS_EUNSUPPORTED, "%s: too many tiles", who);
     void* d_scratch = nullptr;
-    rc = scratch_ptr(&d_scratch, "fss_eval_batch_noalloc");
+    int rc = scratch_ptr(&d_scratch, who);
     if (rc) return rc;
-    return launch_eval_queue(descs, d_scratch, kScratchBytes, (hipStream_t)stream, true);
+    uint32_t* counter = (uint32_t*)d_scratch;
+    QEval* dq = (QEval*)((uint8_t*)d_scratch + kQueueHeader);
+    hipStream_t s = (hipStream_t)stream;
+    constexpr uint32_t kPerChunk = kArgChunk / sizeof(QEval);
+    static_assert(sizeof(QEval) % 4 == 0, "descriptors are whole words");
+    uint64_t tile = 0;
+    for (uint32_t first = 0; first < m; first += kPerChunk) {
+        const uint32_t nq = std::min(kPerChunk, m - first);
+        ArgChunk c{};
+        for (uint32_t j = 0; j < nq; j++) {
+            QEval e{};
+            eval_request(reqs[order[first + j]], order[first + j], who, &e.d);   // checked above
+            e.d.block_start = (uint32_t)tile;
+            tile += (e.d.n + tile_rows - 1) / tile_rows;
+            memcpy((uint8_t*)c.w + (size_t)j * sizeof(QEval), &e, sizeof(QEval));
+        }
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, (uint32_t*)(dq + first),
+                           (uint32_t)(nq * sizeof(QEval) / 4), c);
+        rc = check_launch("k_put_words");
+        if (rc) return rc;
+    }
+    return launch_eval_kernel(dq, m, tiles, counter, s);
 }
 
 int match_query_batch(const match_plan* plans, uint32_t count, int32_t party_mask, void* d_queue,

@@ -24,9 +24,9 @@ def _requests(fss, rows_kinds, seed):
         r = T(rng.integers(0, 2**32, rows, dtype=np.uint64).astype(np.uint32))
         xhat = T(rng.integers(0, 2**32, rows, dtype=np.uint64).astype(np.uint32))
         kb = fss.KeyBatch(kind, 32, rows)
-        if kind == fss.EQ:
+        if rows and kind == fss.EQ:
             fss.fss_keygen(seed, 5, k, 12345, 0, r, kb)
-        else:
+        elif rows:
             fss.fss_keygen(seed, 5, k, 1000, 3_000_000_000, r, kb)
         for b in range(2):
             a = torch.full((fss.words(rows),), -1, dtype=torch.int32, device=DEV)
@@ -44,6 +44,24 @@ def test_eval_batch_noalloc_equals_queue_path(fss):
     ]
     for call, rows_kinds in enumerate(calls):
         reqs, outs = _requests(fss, rows_kinds, 900 + call)
+        fss.fss_eval_batch([(*q, a) for q, a, _ in reqs], queue)
+        fss.fss_eval_batch_noalloc([(*q, n) for q, _, n in reqs])
+        torch.cuda.synchronize()
+        for i, (a, n) in enumerate(outs):
+            np.testing.assert_array_equal(U(n), U(a), err_msg=f"call {call} request {i}")
+
+
+def test_eval_batch_noalloc_many_requests(fss):
+    """Several argument chunks of descriptors (42 to a chunk), empty requests
+    among them, equal row counts whose order must stay stable, then a smaller
+    call."""
+    queue = fss.Queue(64)
+    rng = np.random.default_rng(77)
+    big = [(int(rng.choice([0, 1, 64, 1000, 2049, 3000])), fss.RANGE if rng.random() < 0.5 else fss.EQ)
+           for _ in range(70)]
+    calls = [big, [(2049, fss.EQ), (0, fss.RANGE), (17, fss.RANGE)]]
+    for call, rows_kinds in enumerate(calls):
+        reqs, outs = _requests(fss, rows_kinds, 950 + call)
         fss.fss_eval_batch([(*q, a) for q, a, _ in reqs], queue)
         fss.fss_eval_batch_noalloc([(*q, n) for q, _, n in reqs])
         torch.cuda.synchronize()
