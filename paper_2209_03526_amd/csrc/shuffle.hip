@@ -745,20 +745,26 @@ __device__ __forceinline__ void first_slice(uint64_t t, uint64_t nrows, uint32_t
     const uint64_t sl = t >> 2;
     const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
     const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
-    // a quad shares its record, so these exits keep quads whole; they only
-    // matter for permutations that were not made by this library
+    // The blocks that do not need the load in flight are drawn while it is:
+    // T12 while inv12[i] is, R2 and R1 while inv31[j] is.  A quad shares its
+    // record, so the exits keep quads whole; they only matter for
+    // permutations that were not made by this library, and then leave the
+    // row unwritten.
+    const uint64_t src = (uint64_t)i * nwords + 16 * b;
     const uint32_t j = inv12[i];
-    if (j >= nrows) return;
-    const uint32_t l = inv31[j];
-    if (l >= nrows) return;
-    const uint64_t src = (uint64_t)i * nwords + 16 * b, dst = (uint64_t)l * nwords + 16 * b;
     const uint4 x = load_quarter<VEC>(g0, src, c, len), y = load_quarter<VEC>(g1, src, c, len);
     const uint4 z = load_quarter<VEC>(g2, src, c, len);
-    const uint4 m = xor4(chacha_quad(k12, i, b, kT12, nwords), chacha_quad(k31, j, b, kT31, nwords));
+    const uint4 t12 = chacha_quad(k12, i, b, kT12, nwords);
+    if (j >= nrows) return;
+    const uint32_t l = inv31[j];
+    const uint4 r2 = chacha_quad(k12, i, b, kR2, nwords), r1 = chacha_quad(k31, i, b, kR1, nwords);
+    const uint4 m = xor4(t12, chacha_quad(k31, j, b, kT31, nwords));
+    if (l >= nrows) return;
+    const uint64_t dst = (uint64_t)l * nwords + 16 * b;
+    store_quarter<VEC>(r12, src, c, len, r2);
+    store_quarter<VEC>(r31, src, c, len, r1);
     store_quarter<VEC>(o0, dst, c, len, xor4(xor4(x, y), m));
     store_quarter<VEC>(o1, dst, c, len, xor4(z, m));
-    store_quarter<VEC>(r12, src, c, len, chacha_quad(k12, i, b, kR2, nwords));
-    store_quarter<VEC>(r31, src, c, len, chacha_quad(k31, i, b, kR1, nwords));
 }
 
 template <bool VEC>
@@ -800,6 +806,8 @@ __device__ __forceinline__ void final_slice(uint64_t t, uint64_t nrows, uint32_t
     const uint32_t i = (uint32_t)(sl / nb), b = (uint32_t)(sl - (uint64_t)i * nb);
     const uint32_t len = nwords - 16 * b < 16 ? nwords - 16 * b : 16;
     const uint32_t p = perm[i];
+    // R2 and R1 (indexed by the output row) while the load of p is in flight
+    const uint4 r2 = chacha_quad(k12, i, b, kR2, nwords), r1 = chacha_quad(k31, i, b, kR1, nwords);
     if (p >= nrows) {                // as in first_slice
         if (open && b == 0 && c == 0) flags[i] = 0u;
         return;
@@ -809,8 +817,8 @@ __device__ __forceinline__ void final_slice(uint64_t t, uint64_t nrows, uint32_t
     const uint4 m = chacha_quad(k23, p, b, kT23, nwords);
     uint4 c1 = xor4(x, m);
     pin(c1);
-    c1 = xor4(c1, chacha_quad(k12, i, b, kR2, nwords));
-    const uint4 c2 = xor4(xor4(y, m), chacha_quad(k31, i, b, kR1, nwords));
+    c1 = xor4(c1, r2);
+    const uint4 c2 = xor4(xor4(y, m), r1);
     store_quarter<VEC>(out, dst, c, len, xor4(c1, c2));
     if (open == 1) {
         if (b == 0 && c == 0) flags[i] = (x.x ^ y.x) & 1u;
