@@ -59,7 +59,11 @@ __global__ void k_place_ids(uint64_t n, uint32_t x_bits, const uint32_t* __restr
 
 // Thread m owns words 4m .. 4m+3 of the record table (row-major), lane m & 3
 // of the quad that makes PRF block m / 4 of both split keys; share 1 and 2
-// are those PRF words, share 3 the one-hot record ^ both.
+// are those PRF words, share 3 the one-hot record ^ both.  VEC: the record
+// width is a multiple of four words and the shares are 16-byte aligned, so a
+// thread's four words lie in one record (one division, one ID read) and go
+// out as one 16-byte store per share.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_split_records(uint64_t nwords_total, uint32_t wx,
                                                        const uint32_t* __restrict__ rec_id, ChachaKey ka,
                                                        ChachaKey kb, uint32_t counter, uint32_t* __restrict__ s0,
@@ -67,17 +71,29 @@ __global__ __launch_bounds__(256) void k_split_records(uint64_t nwords_total, ui
     const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint4 fa = chacha_quad(ka, (uint32_t)(m >> 2), counter, 0u, 0u);
     const uint4 fb = chacha_quad(kb, (uint32_t)(m >> 2), counter, 0u, 0u);
-    const uint32_t a[4] = {fa.x, fa.y, fa.z, fa.w}, b[4] = {fb.x, fb.y, fb.z, fb.w};
+    if constexpr (VEC) {
+        if (4 * m >= nwords_total) return;
+        const uint64_t r = 4 * m / wx;
+        const uint32_t w0 = (uint32_t)(4 * m - r * wx), x = rec_id[r];
+        const uint32_t d = (x >> 5) - w0, bit = x != 0xFFFFFFFFu && d < 4u ? 1u << (x & 31u) : 0u;
+        const uint4 plain = make_uint4(d == 0 ? bit : 0u, d == 1 ? bit : 0u, d == 2 ? bit : 0u, d == 3 ? bit : 0u);
+        ((uint4*)s0)[m] = fa;
+        ((uint4*)s1)[m] = fb;
+        ((uint4*)s2)[m] = make_uint4(plain.x ^ fa.x ^ fb.x, plain.y ^ fa.y ^ fb.y, plain.z ^ fa.z ^ fb.z,
+                                     plain.w ^ fa.w ^ fb.w);
+    } else {
+        const uint32_t a[4] = {fa.x, fa.y, fa.z, fa.w}, b[4] = {fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint64_t g = 4 * m + q;
-        if (g >= nwords_total) break;
-        const uint64_t r = g / wx;
-        const uint32_t w = (uint32_t)(g - r * wx), x = rec_id[r];
-        const uint32_t plain = (x != 0xFFFFFFFFu && (x >> 5) == w) ? 1u << (x & 31u) : 0u;
-        s0[g] = a[q];
-        s1[g] = b[q];
-        s2[g] = plain ^ a[q] ^ b[q];
+        for (int q = 0; q < 4; q++) {
+            const uint64_t g = 4 * m + q;
+            if (g >= nwords_total) break;
+            const uint64_t r = g / wx;
+            const uint32_t w = (uint32_t)(g - r * wx), x = rec_id[r];
+            const uint32_t plain = (x != 0xFFFFFFFFu && (x >> 5) == w) ? 1u << (x & 31u) : 0u;
+            s0[g] = a[q];
+            s1[g] = b[q];
+            s2[g] = plain ^ a[q] ^ b[q];
+        }
     }
 }
 
@@ -375,9 +391,14 @@ int rss_enc_posting_lists(uint64_t n, uint32_t x_bits, const uint32_t* d_adj_off
     hipLaunchKernelGGL(k_place_ids, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, n, x_bits, d_adj_off, d_adj,
                        d_slot, d_off, rec_id);
     const uint64_t total = nrec * wx, quads = (total + 3) / 4;
-    hipLaunchKernelGGL(k_split_records, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, total, wx, rec_id,
-                       chacha_key(split_keys[0], 5), chacha_key(split_keys[1], 5), counter, d_out[0], d_out[1],
-                       d_out[2]);
+    const bool vec = wx % 4 == 0 && ((uintptr_t)d_out[0] | (uintptr_t)d_out[1] | (uintptr_t)d_out[2]) % 16 == 0;
+    const ChachaKey ka = chacha_key(split_keys[0], 5), kb = chacha_key(split_keys[1], 5);
+    if (vec)
+        hipLaunchKernelGGL(k_split_records<true>, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, total, wx,
+                           rec_id, ka, kb, counter, d_out[0], d_out[1], d_out[2]);
+    else
+        hipLaunchKernelGGL(k_split_records<false>, dim3((unsigned)((quads + 255) / 256)), dim3(256), 0, s, total, wx,
+                           rec_id, ka, kb, counter, d_out[0], d_out[1], d_out[2]);
     return check_launch("rss_enc_posting_lists");
 }
 
